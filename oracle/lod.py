@@ -1,0 +1,145 @@
+"""Block-wise level-of-detail selection, plain FP64 NumPy: TEST INFRASTRUCTURE ONLY.
+
+Follows Sec. 3.3.2 of the paper step by step:
+  1. per block, a floater-robust bounding box from the Median Absolute Deviation
+     of the finest-level Gaussian centres (Eq. 6, n_MAD = 4);
+  2. per (view, block), the minimum distance from the box's eight corners to the
+     camera centre picks the detail level against the distance intervals;
+  3. the corners in front of the camera are projected; the block is visible when
+     the bounding box of those projections overlaps the screen with positive
+     area (IoU > 0), or when the camera stands inside the block's xy cell;
+  4. the chosen levels of the visible blocks are concatenated in block order.
+
+Readings of points the paper leaves open (also listed in the design notes):
+  * median of an even count = the lower middle element (rank floor((n-1)/2));
+  * distance intervals are half-open [t_k, t_{k+1});
+  * "in front of the camera" means camera-space z > znear;
+  * "the block where the camera is in" is the block's half-open xy cell;
+  * levels are indexed 0 (coarsest) .. L-1 (finest); a near block gets L-1.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+N_MAD = 4.0
+
+
+def lower_median(x: np.ndarray) -> float:
+    """Element of rank floor((n-1)/2) in ascending order."""
+    s = np.sort(np.asarray(x, np.float64))
+    return float(s[(s.shape[0] - 1) // 2])
+
+
+def mad_bounds(means_block: np.ndarray, n_mad: float = N_MAD):
+    """Eq. 6 per axis: lo = max(min p, med - n*MAD), hi = min(max p, med + n*MAD)."""
+    p = np.asarray(means_block, np.float64)
+    lo = np.zeros(3)
+    hi = np.zeros(3)
+    for ax in range(3):
+        x = p[ax]
+        med = lower_median(x)
+        mad = lower_median(np.abs(x - med))
+        lo[ax] = max(float(x.min()), med - n_mad * mad)
+        hi[ax] = min(float(x.max()), med + n_mad * mad)
+    return lo, hi
+
+
+def scene_bounds(scene, n_mad: float = N_MAD):
+    """MAD boxes of every block from its finest-level centres: lo, hi [B, 3]."""
+    fine = scene.levels[-1]
+    L = scene.n_levels
+    B = scene.n_blocks
+    lo = np.zeros((B, 3))
+    hi = np.zeros((B, 3))
+    for b in range(B):
+        o, c = scene.lvl_off[b, L - 1], scene.lvl_cnt[b, L - 1]
+        if c == 0:
+            lo[b] = np.inf
+            hi[b] = -np.inf
+            continue
+        lo[b], hi[b] = mad_bounds(fine.means[:, o:o + c], n_mad)
+    return lo, hi
+
+
+def camera_center(cam):
+    R = np.asarray(cam.R, np.float64)
+    t = np.asarray(cam.t, np.float64)
+    return np.array([-((R[0, k] * t[0] + R[1, k] * t[1]) + R[2, k] * t[2]) for k in range(3)])
+
+
+def corners(lo, hi):
+    return np.array([[(hi if (c >> 0) & 1 else lo)[0], (hi if (c >> 1) & 1 else lo)[1],
+                      (hi if (c >> 2) & 1 else lo)[2]] for c in range(8)])
+
+
+def select_block(lo, hi, cell, thresholds, cam, n_levels):
+    """Level for one (view, block): -1 if culled, else 0 (coarsest) .. n_levels-1."""
+    if not (lo[0] <= hi[0]):
+        return -1  # empty block
+    C = camera_center(cam)
+    R = np.asarray(cam.R, np.float64).reshape(9)
+    t = np.asarray(cam.t, np.float64)
+    dmin2 = np.inf
+    front = []
+    for p in corners(lo, hi):
+        d2 = ((p[0] - C[0]) * (p[0] - C[0]) + (p[1] - C[1]) * (p[1] - C[1])) + (p[2] - C[2]) * (p[2] - C[2])
+        dmin2 = min(dmin2, d2)
+        zc = ((R[6] * p[0] + R[7] * p[1]) + R[8] * p[2]) + t[2]
+        if zc > cam.znear:
+            xc = ((R[0] * p[0] + R[1] * p[1]) + R[2] * p[2]) + t[0]
+            yc = ((R[3] * p[0] + R[4] * p[1]) + R[5] * p[2]) + t[1]
+            rz = 1.0 / zc
+            front.append((cam.fx * (xc * rz) + cam.cx, cam.fy * (yc * rz) + cam.cy))
+    visible = False
+    if front:
+        f = np.array(front)
+        umin, vmin = f.min(axis=0)
+        umax, vmax = f.max(axis=0)
+        # intersection of [umin, umax] x [vmin, vmax] with the screen has positive area
+        visible = (min(umax, float(cam.width)) > max(umin, 0.0)) and (min(vmax, float(cam.height)) > max(vmin, 0.0))
+    in_cell = (cell[0] <= C[0] < cell[1]) and (cell[2] <= C[1] < cell[3])
+    if not (visible or in_cell):
+        return -1
+    level = n_levels - 1
+    for tk in thresholds:
+        if dmin2 >= tk * tk:
+            level -= 1
+    return level
+
+
+def lod_select(lo, hi, cells, thresholds, cams, lvl_cnt):
+    """level [V, B] int8 and offsets [V, B+1] int64 (exclusive prefix of chosen counts)."""
+    B = cells.shape[0]
+    L = lvl_cnt.shape[1]
+    V = len(cams)
+    level = np.full((V, B), -1, np.int8)
+    offsets = np.zeros((V, B + 1), np.int64)
+    for v, cam in enumerate(cams):
+        for b in range(B):
+            level[v, b] = select_block(lo[b], hi[b], cells[b], thresholds, cam, L)
+        counts = np.array([lvl_cnt[b, level[v, b]] if level[v, b] >= 0 else 0 for b in range(B)], np.int64)
+        offsets[v, 1:] = np.cumsum(counts)
+    return level, offsets
+
+
+def aggregate(scene, level_row):
+    """Concatenate the chosen level of every selected block, in block order."""
+    from types import SimpleNamespace
+    parts = {k: [] for k in ("means", "scales", "quats", "opac", "sh")}
+    for b, l in enumerate(level_row):
+        if l < 0:
+            continue
+        o, c = scene.lvl_off[b, l], scene.lvl_cnt[b, l]
+        lev = scene.levels[l]
+        parts["means"].append(lev.means[:, o:o + c])
+        parts["scales"].append(lev.scales[:, o:o + c])
+        parts["quats"].append(lev.quats[:, o:o + c])
+        parts["opac"].append(lev.opac[o:o + c])
+        parts["sh"].append(lev.sh[:, :, o:o + c])
+    if not parts["opac"]:
+        return SimpleNamespace(means=np.zeros((3, 0), np.float32), scales=np.zeros((3, 0), np.float32),
+                               quats=np.zeros((4, 0), np.float32), opac=np.zeros(0, np.float32),
+                               sh=np.zeros((16, 3, 0), np.float32))
+    return SimpleNamespace(means=np.concatenate(parts["means"], 1), scales=np.concatenate(parts["scales"], 1),
+                           quats=np.concatenate(parts["quats"], 1), opac=np.concatenate(parts["opac"]),
+                           sh=np.concatenate(parts["sh"], 2))

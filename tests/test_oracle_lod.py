@@ -1,0 +1,128 @@
+"""Pins of the level-of-detail oracle (Sec. 3.3.2, Eq. 6) against brute force,
+closed-form distances and statistical facts (no GPU)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import lod
+from paper_2404_01133_amd import synth
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")))
+
+
+def rank_median(x):
+    """Lower median by counting: the element m with #{x < m} <= k < #{x <= m}, k = floor((n-1)/2)."""
+    k = (len(x) - 1) // 2
+    for m in x:
+        if (x < m).sum() <= k < (x <= m).sum():
+            return m
+    raise AssertionError
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 8, 33])
+def test_lower_median_matches_rank_count(n):
+    rng = np.random.default_rng(n)
+    for _ in range(20):
+        x = rng.integers(0, 6, n).astype(np.float64) * 0.5   # many ties
+        assert lod.lower_median(x) == rank_median(x)
+
+
+def test_mad_of_uniform_is_quarter():
+    rng = np.random.default_rng(0)
+    x = rng.uniform(0, 1, (3, 200_001))
+    for ax in range(3):
+        med = lod.lower_median(x[ax])
+        mad = lod.lower_median(np.abs(x[ax] - med))
+        assert abs(med - 0.5) < 0.005 and abs(mad - 0.25) < 0.005
+
+
+def test_mad_box_ignores_floaters():
+    rng = np.random.default_rng(1)
+    core = rng.normal(0, 1.0, (3, 50_000))
+    floaters = rng.uniform(40, 60, (3, 1500)) * rng.choice([-1, 1], (3, 1500))
+    pts = np.concatenate([core, floaters], axis=1)
+    lo, hi = lod.mad_bounds(pts, GOLDEN["n_mad"])
+    # normal: MAD = 0.6745 sigma, so the box is about +-2.7 sigma; min/max reach the floaters
+    assert (hi < 3.5).all() and (lo > -3.5).all()
+    assert (pts.max(axis=1) > 39).all() and (pts.min(axis=1) < -39).all()
+    # without floaters the bound is min(max p, med + 4 MAD)
+    lo0, hi0 = lod.mad_bounds(core, GOLDEN["n_mad"])
+    assert np.all(np.abs(hi - hi0) < 0.15) and np.all(np.abs(lo - lo0) < 0.15)
+
+
+def test_mad_box_clamps_to_extremes():
+    x = np.array([[0.0, 1.0, 2.0, 3.0, 4.0]] * 3)
+    lo, hi = lod.mad_bounds(x, 4.0)          # med 2, MAD 1: med +- 4 lies outside [0, 4]
+    assert (lo == 0.0).all() and (hi == 4.0).all()
+
+
+def straight_down(x, y, h, W=1600, H=900):
+    return synth.look_camera((x, y, h), yaw=0.3, pitch=-math.pi / 2, width=W, height=H)
+
+
+def test_distance_from_camera_above_box_centre():
+    lo = np.array([-10.0, -20.0, 0.0])
+    hi = np.array([10.0, 20.0, 30.0])
+    cell = (-10.0, 10.0, -20.0, 20.0)
+    half_diag = math.hypot(10.0, 20.0)
+    t0, t1 = GOLDEN["distance_intervals_m"]["MatrixCity"]
+    L = GOLDEN["n_levels"]
+    for h, want in [(100.0, 2), (200.0, 2), (260.0, 1), (420.0, 1), (440.0, 0)]:
+        d = math.sqrt((h - hi[2]) ** 2 + half_diag ** 2)
+        expect = 2 if d < t0 else (1 if d < t1 else 0)
+        assert expect == want
+        assert lod.select_block(lo, hi, cell, (t0, t1), straight_down(0.0, 0.0, h), L) == want
+
+
+def test_block_behind_camera_is_culled_unless_camera_inside():
+    cam = synth.look_camera((0.0, 0.0, 50.0), yaw=0.0, pitch=-0.2, width=640, height=480)  # looking toward +x
+    lo = np.array([-300.0, -20.0, 0.0])
+    hi = np.array([-200.0, 20.0, 30.0])
+    assert lod.select_block(lo, hi, (-300, -200, -20, 20), (200, 400), cam, 3) == -1
+    # same box, but the camera's xy lies in the block's cell: always rendered
+    assert lod.select_block(lo, hi, (-300, 10, -20, 20), (200, 400), cam, 3) >= 0
+
+
+def test_box_in_view_is_visible_and_far_side_box_is_not():
+    cam = straight_down(0.0, 0.0, 150.0)
+    assert lod.select_block(np.array([-20.0, -20, 0]), np.array([20.0, 20, 10]), (1e9, 1e9 + 1, 0, 1), (200, 400),
+                            cam, 3) == 2
+    # footprint straight down at 150 m, fov 60 deg: half-width 86.6 m; a box 400 m away is outside
+    assert lod.select_block(np.array([380.0, -20, 0]), np.array([420.0, 20, 10]), (1e9, 1e9 + 1, 0, 1), (200, 400),
+                            cam, 3) == -1
+
+
+def test_lod_select_matches_per_block_bruteforce_and_offsets():
+    scene = synth.city_block_scene(n=60_000, seed=11, area_m2=1.5e6, grid=(8, 8))
+    lo, hi = lod.scene_bounds(scene)
+    cams = synth.city_views(seed=11, n_xy=3)
+    level, offsets = lod.lod_select(lo, hi, scene.cells, (200.0, 500.0), cams, scene.lvl_cnt)
+    for v, cam in enumerate(cams):
+        C = cam.center
+        for b in range(scene.n_blocks):
+            cs = lod.corners(lo[b], hi[b])
+            dmin = np.sqrt(((cs - C) ** 2).sum(axis=1)).min()
+            if level[v, b] >= 0:
+                assert level[v, b] == (2 if dmin < 200 else (1 if dmin < 500 else 0))
+        cnt = [scene.lvl_cnt[b, level[v, b]] if level[v, b] >= 0 else 0 for b in range(scene.n_blocks)]
+        assert offsets[v, 0] == 0 and (np.diff(offsets[v]) == cnt).all()
+        agg = lod.aggregate(scene, level[v])
+        assert agg.opac.shape[0] == offsets[v, -1]
+    # the straight-down views see fewer blocks from lower heights
+    assert (level >= 0).sum() > 0
+
+
+def test_nested_levels_and_coarse_scale():
+    scene = synth.city_block_scene(n=20_000, seed=3, grid=(4, 4))
+    fine = scene.levels[-1]
+    for l in range(scene.n_levels - 1):
+        assert scene.levels[l].opac.shape[0] < fine.opac.shape[0]
+    # each coarse Gaussian is a finest-level Gaussian with scales x1.3
+    lvl1 = scene.levels[1]
+    idx = {tuple(fine.means[:, k]): k for k in range(fine.opac.shape[0])}
+    for k in range(0, lvl1.opac.shape[0], 97):
+        j = idx[tuple(lvl1.means[:, k])]
+        np.testing.assert_allclose(lvl1.scales[:, k], fine.scales[:, j] * np.float32(1.3), rtol=1e-6)

@@ -1,0 +1,382 @@
+"""Pins of the CPU oracle against closed forms, invariants, library routines and
+brute force (no GPU).  Each test would fail on a plausible mistake in the oracle:
+a wrong Jacobian entry, quaternion convention, dilation, SH sign/normalisation,
+compositing threshold, sort key or adjoint term."""
+import math
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+import scipy.special as sps
+from scipy.spatial.transform import Rotation
+
+import oracle
+from paper_2404_01133_amd import synth
+
+Y00 = 1.0 / (2.0 * math.sqrt(math.pi))
+
+
+def make_set(means, scales, quats, opac, sh, dtype=np.float32):
+    n = len(opac)
+    sh_full = np.zeros((16, 3, n))
+    sh = np.asarray(sh, np.float64)
+    sh_full[: sh.shape[0]] = sh
+    return SimpleNamespace(means=np.asarray(means, dtype).reshape(3, n), scales=np.asarray(scales, dtype).reshape(3, n),
+                           quats=np.asarray(quats, dtype).reshape(4, n), opac=np.asarray(opac, dtype).reshape(n),
+                           sh=sh_full.astype(dtype))
+
+
+def grey_sh(rgb, n):
+    """SH coefficients whose degree-0 term yields colour `rgb` (no view dependence)."""
+    sh = np.zeros((1, 3, n))
+    sh[0] = ((np.asarray(rgb, np.float64) - 0.5) / Y00)[:, None]
+    return sh
+
+
+def identity_cam(W, H, fx):
+    return synth.Camera(R=np.eye(3), t=np.zeros(3), fx=fx, fy=fx, cx=0.5 * W, cy=0.5 * H, width=W, height=H)
+
+
+# ---------------------------------------------------------------------------
+# lone isotropic Gaussian: footprint, per-pixel values and integral
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("s,z,o,quat", [(0.05, 4.0, 0.8, (1, 0, 0, 0)),
+                                        (0.12, 3.0, 0.3, (0.3, -0.5, 0.7, 0.2)),
+                                        (0.02, 2.0, 0.99, (-0.6, 0.1, 0.1, 0.78))])
+def test_lone_isotropic_gaussian_closed_form(s, z, o, quat):
+    W, H, fx = 96, 80, 300.0
+    cam = identity_cam(W, H, fx)
+    rgb = np.array([0.9, 0.4, 0.2])
+    q = np.asarray(quat, np.float64)
+    q = q / np.linalg.norm(q)
+    g = make_set([[0.0], [0.0], [z]], [[s], [s], [s]], q.reshape(4, 1), [o], grey_sh(rgb, 1), dtype=np.float64)
+    img, T, nc, _ = oracle.render(g, cam, sh_degree=0)
+    sig2 = (fx * s / z) ** 2 + 0.3           # EWA splat of an isotropic Gaussian on the axis, plus dilation
+    r = math.ceil(3.0 * math.sqrt(sig2))
+    u, v = 0.5 * W, 0.5 * H
+    ii, jj = np.meshgrid(np.arange(W), np.arange(H))
+    d2 = (ii + 0.5 - u) ** 2 + (jj + 0.5 - v) ** 2
+    alpha = np.minimum(0.99, o * np.exp(-0.5 * d2 / sig2))
+    inside = (np.abs(ii + 0.5 - u) <= r) & (np.abs(jj + 0.5 - v) <= r) & (alpha >= 1.0 / 255.0)
+    expect = np.where(inside, alpha, 0.0)
+    for ch in range(3):
+        np.testing.assert_allclose(img[ch], rgb[ch] * expect, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(T, 1.0 - expect, rtol=0, atol=1e-12)
+    assert (nc == inside).all()
+
+
+def test_lone_gaussian_integral():
+    # sigma' >= 10 px and o <= 0.35, so the alpha >= 1/255 disc lies inside the 3-sigma square:
+    # the sum over pixels approximates 2 pi sigma'^2 (o - 1/255) (integral of the truncated Gaussian).
+    W = H = 160
+    fx = 400.0
+    s, z, o = 0.1, 2.0, 0.3
+    cam = identity_cam(W, H, fx)
+    rgb = np.array([0.7, 0.7, 0.7])
+    g = make_set([[0.0], [0.0], [z]], [[s], [s], [s]], [[1.0], [0], [0], [0]], [o], grey_sh(rgb, 1), np.float64)
+    img, _, _, _ = oracle.render(g, cam, sh_degree=0)
+    sig2 = (fx * s / z) ** 2 + 0.3
+    assert math.sqrt(sig2) >= 10.0
+    closed = 0.7 * 2.0 * math.pi * sig2 * (o - 1.0 / 255.0)
+    assert abs(img[0].sum() - closed) / closed < 1e-4
+
+
+# ---------------------------------------------------------------------------
+# projection: 2D mean and covariance against the pinhole map's finite-difference
+# Jacobian and SciPy's quaternion rotation
+# ---------------------------------------------------------------------------
+def test_projection_matches_fd_jacobian_and_scipy_rotation():
+    rng = np.random.default_rng(5)
+    cam = synth.look_camera((3.0, -4.0, 5.0), yaw=1.1, pitch=-0.6, width=200, height=150)
+    n = 64
+    # points near the optical axis, 4-12 units ahead
+    C = cam.center
+    fwd = cam.R[2]
+    pts = C[:, None] + fwd[:, None] * rng.uniform(4, 12, n) + rng.normal(0, 0.8, (3, n))
+    scales = np.exp(rng.normal(-1.5, 0.4, (3, n)))
+    q = rng.normal(size=(4, n))
+    q /= np.linalg.norm(q, axis=0)
+    g = make_set(pts, scales, q, np.full(n, 0.5), np.zeros((1, 3, n)), np.float64)
+    pr = oracle.project(g, cam, sh_degree=0)
+    assert pr["visible"].all()
+
+    def pinhole(p):
+        t = cam.R @ p + cam.t
+        return np.array([cam.fx * t[0] / t[2] + cam.cx, cam.fy * t[1] / t[2] + cam.cy])
+
+    for k in range(n):
+        p = pts[:, k]
+        np.testing.assert_allclose(pr["uv"][k], pinhole(p), rtol=1e-12)
+        h = 1e-5
+        Jw = np.stack([(pinhole(p + h * e) - pinhole(p - h * e)) / (2 * h) for e in np.eye(3)], axis=1)
+        Rq = Rotation.from_quat([q[1, k], q[2, k], q[3, k], q[0, k]]).as_matrix()   # SciPy: scalar last
+        Sig = Rq @ np.diag(scales[:, k] ** 2) @ Rq.T
+        S2 = Jw @ Sig @ Jw.T + 0.3 * np.eye(2)
+        got = np.array([[pr["cov2d"][k, 0], pr["cov2d"][k, 1]], [pr["cov2d"][k, 1], pr["cov2d"][k, 2]]])
+        np.testing.assert_allclose(got, S2, rtol=1e-7, atol=1e-9)
+        np.testing.assert_allclose(np.array([[pr["conic"][k, 0], pr["conic"][k, 1]],
+                                             [pr["conic"][k, 1], pr["conic"][k, 2]]]), np.linalg.inv(S2), rtol=1e-6)
+        lam = np.linalg.eigvalsh(S2).max()
+        assert pr["radius"][k] == math.ceil(3.0 * math.sqrt(lam)) or abs(3 * math.sqrt(lam) - round(3 * math.sqrt(lam))) < 1e-9
+
+
+def test_covariance_quaternion_sign_and_scale_invariance():
+    cam = synth.axis_camera(64, 64)
+    rng = np.random.default_rng(2)
+    n = 16
+    means = np.vstack([rng.uniform(-0.3, 0.3, (2, n)), np.full((1, n), 0.5)])
+    scales = np.exp(rng.normal(-3, 0.5, (3, n)))
+    q = rng.normal(size=(4, n))
+    base = oracle.project(make_set(means, scales, q, np.full(n, 0.5), np.zeros((1, 3, n)), np.float64), cam, 0)
+    for qq in (-q, 3.7 * q):
+        other = oracle.project(make_set(means, scales, qq, np.full(n, 0.5), np.zeros((1, 3, n)), np.float64), cam, 0)
+        np.testing.assert_allclose(other["cov2d"], base["cov2d"], rtol=1e-12)
+
+
+def test_identity_camera_depth_is_z():
+    cam = synth.axis_camera(64, 64, dist=0.0)
+    z = np.array([0.25, 1.0, 3.5, 17.125])
+    n = len(z)
+    g = make_set(np.vstack([np.zeros((2, n)), z[None]]), np.full((3, n), 0.01), np.tile([[1.0], [0], [0], [0]], n),
+                 np.full(n, 0.5), np.zeros((1, 3, n)))
+    pr = oracle.project(g, cam, 0)
+    np.testing.assert_array_equal(pr["depth_bits"], z.astype(np.float32).view(np.uint32))
+
+
+# ---------------------------------------------------------------------------
+# spherical harmonics against SciPy's complex harmonics (Condon-Shortley phase)
+# ---------------------------------------------------------------------------
+def real_sh_scipy(l, m, d):
+    x, y, z = d
+    theta = np.arccos(np.clip(z, -1, 1))
+    phi = np.mod(np.arctan2(y, x), 2 * np.pi)
+    Y = sps.sph_harm_y(l, abs(m), theta, phi)
+    if m > 0:
+        return math.sqrt(2) * Y.real
+    if m < 0:
+        return math.sqrt(2) * Y.imag
+    return Y.real
+
+
+def test_sh_basis_matches_scipy():
+    cam = synth.axis_camera(64, 64)
+    rng = np.random.default_rng(3)
+    n = 40
+    means = np.vstack([rng.uniform(-1, 1, (2, n)), rng.uniform(-2.5, 2, (1, n))])
+    C = cam.center
+    dirs = (means - C[:, None]) / np.linalg.norm(means - C[:, None], axis=0)
+    for k in range(16):
+        l = int(math.isqrt(k))
+        m = k - l * l - l
+        sh = np.zeros((16, 3, n))
+        sh[k, 0] = 0.1
+        g = make_set(means, np.full((3, n), 0.01), np.tile([[1.0], [0], [0], [0]], n), np.full(n, 0.5), sh,
+                     np.float64)
+        pr = oracle.project(g, cam, 3)
+        vis = pr["visible"] > 0
+        got = (pr["rgb"][vis, 0] - 0.5) / 0.1
+        want = np.array([real_sh_scipy(l, m, dirs[:, j]) for j in np.nonzero(vis)[0]])
+        np.testing.assert_allclose(got, want, rtol=0, atol=1e-12, err_msg=f"l={l} m={m}")
+
+
+def test_sh_basis_orthonormal_by_quadrature():
+    # Gauss-Legendre in cos(theta) x uniform phi integrates products of degree <= 6 exactly.
+    xs, ws = np.polynomial.legendre.leggauss(8)
+    nphi = 16
+    phis = 2 * np.pi * np.arange(nphi) / nphi
+    dirs, wts = [], []
+    for x, w in zip(xs, ws):
+        for p in phis:
+            st = math.sqrt(1 - x * x)
+            dirs.append((st * math.cos(p), st * math.sin(p), x))
+            wts.append(w * 2 * np.pi / nphi)
+    dirs = np.array(dirs).T
+    wts = np.array(wts)
+    n = dirs.shape[1]
+    means = 5.0 * dirs            # camera at the origin: the view direction of Gaussian j is dirs[:, j]
+    Ymat = np.zeros((16, n))
+    for k in range(16):
+        sh = np.zeros((16, 3, n))
+        sh[k, 0] = 0.1
+        g = make_set(means, np.full((3, n), 0.01), np.tile([[1.0], [0], [0], [0]], n), np.full(n, 0.5), sh,
+                     np.float64)
+        Ymat[k] = (_colour_all_directions(g) - 0.5) / 0.1
+    gram = (Ymat * wts) @ Ymat.T
+    np.testing.assert_allclose(gram, np.eye(16), atol=1e-12)
+
+
+def _colour_all_directions(g):
+    """rgb[0] for every Gaussian, using one camera per hemisphere-free direction:
+    rotate a camera to look straight at each Gaussian."""
+    out = np.zeros(g.opac.shape[0])
+    for j in range(g.opac.shape[0]):
+        p = g.means[:, j]
+        d = p / np.linalg.norm(p)
+        # any rotation whose third row is d
+        a = np.array([1.0, 0, 0]) if abs(d[0]) < 0.9 else np.array([0, 1.0, 0])
+        r0 = np.cross(d, a)
+        r0 /= np.linalg.norm(r0)
+        r1 = np.cross(d, r0)
+        cam = synth.Camera(R=np.stack([r0, r1, d]), t=np.zeros(3), fx=10.0, fy=10.0, cx=8.0, cy=8.0, width=16,
+                           height=16)
+        one = make_set(g.means[:, j:j + 1], g.scales[:, j:j + 1], g.quats[:, j:j + 1], g.opac[j:j + 1],
+                       g.sh[:, :, j:j + 1], np.float64)
+        pr = oracle.project(one, cam, 3)
+        assert pr["visible"][0]
+        out[j] = pr["rgb"][0, 0]
+    return out
+
+
+# ---------------------------------------------------------------------------
+# compositing: closed form for equal-alpha stacks, invariants
+# ---------------------------------------------------------------------------
+def test_equal_alpha_stack_stops_after_13():
+    # Wide Gaussians centred exactly on a pixel centre with o = 0.5: alpha = 0.5 at that pixel.
+    # T after k layers = 2^-k; the 14th would take T to 2^-14 < 1e-4, so 13 contribute.
+    W, H = 65, 49                      # cx = 32.5, cy = 24.5: pixel (32, 24)'s centre
+    cam = identity_cam(W, H, 50.0)
+    n = 20
+    z = 2.0 + 0.01 * np.arange(n)
+    rgb = np.array([0.8, 0.5, 0.25])
+    g = make_set(np.vstack([np.zeros((2, n)), z[None]]), np.full((3, n), 0.3), np.tile([[1.0], [0], [0], [0]], n),
+                 np.full(n, 0.5), grey_sh(rgb, n), np.float64)
+    img, T, nc, _ = oracle.render(g, cam, 0)
+    assert nc[24, 32] == 13
+    np.testing.assert_allclose(img[:, 24, 32], rgb * (1 - 2.0 ** -13), rtol=0, atol=1e-15)
+    assert T[24, 32] == 2.0 ** -13
+
+
+def test_compositing_invariants_and_background():
+    g, cam = synth.small_render_case(1024, seed=4, width=128, height=96)
+    img, T, nc, _ = oracle.render(g, cam)
+    assert (T >= 0).all() and (T <= 1).all()
+    pr = oracle.project(g, cam)
+    vis = pr["visible"] > 0
+    cmax = pr["rgb"][vis].max()
+    assert (img <= cmax * (1 - T)[None] + 1e-12).all()
+    bg = (0.2, 0.5, 0.9)
+    img_bg, T_bg, _, _ = oracle.render(g, cam, bg=bg)
+    np.testing.assert_allclose(img_bg - img, np.asarray(bg)[:, None, None] * T[None], atol=1e-12)
+
+
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16), (32, 8), (16, 4)])
+def test_tiled_equals_untiled(tile):
+    g, cam = synth.small_render_case(4096, seed=0)
+    img, T, nc, _ = oracle.render(g, cam)
+    img_t, T_t, nc_t = oracle.render_tiled(g, cam, tile=tile)
+    np.testing.assert_array_equal(img, img_t)
+    np.testing.assert_array_equal(T, T_t)
+    np.testing.assert_array_equal(nc, nc_t)
+
+
+def test_pixel_subset_matches_full_image():
+    g, cam = synth.small_render_case(2048, seed=9, width=96, height=64)
+    img, T, nc, _ = oracle.render(g, cam)
+    rng = np.random.default_rng(0)
+    pix = rng.choice(96 * 64, 300, replace=False)
+    sub, Ts, ncs, _ = oracle.render(g, cam, pixels=pix)
+    np.testing.assert_array_equal(sub, img.reshape(3, -1)[:, pix])
+    np.testing.assert_array_equal(Ts, T.reshape(-1)[pix])
+
+
+# ---------------------------------------------------------------------------
+# tile pairs: brute-force lexicographic sort of the projected footprints
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 16)])
+def test_pairs_match_bruteforce_lexsort(tile):
+    g, cam = synth.small_render_case(4096, seed=0)
+    pr = oracle.project(g, cam, tile=tile)
+    tx_n = -(-cam.width // tile[0])
+    tiles, depth, index = [], [], []
+    for k in np.nonzero(pr["visible"])[0]:
+        i0, i1, j0, j1 = pr["rect"][k]
+        for ty in range(j0 // tile[1], j1 // tile[1] + 1):
+            for tx in range(i0 // tile[0], i1 // tile[0] + 1):
+                tiles.append(ty * tx_n + tx)
+                depth.append(pr["depth_bits"][k])
+                index.append(k)
+    tiles, depth, index = map(np.array, (tiles, depth, index))
+    order = np.lexsort((index, depth, tiles))
+    t, idx = oracle.pairs(g, cam, tile=tile)
+    assert len(t) == pr["tiles_touched"].sum()
+    np.testing.assert_array_equal(t, tiles[order])
+    np.testing.assert_array_equal(idx, index[order])
+
+
+# ---------------------------------------------------------------------------
+# gradients: central finite differences of the FP64 oracle image
+# ---------------------------------------------------------------------------
+def _signature(g, cam, deg):
+    img, T, nc, amb = oracle.render(g, cam, deg)
+    pr = oracle.project(g, cam, deg)
+    return nc.copy(), pr["rect"].copy(), pr["visible"].copy(), pr["rgb_clamped"].copy()
+
+
+def _same(a, b):
+    return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_gradients_match_finite_differences(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = 12
+    W, H = 40, 32
+    cam = synth.look_camera((0.0, -3.0, 1.0), yaw=math.pi / 2, pitch=-0.3, width=W, height=H)
+    base = cam.center + 3.0 * cam.R[2]
+    means = base[:, None] + rng.normal(0, 0.35, (3, n))
+    scales = np.exp(rng.normal(-2.2, 0.4, (3, n)))
+    q = rng.normal(size=(4, n))
+    opac = rng.uniform(0.2, 0.9, n)
+    sh = rng.normal(0, 0.3, (16, 3, n))
+    g = make_set(means, scales, q, opac, sh, np.float64)
+    dimg = rng.normal(size=(3, H, W))
+    grads = oracle.render_bwd(g, cam, dimg, 3)
+    sig0 = _signature(g, cam, 3)
+
+    def loss(gg):
+        img, _, _, _ = oracle.render(gg, cam, 3)
+        return float((img * dimg).sum())
+
+    checked = 0
+    for name, arr in (("means", "means"), ("scales", "scales"), ("quats", "quats"), ("opac", "opac"), ("sh", "sh")):
+        a = getattr(g, arr)
+        flat = a.reshape(-1)
+        picks = rng.choice(flat.size, min(flat.size, 24), replace=False)
+        for p in picks:
+            h = 1e-6 * max(1.0, abs(flat[p]))
+            gp = SimpleNamespace(**{k: getattr(g, k).copy() for k in ("means", "scales", "quats", "opac", "sh")})
+            gm = SimpleNamespace(**{k: getattr(g, k).copy() for k in ("means", "scales", "quats", "opac", "sh")})
+            getattr(gp, arr).reshape(-1)[p] += h
+            getattr(gm, arr).reshape(-1)[p] -= h
+            if not (_same(_signature(gp, cam, 3), sig0) and _same(_signature(gm, cam, 3), sig0)):
+                continue
+            fd = (loss(gp) - loss(gm)) / (2 * h)
+            got = grads[name].reshape(-1)[p]
+            assert abs(got - fd) <= 1e-6 * max(1.0, abs(fd)), (name, p, got, fd)
+            checked += 1
+    assert checked > 60
+
+
+def test_lone_gaussian_opacity_and_colour_gradient_closed_form():
+    # One pixel, one Gaussian: C = rgb * o * G, so dC/do = rgb * G and dC/drgb = o * G.
+    W, H = 33, 33
+    cam = identity_cam(W, H, 40.0)
+    rgb = np.array([0.6, 0.3, 0.9])
+    o = 0.4
+    g = make_set([[0.013], [-0.021], [2.0]], [[0.08], [0.05], [0.11]], [[0.9], [0.2], [-0.3], [0.1]], [o],
+                 grey_sh(rgb, 1), np.float64)
+    pr = oracle.project(g, cam, 0)
+    i, j = 17, 15
+    dimg = np.zeros((3, H, W))
+    dimg[0, j, i] = 1.0
+    out = oracle.render_bwd(g, cam, dimg, 0)
+    u, v = pr["uv"][0]
+    A, B, C = pr["conic"][0]
+    dx, dy = i + 0.5 - u, j + 0.5 - v
+    G = math.exp(-0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy)
+    assert o * G >= 1 / 255
+    np.testing.assert_allclose(out["g2d"][0, 5], rgb[0] * G, rtol=1e-12)
+    np.testing.assert_allclose(out["g2d"][0, 6], o * G, rtol=1e-12)
+    np.testing.assert_allclose(out["opac"][0], rgb[0] * G, rtol=1e-12)
+    # colour enters through SH degree 0 with weight Y00
+    np.testing.assert_allclose(out["sh"][0, 0, 0], Y00 * o * G, rtol=1e-12)
