@@ -1,0 +1,217 @@
+/*
+ * gs.h -- C ABI of the MI355X (gfx950) rendering path of CityGaussian
+ * (arXiv 2404.01133): block-wise level-of-detail selection (Sec. 3.3.2) feeding
+ * a differentiable tile-based 3D Gaussian splatting rasterizer (Sec. 3.1, Eq. 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Memory: every array argument is DEVICE memory allocated and owned by the
+ *    caller, unless its comment says "host".  The library never allocates or
+ *    frees; scratch comes from a caller-provided workspace whose size is given
+ *    by gs_workspace_bytes().
+ *  - Streams: every call is asynchronous and ordered on `stream` (a
+ *    hipStream_t passed as void*; NULL = the default stream).  Argument checks
+ *    happen on the host before any launch; a failed check returns an error
+ *    code and launches nothing.
+ *  - Sizes that depend on the data (selected Gaussians, visible Gaussians,
+ *    tile pairs) stay on the device, in the caller's `counts` array (int64[8],
+ *    see GS_COUNT_*), so a whole frame can be captured in a HIP graph.  Each
+ *    stage clamps to the capacity the caller passed and raises a bit in
+ *    counts[GS_COUNT_FLAGS] when a capacity was too small; the outputs of that
+ *    frame are then invalid and the caller re-runs with larger buffers.
+ *  - Gaussians are structure-of-arrays FP32:
+ *        means [3][n], scales [3][n] (> 0), quats [4][n] (w, x, y, z, any norm > 0),
+ *        opac [n] in (0, 1), sh [16][3][n] (degree-3 real SH, coefficient-major).
+ *    Gaussians with non-finite geometry, a zero quaternion or opacity below
+ *    1/255 are culled silently; they are not errors.
+ *  - Cameras: world->camera rotation R (row-major) and translation t, camera
+ *    axes x right, y down, z forward; pixel (i, j) has centre (i + 0.5, j + 0.5);
+ *    every view of one call has the same width and height.
+ *  - Images: rgb [V][3][H][W] FP32, transmittance T_final [V][H][W], and
+ *    n_last [V][H][W] = number of tile-list entries walked by each pixel
+ *    (consumed by the backward pass).
+ *  - Return value: GS_OK or a negative gs_status.  gs_status_string() names it;
+ *    after GS_ERR_HIP it also carries the HIP error text of the calling thread.
+ */
+#ifndef GS_H_
+#define GS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gs_status;
+#define GS_OK 0
+#define GS_ERR_INVALID_ARG (-1)
+#define GS_ERR_UNSUPPORTED (-2)
+#define GS_ERR_WORKSPACE (-3)
+#define GS_ERR_CAPACITY (-4)
+#define GS_ERR_HIP (-5)
+
+/* indices into the device int64 counts[8] array */
+#define GS_COUNT_RECORDS 0 /* selected (view, Gaussian) records, written by gs_lod_select */
+#define GS_COUNT_VISIBLE 1 /* records that survived culling, written by gs_bin_sort */
+#define GS_COUNT_PAIRS 2   /* (tile, record) pairs, written by gs_bin_sort */
+#define GS_COUNT_FLAGS 3   /* bit 0: record capacity exceeded; bit 1: pair capacity exceeded;
+                              bit 2: a device-side wait gave up (see GS_FLAG_WAIT) */
+#define GS_COUNT_SLOTS 8
+#define GS_FLAG_RECORDS 1
+#define GS_FLAG_PAIRS 2
+#define GS_FLAG_WAIT 4
+
+/* Camera (device array [V] of these; 152 bytes, 8-byte aligned). */
+typedef struct gs_camera {
+  double R[9];   /* world -> camera rotation, row-major */
+  double t[3];   /* world -> camera translation */
+  double fx, fy; /* focal lengths, pixels */
+  double cx, cy; /* principal point, pixels */
+  double znear;  /* Gaussians and block corners need camera z > znear */
+  int32_t width, height;
+  int32_t pad[2];
+} gs_camera;
+
+/* One detail level of the scene: device SoA arrays (see conventions). */
+typedef struct gs_gaussians {
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* opac;
+  const float* sh;
+  int64_t n;
+} gs_gaussians;
+
+/* Gradient buffers with the same shapes as gs_gaussians (device, accumulated +=). */
+typedef struct gs_gaussian_grads {
+  float* means;
+  float* scales;
+  float* quats;
+  float* opac;
+  float* sh;
+} gs_gaussian_grads;
+
+/* Block table (all pointers device).  Block b of level l occupies
+ * [lvl_off[b*L + l], lvl_off[b*L + l] + lvl_cnt[b*L + l]) of level l's arrays.
+ * lo/hi are the block's bounding box (Eq. 6), cell its half-open xy cell. */
+typedef struct gs_blocks {
+  const double* lo;       /* [B][3] */
+  const double* hi;       /* [B][3] */
+  const double* cell;     /* [B][4] = x0, x1, y0, y1 */
+  const int64_t* lvl_off; /* [B][L] */
+  const int64_t* lvl_cnt; /* [B][L] */
+  int32_t n_blocks;
+  int32_t n_levels;
+} gs_blocks;
+
+/* Launch shape of the tile kernels.  tile_w x tile_h pixels per tile
+ * (supported: 16x16, 8x8, 16x8, 32x8, 32x16); batch = Gaussians staged in LDS per
+ * round (64, 128 or 256).  The image does not depend on these choices. */
+typedef struct gs_tuning {
+  int32_t tile_w, tile_h;
+  int32_t batch;
+  int32_t flags; /* reserved, 0 */
+} gs_tuning;
+
+/* Size in bytes of one projected record (an opaque device structure). */
+size_t gs_record_bytes(void);
+
+/* Workspace needed by gs_bin_sort / gs_rasterize_bwd for the given capacities. */
+#define GS_WS_BIN_SORT 1
+#define GS_WS_RASTERIZE_BWD 2
+size_t gs_workspace_bytes(int32_t which, int64_t record_capacity, int64_t pair_capacity, int32_t n_views,
+                          int32_t width, int32_t height, const gs_tuning* tuning /* host */);
+
+/* Block-wise level-of-detail selection (Sec. 3.3.2).
+ * For every (view v, block b): the level is chosen from the minimum distance
+ * between the camera centre and the eight corners of the block's box, against
+ * the ascending distance thresholds (half-open intervals; near = finest level
+ * L-1); the block is kept if the bounding box of its corners in front of the
+ * camera (z > znear), projected, overlaps the screen with positive area, or if
+ * the camera's xy lies in the block's cell.  The chosen levels are concatenated
+ * in block order (the aggregation step), as offsets into one record space:
+ *   level   [V][B] int8: chosen level or -1 (not rendered)
+ *   offsets [V*B + 1] int64: record range of (v, b) is [offsets[v*B+b], offsets[v*B+b+1])
+ *   counts[GS_COUNT_RECORDS] = offsets[V*B].
+ * mode: GS_LOD_BLOCKWISE (the paper's method) or GS_LOD_ALL_FINEST (every
+ * non-empty block at level L-1, no culling: the plain comparator).
+ * thresholds: host array [L-1], ascending, scene units. */
+#define GS_LOD_BLOCKWISE 0
+#define GS_LOD_ALL_FINEST 1
+gs_status gs_lod_select(const gs_blocks* blocks /* host struct */, const double* thresholds /* host */,
+                        int32_t mode, const gs_camera* cams, int32_t n_views, int8_t* level, int64_t* offsets,
+                        int64_t* counts, void* stream);
+
+/* Projection of every selected record (Sec. 3.1, "proj" in Eq. 1, following
+ * 3DGS): EWA splat of the 3D covariance R S S^T R^T through the pinhole
+ * Jacobian (guard band 1.3x the half field of view) with a 0.3 px^2 dilation,
+ * 3-sigma screen footprint, view-dependent colour from degree <= sh_degree real
+ * SH (clamped at 0), depth = camera z.  Geometry is computed in FP64 in a fixed
+ * operation order so footprints and depth keys are reproducible bit for bit.
+ *   levels: host array [n_levels] of device Gaussian sets
+ *   records [record_capacity] of gs_record_bytes(); depth_keys [record_capacity]
+ *   u32 (float bits of depth; 0xFFFFFFFF if culled); tiles_touched
+ *   [record_capacity] int32 (0 if culled). */
+gs_status gs_preprocess(const gs_gaussians* levels, const gs_blocks* blocks, const int8_t* level,
+                        const int64_t* offsets, const gs_camera* cams, int32_t n_views, int32_t width,
+                        int32_t height, int32_t sh_degree, const gs_tuning* tuning, int64_t record_capacity,
+                        void* records, uint32_t* depth_keys, int32_t* tiles_touched, int64_t* counts,
+                        void* stream);
+
+/* Tile binning: one (tile, record) pair per tile under each visible record's
+ * footprint, sorted by (view*tiles + tile, depth, record index) with a stable
+ * LSD radix sort (depth digits on the visible records, tile digits on the
+ * pairs), so ties go to the lower record index.
+ *   pair_tiles / pair_records [pair_capacity] u32: sorted pairs
+ *   tile_ranges [V*tiles][2] u32: [start, end) of each tile in the sorted pairs
+ *   ws / ws_bytes: workspace of at least gs_workspace_bytes(GS_WS_BIN_SORT, ...). */
+gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys, const int32_t* tiles_touched,
+                      int32_t n_views, int32_t width, int32_t height, const gs_tuning* tuning,
+                      int64_t record_capacity, int64_t pair_capacity, uint32_t* pair_tiles,
+                      uint32_t* pair_records, uint32_t* tile_ranges, int64_t* counts, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/* Per-tile front-to-back alpha compositing of Eq. 1: for each pixel, walk its
+ * tile's list; skip entries whose footprint does not hold the pixel; alpha =
+ * min(0.99, opacity * exp(-d^T conic d / 2)); skip alpha < 1/255; stop before an
+ * entry that would take the transmittance below 1e-4.
+ *   bg: host float[3] background colour. */
+gs_status gs_rasterize_fwd(const void* records, const uint32_t* pair_records, const uint32_t* tile_ranges,
+                           int32_t n_views, int32_t width, int32_t height, const float* bg,
+                           const gs_tuning* tuning, float* rgb, float* T_final, int32_t* n_last, void* stream);
+
+/* Adjoint of the forward pass (Sec. 3.1, differentiable rendering): given
+ * d_rgb = dL/d rgb [V][3][H][W], accumulates (+=) dL/d(parameters) into
+ * grads[n_levels] (host array of device buffers shaped like the levels).  The
+ * blend state of each pixel is recomputed front to back from the saved T_final
+ * and n_last, so no per-(pixel, Gaussian) state is stored.  Accumulation uses
+ * FP32 atomics: results are reproducible to rounding, not bit for bit.
+ * ws: at least gs_workspace_bytes(GS_WS_RASTERIZE_BWD, ...). */
+gs_status gs_rasterize_bwd(const void* records, const uint32_t* pair_records, const uint32_t* tile_ranges,
+                           int32_t n_views, int32_t width, int32_t height, const float* bg,
+                           const gs_tuning* tuning, const float* rgb, const float* T_final, const int32_t* n_last,
+                           const float* d_rgb, const gs_gaussians* levels, const gs_blocks* blocks,
+                           const int8_t* level, const int64_t* offsets, const gs_camera* cams, int32_t sh_degree,
+                           int64_t record_capacity, const int64_t* counts, const gs_gaussian_grads* grads,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* Block bounds of Eq. 6 for every block from its finest-level centres:
+ * per axis, med = lower median (rank floor((n-1)/2)), MAD = lower median of
+ * |p - med| (FP64), lo = max(min p, med - n_mad * MAD), hi = min(max p,
+ * med + n_mad * MAD).  Empty blocks get lo = +inf, hi = -inf.
+ *   finest: device Gaussian set of the finest level; lvl_off/lvl_cnt: device
+ *   [B][L]; lo, hi: device [B][3] FP64.  ws: gs_mad_workspace_bytes(). */
+size_t gs_mad_workspace_bytes(int64_t max_block_count);
+gs_status gs_mad_bounds(const gs_gaussians* finest, const int64_t* lvl_off, const int64_t* lvl_cnt,
+                        int32_t n_blocks, int32_t n_levels, int64_t max_block_count, double n_mad, double* lo,
+                        double* hi, void* ws, size_t ws_bytes, void* stream);
+
+/* Name of a status code (static string, or a thread-local buffer after GS_ERR_HIP). */
+const char* gs_status_string(gs_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS_H_ */

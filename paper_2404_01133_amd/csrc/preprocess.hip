@@ -1,0 +1,129 @@
+// Projection of the selected Gaussians to screen-space records (the "proj"
+// operator of Eq. 1 in Sec. 3.1, which the paper takes from 3DGS: EWA splatting
+// through the local affine approximation of the pinhole map, 0.3 px^2 low-pass
+// dilation, 3-sigma footprint, SH colour).
+//
+// Memory-bound: each record reads 12 B of centre for every selected Gaussian,
+// 28 B of rotation/scale and 4 B of opacity for those in front of the camera,
+// and the 192 B of SH only for those that survive the footprint cull.  Loads
+// are structure-of-arrays, so consecutive lanes touch consecutive words.
+//
+// The geometry that decides integers (culls, footprint, depth key) is FP64 in
+// a fixed operation order; this file is compiled with -ffp-contract=off so the
+// compiler cannot fuse or reorder those operations.
+#include "project.h"
+
+namespace gs {
+namespace {
+
+constexpr int kPreThreads = 256;
+
+struct PreArgs {
+  LevelPtrs lv[kMaxLevels];
+  const int64_t* lvl_off;
+  const int8_t* level;
+  const int64_t* offsets;
+  const gs_camera* cams;
+  int64_t capacity;
+  int32_t B, L, V, W, H, tw, th, sh_degree;
+};
+
+__global__ void __launch_bounds__(kPreThreads) preprocess_kernel(PreArgs a, Record* __restrict__ records,
+                                                                 uint32_t* __restrict__ depth_keys,
+                                                                 int32_t* __restrict__ tiles_touched,
+                                                                 int64_t* __restrict__ counts) {
+  int64_t n_rec = counts[GS_COUNT_RECORDS];
+  if (n_rec > a.capacity) {
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+      atomicOr((unsigned long long*)&counts[GS_COUNT_FLAGS], (unsigned long long)GS_FLAG_RECORDS);
+    n_rec = a.capacity;
+  }
+  const int nseg = a.V * a.B;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_rec; g += stride) {
+    const int p = find_segment(a.offsets, nseg, g);
+    const int v = p / a.B, b = p - v * a.B;
+    const int l = a.level[p];
+    const LevelPtrs& L = a.lv[l];
+    const int64_t gi = a.lvl_off[(int64_t)b * a.L + l] + (g - a.offsets[p]);
+    const gs_camera& cam = a.cams[v];
+    Geo o;
+    uint32_t key = kCulledKey;
+    int32_t tt = 0;
+    if (project_geo(L, gi, cam, a.W, a.H, o)) {
+      tt = (o.i1 / a.tw - o.i0 / a.tw + 1) * (o.j1 / a.th - o.j0 / a.th + 1);
+      key = __float_as_uint(o.depth);
+      Record rec;
+      rec.u_rel = (float)(o.u - (double)o.i0);
+      rec.v_rel = (float)(o.v - (double)o.j0);
+      rec.px = (uint32_t)o.i0 | ((uint32_t)(o.i1 - o.i0) << 16);
+      rec.py = (uint32_t)o.j0 | ((uint32_t)(o.j1 - o.j0) << 16);
+      rec.ca = (float)(kConicScale * sqrt(o.c / o.det));
+      rec.cb = (float)(-kConicScale * o.b / sqrt(o.c * o.det));
+      rec.cc = (float)(kConicScale / sqrt(o.c));
+      rec.opac = (float)o.opac;
+      double C[3];
+      camera_centre(cam, C);
+      const double d0 = o.m[0] - C[0], d1 = o.m[1] - C[1], d2 = o.m[2] - C[2];
+      const double dn = sqrt((d0 * d0 + d1 * d1) + d2 * d2);
+      double Y[16];
+      const int nk = sh_basis(d0 / dn, d1 / dn, d2 / dn, a.sh_degree, Y);
+      double col[3] = {0.0, 0.0, 0.0};
+      for (int k = 0; k < nk; ++k)
+        for (int ch = 0; ch < 3; ++ch) col[ch] += Y[k] * (double)L.sh[(int64_t)(3 * k + ch) * L.n + gi];
+      rec.r = (float)dmax_(col[0] + 0.5, 0.0);
+      rec.g = (float)dmax_(col[1] + 0.5, 0.0);
+      rec.b = (float)dmax_(col[2] + 0.5, 0.0);
+      rec.view = (uint32_t)v;
+      records[g] = rec;
+    }
+    depth_keys[g] = key;
+    tiles_touched[g] = tt;
+  }
+}
+
+}  // namespace
+}  // namespace gs
+
+extern "C" gs_status gs_preprocess(const gs_gaussians* levels, const gs_blocks* blocks, const int8_t* level,
+                                   const int64_t* offsets, const gs_camera* cams, int32_t n_views, int32_t width,
+                                   int32_t height, int32_t sh_degree, const gs_tuning* tuning,
+                                   int64_t record_capacity, void* records, uint32_t* depth_keys,
+                                   int32_t* tiles_touched, int64_t* counts, void* stream) {
+  using namespace gs;
+  if (!levels || !blocks || !level || !offsets || !cams || !tuning || !counts) return GS_ERR_INVALID_ARG;
+  if (n_views <= 0 || width <= 0 || height <= 0 || width > 65535 || height > 65535) return GS_ERR_INVALID_ARG;
+  if (sh_degree < 0 || sh_degree > 3) return GS_ERR_INVALID_ARG;
+  if (blocks->n_blocks <= 0 || blocks->n_levels <= 0 || blocks->n_levels > kMaxLevels || !blocks->lvl_off)
+    return GS_ERR_INVALID_ARG;
+  if (!tile_shape_supported(tuning->tile_w, tuning->tile_h)) return GS_ERR_UNSUPPORTED;
+  if (record_capacity < 0 || (record_capacity > 0 && (!records || !depth_keys || !tiles_touched)))
+    return GS_ERR_INVALID_ARG;
+  if ((int64_t)n_views * blocks->n_blocks > (int64_t)1 << 30) return GS_ERR_INVALID_ARG;
+  if (record_capacity >= ((int64_t)1 << 32)) return GS_ERR_INVALID_ARG;  // record ids are u32
+  PreArgs a{};
+  for (int l = 0; l < blocks->n_levels; ++l) {
+    const gs_gaussians& g = levels[l];
+    if (g.n < 0 || (g.n > 0 && (!g.means || !g.scales || !g.quats || !g.opac || !g.sh))) return GS_ERR_INVALID_ARG;
+    a.lv[l] = LevelPtrs{g.means, g.scales, g.quats, g.opac, g.sh, g.n};
+  }
+  a.lvl_off = blocks->lvl_off;
+  a.level = level;
+  a.offsets = offsets;
+  a.cams = cams;
+  a.capacity = record_capacity;
+  a.B = blocks->n_blocks;
+  a.L = blocks->n_levels;
+  a.V = n_views;
+  a.W = width;
+  a.H = height;
+  a.tw = tuning->tile_w;
+  a.th = tuning->tile_h;
+  a.sh_degree = sh_degree;
+  int64_t blocks_needed = (record_capacity + kPreThreads - 1) / kPreThreads;
+  int grid = (int)(blocks_needed < 8192 ? (blocks_needed > 0 ? blocks_needed : 1) : 8192);
+  hipLaunchKernelGGL(preprocess_kernel, dim3(grid), dim3(kPreThreads), 0, (hipStream_t)stream, a,
+                     (Record*)records, depth_keys, tiles_touched, counts);
+  GS_LAUNCH_CHECK();
+  return GS_OK;
+}

@@ -1,0 +1,230 @@
+// FP64 projection of one Gaussian (the "proj" operator of Eq. 1, Sec. 3.1,
+// following 3DGS), shared by the forward preprocess and its adjoint.  Every
+// translation unit that includes this header is compiled with
+// -ffp-contract=off: the operation order below is the reproducibility contract
+// for culls, footprints and depth keys.
+#pragma once
+
+#include "gs_common.h"
+
+namespace gs {
+
+constexpr int kMaxLevels = 8;
+
+struct LevelPtrs {
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* opac;
+  const float* sh;
+  int64_t n;
+};
+
+__device__ __forceinline__ double dmin_(double a, double b) { return b < a ? b : a; }
+__device__ __forceinline__ double dmax_(double a, double b) { return a < b ? b : a; }
+
+// index of the (view, block) segment holding record g: largest p with offsets[p] <= g
+__device__ __forceinline__ int find_segment(const int64_t* __restrict__ offsets, int nseg, int64_t g) {
+  int lo = 0, hi = nseg;  // invariant: offsets[lo] <= g < offsets[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (offsets[mid] <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Real SH basis up to degree 3 (m = -l..l, Condon-Shortley phase kept) at a unit
+// direction, and optionally its gradient with respect to (x, y, z) treated as
+// independent variables.
+constexpr double kSH00 = 0.28209479177387814;
+constexpr double kSH1 = 0.4886025119029199;
+constexpr double kSH2a = 1.0925484305920792;
+constexpr double kSH2b = 0.31539156525252005;
+constexpr double kSH2c = 0.5462742152960396;
+constexpr double kSH3a = 0.5900435899266435;
+constexpr double kSH3b = 2.890611442640554;
+constexpr double kSH3c = 0.4570457994644658;
+constexpr double kSH3d = 0.3731763325901154;
+constexpr double kSH3e = 1.445305721320277;
+
+__device__ __forceinline__ int sh_basis(double x, double y, double z, int deg, double Y[16]) {
+  Y[0] = kSH00;
+  if (deg < 1) return 1;
+  Y[1] = -kSH1 * y;
+  Y[2] = kSH1 * z;
+  Y[3] = -kSH1 * x;
+  if (deg < 2) return 4;
+  const double xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = kSH2a * (x * y);
+  Y[5] = -kSH2a * (y * z);
+  Y[6] = kSH2b * (2.0 * zz - xx - yy);
+  Y[7] = -kSH2a * (x * z);
+  Y[8] = kSH2c * (xx - yy);
+  if (deg < 3) return 9;
+  Y[9] = -kSH3a * (y * (3.0 * xx - yy));
+  Y[10] = kSH3b * (x * y * z);
+  Y[11] = -kSH3c * (y * (4.0 * zz - xx - yy));
+  Y[12] = kSH3d * (z * (2.0 * zz - 3.0 * xx - 3.0 * yy));
+  Y[13] = -kSH3c * (x * (4.0 * zz - xx - yy));
+  Y[14] = kSH3e * (z * (xx - yy));
+  Y[15] = -kSH3a * (x * (xx - 3.0 * yy));
+  return 16;
+}
+
+// d Y_k / d(x, y, z) of the polynomial forms above.
+__device__ __forceinline__ void sh_basis_grad(double x, double y, double z, int deg, double dY[16][3]) {
+  dY[0][0] = dY[0][1] = dY[0][2] = 0.0;
+  if (deg < 1) return;
+  dY[1][0] = 0.0;   dY[1][1] = -kSH1; dY[1][2] = 0.0;
+  dY[2][0] = 0.0;   dY[2][1] = 0.0;   dY[2][2] = kSH1;
+  dY[3][0] = -kSH1; dY[3][1] = 0.0;   dY[3][2] = 0.0;
+  if (deg < 2) return;
+  dY[4][0] = kSH2a * y;          dY[4][1] = kSH2a * x;          dY[4][2] = 0.0;
+  dY[5][0] = 0.0;                dY[5][1] = -kSH2a * z;         dY[5][2] = -kSH2a * y;
+  dY[6][0] = -2.0 * kSH2b * x;   dY[6][1] = -2.0 * kSH2b * y;   dY[6][2] = 4.0 * kSH2b * z;
+  dY[7][0] = -kSH2a * z;         dY[7][1] = 0.0;                dY[7][2] = -kSH2a * x;
+  dY[8][0] = 2.0 * kSH2c * x;    dY[8][1] = -2.0 * kSH2c * y;   dY[8][2] = 0.0;
+  if (deg < 3) return;
+  const double xx = x * x, yy = y * y, zz = z * z;
+  dY[9][0] = -6.0 * kSH3a * x * y;
+  dY[9][1] = -3.0 * kSH3a * (xx - yy);
+  dY[9][2] = 0.0;
+  dY[10][0] = kSH3b * y * z;
+  dY[10][1] = kSH3b * x * z;
+  dY[10][2] = kSH3b * x * y;
+  dY[11][0] = 2.0 * kSH3c * x * y;
+  dY[11][1] = -kSH3c * (4.0 * zz - xx - 3.0 * yy);
+  dY[11][2] = -8.0 * kSH3c * y * z;
+  dY[12][0] = -6.0 * kSH3d * x * z;
+  dY[12][1] = -6.0 * kSH3d * y * z;
+  dY[12][2] = kSH3d * (6.0 * zz - 3.0 * xx - 3.0 * yy);
+  dY[13][0] = -kSH3c * (4.0 * zz - 3.0 * xx - yy);
+  dY[13][1] = 2.0 * kSH3c * x * y;
+  dY[13][2] = -8.0 * kSH3c * x * z;
+  dY[14][0] = 2.0 * kSH3e * x * z;
+  dY[14][1] = -2.0 * kSH3e * y * z;
+  dY[14][2] = kSH3e * (xx - yy);
+  dY[15][0] = -3.0 * kSH3a * (xx - yy);
+  dY[15][1] = 6.0 * kSH3a * x * y;
+  dY[15][2] = 0.0;
+}
+
+// Everything the forward projection computes for one Gaussian.
+struct Geo {
+  double m[3];         // centre
+  double tx, ty, tz;   // camera-space centre
+  double rz, ux, uy;   // 1/tz, tx/tz, ty/tz
+  bool clamp_x, clamp_y;
+  double uxc, uyc;     // guard-band clamped tan values
+  double q[4];         // normalised quaternion (w, x, y, z)
+  double qinv;         // 1 / |q|
+  double s[3];
+  double Rq[3][3];
+  double Lm[3][3];     // Rq diag(s)
+  double WL[3][3];     // R_cam Lm
+  double J00, J02, J11, J12;
+  double M[2][3];      // J WL
+  double n0, n1, a, b, c, det;
+  double u, v;
+  float depth;
+  int i0, i1, j0, j1;
+  double opac;
+};
+
+// Decides culling and the footprint; returns false if culled.  Reads the
+// centre and opacity first and the rotation/scale only when still visible.
+__device__ __forceinline__ bool project_geo(const LevelPtrs& L, int64_t gi, const gs_camera& cam, int W, int H,
+                                            Geo& o) {
+  const int64_t n = L.n;
+  const double* R = cam.R;
+  o.m[0] = L.means[gi];
+  o.m[1] = L.means[n + gi];
+  o.m[2] = L.means[2 * n + gi];
+  o.tx = ((R[0] * o.m[0] + R[1] * o.m[1]) + R[2] * o.m[2]) + cam.t[0];
+  o.ty = ((R[3] * o.m[0] + R[4] * o.m[1]) + R[5] * o.m[2]) + cam.t[1];
+  o.tz = ((R[6] * o.m[0] + R[7] * o.m[1]) + R[8] * o.m[2]) + cam.t[2];
+  if (!(o.tz > cam.znear)) return false;
+  o.opac = L.opac[gi];
+  if (!(o.opac >= 1.0 / 255.0)) return false;
+  o.depth = (float)o.tz;
+  const double q0 = L.quats[gi], q1 = L.quats[n + gi], q2 = L.quats[2 * n + gi], q3 = L.quats[3 * n + gi];
+  const double qn2 = ((q0 * q0 + q1 * q1) + q2 * q2) + q3 * q3;
+  if (!(qn2 > 0.0 && qn2 <= 1.0e300)) return false;
+  o.qinv = 1.0 / sqrt(qn2);
+  const double w = q0 * o.qinv, x = q1 * o.qinv, y = q2 * o.qinv, z = q3 * o.qinv;
+  o.q[0] = w; o.q[1] = x; o.q[2] = y; o.q[3] = z;
+  o.Rq[0][0] = 1.0 - 2.0 * (y * y + z * z);
+  o.Rq[0][1] = 2.0 * (x * y - w * z);
+  o.Rq[0][2] = 2.0 * (x * z + w * y);
+  o.Rq[1][0] = 2.0 * (x * y + w * z);
+  o.Rq[1][1] = 1.0 - 2.0 * (x * x + z * z);
+  o.Rq[1][2] = 2.0 * (y * z - w * x);
+  o.Rq[2][0] = 2.0 * (x * z - w * y);
+  o.Rq[2][1] = 2.0 * (y * z + w * x);
+  o.Rq[2][2] = 1.0 - 2.0 * (x * x + y * y);
+  o.s[0] = L.scales[gi];
+  o.s[1] = L.scales[n + gi];
+  o.s[2] = L.scales[2 * n + gi];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) o.Lm[i][j] = o.Rq[i][j] * o.s[j];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      o.WL[i][j] = (R[3 * i + 0] * o.Lm[0][j] + R[3 * i + 1] * o.Lm[1][j]) + R[3 * i + 2] * o.Lm[2][j];
+  o.rz = 1.0 / o.tz;
+  o.ux = o.tx * o.rz;
+  o.uy = o.ty * o.rz;
+  const double tanx = (0.5 * W) / cam.fx, tany = (0.5 * H) / cam.fy;
+  const double limx = 1.3 * tanx, limy = 1.3 * tany;
+  o.uxc = dmin_(limx, dmax_(-limx, o.ux));
+  o.uyc = dmin_(limy, dmax_(-limy, o.uy));
+  o.clamp_x = o.uxc != o.ux;
+  o.clamp_y = o.uyc != o.uy;
+  o.J00 = cam.fx * o.rz;
+  o.J02 = -(cam.fx * o.uxc) * o.rz;
+  o.J11 = cam.fy * o.rz;
+  o.J12 = -(cam.fy * o.uyc) * o.rz;
+  for (int j = 0; j < 3; ++j) {
+    o.M[0][j] = o.J00 * o.WL[0][j] + o.J02 * o.WL[2][j];
+    o.M[1][j] = o.J11 * o.WL[1][j] + o.J12 * o.WL[2][j];
+  }
+  o.n0 = (o.M[0][0] * o.M[0][0] + o.M[0][1] * o.M[0][1]) + o.M[0][2] * o.M[0][2];
+  o.n1 = (o.M[1][0] * o.M[1][0] + o.M[1][1] * o.M[1][1]) + o.M[1][2] * o.M[1][2];
+  o.b = (o.M[0][0] * o.M[1][0] + o.M[0][1] * o.M[1][1]) + o.M[0][2] * o.M[1][2];
+  o.a = o.n0 + 0.3;
+  o.c = o.n1 + 0.3;
+  const double cr0 = o.M[0][1] * o.M[1][2] - o.M[0][2] * o.M[1][1];
+  const double cr1 = o.M[0][2] * o.M[1][0] - o.M[0][0] * o.M[1][2];
+  const double cr2 = o.M[0][0] * o.M[1][1] - o.M[0][1] * o.M[1][0];
+  o.det = (((cr0 * cr0 + cr1 * cr1) + cr2 * cr2) + 0.3 * (o.n0 + o.n1)) + 0.09;
+  o.u = cam.fx * o.ux + cam.cx;
+  o.v = cam.fy * o.uy + cam.cy;
+  if (!(o.det > 0.0 && o.det <= 1.0e300)) return false;
+  const double hd = 0.5 * (o.a - o.c);
+  const double lmax = 0.5 * (o.a + o.c) + sqrt(hd * hd + o.b * o.b);
+  if (!(lmax <= 1.0e300)) return false;
+  const double r = ceil(3.0 * sqrt(lmax));
+  const double i0 = dmax_(0.0, ceil((o.u - r) - 0.5));
+  const double i1 = dmin_((double)(W - 1), floor((o.u + r) - 0.5));
+  const double j0 = dmax_(0.0, ceil((o.v - r) - 0.5));
+  const double j1 = dmin_((double)(H - 1), floor((o.v + r) - 0.5));
+  if (!(i0 <= i1) || !(j0 <= j1)) return false;
+  o.i0 = (int)i0;
+  o.i1 = (int)i1;
+  o.j0 = (int)j0;
+  o.j1 = (int)j1;
+  return true;
+}
+
+// Camera centre C = -R^T t.
+__device__ __forceinline__ void camera_centre(const gs_camera& cam, double C[3]) {
+  const double* R = cam.R;
+  C[0] = -((R[0] * cam.t[0] + R[3] * cam.t[1]) + R[6] * cam.t[2]);
+  C[1] = -((R[1] * cam.t[0] + R[4] * cam.t[1]) + R[7] * cam.t[2]);
+  C[2] = -((R[2] * cam.t[0] + R[5] * cam.t[1]) + R[8] * cam.t[2]);
+}
+
+// sqrt(log2(e) / 2): the conic factor is scaled so the Gaussian is exp2(-Q).
+constexpr double kConicScale = 0.84932180028801907;
+constexpr double kConicScale2 = 0.72134752044448170;  // log2(e) / 2
+
+}  // namespace gs

@@ -1,0 +1,576 @@
+// Tile binning: (tile, depth, record) ordering of the projected Gaussians.
+//
+// The (tile | depth) key of every (tile, Gaussian) pair is sorted by a stable
+// least-significant-digit radix sort.  Its low (depth) digits do not depend on
+// the tile, so those passes run once per visible record, before the pairs are
+// duplicated; only the tile digits run over the pairs.  Stages:
+//   1. compact   visible records -> (depth bits, record id), record order kept
+//   2. 4 passes  stable radix sort by the 32-bit depth key (ties keep record order)
+//   3. scan      pair offsets = exclusive prefix of tiles_touched in depth order
+//   4. emit      one (view*tiles + tile, record) pair per tile of each footprint
+//   5. passes    stable radix sort by tile id (ceil(bits / 8) passes)
+//   6. ranges    [start, end) of every tile
+// The result equals a sort by (tile, depth, record id).
+//
+// Scans and radix passes are single-pass with decoupled look-back: work-groups
+// take tile ids from an atomic counter in launch order, publish their local
+// aggregate, then walk back over predecessors' published values.  A work-group
+// only waits on tiles claimed before its own, so the waits always end; each
+// wait is still bounded (kSpinLimit) and raises GS_FLAG_WAIT if it gives up.
+// Every device size is read from the counts array, so nothing here needs a
+// host synchronisation and the whole stage can be captured in a HIP graph.
+#include "gs_common.h"
+
+namespace gs {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 8;
+constexpr int kTile = kThreads * kItems;  // 2048 keys per radix / scan tile
+constexpr int kRadix = 256;
+constexpr int kMaxPasses = 8;
+constexpr uint32_t kFlagAgg = 1u << 30;
+constexpr uint32_t kFlagInc = 2u << 30;
+constexpr uint32_t kValMask = (1u << 30) - 1;
+constexpr uint64_t kFlagAgg64 = 1ull << 62;
+constexpr uint64_t kFlagInc64 = 2ull << 62;
+constexpr uint64_t kValMask64 = (1ull << 62) - 1;
+constexpr int kPersistentBlocks = 1024;
+
+__device__ __forceinline__ int64_t count_clamped(const int64_t* counts, int idx, int64_t cap) {
+  int64_t n = counts[idx];
+  return n < cap ? n : cap;
+}
+
+__device__ __forceinline__ void raise_flag(int64_t* counts, int64_t bit) {
+  atomicOr((unsigned long long*)&counts[GS_COUNT_FLAGS], (unsigned long long)bit);
+}
+
+// ---------------------------------------------------------------------------
+// zero fill of look-back state, sized from a device count
+// ---------------------------------------------------------------------------
+__global__ void clear_words_kernel(uint32_t* __restrict__ p, int64_t fixed_words, const int64_t* counts, int count_idx,
+                                   int64_t cap, int64_t words_per_tile, int64_t tiles_extra) {
+  int64_t words = fixed_words;
+  if (count_idx >= 0) {
+    const int64_t n = count_clamped(counts, count_idx, cap);
+    words = ((n + kTile - 1) / kTile + tiles_extra) * words_per_tile;
+  }
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// block-level exclusive scan of one u32 per thread (256 threads, 4 waves)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_wave, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t inc = x;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += y;
+  }
+  if (lane == 63) s_wave[wid] = inc;
+  __syncthreads();
+  uint32_t wave_base = 0, tot = 0;
+  for (int w = 0; w < kThreads / 64; ++w) {
+    const uint32_t s = s_wave[w];
+    if (w < wid) wave_base += s;
+    tot += s;
+  }
+  *total = tot;
+  __syncthreads();
+  return wave_base + inc - x;
+}
+
+// ---------------------------------------------------------------------------
+// decoupled look-back on 64-bit status words (one per scan tile)
+// ---------------------------------------------------------------------------
+__device__ uint64_t lookback64(uint64_t* status, int64_t t, uint64_t aggregate, int64_t* counts) {
+  uint64_t excl = 0;
+  if (t == 0) {
+    store_agent(&status[0], kFlagInc64 | aggregate);
+    return 0;
+  }
+  store_agent(&status[t], kFlagAgg64 | aggregate);
+  int64_t k = t - 1;
+  int64_t spins = 0;
+  while (k >= 0) {
+    const uint64_t s = load_agent(&status[k]);
+    const uint64_t flag = s & ~kValMask64;
+    if (flag == 0) {
+      if (++spins > kSpinLimit) {
+        raise_flag(counts, GS_FLAG_WAIT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    excl += s & kValMask64;
+    if (flag == kFlagInc64) break;
+    --k;
+  }
+  store_agent(&status[t], kFlagInc64 | (excl + aggregate));
+  return excl;
+}
+
+// ---------------------------------------------------------------------------
+// 1. compaction of visible records
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) compact_kernel(const int32_t* __restrict__ tiles_touched,
+                                                           const uint32_t* __restrict__ depth_keys, int64_t cap,
+                                                           uint32_t* __restrict__ keys_out,
+                                                           uint32_t* __restrict__ vals_out, uint64_t* status,
+                                                           uint32_t* tile_counter, int64_t* counts) {
+  __shared__ uint32_t s_wave[kThreads / 64];
+  __shared__ uint32_t s_tile;
+  __shared__ uint64_t s_excl;
+  const int64_t n = count_clamped(counts, GS_COUNT_RECORDS, cap);
+  const int64_t ntiles = (n + kTile - 1) / kTile;
+  if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0) counts[GS_COUNT_VISIBLE] = 0;
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
+    __syncthreads();
+    const int64_t t = s_tile;
+    if (t >= ntiles) break;
+    const int64_t base = t * kTile + (int64_t)threadIdx.x * kItems;
+    uint32_t f[kItems];
+    uint32_t mine = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const int64_t idx = base + k;
+      f[k] = (idx < n && tiles_touched[idx] > 0) ? 1u : 0u;
+      mine += f[k];
+    }
+    uint32_t total;
+    const uint32_t excl_thread = block_excl_scan(mine, s_wave, &total);
+    if (threadIdx.x == 0) {
+      const uint64_t ex = lookback64(status, t, total, counts);
+      s_excl = ex;
+      if (t == ntiles - 1) counts[GS_COUNT_VISIBLE] = (int64_t)(ex + total);
+    }
+    __syncthreads();
+    uint64_t pos = s_excl + excl_thread;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      if (f[k]) {
+        const int64_t idx = base + k;
+        keys_out[pos] = depth_keys[idx];
+        vals_out[pos] = (uint32_t)idx;
+        ++pos;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 3. pair offsets: exclusive prefix of tiles_touched in depth order
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) pair_offsets_kernel(const uint32_t* __restrict__ sorted_records,
+                                                                const int32_t* __restrict__ tiles_touched,
+                                                                int64_t cap, uint32_t* __restrict__ pair_off,
+                                                                uint64_t* status, uint32_t* tile_counter,
+                                                                int64_t* counts, int64_t pair_cap) {
+  __shared__ uint32_t s_wave[kThreads / 64];
+  __shared__ uint32_t s_tile;
+  __shared__ uint64_t s_excl;
+  const int64_t n = count_clamped(counts, GS_COUNT_VISIBLE, cap);
+  const int64_t ntiles = (n + kTile - 1) / kTile;
+  if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0) counts[GS_COUNT_PAIRS] = 0;
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
+    __syncthreads();
+    const int64_t t = s_tile;
+    if (t >= ntiles) break;
+    const int64_t base = t * kTile + (int64_t)threadIdx.x * kItems;
+    uint32_t v[kItems];
+    uint32_t mine = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const int64_t idx = base + k;
+      v[k] = idx < n ? (uint32_t)tiles_touched[sorted_records[idx]] : 0u;
+      mine += v[k];
+    }
+    uint32_t total;
+    const uint32_t excl_thread = block_excl_scan(mine, s_wave, &total);
+    if (threadIdx.x == 0) {
+      const uint64_t ex = lookback64(status, t, total, counts);
+      s_excl = ex;
+      if (t == ntiles - 1) {
+        const int64_t m = (int64_t)(ex + total);
+        counts[GS_COUNT_PAIRS] = m;
+        if (m > pair_cap) raise_flag(counts, GS_FLAG_PAIRS);
+      }
+    }
+    __syncthreads();
+    uint64_t pos = s_excl + excl_thread;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const int64_t idx = base + k;
+      if (idx < n) pair_off[idx] = (uint32_t)(pos < 0xFFFFFFFFull ? pos : 0xFFFFFFFFull);
+      pos += v[k];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 4. pair emission
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) emit_kernel(const Record* __restrict__ records,
+                                                        const uint32_t* __restrict__ sorted_records,
+                                                        const uint32_t* __restrict__ pair_off, int64_t cap,
+                                                        const int64_t* counts, int64_t pair_cap, int tw, int th,
+                                                        int tiles_x_n, int tiles_per_view,
+                                                        uint32_t* __restrict__ out_tiles,
+                                                        uint32_t* __restrict__ out_records) {
+  const int64_t n = count_clamped(counts, GS_COUNT_VISIBLE, cap);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+    const uint32_t rid = sorted_records[j];
+    const uint4 w0 = *reinterpret_cast<const uint4*>(&records[rid]);
+    const uint32_t view = reinterpret_cast<const uint32_t*>(&records[rid])[11];
+    const int i0 = (int)(w0.z & 0xFFFFu), i1 = i0 + (int)(w0.z >> 16);
+    const int j0 = (int)(w0.w & 0xFFFFu), j1 = j0 + (int)(w0.w >> 16);
+    int64_t o = pair_off[j];
+    const uint32_t vbase = view * (uint32_t)tiles_per_view;
+    for (int ty = j0 / th; ty <= j1 / th; ++ty)
+      for (int tx = i0 / tw; tx <= i1 / tw; ++tx) {
+        if (o < pair_cap) {
+          out_tiles[o] = vbase + (uint32_t)(ty * tiles_x_n + tx);
+          out_records[o] = rid;
+        }
+        ++o;
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// radix sort: histograms of all passes in one read, then one kernel per pass
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) radix_hist_kernel(const uint32_t* __restrict__ keys,
+                                                              const int64_t* counts, int count_idx, int64_t cap,
+                                                              int shift0, int npasses,
+                                                              uint32_t* __restrict__ hist /*[passes][256]*/) {
+  __shared__ uint32_t s_hist[kMaxPasses][kRadix];
+  for (int i = threadIdx.x; i < npasses * kRadix; i += kThreads) (&s_hist[0][0])[i] = 0u;
+  __syncthreads();
+  const int64_t n = count_clamped(counts, count_idx, cap);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const uint32_t k = keys[i];
+    for (int p = 0; p < npasses; ++p) atomicAdd(&s_hist[p][(k >> (shift0 + 8 * p)) & 255u], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < npasses * kRadix; i += kThreads) {
+    const uint32_t c = (&s_hist[0][0])[i];
+    if (c) atomicAdd(&hist[i], c);
+  }
+}
+
+__global__ void __launch_bounds__(kRadix) radix_hist_scan_kernel(const uint32_t* __restrict__ hist,
+                                                                 uint32_t* __restrict__ global_off) {
+  __shared__ uint32_t s_wave[kThreads / 64];
+  const int p = blockIdx.x;
+  const uint32_t c = hist[p * kRadix + threadIdx.x];
+  uint32_t total;
+  const uint32_t ex = block_excl_scan(c, s_wave, &total);
+  global_off[p * kRadix + threadIdx.x] = ex;
+}
+
+__global__ void __launch_bounds__(kThreads) radix_pass_kernel(
+    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
+    uint32_t* __restrict__ vals_out, const int64_t* counts_in, int count_idx, int64_t cap, int shift,
+    const uint32_t* __restrict__ global_off, uint32_t* status, int64_t status_stride, uint32_t* tile_counter,
+    int64_t* counts) {
+  __shared__ uint32_t s_keys[kTile];
+  __shared__ uint32_t s_vals[kTile];
+  __shared__ uint32_t s_wave_hist[kThreads / 64][kRadix];
+  __shared__ uint32_t s_tile_excl[kRadix];
+  __shared__ uint32_t s_digit_base[kRadix];
+  __shared__ uint32_t s_wave[kThreads / 64];
+  __shared__ uint32_t s_tile;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t n = count_clamped(counts_in, count_idx, cap);
+  const int64_t ntiles = (n + kTile - 1) / kTile;
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
+    for (int i = threadIdx.x; i < (kThreads / 64) * kRadix; i += kThreads) (&s_wave_hist[0][0])[i] = 0u;
+    __syncthreads();
+    const int64_t t = s_tile;
+    if (t >= ntiles) break;
+    const int64_t tile_base = t * kTile;
+    const int tile_n = (int)((n - tile_base) < kTile ? (n - tile_base) : kTile);
+    // wave w owns the contiguous slice [w*64*kItems, (w+1)*64*kItems) of the tile;
+    // item k of lane l is element k*64 + l of that slice (coalesced loads)
+    uint32_t key[kItems], val[kItems], rank[kItems];
+    bool valid[kItems];
+    const int slice = wid * 64 * kItems;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const int li = slice + k * 64 + lane;
+      valid[k] = li < tile_n;
+      key[k] = valid[k] ? keys_in[tile_base + li] : 0u;
+      val[k] = valid[k] ? vals_in[tile_base + li] : 0u;
+    }
+    // stable rank inside the wave: items in order k, lanes in order within an item
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const uint32_t d = (key[k] >> shift) & 255u;
+      uint64_t peers = __ballot(valid[k]);
+#pragma unroll
+      for (int bit = 0; bit < 8; ++bit) {
+        const bool b = (d >> bit) & 1u;
+        const uint64_t m = __ballot(b);
+        peers &= b ? m : ~m;
+      }
+      uint32_t prev = 0;
+      if (valid[k]) prev = s_wave_hist[wid][d];
+      const uint32_t below = (uint32_t)lanemask_lt_count(peers);
+      rank[k] = prev + below;
+      if (valid[k] && below == 0) s_wave_hist[wid][d] = prev + (uint32_t)__popcll(peers);
+      __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // per digit: exclusive prefix over waves, tile count, tile-local digit prefix
+    const int d = threadIdx.x;
+    uint32_t run = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+      const uint32_t c = s_wave_hist[w][d];
+      s_wave_hist[w][d] = run;
+      run += c;
+    }
+    const uint32_t tile_cnt = run;
+    uint32_t tile_total;
+    const uint32_t tile_excl = block_excl_scan(tile_cnt, s_wave, &tile_total);
+    s_tile_excl[d] = tile_excl;
+    // decoupled look-back for digit d
+    uint32_t excl = 0;
+    uint32_t* st = status + t * status_stride + d;
+    if (t == 0) {
+      store_agent(st, kFlagInc | tile_cnt);
+    } else {
+      store_agent(st, kFlagAgg | tile_cnt);
+      int64_t k = t - 1;
+      int64_t spins = 0;
+      while (k >= 0) {
+        const uint32_t s = load_agent(status + k * status_stride + d);
+        const uint32_t flag = s & ~kValMask;
+        if (flag == 0) {
+          if (++spins > kSpinLimit) {
+            raise_flag(counts, GS_FLAG_WAIT);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        excl += s & kValMask;
+        if (flag == kFlagInc) break;
+        --k;
+      }
+      store_agent(st, kFlagInc | (excl + tile_cnt));
+    }
+    s_digit_base[d] = global_off[d] + excl;
+    __syncthreads();
+    // local scatter by digit, then coalesced write-out
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      if (valid[k]) {
+        const uint32_t dd = (key[k] >> shift) & 255u;
+        const uint32_t pos = s_tile_excl[dd] + s_wave_hist[wid][dd] + rank[k];
+        s_keys[pos] = key[k];
+        s_vals[pos] = val[k];
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < tile_n; i += kThreads) {
+      const uint32_t kk = s_keys[i];
+      const uint32_t dd = (kk >> shift) & 255u;
+      const uint32_t out = s_digit_base[dd] + ((uint32_t)i - s_tile_excl[dd]);
+      keys_out[out] = kk;
+      vals_out[out] = s_vals[i];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 6. tile ranges
+// ---------------------------------------------------------------------------
+__global__ void ranges_kernel(const uint32_t* __restrict__ tiles, const int64_t* counts, int64_t pair_cap,
+                              uint32_t* __restrict__ ranges) {
+  const int64_t m = count_clamped(counts, GS_COUNT_PAIRS, pair_cap);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) {
+    const uint32_t k = tiles[j];
+    if (j == 0 || tiles[j - 1] != k) ranges[2 * (int64_t)k] = (uint32_t)j;
+    if (j == m - 1 || tiles[j + 1] != k) ranges[2 * (int64_t)k + 1] = (uint32_t)(j + 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+struct SortWs {
+  uint32_t* dkeys_a;      // [rc]
+  uint32_t* dvals_a;      // [rc]
+  uint32_t* dkeys_b;      // [rc]
+  uint32_t* dvals_b;      // [rc]
+  uint32_t* pair_off;     // [rc]
+  uint32_t* ptiles_alt;   // [pc]
+  uint32_t* precs_alt;    // [pc]
+  uint32_t* hist;         // [2][kMaxPasses][256]
+  uint32_t* goff;         // [2][kMaxPasses][256]
+  uint32_t* counters;     // [64]
+  uint64_t* scan_status;  // [2][rtiles]
+  uint32_t* dstatus;      // [rtiles][4][256]   (tile-major so a prefix covers every pass)
+  uint32_t* pstatus;      // [ptiles][kMaxPasses][256]
+  size_t bytes;
+};
+
+inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+SortWs sort_ws_layout(char* base, int64_t rc, int64_t pc) {
+  SortWs w{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off = align_up(off + bytes);
+    return p;
+  };
+  const int64_t rtiles = (rc + kTile - 1) / kTile + 1;
+  const int64_t ptiles = (pc + kTile - 1) / kTile + 1;
+  w.dkeys_a = (uint32_t*)take(4 * (size_t)rc);
+  w.dvals_a = (uint32_t*)take(4 * (size_t)rc);
+  w.dkeys_b = (uint32_t*)take(4 * (size_t)rc);
+  w.dvals_b = (uint32_t*)take(4 * (size_t)rc);
+  w.pair_off = (uint32_t*)take(4 * (size_t)rc);
+  w.ptiles_alt = (uint32_t*)take(4 * (size_t)pc);
+  w.precs_alt = (uint32_t*)take(4 * (size_t)pc);
+  w.hist = (uint32_t*)take(4 * 2 * kMaxPasses * kRadix);
+  w.goff = (uint32_t*)take(4 * 2 * kMaxPasses * kRadix);
+  w.counters = (uint32_t*)take(4 * 64);
+  w.scan_status = (uint64_t*)take(8 * 2 * (size_t)rtiles);
+  w.dstatus = (uint32_t*)take(4 * 4 * (size_t)rtiles * kRadix);
+  w.pstatus = (uint32_t*)take(4 * (size_t)kMaxPasses * (size_t)ptiles * kRadix);
+  w.bytes = off;
+  return w;
+}
+
+int tile_bits(int64_t n_ids) {
+  int b = 0;
+  while (((int64_t)1 << b) < n_ids) ++b;
+  return b;
+}
+
+}  // namespace
+
+size_t bin_sort_ws_bytes(int64_t rc, int64_t pc) { return sort_ws_layout(nullptr, rc, pc).bytes; }
+
+}  // namespace gs
+
+extern "C" gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys, const int32_t* tiles_touched,
+                                 int32_t n_views, int32_t width, int32_t height, const gs_tuning* tuning,
+                                 int64_t record_capacity, int64_t pair_capacity, uint32_t* pair_tiles,
+                                 uint32_t* pair_records, uint32_t* tile_ranges, int64_t* counts, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  using namespace gs;
+  if (!records || !depth_keys || !tiles_touched || !tuning || !pair_tiles || !pair_records || !tile_ranges ||
+      !counts || !ws)
+    return GS_ERR_INVALID_ARG;
+  if (n_views <= 0 || width <= 0 || height <= 0 || width > 65535 || height > 65535) return GS_ERR_INVALID_ARG;
+  if (!tile_shape_supported(tuning->tile_w, tuning->tile_h)) return GS_ERR_UNSUPPORTED;
+  if (record_capacity <= 0 || pair_capacity <= 0) return GS_ERR_INVALID_ARG;
+  // look-back words carry 30-bit counts
+  if (record_capacity >= ((int64_t)1 << 30) || pair_capacity >= ((int64_t)1 << 30)) return GS_ERR_INVALID_ARG;
+  const SortWs w = sort_ws_layout((char*)ws, record_capacity, pair_capacity);
+  if (ws_bytes < w.bytes) return GS_ERR_WORKSPACE;
+  const int tw = tuning->tile_w, th = tuning->tile_h;
+  const int tx_n = tiles_x(width, tw), ty_n = tiles_y(height, th);
+  const int64_t tiles_per_view = (int64_t)tx_n * ty_n;
+  const int64_t n_tile_ids = tiles_per_view * n_views;
+  if (n_tile_ids >= ((int64_t)1 << 32)) return GS_ERR_INVALID_ARG;
+  const int tbits = tile_bits(n_tile_ids);
+  const int tpasses = tbits == 0 ? 0 : (tbits + 7) / 8;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t rtiles = (record_capacity + kTile - 1) / kTile + 1;
+  const dim3 blk(kThreads);
+  auto grid_for = [](int64_t items) {
+    int64_t g = (items + kThreads - 1) / kThreads;
+    return dim3((unsigned)(g < 1 ? 1 : (g > 4096 ? 4096 : g)));
+  };
+  auto persistent = [](int64_t cap) {
+    int64_t g = (cap + kTile - 1) / kTile;
+    return dim3((unsigned)(g < 1 ? 1 : (g > kPersistentBlocks ? kPersistentBlocks : g)));
+  };
+  // counters, histograms and scan status (sized by capacity: small)
+  hipLaunchKernelGGL(clear_words_kernel, dim3(1), blk, 0, s, w.counters, (int64_t)64, counts, -1, (int64_t)0,
+                     (int64_t)0, (int64_t)0);
+  hipLaunchKernelGGL(clear_words_kernel, dim3(8), blk, 0, s, w.hist, (int64_t)2 * kMaxPasses * kRadix, counts, -1,
+                     (int64_t)0, (int64_t)0, (int64_t)0);
+  hipLaunchKernelGGL(clear_words_kernel, grid_for(4 * rtiles), blk, 0, s, (uint32_t*)w.scan_status,
+                     (int64_t)4 * rtiles, counts, -1, (int64_t)0, (int64_t)0, (int64_t)0);
+  // look-back state of the depth passes, sized by the selected record count
+  hipLaunchKernelGGL(clear_words_kernel, grid_for(4 * rtiles * kRadix), blk, 0, s, w.dstatus, (int64_t)0, counts,
+                     GS_COUNT_RECORDS, record_capacity, (int64_t)4 * kRadix, (int64_t)0);
+  GS_LAUNCH_CHECK();
+  // 1. compaction
+  hipLaunchKernelGGL(compact_kernel, persistent(record_capacity), blk, 0, s, tiles_touched, depth_keys,
+                     record_capacity, w.dkeys_a, w.dvals_a, w.scan_status, w.counters + 0, counts);
+  GS_LAUNCH_CHECK();
+  // 2. depth sort, 4 passes of 8 bits: a -> b -> a -> b -> a
+  hipLaunchKernelGGL(radix_hist_kernel, dim3(512), blk, 0, s, w.dkeys_a, counts, GS_COUNT_VISIBLE, record_capacity,
+                     0, 4, w.hist);
+  hipLaunchKernelGGL(radix_hist_scan_kernel, dim3(4), dim3(kRadix), 0, s, w.hist, w.goff);
+  GS_LAUNCH_CHECK();
+  for (int p = 0; p < 4; ++p) {
+    const bool even = (p % 2) == 0;
+    hipLaunchKernelGGL(radix_pass_kernel, persistent(record_capacity), blk, 0, s, even ? w.dkeys_a : w.dkeys_b,
+                       even ? w.dvals_a : w.dvals_b, even ? w.dkeys_b : w.dkeys_a, even ? w.dvals_b : w.dvals_a,
+                       counts, GS_COUNT_VISIBLE, record_capacity, 8 * p, w.goff + p * kRadix,
+                       w.dstatus + p * kRadix, (int64_t)4 * kRadix, w.counters + 1 + p, counts);
+    GS_LAUNCH_CHECK();
+  }
+  // 3. pair offsets in depth order
+  hipLaunchKernelGGL(pair_offsets_kernel, persistent(record_capacity), blk, 0, s, w.dvals_a, tiles_touched,
+                     record_capacity, w.pair_off, w.scan_status + rtiles, w.counters + 8, counts, pair_capacity);
+  GS_LAUNCH_CHECK();
+  // 4. emission: into the buffer that the last tile pass will read last
+  uint32_t* em_tiles = (tpasses % 2 == 0) ? pair_tiles : w.ptiles_alt;
+  uint32_t* em_recs = (tpasses % 2 == 0) ? pair_records : w.precs_alt;
+  hipLaunchKernelGGL(emit_kernel, grid_for(record_capacity), blk, 0, s, (const Record*)records, w.dvals_a,
+                     w.pair_off, record_capacity, counts, pair_capacity, tw, th, tx_n, (int)tiles_per_view, em_tiles,
+                     em_recs);
+  GS_LAUNCH_CHECK();
+  // 5. tile passes
+  if (tpasses > 0) {
+    const int64_t ptiles = (pair_capacity + kTile - 1) / kTile + 1;
+    hipLaunchKernelGGL(clear_words_kernel, grid_for(tpasses * ptiles * kRadix), blk, 0, s, w.pstatus, (int64_t)0,
+                       counts, GS_COUNT_PAIRS, pair_capacity, (int64_t)tpasses * kRadix, (int64_t)0);
+    hipLaunchKernelGGL(radix_hist_kernel, dim3(512), blk, 0, s, em_tiles, counts, GS_COUNT_PAIRS, pair_capacity, 0,
+                       tpasses, w.hist + kMaxPasses * kRadix);
+    hipLaunchKernelGGL(radix_hist_scan_kernel, dim3(tpasses), dim3(kRadix), 0, s, w.hist + kMaxPasses * kRadix,
+                       w.goff + kMaxPasses * kRadix);
+    GS_LAUNCH_CHECK();
+    uint32_t* kin = em_tiles;
+    uint32_t* vin = em_recs;
+    for (int p = 0; p < tpasses; ++p) {
+      uint32_t* kout = (kin == pair_tiles) ? w.ptiles_alt : pair_tiles;
+      uint32_t* vout = (vin == pair_records) ? w.precs_alt : pair_records;
+      hipLaunchKernelGGL(radix_pass_kernel, persistent(pair_capacity), blk, 0, s, kin, vin, kout, vout, counts,
+                         GS_COUNT_PAIRS, pair_capacity, 8 * p, w.goff + kMaxPasses * kRadix + p * kRadix,
+                         w.pstatus + p * kRadix, (int64_t)tpasses * kRadix, w.counters + 16 + p, counts);
+      GS_LAUNCH_CHECK();
+      kin = kout;
+      vin = vout;
+    }
+  }
+  // 6. ranges
+  hipLaunchKernelGGL(clear_words_kernel, grid_for(2 * n_tile_ids), blk, 0, s, tile_ranges, 2 * n_tile_ids, counts,
+                     -1, (int64_t)0, (int64_t)0, (int64_t)0);
+  hipLaunchKernelGGL(ranges_kernel, dim3(2048), blk, 0, s, pair_tiles, counts, pair_capacity, tile_ranges);
+  GS_LAUNCH_CHECK();
+  return GS_OK;
+}

@@ -1,0 +1,238 @@
+"""Thin ctypes binding of libgs (include/gs.h): same names as the C entry points,
+argument marshalling only.  torch supplies device memory and the stream; every
+step of the rendering path runs in the HIP kernels of libgs.
+
+Importing this module loads torch first so that libgs binds to the HIP runtime
+torch already uses; if libgs.so is missing it raises immediately (there is no
+fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgs.so")
+
+GS_OK = 0
+GS_ERR_INVALID_ARG = -1
+GS_ERR_UNSUPPORTED = -2
+GS_ERR_WORKSPACE = -3
+GS_ERR_CAPACITY = -4
+GS_ERR_HIP = -5
+
+GS_COUNT_RECORDS, GS_COUNT_VISIBLE, GS_COUNT_PAIRS, GS_COUNT_FLAGS = 0, 1, 2, 3
+GS_COUNT_SLOTS = 8
+GS_FLAG_RECORDS, GS_FLAG_PAIRS, GS_FLAG_WAIT = 1, 2, 4
+GS_WS_BIN_SORT, GS_WS_RASTERIZE_BWD = 1, 2
+GS_LOD_BLOCKWISE, GS_LOD_ALL_FINEST = 0, 1
+
+c_double, c_int32, c_int64, c_void_p, c_size_t = (ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
+                                                  ctypes.c_size_t)
+
+
+class gs_camera(ctypes.Structure):
+    _fields_ = [("R", c_double * 9), ("t", c_double * 3), ("fx", c_double), ("fy", c_double), ("cx", c_double),
+                ("cy", c_double), ("znear", c_double), ("width", c_int32), ("height", c_int32),
+                ("pad", c_int32 * 2)]
+
+
+class gs_gaussians(ctypes.Structure):
+    _fields_ = [("means", c_void_p), ("scales", c_void_p), ("quats", c_void_p), ("opac", c_void_p),
+                ("sh", c_void_p), ("n", c_int64)]
+
+
+class gs_gaussian_grads(ctypes.Structure):
+    _fields_ = [("means", c_void_p), ("scales", c_void_p), ("quats", c_void_p), ("opac", c_void_p),
+                ("sh", c_void_p)]
+
+
+class gs_blocks(ctypes.Structure):
+    _fields_ = [("lo", c_void_p), ("hi", c_void_p), ("cell", c_void_p), ("lvl_off", c_void_p),
+                ("lvl_cnt", c_void_p), ("n_blocks", c_int32), ("n_levels", c_int32)]
+
+
+class gs_tuning(ctypes.Structure):
+    _fields_ = [("tile_w", c_int32), ("tile_h", c_int32), ("batch", c_int32), ("flags", c_int32)]
+
+
+assert ctypes.sizeof(gs_camera) == 152
+
+_lib = None
+
+_SIGNATURES = {
+    "gs_record_bytes": (c_size_t, []),
+    "gs_workspace_bytes": (c_size_t, [c_int32, c_int64, c_int64, c_int32, c_int32, c_int32, c_void_p]),
+    "gs_lod_select": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
+                                c_void_p]),
+    "gs_preprocess": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32,
+                                c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "gs_bin_sort": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_int64, c_int64,
+                              c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "gs_rasterize_fwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p,
+                                   c_void_p, c_void_p, c_void_p, c_void_p]),
+    "gs_rasterize_bwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p,
+                                   c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                   c_void_p, c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "gs_mad_workspace_bytes": (c_size_t, [c_int64]),
+    "gs_mad_bounds": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int64, c_double, c_void_p,
+                                c_void_p, c_void_p, c_size_t, c_void_p]),
+    "gs_status_string": (ctypes.c_char_p, [c_int32]),
+}
+
+
+def lib():
+    """Load libgs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libgs.so not found at %s: build it with __graft_entry__.build() "
+                               "(the HIP path has no fallback)" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class GsError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__("%s failed: %s" % (where, status_string(status)))
+        self.status = status
+
+
+def status_string(status: int) -> str:
+    return lib().gs_status_string(status).decode()
+
+
+def _check(status: int, where: str):
+    if status != GS_OK:
+        raise GsError(status, where)
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def record_bytes() -> int:
+    return int(lib().gs_record_bytes())
+
+
+def workspace_bytes(which: int, record_capacity: int, pair_capacity: int, n_views: int, width: int, height: int,
+                    tuning: gs_tuning) -> int:
+    return int(lib().gs_workspace_bytes(which, record_capacity, pair_capacity, n_views, width, height,
+                                        ctypes.byref(tuning)))
+
+
+def mad_workspace_bytes(max_block_count: int) -> int:
+    return int(lib().gs_mad_workspace_bytes(max_block_count))
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------
+def camera_struct(cam) -> gs_camera:
+    c = gs_camera()
+    R = np.asarray(cam.R, np.float64).reshape(9)
+    t = np.asarray(cam.t, np.float64).reshape(3)
+    for k in range(9):
+        c.R[k] = float(R[k])
+    for k in range(3):
+        c.t[k] = float(t[k])
+    c.fx, c.fy, c.cx, c.cy, c.znear = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy), float(cam.znear)
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+def cameras_to_device(cams, device="cuda") -> torch.Tensor:
+    """Pack cameras into a device byte tensor holding gs_camera[V]."""
+    arr = (gs_camera * len(cams))(*[camera_struct(c) for c in cams])
+    host = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8)
+    return host.to(device)
+
+
+def gaussians_struct(means, scales, quats, opac, sh) -> gs_gaussians:
+    n = int(opac.shape[0])
+    for t, shape in ((means, (3, n)), (scales, (3, n)), (quats, (4, n)), (opac, (n,)), (sh, (16, 3, n))):
+        if tuple(t.shape) != shape or t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("Gaussian arrays must be contiguous float32 device tensors in SoA layout; got %s %s"
+                             % (tuple(t.shape), t.dtype))
+    return gs_gaussians(means.data_ptr(), scales.data_ptr(), quats.data_ptr(), opac.data_ptr(), sh.data_ptr(), n)
+
+
+def grads_struct(gm, gs_, gq, go, gsh) -> gs_gaussian_grads:
+    return gs_gaussian_grads(gm.data_ptr(), gs_.data_ptr(), gq.data_ptr(), go.data_ptr(), gsh.data_ptr())
+
+
+def blocks_struct(lo, hi, cell, lvl_off, lvl_cnt) -> gs_blocks:
+    B, L = lvl_off.shape
+    ptr = lambda t: None if t is None else t.data_ptr()
+    return gs_blocks(ptr(lo), ptr(hi), ptr(cell), lvl_off.data_ptr(), lvl_cnt.data_ptr(), B, L)
+
+
+def tuning_struct(tile_w=16, tile_h=16, batch=256) -> gs_tuning:
+    return gs_tuning(tile_w, tile_h, batch, 0)
+
+
+# ---------------------------------------------------------------------------
+# entry points (same names as the C ABI, without the gs_ prefix)
+# ---------------------------------------------------------------------------
+def lod_select(blocks: gs_blocks, thresholds, mode, cams_dev, n_views, level, offsets, counts, stream=None):
+    thr = (c_double * max(1, len(thresholds)))(*[float(x) for x in thresholds])
+    _check(lib().gs_lod_select(ctypes.byref(blocks), thr, mode, _p(cams_dev), n_views, _p(level), _p(offsets),
+                               _p(counts), _stream(stream)), "gs_lod_select")
+
+
+def preprocess(levels, blocks: gs_blocks, level, offsets, cams_dev, n_views, width, height, sh_degree,
+               tuning: gs_tuning, record_capacity, records, depth_keys, tiles_touched, counts, stream=None):
+    arr = (gs_gaussians * len(levels))(*levels)
+    _check(lib().gs_preprocess(arr, ctypes.byref(blocks), _p(level), _p(offsets), _p(cams_dev), n_views, width, height,
+                               sh_degree, ctypes.byref(tuning), record_capacity, _p(records), _p(depth_keys),
+                               _p(tiles_touched), _p(counts), _stream(stream)), "gs_preprocess")
+
+
+def bin_sort(records, depth_keys, tiles_touched, n_views, width, height, tuning: gs_tuning, record_capacity,
+             pair_capacity, pair_tiles, pair_records, tile_ranges, counts, ws, stream=None):
+    _check(lib().gs_bin_sort(_p(records), _p(depth_keys), _p(tiles_touched), n_views, width, height,
+                             ctypes.byref(tuning), record_capacity, pair_capacity, _p(pair_tiles), _p(pair_records),
+                             _p(tile_ranges), _p(counts), _p(ws), ws.numel() * ws.element_size(), _stream(stream)),
+           "gs_bin_sort")
+
+
+def rasterize_fwd(records, pair_records, tile_ranges, n_views, width, height, bg, tuning: gs_tuning, rgb, T_final,
+                  n_last, stream=None):
+    bgv = (ctypes.c_float * 3)(*[float(x) for x in bg])
+    _check(lib().gs_rasterize_fwd(_p(records), _p(pair_records), _p(tile_ranges), n_views, width, height, bgv,
+                                  ctypes.byref(tuning), _p(rgb), _p(T_final), _p(n_last), _stream(stream)),
+           "gs_rasterize_fwd")
+
+
+def rasterize_bwd(records, pair_records, tile_ranges, n_views, width, height, bg, tuning: gs_tuning, rgb, T_final,
+                  n_last, d_rgb, levels, blocks: gs_blocks, level, offsets, cams_dev, sh_degree, record_capacity,
+                  counts, grads, ws, stream=None):
+    bgv = (ctypes.c_float * 3)(*[float(x) for x in bg])
+    lv = (gs_gaussians * len(levels))(*levels)
+    gr = (gs_gaussian_grads * len(grads))(*grads)
+    _check(lib().gs_rasterize_bwd(_p(records), _p(pair_records), _p(tile_ranges), n_views, width, height, bgv,
+                                  ctypes.byref(tuning), _p(rgb), _p(T_final), _p(n_last), _p(d_rgb), lv,
+                                  ctypes.byref(blocks), _p(level), _p(offsets), _p(cams_dev), sh_degree,
+                                  record_capacity, _p(counts), gr, _p(ws), ws.numel() * ws.element_size(),
+                                  _stream(stream)), "gs_rasterize_bwd")
+
+
+def mad_bounds(finest: gs_gaussians, lvl_off, lvl_cnt, n_mad, lo, hi, max_block_count, ws, stream=None):
+    B, L = lvl_off.shape
+    _check(lib().gs_mad_bounds(ctypes.byref(finest), _p(lvl_off), _p(lvl_cnt), B, L, max_block_count, float(n_mad),
+                               _p(lo), _p(hi), _p(ws), ws.numel() * ws.element_size(), _stream(stream)),
+           "gs_mad_bounds")

@@ -1,0 +1,237 @@
+"""Frame pipeline over the C ABI: device-resident scenes, frame buffers, and the
+differentiable render (torch.autograd.Function).
+
+A frame is five library calls on one stream (Sec. 3.3.2 then Sec. 3.1):
+    lod_select -> preprocess -> bin_sort -> rasterize_fwd  [-> rasterize_bwd]
+Buffers are allocated once per capacity and reused; data-dependent sizes stay
+on the device (the counts array), so a frame issues no host synchronisation
+unless a capacity check is requested.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import gs
+
+
+# ---------------------------------------------------------------------------
+# scenes
+# ---------------------------------------------------------------------------
+@dataclass
+class DeviceLevel:
+    means: torch.Tensor
+    scales: torch.Tensor
+    quats: torch.Tensor
+    opac: torch.Tensor
+    sh: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return int(self.opac.shape[0])
+
+    def struct(self) -> gs.gs_gaussians:
+        return gs.gaussians_struct(self.means, self.scales, self.quats, self.opac, self.sh)
+
+    def zeros_like(self) -> "DeviceLevel":
+        return DeviceLevel(*(torch.zeros_like(t) for t in (self.means, self.scales, self.quats, self.opac, self.sh)))
+
+
+class DeviceScene:
+    """Gaussians of every detail level plus the block table, in device memory."""
+
+    def __init__(self, levels, lvl_off, lvl_cnt, cells=None, lo=None, hi=None, device="cuda"):
+        self.levels = levels
+        self.device = device
+        self.lvl_off = torch.as_tensor(np.asarray(lvl_off, np.int64)).to(device)
+        self.lvl_cnt = torch.as_tensor(np.asarray(lvl_cnt, np.int64)).to(device)
+        self.lvl_cnt_host = np.asarray(lvl_cnt, np.int64)
+        self.cells = None if cells is None else torch.as_tensor(np.asarray(cells, np.float64)).to(device)
+        self.lo = None if lo is None else torch.as_tensor(np.asarray(lo, np.float64)).to(device)
+        self.hi = None if hi is None else torch.as_tensor(np.asarray(hi, np.float64)).to(device)
+
+    @property
+    def n_blocks(self) -> int:
+        return int(self.lvl_off.shape[0])
+
+    @property
+    def n_levels(self) -> int:
+        return len(self.levels)
+
+    @property
+    def n_finest(self) -> int:
+        return self.levels[-1].n
+
+    def max_records_per_view(self) -> int:
+        """Upper bound of the records one view can select."""
+        return int(self.lvl_cnt_host.max(axis=1).sum())
+
+    @staticmethod
+    def from_sets(levels_np, lvl_off, lvl_cnt, cells=None, lo=None, hi=None, device="cuda"):
+        levels = [DeviceLevel(*(torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
+                                for a in (g.means, g.scales, g.quats, g.opac, g.sh))) for g in levels_np]
+        return DeviceScene(levels, lvl_off, lvl_cnt, cells, lo, hi, device)
+
+    @staticmethod
+    def single(g, device="cuda") -> "DeviceScene":
+        """One block, one level: the plain rasterizer input."""
+        n = int(np.asarray(g.opac).shape[0])
+        return DeviceScene.from_sets([g], [[0]], [[n]], device=device)
+
+    @staticmethod
+    def from_tensors(means, scales, quats, opac, sh) -> "DeviceScene":
+        lev = DeviceLevel(means, scales, quats, opac, sh)
+        n = lev.n
+        return DeviceScene([lev], [[0]], [[n]], device=means.device)
+
+    @staticmethod
+    def from_block_scene(bs, device="cuda") -> "DeviceScene":
+        return DeviceScene.from_sets(bs.levels, bs.lvl_off, bs.lvl_cnt, cells=bs.cells, device=device)
+
+    def compute_bounds(self, n_mad: float = 4.0, stream=None):
+        """Eq. 6 block boxes from the finest level, on the GPU."""
+        B = self.n_blocks
+        self.lo = torch.empty((B, 3), dtype=torch.float64, device=self.device)
+        self.hi = torch.empty((B, 3), dtype=torch.float64, device=self.device)
+        max_cnt = int(self.lvl_cnt_host[:, -1].max()) if B else 0
+        ws = torch.empty(gs.mad_workspace_bytes(max_cnt), dtype=torch.uint8, device=self.device)
+        gs.mad_bounds(self.levels[-1].struct(), self.lvl_off, self.lvl_cnt, n_mad, self.lo, self.hi, max_cnt, ws,
+                      stream)
+        return self.lo, self.hi
+
+    def blocks_struct(self) -> gs.gs_blocks:
+        return gs.blocks_struct(self.lo, self.hi, self.cells, self.lvl_off, self.lvl_cnt)
+
+
+# ---------------------------------------------------------------------------
+# frame buffers
+# ---------------------------------------------------------------------------
+class Frame:
+    """All buffers of one batched frame (V views at one resolution)."""
+
+    def __init__(self, n_blocks, n_views, width, height, record_capacity, pair_capacity, tuning=None,
+                 device="cuda"):
+        self.B, self.V, self.W, self.H = n_blocks, n_views, width, height
+        self.tuning = tuning or gs.tuning_struct()
+        self.device = device
+        tw, th = self.tuning.tile_w, self.tuning.tile_h
+        self.tiles_x = (width + tw - 1) // tw
+        self.tiles_y = (height + th - 1) // th
+        self.n_tiles = self.tiles_x * self.tiles_y * n_views
+        d = device
+        self.level = torch.empty((n_views, n_blocks), dtype=torch.int8, device=d)
+        self.offsets = torch.empty(n_views * n_blocks + 1, dtype=torch.int64, device=d)
+        self.counts = torch.zeros(gs.GS_COUNT_SLOTS, dtype=torch.int64, device=d)
+        self.rgb = torch.empty((n_views, 3, height, width), dtype=torch.float32, device=d)
+        self.T = torch.empty((n_views, height, width), dtype=torch.float32, device=d)
+        self.n_last = torch.empty((n_views, height, width), dtype=torch.int32, device=d)
+        self.tile_ranges = torch.empty((self.n_tiles, 2), dtype=torch.int32, device=d)
+        self.record_capacity = 0
+        self.pair_capacity = 0
+        self.reserve(record_capacity, pair_capacity)
+
+    def reserve(self, record_capacity, pair_capacity):
+        d = self.device
+        if record_capacity > self.record_capacity:
+            self.record_capacity = int(record_capacity)
+            rb = gs.record_bytes()
+            self.records = torch.empty(self.record_capacity * rb, dtype=torch.uint8, device=d)
+            self.depth_keys = torch.empty(self.record_capacity, dtype=torch.int32, device=d)
+            self.tiles_touched = torch.empty(self.record_capacity, dtype=torch.int32, device=d)
+            self.bwd_ws = None
+        if pair_capacity > self.pair_capacity:
+            self.pair_capacity = int(pair_capacity)
+            self.pair_tiles = torch.empty(self.pair_capacity, dtype=torch.int32, device=d)
+            self.pair_records = torch.empty(self.pair_capacity, dtype=torch.int32, device=d)
+        nbytes = gs.workspace_bytes(gs.GS_WS_BIN_SORT, self.record_capacity, self.pair_capacity, self.V, self.W,
+                                    self.H, self.tuning)
+        if getattr(self, "sort_ws", None) is None or self.sort_ws.numel() < nbytes:
+            self.sort_ws = torch.empty(nbytes, dtype=torch.uint8, device=d)
+
+    def host_counts(self):
+        c = self.counts.cpu().numpy()
+        return dict(records=int(c[0]), visible=int(c[1]), pairs=int(c[2]), flags=int(c[3]))
+
+
+def render_frame(scene: DeviceScene, frame: Frame, cams_dev, mode=gs.GS_LOD_BLOCKWISE, thresholds=(200.0, 500.0),
+                 sh_degree=3, bg=(0.0, 0.0, 0.0), stream=None, check=True):
+    """LoD select + preprocess + bin/sort + composite for every view of `frame`.
+
+    With check=True the counts are read back once (a host sync); if a capacity
+    was too small the buffers grow and the frame is rendered again."""
+    for _ in range(4):
+        blocks = scene.blocks_struct()
+        gs.lod_select(blocks, thresholds, mode, cams_dev, frame.V, frame.level, frame.offsets, frame.counts, stream)
+        gs.preprocess([lv.struct() for lv in scene.levels], blocks, frame.level, frame.offsets, cams_dev, frame.V,
+                      frame.W, frame.H, sh_degree, frame.tuning, frame.record_capacity, frame.records,
+                      frame.depth_keys, frame.tiles_touched, frame.counts, stream)
+        gs.bin_sort(frame.records, frame.depth_keys, frame.tiles_touched, frame.V, frame.W, frame.H, frame.tuning,
+                    frame.record_capacity, frame.pair_capacity, frame.pair_tiles, frame.pair_records,
+                    frame.tile_ranges, frame.counts, frame.sort_ws, stream)
+        gs.rasterize_fwd(frame.records, frame.pair_records, frame.tile_ranges, frame.V, frame.W, frame.H, bg,
+                         frame.tuning, frame.rgb, frame.T, frame.n_last, stream)
+        if not check:
+            return frame.rgb
+        c = frame.host_counts()
+        if c["flags"] & gs.GS_FLAG_WAIT:
+            raise RuntimeError("a device-side wait gave up during the frame (counts=%s)" % c)
+        if c["flags"] == 0:
+            return frame.rgb
+        frame.reserve(max(frame.record_capacity, int(c["records"] * 1.1) + 1024),
+                      max(frame.pair_capacity, int(c["pairs"] * 1.25) + 4096))
+    raise RuntimeError("frame did not fit after growing the buffers: %s" % frame.host_counts())
+
+
+def backward_frame(scene: DeviceScene, frame: Frame, cams_dev, d_rgb, grads, sh_degree=3, bg=(0.0, 0.0, 0.0),
+                   stream=None):
+    """Accumulate dL/d(parameters) of every level into `grads` (list of DeviceLevel)."""
+    nbytes = gs.workspace_bytes(gs.GS_WS_RASTERIZE_BWD, frame.record_capacity, frame.pair_capacity, frame.V, frame.W,
+                                frame.H, frame.tuning)
+    if getattr(frame, "bwd_ws", None) is None or frame.bwd_ws.numel() < nbytes:
+        frame.bwd_ws = torch.empty(nbytes, dtype=torch.uint8, device=frame.device)
+    gs.rasterize_bwd(frame.records, frame.pair_records, frame.tile_ranges, frame.V, frame.W, frame.H, bg,
+                     frame.tuning, frame.rgb, frame.T, frame.n_last, d_rgb.contiguous(),
+                     [lv.struct() for lv in scene.levels], scene.blocks_struct(), frame.level, frame.offsets,
+                     cams_dev, sh_degree, frame.record_capacity, frame.counts,
+                     [gs.grads_struct(g.means, g.scales, g.quats, g.opac, g.sh) for g in grads], frame.bwd_ws, stream)
+
+
+# ---------------------------------------------------------------------------
+# differentiable render of one Gaussian set
+# ---------------------------------------------------------------------------
+class GaussianRasterize(torch.autograd.Function):
+    """image[V,3,H,W] = render(means[3,N], scales[3,N], quats[4,N], opac[N], sh[16,3,N]; cameras).
+
+    Forward runs the library's preprocess, bin_sort and rasterize_fwd; backward
+    runs rasterize_bwd, which recomputes the per-pixel blend state."""
+
+    @staticmethod
+    def forward(ctx, means, scales, quats, opac, sh, cams_dev, n_views, width, height, sh_degree, bg, frame):
+        scene = DeviceScene.from_tensors(means.detach().contiguous(), scales.detach().contiguous(),
+                                         quats.detach().contiguous(), opac.detach().contiguous(),
+                                         sh.detach().contiguous())
+        if frame is None:
+            frame = Frame(1, n_views, width, height, n_views * scene.n_finest, max(4096, 4 * n_views * scene.n_finest))
+        else:
+            frame.reserve(n_views * scene.n_finest, 0)
+        render_frame(scene, frame, cams_dev, mode=gs.GS_LOD_ALL_FINEST, thresholds=(), sh_degree=sh_degree, bg=bg)
+        ctx.scene, ctx.frame, ctx.cams = scene, frame, cams_dev
+        ctx.sh_degree, ctx.bg = sh_degree, bg
+        return frame.rgb.clone()
+
+    @staticmethod
+    def backward(ctx, d_rgb):
+        scene, frame = ctx.scene, ctx.frame
+        grads = [scene.levels[0].zeros_like()]
+        backward_frame(scene, frame, ctx.cams, d_rgb, grads, ctx.sh_degree, ctx.bg)
+        g = grads[0]
+        return g.means, g.scales, g.quats, g.opac, g.sh, None, None, None, None, None, None, None
+
+
+def rasterize(means, scales, quats, opac, sh, cams, sh_degree=3, bg=(0.0, 0.0, 0.0), frame=None):
+    """Differentiable render of one Gaussian set for a list of cameras (same size)."""
+    cams_dev = gs.cameras_to_device(cams, means.device)
+    W, H = cams[0].width, cams[0].height
+    return GaussianRasterize.apply(means, scales, quats, opac, sh, cams_dev, len(cams), W, H, sh_degree, bg, frame)

@@ -1,0 +1,319 @@
+"""GPU path vs the FP64 CPU oracle, through the C ABI.
+
+Integer work (footprints, tiles touched, depth keys, sorted pairs, tile ranges,
+LoD levels, MAD boxes) must be bit-exact; colours within 1e-4 max abs per
+channel (pixels where the oracle marks a threshold decision as ambiguous are
+excluded and counted); gradients within 1e-3 relative (per-tensor L2)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import lod as olod
+from paper_2404_01133_amd import gs, render, synth
+
+from gpu_util import frame_pairs, image_np, records_np, run_single, scaled_city
+
+pytestmark = pytest.mark.gpu
+
+COLOUR_TOL = 1e-4
+GRAD_TOL = 1e-3
+
+
+def compare_image(img_gpu, T_gpu, g, cam, bg=(0.0, 0.0, 0.0), sh_degree=3, max_amb_frac=2e-3):
+    ref, T_ref, nc, amb = oracle.render(g, cam, sh_degree=sh_degree, bg=bg)
+    ok = amb == 0
+    assert ok.mean() >= 1 - max_amb_frac, "too many ambiguous pixels: %d" % (~ok).sum()
+    err = np.abs(img_gpu - ref)[:, ok]
+    assert err.max() <= COLOUR_TOL, "max colour error %.3g at %s" % (err.max(), np.unravel_index(
+        np.argmax(np.abs(img_gpu - ref) * ok[None]), img_gpu.shape))
+    assert np.abs(T_gpu - T_ref)[ok].max() <= COLOUR_TOL
+    return ref
+
+
+def check_integer_parity(g, cam, frame, tile=(16, 16)):
+    n = g.opac.shape[0]
+    pr = oracle.project(g, cam, tile=tile)
+    keys = frame.depth_keys[:n].cpu().numpy().view(np.uint32)
+    tt = frame.tiles_touched[:n].cpu().numpy()
+    np.testing.assert_array_equal(tt, pr["tiles_touched"])
+    np.testing.assert_array_equal(keys, pr["depth_bits"])
+    vis = pr["visible"] > 0
+    rec = records_np(frame, n)
+    np.testing.assert_array_equal(rec["rect"][vis], pr["rect"][vis])
+    np.testing.assert_allclose(rec["u"][vis], pr["uv"][vis, 0], rtol=0, atol=1e-3)
+    t_ref, i_ref = oracle.pairs(g, cam, tile=tile)
+    t_gpu, i_gpu = frame_pairs(frame)
+    np.testing.assert_array_equal(t_gpu, t_ref)
+    np.testing.assert_array_equal(i_gpu, i_ref)
+    rng_ref = oracle.tile_ranges(t_ref, frame.n_tiles)
+    rng_gpu = frame.tile_ranges.cpu().numpy().view(np.uint32)
+    nonempty = rng_ref[:, 1] > rng_ref[:, 0]
+    np.testing.assert_array_equal(rng_gpu[nonempty], rng_ref[nonempty])
+    assert (rng_gpu[~nonempty, 1] == rng_gpu[~nonempty, 0]).all()
+    return pr
+
+
+# ---------------------------------------------------------------------------
+def test_small_render_config_bit_exact_integers_and_colour():
+    """4096 Gaussians in [-1,1]^3, 256x256, 16x16 tiles, seed 0."""
+    g, cam = synth.small_render_case(4096, seed=0)
+    print("case: small render 4096 @ 256x256", flush=True)
+    _, frame, _ = run_single(g, cam)
+    check_integer_parity(g, cam, frame)
+    img, T, _ = image_np(frame)
+    compare_image(img[0], T[0], g, cam)
+
+
+@pytest.mark.parametrize("seed,n,W,H", [(1, 3000, 200, 120), (2, 6000, 97, 61), (3, 500, 33, 17)])
+def test_ragged_images_and_seeds(seed, n, W, H):
+    g = synth.cube_gaussians(n, seed)
+    cam = synth.axis_camera(W, H)
+    print("case: ragged", seed, n, W, H, flush=True)
+    _, frame, _ = run_single(g, cam)
+    check_integer_parity(g, cam, frame)
+    img, T, _ = image_np(frame)
+    compare_image(img[0], T[0], g, cam)
+
+
+@pytest.mark.parametrize("tile,batch", [((8, 8), 64), ((16, 8), 128), ((32, 8), 256), ((32, 16), 64),
+                                        ((16, 16), 128)])
+def test_image_bit_identical_across_tile_shapes_and_batches(tile, batch):
+    g, cam = synth.small_render_case(4096, seed=0)
+    print("case: tiles", tile, batch, flush=True)
+    _, f0, _ = run_single(g, cam)
+    _, f1, _ = run_single(g, cam, tuning=gs.tuning_struct(tile[0], tile[1], batch))
+    check_integer_parity(g, cam, f1, tile=tile)
+    np.testing.assert_array_equal(f1.rgb.cpu().numpy(), f0.rgb.cpu().numpy())
+    np.testing.assert_array_equal(f1.T.cpu().numpy(), f0.T.cpu().numpy())
+
+
+def test_forward_is_deterministic():
+    g, cam = synth.small_render_case(4096, seed=5)
+    _, f0, _ = run_single(g, cam)
+    _, f1, _ = run_single(g, cam)
+    np.testing.assert_array_equal(f0.rgb.cpu().numpy(), f1.rgb.cpu().numpy())
+    t0, i0 = frame_pairs(f0)
+    t1, i1 = frame_pairs(f1)
+    np.testing.assert_array_equal(t0, t1)
+    np.testing.assert_array_equal(i0, i1)
+
+
+def test_background_and_sh_degrees():
+    g, cam = synth.small_render_case(2048, seed=7, width=128, height=96)
+    for deg in (0, 1, 2, 3):
+        bg = (0.1 * deg, 0.5, 0.9)
+        _, frame, _ = run_single(g, cam, sh_degree=deg, bg=bg)
+        img, T, _ = image_np(frame)
+        compare_image(img[0], T[0], g, cam, bg=bg, sh_degree=deg)
+
+
+def test_aerial_box_scene_reduced():
+    """Config-1 geometry (200x200x40 m box, 45-degree view) at reduced size."""
+    g = synth.box_gaussians(60_000, seed=1)
+    cam = synth.look_camera((0.0, -100.0, 60.0), yaw=math.pi / 2, pitch=-math.pi / 4, width=480, height=270)
+    print("case: aerial box 60k @ 480x270", flush=True)
+    _, frame, _ = run_single(g, cam)
+    check_integer_parity(g, cam, frame)
+    img, T, _ = image_np(frame)
+    compare_image(img[0], T[0], g, cam)
+
+
+def test_aerial_box_full_size_sampled_pixels():
+    """1M Gaussians at 1920x1080 (the fwd+bwd training view): integer parity in
+    full, colour on sampled pixels (tile corners and random)."""
+    g, cam, _ = synth.single_view_training_case()
+    print("case: aerial box 1M @ 1920x1080", flush=True)
+    _, frame, _ = run_single(g, cam)
+    check_integer_parity(g, cam, frame)
+    img, T, _ = image_np(frame)
+    rng = np.random.default_rng(0)
+    W, H = cam.width, cam.height
+    pix = np.concatenate([rng.choice(W * H, 3000, replace=False),
+                          np.array([j * W + i for j in (0, 15, 16, 1079) for i in (0, 15, 16, 1919)])])
+    ref, T_ref, _, amb = oracle.render(g, cam, pixels=pix)
+    ok = amb == 0
+    got = img[0].reshape(3, -1)[:, pix]
+    assert np.abs(got - ref)[:, ok].max() <= COLOUR_TOL
+    assert np.abs(T[0].reshape(-1)[pix] - T_ref)[ok].max() <= COLOUR_TOL
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+def test_empty_and_fully_culled_scenes():
+    cam = synth.axis_camera(64, 48)
+    empty = synth.cube_gaussians(0, 0)
+    behind = synth.cube_gaussians(5, 0)
+    behind.means[2] = -10.0  # every centre behind the camera
+    for g in (empty, behind):
+        print("case: culled n =", g.opac.shape[0], flush=True)
+        _, frame, _ = run_single(g, cam, bg=(0.25, 0.5, 0.75))
+        c = frame.host_counts()
+        assert c["visible"] == 0 and c["pairs"] == 0 and c["flags"] == 0
+        img, T, _ = image_np(frame)
+        assert (T == 1).all()
+        np.testing.assert_array_equal(img[0], np.broadcast_to(np.array([0.25, 0.5, 0.75], np.float32)[:, None, None],
+                                                              img[0].shape))
+
+
+def test_degenerate_gaussians_are_culled():
+    g = synth.cube_gaussians(64, 3)
+    g.means[0, 0] = np.nan
+    g.quats[:, 1] = 0.0
+    g.scales[0, 2] = np.inf
+    g.opac[3] = 0.001
+    cam = synth.axis_camera(64, 64)
+    _, frame, _ = run_single(g, cam)
+    tt = frame.tiles_touched[:64].cpu().numpy()
+    assert tt[0] == 0 and tt[1] == 0 and tt[2] == 0 and tt[3] == 0
+    pr = oracle.project(g, cam)
+    np.testing.assert_array_equal(tt, pr["tiles_touched"])
+    img, _, _ = image_np(frame)
+    assert np.isfinite(img).all()
+
+
+def test_pair_capacity_overflow_sets_flag_and_recovers():
+    g, cam = synth.small_render_case(4096, seed=0)
+    scene = render.DeviceScene.single(g)
+    cams_dev = gs.cameras_to_device([cam])
+    frame = render.Frame(1, 1, cam.width, cam.height, 4096, 1000)
+    render.render_frame(scene, frame, cams_dev, mode=gs.GS_LOD_ALL_FINEST, thresholds=(), check=False)
+    c = frame.host_counts()
+    assert c["flags"] & gs.GS_FLAG_PAIRS and c["pairs"] > 1000
+    render.render_frame(scene, frame, cams_dev, mode=gs.GS_LOD_ALL_FINEST, thresholds=())
+    assert frame.host_counts()["flags"] == 0
+    compare_image(frame.rgb[0].cpu().numpy(), frame.T[0].cpu().numpy(), g, cam)
+
+
+def test_equal_alpha_stack_closed_form_on_gpu():
+    # 20 wide Gaussians centred on pixel (32, 24), o = 0.5: 13 contribute, C = rgb (1 - 2^-13)
+    W, H = 65, 49
+    cam = synth.Camera(R=np.eye(3), t=np.zeros(3), fx=50.0, fy=50.0, cx=32.5, cy=24.5, width=W, height=H)
+    n = 20
+    g = synth.cube_gaussians(n, 0)
+    g.means[:] = np.vstack([np.zeros((2, n)), (2.0 + 0.01 * np.arange(n))[None]]).astype(np.float32)
+    g.scales[:] = 0.3
+    g.quats[:] = np.array([[1.0], [0], [0], [0]], np.float32)
+    g.opac[:] = 0.5
+    g.sh[:] = 0.0
+    rgb = np.array([0.8, 0.5, 0.25])
+    g.sh[0] = ((rgb - 0.5) / 0.28209479177387814)[:, None].astype(np.float32)
+    _, frame, _ = run_single(g, cam, sh_degree=0)
+    img, T, _ = image_np(frame)
+    np.testing.assert_allclose(img[0][:, 24, 32], rgb * (1 - 2.0 ** -13), atol=1e-6)
+    assert abs(T[0][24, 32] - 2.0 ** -13) < 1e-9
+
+
+# ---------------------------------------------------------------------------
+# level of detail
+# ---------------------------------------------------------------------------
+def test_mad_bounds_bit_exact():
+    bs = scaled_city(150_000, seed=31)
+    scene = render.DeviceScene.from_block_scene(bs)
+    lo, hi = scene.compute_bounds(4.0)
+    torch.cuda.synchronize()
+    lo_ref, hi_ref = olod.scene_bounds(bs, 4.0)
+    np.testing.assert_array_equal(lo.cpu().numpy(), lo_ref)
+    np.testing.assert_array_equal(hi.cpu().numpy(), hi_ref)
+
+
+def test_lod_select_bit_exact_levels_and_offsets():
+    bs = scaled_city(150_000, seed=32)
+    scene = render.DeviceScene.from_block_scene(bs)
+    scene.compute_bounds(4.0)
+    lo_ref, hi_ref = olod.scene_bounds(bs, 4.0)
+    cams = synth.city_views(seed=32, n_xy=4)
+    frame = render.Frame(bs.n_blocks, len(cams), 1600, 900, len(cams) * scene.max_records_per_view(), 1 << 22)
+    cams_dev = gs.cameras_to_device(cams)
+    gs.lod_select(scene.blocks_struct(), (200.0, 500.0), gs.GS_LOD_BLOCKWISE, cams_dev, len(cams), frame.level,
+                  frame.offsets, frame.counts)
+    torch.cuda.synchronize()
+    level_ref, off_ref = olod.lod_select(lo_ref, hi_ref, bs.cells, (200.0, 500.0), cams, bs.lvl_cnt)
+    np.testing.assert_array_equal(frame.level.cpu().numpy(), level_ref)
+    per_view = np.diff(off_ref, axis=1)
+    flat = np.concatenate([[0], np.cumsum(per_view.reshape(-1))])
+    np.testing.assert_array_equal(frame.offsets.cpu().numpy(), flat)
+    assert len(np.unique(level_ref)) >= 3
+
+
+@pytest.mark.parametrize("view_idx", [0, 9, 17, 30, 47])
+def test_lod_frame_matches_oracle_on_aggregated_set(view_idx):
+    bs = scaled_city(200_000, seed=33)
+    scene = render.DeviceScene.from_block_scene(bs)
+    scene.compute_bounds(4.0)
+    lo_ref, hi_ref = olod.scene_bounds(bs, 4.0)
+    cam = synth.city_views(seed=33)[view_idx]
+    print("case: lod view", view_idx, flush=True)
+    frame = render.Frame(bs.n_blocks, 1, cam.width, cam.height, scene.max_records_per_view(), 1 << 20)
+    render.render_frame(scene, frame, gs.cameras_to_device([cam]), thresholds=(200.0, 500.0))
+    level_ref, off_ref = olod.lod_select(lo_ref, hi_ref, bs.cells, (200.0, 500.0), [cam], bs.lvl_cnt)
+    agg = olod.aggregate(bs, level_ref[0])
+    check_integer_parity(agg, cam, frame)
+    img, T, _ = image_np(frame)
+    compare_image(img[0], T[0], agg, cam)
+
+
+def test_batched_views_equal_single_views():
+    bs = scaled_city(100_000, seed=34)
+    scene = render.DeviceScene.from_block_scene(bs)
+    scene.compute_bounds(4.0)
+    cams = synth.city_views(seed=34, n_xy=2, width=640, height=360)
+    fb = render.Frame(bs.n_blocks, len(cams), 640, 360, len(cams) * scene.max_records_per_view(), 1 << 20)
+    render.render_frame(scene, fb, gs.cameras_to_device(cams))
+    batched = fb.rgb.cpu().numpy()
+    for v, cam in enumerate(cams):
+        f1 = render.Frame(bs.n_blocks, 1, 640, 360, scene.max_records_per_view(), 1 << 18)
+        render.render_frame(scene, f1, gs.cameras_to_device([cam]))
+        np.testing.assert_array_equal(f1.rgb[0].cpu().numpy(), batched[v])
+
+
+# ---------------------------------------------------------------------------
+# backward
+# ---------------------------------------------------------------------------
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def grads_gpu(g, cam, dimg, sh_degree=3):
+    dev = "cuda"
+    params = [torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev, requires_grad=True)
+              for a in (g.means, g.scales, g.quats, g.opac, g.sh)]
+    img = render.rasterize(*params, [cam], sh_degree=sh_degree)
+    img.backward(torch.tensor(dimg[None], dtype=torch.float32, device=dev))
+    return [p.grad.cpu().numpy() for p in params], img.detach().cpu().numpy()[0]
+
+
+@pytest.mark.parametrize("seed,n,W,H", [(0, 2048, 128, 96), (1, 4096, 256, 256)])
+def test_gradients_match_oracle(seed, n, W, H):
+    g = synth.cube_gaussians(n, seed)
+    cam = synth.axis_camera(W, H)
+    rng = np.random.default_rng(seed + 50)
+    dimg = rng.normal(size=(3, H, W)).astype(np.float32)
+    print("case: grads", seed, n, W, H, flush=True)
+    got, _ = grads_gpu(g, cam, dimg)
+    ref = oracle.render_bwd(g, cam, dimg.astype(np.float64))
+    for name, gg in zip(("means", "scales", "quats", "opac", "sh"), got):
+        err = rel_l2(gg, ref[name])
+        print("  grad", name, "rel L2 %.2e" % err, flush=True)
+        assert err <= GRAD_TOL, (name, err)
+
+
+def test_l1_loss_gradients_aerial_box_reduced():
+    g = synth.box_gaussians(30_000, seed=1)
+    cam = synth.look_camera((0.0, -100.0, 60.0), yaw=math.pi / 2, pitch=-math.pi / 4, width=320, height=180)
+    target = np.random.default_rng(1001).uniform(size=(3, 180, 320)).astype(np.float32)
+    dev = "cuda"
+    params = [torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev, requires_grad=True)
+              for a in (g.means, g.scales, g.quats, g.opac, g.sh)]
+    img = render.rasterize(*params, [cam])
+    loss = (img[0] - torch.from_numpy(target).to(dev)).abs().mean()
+    loss.backward()
+    dimg = (np.sign(img.detach().cpu().numpy()[0] - target) / target.size).astype(np.float64)
+    ref = oracle.render_bwd(g, cam, dimg)
+    for name, p in zip(("means", "scales", "quats", "opac", "sh"), params):
+        err = rel_l2(p.grad.cpu().numpy(), ref[name])
+        print("  grad", name, "rel L2 %.2e" % err, flush=True)
+        assert err <= GRAD_TOL, (name, err)
