@@ -87,6 +87,37 @@ class DeviceScene:
         return DeviceScene([lev], [[0]], [[n]], device=means.device)
 
     @staticmethod
+    def from_finest(fine, block_id, u, cells, fractions=(0.30, 0.50, 1.00), coarse_scale=1.3,
+                    device="cuda") -> "DeviceScene":
+        """Upload the finest level and derive the nested coarser levels on the
+        device (level l keeps the Gaussians with u < fractions[l]; coarser
+        levels have scales x coarse_scale), so a 20M-Gaussian scene is built
+        without host copies of the coarse levels."""
+        B = cells.shape[0]
+        L = len(fractions)
+        fine_dev = DeviceLevel(*(torch.from_numpy(np.ascontiguousarray(a)).to(device) for a in fine.astuple()))
+        lvl_cnt = np.zeros((B, L), np.int64)
+        levels = []
+        for l, frac in enumerate(fractions):
+            if frac >= 1.0:
+                lvl_cnt[:, l] = np.bincount(block_id, minlength=B)
+                levels.append(fine_dev)
+                continue
+            idx_np = np.nonzero(u < frac)[0]
+            lvl_cnt[:, l] = np.bincount(block_id[idx_np], minlength=B)
+            idx = torch.from_numpy(idx_np).to(device)
+            k = torch.tensor(np.float32(coarse_scale), device=device)
+            levels.append(DeviceLevel(fine_dev.means.index_select(1, idx).contiguous(),
+                                      (fine_dev.scales.index_select(1, idx) * k).contiguous(),
+                                      fine_dev.quats.index_select(1, idx).contiguous(),
+                                      fine_dev.opac.index_select(0, idx).contiguous(),
+                                      fine_dev.sh.index_select(2, idx).contiguous()))
+            del idx
+        lvl_off = np.zeros_like(lvl_cnt)
+        lvl_off[1:] = np.cumsum(lvl_cnt, axis=0)[:-1]
+        return DeviceScene(levels, lvl_off, lvl_cnt, cells=cells, device=device)
+
+    @staticmethod
     def from_block_scene(bs, device="cuda") -> "DeviceScene":
         return DeviceScene.from_sets(bs.levels, bs.lvl_off, bs.lvl_cnt, cells=bs.cells, device=device)
 

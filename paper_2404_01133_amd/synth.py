@@ -261,22 +261,45 @@ def grid_cells(x0, y0, cell, nx, ny):
     return cells
 
 
-def city_block_scene(n=20_000_000, seed=2, area_m2=1.5e6, grid=(8, 8),
-                     fractions=(0.30, 0.50, 1.00)) -> BlockScene:
-    """Square city of `area_m2`, split into grid[0] x grid[1] blocks, n finest Gaussians."""
+def city_finest(n=20_000_000, seed=2, area_m2=1.5e6, grid=(8, 8)):
+    """Finest level of the synthetic city, sorted by block (row-major xy cells).
+
+    Returns (GaussianSet, block_id [n], u [n], cells [B, 4]); u is the uniform
+    draw that decides membership of the coarser nested levels.  Centres are
+    drawn and sorted first, attributes are drawn afterwards in block order, so
+    no large array is permuted."""
     rng = np.random.default_rng(seed)
     side = math.sqrt(area_m2)
     x0 = y0 = -0.5 * side
-    means = city_points(rng, n, x0, y0, side, side).astype(np.float32)
-    scales, quats, opac, sh = draw_attributes(rng, n)
-    u = rng.uniform(size=n)
     nx, ny = grid
     cell = side / nx
-    bx = np.clip(np.floor((means[0].astype(np.float64) - x0) / cell), 0, nx - 1).astype(np.int64)
-    by = np.clip(np.floor((means[1].astype(np.float64) - y0) / cell), 0, ny - 1).astype(np.int64)
+    means = city_points(rng, n, x0, y0, side, side)
+    bx = np.clip(np.floor((means[0] - x0) / cell), 0, nx - 1).astype(np.int64)
+    by = np.clip(np.floor((means[1] - y0) / cell), 0, ny - 1).astype(np.int64)
+    block_id = by * nx + bx
+    order = np.argsort(block_id, kind="stable")
+    means = np.ascontiguousarray(means[:, order], dtype=np.float32)
+    block_id = block_id[order]
+    scales, quats, opac, sh = draw_attributes(rng, n)
+    u = rng.uniform(size=n)
     cells = grid_cells(x0, y0, cell, nx, ny)
-    return block_scene_from_finest(GaussianSet(means, scales, quats, opac, sh), by * nx + bx, cells, u,
-                                   fractions)
+    return GaussianSet(means, scales, quats, opac, sh), block_id, u, cells
+
+
+def city_block_scene(n=20_000_000, seed=2, area_m2=1.5e6, grid=(8, 8),
+                     fractions=(0.30, 0.50, 1.00)) -> BlockScene:
+    """Square city of `area_m2`, split into grid[0] x grid[1] blocks, n finest Gaussians."""
+    fine, block_id, u, cells = city_finest(n, seed, area_m2, grid)
+    return block_scene_from_finest(fine, block_id, cells, u, fractions)
+
+
+def level_membership(block_id, u, n_blocks, fractions=(0.30, 0.50, 1.00)):
+    """For each level: the (sorted) finest-level indices it keeps, and per-block counts."""
+    out = []
+    for frac in fractions:
+        idx = np.arange(block_id.shape[0]) if frac >= 1.0 else np.nonzero(u < frac)[0]
+        out.append((idx, np.bincount(block_id[idx], minlength=n_blocks)))
+    return out
 
 
 def city_views(seed=2, area_m2=1.5e6, heights=(50.0, 150.0, 400.0), n_xy=8,
