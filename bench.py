@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--frames-only", action="store_true", help="only the timed LoD frames (for profilers)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run three 512 MiB device-to-device copies (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -111,8 +113,17 @@ def main():
     if frame.host_counts()["flags"]:
         raise RuntimeError("capacity flag raised during the timed frames: %s" % frame.host_counts())
     log("LoD graph: %.3f ms/step, %.1f FPS" % (ms_per_step, fps))
+    if args.copy_calibration:
+        src = torch.ones(128 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.frames_only:
-        print(json.dumps({"metric": "FPS", "value": fps, "ms_per_step": ms_per_step}))
+        print(json.dumps({"metric": "FPS", "value": fps, "ms_per_step": ms_per_step,
+                          "n_sel_mean": float(n_sel.mean()), "n_vis_mean": float(n_vis.mean()),
+                          "pairs_mean": float(n_pairs.mean())}))
         return
 
     # ---- per-view FPS distribution (one graph per view) ----------------------------

@@ -43,6 +43,28 @@ __device__ __forceinline__ void evaluate(const float4& w0, const float4& w1, int
   e.alpha = fminf(kAlphaMax, w1.w * e.G);
 }
 
+// Each wave keeps the indices of the staged records whose footprint rows meet
+// its own pixel rows (ballot compaction), so the blend loop never visits a
+// record that cannot touch the wave.
+template <int TW, int BATCH>
+__device__ __forceinline__ int wave_compact_rows(const float4* s_w0, int nb, int row0, int row1, uint16_t* list) {
+  const int lane = threadIdx.x & 63;
+  int cnt = 0;
+  for (int base = 0; base < nb; base += 64) {
+    const int k = base + lane;
+    bool hit = false;
+    if (k < nb) {
+      const uint32_t py = __float_as_uint(s_w0[k].w);
+      const int j0 = (int)(py & 0xFFFFu), j1 = j0 + (int)(py >> 16);
+      hit = !(j1 < row0 || j0 > row1);
+    }
+    const uint64_t m = __ballot(hit);
+    if (hit) list[cnt + (int)lanemask_lt_count(m)] = (uint16_t)k;
+    cnt += (int)__popcll(m);
+  }
+  return cnt;
+}
+
 template <int TW, int TH, int BATCH>
 __global__ void __launch_bounds__(TW* TH) raster_fwd_kernel(const Record* __restrict__ records,
                                                             const uint32_t* __restrict__ pair_records,
@@ -52,7 +74,9 @@ __global__ void __launch_bounds__(TW* TH) raster_fwd_kernel(const Record* __rest
                                                             float* __restrict__ T_final,
                                                             int32_t* __restrict__ n_last) {
   constexpr int NT = TW * TH;
+  constexpr int NW = NT / 64;
   __shared__ float4 s_w0[BATCH], s_w1[BATCH], s_w2[BATCH];
+  __shared__ uint16_t s_list[NW][BATCH];
   const int tile_g = blockIdx.x;
   const int view = tile_g / tiles_per_view;
   const int tile = tile_g - view * tiles_per_view;
@@ -60,10 +84,15 @@ __global__ void __launch_bounds__(TW* TH) raster_fwd_kernel(const Record* __rest
   const int i = txi * TW + (int)(threadIdx.x % TW);
   const int j = tyi * TH + (int)(threadIdx.x / TW);
   const bool inside = (i < W) && (j < H);
+  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  // rows covered by this wave (a wave is 64 consecutive pixels of the row-major tile)
+  const int wave_row0 = tyi * TH + wid * (64 / TW);
+  const int wave_row1 = wave_row0 + 64 / TW - 1;
   const uint32_t start = ranges[2 * tile_g], end = ranges[2 * tile_g + 1];
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
   int last = 0;
   bool done = !inside;
+  uint16_t* list = s_list[wid];
   for (uint32_t b = start; b < end; b += BATCH) {
     if (__syncthreads_and(done)) break;
     const int nb = (int)min((uint32_t)BATCH, end - b);
@@ -74,27 +103,35 @@ __global__ void __launch_bounds__(TW* TH) raster_fwd_kernel(const Record* __rest
       s_w2[k] = r[2];
     }
     __syncthreads();
-    if (!done) {
-      for (int k = 0; k < nb; ++k) {
-        const float4 w0 = s_w0[k];
+    const int cnt = wave_compact_rows<TW, BATCH>(s_w0, nb, wave_row0, wave_row1, list);
+    const int base_idx = (int)(b - start);
+    if (cnt > 0 && __ballot(!done) != 0) {
+      int k = __builtin_amdgcn_readfirstlane((int)list[0]);
+      float4 w0 = s_w0[k], w1 = s_w1[k], w2 = s_w2[k];
+      for (int t = 0; t < cnt; ++t) {
+        // prefetch the next compacted record while this one is blended
+        const int kn = __builtin_amdgcn_readfirstlane((int)list[t + 1 < cnt ? t + 1 : t]);
+        const float4 n0 = s_w0[kn], n1 = s_w1[kn], n2 = s_w2[kn];
         int di, dj;
-        if (!in_footprint(i, j, __float_as_uint(w0.z), __float_as_uint(w0.w), di, dj)) continue;
-        const float4 w1 = s_w1[k];
+        const bool in_fp = in_footprint(i, j, __float_as_uint(w0.z), __float_as_uint(w0.w), di, dj);
         Eval e;
         evaluate(w0, w1, di, dj, e);
-        if (e.alpha < kAlphaMin) continue;
+        bool use = !done && in_fp && (e.alpha >= kAlphaMin);
         const float Tn = T * (1.0f - e.alpha);
-        if (Tn < kTMin) {
-          done = true;
-          break;
-        }
-        const float4 w2 = s_w2[k];
+        const bool stop = use && (Tn < kTMin);
+        done = done || stop;
+        use = use && !stop;
         const float aT = e.alpha * T;
-        C0 = fmaf(w2.x, aT, C0);
-        C1 = fmaf(w2.y, aT, C1);
-        C2 = fmaf(w2.z, aT, C2);
-        T = Tn;
-        last = (int)(b - start) + k + 1;
+        C0 = use ? fmaf(w2.x, aT, C0) : C0;
+        C1 = use ? fmaf(w2.y, aT, C1) : C1;
+        C2 = use ? fmaf(w2.z, aT, C2) : C2;
+        T = use ? Tn : T;
+        last = use ? base_idx + k + 1 : last;
+        if (__ballot(!done) == 0) break;
+        k = kn;
+        w0 = n0;
+        w1 = n1;
+        w2 = n2;
       }
     }
     __syncthreads();
@@ -143,6 +180,7 @@ __global__ void __launch_bounds__(TW* TH) raster_bwd_kernel(
   __shared__ float4 s_w0[BATCH], s_w1[BATCH], s_w2[BATCH];
   __shared__ uint32_t s_rec[BATCH];
   __shared__ float s_grad[BATCH * kG];
+  __shared__ uint16_t s_list[NW][BATCH];
   __shared__ int s_wave_last[NW];
   const int tile_g = blockIdx.x;
   const int view = tile_g / tiles_per_view;
@@ -150,9 +188,12 @@ __global__ void __launch_bounds__(TW* TH) raster_bwd_kernel(
   const int tyi = tile / tiles_x_n, txi = tile - tyi * tiles_x_n;
   const int i = txi * TW + (int)(threadIdx.x % TW);
   const int j = tyi * TH + (int)(threadIdx.x / TW);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const bool inside = (i < W) && (j < H);
-  const uint32_t start = ranges[2 * tile_g], end = ranges[2 * tile_g + 1];
+  const int wave_row0 = tyi * TH + wid * (64 / TW);
+  const int wave_row1 = wave_row0 + 64 / TW - 1;
+  const uint32_t start = ranges[2 * tile_g];
   const int64_t plane = (int64_t)H * W;
   const int64_t pix = (int64_t)j * W + i;
   float g0 = 0.f, g1 = 0.f, g2 = 0.f, out0 = 0.f, out1 = 0.f, out2 = 0.f;
@@ -174,7 +215,8 @@ __global__ void __launch_bounds__(TW* TH) raster_bwd_kernel(
   __syncthreads();
   int tile_last = 0;
   for (int w = 0; w < NW; ++w) tile_last = max(tile_last, s_wave_last[w]);
-  const int wave_last = s_wave_last[wid];
+  const int wave_last = __builtin_amdgcn_readfirstlane(s_wave_last[wid]);
+  uint16_t* list = s_list[wid];
   float T = 1.0f, A0 = 0.f, A1c = 0.f, A2c = 0.f;  // transmittance and colour accumulated in front
   for (uint32_t b = start; b < start + (uint32_t)tile_last; b += BATCH) {
     const int nb = (int)min((uint32_t)BATCH, start + (uint32_t)tile_last - b);
@@ -188,52 +230,45 @@ __global__ void __launch_bounds__(TW* TH) raster_bwd_kernel(
     }
     for (int k = threadIdx.x; k < nb * kG; k += NT) s_grad[k] = 0.0f;
     __syncthreads();
-    const int kmax = min(nb, wave_last - (int)(b - start));
-    for (int k = 0; k < kmax; ++k) {
-      const int e_idx = (int)(b - start) + k;
-      float c[kG];
-#pragma unroll
-      for (int q = 0; q < kG; ++q) c[q] = 0.0f;
-      bool contrib = false;
-      const float4 w0 = s_w0[k];
+    const int base_idx = (int)(b - start);
+    const int kmax = min(nb, wave_last - base_idx);  // entries past every lane's n_last are not needed
+    const int cnt = kmax > 0 ? wave_compact_rows<TW, BATCH>(s_w0, kmax, wave_row0, wave_row1, list) : 0;
+    for (int t = 0; t < cnt; ++t) {
+      const int k = __builtin_amdgcn_readfirstlane((int)list[t]);
+      const float4 w0 = s_w0[k], w1 = s_w1[k], w2 = s_w2[k];
       int di, dj;
-      if (e_idx < last && in_footprint(i, j, __float_as_uint(w0.z), __float_as_uint(w0.w), di, dj)) {
-        const float4 w1 = s_w1[k];
-        Eval e;
-        evaluate(w0, w1, di, dj, e);
-        if (e.alpha >= kAlphaMin) {
-          contrib = true;
-          const float4 w2 = s_w2[k];
-          const float aT = e.alpha * T;
-          c[0] = aT * g0;
-          c[1] = aT * g1;
-          c[2] = aT * g2;
-          A0 = fmaf(w2.x, aT, A0);
-          A1c = fmaf(w2.y, aT, A1c);
-          A2c = fmaf(w2.z, aT, A2c);
-          const float inv1ma = 1.0f / (1.0f - e.alpha);
-          // dL/dalpha = sum_c g_c (colour_c T - (colour behind)_c / (1 - alpha))
-          const float dalpha = g0 * (w2.x * T - (out0 - A0) * inv1ma) + g1 * (w2.y * T - (out1 - A1c) * inv1ma) +
-                               g2 * (w2.z * T - (out2 - A2c) * inv1ma);
-          if (w1.w * e.G <= kAlphaMax) {
-            c[3] = dalpha * e.G;
-            // dL/dQ with G = exp2(-Q): dG/dQ = -ln2 G
-            const float gQ = -0.69314718055994531f * dalpha * w1.w * e.G;
-            c[4] = gQ * e.p1;
-            c[5] = gQ * e.p2;
-            c[6] = gQ * e.dx * e.dx;
-            c[7] = gQ * e.dx * e.dy;
-            c[8] = gQ * e.dy * e.dy;
-          }
-          T = T * (1.0f - e.alpha);
-        }
-      }
-      if (__ballot(contrib) != 0) {
+      const bool in_fp = in_footprint(i, j, __float_as_uint(w0.z), __float_as_uint(w0.w), di, dj);
+      Eval e;
+      evaluate(w0, w1, di, dj, e);
+      const bool use = (base_idx + k < last) && in_fp && (e.alpha >= kAlphaMin);
+      if (__ballot(use) == 0) continue;
+      const float aT = e.alpha * T;
+      const float nA0 = fmaf(w2.x, aT, A0), nA1 = fmaf(w2.y, aT, A1c), nA2 = fmaf(w2.z, aT, A2c);
+      const float inv1ma = 1.0f / (1.0f - e.alpha);
+      // dL/dalpha = sum_c g_c (colour_c T - (colour behind)_c / (1 - alpha))
+      const float dalpha = g0 * (w2.x * T - (out0 - nA0) * inv1ma) + g1 * (w2.y * T - (out1 - nA1) * inv1ma) +
+                           g2 * (w2.z * T - (out2 - nA2) * inv1ma);
+      const bool unclamped = use && (w1.w * e.G <= kAlphaMax);
+      // dL/dQ with G = exp2(-Q): dG/dQ = -ln2 G
+      const float gQ = unclamped ? -0.69314718055994531f * dalpha * w1.w * e.G : 0.0f;
+      float c[kG];
+      c[0] = use ? aT * g0 : 0.0f;
+      c[1] = use ? aT * g1 : 0.0f;
+      c[2] = use ? aT * g2 : 0.0f;
+      c[3] = unclamped ? dalpha * e.G : 0.0f;
+      c[4] = gQ * e.p1;
+      c[5] = gQ * e.p2;
+      c[6] = gQ * e.dx * e.dx;
+      c[7] = gQ * e.dx * e.dy;
+      c[8] = gQ * e.dy * e.dy;
+      A0 = use ? nA0 : A0;
+      A1c = use ? nA1 : A1c;
+      A2c = use ? nA2 : A2c;
+      T = use ? T * (1.0f - e.alpha) : T;
 #pragma unroll
-        for (int q = 0; q < kG; ++q) {
-          const float s = wave_sum_to_lane63(c[q]);
-          if (lane == 63 && s != 0.0f) atomicAdd(&s_grad[k * kG + q], s);
-        }
+      for (int q = 0; q < kG; ++q) {
+        const float sum = wave_sum_to_lane63(c[q]);
+        if (lane == 63 && sum != 0.0f) atomicAdd(&s_grad[k * kG + q], sum);
       }
     }
     __syncthreads();

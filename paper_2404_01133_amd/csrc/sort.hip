@@ -47,17 +47,24 @@ __device__ __forceinline__ void raise_flag(int64_t* counts, int64_t bit) {
 }
 
 // ---------------------------------------------------------------------------
-// zero fill of look-back state, sized from a device count
+// zero fill of the small fixed state and of the look-back words of the scans
+// and depth passes, sized by the selected record count
 // ---------------------------------------------------------------------------
-__global__ void clear_words_kernel(uint32_t* __restrict__ p, int64_t fixed_words, const int64_t* counts, int count_idx,
-                                   int64_t cap, int64_t words_per_tile, int64_t tiles_extra) {
-  int64_t words = fixed_words;
-  if (count_idx >= 0) {
-    const int64_t n = count_clamped(counts, count_idx, cap);
-    words = ((n + kTile - 1) / kTile + tiles_extra) * words_per_tile;
-  }
+__global__ void clear_front_kernel(uint32_t* __restrict__ fixed, int64_t fixed_words, uint32_t* __restrict__ scan0,
+                                   uint32_t* __restrict__ scan1, uint32_t* __restrict__ dstatus,
+                                   const int64_t* counts, int64_t cap) {
+  const int64_t n = count_clamped(counts, GS_COUNT_RECORDS, cap);
+  const int64_t ntiles = (n + kTile - 1) / kTile;
+  const int64_t scan_words = 2 * (ntiles + 1);  // one u64 status per scan tile
+  const int64_t dwords = ntiles * 4 * kRadix;   // [ntiles][4 passes][256]
+  const int64_t total = fixed_words + 2 * scan_words + dwords;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride) p[i] = 0u;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    if (i < fixed_words) fixed[i] = 0u;
+    else if (i < fixed_words + scan_words) scan0[i - fixed_words] = 0u;
+    else if (i < fixed_words + 2 * scan_words) scan1[i - fixed_words - scan_words] = 0u;
+    else dstatus[i - fixed_words - 2 * scan_words] = 0u;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -121,13 +128,17 @@ __global__ void __launch_bounds__(kThreads) compact_kernel(const int32_t* __rest
                                                            const uint32_t* __restrict__ depth_keys, int64_t cap,
                                                            uint32_t* __restrict__ keys_out,
                                                            uint32_t* __restrict__ vals_out, uint64_t* status,
-                                                           uint32_t* tile_counter, int64_t* counts) {
+                                                           uint32_t* tile_counter, uint32_t* __restrict__ hist,
+                                                           int64_t* counts) {
   __shared__ uint32_t s_wave[kThreads / 64];
   __shared__ uint32_t s_tile;
   __shared__ uint64_t s_excl;
+  __shared__ uint32_t s_hist[4][kRadix];
   const int64_t n = count_clamped(counts, GS_COUNT_RECORDS, cap);
   const int64_t ntiles = (n + kTile - 1) / kTile;
   if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0) counts[GS_COUNT_VISIBLE] = 0;
+  if ((int64_t)blockIdx.x >= ntiles) return;  // idle work-groups never touch the tile counter
+  for (int i = threadIdx.x; i < 4 * kRadix; i += kThreads) (&s_hist[0][0])[i] = 0u;
   for (;;) {
     if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
     __syncthreads();
@@ -155,12 +166,19 @@ __global__ void __launch_bounds__(kThreads) compact_kernel(const int32_t* __rest
     for (int k = 0; k < kItems; ++k) {
       if (f[k]) {
         const int64_t idx = base + k;
-        keys_out[pos] = depth_keys[idx];
+        const uint32_t key = depth_keys[idx];
+        keys_out[pos] = key;
         vals_out[pos] = (uint32_t)idx;
         ++pos;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
       }
     }
     __syncthreads();
+  }
+  for (int i = threadIdx.x; i < 4 * kRadix; i += kThreads) {
+    const uint32_t c = (&s_hist[0][0])[i];
+    if (c) atomicAdd(&hist[i], c);
   }
 }
 
@@ -178,6 +196,7 @@ __global__ void __launch_bounds__(kThreads) pair_offsets_kernel(const uint32_t* 
   const int64_t n = count_clamped(counts, GS_COUNT_VISIBLE, cap);
   const int64_t ntiles = (n + kTile - 1) / kTile;
   if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0) counts[GS_COUNT_PAIRS] = 0;
+  if ((int64_t)blockIdx.x >= ntiles) return;
   for (;;) {
     if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
     __syncthreads();
@@ -224,10 +243,23 @@ __global__ void __launch_bounds__(kThreads) emit_kernel(const Record* __restrict
                                                         const int64_t* counts, int64_t pair_cap, int tw, int th,
                                                         int tiles_x_n, int tiles_per_view,
                                                         uint32_t* __restrict__ out_tiles,
-                                                        uint32_t* __restrict__ out_records) {
-  const int64_t n = count_clamped(counts, GS_COUNT_VISIBLE, cap);
+                                                        uint32_t* __restrict__ out_records, int tpasses,
+                                                        uint32_t* __restrict__ hist, uint32_t* __restrict__ pstatus,
+                                                        uint32_t* __restrict__ ranges, int64_t range_words) {
+  __shared__ uint32_t s_hist[kMaxPasses][kRadix];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // zero the look-back words of the tile passes (sized by the pair count) and the ranges
+  {
+    const int64_t m = count_clamped(counts, GS_COUNT_PAIRS, pair_cap);
+    const int64_t words = ((m + kTile - 1) / kTile) * (int64_t)tpasses * kRadix;
+    for (int64_t i = gtid; i < words; i += stride) pstatus[i] = 0u;
+    for (int64_t i = gtid; i < range_words; i += stride) ranges[i] = 0u;
+  }
+  for (int i = threadIdx.x; i < tpasses * kRadix; i += kThreads) (&s_hist[0][0])[i] = 0u;
+  __syncthreads();
+  const int64_t n = count_clamped(counts, GS_COUNT_VISIBLE, cap);
+  for (int64_t j = gtid; j < n; j += stride) {
     const uint32_t rid = sorted_records[j];
     const uint4 w0 = *reinterpret_cast<const uint4*>(&records[rid]);
     const uint32_t view = reinterpret_cast<const uint32_t*>(&records[rid])[11];
@@ -238,51 +270,29 @@ __global__ void __launch_bounds__(kThreads) emit_kernel(const Record* __restrict
     for (int ty = j0 / th; ty <= j1 / th; ++ty)
       for (int tx = i0 / tw; tx <= i1 / tw; ++tx) {
         if (o < pair_cap) {
-          out_tiles[o] = vbase + (uint32_t)(ty * tiles_x_n + tx);
+          const uint32_t key = vbase + (uint32_t)(ty * tiles_x_n + tx);
+          out_tiles[o] = key;
           out_records[o] = rid;
+          for (int p = 0; p < tpasses; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
         }
         ++o;
       }
   }
-}
-
-// ---------------------------------------------------------------------------
-// radix sort: histograms of all passes in one read, then one kernel per pass
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) radix_hist_kernel(const uint32_t* __restrict__ keys,
-                                                              const int64_t* counts, int count_idx, int64_t cap,
-                                                              int shift0, int npasses,
-                                                              uint32_t* __restrict__ hist /*[passes][256]*/) {
-  __shared__ uint32_t s_hist[kMaxPasses][kRadix];
-  for (int i = threadIdx.x; i < npasses * kRadix; i += kThreads) (&s_hist[0][0])[i] = 0u;
   __syncthreads();
-  const int64_t n = count_clamped(counts, count_idx, cap);
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const uint32_t k = keys[i];
-    for (int p = 0; p < npasses; ++p) atomicAdd(&s_hist[p][(k >> (shift0 + 8 * p)) & 255u], 1u);
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < npasses * kRadix; i += kThreads) {
+  for (int i = threadIdx.x; i < tpasses * kRadix; i += kThreads) {
     const uint32_t c = (&s_hist[0][0])[i];
     if (c) atomicAdd(&hist[i], c);
   }
 }
 
-__global__ void __launch_bounds__(kRadix) radix_hist_scan_kernel(const uint32_t* __restrict__ hist,
-                                                                 uint32_t* __restrict__ global_off) {
-  __shared__ uint32_t s_wave[kThreads / 64];
-  const int p = blockIdx.x;
-  const uint32_t c = hist[p * kRadix + threadIdx.x];
-  uint32_t total;
-  const uint32_t ex = block_excl_scan(c, s_wave, &total);
-  global_off[p * kRadix + threadIdx.x] = ex;
-}
-
+// ---------------------------------------------------------------------------
+// one stable LSD pass over 8 bits; the digit histogram of the whole input was
+// accumulated by the kernel that produced the keys
+// ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kThreads) radix_pass_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, const int64_t* counts_in, int count_idx, int64_t cap, int shift,
-    const uint32_t* __restrict__ global_off, uint32_t* status, int64_t status_stride, uint32_t* tile_counter,
+    const uint32_t* __restrict__ hist, uint32_t* status, int64_t status_stride, uint32_t* tile_counter,
     int64_t* counts) {
   __shared__ uint32_t s_keys[kTile];
   __shared__ uint32_t s_vals[kTile];
@@ -291,9 +301,15 @@ __global__ void __launch_bounds__(kThreads) radix_pass_kernel(
   __shared__ uint32_t s_digit_base[kRadix];
   __shared__ uint32_t s_wave[kThreads / 64];
   __shared__ uint32_t s_tile;
+  __shared__ uint32_t s_goff[kRadix];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int64_t n = count_clamped(counts_in, count_idx, cap);
   const int64_t ntiles = (n + kTile - 1) / kTile;
+  if ((int64_t)blockIdx.x >= ntiles) return;
+  {
+    uint32_t tot;
+    s_goff[threadIdx.x] = block_excl_scan(hist[threadIdx.x], s_wave, &tot);  // global digit offsets
+  }
   for (;;) {
     if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
     for (int i = threadIdx.x; i < (kThreads / 64) * kRadix; i += kThreads) (&s_wave_hist[0][0])[i] = 0u;
@@ -372,7 +388,7 @@ __global__ void __launch_bounds__(kThreads) radix_pass_kernel(
       }
       store_agent(st, kFlagInc | (excl + tile_cnt));
     }
-    s_digit_base[d] = global_off[d] + excl;
+    s_digit_base[d] = s_goff[d] + excl;
     __syncthreads();
     // local scatter by digit, then coalesced write-out
 #pragma unroll
@@ -413,6 +429,8 @@ __global__ void ranges_kernel(const uint32_t* __restrict__ tiles, const int64_t*
 // ---------------------------------------------------------------------------
 // workspace layout
 // ---------------------------------------------------------------------------
+constexpr int64_t kFixedWords = 64 + 2 * kMaxPasses * kRadix;  // tile counters + two histogram sets
+
 struct SortWs {
   uint32_t* dkeys_a;      // [rc]
   uint32_t* dvals_a;      // [rc]
@@ -421,9 +439,7 @@ struct SortWs {
   uint32_t* pair_off;     // [rc]
   uint32_t* ptiles_alt;   // [pc]
   uint32_t* precs_alt;    // [pc]
-  uint32_t* hist;         // [2][kMaxPasses][256]
-  uint32_t* goff;         // [2][kMaxPasses][256]
-  uint32_t* counters;     // [64]
+  uint32_t* fixed;        // counters [64], then hist [2][kMaxPasses][256]
   uint64_t* scan_status;  // [2][rtiles]
   uint32_t* dstatus;      // [rtiles][4][256]   (tile-major so a prefix covers every pass)
   uint32_t* pstatus;      // [ptiles][kMaxPasses][256]
@@ -449,9 +465,8 @@ SortWs sort_ws_layout(char* base, int64_t rc, int64_t pc) {
   w.pair_off = (uint32_t*)take(4 * (size_t)rc);
   w.ptiles_alt = (uint32_t*)take(4 * (size_t)pc);
   w.precs_alt = (uint32_t*)take(4 * (size_t)pc);
-  w.hist = (uint32_t*)take(4 * 2 * kMaxPasses * kRadix);
-  w.goff = (uint32_t*)take(4 * 2 * kMaxPasses * kRadix);
-  w.counters = (uint32_t*)take(4 * 64);
+  w.fixed = (uint32_t*)take(4 * (size_t)kFixedWords);
+  // the two scan status arrays are adjacent: [rtiles] then [rtiles]
   w.scan_status = (uint64_t*)take(8 * 2 * (size_t)rtiles);
   w.dstatus = (uint32_t*)take(4 * 4 * (size_t)rtiles * kRadix);
   w.pstatus = (uint32_t*)take(4 * (size_t)kMaxPasses * (size_t)ptiles * kRadix);
@@ -491,7 +506,7 @@ extern "C" gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys
   const int tx_n = tiles_x(width, tw), ty_n = tiles_y(height, th);
   const int64_t tiles_per_view = (int64_t)tx_n * ty_n;
   const int64_t n_tile_ids = tiles_per_view * n_views;
-  if (n_tile_ids >= ((int64_t)1 << 32)) return GS_ERR_INVALID_ARG;
+  if (n_tile_ids >= ((int64_t)1 << 31)) return GS_ERR_INVALID_ARG;
   const int tbits = tile_bits(n_tile_ids);
   const int tpasses = tbits == 0 ? 0 : (tbits + 7) / 8;
   hipStream_t s = (hipStream_t)stream;
@@ -499,77 +514,59 @@ extern "C" gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys
   const dim3 blk(kThreads);
   auto grid_for = [](int64_t items) {
     int64_t g = (items + kThreads - 1) / kThreads;
-    return dim3((unsigned)(g < 1 ? 1 : (g > 4096 ? 4096 : g)));
+    return dim3((unsigned)(g < 1 ? 1 : (g > 2048 ? 2048 : g)));
   };
   auto persistent = [](int64_t cap) {
     int64_t g = (cap + kTile - 1) / kTile;
     return dim3((unsigned)(g < 1 ? 1 : (g > kPersistentBlocks ? kPersistentBlocks : g)));
   };
-  // counters, histograms and scan status (sized by capacity: small)
-  hipLaunchKernelGGL(clear_words_kernel, dim3(1), blk, 0, s, w.counters, (int64_t)64, counts, -1, (int64_t)0,
-                     (int64_t)0, (int64_t)0);
-  hipLaunchKernelGGL(clear_words_kernel, dim3(8), blk, 0, s, w.hist, (int64_t)2 * kMaxPasses * kRadix, counts, -1,
-                     (int64_t)0, (int64_t)0, (int64_t)0);
-  hipLaunchKernelGGL(clear_words_kernel, grid_for(4 * rtiles), blk, 0, s, (uint32_t*)w.scan_status,
-                     (int64_t)4 * rtiles, counts, -1, (int64_t)0, (int64_t)0, (int64_t)0);
-  // look-back state of the depth passes, sized by the selected record count
-  hipLaunchKernelGGL(clear_words_kernel, grid_for(4 * rtiles * kRadix), blk, 0, s, w.dstatus, (int64_t)0, counts,
-                     GS_COUNT_RECORDS, record_capacity, (int64_t)4 * kRadix, (int64_t)0);
+  uint32_t* counters = w.fixed;
+  uint32_t* dhist = w.fixed + 64;
+  uint32_t* thist = w.fixed + 64 + kMaxPasses * kRadix;
+  // 0. zero the counters, histograms and the look-back words of the record-sized stages
+  hipLaunchKernelGGL(clear_front_kernel, grid_for(kFixedWords + 4 * rtiles + 4 * rtiles * kRadix), blk, 0, s,
+                     w.fixed, kFixedWords, (uint32_t*)w.scan_status, (uint32_t*)(w.scan_status + rtiles), w.dstatus,
+                     counts, record_capacity);
   GS_LAUNCH_CHECK();
-  // 1. compaction
+  // 1. compaction (+ histograms of the four depth digits)
   hipLaunchKernelGGL(compact_kernel, persistent(record_capacity), blk, 0, s, tiles_touched, depth_keys,
-                     record_capacity, w.dkeys_a, w.dvals_a, w.scan_status, w.counters + 0, counts);
+                     record_capacity, w.dkeys_a, w.dvals_a, w.scan_status, counters + 0, dhist, counts);
   GS_LAUNCH_CHECK();
   // 2. depth sort, 4 passes of 8 bits: a -> b -> a -> b -> a
-  hipLaunchKernelGGL(radix_hist_kernel, dim3(512), blk, 0, s, w.dkeys_a, counts, GS_COUNT_VISIBLE, record_capacity,
-                     0, 4, w.hist);
-  hipLaunchKernelGGL(radix_hist_scan_kernel, dim3(4), dim3(kRadix), 0, s, w.hist, w.goff);
-  GS_LAUNCH_CHECK();
   for (int p = 0; p < 4; ++p) {
     const bool even = (p % 2) == 0;
     hipLaunchKernelGGL(radix_pass_kernel, persistent(record_capacity), blk, 0, s, even ? w.dkeys_a : w.dkeys_b,
                        even ? w.dvals_a : w.dvals_b, even ? w.dkeys_b : w.dkeys_a, even ? w.dvals_b : w.dvals_a,
-                       counts, GS_COUNT_VISIBLE, record_capacity, 8 * p, w.goff + p * kRadix,
-                       w.dstatus + p * kRadix, (int64_t)4 * kRadix, w.counters + 1 + p, counts);
+                       counts, GS_COUNT_VISIBLE, record_capacity, 8 * p, dhist + p * kRadix, w.dstatus + p * kRadix,
+                       (int64_t)4 * kRadix, counters + 1 + p, counts);
     GS_LAUNCH_CHECK();
   }
   // 3. pair offsets in depth order
   hipLaunchKernelGGL(pair_offsets_kernel, persistent(record_capacity), blk, 0, s, w.dvals_a, tiles_touched,
-                     record_capacity, w.pair_off, w.scan_status + rtiles, w.counters + 8, counts, pair_capacity);
+                     record_capacity, w.pair_off, w.scan_status + rtiles, counters + 8, counts, pair_capacity);
   GS_LAUNCH_CHECK();
-  // 4. emission: into the buffer that the last tile pass will read last
+  // 4. emission (+ tile-digit histograms, + zeroing of the tile-pass state and ranges), into the
+  //    buffer that the last tile pass will read last
   uint32_t* em_tiles = (tpasses % 2 == 0) ? pair_tiles : w.ptiles_alt;
   uint32_t* em_recs = (tpasses % 2 == 0) ? pair_records : w.precs_alt;
-  hipLaunchKernelGGL(emit_kernel, grid_for(record_capacity), blk, 0, s, (const Record*)records, w.dvals_a,
-                     w.pair_off, record_capacity, counts, pair_capacity, tw, th, tx_n, (int)tiles_per_view, em_tiles,
-                     em_recs);
+  hipLaunchKernelGGL(emit_kernel, grid_for(record_capacity), blk, 0, s, (const Record*)records, w.dvals_a, w.pair_off,
+                     record_capacity, counts, pair_capacity, tw, th, tx_n, (int)tiles_per_view, em_tiles, em_recs,
+                     tpasses, thist, w.pstatus, tile_ranges, 2 * n_tile_ids);
   GS_LAUNCH_CHECK();
   // 5. tile passes
-  if (tpasses > 0) {
-    const int64_t ptiles = (pair_capacity + kTile - 1) / kTile + 1;
-    hipLaunchKernelGGL(clear_words_kernel, grid_for(tpasses * ptiles * kRadix), blk, 0, s, w.pstatus, (int64_t)0,
-                       counts, GS_COUNT_PAIRS, pair_capacity, (int64_t)tpasses * kRadix, (int64_t)0);
-    hipLaunchKernelGGL(radix_hist_kernel, dim3(512), blk, 0, s, em_tiles, counts, GS_COUNT_PAIRS, pair_capacity, 0,
-                       tpasses, w.hist + kMaxPasses * kRadix);
-    hipLaunchKernelGGL(radix_hist_scan_kernel, dim3(tpasses), dim3(kRadix), 0, s, w.hist + kMaxPasses * kRadix,
-                       w.goff + kMaxPasses * kRadix);
+  uint32_t* kin = em_tiles;
+  uint32_t* vin = em_recs;
+  for (int p = 0; p < tpasses; ++p) {
+    uint32_t* kout = (kin == pair_tiles) ? w.ptiles_alt : pair_tiles;
+    uint32_t* vout = (vin == pair_records) ? w.precs_alt : pair_records;
+    hipLaunchKernelGGL(radix_pass_kernel, persistent(pair_capacity), blk, 0, s, kin, vin, kout, vout, counts,
+                       GS_COUNT_PAIRS, pair_capacity, 8 * p, thist + p * kRadix, w.pstatus + p * kRadix,
+                       (int64_t)tpasses * kRadix, counters + 16 + p, counts);
     GS_LAUNCH_CHECK();
-    uint32_t* kin = em_tiles;
-    uint32_t* vin = em_recs;
-    for (int p = 0; p < tpasses; ++p) {
-      uint32_t* kout = (kin == pair_tiles) ? w.ptiles_alt : pair_tiles;
-      uint32_t* vout = (vin == pair_records) ? w.precs_alt : pair_records;
-      hipLaunchKernelGGL(radix_pass_kernel, persistent(pair_capacity), blk, 0, s, kin, vin, kout, vout, counts,
-                         GS_COUNT_PAIRS, pair_capacity, 8 * p, w.goff + kMaxPasses * kRadix + p * kRadix,
-                         w.pstatus + p * kRadix, (int64_t)tpasses * kRadix, w.counters + 16 + p, counts);
-      GS_LAUNCH_CHECK();
-      kin = kout;
-      vin = vout;
-    }
+    kin = kout;
+    vin = vout;
   }
   // 6. ranges
-  hipLaunchKernelGGL(clear_words_kernel, grid_for(2 * n_tile_ids), blk, 0, s, tile_ranges, 2 * n_tile_ids, counts,
-                     -1, (int64_t)0, (int64_t)0, (int64_t)0);
   hipLaunchKernelGGL(ranges_kernel, dim3(2048), blk, 0, s, pair_tiles, counts, pair_capacity, tile_ranges);
   GS_LAUNCH_CHECK();
   return GS_OK;
