@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--frames-only", action="store_true", help="only the timed LoD frames (for profilers)")
+    ap.add_argument("--bwd-only", action="store_true", help="only the LoD fwd+bwd loop (for profilers)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run three 512 MiB device-to-device copies (reference for HBM byte counters)")
     return ap.parse_args()
@@ -88,6 +89,18 @@ def main():
     n_pairs = np.array([s["pairs"] for s in stats])
     log("per view: N_sel mean %.0f (max %d), N_vis mean %.0f, pairs mean %.0f (max %d)" %
         (n_sel.mean(), n_sel.max(), n_vis.mean(), n_pairs.mean(), n_pairs.max()))
+
+    if args.bwd_only:
+        grads = [lv.zeros_like() for lv in scene.levels]
+        target = torch.rand((1, 3, H, W), generator=torch.Generator(device=dev).manual_seed(3), device=dev)
+        for _ in range(2):
+            for v in range(0, V, max(1, V // args.bwd_views)):
+                render.render_frame(scene, frame, cam_slot[v], thresholds=thresholds, check=False)
+                d = torch.sign(frame.rgb - target) / frame.rgb.numel()
+                render.backward_frame(scene, frame, cam_slot[v], d, grads)
+        torch.cuda.synchronize()
+        print(json.dumps({"bwd_only": True}))
+        return
 
     # ---- HIP graph of one step (all views, one frame each) -------------------------
     stream = torch.cuda.Stream()

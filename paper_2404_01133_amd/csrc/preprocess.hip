@@ -3,10 +3,11 @@
 // through the local affine approximation of the pinhole map, 0.3 px^2 low-pass
 // dilation, 3-sigma footprint, SH colour).
 //
-// Memory-bound: each record reads 12 B of centre for every selected Gaussian,
-// 28 B of rotation/scale and 4 B of opacity for those in front of the camera,
-// and the 192 B of SH only for those that survive the footprint cull.  Loads
-// are structure-of-arrays, so consecutive lanes touch consecutive words.
+// Memory-bound: each record reads the 44 B of geometry (centre, opacity,
+// rotation, scale) in one round of loads, and the 192 B of SH only if it
+// survives the footprint cull.  Loads are structure-of-arrays, so consecutive
+// lanes touch consecutive words; the (view, block) segment of a record is
+// found by binary search in an LDS copy of the segment offsets.
 //
 // The geometry that decides integers (culls, footprint, depth key) is FP64 in
 // a fixed operation order; this file is compiled with -ffp-contract=off so the
@@ -17,6 +18,7 @@ namespace gs {
 namespace {
 
 constexpr int kPreThreads = 256;
+constexpr int kLdsOffsets = 4096;
 
 struct PreArgs {
   LevelPtrs lv[kMaxLevels];
@@ -39,13 +41,19 @@ __global__ void __launch_bounds__(kPreThreads) preprocess_kernel(PreArgs a, Reco
     n_rec = a.capacity;
   }
   const int nseg = a.V * a.B;
+  // segment offsets staged in LDS when they fit (the usual case: V * B <= 4095)
+  __shared__ int64_t s_off[kLdsOffsets];
+  const bool lds_off = nseg < kLdsOffsets;
+  if (lds_off)
+    for (int k = threadIdx.x; k <= nseg; k += blockDim.x) s_off[k] = a.offsets[k];
+  __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_rec; g += stride) {
-    const int p = find_segment(a.offsets, nseg, g);
+    const int p = lds_off ? find_segment(s_off, nseg, g) : find_segment(a.offsets, nseg, g);
     const int v = p / a.B, b = p - v * a.B;
     const int l = a.level[p];
     const LevelPtrs& L = a.lv[l];
-    const int64_t gi = a.lvl_off[(int64_t)b * a.L + l] + (g - a.offsets[p]);
+    const int64_t gi = a.lvl_off[(int64_t)b * a.L + l] + (g - (lds_off ? s_off[p] : a.offsets[p]));
     const gs_camera& cam = a.cams[v];
     Geo o;
     uint32_t key = kCulledKey;

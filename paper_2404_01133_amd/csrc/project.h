@@ -131,23 +131,28 @@ struct Geo {
   double opac;
 };
 
-// Decides culling and the footprint; returns false if culled.  Reads the
-// centre and opacity first and the rotation/scale only when still visible.
+// Decides culling and the footprint; returns false if culled.  All 44 bytes of
+// geometry (centre, opacity, rotation, scale) are requested at once so the
+// loads overlap; the SH coefficients are read later, only for survivors.
 __device__ __forceinline__ bool project_geo(const LevelPtrs& L, int64_t gi, const gs_camera& cam, int W, int H,
                                             Geo& o) {
   const int64_t n = L.n;
   const double* R = cam.R;
+  // every geometry load is issued before the first cull, so they overlap
   o.m[0] = L.means[gi];
   o.m[1] = L.means[n + gi];
   o.m[2] = L.means[2 * n + gi];
+  const float op32 = L.opac[gi];
+  const float q0f = L.quats[gi], q1f = L.quats[n + gi], q2f = L.quats[2 * n + gi], q3f = L.quats[3 * n + gi];
+  const float s0f = L.scales[gi], s1f = L.scales[n + gi], s2f = L.scales[2 * n + gi];
   o.tx = ((R[0] * o.m[0] + R[1] * o.m[1]) + R[2] * o.m[2]) + cam.t[0];
   o.ty = ((R[3] * o.m[0] + R[4] * o.m[1]) + R[5] * o.m[2]) + cam.t[1];
   o.tz = ((R[6] * o.m[0] + R[7] * o.m[1]) + R[8] * o.m[2]) + cam.t[2];
   if (!(o.tz > cam.znear)) return false;
-  o.opac = L.opac[gi];
+  o.opac = op32;
   if (!(o.opac >= 1.0 / 255.0)) return false;
   o.depth = (float)o.tz;
-  const double q0 = L.quats[gi], q1 = L.quats[n + gi], q2 = L.quats[2 * n + gi], q3 = L.quats[3 * n + gi];
+  const double q0 = q0f, q1 = q1f, q2 = q2f, q3 = q3f;
   const double qn2 = ((q0 * q0 + q1 * q1) + q2 * q2) + q3 * q3;
   if (!(qn2 > 0.0 && qn2 <= 1.0e300)) return false;
   o.qinv = 1.0 / sqrt(qn2);
@@ -162,9 +167,9 @@ __device__ __forceinline__ bool project_geo(const LevelPtrs& L, int64_t gi, cons
   o.Rq[2][0] = 2.0 * (x * z - w * y);
   o.Rq[2][1] = 2.0 * (y * z + w * x);
   o.Rq[2][2] = 1.0 - 2.0 * (x * x + y * y);
-  o.s[0] = L.scales[gi];
-  o.s[1] = L.scales[n + gi];
-  o.s[2] = L.scales[2 * n + gi];
+  o.s[0] = s0f;
+  o.s[1] = s1f;
+  o.s[2] = s2f;
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) o.Lm[i][j] = o.Rq[i][j] * o.s[j];
   for (int i = 0; i < 3; ++i)

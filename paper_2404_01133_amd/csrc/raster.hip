@@ -149,22 +149,45 @@ __global__ void __launch_bounds__(TW* TH) raster_fwd_kernel(const Record* __rest
 }
 
 // ---------------------------------------------------------------------------
-// wave64 sum with DPP row operations; the total ends in lane 63
+// Wave64 sums of nine per-lane values at once.  At butterfly level k (partner
+// lane = lane ^ 2^k) two quantities share one register: lanes with bit k clear
+// keep the first, lanes with bit k set the second, and each lane adds the
+// partner's copy of the quantity it keeps.  Nine registers become one after
+// four levels; two plain levels finish the sum.  On return lane q (q < 8)
+// holds the total of value q and lanes 8..15 the total of value 8.
 // ---------------------------------------------------------------------------
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ float dpp_add(float v) {
-  const int moved = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false);
-  return v + __int_as_float(moved);
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int PATTERN>
+__device__ __forceinline__ float swz(float v) {
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), PATTERN));
+}
+__device__ __forceinline__ float pack_add1(bool hi, float a, float b) {  // partner lane ^ 1
+  return (hi ? b : a) + dpp_mov<0xB1>(hi ? a : b);                      // quad_perm [1,0,3,2]
+}
+__device__ __forceinline__ float pack_add2(bool hi, float a, float b) {  // partner lane ^ 2
+  return (hi ? b : a) + dpp_mov<0x4E>(hi ? a : b);                      // quad_perm [2,3,0,1]
 }
 
-__device__ __forceinline__ float wave_sum_to_lane63(float v) {
-  v = dpp_add<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
-  v = dpp_add<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
-  v = dpp_add<0x141, 0xF>(v);  // row_half_mirror
-  v = dpp_add<0x140, 0xF>(v);  // row_mirror: every lane of a row holds the row sum
-  v = dpp_add<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-  v = dpp_add<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
-  return v;
+__device__ __forceinline__ float wave_sum9(const float v[9], int lane) {
+  const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4, b3 = lane & 8;
+  const float r0 = pack_add1(b0, v[0], v[1]);
+  const float r1 = pack_add1(b0, v[2], v[3]);
+  const float r2 = pack_add1(b0, v[4], v[5]);
+  const float r3 = pack_add1(b0, v[6], v[7]);
+  const float r4 = v[8] + dpp_mov<0xB1>(v[8]);
+  const float s0 = pack_add2(b1, r0, r1);
+  const float s1 = pack_add2(b1, r2, r3);
+  const float s2 = r4 + dpp_mov<0x4E>(r4);
+  // ds_swizzle bit-mask mode (and 0x1F, xor m) exchanges with lane ^ m inside 32 lanes
+  const float u0 = (b2 ? s1 : s0) + swz<0x101F>(b2 ? s0 : s1);
+  const float u1 = s2 + swz<0x101F>(s2);
+  float x = (b3 ? u1 : u0) + swz<0x201F>(b3 ? u0 : u1);
+  x += swz<0x401F>(x);
+  x += __shfl_xor(x, 32, 64);
+  return x;
 }
 
 constexpr int kG = 9;  // partials per Gaussian: r, g, b, opacity, A1, A2, Axx, Axy, Ayy
@@ -265,11 +288,8 @@ __global__ void __launch_bounds__(TW* TH) raster_bwd_kernel(
       A1c = use ? nA1 : A1c;
       A2c = use ? nA2 : A2c;
       T = use ? T * (1.0f - e.alpha) : T;
-#pragma unroll
-      for (int q = 0; q < kG; ++q) {
-        const float sum = wave_sum_to_lane63(c[q]);
-        if (lane == 63 && sum != 0.0f) atomicAdd(&s_grad[k * kG + q], sum);
-      }
+      const float sum = wave_sum9(c, lane);
+      if (lane < kG && sum != 0.0f) atomicAdd(&s_grad[k * kG + lane], sum);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < nb * kG; t += NT) {
@@ -294,7 +314,60 @@ struct BwdArgs {
   int32_t B, L, V, W, H, sh_degree;
 };
 
-__global__ void __launch_bounds__(256) preprocess_bwd_kernel(BwdArgs a, const float* __restrict__ grad2d,
+// With one view per call every Gaussian owns at most one record, so its
+// gradient is a plain read-modify-write; with several views records of the
+// same Gaussian may run concurrently and FP32 atomics are used.
+template <bool ATOMIC>
+__device__ __forceinline__ void accumulate(float* p, float v) {
+  if (ATOMIC) unsafeAtomicAdd(p, v);
+  else *p += v;
+}
+
+// Adjoint of the SH colour, FP32, one basis term at a time (no basis arrays
+// live): dL/df_{k,c} = Y_k g_c and dL/d(direction) += (sum_c g_c f_{k,c}) grad Y_k.
+template <bool ATOMIC>
+__device__ __forceinline__ void sh_adjoint(float x, float y, float z, int deg, const float* __restrict__ sh, int64_t n,
+                                           int64_t gi, const float g[3], float* __restrict__ dsh, float gdir[3]) {
+  auto term = [&](int k, float Y, float dx, float dy, float dz) {
+    const float f0 = sh[(int64_t)(3 * k + 0) * n + gi];
+    const float f1 = sh[(int64_t)(3 * k + 1) * n + gi];
+    const float f2 = sh[(int64_t)(3 * k + 2) * n + gi];
+    const float w = fmaf(g[0], f0, fmaf(g[1], f1, g[2] * f2));
+    gdir[0] = fmaf(w, dx, gdir[0]);
+    gdir[1] = fmaf(w, dy, gdir[1]);
+    gdir[2] = fmaf(w, dz, gdir[2]);
+    if (g[0] != 0.0f) accumulate<ATOMIC>(&dsh[(int64_t)(3 * k + 0) * n + gi], Y * g[0]);
+    if (g[1] != 0.0f) accumulate<ATOMIC>(&dsh[(int64_t)(3 * k + 1) * n + gi], Y * g[1]);
+    if (g[2] != 0.0f) accumulate<ATOMIC>(&dsh[(int64_t)(3 * k + 2) * n + gi], Y * g[2]);
+  };
+  const float k1 = (float)kSH1, k2a = (float)kSH2a, k2b = (float)kSH2b, k2c = (float)kSH2c;
+  const float k3a = (float)kSH3a, k3b = (float)kSH3b, k3c = (float)kSH3c, k3d = (float)kSH3d, k3e = (float)kSH3e;
+  term(0, (float)kSH00, 0.f, 0.f, 0.f);
+  if (deg < 1) return;
+  term(1, -k1 * y, 0.f, -k1, 0.f);
+  term(2, k1 * z, 0.f, 0.f, k1);
+  term(3, -k1 * x, -k1, 0.f, 0.f);
+  if (deg < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  term(4, k2a * x * y, k2a * y, k2a * x, 0.f);
+  term(5, -k2a * y * z, 0.f, -k2a * z, -k2a * y);
+  term(6, k2b * (2.f * zz - xx - yy), -2.f * k2b * x, -2.f * k2b * y, 4.f * k2b * z);
+  term(7, -k2a * x * z, -k2a * z, 0.f, -k2a * x);
+  term(8, k2c * (xx - yy), 2.f * k2c * x, -2.f * k2c * y, 0.f);
+  if (deg < 3) return;
+  term(9, -k3a * y * (3.f * xx - yy), -6.f * k3a * x * y, -3.f * k3a * (xx - yy), 0.f);
+  term(10, k3b * x * y * z, k3b * y * z, k3b * x * z, k3b * x * y);
+  term(11, -k3c * y * (4.f * zz - xx - yy), 2.f * k3c * x * y, -k3c * (4.f * zz - xx - 3.f * yy), -8.f * k3c * y * z);
+  term(12, k3d * z * (2.f * zz - 3.f * xx - 3.f * yy), -6.f * k3d * x * z, -6.f * k3d * y * z,
+       k3d * (6.f * zz - 3.f * xx - 3.f * yy));
+  term(13, -k3c * x * (4.f * zz - xx - yy), -k3c * (4.f * zz - 3.f * xx - yy), 2.f * k3c * x * y, -8.f * k3c * x * z);
+  term(14, k3e * z * (xx - yy), 2.f * k3e * x * z, -2.f * k3e * y * z, k3e * (xx - yy));
+  term(15, -k3a * x * (xx - 3.f * yy), -3.f * k3a * (xx - yy), 6.f * k3a * x * y, 0.f);
+}
+
+template <bool ATOMIC>
+__global__ void __launch_bounds__(256) preprocess_bwd_kernel(BwdArgs a, const Record* __restrict__ records,
+                                                             const float* __restrict__ grad2d,
                                                              const int64_t* __restrict__ counts) {
   int64_t n_rec = counts[GS_COUNT_RECORDS];
   if (n_rec > a.capacity) n_rec = a.capacity;
@@ -317,121 +390,152 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(BwdArgs a, const fl
     const int64_t n = L.n;
     const int64_t gi = a.lvl_off[(int64_t)b * a.L + l] + (g - a.offsets[p]);
     const gs_camera& cam = a.cams[v];
-    Geo o;
-    if (!project_geo(L, gi, cam, a.W, a.H, o)) continue;
-    const double* R = cam.R;
+    // A record with a non-zero 2D gradient was visible in the forward pass, so
+    // the projection below (same code, same inputs) takes the same decisions.
+    // ---- colour first (FP32): clamped channels (record colour exactly 0) pass no gradient
+    double dm_col[3];
+    {
+      const float4 w2 = reinterpret_cast<const float4*>(&records[g])[2];
+      const float grgb[3] = {w2.x > 0.0f ? p2[0] : 0.0f, w2.y > 0.0f ? p2[1] : 0.0f, w2.z > 0.0f ? p2[2] : 0.0f};
+      double C[3];
+      camera_centre(cam, C);
+      const double d0 = (double)L.means[gi] - C[0], d1 = (double)L.means[n + gi] - C[1],
+                   d2 = (double)L.means[2 * n + gi] - C[2];
+      const double dn = sqrt((d0 * d0 + d1 * d1) + d2 * d2);
+      const float dir[3] = {(float)(d0 / dn), (float)(d1 / dn), (float)(d2 / dn)};
+      float gdir[3] = {0.0f, 0.0f, 0.0f};
+      sh_adjoint<ATOMIC>(dir[0], dir[1], dir[2], a.sh_degree, L.sh, n, gi, grgb, G.sh, gdir);
+      const float gd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
+      for (int k = 0; k < 3; ++k) dm_col[k] = (double)(gdir[k] - dir[k] * gd) / dn;
+    }
+    // ---- geometry adjoint (FP32); the guard-band clamp is decided in FP64 exactly as in the forward pass
+    const double* R64 = cam.R;
+    const double m0 = L.means[gi], m1 = L.means[n + gi], m2 = L.means[2 * n + gi];
+    const double tx64 = ((R64[0] * m0 + R64[1] * m1) + R64[2] * m2) + cam.t[0];
+    const double ty64 = ((R64[3] * m0 + R64[4] * m1) + R64[5] * m2) + cam.t[1];
+    const double tz64 = ((R64[6] * m0 + R64[7] * m1) + R64[8] * m2) + cam.t[2];
+    const double rz64 = 1.0 / tz64;
+    const double ux64 = tx64 * rz64, uy64 = ty64 * rz64;
+    const double limx = 1.3 * ((0.5 * a.W) / cam.fx), limy = 1.3 * ((0.5 * a.H) / cam.fy);
+    const double uxc64 = dmin_(limx, dmax_(-limx, ux64)), uyc64 = dmin_(limy, dmax_(-limy, uy64));
+    const bool clamp_x = uxc64 != ux64, clamp_y = uyc64 != uy64;
+    const float tx = (float)tx64, ty = (float)ty64, rz = (float)rz64;
+    const float uxc = (float)uxc64, uyc = (float)uyc64;
+    const float fx = (float)cam.fx, fy = (float)cam.fy;
+    float Rc[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Rc[k] = (float)R64[k];
+    // rotation of the normalised quaternion, scales
+    const float qa = L.quats[gi], qb = L.quats[n + gi], qc = L.quats[2 * n + gi], qd_ = L.quats[3 * n + gi];
+    const float qinv = 1.0f / sqrtf(qa * qa + qb * qb + qc * qc + qd_ * qd_);
+    const float w = qa * qinv, x = qb * qinv, y = qc * qinv, z = qd_ * qinv;
+    float Rq[3][3];
+    Rq[0][0] = 1.f - 2.f * (y * y + z * z);
+    Rq[0][1] = 2.f * (x * y - w * z);
+    Rq[0][2] = 2.f * (x * z + w * y);
+    Rq[1][0] = 2.f * (x * y + w * z);
+    Rq[1][1] = 1.f - 2.f * (x * x + z * z);
+    Rq[1][2] = 2.f * (y * z - w * x);
+    Rq[2][0] = 2.f * (x * z - w * y);
+    Rq[2][1] = 2.f * (y * z + w * x);
+    Rq[2][2] = 1.f - 2.f * (x * x + y * y);
+    const float sc[3] = {L.scales[gi], L.scales[n + gi], L.scales[2 * n + gi]};
+    float WL[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        WL[i][j] = (Rc[3 * i] * Rq[0][j] + Rc[3 * i + 1] * Rq[1][j] + Rc[3 * i + 2] * Rq[2][j]) * sc[j];
+    const float J00 = fx * rz, J02 = -(fx * uxc) * rz, J11 = fy * rz, J12 = -(fy * uyc) * rz;
+    float M[2][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      M[0][j] = J00 * WL[0][j] + J02 * WL[2][j];
+      M[1][j] = J11 * WL[1][j] + J12 * WL[2][j];
+    }
+    const float n0 = M[0][0] * M[0][0] + M[0][1] * M[0][1] + M[0][2] * M[0][2];
+    const float n1 = M[1][0] * M[1][0] + M[1][1] * M[1][1] + M[1][2] * M[1][2];
+    const float sb = M[0][0] * M[1][0] + M[0][1] * M[1][1] + M[0][2] * M[1][2];
+    const float sa = n0 + 0.3f, sc2 = n1 + 0.3f;
+    const float cr0 = M[0][1] * M[1][2] - M[0][2] * M[1][1];
+    const float cr1 = M[0][2] * M[1][0] - M[0][0] * M[1][2];
+    const float cr2 = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+    const float det = cr0 * cr0 + cr1 * cr1 + cr2 * cr2 + 0.3f * (n0 + n1) + 0.09f;
     // ---- 2D mean and conic partials ----
-    const double ca = kConicScale * sqrt(o.c / o.det);
-    const double cb = -kConicScale * o.b / sqrt(o.c * o.det);
-    const double cc = kConicScale / sqrt(o.c);
-    const double gu = -2.0 * ca * p2[4];
-    const double gv = -2.0 * (cb * p2[4] + cc * p2[5]);
-    const double gA = kConicScale2 * p2[6];
-    const double gB = 2.0 * kConicScale2 * p2[7];
-    const double gC = kConicScale2 * p2[8];
+    const float kS = (float)kConicScale, kS2 = (float)kConicScale2;
+    const float ca = kS * sqrtf(sc2 / det);
+    const float cb = -kS * sb / sqrtf(sc2 * det);
+    const float cc = kS / sqrtf(sc2);
+    const float gu = -2.0f * ca * p2[4];
+    const float gv = -2.0f * (cb * p2[4] + cc * p2[5]);
+    const float gA = kS2 * p2[6], gB = 2.0f * kS2 * p2[7], gC = kS2 * p2[8];
     // conic K = Sigma2D^-1;  dL/dSigma = -K Gk K with Gk = [[gA, gB/2], [gB/2, gC]]
-    const double KA = o.c / o.det, KB = -o.b / o.det, KC = o.a / o.det;
-    const double h = 0.5 * gB;
-    const double t00 = gA * KA + h * KB, t01 = gA * KB + h * KC;  // Gk K
-    const double t10 = h * KA + gC * KB, t11 = h * KB + gC * KC;
-    const double S00 = -(KA * t00 + KB * t10);
-    const double S01 = -(KA * t01 + KB * t11);
-    const double S11 = -(KB * t01 + KC * t11);
-    // Sigma2D = M M^T + 0.3 I  ->  dL/dM = 2 Gs M, Gs = [[S00, S01], [S01, S11]]
-    double dM[2][3];
-    for (int jj = 0; jj < 3; ++jj) {
-      dM[0][jj] = 2.0 * (S00 * o.M[0][jj] + S01 * o.M[1][jj]);
-      dM[1][jj] = 2.0 * (S01 * o.M[0][jj] + S11 * o.M[1][jj]);
-    }
-    // M = J WL
-    const double dJ00 = dM[0][0] * o.WL[0][0] + dM[0][1] * o.WL[0][1] + dM[0][2] * o.WL[0][2];
-    const double dJ02 = dM[0][0] * o.WL[2][0] + dM[0][1] * o.WL[2][1] + dM[0][2] * o.WL[2][2];
-    const double dJ11 = dM[1][0] * o.WL[1][0] + dM[1][1] * o.WL[1][1] + dM[1][2] * o.WL[1][2];
-    const double dJ12 = dM[1][0] * o.WL[2][0] + dM[1][1] * o.WL[2][1] + dM[1][2] * o.WL[2][2];
-    double dWL[3][3];
-    for (int jj = 0; jj < 3; ++jj) {
-      dWL[0][jj] = o.J00 * dM[0][jj];
-      dWL[1][jj] = o.J11 * dM[1][jj];
-      dWL[2][jj] = o.J02 * dM[0][jj] + o.J12 * dM[1][jj];
-    }
-    // WL = R_cam Lm,  Lm = Rq diag(s)
-    double dLm[3][3];
-    for (int ii = 0; ii < 3; ++ii)
-      for (int jj = 0; jj < 3; ++jj)
-        dLm[ii][jj] = R[ii] * dWL[0][jj] + R[3 + ii] * dWL[1][jj] + R[6 + ii] * dWL[2][jj];
-    double ds[3], dRq[3][3];
-    for (int jj = 0; jj < 3; ++jj) {
-      ds[jj] = o.Rq[0][jj] * dLm[0][jj] + o.Rq[1][jj] * dLm[1][jj] + o.Rq[2][jj] * dLm[2][jj];
-      for (int ii = 0; ii < 3; ++ii) dRq[ii][jj] = o.s[jj] * dLm[ii][jj];
-    }
-    // rotation matrix of the unit quaternion (w, x, y, z)
-    const double w = o.q[0], x = o.q[1], y = o.q[2], z = o.q[3];
-    double dq[4];
-    dq[0] = 2.0 * (-z * dRq[0][1] + y * dRq[0][2] + z * dRq[1][0] - x * dRq[1][2] - y * dRq[2][0] + x * dRq[2][1]);
-    dq[1] = 2.0 * (y * dRq[0][1] + z * dRq[0][2] + y * dRq[1][0] - w * dRq[1][2] + z * dRq[2][0] + w * dRq[2][1]) -
-            4.0 * x * (dRq[1][1] + dRq[2][2]);
-    dq[2] = 2.0 * (x * dRq[0][1] + w * dRq[0][2] + x * dRq[1][0] + z * dRq[1][2] - w * dRq[2][0] + z * dRq[2][1]) -
-            4.0 * y * (dRq[0][0] + dRq[2][2]);
-    dq[3] = 2.0 * (-w * dRq[0][1] + x * dRq[0][2] + w * dRq[1][0] + y * dRq[1][2] + x * dRq[2][0] + y * dRq[2][1]) -
-            4.0 * z * (dRq[0][0] + dRq[1][1]);
-    // normalisation q_hat = q / |q|
-    const double qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
-    double gq[4];
-    for (int k = 0; k < 4; ++k) gq[k] = (dq[k] - o.q[k] * qd) * o.qinv;
-    // J(t) and (u, v)(t)
-    const double fx = cam.fx, fy = cam.fy, rz = o.rz, rz2 = rz * rz;
-    double dt0 = gu * fx * rz, dt1 = gv * fy * rz;
-    double dt2 = -gu * fx * o.tx * rz2 - gv * fy * o.ty * rz2;
-    dt2 += -dJ00 * fx * rz2 - dJ11 * fy * rz2;
-    if (!o.clamp_x) {
-      dt0 += -dJ02 * fx * rz2;
-      dt2 += dJ02 * 2.0 * fx * o.tx * rz2 * rz;
-    } else {
-      dt2 += dJ02 * fx * o.uxc * rz2;
-    }
-    if (!o.clamp_y) {
-      dt1 += -dJ12 * fy * rz2;
-      dt2 += dJ12 * 2.0 * fy * o.ty * rz2 * rz;
-    } else {
-      dt2 += dJ12 * fy * o.uyc * rz2;
-    }
-    double dm[3];
-    for (int k = 0; k < 3; ++k) dm[k] = R[k] * dt0 + R[3 + k] * dt1 + R[6 + k] * dt2;
-    // colour: SH coefficients and the view direction
-    double C[3];
-    camera_centre(cam, C);
-    const double d0 = o.m[0] - C[0], d1 = o.m[1] - C[1], d2 = o.m[2] - C[2];
-    const double dn = sqrt((d0 * d0 + d1 * d1) + d2 * d2);
-    const double dir[3] = {d0 / dn, d1 / dn, d2 / dn};
-    double Y[16], dY[16][3];
-    const int nk = sh_basis(dir[0], dir[1], dir[2], a.sh_degree, Y);
-    sh_basis_grad(dir[0], dir[1], dir[2], a.sh_degree, dY);
-    double col[3] = {0.0, 0.0, 0.0};
-    for (int k = 0; k < nk; ++k)
-      for (int ch = 0; ch < 3; ++ch) col[ch] += Y[k] * (double)L.sh[(int64_t)(3 * k + ch) * n + gi];
-    double grgb[3];
-    for (int ch = 0; ch < 3; ++ch) grgb[ch] = (col[ch] + 0.5 >= 0.0) ? (double)p2[ch] : 0.0;
-    double gdir[3] = {0.0, 0.0, 0.0};
-    for (int k = 0; k < nk; ++k) {
-      double wk = 0.0;
-      for (int ch = 0; ch < 3; ++ch) {
-        const double f = L.sh[(int64_t)(3 * k + ch) * n + gi];
-        wk += grgb[ch] * f;
-        const float gsh = (float)(Y[k] * grgb[ch]);
-        if (gsh != 0.0f) unsafeAtomicAdd(&G.sh[(int64_t)(3 * k + ch) * n + gi], gsh);
+    const float KA = sc2 / det, KB = -sb / det, KC = sa / det;
+    const float h = 0.5f * gB;
+    const float t00 = gA * KA + h * KB, t01 = gA * KB + h * KC;
+    const float t10 = h * KA + gC * KB, t11 = h * KB + gC * KC;
+    const float S00 = -(KA * t00 + KB * t10);
+    const float S01 = -(KA * t01 + KB * t11);
+    const float S11 = -(KB * t01 + KC * t11);
+    // Sigma2D = M M^T + 0.3 I -> dL/dM = 2 Gs M; M = J WL; WL = R_cam Rq diag(s), one column at a time
+    float dJ00 = 0.f, dJ02 = 0.f, dJ11 = 0.f, dJ12 = 0.f;
+    float ds[3], dRq[3][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const float dM0 = 2.0f * (S00 * M[0][j] + S01 * M[1][j]);
+      const float dM1 = 2.0f * (S01 * M[0][j] + S11 * M[1][j]);
+      dJ00 += dM0 * WL[0][j];
+      dJ02 += dM0 * WL[2][j];
+      dJ11 += dM1 * WL[1][j];
+      dJ12 += dM1 * WL[2][j];
+      const float dW0 = J00 * dM0, dW1 = J11 * dM1, dW2 = J02 * dM0 + J12 * dM1;
+      float acc = 0.f;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const float dLm = Rc[i] * dW0 + Rc[3 + i] * dW1 + Rc[6 + i] * dW2;  // (R_cam^T dWL)[i][j]
+        acc += Rq[i][j] * dLm;
+        dRq[i][j] = sc[j] * dLm;
       }
-      gdir[0] += wk * dY[k][0];
-      gdir[1] += wk * dY[k][1];
-      gdir[2] += wk * dY[k][2];
+      ds[j] = acc;
     }
-    const double gd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
-    for (int k = 0; k < 3; ++k) dm[k] += (gdir[k] - dir[k] * gd) / dn;
+    float dq[4];
+    dq[0] = 2.f * (-z * dRq[0][1] + y * dRq[0][2] + z * dRq[1][0] - x * dRq[1][2] - y * dRq[2][0] + x * dRq[2][1]);
+    dq[1] = 2.f * (y * dRq[0][1] + z * dRq[0][2] + y * dRq[1][0] - w * dRq[1][2] + z * dRq[2][0] + w * dRq[2][1]) -
+            4.f * x * (dRq[1][1] + dRq[2][2]);
+    dq[2] = 2.f * (x * dRq[0][1] + w * dRq[0][2] + x * dRq[1][0] + z * dRq[1][2] - w * dRq[2][0] + z * dRq[2][1]) -
+            4.f * y * (dRq[0][0] + dRq[2][2]);
+    dq[3] = 2.f * (-w * dRq[0][1] + x * dRq[0][2] + w * dRq[1][0] + y * dRq[1][2] + x * dRq[2][0] + y * dRq[2][1]) -
+            4.f * z * (dRq[0][0] + dRq[1][1]);
+    const float qdot = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
+    const float qn[4] = {w, x, y, z};
+    float gq[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) gq[k] = (dq[k] - qn[k] * qdot) * qinv;
+    // J(t) and (u, v)(t)
+    const float rz2 = rz * rz;
+    float dt0 = gu * fx * rz, dt1 = gv * fy * rz;
+    float dt2 = -gu * fx * tx * rz2 - gv * fy * ty * rz2 - dJ00 * fx * rz2 - dJ11 * fy * rz2;
+    if (!clamp_x) {
+      dt0 += -dJ02 * fx * rz2;
+      dt2 += dJ02 * 2.0f * fx * tx * rz2 * rz;
+    } else {
+      dt2 += dJ02 * fx * uxc * rz2;
+    }
+    if (!clamp_y) {
+      dt1 += -dJ12 * fy * rz2;
+      dt2 += dJ12 * 2.0f * fy * ty * rz2 * rz;
+    } else {
+      dt2 += dJ12 * fy * uyc * rz2;
+    }
+    float dm[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dm[k] = Rc[k] * dt0 + Rc[3 + k] * dt1 + Rc[6 + k] * dt2 + (float)dm_col[k];
     for (int k = 0; k < 3; ++k) {
-      unsafeAtomicAdd(&G.means[k * n + gi], (float)dm[k]);
-      unsafeAtomicAdd(&G.scales[k * n + gi], (float)ds[k]);
+      accumulate<ATOMIC>(&G.means[k * n + gi], dm[k]);
+      accumulate<ATOMIC>(&G.scales[k * n + gi], ds[k]);
     }
-    for (int k = 0; k < 4; ++k) unsafeAtomicAdd(&G.quats[k * n + gi], (float)gq[k]);
-    unsafeAtomicAdd(&G.opac[gi], p2[3]);
+    for (int k = 0; k < 4; ++k) accumulate<ATOMIC>(&G.quats[k * n + gi], gq[k]);
+    accumulate<ATOMIC>(&G.opac[gi], p2[3]);
   }
 }
 
@@ -568,8 +672,11 @@ extern "C" gs_status gs_rasterize_bwd(const void* records, const uint32_t* pair_
   a.H = height;
   a.sh_degree = sh_degree;
   int64_t gb = (record_capacity + 255) / 256;
-  hipLaunchKernelGGL(preprocess_bwd_kernel, dim3((unsigned)(gb < 8192 ? (gb < 1 ? 1 : gb) : 8192)), dim3(256), 0, s, a,
-                     grad2d, counts);
+  const dim3 gbg((unsigned)(gb < 8192 ? (gb < 1 ? 1 : gb) : 8192));
+  if (n_views == 1)
+    hipLaunchKernelGGL(preprocess_bwd_kernel<false>, gbg, dim3(256), 0, s, a, rec, grad2d, counts);
+  else
+    hipLaunchKernelGGL(preprocess_bwd_kernel<true>, gbg, dim3(256), 0, s, a, rec, grad2d, counts);
   GS_LAUNCH_CHECK();
   return GS_OK;
 }
