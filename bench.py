@@ -27,6 +27,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 VALU peak without packed-FP32 instructions (which this build does not
+# emit): 256 CUs x 64 FMA lanes per clock x 2 flops x 2.4 GHz
+VALU_FP32_PEAK_TFLOPS = 78.6
+# algorithmic FP32 work of one (pixel, Gaussian) evaluation inside the footprint:
+# offset (4), conic quadratic form (7), exp (1), alpha (1), transmittance (2),
+# alpha*T (1), colour update (3 FMA = 6)
+FLOPS_PER_EVAL = 22
 
 
 def log(*a):
@@ -81,12 +88,21 @@ def main():
     # ---- capacities from one eager pass over every view -------------------------
     frame = render.Frame(scene.n_blocks, 1, W, H, scene.max_records_per_view(), 1 << 22, device=dev)
     stats = []
+    evals = []
     for v in range(V):
         render.render_frame(scene, frame, cam_slot[v], thresholds=thresholds)
-        stats.append(frame.host_counts())
+        c = frame.host_counts()
+        stats.append(c)
+        # (pixel, Gaussian) evaluations the compositing must do: sum of the visible footprints' areas
+        nr = c["records"]
+        rec = frame.records[: nr * gs.record_bytes()].view(torch.int32).view(nr, 12)
+        w = ((rec[:, 2] >> 16) & 0xFFFF).to(torch.int64) + 1
+        h = ((rec[:, 3] >> 16) & 0xFFFF).to(torch.int64) + 1
+        evals.append(int(((w * h) * (frame.tiles_touched[:nr] > 0)).sum().item()))
     n_sel = np.array([s["records"] for s in stats])
     n_vis = np.array([s["visible"] for s in stats])
     n_pairs = np.array([s["pairs"] for s in stats])
+    n_eval = np.array(evals, dtype=np.float64)
     log("per view: N_sel mean %.0f (max %d), N_vis mean %.0f, pairs mean %.0f (max %d)" %
         (n_sel.mean(), n_sel.max(), n_vis.mean(), n_pairs.mean(), n_pairs.max()))
 
@@ -190,6 +206,9 @@ def main():
     # 224 B (rotation, scale, opacity, SH) read + 48 B record written per visible record
     pre_bytes = float(np.mean(20.0 * n_sel + 272.0 * n_vis))
     pre_gbs = pre_bytes / (pre_ms * 1e-3) / 1e9
+    ras_ms = float(np.mean(kern_ms["rasterize_fwd"]))
+    ras_flops = float(np.mean(n_eval)) * FLOPS_PER_EVAL
+    ras_tflops = ras_flops / (ras_ms * 1e-3) / 1e12
     log("kernel ms (mean over views): preprocess %.4f, bin_sort %.4f, rasterize_fwd %.4f" %
         (pre_ms, np.mean(kern_ms["bin_sort"]), np.mean(kern_ms["rasterize_fwd"])))
 
@@ -313,9 +332,14 @@ def main():
         "fps_min_view": float(fps_views.min()),
         "gaussians_per_s": float(n_sel.mean() * fps),
         "n_sel_mean": float(n_sel.mean()), "n_vis_mean": float(n_vis.mean()), "pairs_mean": float(n_pairs.mean()),
-        "roofline": {"bound": "hbm", "kernel": "preprocess", "achieved": pre_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": pre_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "avg_launch_ms": pre_ms, "algorithmic_bytes_per_launch": pre_bytes},
+        "roofline": {"bound": "alu", "kernel": "rasterize_fwd (raster_fwd_kernel<16,16,256>)",
+                     "achieved": ras_tflops, "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": ras_tflops / VALU_FP32_PEAK_TFLOPS, "traffic": None, "avg_launch_ms": ras_ms,
+                     "algorithmic_flops_per_launch": ras_flops, "evals_per_launch": float(np.mean(n_eval)),
+                     "flops_per_eval": FLOPS_PER_EVAL},
+        "roofline_preprocess": {"bound": "hbm", "kernel": "preprocess", "achieved": pre_gbs, "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": pre_gbs / HBM_PEAK_GBS, "traffic": None,
+                                "avg_launch_ms": pre_ms, "algorithmic_bytes_per_launch": pre_bytes},
         "kernel_ms": {k: float(np.mean(v)) for k, v in kern_ms.items()},
         "cpu_baseline": cpu,
     }
