@@ -1,22 +1,32 @@
-"""Benchmark: block-wise LoD render of a 20M-Gaussian synthetic city at 1600x900.
+"""Benchmark of the MI355X rendering path.
 
-One step = LoD-render every evaluation view once (48 views: heights 50/150/400 m,
-8 positions each, pitch -90 and -45 degrees), one frame at a time:
-    lod_select -> preprocess -> bin_sort -> rasterize_fwd
-replayed from a HIP graph.  `value` = frames per second over the step.
+Default workload (the headline line): block-wise LoD render of a 20M-Gaussian
+synthetic city at 1600x900.  One step = every evaluation view rendered once
+(48 views: heights 50/150/400 m, 8 positions each, pitch -90 and -45 degrees),
+one frame at a time:  lod_select -> preprocess -> bin_sort -> rasterize_fwd,
+replayed from a HIP graph, with the tile launch shape chosen by the autotuner
+(bit-identical images required).  `value` = frames per second over the step.
 
-Also reported: per-view FPS distribution (mean / median / min, as in the paper's
-Fig. 5), the plain comparator (same library, LoD off: every block at the finest
-level, eager launches), fwd+bwd ms/view for LoD and plain, the roofline of the
-dominant kernel measured with HIP events, and the CPU oracle's frame time.
+Also reported: per-view FPS distribution (mean / median / min), the plain
+comparator (same library, LoD off: every block at the finest level, eager
+launches, default 16x16 tiles), fwd+bwd ms/view for LoD and plain, the
+roofline of the dominant kernel measured with HIP events, the preprocess HBM
+roofline, and the CPU oracle's frame time on a bounded sample.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 20000000]
+Other workloads (their own JSON line, not the headline):
+  --workload batched   16 training views of one 2M-Gaussian block at 1600x900 in one
+                       call (shared selection, persistent work queue), fwd+L1+bwd
+                       captured in a HIP graph, vs 16 separate plain fwd+bwd calls
+  --workload uneven    32 blocks of 0.2M-3M Gaussians, 4 views each at 1280x720:
+                       LoD select + fwd + bwd batched, autotuned launch shape, vs
+                       per-view calls with the default shape
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 20000000] [--workload lod]
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -45,31 +55,47 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=20_000_000, help="finest-level Gaussians")
+    ap.add_argument("--workload", choices=("lod", "batched", "uneven"), default="lod")
+    ap.add_argument("--n", type=int, default=20_000_000, help="finest-level Gaussians (lod workload)")
     ap.add_argument("--n-xy", type=int, default=8, help="camera positions per height")
     ap.add_argument("--bwd-views", type=int, default=12, help="views used for the fwd+bwd timing")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--frames-only", action="store_true", help="only the timed LoD frames (for profilers)")
     ap.add_argument("--bwd-only", action="store_true", help="only the LoD fwd+bwd loop (for profilers)")
+    ap.add_argument("--tuning", default=None, help="tile_w,tile_h,batch,flags instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run three 512 MiB device-to-device copies (reference for HBM byte counters)")
     return ap.parse_args()
 
 
-def main():
-    args = parse()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
-              file=sys.stderr)
-        sys.exit(2)
-    import torch
+def graph_of(torch, fn, stream):
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        fn()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=stream):
+            fn()
+    torch.cuda.synchronize()
+    return g
 
-    from paper_2404_01133_amd import gs, render, synth
 
+def timed_replays(torch, g, steps, warmup):
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) / steps
+
+
+# -------------------------------------------------------------------------------------------
+def workload_lod(args, torch, gs, render, synth):
     dev = "cuda:0"
-    torch.cuda.set_device(0)
     W, H = 1600, 900
     thresholds = (200.0, 500.0)
     t0 = time.time()
@@ -84,11 +110,17 @@ def main():
     V = len(cams)
     cams_all = gs.cameras_to_device(cams, dev)
     cam_slot = [cams_all[v * 152:(v + 1) * 152] for v in range(V)]
+    rc = scene.max_records_per_view()
 
-    # ---- capacities from one eager pass over every view -------------------------
-    frame = render.Frame(scene.n_blocks, 1, W, H, scene.max_records_per_view(), 1 << 22, device=dev)
-    stats = []
-    evals = []
+    def new_frame(tw=16, th=16, batch=256, flags=0):
+        f = render.Frame(scene.n_blocks, 1, W, H, rc, 1 << 22, gs.tuning_struct(tw, th, batch, flags), device=dev)
+        for v in range(V):  # grow the pair capacity to fit every view
+            render.render_frame(scene, f, cam_slot[v], thresholds=thresholds)
+        return f
+
+    # ---- capacities and per-view statistics from one eager pass ----------------------
+    frame = render.Frame(scene.n_blocks, 1, W, H, rc, 1 << 22, device=dev)
+    stats, evals = [], []
     for v in range(V):
         render.render_frame(scene, frame, cam_slot[v], thresholds=thresholds)
         c = frame.host_counts()
@@ -103,8 +135,13 @@ def main():
     n_vis = np.array([s["visible"] for s in stats])
     n_pairs = np.array([s["pairs"] for s in stats])
     n_eval = np.array(evals, dtype=np.float64)
-    log("per view: N_sel mean %.0f (max %d), N_vis mean %.0f, pairs mean %.0f (max %d)" %
-        (n_sel.mean(), n_sel.max(), n_vis.mean(), n_pairs.mean(), n_pairs.max()))
+    log("per view: N_sel mean %.0f (max %d), N_vis mean %.0f, pairs mean %.0f (max %d), evals mean %.0f" %
+        (n_sel.mean(), n_sel.max(), n_vis.mean(), n_pairs.mean(), n_pairs.max(), n_eval.mean()))
+    stream = torch.cuda.Stream()
+
+    def lod_step(f):
+        return lambda: [render.render_frame(scene, f, cam_slot[v], thresholds=thresholds, check=False)
+                        for v in range(V)]
 
     if args.bwd_only:
         grads = [lv.zeros_like() for lv in scene.levels]
@@ -118,30 +155,55 @@ def main():
         print(json.dumps({"bwd_only": True}))
         return
 
-    # ---- HIP graph of one step (all views, one frame each) -------------------------
-    stream = torch.cuda.Stream()
-    torch.cuda.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.stream(stream):
-        render.render_frame(scene, frame, cam_slot[0], thresholds=thresholds, check=False)  # warm the stream
-        torch.cuda.synchronize()
-        with torch.cuda.graph(graph, stream=stream):
-            for v in range(V):
-                render.render_frame(scene, frame, cam_slot[v], thresholds=thresholds, check=False)
-    torch.cuda.synchronize()
-    for _ in range(args.warmup):
-        graph.replay()
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        graph.replay()
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t_start
-    ms_per_step = 1e3 * t_total / args.steps
-    fps = V * args.steps / t_total
+    # ---- launch shape: autotuned (bit-identical images required) or given ------------
+    default_step_ms = None
+    tune_report = None
+    if args.tuning:
+        tw, th, b, fl = (int(x) for x in args.tuning.split(","))
+        frame = new_frame(tw, th, b, fl)
+    elif not (args.no_autotune or args.frames_only):
+        from paper_2404_01133_amd import autotune
+        frames = {(16, 16): frame}
+        gate_views = [0, V // 3, 2 * V // 3, V - 1]
+
+        def make_runner(cand):
+            key = (cand.tile_w, cand.tile_h)
+            if key not in frames:
+                frames[key] = new_frame(*key)
+            f = frames[key]
+            f.tuning = cand.tuning()
+
+            def images():
+                out = []
+                for v in gate_views:
+                    render.render_frame(scene, f, cam_slot[v], thresholds=thresholds, check=False)
+                    out.append(f.rgb.clone())
+                return torch.cat(out)
+            return lod_step(f), images
+
+        t_at = time.time()
+        best, tune_report = autotune.tune("lod_city_%d_%dx%d_%dviews" % (args.n, W, H, V), make_runner,
+                                          use_cache=False)
+        log("autotune: best %s at %.3f ms/step (default %.3f ms), %d candidates rejected, %.1fs" %
+            (best.as_dict(), tune_report["best_ms"], tune_report["default_ms"], tune_report["rejected"],
+             time.time() - t_at))
+        default_step_ms = tune_report["default_ms"]
+        frame = frames[(best.tile_w, best.tile_h)]
+        frame.tuning = best.tuning()
+        for key in list(frames):
+            if key != (best.tile_w, best.tile_h):
+                del frames[key]
+    tun = frame.tuning
+    tuning_desc = dict(tile_w=tun.tile_w, tile_h=tun.tile_h, batch=tun.batch, flags=tun.flags)
+
+    # ---- HIP graph of one step (all views, one frame each) ---------------------------
+    graph = graph_of(torch, lod_step(frame), stream)
+    step_s = timed_replays(torch, graph, args.steps, args.warmup)
+    ms_per_step = 1e3 * step_s
+    fps = V / step_s
     if frame.host_counts()["flags"]:
         raise RuntimeError("capacity flag raised during the timed frames: %s" % frame.host_counts())
-    log("LoD graph: %.3f ms/step, %.1f FPS" % (ms_per_step, fps))
+    log("LoD graph (%s): %.3f ms/step, %.1f FPS" % (tuning_desc, ms_per_step, fps))
     if args.copy_calibration:
         src = torch.ones(128 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -150,18 +212,18 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if args.frames_only:
-        print(json.dumps({"metric": "FPS", "value": fps, "ms_per_step": ms_per_step,
+        print(json.dumps({"metric": "FPS", "value": fps, "ms_per_step": ms_per_step, "tuning": tuning_desc,
                           "n_sel_mean": float(n_sel.mean()), "n_vis_mean": float(n_vis.mean()),
                           "pairs_mean": float(n_pairs.mean())}))
         return
+    del graph
 
-    # ---- per-view FPS distribution (one graph per view) ----------------------------
+    # ---- per-view FPS distribution (one graph per view) ------------------------------
     per_view_ms = []
-    with torch.cuda.stream(stream):
-        for v in range(V):
-            gv = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(gv, stream=stream):
-                render.render_frame(scene, frame, cam_slot[v], thresholds=thresholds, check=False)
+    for v in range(V):
+        gv = graph_of(torch, lambda: render.render_frame(scene, frame, cam_slot[v], thresholds=thresholds,
+                                                         check=False), stream)
+        with torch.cuda.stream(stream):
             for _ in range(2):
                 gv.replay()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -171,12 +233,11 @@ def main():
                 gv.replay()
             e1.record(stream)
             e1.synchronize()
-            per_view_ms.append(e0.elapsed_time(e1) / reps)
-            del gv
-    per_view_ms = np.array(per_view_ms)
-    fps_views = 1e3 / per_view_ms
+        per_view_ms.append(e0.elapsed_time(e1) / reps)
+        del gv
+    fps_views = 1e3 / np.array(per_view_ms)
 
-    # ---- dominant kernels timed with HIP events (eager, on their own stream) -------
+    # ---- kernels timed with HIP events on the stream they run on ---------------------
     kern_ms = {"preprocess": [], "rasterize_fwd": [], "bin_sort": []}
     blocks = scene.blocks_struct()
     with torch.cuda.stream(stream):
@@ -192,10 +253,10 @@ def main():
             ev[1].record(stream)
             gs.bin_sort(frame.records, frame.depth_keys, frame.tiles_touched, 1, W, H, frame.tuning,
                         frame.record_capacity, frame.pair_capacity, frame.pair_tiles, frame.pair_records,
-                        frame.tile_ranges, frame.counts, frame.sort_ws, stream)
+                        frame.tile_ranges, frame.counts, frame.sort_ws, stream, frame.tile_queue)
             ev[2].record(stream)
             gs.rasterize_fwd(frame.records, frame.pair_records, frame.tile_ranges, 1, W, H, (0.0, 0.0, 0.0),
-                             frame.tuning, frame.rgb, frame.T, frame.n_last, stream)
+                             frame.tuning, frame.rgb, frame.T, frame.n_last, stream, frame.tile_queue)
             ev[3].record(stream)
             ev[3].synchronize()
             kern_ms["preprocess"].append(ev[0].elapsed_time(ev[1]))
@@ -210,13 +271,13 @@ def main():
     ras_flops = float(np.mean(n_eval)) * FLOPS_PER_EVAL
     ras_tflops = ras_flops / (ras_ms * 1e-3) / 1e12
     log("kernel ms (mean over views): preprocess %.4f, bin_sort %.4f, rasterize_fwd %.4f" %
-        (pre_ms, np.mean(kern_ms["bin_sort"]), np.mean(kern_ms["rasterize_fwd"])))
+        (pre_ms, np.mean(kern_ms["bin_sort"]), ras_ms))
 
     out_extra = {}
-    # ---- plain comparator: LoD off, every block at the finest level, eager ----------
+    # ---- plain comparator: LoD off, every block at the finest level, eager, 16x16 ----
+    pframe = None
     if not args.no_plain:
         pframe = render.Frame(scene.n_blocks, 1, W, H, scene.n_finest, 1 << 23, device=dev)
-        render.render_frame(scene, pframe, cam_slot[0], mode=gs.GS_LOD_ALL_FINEST, thresholds=())
         for v in range(V):
             render.render_frame(scene, pframe, cam_slot[v], mode=gs.GS_LOD_ALL_FINEST, thresholds=())
         torch.cuda.synchronize()
@@ -229,18 +290,16 @@ def main():
         torch.cuda.synchronize()
         plain_ms = 1e3 * (time.perf_counter() - tp) / (reps * V)
         out_extra["plain_fps"] = 1e3 / plain_ms
-        out_extra["lod_speedup_vs_plain"] = (1e3 / plain_ms) and fps / (1e3 / plain_ms)
-        log("plain (LoD off, eager): %.3f ms/frame, %.1f FPS" % (plain_ms, 1e3 / plain_ms))
-        # LoD eager, same protocol, for an apples-to-apples launch mode
+        out_extra["lod_speedup_vs_plain"] = fps / (1e3 / plain_ms)
+        log("plain (LoD off, eager, 16x16): %.3f ms/frame, %.1f FPS" % (plain_ms, 1e3 / plain_ms))
         torch.cuda.synchronize()
         tp = time.perf_counter()
         for _ in range(reps):
-            for v in range(V):
-                render.render_frame(scene, frame, cam_slot[v], thresholds=thresholds, check=False)
+            lod_step(frame)()
         torch.cuda.synchronize()
         out_extra["lod_eager_fps"] = reps * V / (time.perf_counter() - tp)
 
-    # ---- fwd + bwd ms/view (L1 loss against a seeded target) ------------------------
+    # ---- fwd + bwd ms/view (L1 loss against a seeded target) --------------------------
     if not args.no_bwd:
         grads = [lv.zeros_like() for lv in scene.levels]
         target = torch.rand((1, 3, H, W), generator=torch.Generator(device=dev).manual_seed(3), device=dev)
@@ -252,62 +311,24 @@ def main():
                 d = torch.sign(fr.rgb - target) / fr.rgb.numel()
                 render.backward_frame(scene, fr, cam_slot[v], d, grads)
 
-        fwd_bwd(frame, gs.GS_LOD_BLOCKWISE, thresholds)
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
-        fwd_bwd(frame, gs.GS_LOD_BLOCKWISE, thresholds)
-        torch.cuda.synchronize()
-        out_extra["fwd_bwd_ms_per_view_lod"] = 1e3 * (time.perf_counter() - tb) / len(views)
-        if not args.no_plain:
-            fwd_bwd(pframe, gs.GS_LOD_ALL_FINEST, ())
+        for fr, mode, thr, key in ((frame, gs.GS_LOD_BLOCKWISE, thresholds, "lod"),
+                                   (pframe, gs.GS_LOD_ALL_FINEST, (), "plain")):
+            if fr is None:
+                continue
+            fwd_bwd(fr, mode, thr)
             torch.cuda.synchronize()
             tb = time.perf_counter()
-            fwd_bwd(pframe, gs.GS_LOD_ALL_FINEST, ())
+            fwd_bwd(fr, mode, thr)
             torch.cuda.synchronize()
-            out_extra["fwd_bwd_ms_per_view_plain"] = 1e3 * (time.perf_counter() - tb) / len(views)
+            out_extra["fwd_bwd_ms_per_view_" + key] = 1e3 * (time.perf_counter() - tb) / len(views)
         log("fwd+bwd ms/view: %s" % {k: v for k, v in out_extra.items() if k.startswith("fwd_bwd")})
         del grads
+    del pframe
 
-    # ---- CPU oracle on a bounded sample: one full LoD frame -------------------------
+    # ---- CPU oracle on a bounded sample: one full LoD frame ---------------------------
     cpu = None
     if not args.no_cpu:
-        import oracle
-        from oracle import lod as olod
-        oracle.build(force=False)
-        vi = int(np.argsort(n_sel[V // 3:2 * V // 3])[len(n_sel[V // 3:2 * V // 3]) // 2]) + V // 3  # a 150 m view
-        cam = cams[vi]
-        fractions = (0.30, 0.50, 1.00)
-        memb = synth.level_membership(block_id, u, scene.n_blocks, fractions)
-        lvl_cnt = np.stack([m[1] for m in memb], axis=1)
-        bounds = np.concatenate([[0], np.cumsum(lvl_cnt[:, -1])])
-        lo = np.zeros((scene.n_blocks, 3))
-        hi = np.zeros((scene.n_blocks, 3))
-        t_c0 = time.perf_counter()
-        for b in range(scene.n_blocks):
-            lo[b], hi[b] = olod.mad_bounds(fine.means[:, bounds[b]:bounds[b + 1]])
-        level_ref, _ = olod.lod_select(lo, hi, cells, thresholds, [cam], lvl_cnt)
-        t_lod = time.perf_counter() - t_c0
-        sel = []
-        for b in range(scene.n_blocks):
-            l = level_ref[0, b]
-            if l < 0:
-                continue
-            idx = memb[l][0]
-            idx = idx[(idx >= bounds[b]) & (idx < bounds[b + 1])]
-            sel.append((idx, l))
-        idx_all = np.concatenate([s[0] for s in sel])
-        scale_k = np.concatenate([np.full(len(s[0]), 1.0 if s[1] == 2 else 1.3, np.float32) for s in sel])
-        agg = synth.GaussianSet(fine.means[:, idx_all], (fine.scales[:, idx_all] * scale_k).astype(np.float32),
-                                fine.quats[:, idx_all], fine.opac[idx_all], fine.sh[:, :, idx_all])
-        tc = time.perf_counter()
-        oracle.render(agg, cam)
-        t_render = time.perf_counter() - tc
-        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        cpu = {"value": 1.0 / t_render, "unit": "frames/s", "cores": cores, "kind": "oracle",
-               "sample": "one full 1600x900 LoD frame (view %d, 150 m, %d selected Gaussians): FP64 projection + "
-                         "untiled per-pixel compositing; the per-scene MAD boxes and selection (%.1fs) are not "
-                         "counted" % (vi, agg.opac.shape[0], t_lod)}
-        log("cpu oracle: %.2f s/frame on %d threads" % (t_render, cores))
+        cpu = cpu_oracle_frame(scene, fine, block_id, u, cells, cams, n_sel, thresholds, synth)
 
     result = {
         "metric": "FPS @1600x900 on 20M-Gaussian LoD scene",
@@ -326,25 +347,226 @@ def main():
                                "8x8 blocks, 1600x900, %d views per step (heights 50/150/400 m, pitch -90/-45)" %
                                (args.n, n_stored, V),
                    "n_gaussians": args.n, "width": W, "height": H, "views_per_step": V,
-                   "distance_thresholds_m": list(thresholds), "launch": "hipGraph, one frame at a time"},
+                   "distance_thresholds_m": list(thresholds), "launch": "hipGraph, one frame at a time",
+                   "tuning": tuning_desc},
         "fps_mean_view": float(fps_views.mean()),
         "fps_median_view": float(np.median(fps_views)),
         "fps_min_view": float(fps_views.min()),
+        "default_tuning_fps": (V / (default_step_ms * 1e-3)) if default_step_ms else None,
         "gaussians_per_s": float(n_sel.mean() * fps),
         "n_sel_mean": float(n_sel.mean()), "n_vis_mean": float(n_vis.mean()), "pairs_mean": float(n_pairs.mean()),
-        "roofline": {"bound": "alu", "kernel": "rasterize_fwd (raster_fwd_kernel<16,16,256>)",
+        "roofline": {"bound": "alu", "kernel": "raster_fwd_kernel<%d,%d,%d>" % (tun.tile_w, tun.tile_h, tun.batch),
                      "achieved": ras_tflops, "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": ras_tflops / VALU_FP32_PEAK_TFLOPS, "traffic": None, "avg_launch_ms": ras_ms,
                      "algorithmic_flops_per_launch": ras_flops, "evals_per_launch": float(np.mean(n_eval)),
                      "flops_per_eval": FLOPS_PER_EVAL},
-        "roofline_preprocess": {"bound": "hbm", "kernel": "preprocess", "achieved": pre_gbs, "peak": HBM_PEAK_GBS,
-                                "unit": "GB/s", "frac": pre_gbs / HBM_PEAK_GBS, "traffic": None,
+        "roofline_preprocess": {"bound": "hbm", "kernel": "preprocess_kernel", "achieved": pre_gbs,
+                                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": pre_gbs / HBM_PEAK_GBS, "traffic": None,
                                 "avg_launch_ms": pre_ms, "algorithmic_bytes_per_launch": pre_bytes},
         "kernel_ms": {k: float(np.mean(v)) for k, v in kern_ms.items()},
         "cpu_baseline": cpu,
     }
+    if tune_report:
+        result["autotune"] = {k: tune_report[k] for k in ("best", "best_ms", "default_ms", "rejected")}
     result.update(out_extra)
     print(json.dumps(result))
+
+
+def cpu_oracle_frame(scene, fine, block_id, u, cells, cams, n_sel, thresholds, synth):
+    """Time the oracle on one full LoD frame of a 150 m view (selection by the oracle's own LoD code)."""
+    import oracle
+    from oracle import lod as olod
+    oracle.build(force=False)
+    V = len(cams)
+    mid = n_sel[V // 3:2 * V // 3]
+    vi = int(np.argsort(mid)[len(mid) // 2]) + V // 3
+    cam = cams[vi]
+    fractions = (0.30, 0.50, 1.00)
+    memb = synth.level_membership(block_id, u, scene.n_blocks, fractions)
+    lvl_cnt = np.stack([m[1] for m in memb], axis=1)
+    bounds = np.concatenate([[0], np.cumsum(lvl_cnt[:, -1])])
+    lo = np.zeros((scene.n_blocks, 3))
+    hi = np.zeros((scene.n_blocks, 3))
+    t_c0 = time.perf_counter()
+    for b in range(scene.n_blocks):
+        lo[b], hi[b] = olod.mad_bounds(fine.means[:, bounds[b]:bounds[b + 1]])
+    level_ref, _ = olod.lod_select(lo, hi, cells, thresholds, [cam], lvl_cnt)
+    t_lod = time.perf_counter() - t_c0
+    sel = []
+    for b in range(scene.n_blocks):
+        l = level_ref[0, b]
+        if l < 0:
+            continue
+        idx = memb[l][0]
+        idx = idx[(idx >= bounds[b]) & (idx < bounds[b + 1])]
+        sel.append((idx, l))
+    idx_all = np.concatenate([s[0] for s in sel])
+    scale_k = np.concatenate([np.full(len(s[0]), 1.0 if s[1] == 2 else 1.3, np.float32) for s in sel])
+    agg = synth.GaussianSet(fine.means[:, idx_all], (fine.scales[:, idx_all] * scale_k).astype(np.float32),
+                            fine.quats[:, idx_all], fine.opac[idx_all], fine.sh[:, :, idx_all])
+    tc = time.perf_counter()
+    oracle.render(agg, cam)
+    t_render = time.perf_counter() - tc
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    log("cpu oracle: %.2f s/frame on %d threads" % (t_render, cores))
+    return {"value": 1.0 / t_render, "unit": "frames/s", "cores": cores, "kind": "oracle",
+            "sample": "one full 1600x900 LoD frame (view %d, 150 m, %d selected Gaussians): FP64 projection + "
+                      "untiled per-pixel compositing; the per-scene MAD boxes and selection (%.1fs) are not "
+                      "counted" % (vi, agg.opac.shape[0], t_lod)}
+
+
+# -------------------------------------------------------------------------------------------
+def workload_batched(args, torch, gs, render, synth):
+    """16 training views of one 2M-Gaussian block in one call vs 16 plain calls."""
+    dev = "cuda:0"
+    W, H, V = 1600, 900, 16
+    cell = 153.1
+    fine, block_id, u, cells = synth.city_finest(2_000_000, seed=3, area_m2=cell * cell, grid=(1, 1))
+    scene = render.DeviceScene.from_finest(fine, block_id, u, cells, fractions=(1.0,), device=dev)
+    cams = synth.orbit_views((0.0, 0.0), n_views=V, radius=60.0, height=60.0, width=W, h_px=H)
+    cams_dev = gs.cameras_to_device(cams, dev)
+    target = torch.rand((V, 3, H, W), generator=torch.Generator(device=dev).manual_seed(3), device=dev)
+    grads = [lv.zeros_like() for lv in scene.levels]
+    flags = gs.GS_TUNE_SHARED_SELECTION | gs.GS_TUNE_WORK_QUEUE
+    fb = render.Frame(1, V, W, H, V * scene.n_finest, 1 << 24, gs.tuning_struct(16, 16, 256, flags), device=dev)
+    render.render_frame(scene, fb, cams_dev, mode=gs.GS_LOD_ALL_FINEST, thresholds=())
+    counts = fb.host_counts()
+
+    def step():
+        render.render_frame(scene, fb, cams_dev, mode=gs.GS_LOD_ALL_FINEST, thresholds=(), check=False)
+        d = torch.sign(fb.rgb - target) / fb.rgb.numel()
+        render.backward_frame(scene, fb, cams_dev, d, grads)
+
+    stream = torch.cuda.Stream()
+    g = graph_of(torch, step, stream)
+    t_batched = timed_replays(torch, g, args.steps, args.warmup)
+    del g
+    # comparator: 16 plain single-view calls, default shape, eager
+    f1 = render.Frame(1, 1, W, H, scene.n_finest, 1 << 22, device=dev)
+    slots = [cams_dev[v * 152:(v + 1) * 152] for v in range(V)]
+    for v in range(V):
+        render.render_frame(scene, f1, slots[v], mode=gs.GS_LOD_ALL_FINEST, thresholds=())
+
+    def plain():
+        for v in range(V):
+            render.render_frame(scene, f1, slots[v], mode=gs.GS_LOD_ALL_FINEST, thresholds=(), check=False)
+            d = torch.sign(f1.rgb - target[v:v + 1]) / f1.rgb.numel()
+            render.backward_frame(scene, f1, slots[v], d, grads)
+
+    plain()
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // 4)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plain()
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / reps
+    print(json.dumps({"metric": "fwd+bwd ms/view, 16 views of one 2M-Gaussian block, batched vs plain",
+                      "value": 1e3 * t_batched / V, "unit": "ms/view", "higher_is_better": False,
+                      "plain_ms_per_view": 1e3 * t_plain / V, "speedup_vs_plain": t_plain / t_batched,
+                      "views": V, "n_gaussians": scene.n_finest, "width": W, "height": H,
+                      "launch": "one batched call per step, hipGraph; shared selection + work queue",
+                      "records": counts["records"], "visible": counts["visible"], "pairs": counts["pairs"],
+                      "dtype": "f32", "data": "synthetic"}))
+
+
+def workload_uneven(args, torch, gs, render, synth):
+    """32 uneven blocks x 4 views at 1280x720: LoD select + fwd + bwd batched, autotuned."""
+    from paper_2404_01133_amd import autotune
+    dev = "cuda:0"
+    W, H = 1280, 720
+    thresholds = (200.0, 500.0)
+    bs, cams = synth.uneven_block_scene(seed=4)
+    scene = render.DeviceScene.from_block_scene(bs, device=dev)
+    del bs
+    scene.compute_bounds(4.0)
+    V = len(cams)
+    chunk = 16  # views per batched call (bounds the record and pair buffers)
+    cams_dev = gs.cameras_to_device(cams, dev)
+    target = torch.rand((chunk, 3, H, W), generator=torch.Generator(device=dev).manual_seed(4), device=dev)
+    grads = [lv.zeros_like() for lv in scene.levels]
+    rc = chunk * scene.max_records_per_view() // 4
+
+    def chunk_slot(k):
+        return cams_dev[k * chunk * 152:(k + 1) * chunk * 152]
+
+    frames = {}
+
+    def get_frame(tw, th):
+        if (tw, th) not in frames:
+            f = render.Frame(scene.n_blocks, chunk, W, H, rc, 1 << 24, gs.tuning_struct(tw, th, 256), device=dev)
+            for k in range(V // chunk):
+                render.render_frame(scene, f, chunk_slot(k), thresholds=thresholds)
+            frames[(tw, th)] = f
+        return frames[(tw, th)]
+
+    def step_with(f):
+        def run():
+            for k in range(V // chunk):
+                render.render_frame(scene, f, chunk_slot(k), thresholds=thresholds, check=False)
+                d = torch.sign(f.rgb - target) / f.rgb.numel()
+                render.backward_frame(scene, f, chunk_slot(k), d, grads)
+        return run
+
+    def make_runner(cand):
+        f = get_frame(cand.tile_w, cand.tile_h)
+        f.tuning = cand.tuning()
+
+        def images():
+            render.render_frame(scene, f, chunk_slot(0), thresholds=thresholds, check=False)
+            return f.rgb.clone()
+        return step_with(f), images
+
+    best, report = autotune.tune("uneven_32blocks_%dviews_%dx%d" % (V, W, H), make_runner, use_cache=False, log=log)
+    f = get_frame(best.tile_w, best.tile_h)
+    f.tuning = best.tuning()
+    stream = torch.cuda.Stream()
+    g = graph_of(torch, step_with(f), stream)
+    t_batched = timed_replays(torch, g, max(2, args.steps // 4), 1)
+    del g
+    # comparator: per-view calls, default shape, eager
+    f1 = render.Frame(scene.n_blocks, 1, W, H, scene.max_records_per_view(), 1 << 22, device=dev)
+    slots = [cams_dev[v * 152:(v + 1) * 152] for v in range(V)]
+    for v in range(V):
+        render.render_frame(scene, f1, slots[v], thresholds=thresholds)
+
+    def plain():
+        for v in range(V):
+            render.render_frame(scene, f1, slots[v], thresholds=thresholds, check=False)
+            d = torch.sign(f1.rgb - target[v % chunk:v % chunk + 1]) / f1.rgb.numel()
+            render.backward_frame(scene, f1, slots[v], d, grads)
+
+    plain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    print(json.dumps({"metric": "LoD fwd+bwd ms/view, 32 uneven blocks x 4 views, batched + autotuned vs per-view",
+                      "value": 1e3 * t_batched / V, "unit": "ms/view", "higher_is_better": False,
+                      "per_view_default_ms_per_view": 1e3 * t_plain / V, "speedup": t_plain / t_batched,
+                      "views": V, "views_per_call": chunk, "width": W, "height": H,
+                      "autotune": {k: report[k] for k in ("best", "best_ms", "default_ms", "rejected")},
+                      "n_finest": scene.n_finest, "dtype": "f32", "data": "synthetic"}))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2404_01133_amd import gs, render, synth
+
+    torch.cuda.set_device(0)
+    if args.workload == "lod":
+        workload_lod(args, torch, gs, render, synth)
+    elif args.workload == "batched":
+        workload_batched(args, torch, gs, render, synth)
+    else:
+        workload_uneven(args, torch, gs, render, synth)
 
 
 if __name__ == "__main__":

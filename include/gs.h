@@ -111,8 +111,18 @@ typedef struct gs_blocks {
 typedef struct gs_tuning {
   int32_t tile_w, tile_h;
   int32_t batch;
-  int32_t flags; /* reserved, 0 */
+  int32_t flags; /* GS_TUNE_* bits */
 } gs_tuning;
+
+/* tuning.flags: every view of the call selected the same records (gs_lod_select in
+ * GS_LOD_ALL_FINEST mode, e.g. several training views of one block).  preprocess and
+ * rasterize_bwd then iterate Gaussian-major: one thread handles a Gaussian for all
+ * views, reading its parameters from HBM once and accumulating its gradient without
+ * atomics.  Segments and levels of view 0 are used for every view. */
+#define GS_TUNE_SHARED_SELECTION 1
+/* tuning.flags: rasterize_fwd / rasterize_bwd run as persistent kernels that take
+ * tiles from a device work queue, longest tile lists first. */
+#define GS_TUNE_WORK_QUEUE 2
 
 /* Size in bytes of one projected record (an opaque device structure). */
 size_t gs_record_bytes(void);
@@ -165,20 +175,25 @@ gs_status gs_preprocess(const gs_gaussians* levels, const gs_blocks* blocks, con
  * pairs), so ties go to the lower record index.
  *   pair_tiles / pair_records [pair_capacity] u32: sorted pairs
  *   tile_ranges [V*tiles][2] u32: [start, end) of each tile in the sorted pairs
+ *   tile_queue: NULL, or u32[2 + V*tiles]; with GS_TUNE_WORK_QUEUE it receives the
+ *     tiles ordered by decreasing list length (power-of-two buckets) and its two
+ *     head counters are reset, for the persistent tile kernels
  *   ws / ws_bytes: workspace of at least gs_workspace_bytes(GS_WS_BIN_SORT, ...). */
 gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys, const int32_t* tiles_touched,
                       int32_t n_views, int32_t width, int32_t height, const gs_tuning* tuning,
                       int64_t record_capacity, int64_t pair_capacity, uint32_t* pair_tiles,
-                      uint32_t* pair_records, uint32_t* tile_ranges, int64_t* counts, void* ws, size_t ws_bytes,
-                      void* stream);
+                      uint32_t* pair_records, uint32_t* tile_ranges, uint32_t* tile_queue, int64_t* counts,
+                      void* ws, size_t ws_bytes, void* stream);
 
 /* Per-tile front-to-back alpha compositing of Eq. 1: for each pixel, walk its
  * tile's list; skip entries whose footprint does not hold the pixel; alpha =
  * min(0.99, opacity * exp(-d^T conic d / 2)); skip alpha < 1/255; stop before an
  * entry that would take the transmittance below 1e-4.
- *   bg: host float[3] background colour. */
+ *   bg: host float[3] background colour.
+ *   tile_queue: NULL (one work-group per tile), or the queue gs_bin_sort filled
+ *     with GS_TUNE_WORK_QUEUE (persistent work-groups take tiles from it). */
 gs_status gs_rasterize_fwd(const void* records, const uint32_t* pair_records, const uint32_t* tile_ranges,
-                           int32_t n_views, int32_t width, int32_t height, const float* bg,
+                           uint32_t* tile_queue, int32_t n_views, int32_t width, int32_t height, const float* bg,
                            const gs_tuning* tuning, float* rgb, float* T_final, int32_t* n_last, void* stream);
 
 /* Adjoint of the forward pass (Sec. 3.1, differentiable rendering): given
@@ -187,9 +202,10 @@ gs_status gs_rasterize_fwd(const void* records, const uint32_t* pair_records, co
  * blend state of each pixel is recomputed front to back from the saved T_final
  * and n_last, so no per-(pixel, Gaussian) state is stored.  Accumulation uses
  * FP32 atomics: results are reproducible to rounding, not bit for bit.
+ * tile_queue: as for gs_rasterize_fwd (uses the second head counter).
  * ws: at least gs_workspace_bytes(GS_WS_RASTERIZE_BWD, ...). */
 gs_status gs_rasterize_bwd(const void* records, const uint32_t* pair_records, const uint32_t* tile_ranges,
-                           int32_t n_views, int32_t width, int32_t height, const float* bg,
+                           uint32_t* tile_queue, int32_t n_views, int32_t width, int32_t height, const float* bg,
                            const gs_tuning* tuning, const float* rgb, const float* T_final, const int32_t* n_last,
                            const float* d_rgb, const gs_gaussians* levels, const gs_blocks* blocks,
                            const int8_t* level, const int64_t* offsets, const gs_camera* cams, int32_t sh_degree,

@@ -30,18 +30,64 @@ struct PreArgs {
   int32_t B, L, V, W, H, tw, th, sh_degree;
 };
 
-__global__ void __launch_bounds__(kPreThreads) preprocess_kernel(PreArgs a, Record* __restrict__ records,
-                                                                 uint32_t* __restrict__ depth_keys,
-                                                                 int32_t* __restrict__ tiles_touched,
-                                                                 int64_t* __restrict__ counts) {
+// One record: Gaussian gi of level l, seen by view v, stored at record index g.
+__device__ __forceinline__ void preprocess_record(const PreArgs& a, int64_t g, int v, int l, int64_t gi,
+                                                  Record* __restrict__ records, uint32_t* __restrict__ depth_keys,
+                                                  int32_t* __restrict__ tiles_touched) {
+  const LevelPtrs& L = a.lv[l];
+  const gs_camera& cam = a.cams[v];
+  Geo o;
+  uint32_t key = kCulledKey;
+  int32_t tt = 0;
+  if (project_geo(L, gi, cam, a.W, a.H, o)) {
+    tt = (o.i1 / a.tw - o.i0 / a.tw + 1) * (o.j1 / a.th - o.j0 / a.th + 1);
+    key = __float_as_uint(o.depth);
+    Record rec;
+    rec.u_rel = (float)(o.u - (double)o.i0);
+    rec.v_rel = (float)(o.v - (double)o.j0);
+    rec.px = (uint32_t)o.i0 | ((uint32_t)(o.i1 - o.i0) << 16);
+    rec.py = (uint32_t)o.j0 | ((uint32_t)(o.j1 - o.j0) << 16);
+    rec.ca = (float)(kConicScale * sqrt(o.c / o.det));
+    rec.cb = (float)(-kConicScale * o.b / sqrt(o.c * o.det));
+    rec.cc = (float)(kConicScale / sqrt(o.c));
+    rec.opac = (float)o.opac;
+    double C[3];
+    camera_centre(cam, C);
+    const double d0 = o.m[0] - C[0], d1 = o.m[1] - C[1], d2 = o.m[2] - C[2];
+    const double dn = sqrt((d0 * d0 + d1 * d1) + d2 * d2);
+    double Y[16];
+    const int nk = sh_basis(d0 / dn, d1 / dn, d2 / dn, a.sh_degree, Y);
+    double col[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < nk; ++k)
+      for (int ch = 0; ch < 3; ++ch) col[ch] += Y[k] * (double)L.sh[(int64_t)(3 * k + ch) * L.n + gi];
+    rec.r = (float)dmax_(col[0] + 0.5, 0.0);
+    rec.g = (float)dmax_(col[1] + 0.5, 0.0);
+    rec.b = (float)dmax_(col[2] + 0.5, 0.0);
+    rec.view = (uint32_t)v;
+    records[g] = rec;
+  }
+  depth_keys[g] = key;
+  tiles_touched[g] = tt;
+}
+
+__device__ __forceinline__ int64_t clamp_records(const PreArgs& a, int64_t* counts) {
   int64_t n_rec = counts[GS_COUNT_RECORDS];
   if (n_rec > a.capacity) {
     if (blockIdx.x == 0 && threadIdx.x == 0)
       atomicOr((unsigned long long*)&counts[GS_COUNT_FLAGS], (unsigned long long)GS_FLAG_RECORDS);
     n_rec = a.capacity;
   }
+  return n_rec;
+}
+
+// View-major: records in index order, each mapped to (view, block, level) by
+// a binary search of the segment offsets (staged in LDS when they fit).
+__global__ void __launch_bounds__(kPreThreads) preprocess_kernel(PreArgs a, Record* __restrict__ records,
+                                                                 uint32_t* __restrict__ depth_keys,
+                                                                 int32_t* __restrict__ tiles_touched,
+                                                                 int64_t* __restrict__ counts) {
+  const int64_t n_rec = clamp_records(a, counts);
   const int nseg = a.V * a.B;
-  // segment offsets staged in LDS when they fit (the usual case: V * B <= 4095)
   __shared__ int64_t s_off[kLdsOffsets];
   const bool lds_off = nseg < kLdsOffsets;
   if (lds_off)
@@ -52,41 +98,36 @@ __global__ void __launch_bounds__(kPreThreads) preprocess_kernel(PreArgs a, Reco
     const int p = lds_off ? find_segment(s_off, nseg, g) : find_segment(a.offsets, nseg, g);
     const int v = p / a.B, b = p - v * a.B;
     const int l = a.level[p];
-    const LevelPtrs& L = a.lv[l];
     const int64_t gi = a.lvl_off[(int64_t)b * a.L + l] + (g - (lds_off ? s_off[p] : a.offsets[p]));
-    const gs_camera& cam = a.cams[v];
-    Geo o;
-    uint32_t key = kCulledKey;
-    int32_t tt = 0;
-    if (project_geo(L, gi, cam, a.W, a.H, o)) {
-      tt = (o.i1 / a.tw - o.i0 / a.tw + 1) * (o.j1 / a.th - o.j0 / a.th + 1);
-      key = __float_as_uint(o.depth);
-      Record rec;
-      rec.u_rel = (float)(o.u - (double)o.i0);
-      rec.v_rel = (float)(o.v - (double)o.j0);
-      rec.px = (uint32_t)o.i0 | ((uint32_t)(o.i1 - o.i0) << 16);
-      rec.py = (uint32_t)o.j0 | ((uint32_t)(o.j1 - o.j0) << 16);
-      rec.ca = (float)(kConicScale * sqrt(o.c / o.det));
-      rec.cb = (float)(-kConicScale * o.b / sqrt(o.c * o.det));
-      rec.cc = (float)(kConicScale / sqrt(o.c));
-      rec.opac = (float)o.opac;
-      double C[3];
-      camera_centre(cam, C);
-      const double d0 = o.m[0] - C[0], d1 = o.m[1] - C[1], d2 = o.m[2] - C[2];
-      const double dn = sqrt((d0 * d0 + d1 * d1) + d2 * d2);
-      double Y[16];
-      const int nk = sh_basis(d0 / dn, d1 / dn, d2 / dn, a.sh_degree, Y);
-      double col[3] = {0.0, 0.0, 0.0};
-      for (int k = 0; k < nk; ++k)
-        for (int ch = 0; ch < 3; ++ch) col[ch] += Y[k] * (double)L.sh[(int64_t)(3 * k + ch) * L.n + gi];
-      rec.r = (float)dmax_(col[0] + 0.5, 0.0);
-      rec.g = (float)dmax_(col[1] + 0.5, 0.0);
-      rec.b = (float)dmax_(col[2] + 0.5, 0.0);
-      rec.view = (uint32_t)v;
-      records[g] = rec;
+    preprocess_record(a, g, v, l, gi, records, depth_keys, tiles_touched);
+  }
+}
+
+// Gaussian-major, for batches in which every view selected the same records
+// (view v's records are [v * n_view, (v + 1) * n_view)): one thread projects a
+// Gaussian for all views in turn, so its parameters come from HBM once and
+// from cache afterwards.  View 0's segments and levels are used for all views.
+__global__ void __launch_bounds__(kPreThreads) preprocess_shared_kernel(PreArgs a, Record* __restrict__ records,
+                                                                        uint32_t* __restrict__ depth_keys,
+                                                                        int32_t* __restrict__ tiles_touched,
+                                                                        int64_t* __restrict__ counts) {
+  const int64_t n_rec = clamp_records(a, counts);
+  __shared__ int64_t s_off[kLdsOffsets];
+  const bool lds_off = a.B < kLdsOffsets;
+  if (lds_off)
+    for (int k = threadIdx.x; k <= a.B; k += blockDim.x) s_off[k] = a.offsets[k];
+  __syncthreads();
+  const int64_t n_view = a.offsets[a.B];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_view; i += stride) {
+    const int b = lds_off ? find_segment(s_off, a.B, i) : find_segment(a.offsets, a.B, i);
+    const int l = a.level[b];
+    const int64_t gi = a.lvl_off[(int64_t)b * a.L + l] + (i - (lds_off ? s_off[b] : a.offsets[b]));
+    for (int v = 0; v < a.V; ++v) {
+      const int64_t g = (int64_t)v * n_view + i;
+      if (g >= n_rec) break;
+      preprocess_record(a, g, v, l, gi, records, depth_keys, tiles_touched);
     }
-    depth_keys[g] = key;
-    tiles_touched[g] = tt;
   }
 }
 
@@ -130,8 +171,15 @@ extern "C" gs_status gs_preprocess(const gs_gaussians* levels, const gs_blocks* 
   a.sh_degree = sh_degree;
   int64_t blocks_needed = (record_capacity + kPreThreads - 1) / kPreThreads;
   int grid = (int)(blocks_needed < 8192 ? (blocks_needed > 0 ? blocks_needed : 1) : 8192);
-  hipLaunchKernelGGL(preprocess_kernel, dim3(grid), dim3(kPreThreads), 0, (hipStream_t)stream, a,
-                     (Record*)records, depth_keys, tiles_touched, counts);
+  if ((tuning->flags & GS_TUNE_SHARED_SELECTION) && n_views > 1) {
+    int64_t per_view = (record_capacity / n_views + kPreThreads - 1) / kPreThreads;
+    int g2 = (int)(per_view < 8192 ? (per_view > 0 ? per_view : 1) : 8192);
+    hipLaunchKernelGGL(preprocess_shared_kernel, dim3(g2), dim3(kPreThreads), 0, (hipStream_t)stream, a,
+                       (Record*)records, depth_keys, tiles_touched, counts);
+  } else {
+    hipLaunchKernelGGL(preprocess_kernel, dim3(grid), dim3(kPreThreads), 0, (hipStream_t)stream, a,
+                       (Record*)records, depth_keys, tiles_touched, counts);
+  }
   GS_LAUNCH_CHECK();
   return GS_OK;
 }

@@ -66,18 +66,51 @@ __device__ __forceinline__ int wave_compact_rows(const float4* s_w0, int nb, int
 }
 
 template <int TW, int TH, int BATCH>
-__global__ void __launch_bounds__(TW* TH) raster_fwd_kernel(const Record* __restrict__ records,
-                                                            const uint32_t* __restrict__ pair_records,
-                                                            const uint32_t* __restrict__ ranges, int W, int H,
-                                                            int tiles_x_n, int tiles_per_view, float bg0, float bg1,
-                                                            float bg2, float* __restrict__ rgb,
-                                                            float* __restrict__ T_final,
-                                                            int32_t* __restrict__ n_last) {
+struct FwdLds {
+  float4 w0[BATCH], w1[BATCH], w2[BATCH];
+  uint16_t list[(TW * TH) / 64][BATCH];
+};
+
+struct TileArgs {
+  const Record* records;
+  const uint32_t* pair_records;
+  const uint32_t* ranges;
+  int W, H, tiles_x_n, tiles_per_view;
+  int64_t n_tiles;
+};
+
+// Work distribution shared by the tile kernels: either one work-group per tile
+// (queue == nullptr) or persistent work-groups taking tiles from the device
+// queue built by bin_sort, longest lists first.
+template <class Body>
+__device__ __forceinline__ void for_each_tile(const TileArgs& t, uint32_t* queue, int head, Body body) {
+  if (queue == nullptr) {
+    body((int)blockIdx.x);
+    return;
+  }
+  __shared__ uint32_t s_next;
+  for (;;) {
+    if (threadIdx.x == 0) s_next = atomicAdd(&queue[head], 1u);
+    __syncthreads();
+    const uint32_t k = s_next;
+    __syncthreads();
+    if ((int64_t)k >= t.n_tiles) break;
+    body((int)queue[2 + k]);
+  }
+}
+
+template <int TW, int TH, int BATCH>
+__device__ __forceinline__ void raster_fwd_tile(const TileArgs& ta, FwdLds<TW, TH, BATCH>& lds, int tile_g,
+                                                float bg0, float bg1, float bg2, float* __restrict__ rgb,
+                                                float* __restrict__ T_final, int32_t* __restrict__ n_last) {
   constexpr int NT = TW * TH;
-  constexpr int NW = NT / 64;
-  __shared__ float4 s_w0[BATCH], s_w1[BATCH], s_w2[BATCH];
-  __shared__ uint16_t s_list[NW][BATCH];
-  const int tile_g = blockIdx.x;
+  const Record* __restrict__ records = ta.records;
+  const uint32_t* __restrict__ pair_records = ta.pair_records;
+  const uint32_t* __restrict__ ranges = ta.ranges;
+  const int W = ta.W, H = ta.H, tiles_x_n = ta.tiles_x_n, tiles_per_view = ta.tiles_per_view;
+  float4* s_w0 = lds.w0;
+  float4* s_w1 = lds.w1;
+  float4* s_w2 = lds.w2;
   const int view = tile_g / tiles_per_view;
   const int tile = tile_g - view * tiles_per_view;
   const int tyi = tile / tiles_x_n, txi = tile - tyi * tiles_x_n;
@@ -92,7 +125,7 @@ __global__ void __launch_bounds__(TW* TH) raster_fwd_kernel(const Record* __rest
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
   int last = 0;
   bool done = !inside;
-  uint16_t* list = s_list[wid];
+  uint16_t* list = lds.list[wid];
   for (uint32_t b = start; b < end; b += BATCH) {
     if (__syncthreads_and(done)) break;
     const int nb = (int)min((uint32_t)BATCH, end - b);
@@ -148,6 +181,17 @@ __global__ void __launch_bounds__(TW* TH) raster_fwd_kernel(const Record* __rest
   }
 }
 
+template <int TW, int TH, int BATCH>
+__global__ void __launch_bounds__(TW* TH) raster_fwd_kernel(TileArgs ta, uint32_t* queue, float bg0, float bg1,
+                                                            float bg2, float* __restrict__ rgb,
+                                                            float* __restrict__ T_final,
+                                                            int32_t* __restrict__ n_last) {
+  __shared__ FwdLds<TW, TH, BATCH> lds;
+  for_each_tile(ta, queue, 0, [&](int tile_g) {
+    raster_fwd_tile<TW, TH, BATCH>(ta, lds, tile_g, bg0, bg1, bg2, rgb, T_final, n_last);
+  });
+}
+
 // ---------------------------------------------------------------------------
 // Wave64 sums of nine per-lane values at once.  At butterfly level k (partner
 // lane = lane ^ 2^k) two quantities share one register: lanes with bit k clear
@@ -193,19 +237,31 @@ __device__ __forceinline__ float wave_sum9(const float v[9], int lane) {
 constexpr int kG = 9;  // partials per Gaussian: r, g, b, opacity, A1, A2, Axx, Axy, Ayy
 
 template <int TW, int TH, int BATCH>
-__global__ void __launch_bounds__(TW* TH) raster_bwd_kernel(
-    const Record* __restrict__ records, const uint32_t* __restrict__ pair_records,
-    const uint32_t* __restrict__ ranges, int W, int H, int tiles_x_n, int tiles_per_view,
-    const float* __restrict__ rgb, const float* __restrict__ T_final, const int32_t* __restrict__ n_last,
-    const float* __restrict__ d_rgb, float* __restrict__ grad2d) {
+struct BwdLds {
+  float4 w0[BATCH], w1[BATCH], w2[BATCH];
+  uint32_t rec[BATCH];
+  float grad[BATCH * kG];
+  uint16_t list[(TW * TH) / 64][BATCH];
+  int wave_last[(TW * TH) / 64];
+};
+
+template <int TW, int TH, int BATCH>
+__device__ __forceinline__ void raster_bwd_tile(const TileArgs& ta, BwdLds<TW, TH, BATCH>& lds, int tile_g,
+                                                const float* __restrict__ rgb, const float* __restrict__ T_final,
+                                                const int32_t* __restrict__ n_last, const float* __restrict__ d_rgb,
+                                                float* __restrict__ grad2d) {
   constexpr int NT = TW * TH;
   constexpr int NW = NT / 64;
-  __shared__ float4 s_w0[BATCH], s_w1[BATCH], s_w2[BATCH];
-  __shared__ uint32_t s_rec[BATCH];
-  __shared__ float s_grad[BATCH * kG];
-  __shared__ uint16_t s_list[NW][BATCH];
-  __shared__ int s_wave_last[NW];
-  const int tile_g = blockIdx.x;
+  const Record* __restrict__ records = ta.records;
+  const uint32_t* __restrict__ pair_records = ta.pair_records;
+  const uint32_t* __restrict__ ranges = ta.ranges;
+  const int W = ta.W, H = ta.H, tiles_x_n = ta.tiles_x_n, tiles_per_view = ta.tiles_per_view;
+  float4* s_w0 = lds.w0;
+  float4* s_w1 = lds.w1;
+  float4* s_w2 = lds.w2;
+  uint32_t* s_rec = lds.rec;
+  float* s_grad = lds.grad;
+  int* s_wave_last = lds.wave_last;
   const int view = tile_g / tiles_per_view;
   const int tile = tile_g - view * tiles_per_view;
   const int tyi = tile / tiles_x_n, txi = tile - tyi * tiles_x_n;
@@ -239,7 +295,7 @@ __global__ void __launch_bounds__(TW* TH) raster_bwd_kernel(
   int tile_last = 0;
   for (int w = 0; w < NW; ++w) tile_last = max(tile_last, s_wave_last[w]);
   const int wave_last = __builtin_amdgcn_readfirstlane(s_wave_last[wid]);
-  uint16_t* list = s_list[wid];
+  uint16_t* list = lds.list[wid];
   float T = 1.0f, A0 = 0.f, A1c = 0.f, A2c = 0.f;  // transmittance and colour accumulated in front
   for (uint32_t b = start; b < start + (uint32_t)tile_last; b += BATCH) {
     const int nb = (int)min((uint32_t)BATCH, start + (uint32_t)tile_last - b);
@@ -298,6 +354,19 @@ __global__ void __launch_bounds__(TW* TH) raster_bwd_kernel(
     }
     __syncthreads();
   }
+}
+
+template <int TW, int TH, int BATCH>
+__global__ void __launch_bounds__(TW* TH) raster_bwd_kernel(TileArgs ta, uint32_t* queue,
+                                                            const float* __restrict__ rgb,
+                                                            const float* __restrict__ T_final,
+                                                            const int32_t* __restrict__ n_last,
+                                                            const float* __restrict__ d_rgb,
+                                                            float* __restrict__ grad2d) {
+  __shared__ BwdLds<TW, TH, BATCH> lds;
+  for_each_tile(ta, queue, 1, [&](int tile_g) {
+    raster_bwd_tile<TW, TH, BATCH>(ta, lds, tile_g, rgb, T_final, n_last, d_rgb, grad2d);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -366,6 +435,171 @@ __device__ __forceinline__ void sh_adjoint(float x, float y, float z, int deg, c
 }
 
 template <bool ATOMIC>
+__device__ __forceinline__ void preprocess_bwd_record(const BwdArgs& a, const Record* __restrict__ records,
+                                                      const float* __restrict__ grad2d, int64_t g, int v, int l,
+                                                      int64_t gi) {
+  float p2[kG];
+  bool any = false;
+#pragma unroll
+  for (int q = 0; q < kG; ++q) {
+    p2[q] = grad2d[g * kG + q];
+    any |= p2[q] != 0.0f;
+  }
+  if (!any) return;
+  const LevelPtrs& L = a.lv[l];
+  const gs_gaussian_grads& G = a.gr[l];
+  const int64_t n = L.n;
+  const gs_camera& cam = a.cams[v];
+  // A record with a non-zero 2D gradient was visible in the forward pass, so
+  // the projection below (same code, same inputs) takes the same decisions.
+  // ---- colour first (FP32): clamped channels (record colour exactly 0) pass no gradient
+  double dm_col[3];
+  {
+    const float4 w2 = reinterpret_cast<const float4*>(&records[g])[2];
+    const float grgb[3] = {w2.x > 0.0f ? p2[0] : 0.0f, w2.y > 0.0f ? p2[1] : 0.0f, w2.z > 0.0f ? p2[2] : 0.0f};
+    double C[3];
+    camera_centre(cam, C);
+    const double d0 = (double)L.means[gi] - C[0], d1 = (double)L.means[n + gi] - C[1],
+                 d2 = (double)L.means[2 * n + gi] - C[2];
+    const double dn = sqrt((d0 * d0 + d1 * d1) + d2 * d2);
+    const float dir[3] = {(float)(d0 / dn), (float)(d1 / dn), (float)(d2 / dn)};
+    float gdir[3] = {0.0f, 0.0f, 0.0f};
+    sh_adjoint<ATOMIC>(dir[0], dir[1], dir[2], a.sh_degree, L.sh, n, gi, grgb, G.sh, gdir);
+    const float gd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
+    for (int k = 0; k < 3; ++k) dm_col[k] = (double)(gdir[k] - dir[k] * gd) / dn;
+  }
+  // ---- geometry adjoint (FP32); the guard-band clamp is decided in FP64 exactly as in the forward pass
+  const double* R64 = cam.R;
+  const double m0 = L.means[gi], m1 = L.means[n + gi], m2 = L.means[2 * n + gi];
+  const double tx64 = ((R64[0] * m0 + R64[1] * m1) + R64[2] * m2) + cam.t[0];
+  const double ty64 = ((R64[3] * m0 + R64[4] * m1) + R64[5] * m2) + cam.t[1];
+  const double tz64 = ((R64[6] * m0 + R64[7] * m1) + R64[8] * m2) + cam.t[2];
+  const double rz64 = 1.0 / tz64;
+  const double ux64 = tx64 * rz64, uy64 = ty64 * rz64;
+  const double limx = 1.3 * ((0.5 * a.W) / cam.fx), limy = 1.3 * ((0.5 * a.H) / cam.fy);
+  const double uxc64 = dmin_(limx, dmax_(-limx, ux64)), uyc64 = dmin_(limy, dmax_(-limy, uy64));
+  const bool clamp_x = uxc64 != ux64, clamp_y = uyc64 != uy64;
+  const float tx = (float)tx64, ty = (float)ty64, rz = (float)rz64;
+  const float uxc = (float)uxc64, uyc = (float)uyc64;
+  const float fx = (float)cam.fx, fy = (float)cam.fy;
+  float Rc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Rc[k] = (float)R64[k];
+  // rotation of the normalised quaternion, scales
+  const float qa = L.quats[gi], qb = L.quats[n + gi], qc = L.quats[2 * n + gi], qd_ = L.quats[3 * n + gi];
+  const float qinv = 1.0f / sqrtf(qa * qa + qb * qb + qc * qc + qd_ * qd_);
+  const float w = qa * qinv, x = qb * qinv, y = qc * qinv, z = qd_ * qinv;
+  float Rq[3][3];
+  Rq[0][0] = 1.f - 2.f * (y * y + z * z);
+  Rq[0][1] = 2.f * (x * y - w * z);
+  Rq[0][2] = 2.f * (x * z + w * y);
+  Rq[1][0] = 2.f * (x * y + w * z);
+  Rq[1][1] = 1.f - 2.f * (x * x + z * z);
+  Rq[1][2] = 2.f * (y * z - w * x);
+  Rq[2][0] = 2.f * (x * z - w * y);
+  Rq[2][1] = 2.f * (y * z + w * x);
+  Rq[2][2] = 1.f - 2.f * (x * x + y * y);
+  const float sc[3] = {L.scales[gi], L.scales[n + gi], L.scales[2 * n + gi]};
+  float WL[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      WL[i][j] = (Rc[3 * i] * Rq[0][j] + Rc[3 * i + 1] * Rq[1][j] + Rc[3 * i + 2] * Rq[2][j]) * sc[j];
+  const float J00 = fx * rz, J02 = -(fx * uxc) * rz, J11 = fy * rz, J12 = -(fy * uyc) * rz;
+  float M[2][3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    M[0][j] = J00 * WL[0][j] + J02 * WL[2][j];
+    M[1][j] = J11 * WL[1][j] + J12 * WL[2][j];
+  }
+  const float n0 = M[0][0] * M[0][0] + M[0][1] * M[0][1] + M[0][2] * M[0][2];
+  const float n1 = M[1][0] * M[1][0] + M[1][1] * M[1][1] + M[1][2] * M[1][2];
+  const float sb = M[0][0] * M[1][0] + M[0][1] * M[1][1] + M[0][2] * M[1][2];
+  const float sa = n0 + 0.3f, sc2 = n1 + 0.3f;
+  const float cr0 = M[0][1] * M[1][2] - M[0][2] * M[1][1];
+  const float cr1 = M[0][2] * M[1][0] - M[0][0] * M[1][2];
+  const float cr2 = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+  const float det = cr0 * cr0 + cr1 * cr1 + cr2 * cr2 + 0.3f * (n0 + n1) + 0.09f;
+  // ---- 2D mean and conic partials ----
+  const float kS = (float)kConicScale, kS2 = (float)kConicScale2;
+  const float ca = kS * sqrtf(sc2 / det);
+  const float cb = -kS * sb / sqrtf(sc2 * det);
+  const float cc = kS / sqrtf(sc2);
+  const float gu = -2.0f * ca * p2[4];
+  const float gv = -2.0f * (cb * p2[4] + cc * p2[5]);
+  const float gA = kS2 * p2[6], gB = 2.0f * kS2 * p2[7], gC = kS2 * p2[8];
+  // conic K = Sigma2D^-1;  dL/dSigma = -K Gk K with Gk = [[gA, gB/2], [gB/2, gC]]
+  const float KA = sc2 / det, KB = -sb / det, KC = sa / det;
+  const float h = 0.5f * gB;
+  const float t00 = gA * KA + h * KB, t01 = gA * KB + h * KC;
+  const float t10 = h * KA + gC * KB, t11 = h * KB + gC * KC;
+  const float S00 = -(KA * t00 + KB * t10);
+  const float S01 = -(KA * t01 + KB * t11);
+  const float S11 = -(KB * t01 + KC * t11);
+  // Sigma2D = M M^T + 0.3 I -> dL/dM = 2 Gs M; M = J WL; WL = R_cam Rq diag(s), one column at a time
+  float dJ00 = 0.f, dJ02 = 0.f, dJ11 = 0.f, dJ12 = 0.f;
+  float ds[3], dRq[3][3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const float dM0 = 2.0f * (S00 * M[0][j] + S01 * M[1][j]);
+    const float dM1 = 2.0f * (S01 * M[0][j] + S11 * M[1][j]);
+    dJ00 += dM0 * WL[0][j];
+    dJ02 += dM0 * WL[2][j];
+    dJ11 += dM1 * WL[1][j];
+    dJ12 += dM1 * WL[2][j];
+    const float dW0 = J00 * dM0, dW1 = J11 * dM1, dW2 = J02 * dM0 + J12 * dM1;
+    float acc = 0.f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const float dLm = Rc[i] * dW0 + Rc[3 + i] * dW1 + Rc[6 + i] * dW2;  // (R_cam^T dWL)[i][j]
+      acc += Rq[i][j] * dLm;
+      dRq[i][j] = sc[j] * dLm;
+    }
+    ds[j] = acc;
+  }
+  float dq[4];
+  dq[0] = 2.f * (-z * dRq[0][1] + y * dRq[0][2] + z * dRq[1][0] - x * dRq[1][2] - y * dRq[2][0] + x * dRq[2][1]);
+  dq[1] = 2.f * (y * dRq[0][1] + z * dRq[0][2] + y * dRq[1][0] - w * dRq[1][2] + z * dRq[2][0] + w * dRq[2][1]) -
+          4.f * x * (dRq[1][1] + dRq[2][2]);
+  dq[2] = 2.f * (x * dRq[0][1] + w * dRq[0][2] + x * dRq[1][0] + z * dRq[1][2] - w * dRq[2][0] + z * dRq[2][1]) -
+          4.f * y * (dRq[0][0] + dRq[2][2]);
+  dq[3] = 2.f * (-w * dRq[0][1] + x * dRq[0][2] + w * dRq[1][0] + y * dRq[1][2] + x * dRq[2][0] + y * dRq[2][1]) -
+          4.f * z * (dRq[0][0] + dRq[1][1]);
+  const float qdot = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
+  const float qn[4] = {w, x, y, z};
+  float gq[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) gq[k] = (dq[k] - qn[k] * qdot) * qinv;
+  // J(t) and (u, v)(t)
+  const float rz2 = rz * rz;
+  float dt0 = gu * fx * rz, dt1 = gv * fy * rz;
+  float dt2 = -gu * fx * tx * rz2 - gv * fy * ty * rz2 - dJ00 * fx * rz2 - dJ11 * fy * rz2;
+  if (!clamp_x) {
+    dt0 += -dJ02 * fx * rz2;
+    dt2 += dJ02 * 2.0f * fx * tx * rz2 * rz;
+  } else {
+    dt2 += dJ02 * fx * uxc * rz2;
+  }
+  if (!clamp_y) {
+    dt1 += -dJ12 * fy * rz2;
+    dt2 += dJ12 * 2.0f * fy * ty * rz2 * rz;
+  } else {
+    dt2 += dJ12 * fy * uyc * rz2;
+  }
+  float dm[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) dm[k] = Rc[k] * dt0 + Rc[3 + k] * dt1 + Rc[6 + k] * dt2 + (float)dm_col[k];
+  for (int k = 0; k < 3; ++k) {
+    accumulate<ATOMIC>(&G.means[k * n + gi], dm[k]);
+    accumulate<ATOMIC>(&G.scales[k * n + gi], ds[k]);
+  }
+  for (int k = 0; k < 4; ++k) accumulate<ATOMIC>(&G.quats[k * n + gi], gq[k]);
+  accumulate<ATOMIC>(&G.opac[gi], p2[3]);
+}
+
+// View-major: records in index order (FP32 atomics when views may share Gaussians).
+template <bool ATOMIC>
 __global__ void __launch_bounds__(256) preprocess_bwd_kernel(BwdArgs a, const Record* __restrict__ records,
                                                              const float* __restrict__ grad2d,
                                                              const int64_t* __restrict__ counts) {
@@ -374,168 +608,32 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(BwdArgs a, const Re
   const int nseg = a.V * a.B;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_rec; g += stride) {
-    float p2[kG];
-    bool any = false;
-#pragma unroll
-    for (int q = 0; q < kG; ++q) {
-      p2[q] = grad2d[g * kG + q];
-      any |= p2[q] != 0.0f;
-    }
-    if (!any) continue;
     const int p = find_segment(a.offsets, nseg, g);
     const int v = p / a.B, b = p - v * a.B;
     const int l = a.level[p];
-    const LevelPtrs& L = a.lv[l];
-    const gs_gaussian_grads& G = a.gr[l];
-    const int64_t n = L.n;
     const int64_t gi = a.lvl_off[(int64_t)b * a.L + l] + (g - a.offsets[p]);
-    const gs_camera& cam = a.cams[v];
-    // A record with a non-zero 2D gradient was visible in the forward pass, so
-    // the projection below (same code, same inputs) takes the same decisions.
-    // ---- colour first (FP32): clamped channels (record colour exactly 0) pass no gradient
-    double dm_col[3];
-    {
-      const float4 w2 = reinterpret_cast<const float4*>(&records[g])[2];
-      const float grgb[3] = {w2.x > 0.0f ? p2[0] : 0.0f, w2.y > 0.0f ? p2[1] : 0.0f, w2.z > 0.0f ? p2[2] : 0.0f};
-      double C[3];
-      camera_centre(cam, C);
-      const double d0 = (double)L.means[gi] - C[0], d1 = (double)L.means[n + gi] - C[1],
-                   d2 = (double)L.means[2 * n + gi] - C[2];
-      const double dn = sqrt((d0 * d0 + d1 * d1) + d2 * d2);
-      const float dir[3] = {(float)(d0 / dn), (float)(d1 / dn), (float)(d2 / dn)};
-      float gdir[3] = {0.0f, 0.0f, 0.0f};
-      sh_adjoint<ATOMIC>(dir[0], dir[1], dir[2], a.sh_degree, L.sh, n, gi, grgb, G.sh, gdir);
-      const float gd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
-      for (int k = 0; k < 3; ++k) dm_col[k] = (double)(gdir[k] - dir[k] * gd) / dn;
+    preprocess_bwd_record<ATOMIC>(a, records, grad2d, g, v, l, gi);
+  }
+}
+
+// Gaussian-major (every view selected the same records): one thread owns a
+// Gaussian's records in all views, so its gradient is accumulated in place.
+__global__ void __launch_bounds__(256) preprocess_bwd_shared_kernel(BwdArgs a, const Record* __restrict__ records,
+                                                                    const float* __restrict__ grad2d,
+                                                                    const int64_t* __restrict__ counts) {
+  int64_t n_rec = counts[GS_COUNT_RECORDS];
+  if (n_rec > a.capacity) n_rec = a.capacity;
+  const int64_t n_view = a.offsets[a.B];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_view; i += stride) {
+    const int b = find_segment(a.offsets, a.B, i);
+    const int l = a.level[b];
+    const int64_t gi = a.lvl_off[(int64_t)b * a.L + l] + (i - a.offsets[b]);
+    for (int v = 0; v < a.V; ++v) {
+      const int64_t g = (int64_t)v * n_view + i;
+      if (g >= n_rec) break;
+      preprocess_bwd_record<false>(a, records, grad2d, g, v, l, gi);
     }
-    // ---- geometry adjoint (FP32); the guard-band clamp is decided in FP64 exactly as in the forward pass
-    const double* R64 = cam.R;
-    const double m0 = L.means[gi], m1 = L.means[n + gi], m2 = L.means[2 * n + gi];
-    const double tx64 = ((R64[0] * m0 + R64[1] * m1) + R64[2] * m2) + cam.t[0];
-    const double ty64 = ((R64[3] * m0 + R64[4] * m1) + R64[5] * m2) + cam.t[1];
-    const double tz64 = ((R64[6] * m0 + R64[7] * m1) + R64[8] * m2) + cam.t[2];
-    const double rz64 = 1.0 / tz64;
-    const double ux64 = tx64 * rz64, uy64 = ty64 * rz64;
-    const double limx = 1.3 * ((0.5 * a.W) / cam.fx), limy = 1.3 * ((0.5 * a.H) / cam.fy);
-    const double uxc64 = dmin_(limx, dmax_(-limx, ux64)), uyc64 = dmin_(limy, dmax_(-limy, uy64));
-    const bool clamp_x = uxc64 != ux64, clamp_y = uyc64 != uy64;
-    const float tx = (float)tx64, ty = (float)ty64, rz = (float)rz64;
-    const float uxc = (float)uxc64, uyc = (float)uyc64;
-    const float fx = (float)cam.fx, fy = (float)cam.fy;
-    float Rc[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) Rc[k] = (float)R64[k];
-    // rotation of the normalised quaternion, scales
-    const float qa = L.quats[gi], qb = L.quats[n + gi], qc = L.quats[2 * n + gi], qd_ = L.quats[3 * n + gi];
-    const float qinv = 1.0f / sqrtf(qa * qa + qb * qb + qc * qc + qd_ * qd_);
-    const float w = qa * qinv, x = qb * qinv, y = qc * qinv, z = qd_ * qinv;
-    float Rq[3][3];
-    Rq[0][0] = 1.f - 2.f * (y * y + z * z);
-    Rq[0][1] = 2.f * (x * y - w * z);
-    Rq[0][2] = 2.f * (x * z + w * y);
-    Rq[1][0] = 2.f * (x * y + w * z);
-    Rq[1][1] = 1.f - 2.f * (x * x + z * z);
-    Rq[1][2] = 2.f * (y * z - w * x);
-    Rq[2][0] = 2.f * (x * z - w * y);
-    Rq[2][1] = 2.f * (y * z + w * x);
-    Rq[2][2] = 1.f - 2.f * (x * x + y * y);
-    const float sc[3] = {L.scales[gi], L.scales[n + gi], L.scales[2 * n + gi]};
-    float WL[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j)
-        WL[i][j] = (Rc[3 * i] * Rq[0][j] + Rc[3 * i + 1] * Rq[1][j] + Rc[3 * i + 2] * Rq[2][j]) * sc[j];
-    const float J00 = fx * rz, J02 = -(fx * uxc) * rz, J11 = fy * rz, J12 = -(fy * uyc) * rz;
-    float M[2][3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      M[0][j] = J00 * WL[0][j] + J02 * WL[2][j];
-      M[1][j] = J11 * WL[1][j] + J12 * WL[2][j];
-    }
-    const float n0 = M[0][0] * M[0][0] + M[0][1] * M[0][1] + M[0][2] * M[0][2];
-    const float n1 = M[1][0] * M[1][0] + M[1][1] * M[1][1] + M[1][2] * M[1][2];
-    const float sb = M[0][0] * M[1][0] + M[0][1] * M[1][1] + M[0][2] * M[1][2];
-    const float sa = n0 + 0.3f, sc2 = n1 + 0.3f;
-    const float cr0 = M[0][1] * M[1][2] - M[0][2] * M[1][1];
-    const float cr1 = M[0][2] * M[1][0] - M[0][0] * M[1][2];
-    const float cr2 = M[0][0] * M[1][1] - M[0][1] * M[1][0];
-    const float det = cr0 * cr0 + cr1 * cr1 + cr2 * cr2 + 0.3f * (n0 + n1) + 0.09f;
-    // ---- 2D mean and conic partials ----
-    const float kS = (float)kConicScale, kS2 = (float)kConicScale2;
-    const float ca = kS * sqrtf(sc2 / det);
-    const float cb = -kS * sb / sqrtf(sc2 * det);
-    const float cc = kS / sqrtf(sc2);
-    const float gu = -2.0f * ca * p2[4];
-    const float gv = -2.0f * (cb * p2[4] + cc * p2[5]);
-    const float gA = kS2 * p2[6], gB = 2.0f * kS2 * p2[7], gC = kS2 * p2[8];
-    // conic K = Sigma2D^-1;  dL/dSigma = -K Gk K with Gk = [[gA, gB/2], [gB/2, gC]]
-    const float KA = sc2 / det, KB = -sb / det, KC = sa / det;
-    const float h = 0.5f * gB;
-    const float t00 = gA * KA + h * KB, t01 = gA * KB + h * KC;
-    const float t10 = h * KA + gC * KB, t11 = h * KB + gC * KC;
-    const float S00 = -(KA * t00 + KB * t10);
-    const float S01 = -(KA * t01 + KB * t11);
-    const float S11 = -(KB * t01 + KC * t11);
-    // Sigma2D = M M^T + 0.3 I -> dL/dM = 2 Gs M; M = J WL; WL = R_cam Rq diag(s), one column at a time
-    float dJ00 = 0.f, dJ02 = 0.f, dJ11 = 0.f, dJ12 = 0.f;
-    float ds[3], dRq[3][3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const float dM0 = 2.0f * (S00 * M[0][j] + S01 * M[1][j]);
-      const float dM1 = 2.0f * (S01 * M[0][j] + S11 * M[1][j]);
-      dJ00 += dM0 * WL[0][j];
-      dJ02 += dM0 * WL[2][j];
-      dJ11 += dM1 * WL[1][j];
-      dJ12 += dM1 * WL[2][j];
-      const float dW0 = J00 * dM0, dW1 = J11 * dM1, dW2 = J02 * dM0 + J12 * dM1;
-      float acc = 0.f;
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const float dLm = Rc[i] * dW0 + Rc[3 + i] * dW1 + Rc[6 + i] * dW2;  // (R_cam^T dWL)[i][j]
-        acc += Rq[i][j] * dLm;
-        dRq[i][j] = sc[j] * dLm;
-      }
-      ds[j] = acc;
-    }
-    float dq[4];
-    dq[0] = 2.f * (-z * dRq[0][1] + y * dRq[0][2] + z * dRq[1][0] - x * dRq[1][2] - y * dRq[2][0] + x * dRq[2][1]);
-    dq[1] = 2.f * (y * dRq[0][1] + z * dRq[0][2] + y * dRq[1][0] - w * dRq[1][2] + z * dRq[2][0] + w * dRq[2][1]) -
-            4.f * x * (dRq[1][1] + dRq[2][2]);
-    dq[2] = 2.f * (x * dRq[0][1] + w * dRq[0][2] + x * dRq[1][0] + z * dRq[1][2] - w * dRq[2][0] + z * dRq[2][1]) -
-            4.f * y * (dRq[0][0] + dRq[2][2]);
-    dq[3] = 2.f * (-w * dRq[0][1] + x * dRq[0][2] + w * dRq[1][0] + y * dRq[1][2] + x * dRq[2][0] + y * dRq[2][1]) -
-            4.f * z * (dRq[0][0] + dRq[1][1]);
-    const float qdot = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
-    const float qn[4] = {w, x, y, z};
-    float gq[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) gq[k] = (dq[k] - qn[k] * qdot) * qinv;
-    // J(t) and (u, v)(t)
-    const float rz2 = rz * rz;
-    float dt0 = gu * fx * rz, dt1 = gv * fy * rz;
-    float dt2 = -gu * fx * tx * rz2 - gv * fy * ty * rz2 - dJ00 * fx * rz2 - dJ11 * fy * rz2;
-    if (!clamp_x) {
-      dt0 += -dJ02 * fx * rz2;
-      dt2 += dJ02 * 2.0f * fx * tx * rz2 * rz;
-    } else {
-      dt2 += dJ02 * fx * uxc * rz2;
-    }
-    if (!clamp_y) {
-      dt1 += -dJ12 * fy * rz2;
-      dt2 += dJ12 * 2.0f * fy * ty * rz2 * rz;
-    } else {
-      dt2 += dJ12 * fy * uyc * rz2;
-    }
-    float dm[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) dm[k] = Rc[k] * dt0 + Rc[3 + k] * dt1 + Rc[6 + k] * dt2 + (float)dm_col[k];
-    for (int k = 0; k < 3; ++k) {
-      accumulate<ATOMIC>(&G.means[k * n + gi], dm[k]);
-      accumulate<ATOMIC>(&G.scales[k * n + gi], ds[k]);
-    }
-    for (int k = 0; k < 4; ++k) accumulate<ATOMIC>(&G.quats[k * n + gi], gq[k]);
-    accumulate<ATOMIC>(&G.opac[gi], p2[3]);
   }
 }
 
@@ -547,35 +645,39 @@ __global__ void clear_floats_kernel(float* __restrict__ p, const int64_t* counts
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < words; k += stride) p[k] = 0.0f;
 }
 
-template <int TW, int TH>
-void launch_fwd(int batch, dim3 grid, hipStream_t s, const Record* rec, const uint32_t* pr, const uint32_t* rg, int W,
-                int H, int tx, int tpv, const float* bg, float* rgb, float* T, int32_t* nl) {
-  constexpr int NT = TW * TH;
-  if (batch == 64)
-    hipLaunchKernelGGL((raster_fwd_kernel<TW, TH, 64>), grid, dim3(NT), 0, s, rec, pr, rg, W, H, tx, tpv, bg[0], bg[1],
-                       bg[2], rgb, T, nl);
-  else if (batch == 128)
-    hipLaunchKernelGGL((raster_fwd_kernel<TW, TH, 128>), grid, dim3(NT), 0, s, rec, pr, rg, W, H, tx, tpv, bg[0],
-                       bg[1], bg[2], rgb, T, nl);
-  else
-    hipLaunchKernelGGL((raster_fwd_kernel<TW, TH, 256>), grid, dim3(NT), 0, s, rec, pr, rg, W, H, tx, tpv, bg[0],
-                       bg[1], bg[2], rgb, T, nl);
+// Persistent grid for the queue mode: enough work-groups to fill every CU a few times over.
+inline dim3 tile_grid(int64_t n_tiles, bool queued) {
+  const int64_t cap = 256 * 8;
+  return dim3((unsigned)(queued ? (n_tiles < cap ? (n_tiles > 0 ? n_tiles : 1) : cap) : n_tiles));
 }
 
 template <int TW, int TH>
-void launch_bwd(int batch, dim3 grid, hipStream_t s, const Record* rec, const uint32_t* pr, const uint32_t* rg, int W,
-                int H, int tx, int tpv, const float* rgb, const float* T, const int32_t* nl, const float* drgb,
-                float* g2d) {
+void launch_fwd(int batch, const TileArgs& ta, uint32_t* queue, hipStream_t s, const float* bg, float* rgb, float* T,
+                int32_t* nl) {
   constexpr int NT = TW * TH;
+  const dim3 grid = tile_grid(ta.n_tiles, queue != nullptr);
   if (batch == 64)
-    hipLaunchKernelGGL((raster_bwd_kernel<TW, TH, 64>), grid, dim3(NT), 0, s, rec, pr, rg, W, H, tx, tpv, rgb, T, nl,
-                       drgb, g2d);
+    hipLaunchKernelGGL((raster_fwd_kernel<TW, TH, 64>), grid, dim3(NT), 0, s, ta, queue, bg[0], bg[1], bg[2], rgb, T,
+                       nl);
   else if (batch == 128)
-    hipLaunchKernelGGL((raster_bwd_kernel<TW, TH, 128>), grid, dim3(NT), 0, s, rec, pr, rg, W, H, tx, tpv, rgb, T,
-                       nl, drgb, g2d);
+    hipLaunchKernelGGL((raster_fwd_kernel<TW, TH, 128>), grid, dim3(NT), 0, s, ta, queue, bg[0], bg[1], bg[2], rgb,
+                       T, nl);
   else
-    hipLaunchKernelGGL((raster_bwd_kernel<TW, TH, 256>), grid, dim3(NT), 0, s, rec, pr, rg, W, H, tx, tpv, rgb, T,
-                       nl, drgb, g2d);
+    hipLaunchKernelGGL((raster_fwd_kernel<TW, TH, 256>), grid, dim3(NT), 0, s, ta, queue, bg[0], bg[1], bg[2], rgb,
+                       T, nl);
+}
+
+template <int TW, int TH>
+void launch_bwd(int batch, const TileArgs& ta, uint32_t* queue, hipStream_t s, const float* rgb, const float* T,
+                const int32_t* nl, const float* drgb, float* g2d) {
+  constexpr int NT = TW * TH;
+  const dim3 grid = tile_grid(ta.n_tiles, queue != nullptr);
+  if (batch == 64)
+    hipLaunchKernelGGL((raster_bwd_kernel<TW, TH, 64>), grid, dim3(NT), 0, s, ta, queue, rgb, T, nl, drgb, g2d);
+  else if (batch == 128)
+    hipLaunchKernelGGL((raster_bwd_kernel<TW, TH, 128>), grid, dim3(NT), 0, s, ta, queue, rgb, T, nl, drgb, g2d);
+  else
+    hipLaunchKernelGGL((raster_bwd_kernel<TW, TH, 256>), grid, dim3(NT), 0, s, ta, queue, rgb, T, nl, drgb, g2d);
 }
 
 bool batch_supported(int b) { return b == 64 || b == 128 || b == 256; }
@@ -587,7 +689,8 @@ size_t rasterize_bwd_ws_bytes(int64_t rc) { return (size_t)rc * kG * sizeof(floa
 }  // namespace gs
 
 extern "C" gs_status gs_rasterize_fwd(const void* records, const uint32_t* pair_records, const uint32_t* tile_ranges,
-                                      int32_t n_views, int32_t width, int32_t height, const float* bg,
+                                      uint32_t* tile_queue, int32_t n_views, int32_t width, int32_t height,
+                                      const float* bg,
                                       const gs_tuning* tuning, float* rgb, float* T_final, int32_t* n_last,
                                       void* stream) {
   using namespace gs;
@@ -600,21 +703,22 @@ extern "C" gs_status gs_rasterize_fwd(const void* records, const uint32_t* pair_
   const int64_t tpv = (int64_t)tx * ty;
   const int64_t nblocks = tpv * n_views;
   if (nblocks >= ((int64_t)1 << 31)) return GS_ERR_INVALID_ARG;
-  const dim3 grid((unsigned)nblocks);
   hipStream_t s = (hipStream_t)stream;
-  const Record* rec = (const Record*)records;
+  const TileArgs ta{(const Record*)records, pair_records, tile_ranges, width, height, tx, (int)tpv, nblocks};
+  uint32_t* q = ((tuning->flags & GS_TUNE_WORK_QUEUE) && tile_queue) ? tile_queue : nullptr;
   const int b = tuning->batch;
-  if (tw == 16 && th == 16) launch_fwd<16, 16>(b, grid, s, rec, pair_records, tile_ranges, width, height, tx, (int)tpv, bg, rgb, T_final, n_last);
-  else if (tw == 8 && th == 8) launch_fwd<8, 8>(b, grid, s, rec, pair_records, tile_ranges, width, height, tx, (int)tpv, bg, rgb, T_final, n_last);
-  else if (tw == 16 && th == 8) launch_fwd<16, 8>(b, grid, s, rec, pair_records, tile_ranges, width, height, tx, (int)tpv, bg, rgb, T_final, n_last);
-  else if (tw == 32 && th == 8) launch_fwd<32, 8>(b, grid, s, rec, pair_records, tile_ranges, width, height, tx, (int)tpv, bg, rgb, T_final, n_last);
-  else launch_fwd<32, 16>(b, grid, s, rec, pair_records, tile_ranges, width, height, tx, (int)tpv, bg, rgb, T_final, n_last);
+  if (tw == 16 && th == 16) launch_fwd<16, 16>(b, ta, q, s, bg, rgb, T_final, n_last);
+  else if (tw == 8 && th == 8) launch_fwd<8, 8>(b, ta, q, s, bg, rgb, T_final, n_last);
+  else if (tw == 16 && th == 8) launch_fwd<16, 8>(b, ta, q, s, bg, rgb, T_final, n_last);
+  else if (tw == 32 && th == 8) launch_fwd<32, 8>(b, ta, q, s, bg, rgb, T_final, n_last);
+  else launch_fwd<32, 16>(b, ta, q, s, bg, rgb, T_final, n_last);
   GS_LAUNCH_CHECK();
   return GS_OK;
 }
 
 extern "C" gs_status gs_rasterize_bwd(const void* records, const uint32_t* pair_records, const uint32_t* tile_ranges,
-                                      int32_t n_views, int32_t width, int32_t height, const float* bg,
+                                      uint32_t* tile_queue, int32_t n_views, int32_t width, int32_t height,
+                                      const float* bg,
                                       const gs_tuning* tuning, const float* rgb, const float* T_final,
                                       const int32_t* n_last, const float* d_rgb, const gs_gaussians* levels,
                                       const gs_blocks* blocks, const int8_t* level, const int64_t* offsets,
@@ -643,14 +747,15 @@ extern "C" gs_status gs_rasterize_bwd(const void* records, const uint32_t* pair_
   hipLaunchKernelGGL(clear_floats_kernel, dim3((unsigned)(cg < 4096 ? (cg < 1 ? 1 : cg) : 4096)), dim3(256), 0, s,
                      grad2d, counts, record_capacity, kG);
   GS_LAUNCH_CHECK();
-  const dim3 grid((unsigned)nblocks);
   const Record* rec = (const Record*)records;
+  const TileArgs ta{rec, pair_records, tile_ranges, width, height, tx, (int)tpv, nblocks};
+  uint32_t* q = ((tuning->flags & GS_TUNE_WORK_QUEUE) && tile_queue) ? tile_queue : nullptr;
   const int b = tuning->batch;
-  if (tw == 16 && th == 16) launch_bwd<16, 16>(b, grid, s, rec, pair_records, tile_ranges, width, height, tx, (int)tpv, rgb, T_final, n_last, d_rgb, grad2d);
-  else if (tw == 8 && th == 8) launch_bwd<8, 8>(b, grid, s, rec, pair_records, tile_ranges, width, height, tx, (int)tpv, rgb, T_final, n_last, d_rgb, grad2d);
-  else if (tw == 16 && th == 8) launch_bwd<16, 8>(b, grid, s, rec, pair_records, tile_ranges, width, height, tx, (int)tpv, rgb, T_final, n_last, d_rgb, grad2d);
-  else if (tw == 32 && th == 8) launch_bwd<32, 8>(b, grid, s, rec, pair_records, tile_ranges, width, height, tx, (int)tpv, rgb, T_final, n_last, d_rgb, grad2d);
-  else launch_bwd<32, 16>(b, grid, s, rec, pair_records, tile_ranges, width, height, tx, (int)tpv, rgb, T_final, n_last, d_rgb, grad2d);
+  if (tw == 16 && th == 16) launch_bwd<16, 16>(b, ta, q, s, rgb, T_final, n_last, d_rgb, grad2d);
+  else if (tw == 8 && th == 8) launch_bwd<8, 8>(b, ta, q, s, rgb, T_final, n_last, d_rgb, grad2d);
+  else if (tw == 16 && th == 8) launch_bwd<16, 8>(b, ta, q, s, rgb, T_final, n_last, d_rgb, grad2d);
+  else if (tw == 32 && th == 8) launch_bwd<32, 8>(b, ta, q, s, rgb, T_final, n_last, d_rgb, grad2d);
+  else launch_bwd<32, 16>(b, ta, q, s, rgb, T_final, n_last, d_rgb, grad2d);
   GS_LAUNCH_CHECK();
   BwdArgs a{};
   for (int l = 0; l < blocks->n_levels; ++l) {
@@ -673,10 +778,15 @@ extern "C" gs_status gs_rasterize_bwd(const void* records, const uint32_t* pair_
   a.sh_degree = sh_degree;
   int64_t gb = (record_capacity + 255) / 256;
   const dim3 gbg((unsigned)(gb < 8192 ? (gb < 1 ? 1 : gb) : 8192));
-  if (n_views == 1)
+  if ((tuning->flags & GS_TUNE_SHARED_SELECTION) && n_views > 1) {
+    int64_t pv = (record_capacity / n_views + 255) / 256;
+    const dim3 gs_grid((unsigned)(pv < 8192 ? (pv < 1 ? 1 : pv) : 8192));
+    hipLaunchKernelGGL(preprocess_bwd_shared_kernel, gs_grid, dim3(256), 0, s, a, rec, grad2d, counts);
+  } else if (n_views == 1) {
     hipLaunchKernelGGL(preprocess_bwd_kernel<false>, gbg, dim3(256), 0, s, a, rec, grad2d, counts);
-  else
+  } else {
     hipLaunchKernelGGL(preprocess_bwd_kernel<true>, gbg, dim3(256), 0, s, a, rec, grad2d, counts);
+  }
   GS_LAUNCH_CHECK();
   return GS_OK;
 }

@@ -427,9 +427,57 @@ __global__ void ranges_kernel(const uint32_t* __restrict__ tiles, const int64_t*
 }
 
 // ---------------------------------------------------------------------------
+// 7. work queue for the persistent tile kernels: tiles ordered by decreasing
+//    list length, bucketed by floor(log2(length)) (empty tiles last); the order
+//    inside a bucket is irrelevant because tiles are independent
+// ---------------------------------------------------------------------------
+constexpr int kQueueBins = 33;
+
+__device__ __forceinline__ int queue_bin(const uint32_t* ranges, int64_t t) {
+  const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+  return len == 0 ? 32 : __clz(len);  // 0 = longest (bit 31 set) ... 31 = length 1
+}
+
+__global__ void queue_hist_kernel(const uint32_t* __restrict__ ranges, int64_t n_tiles, uint32_t* __restrict__ qhist) {
+  __shared__ uint32_t s_h[kQueueBins];
+  for (int i = threadIdx.x; i < kQueueBins; i += blockDim.x) s_h[i] = 0u;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles; t += stride)
+    atomicAdd(&s_h[queue_bin(ranges, t)], 1u);
+  __syncthreads();
+  for (int i = threadIdx.x; i < kQueueBins; i += blockDim.x)
+    if (s_h[i]) atomicAdd(&qhist[i], s_h[i]);
+}
+
+__global__ void queue_scatter_kernel(const uint32_t* __restrict__ ranges, int64_t n_tiles,
+                                     const uint32_t* __restrict__ qhist, uint32_t* __restrict__ qcur,
+                                     uint32_t* __restrict__ queue) {
+  __shared__ uint32_t s_base[kQueueBins];
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int i = 0; i < kQueueBins; ++i) {
+      s_base[i] = acc;
+      acc += qhist[i];
+    }
+    if (blockIdx.x == 0) {
+      queue[0] = 0u;  // head counters of the forward and backward tile kernels
+      queue[1] = 0u;
+    }
+  }
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles; t += stride) {
+    const int bin = queue_bin(ranges, t);
+    queue[2 + s_base[bin] + atomicAdd(&qcur[bin], 1u)] = (uint32_t)t;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // workspace layout
 // ---------------------------------------------------------------------------
-constexpr int64_t kFixedWords = 64 + 2 * kMaxPasses * kRadix;  // tile counters + two histogram sets
+// tile counters [64], depth + tile digit histograms [2][kMaxPasses][256], queue histogram and cursors
+constexpr int64_t kFixedWords = 64 + 2 * kMaxPasses * kRadix + 2 * 40;
 
 struct SortWs {
   uint32_t* dkeys_a;      // [rc]
@@ -489,8 +537,8 @@ size_t bin_sort_ws_bytes(int64_t rc, int64_t pc) { return sort_ws_layout(nullptr
 extern "C" gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys, const int32_t* tiles_touched,
                                  int32_t n_views, int32_t width, int32_t height, const gs_tuning* tuning,
                                  int64_t record_capacity, int64_t pair_capacity, uint32_t* pair_tiles,
-                                 uint32_t* pair_records, uint32_t* tile_ranges, int64_t* counts, void* ws,
-                                 size_t ws_bytes, void* stream) {
+                                 uint32_t* pair_records, uint32_t* tile_ranges, uint32_t* tile_queue,
+                                 int64_t* counts, void* ws, size_t ws_bytes, void* stream) {
   using namespace gs;
   if (!records || !depth_keys || !tiles_touched || !tuning || !pair_tiles || !pair_records || !tile_ranges ||
       !counts || !ws)
@@ -569,5 +617,14 @@ extern "C" gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys
   // 6. ranges
   hipLaunchKernelGGL(ranges_kernel, dim3(2048), blk, 0, s, pair_tiles, counts, pair_capacity, tile_ranges);
   GS_LAUNCH_CHECK();
+  // 7. work queue
+  if ((tuning->flags & GS_TUNE_WORK_QUEUE) && tile_queue) {
+    uint32_t* qhist = w.fixed + 64 + 2 * kMaxPasses * kRadix;
+    uint32_t* qcur = qhist + 40;
+    hipLaunchKernelGGL(queue_hist_kernel, grid_for(n_tile_ids), blk, 0, s, tile_ranges, n_tile_ids, qhist);
+    hipLaunchKernelGGL(queue_scatter_kernel, grid_for(n_tile_ids), blk, 0, s, tile_ranges, n_tile_ids, qhist, qcur,
+                       tile_queue);
+    GS_LAUNCH_CHECK();
+  }
   return GS_OK;
 }

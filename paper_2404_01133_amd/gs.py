@@ -29,6 +29,7 @@ GS_COUNT_SLOTS = 8
 GS_FLAG_RECORDS, GS_FLAG_PAIRS, GS_FLAG_WAIT = 1, 2, 4
 GS_WS_BIN_SORT, GS_WS_RASTERIZE_BWD = 1, 2
 GS_LOD_BLOCKWISE, GS_LOD_ALL_FINEST = 0, 1
+GS_TUNE_SHARED_SELECTION, GS_TUNE_WORK_QUEUE = 1, 2
 
 c_double, c_int32, c_int64, c_void_p, c_size_t = (ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
                                                   ctypes.c_size_t)
@@ -71,10 +72,11 @@ _SIGNATURES = {
     "gs_preprocess": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32,
                                 c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "gs_bin_sort": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_int64, c_int64,
-                              c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
-    "gs_rasterize_fwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p,
-                                   c_void_p, c_void_p, c_void_p, c_void_p]),
-    "gs_rasterize_bwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p,
+                              c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "gs_rasterize_fwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p,
+                                   c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "gs_rasterize_bwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p,
+                                   c_void_p,
                                    c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                    c_void_p, c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "gs_mad_workspace_bytes": (c_size_t, [c_int64]),
@@ -181,8 +183,8 @@ def blocks_struct(lo, hi, cell, lvl_off, lvl_cnt) -> gs_blocks:
     return gs_blocks(ptr(lo), ptr(hi), ptr(cell), lvl_off.data_ptr(), lvl_cnt.data_ptr(), B, L)
 
 
-def tuning_struct(tile_w=16, tile_h=16, batch=256) -> gs_tuning:
-    return gs_tuning(tile_w, tile_h, batch, 0)
+def tuning_struct(tile_w=16, tile_h=16, batch=256, flags=0) -> gs_tuning:
+    return gs_tuning(tile_w, tile_h, batch, flags)
 
 
 # ---------------------------------------------------------------------------
@@ -203,28 +205,29 @@ def preprocess(levels, blocks: gs_blocks, level, offsets, cams_dev, n_views, wid
 
 
 def bin_sort(records, depth_keys, tiles_touched, n_views, width, height, tuning: gs_tuning, record_capacity,
-             pair_capacity, pair_tiles, pair_records, tile_ranges, counts, ws, stream=None):
+             pair_capacity, pair_tiles, pair_records, tile_ranges, counts, ws, stream=None, tile_queue=None):
     _check(lib().gs_bin_sort(_p(records), _p(depth_keys), _p(tiles_touched), n_views, width, height,
                              ctypes.byref(tuning), record_capacity, pair_capacity, _p(pair_tiles), _p(pair_records),
-                             _p(tile_ranges), _p(counts), _p(ws), ws.numel() * ws.element_size(), _stream(stream)),
-           "gs_bin_sort")
+                             _p(tile_ranges), _p(tile_queue), _p(counts), _p(ws), ws.numel() * ws.element_size(),
+                             _stream(stream)), "gs_bin_sort")
 
 
 def rasterize_fwd(records, pair_records, tile_ranges, n_views, width, height, bg, tuning: gs_tuning, rgb, T_final,
-                  n_last, stream=None):
+                  n_last, stream=None, tile_queue=None):
     bgv = (ctypes.c_float * 3)(*[float(x) for x in bg])
-    _check(lib().gs_rasterize_fwd(_p(records), _p(pair_records), _p(tile_ranges), n_views, width, height, bgv,
-                                  ctypes.byref(tuning), _p(rgb), _p(T_final), _p(n_last), _stream(stream)),
-           "gs_rasterize_fwd")
+    _check(lib().gs_rasterize_fwd(_p(records), _p(pair_records), _p(tile_ranges), _p(tile_queue), n_views, width,
+                                  height, bgv, ctypes.byref(tuning), _p(rgb), _p(T_final), _p(n_last),
+                                  _stream(stream)), "gs_rasterize_fwd")
 
 
 def rasterize_bwd(records, pair_records, tile_ranges, n_views, width, height, bg, tuning: gs_tuning, rgb, T_final,
                   n_last, d_rgb, levels, blocks: gs_blocks, level, offsets, cams_dev, sh_degree, record_capacity,
-                  counts, grads, ws, stream=None):
+                  counts, grads, ws, stream=None, tile_queue=None):
     bgv = (ctypes.c_float * 3)(*[float(x) for x in bg])
     lv = (gs_gaussians * len(levels))(*levels)
     gr = (gs_gaussian_grads * len(grads))(*grads)
-    _check(lib().gs_rasterize_bwd(_p(records), _p(pair_records), _p(tile_ranges), n_views, width, height, bgv,
+    _check(lib().gs_rasterize_bwd(_p(records), _p(pair_records), _p(tile_ranges), _p(tile_queue), n_views, width,
+                                  height, bgv,
                                   ctypes.byref(tuning), _p(rgb), _p(T_final), _p(n_last), _p(d_rgb), lv,
                                   ctypes.byref(blocks), _p(level), _p(offsets), _p(cams_dev), sh_degree,
                                   record_capacity, _p(counts), gr, _p(ws), ws.numel() * ws.element_size(),

@@ -159,6 +159,8 @@ class Frame:
         self.T = torch.empty((n_views, height, width), dtype=torch.float32, device=d)
         self.n_last = torch.empty((n_views, height, width), dtype=torch.int32, device=d)
         self.tile_ranges = torch.empty((self.n_tiles, 2), dtype=torch.int32, device=d)
+        # device work queue of the persistent tile kernels (used with GS_TUNE_WORK_QUEUE)
+        self.tile_queue = torch.zeros(2 + self.n_tiles, dtype=torch.int32, device=d)
         self.record_capacity = 0
         self.pair_capacity = 0
         self.reserve(record_capacity, pair_capacity)
@@ -200,9 +202,9 @@ def render_frame(scene: DeviceScene, frame: Frame, cams_dev, mode=gs.GS_LOD_BLOC
                       frame.depth_keys, frame.tiles_touched, frame.counts, stream)
         gs.bin_sort(frame.records, frame.depth_keys, frame.tiles_touched, frame.V, frame.W, frame.H, frame.tuning,
                     frame.record_capacity, frame.pair_capacity, frame.pair_tiles, frame.pair_records,
-                    frame.tile_ranges, frame.counts, frame.sort_ws, stream)
+                    frame.tile_ranges, frame.counts, frame.sort_ws, stream, frame.tile_queue)
         gs.rasterize_fwd(frame.records, frame.pair_records, frame.tile_ranges, frame.V, frame.W, frame.H, bg,
-                         frame.tuning, frame.rgb, frame.T, frame.n_last, stream)
+                         frame.tuning, frame.rgb, frame.T, frame.n_last, stream, frame.tile_queue)
         if not check:
             return frame.rgb
         c = frame.host_counts()
@@ -226,7 +228,8 @@ def backward_frame(scene: DeviceScene, frame: Frame, cams_dev, d_rgb, grads, sh_
                      frame.tuning, frame.rgb, frame.T, frame.n_last, d_rgb.contiguous(),
                      [lv.struct() for lv in scene.levels], scene.blocks_struct(), frame.level, frame.offsets,
                      cams_dev, sh_degree, frame.record_capacity, frame.counts,
-                     [gs.grads_struct(g.means, g.scales, g.quats, g.opac, g.sh) for g in grads], frame.bwd_ws, stream)
+                     [gs.grads_struct(g.means, g.scales, g.quats, g.opac, g.sh) for g in grads], frame.bwd_ws, stream,
+                     frame.tile_queue)
 
 
 # ---------------------------------------------------------------------------

@@ -56,8 +56,8 @@ def test_invalid_arguments_rejected_before_launch(libgs):
     # NULL structures and pointers: every entry point returns GS_ERR_INVALID_ARG
     assert libgs.gs_lod_select(None, None, 0, None, 1, None, None, None, None) == -1
     assert libgs.gs_bin_sort(*([None] * 3), 1, 64, 64, *([None] * 1), ctypes.c_int64(10), ctypes.c_int64(10),
-                             *([None] * 5), ctypes.c_size_t(0), None) == -1
-    assert libgs.gs_rasterize_fwd(*([None] * 3), 1, 64, 64, *([None] * 6)) == -1
+                             *([None] * 6), ctypes.c_size_t(0), None) == -1
+    assert libgs.gs_rasterize_fwd(*([None] * 4), 1, 64, 64, *([None] * 6)) == -1
 
 
 def test_unsupported_tile_shape_rejected(libgs):
@@ -67,5 +67,5 @@ def test_unsupported_tile_shape_rejected(libgs):
     t = Tuning(12, 12, 256, 0)
     dummy = ctypes.c_void_p(0x1000)
     bg = (ctypes.c_float * 3)(0, 0, 0)
-    r = libgs.gs_rasterize_fwd(dummy, dummy, dummy, 1, 64, 64, bg, ctypes.byref(t), dummy, dummy, dummy, None)
+    r = libgs.gs_rasterize_fwd(dummy, dummy, dummy, None, 1, 64, 64, bg, ctypes.byref(t), dummy, dummy, dummy, None)
     assert r == -2

@@ -317,3 +317,117 @@ def test_l1_loss_gradients_aerial_box_reduced():
         err = rel_l2(p.grad.cpu().numpy(), ref[name])
         print("  grad", name, "rel L2 %.2e" % err, flush=True)
         assert err <= GRAD_TOL, (name, err)
+
+
+# ---------------------------------------------------------------------------
+# batching: work queue, shared selections, graph capture
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("tile,batch", [((16, 16), 256), ((8, 8), 64)])
+def test_work_queue_image_bit_identical(tile, batch):
+    bs = scaled_city(150_000, seed=35)
+    scene = render.DeviceScene.from_block_scene(bs)
+    scene.compute_bounds(4.0)
+    cams = synth.city_views(seed=35, n_xy=2, width=480, height=270)
+    cams_dev = gs.cameras_to_device(cams)
+    cap = len(cams) * scene.max_records_per_view()
+    f0 = render.Frame(bs.n_blocks, len(cams), 480, 270, cap, 1 << 20, gs.tuning_struct(tile[0], tile[1], batch))
+    render.render_frame(scene, f0, cams_dev)
+    f1 = render.Frame(bs.n_blocks, len(cams), 480, 270, cap, 1 << 20,
+                      gs.tuning_struct(tile[0], tile[1], batch, gs.GS_TUNE_WORK_QUEUE))
+    render.render_frame(scene, f1, cams_dev)
+    np.testing.assert_array_equal(f1.rgb.cpu().numpy(), f0.rgb.cpu().numpy())
+    np.testing.assert_array_equal(f1.n_last.cpu().numpy(), f0.n_last.cpu().numpy())
+    # every tile appears exactly once in the queue
+    q = f1.tile_queue.cpu().numpy()[2:]
+    assert sorted(q.tolist()) == list(range(f1.n_tiles))
+
+
+def _grads_for(scene, frame, cams_dev, d_rgb):
+    grads = [lv.zeros_like() for lv in scene.levels]
+    render.backward_frame(scene, frame, cams_dev, d_rgb, grads)
+    torch.cuda.synchronize()
+    return [[t.cpu().numpy() for t in (g.means, g.scales, g.quats, g.opac, g.sh)] for g in grads]
+
+
+@pytest.mark.parametrize("flags", [0, gs.GS_TUNE_SHARED_SELECTION,
+                                   gs.GS_TUNE_SHARED_SELECTION | gs.GS_TUNE_WORK_QUEUE])
+def test_batched_views_of_one_set_match_single_views_and_oracle(flags):
+    """Several training views of one Gaussian set in one call: images equal the
+    single-view renders; gradients equal the sum of the per-view oracle gradients."""
+    g = synth.box_gaussians(20_000, seed=7, extent=((-20, 20), (-20, 20), (0, 8)))
+    cams = synth.orbit_views((0.0, 0.0), n_views=4, radius=30.0, height=25.0, width=160, h_px=96)
+    scene = render.DeviceScene.single(g)
+    cams_dev = gs.cameras_to_device(cams)
+    V = len(cams)
+    fb = render.Frame(1, V, 160, 96, V * scene.n_finest, 1 << 20, gs.tuning_struct(16, 16, 256, flags))
+    render.render_frame(scene, fb, cams_dev, mode=gs.GS_LOD_ALL_FINEST, thresholds=())
+    rng = np.random.default_rng(3)
+    d = rng.normal(size=(V, 3, 96, 160)).astype(np.float32)
+    got = _grads_for(scene, fb, cams_dev, torch.from_numpy(d).cuda())[0]
+    ref = {k: 0.0 for k in ("means", "scales", "quats", "opac", "sh")}
+    for v, cam in enumerate(cams):
+        f1 = render.Frame(1, 1, 160, 96, scene.n_finest, 1 << 18)
+        render.render_frame(scene, f1, gs.cameras_to_device([cam]), mode=gs.GS_LOD_ALL_FINEST, thresholds=())
+        np.testing.assert_array_equal(fb.rgb[v].cpu().numpy(), f1.rgb[0].cpu().numpy())
+        r = oracle.render_bwd(g, cam, d[v].astype(np.float64))
+        for k in ref:
+            ref[k] = ref[k] + r[k]
+    for name, gg in zip(("means", "scales", "quats", "opac", "sh"), got):
+        err = rel_l2(gg, ref[name])
+        print("  batched grad", name, "rel L2 %.2e" % err, flush=True)
+        assert err <= GRAD_TOL, (name, err)
+
+
+def test_lod_batch_backward_with_shared_gaussians():
+    """Multi-view LoD call: views select overlapping blocks, so records of one
+    Gaussian are accumulated with atomics; compare with per-view calls."""
+    bs = scaled_city(60_000, seed=36, grid=(4, 4))
+    scene = render.DeviceScene.from_block_scene(bs)
+    scene.compute_bounds(4.0)
+    cams = [synth.look_camera((x, y, 120.0), 0.3, -math.pi / 3, 200, 120) for x, y in ((0, 0), (40, 20), (-60, 10))]
+    V = len(cams)
+    cams_dev = gs.cameras_to_device(cams)
+    fb = render.Frame(bs.n_blocks, V, 200, 120, V * scene.max_records_per_view(), 1 << 20)
+    render.render_frame(scene, fb, cams_dev)
+    d = np.random.default_rng(4).normal(size=(V, 3, 120, 200)).astype(np.float32)
+    got = _grads_for(scene, fb, cams_dev, torch.from_numpy(d).cuda())
+    acc = None
+    for v, cam in enumerate(cams):
+        f1 = render.Frame(bs.n_blocks, 1, 200, 120, scene.max_records_per_view(), 1 << 18)
+        c1 = gs.cameras_to_device([cam])
+        render.render_frame(scene, f1, c1)
+        gv = _grads_for(scene, f1, c1, torch.from_numpy(d[v:v + 1]).cuda())
+        acc = gv if acc is None else [[a + b for a, b in zip(la, lb)] for la, lb in zip(acc, gv)]
+    for l in range(len(acc)):
+        for a, b in zip(got[l], acc[l]):
+            if np.linalg.norm(b) > 0:
+                assert rel_l2(a, b) <= 1e-5
+
+
+def test_graph_replay_equals_eager():
+    bs = scaled_city(100_000, seed=37)
+    scene = render.DeviceScene.from_block_scene(bs)
+    scene.compute_bounds(4.0)
+    cams = synth.city_views(seed=37, n_xy=2, width=320, height=180)
+    cams_dev = gs.cameras_to_device(cams)
+    slots = [cams_dev[v * 152:(v + 1) * 152] for v in range(len(cams))]
+    frame = render.Frame(bs.n_blocks, 1, 320, 180, scene.max_records_per_view(), 1 << 20,
+                         gs.tuning_struct(16, 16, 256, gs.GS_TUNE_WORK_QUEUE))
+    eager = []
+    for v in range(len(cams)):
+        render.render_frame(scene, frame, slots[v])
+        eager.append(frame.rgb.clone())
+    stream = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        render.render_frame(scene, frame, slots[0], check=False)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=stream):
+            render.render_frame(scene, frame, slots[-1], check=False)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        # unrelated eager work between replays
+        render.render_frame(scene, frame, slots[rep % len(cams)])
+        graph.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(frame.rgb.cpu().numpy(), eager[-1].cpu().numpy())
