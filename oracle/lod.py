@@ -143,3 +143,85 @@ def aggregate(scene, level_row):
     return SimpleNamespace(means=np.concatenate(parts["means"], 1), scales=np.concatenate(parts["scales"], 1),
                            quats=np.concatenate(parts["quats"], 1), opac=np.concatenate(parts["opac"]),
                            sh=np.concatenate(parts["sh"], 2))
+
+
+# ---------------------------------------------------------------------------
+# Point-wise baseline (Sec. 3.3.2 opening, ablated in Table 5): every Gaussian
+# of every level is tested on its own.  Level l keeps the Gaussians of level l
+# whose centre distance to the camera centre falls in level l's interval and
+# whose centre lies in the view frustum.
+#
+# Readings (also listed in the design notes):
+#   * distance = Euclidean distance from the Gaussian centre to the camera
+#     centre, same intervals and the same level numbering as the block-wise
+#     selection;
+#   * "in the frustum" = camera-space z > znear and the projected centre inside
+#     the screen widened by POINT_GUARD of its size on every side (the 1.3x
+#     guard band of the rasterizer's projection for a centred principal point),
+#     so Gaussians centred just off screen still reach the rasterizer;
+#   * the selection of view v is laid out as L segments (level 0 .. L-1), each
+#     listing its Gaussians by ascending index within the level.
+# ---------------------------------------------------------------------------
+POINT_GUARD = 0.15
+
+
+def point_levels(means, cam, thresholds, n_levels):
+    """Per centre (means [3, n]): level from the distance intervals, and the
+    frustum test; returns (level int array, in_frustum bool array)."""
+    p = np.asarray(means, np.float64)
+    C = camera_center(cam)
+    R = np.asarray(cam.R, np.float64).reshape(9)
+    t = np.asarray(cam.t, np.float64)
+    dx, dy, dz = p[0] - C[0], p[1] - C[1], p[2] - C[2]
+    d2 = (dx * dx + dy * dy) + dz * dz
+    level = np.full(p.shape[1], n_levels - 1, np.int64)
+    for tk in thresholds:
+        level -= (d2 >= tk * tk).astype(np.int64)
+    zc = ((R[6] * p[0] + R[7] * p[1]) + R[8] * p[2]) + t[2]
+    xc = ((R[0] * p[0] + R[1] * p[1]) + R[2] * p[2]) + t[0]
+    yc = ((R[3] * p[0] + R[4] * p[1]) + R[5] * p[2]) + t[1]
+    front = zc > cam.znear
+    with np.errstate(divide="ignore", invalid="ignore"):
+        rz = 1.0 / zc
+        u = cam.fx * (xc * rz) + cam.cx
+        v = cam.fy * (yc * rz) + cam.cy
+    W, H = float(cam.width), float(cam.height)
+    inside = ((u > -POINT_GUARD * W) & (u < (1.0 + POINT_GUARD) * W) &
+              (v > -POINT_GUARD * H) & (v < (1.0 + POINT_GUARD) * H))
+    return level, front & inside
+
+
+def pointwise_select(level_means, thresholds, cams):
+    """level_means: list of [3, n_l] centre arrays, level 0 (coarsest) first.
+    Returns offsets [V*L + 1] (int64) and gather (uint32): segment v*L + l of
+    the selection holds gather[offsets[s]:offsets[s+1]], indices into level l."""
+    L = len(level_means)
+    parts = []
+    for cam in cams:
+        for l, m in enumerate(level_means):
+            level, ok = point_levels(m, cam, thresholds, L)
+            parts.append(np.nonzero(ok & (level == l))[0].astype(np.uint32))
+    sizes = np.array([p.shape[0] for p in parts], np.int64)
+    offsets = np.zeros(len(parts) + 1, np.int64)
+    offsets[1:] = np.cumsum(sizes)
+    gather = np.concatenate(parts) if parts else np.zeros(0, np.uint32)
+    return offsets, gather
+
+
+def gather_selection(level_sets, offsets, gather, view, n_levels):
+    """Concatenate view `view`'s point-wise selection (level 0 first) into one
+    Gaussian set with the attributes of the chosen Gaussians."""
+    from types import SimpleNamespace
+    parts = {k: [] for k in ("means", "scales", "quats", "opac", "sh")}
+    for l in range(n_levels):
+        s = view * n_levels + l
+        idx = gather[offsets[s]:offsets[s + 1]].astype(np.int64)
+        lev = level_sets[l]
+        parts["means"].append(lev.means[:, idx])
+        parts["scales"].append(lev.scales[:, idx])
+        parts["quats"].append(lev.quats[:, idx])
+        parts["opac"].append(lev.opac[idx])
+        parts["sh"].append(lev.sh[:, :, idx])
+    return SimpleNamespace(means=np.concatenate(parts["means"], 1), scales=np.concatenate(parts["scales"], 1),
+                           quats=np.concatenate(parts["quats"], 1), opac=np.concatenate(parts["opac"]),
+                           sh=np.concatenate(parts["sh"], 2))

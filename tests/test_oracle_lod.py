@@ -126,3 +126,94 @@ def test_nested_levels_and_coarse_scale():
     for k in range(0, lvl1.opac.shape[0], 97):
         j = idx[tuple(lvl1.means[:, k])]
         np.testing.assert_allclose(lvl1.scales[:, k], fine.scales[:, j] * np.float32(1.3), rtol=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# point-wise baseline (Sec. 3.3.2 opening, Table 5)
+# ---------------------------------------------------------------------------
+def _world_point(cam, u, v, d, behind=False):
+    """Point at distance d from the camera centre whose projection is pixel (u, v)."""
+    ray = np.array([(u - cam.cx) / cam.fx, (v - cam.cy) / cam.fy, 1.0])
+    ray /= np.linalg.norm(ray)
+    if behind:
+        ray = -ray
+    return cam.center + d * (np.asarray(cam.R).T @ ray)
+
+
+def test_pointwise_selects_constructed_points():
+    cam = synth.look_camera((10.0, 20.0, 150.0), yaw=0.7, pitch=-0.9, width=1600, height=900)
+    # pixel targets: on screen, off screen but inside the 15 % guard band, outside it
+    on_screen = [(100.0, 50.0), (800.0, 450.0), (1500.0, 850.0)]
+    guard = [(-100.0, 450.0), (800.0, 1000.0), (1700.0, -80.0)]
+    outside = [(-300.0, 450.0), (1900.0, 450.0), (800.0, 1100.0)]
+    # distances and the level each falls in for intervals [0,200), [200,500), [500,inf)
+    dist_level = [(50.0, 2), (150.0, 2), (250.0, 1), (450.0, 1), (600.0, 0), (1200.0, 0)]
+    pts, expect_level, expect_in = [], [], []
+    for group, inside in ((on_screen, True), (guard, True), (outside, False)):
+        for (u, v) in group:
+            for d, lvl in dist_level:
+                for behind in (False, True):
+                    pts.append(_world_point(cam, u, v, d, behind))
+                    expect_level.append(lvl)
+                    expect_in.append(inside and not behind)
+    means = np.array(pts).T
+    expect_level = np.array(expect_level)
+    expect_in = np.array(expect_in)
+    offsets, gather = lod.pointwise_select([means, means, means], (200.0, 500.0), [cam])
+    assert offsets.shape == (4,) and offsets[0] == 0
+    for l in range(3):
+        got = gather[offsets[l]:offsets[l + 1]]
+        want = np.nonzero(expect_in & (expect_level == l))[0]
+        np.testing.assert_array_equal(got, want)
+    # 6 in-frustum pixel targets x 2 distances per level
+    assert list(np.diff(offsets)) == [12, 12, 12]
+
+
+def test_pointwise_level_equals_blockwise_level_of_one_point_blocks():
+    """A block holding one Gaussian has a degenerate box at that centre, so its
+    minimum corner distance is the point's distance; with the camera standing in
+    the block's cell the block is always rendered, at the point-wise level."""
+    rng = np.random.default_rng(5)
+    cam = synth.look_camera((0.0, 0.0, 120.0), yaw=1.1, pitch=-0.6, width=1280, height=720)
+    C = cam.center
+    cell = (C[0] - 1.0, C[0] + 1.0, C[1] - 1.0, C[1] + 1.0)
+    means = rng.uniform(-900.0, 900.0, (3, 400)) * np.array([[1.0], [1.0], [0.2]])
+    level, _ = lod.point_levels(means, cam, (200.0, 500.0), 3)
+    for k in range(means.shape[1]):
+        p = means[:, k]
+        assert lod.select_block(p, p, cell, (200.0, 500.0), cam, 3) == level[k]
+
+
+def test_pointwise_partitions_the_frustum_against_scalar_bruteforce():
+    """Three levels holding the same centres: every centre in the frustum is
+    listed by exactly one level, chosen by its distance; checked against a
+    per-point scalar evaluation (math.dist, matrix-vector projection)."""
+    rng = np.random.default_rng(6)
+    n = 3000
+    means = np.stack([rng.uniform(-700, 700, n), rng.uniform(-700, 700, n), rng.uniform(0, 200, n)])
+    cams = [synth.look_camera((50.0, -30.0, 160.0), yaw=0.2, pitch=-0.7, width=800, height=450),
+            synth.look_camera((-200.0, 100.0, 60.0), yaw=2.5, pitch=-0.3, width=640, height=480)]
+    offsets, gather = lod.pointwise_select([means, means, means], (200.0, 500.0), cams)
+    for v, cam in enumerate(cams):
+        seen = np.zeros(n, np.int64)
+        for l in range(3):
+            s = v * 3 + l
+            for k in gather[offsets[s]:offsets[s + 1]]:
+                seen[k] += 1
+                d = math.dist(means[:, k], cam.center)
+                if abs(d - 200.0) > 1e-6 and abs(d - 500.0) > 1e-6:
+                    assert l == (2 if d < 200.0 else (1 if d < 500.0 else 0))
+        assert seen.max() <= 1
+        for k in range(n):
+            pc = np.asarray(cam.R) @ means[:, k] + np.asarray(cam.t)
+            if pc[2] <= cam.znear + 1e-9:
+                assert seen[k] == 0
+                continue
+            u = cam.fx * pc[0] / pc[2] + cam.cx
+            w = cam.fy * pc[1] / pc[2] + cam.cy
+            margin = min(abs(u + 0.15 * cam.width), abs(u - 1.15 * cam.width),
+                         abs(w + 0.15 * cam.height), abs(w - 1.15 * cam.height))
+            if margin < 1e-6:
+                continue
+            inside = -0.15 * cam.width < u < 1.15 * cam.width and -0.15 * cam.height < w < 1.15 * cam.height
+            assert seen[k] == (1 if inside else 0)
