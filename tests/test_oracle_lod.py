@@ -217,3 +217,88 @@ def test_pointwise_partitions_the_frustum_against_scalar_bruteforce():
                 continue
             inside = -0.15 * cam.width < u < 1.15 * cam.width and -0.15 * cam.height < w < 1.15 * cam.height
             assert seen[k] == (1 if inside else 0)
+
+
+# ---------------------------------------------------------------------------
+# contraction and uniform grid partition (Sec. 3.2.2, Eq. 2)
+# ---------------------------------------------------------------------------
+from oracle import partition as opart  # noqa: E402
+
+
+def test_contraction_closed_forms():
+    # inside the unit cube: identity; on an axis at distance r > 1: 2 - 1/r
+    p = np.array([[0.3, -0.99, 1.0, 3.0, -4.0, 0.0, 2.0],
+                  [0.0, 0.5, -1.0, 0.0, 0.0, 10.0, 2.0],
+                  [-0.7, 0.2, 0.0, 0.0, 0.0, 0.0, -1.0]])
+    c = opart.contract(p)
+    np.testing.assert_array_equal(c[:, :3], p[:, :3])
+    assert c[0, 3] == 2.0 - 1.0 / 3.0 and c[1, 3] == 0.0
+    assert c[0, 4] == -(2.0 - 1.0 / 4.0)
+    assert c[1, 5] == 2.0 - 1.0 / 10.0
+    # (2, 2, -1): norm 2, scale (2 - 1/2) / 2 = 0.75
+    np.testing.assert_allclose(c[:, 6], [1.5, 1.5, -0.75], rtol=0, atol=1e-15)
+
+
+def test_contraction_is_continuous_monotone_and_bounded():
+    rng = np.random.default_rng(0)
+    d = rng.normal(size=(3, 200))
+    d /= np.abs(d).max(axis=0)          # unit infinity norm directions
+    prev = None
+    for r in (0.5, 0.999999, 1.0, 1.000001, 1.5, 3.0, 10.0, 1e6):
+        c = opart.contract(d * r)
+        nc = np.abs(c).max(axis=0)
+        assert (nc < 2.0).all()
+        if r <= 1.0:
+            np.testing.assert_allclose(nc, r, rtol=1e-12)
+        else:
+            np.testing.assert_allclose(nc, 2.0 - 1.0 / r, rtol=1e-12)
+        if prev is not None:
+            assert (nc >= prev - 1e-12).all()  # grows along every ray
+        prev = nc
+        # direction is kept
+        np.testing.assert_allclose(c / nc, d, rtol=1e-12, atol=1e-12)
+
+
+def test_normalisation_maps_foreground_box_to_unit_cube():
+    p_min = np.array([-350.0, -400.0, -5.0])
+    p_max = np.array([450.0, 200.0, 95.0])
+    corners = np.array([[-350.0, 450.0, 50.0], [-400.0, 200.0, -600.0], [-5.0, 95.0, 45.0]])
+    q = opart.normalise(corners, p_min, p_max)
+    np.testing.assert_allclose(q[:, 0], [-1.0, -1.0, -1.0], atol=1e-15)
+    np.testing.assert_allclose(q[:, 1], [1.0, 1.0, 1.0], atol=1e-15)
+    np.testing.assert_allclose(q[:, 2], [0.0, -5.0 / 3.0, 0.0], atol=1e-15)
+
+
+def test_printed_box_with_swapped_ends():
+    p = np.array([[0.0, 10.0], [0.0, -200.0], [1.0, 3.0]])
+    lo, hi = opart.foreground_box(p, (-50.0, -5.0), (50.0, -135.0))
+    np.testing.assert_array_equal(lo, [-50.0, -135.0, 1.0])
+    np.testing.assert_array_equal(hi, [50.0, -5.0, 3.0])
+
+
+def test_grid_partition_against_bruteforce_boxes():
+    """Block of every point by scanning the block boxes [b_min, b_max) one by one."""
+    rng = np.random.default_rng(1)
+    n = 4000
+    means = np.stack([rng.normal(50, 400, n), rng.normal(-100, 300, n), rng.uniform(0, 80, n)])
+    means[:, :5] = np.array([[50.0, -100.0, 40.0]] * 5).T  # centre of the foreground
+    p_min, p_max = opart.foreground_box(means, (-350.0, -400.0), (450.0, 200.0))
+    nx, ny = 6, 6
+    b, perm, off = opart.partition(means, p_min, p_max, nx, ny)
+    c = opart.contract(opart.normalise(means, p_min, p_max))
+    edges_x = [-2.0 + 4.0 * k / nx for k in range(nx + 1)]
+    edges_y = [-2.0 + 4.0 * k / ny for k in range(ny + 1)]
+    for k in range(0, n, 7):
+        hits = [iy * nx + ix for iy in range(ny) for ix in range(nx)
+                if edges_x[ix] <= c[0, k] < edges_x[ix + 1] and edges_y[iy] <= c[1, k] < edges_y[iy + 1]]
+        assert hits == [b[k]]
+    # the foreground centre maps to the centre of the contracted square: blocks (2|3, 2|3)
+    assert b[0] in (2 * 6 + 2, 2 * 6 + 3, 3 * 6 + 2, 3 * 6 + 3)
+    # grouping: blocks in order, original order inside a block
+    assert off[0] == 0 and off[-1] == n
+    for blk in range(nx * ny):
+        seg = perm[off[blk]:off[blk + 1]]
+        assert (b[seg] == blk).all() and (np.diff(seg) > 0).all()
+    # contraction balances the counts better than a plain grid over the points' bounding box
+    plain = np.histogram2d(means[0], means[1], bins=(nx, ny))[0]
+    assert np.diff(off).max() < plain.max()
