@@ -9,7 +9,10 @@ replayed from a HIP graph, with the tile launch shape chosen by the autotuner
 
 Also reported: per-view FPS distribution (mean / median / min), the plain
 comparator (same library, LoD off: every block at the finest level, eager
-launches, default 16x16 tiles), fwd+bwd ms/view for LoD and plain, the
+launches, default 16x16 tiles), the point-wise LoD comparator (every Gaussian
+of every level tested on its own, HIP graph, same launch shape; the baseline
+of the block-wise strategy in the paper's LoD ablation), fwd+bwd ms/view for
+LoD and plain, the
 roofline of the dominant kernel measured with HIP events, the preprocess HBM
 roofline, and the CPU oracle's frame time on a bounded sample.
 
@@ -60,6 +63,9 @@ def parse():
     ap.add_argument("--n-xy", type=int, default=8, help="camera positions per height")
     ap.add_argument("--bwd-views", type=int, default=12, help="views used for the fwd+bwd timing")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-pointwise", action="store_true", help="skip the point-wise LoD comparator")
+    ap.add_argument("--pointwise-only", action="store_true",
+                    help="only the timed point-wise LoD frames (for profilers)")
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -143,6 +149,10 @@ def workload_lod(args, torch, gs, render, synth):
         return lambda: [render.render_frame(scene, f, cam_slot[v], thresholds=thresholds, check=False)
                         for v in range(V)]
 
+    if args.pointwise_only:
+        print(json.dumps(pointwise_frames(args, torch, gs, render, scene, cam_slot, thresholds, W, H,
+                                          frame.tuning, stream, None)))
+        return
     if args.bwd_only:
         grads = [lv.zeros_like() for lv in scene.levels]
         target = torch.rand((1, 3, H, W), generator=torch.Generator(device=dev).manual_seed(3), device=dev)
@@ -299,6 +309,11 @@ def workload_lod(args, torch, gs, render, synth):
         torch.cuda.synchronize()
         out_extra["lod_eager_fps"] = reps * V / (time.perf_counter() - tp)
 
+    # ---- point-wise LoD comparator (the baseline of the block-wise strategy) -----------
+    if not args.no_pointwise:
+        out_extra["pointwise"] = pointwise_frames(args, torch, gs, render, scene, cam_slot, thresholds, W, H,
+                                                  frame.tuning, stream, fps)
+
     # ---- fwd + bwd ms/view (L1 loss against a seeded target) --------------------------
     if not args.no_bwd:
         grads = [lv.zeros_like() for lv in scene.levels]
@@ -370,6 +385,52 @@ def workload_lod(args, torch, gs, render, synth):
         result["autotune"] = {k: tune_report[k] for k in ("best", "best_ms", "default_ms", "rejected")}
     result.update(out_extra)
     print(json.dumps(result))
+
+
+def pointwise_frames(args, torch, gs, render, scene, cam_slot, thresholds, W, H, tuning, stream, blockwise_fps):
+    """The same views with the point-wise selection (every Gaussian of every level
+    tested against the distance intervals and the frustum), HIP graph, same launch
+    shape; plus the selection kernel's time and HBM roofline (12 B of centre read
+    per stored Gaussian, 4 B of gather index written per selected one)."""
+    dev = "cuda:0"
+    V = len(cam_slot)
+    f = render.Frame(scene.n_blocks, 1, W, H, scene.max_records_per_view(), 1 << 22, tuning, device=dev)
+    sel = []
+    for v in range(V):
+        render.render_frame(scene, f, cam_slot[v], mode=render.LOD_POINTWISE, thresholds=thresholds)
+        sel.append(f.host_counts()["records"])
+    step = lambda: [render.render_frame(scene, f, cam_slot[v], mode=render.LOD_POINTWISE, thresholds=thresholds,
+                                        check=False) for v in range(V)]
+    g = graph_of(torch, step, stream)
+    step_s = timed_replays(torch, g, max(3, args.steps // 2), 1)
+    del g
+    if f.host_counts()["flags"]:
+        raise RuntimeError("capacity flag raised during the point-wise frames: %s" % f.host_counts())
+    pw_fps = V / step_s
+    levels = [lv.struct() for lv in scene.levels]
+    n_stored = sum(lv.n for lv in scene.levels)
+    sel_ms = []
+    with torch.cuda.stream(stream):
+        for v in range(V):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            gs.lod_select_points(levels, thresholds, cam_slot[v], 1, f.record_capacity, f.gather, f.pts_offsets,
+                                 f.counts, f.pts_ws, stream)
+            e1.record(stream)
+            e1.synchronize()
+            sel_ms.append(e0.elapsed_time(e1))
+    ms = float(np.mean(sel_ms))
+    nbytes = 12.0 * n_stored + 4.0 * float(np.mean(sel))
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    log("point-wise LoD: %.1f FPS (%.3f ms/frame), selection %.4f ms, %.0f GB/s, %.0f records/view" %
+        (pw_fps, 1e3 / pw_fps, ms, gbs, float(np.mean(sel))))
+    out = {"fps": pw_fps, "ms_per_frame": 1e3 / pw_fps, "n_sel_mean": float(np.mean(sel)),
+           "select_kernel": "point_select_kernel", "select_ms": ms,
+           "select_roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": nbytes}}
+    if blockwise_fps:
+        out["blockwise_speedup"] = blockwise_fps / pw_fps
+    return out
 
 
 def cpu_oracle_frame(scene, fine, block_id, u, cells, cams, n_sel, thresholds, synth):

@@ -94,7 +94,11 @@ typedef struct gs_gaussian_grads {
 
 /* Block table (all pointers device).  Block b of level l occupies
  * [lvl_off[b*L + l], lvl_off[b*L + l] + lvl_cnt[b*L + l]) of level l's arrays.
- * lo/hi are the block's bounding box (Eq. 6), cell its half-open xy cell. */
+ * lo/hi are the block's bounding box (Eq. 6), cell its half-open xy cell.
+ * contraction: NULL (cells are world xy rectangles), or device double[6] =
+ * p_min[3], p_max[3] of the foreground box of a contracted partition
+ * (gs_partition): cells are then rectangles of the contracted x, y, and the
+ * camera centre is normalised and contracted (Eq. 2) before the cell test. */
 typedef struct gs_blocks {
   const double* lo;       /* [B][3] */
   const double* hi;       /* [B][3] */
@@ -103,6 +107,7 @@ typedef struct gs_blocks {
   const int64_t* lvl_cnt; /* [B][L] */
   int32_t n_blocks;
   int32_t n_levels;
+  const double* contraction; /* NULL or [6] */
 } gs_blocks;
 
 /* Launch shape of the tile kernels.  tile_w x tile_h pixels per tile
@@ -153,6 +158,29 @@ gs_status gs_lod_select(const gs_blocks* blocks /* host struct */, const double*
                         int32_t mode, const gs_camera* cams, int32_t n_views, int8_t* level, int64_t* offsets,
                         int64_t* counts, void* stream);
 
+/* Point-wise level-of-detail selection: the baseline Sec. 3.3.2 sets against
+ * the block-wise strategy (ablated in Table 5).  Each Gaussian of each level is
+ * tested on its own: level l keeps the Gaussians whose centre distance to the
+ * camera centre lies in level l's interval (same thresholds and numbering as
+ * gs_lod_select: near = finest level L-1) and whose centre is in the frustum:
+ * camera z > znear and projection (u, v) with -0.15 W < u < 1.15 W and
+ * -0.15 H < v < 1.15 H.  All tests are FP64 in a fixed operation order.
+ *   levels: host array [n_levels] of device Gaussian sets (only means are read)
+ *   thresholds: host array [n_levels-1], ascending, scene units
+ *   gather [record_capacity] u32: the selection, index within the level
+ *   offsets [V*L + 1] int64: segment v*L + l (view v, level l) is
+ *     gather[offsets[v*L+l] .. offsets[v*L+l+1]), ascending indices
+ *   counts[GS_COUNT_RECORDS] = offsets[V*L]; GS_FLAG_RECORDS is raised (and the
+ *     gather list truncated) if that exceeds record_capacity
+ *   ws / ws_bytes: workspace of at least gs_points_workspace_bytes(...).
+ * The selection feeds gs_preprocess / gs_rasterize_bwd through their gather
+ * argument. */
+size_t gs_points_workspace_bytes(const int64_t* level_sizes /* host [n_levels] */, int32_t n_levels,
+                                 int32_t n_views);
+gs_status gs_lod_select_points(const gs_gaussians* levels, int32_t n_levels, const double* thresholds,
+                               const gs_camera* cams, int32_t n_views, int64_t record_capacity, uint32_t* gather,
+                               int64_t* offsets, int64_t* counts, void* ws, size_t ws_bytes, void* stream);
+
 /* Projection of every selected record (Sec. 3.1, "proj" in Eq. 1, following
  * 3DGS): EWA splat of the 3D covariance R S S^T R^T through the pinhole
  * Jacobian (guard band 1.3x the half field of view) with a 0.3 px^2 dilation,
@@ -160,11 +188,15 @@ gs_status gs_lod_select(const gs_blocks* blocks /* host struct */, const double*
  * SH (clamped at 0), depth = camera z.  Geometry is computed in FP64 in a fixed
  * operation order so footprints and depth keys are reproducible bit for bit.
  *   levels: host array [n_levels] of device Gaussian sets
+ *   selection: gather == NULL: block-wise, from gs_lod_select (level, offsets
+ *     [V*B+1]); gather != NULL: point-wise, from gs_lod_select_points (offsets
+ *     [V*L+1], level unused and may be NULL, blocks only supplies n_levels)
  *   records [record_capacity] of gs_record_bytes(); depth_keys [record_capacity]
  *   u32 (float bits of depth; 0xFFFFFFFF if culled); tiles_touched
  *   [record_capacity] int32 (0 if culled). */
 gs_status gs_preprocess(const gs_gaussians* levels, const gs_blocks* blocks, const int8_t* level,
-                        const int64_t* offsets, const gs_camera* cams, int32_t n_views, int32_t width,
+                        const int64_t* offsets, const uint32_t* gather, const gs_camera* cams, int32_t n_views,
+                        int32_t width,
                         int32_t height, int32_t sh_degree, const gs_tuning* tuning, int64_t record_capacity,
                         void* records, uint32_t* depth_keys, int32_t* tiles_touched, int64_t* counts,
                         void* stream);
@@ -203,13 +235,15 @@ gs_status gs_rasterize_fwd(const void* records, const uint32_t* pair_records, co
  * and n_last, so no per-(pixel, Gaussian) state is stored.  Accumulation uses
  * FP32 atomics: results are reproducible to rounding, not bit for bit.
  * tile_queue: as for gs_rasterize_fwd (uses the second head counter).
+ * level / offsets / gather: the selection passed to gs_preprocess.
  * ws: at least gs_workspace_bytes(GS_WS_RASTERIZE_BWD, ...). */
 gs_status gs_rasterize_bwd(const void* records, const uint32_t* pair_records, const uint32_t* tile_ranges,
                            uint32_t* tile_queue, int32_t n_views, int32_t width, int32_t height, const float* bg,
                            const gs_tuning* tuning, const float* rgb, const float* T_final, const int32_t* n_last,
                            const float* d_rgb, const gs_gaussians* levels, const gs_blocks* blocks,
-                           const int8_t* level, const int64_t* offsets, const gs_camera* cams, int32_t sh_degree,
-                           int64_t record_capacity, const int64_t* counts, const gs_gaussian_grads* grads,
+                           const int8_t* level, const int64_t* offsets, const uint32_t* gather,
+                           const gs_camera* cams, int32_t sh_degree, int64_t record_capacity,
+                           const int64_t* counts, const gs_gaussian_grads* grads,
                            void* ws, size_t ws_bytes, void* stream);
 
 /* Block bounds of Eq. 6 for every block from its finest-level centres:
@@ -222,6 +256,34 @@ size_t gs_mad_workspace_bytes(int64_t max_block_count);
 gs_status gs_mad_bounds(const gs_gaussians* finest, const int64_t* lvl_off, const int64_t* lvl_cnt,
                         int32_t n_blocks, int32_t n_levels, int64_t max_block_count, double n_mad, double* lo,
                         double* hi, void* ws, size_t ws_bytes, void* stream);
+
+/* Block partition of a Gaussian cloud (Sec. 3.2.2, Eq. 2), the set-up step
+ * that builds the block table.  Per centre p (FP64, fixed operation order):
+ * p_hat_i = (2 (p_i - min_i)) / (max_i - min_i) - 1 with the foreground box
+ * x, y from xy_box and z from the min and max centre z; c = p_hat if
+ * max_i |p_hat_i| <= 1, else (2 - 1/n) (p_hat / n) with n = max_i |p_hat_i|;
+ * ix = number of boundaries -2 + 4k/nx (k = 1 .. nx-1) <= c_x, iy likewise
+ * for c_y; block = iy * nx + ix.
+ *   means: device [3][n] FP32 centres (finite)
+ *   xy_box: host double[4] = x_a, y_a, x_b, y_b (the ends of each interval in
+ *     either order; the extents must be non-zero)
+ *   block_id: device u32[n] or NULL; perm: device u32[n], the Gaussians listed
+ *     block by block, ascending original index inside a block (stable)
+ *   block_off: device int64[nx*ny + 1]: block b is perm[block_off[b] .. block_off[b+1])
+ *   cells: device double[nx*ny][4] or NULL: each block's cell in contracted
+ *     x, y (the boundaries above, outermost ends infinite), for gs_blocks.cell
+ *     together with gs_blocks.contraction
+ *   nx * ny <= 65536; ws: gs_partition_workspace_bytes(n). */
+size_t gs_partition_workspace_bytes(int64_t n);
+gs_status gs_partition(const float* means, int64_t n, const double* xy_box, int32_t nx, int32_t ny,
+                       uint32_t* block_id, uint32_t* perm, int64_t* block_off, double* cells, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/* dst = src[perm]: every attribute array of a Gaussian set gathered into a new
+ * order (dst holds n Gaussians; src->n is the source count; perm entries
+ * < src->n).  Used to store a partitioned set block by block. */
+gs_status gs_gather_gaussians(const gs_gaussians* src, const uint32_t* perm, int64_t n,
+                              const gs_gaussian_grads* dst, void* stream);
 
 /* Name of a status code (static string, or a thread-local buffer after GS_ERR_HIP). */
 const char* gs_status_string(gs_status status);

@@ -72,8 +72,12 @@ def corners(lo, hi):
                       (hi if (c >> 2) & 1 else lo)[2]] for c in range(8)])
 
 
-def select_block(lo, hi, cell, thresholds, cam, n_levels):
-    """Level for one (view, block): -1 if culled, else 0 (coarsest) .. n_levels-1."""
+def select_block(lo, hi, cell, thresholds, cam, n_levels, contraction=None):
+    """Level for one (view, block): -1 if culled, else 0 (coarsest) .. n_levels-1.
+
+    contraction: None (cell is a world xy rectangle) or (p_min, p_max) of a
+    contracted partition (Sec. 3.2.2): the camera centre is then normalised and
+    contracted by Eq. 2, as a Gaussian centre would be, before the cell test."""
     if not (lo[0] <= hi[0]):
         return -1  # empty block
     C = camera_center(cam)
@@ -97,7 +101,12 @@ def select_block(lo, hi, cell, thresholds, cam, n_levels):
         umax, vmax = f.max(axis=0)
         # intersection of [umin, umax] x [vmin, vmax] with the screen has positive area
         visible = (min(umax, float(cam.width)) > max(umin, 0.0)) and (min(vmax, float(cam.height)) > max(vmin, 0.0))
-    in_cell = (cell[0] <= C[0] < cell[1]) and (cell[2] <= C[1] < cell[3])
+    X, Y = C[0], C[1]
+    if contraction is not None:
+        from oracle import partition
+        c = partition.contract(partition.normalise(C[:, None], contraction[0], contraction[1]))[:, 0]
+        X, Y = c[0], c[1]
+    in_cell = (cell[0] <= X < cell[1]) and (cell[2] <= Y < cell[3])
     if not (visible or in_cell):
         return -1
     level = n_levels - 1
@@ -107,7 +116,7 @@ def select_block(lo, hi, cell, thresholds, cam, n_levels):
     return level
 
 
-def lod_select(lo, hi, cells, thresholds, cams, lvl_cnt):
+def lod_select(lo, hi, cells, thresholds, cams, lvl_cnt, contraction=None):
     """level [V, B] int8 and offsets [V, B+1] int64 (exclusive prefix of chosen counts)."""
     B = cells.shape[0]
     L = lvl_cnt.shape[1]
@@ -116,7 +125,7 @@ def lod_select(lo, hi, cells, thresholds, cams, lvl_cnt):
     offsets = np.zeros((V, B + 1), np.int64)
     for v, cam in enumerate(cams):
         for b in range(B):
-            level[v, b] = select_block(lo[b], hi[b], cells[b], thresholds, cam, L)
+            level[v, b] = select_block(lo[b], hi[b], cells[b], thresholds, cam, L, contraction)
         counts = np.array([lvl_cnt[b, level[v, b]] if level[v, b] >= 0 else 0 for b in range(B)], np.int64)
         offsets[v, 1:] = np.cumsum(counts)
     return level, offsets

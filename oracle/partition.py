@@ -78,3 +78,18 @@ def partition(means, p_min, p_max, nx, ny):
     off = np.zeros(nx * ny + 1, np.int64)
     off[1:] = np.cumsum(counts)
     return b, perm, off
+
+
+def contracted_cells(nx, ny):
+    """Cells [nx*ny, 4] (x0, x1, y0, y1) of the grid in contracted coordinates,
+    block id iy * nx + ix; the outermost ends are open (-inf / +inf) so the cell
+    test gives every point the block grid_index gives it."""
+    def edges(n):
+        e = [-np.inf] + [-2.0 + (4.0 * k) / n for k in range(1, n)] + [np.inf]
+        return e
+    ex, ey = edges(nx), edges(ny)
+    cells = np.zeros((nx * ny, 4))
+    for iy in range(ny):
+        for ix in range(nx):
+            cells[iy * nx + ix] = (ex[ix], ex[ix + 1], ey[iy], ey[iy + 1])
+    return cells

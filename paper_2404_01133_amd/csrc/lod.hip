@@ -17,6 +17,7 @@ struct LodArgs {
   const double* lo;
   const double* hi;
   const double* cell;
+  const double* contraction;  // NULL, or p_min[3], p_max[3] of a contracted partition
   const int64_t* lvl_cnt;
   int32_t B, L, V, mode;
   double thr[kMaxLevels - 1];
@@ -66,8 +67,29 @@ __device__ int select_level(const LodArgs& a, const gs_camera& cam, int b) {
     const double iy1 = vmax < H ? vmax : H, iy0 = vmin > 0.0 ? vmin : 0.0;
     visible = (ix1 > ix0) && (iy1 > iy0);
   }
+  // "the block where the camera is in": the camera centre's cell, in the
+  // contracted space of the partition when there is one (Eq. 2, as a Gaussian
+  // centre would be assigned)
+  double X = C0, Y = C1;
+  if (a.contraction) {
+    const double* pc = a.contraction;
+    const double q0 = (2.0 * (C0 - pc[0])) / (pc[3] - pc[0]) - 1.0;
+    const double q1 = (2.0 * (C1 - pc[1])) / (pc[4] - pc[1]) - 1.0;
+    const double q2 = (2.0 * (C2 - pc[2])) / (pc[5] - pc[2]) - 1.0;
+    const double m0 = fabs(q0), m1 = fabs(q1), m2 = fabs(q2);
+    const bool nan = !(m0 == m0) || !(m1 == m1) || !(m2 == m2);
+    double nrm = m0 > m1 ? m0 : m1;
+    nrm = m2 > nrm ? m2 : nrm;
+    X = q0;
+    Y = q1;
+    if (!nan && nrm > 1.0) {
+      const double sc = 2.0 - 1.0 / nrm;
+      X = sc * (q0 / nrm);
+      Y = sc * (q1 / nrm);
+    }
+  }
   const double* cl = a.cell + 4 * b;
-  const bool in_cell = (cl[0] <= C0) && (C0 < cl[1]) && (cl[2] <= C1) && (C1 < cl[3]);
+  const bool in_cell = (cl[0] <= X) && (X < cl[1]) && (cl[2] <= Y) && (Y < cl[3]);
   if (!(visible || in_cell)) return -1;
   int level = a.L - 1;
   for (int k = 0; k < a.L - 1; ++k)
@@ -144,6 +166,7 @@ extern "C" gs_status gs_lod_select(const gs_blocks* blocks, const double* thresh
   a.lo = blocks->lo;
   a.hi = blocks->hi;
   a.cell = blocks->cell;
+  a.contraction = blocks->contraction;
   a.lvl_cnt = blocks->lvl_cnt;
   a.B = blocks->n_blocks;
   a.L = blocks->n_levels;

@@ -25,9 +25,11 @@ struct PreArgs {
   const int64_t* lvl_off;
   const int8_t* level;
   const int64_t* offsets;
+  const uint32_t* gather;  // point-wise selection: record -> index within its level
   const gs_camera* cams;
   int64_t capacity;
   int32_t B, L, V, W, H, tw, th, sh_degree;
+  int32_t segs;  // segments per view: B (block-wise) or L (point-wise)
 };
 
 // One record: Gaussian gi of level l, seen by view v, stored at record index g.
@@ -80,14 +82,16 @@ __device__ __forceinline__ int64_t clamp_records(const PreArgs& a, int64_t* coun
   return n_rec;
 }
 
-// View-major: records in index order, each mapped to (view, block, level) by
-// a binary search of the segment offsets (staged in LDS when they fit).
+// View-major: records in index order, each mapped to (view, segment) by a
+// binary search of the segment offsets (staged in LDS when they fit).  A
+// block-wise segment is (view, block) at the block's chosen level; a
+// point-wise segment is (view, level) with the Gaussian read from the gather list.
 __global__ void __launch_bounds__(kPreThreads) preprocess_kernel(PreArgs a, Record* __restrict__ records,
                                                                  uint32_t* __restrict__ depth_keys,
                                                                  int32_t* __restrict__ tiles_touched,
                                                                  int64_t* __restrict__ counts) {
   const int64_t n_rec = clamp_records(a, counts);
-  const int nseg = a.V * a.B;
+  const int nseg = a.V * a.segs;
   __shared__ int64_t s_off[kLdsOffsets];
   const bool lds_off = nseg < kLdsOffsets;
   if (lds_off)
@@ -96,9 +100,16 @@ __global__ void __launch_bounds__(kPreThreads) preprocess_kernel(PreArgs a, Reco
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_rec; g += stride) {
     const int p = lds_off ? find_segment(s_off, nseg, g) : find_segment(a.offsets, nseg, g);
-    const int v = p / a.B, b = p - v * a.B;
-    const int l = a.level[p];
-    const int64_t gi = a.lvl_off[(int64_t)b * a.L + l] + (g - (lds_off ? s_off[p] : a.offsets[p]));
+    const int v = p / a.segs, b = p - v * a.segs;
+    int l;
+    int64_t gi;
+    if (a.gather) {
+      l = b;
+      gi = a.gather[g];
+    } else {
+      l = a.level[p];
+      gi = a.lvl_off[(int64_t)b * a.L + l] + (g - (lds_off ? s_off[p] : a.offsets[p]));
+    }
     preprocess_record(a, g, v, l, gi, records, depth_keys, tiles_touched);
   }
 }
@@ -113,16 +124,17 @@ __global__ void __launch_bounds__(kPreThreads) preprocess_shared_kernel(PreArgs 
                                                                         int64_t* __restrict__ counts) {
   const int64_t n_rec = clamp_records(a, counts);
   __shared__ int64_t s_off[kLdsOffsets];
-  const bool lds_off = a.B < kLdsOffsets;
+  const bool lds_off = a.segs < kLdsOffsets;
   if (lds_off)
-    for (int k = threadIdx.x; k <= a.B; k += blockDim.x) s_off[k] = a.offsets[k];
+    for (int k = threadIdx.x; k <= a.segs; k += blockDim.x) s_off[k] = a.offsets[k];
   __syncthreads();
-  const int64_t n_view = a.offsets[a.B];
+  const int64_t n_view = a.offsets[a.segs];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_view; i += stride) {
-    const int b = lds_off ? find_segment(s_off, a.B, i) : find_segment(a.offsets, a.B, i);
-    const int l = a.level[b];
-    const int64_t gi = a.lvl_off[(int64_t)b * a.L + l] + (i - (lds_off ? s_off[b] : a.offsets[b]));
+    const int b = lds_off ? find_segment(s_off, a.segs, i) : find_segment(a.offsets, a.segs, i);
+    const int l = a.gather ? b : a.level[b];
+    const int64_t gi = a.gather ? (int64_t)a.gather[i]
+                                : a.lvl_off[(int64_t)b * a.L + l] + (i - (lds_off ? s_off[b] : a.offsets[b]));
     for (int v = 0; v < a.V; ++v) {
       const int64_t g = (int64_t)v * n_view + i;
       if (g >= n_rec) break;
@@ -135,20 +147,21 @@ __global__ void __launch_bounds__(kPreThreads) preprocess_shared_kernel(PreArgs 
 }  // namespace gs
 
 extern "C" gs_status gs_preprocess(const gs_gaussians* levels, const gs_blocks* blocks, const int8_t* level,
-                                   const int64_t* offsets, const gs_camera* cams, int32_t n_views, int32_t width,
+                                   const int64_t* offsets, const uint32_t* gather, const gs_camera* cams, int32_t n_views, int32_t width,
                                    int32_t height, int32_t sh_degree, const gs_tuning* tuning,
                                    int64_t record_capacity, void* records, uint32_t* depth_keys,
                                    int32_t* tiles_touched, int64_t* counts, void* stream) {
   using namespace gs;
-  if (!levels || !blocks || !level || !offsets || !cams || !tuning || !counts) return GS_ERR_INVALID_ARG;
+  if (!levels || !blocks || (!level && !gather) || !offsets || !cams || !tuning || !counts) return GS_ERR_INVALID_ARG;
   if (n_views <= 0 || width <= 0 || height <= 0 || width > 65535 || height > 65535) return GS_ERR_INVALID_ARG;
   if (sh_degree < 0 || sh_degree > 3) return GS_ERR_INVALID_ARG;
-  if (blocks->n_blocks <= 0 || blocks->n_levels <= 0 || blocks->n_levels > kMaxLevels || !blocks->lvl_off)
-    return GS_ERR_INVALID_ARG;
+  if (blocks->n_levels <= 0 || blocks->n_levels > kMaxLevels) return GS_ERR_INVALID_ARG;
+  if (!gather && (blocks->n_blocks <= 0 || !blocks->lvl_off)) return GS_ERR_INVALID_ARG;
   if (!tile_shape_supported(tuning->tile_w, tuning->tile_h)) return GS_ERR_UNSUPPORTED;
   if (record_capacity < 0 || (record_capacity > 0 && (!records || !depth_keys || !tiles_touched)))
     return GS_ERR_INVALID_ARG;
-  if ((int64_t)n_views * blocks->n_blocks > (int64_t)1 << 30) return GS_ERR_INVALID_ARG;
+  const int32_t segs = gather ? blocks->n_levels : blocks->n_blocks;
+  if ((int64_t)n_views * segs > (int64_t)1 << 30) return GS_ERR_INVALID_ARG;
   if (record_capacity >= ((int64_t)1 << 32)) return GS_ERR_INVALID_ARG;  // record ids are u32
   PreArgs a{};
   for (int l = 0; l < blocks->n_levels; ++l) {
@@ -159,6 +172,8 @@ extern "C" gs_status gs_preprocess(const gs_gaussians* levels, const gs_blocks* 
   a.lvl_off = blocks->lvl_off;
   a.level = level;
   a.offsets = offsets;
+  a.gather = gather;
+  a.segs = segs;
   a.cams = cams;
   a.capacity = record_capacity;
   a.B = blocks->n_blocks;

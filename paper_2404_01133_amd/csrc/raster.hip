@@ -1,7 +1,7 @@
 // Per-tile alpha compositing (Eq. 1 of the paper) and its adjoint.
 //
-// Forward: one work-group per (view, tile); one lane per pixel, so a 16x16
-// tile is four wave64s covering 16x4 pixel strips.  The tile's Gaussians are
+// Forward: one work-group per (view, tile); one lane per pixel, each wave64 an
+// 8x8 pixel block of the tile (a 16x16 tile is four waves).  The tile's Gaussians are
 // staged through LDS in batches (coalesced gathers of 48-byte records, one per
 // lane); every lane then reads the same LDS record (a broadcast, no bank
 // conflicts).  A lane leaves the loop when its transmittance would drop below
@@ -43,20 +43,38 @@ __device__ __forceinline__ void evaluate(const float4& w0, const float4& w1, int
   e.alpha = fminf(kAlphaMax, w1.w * e.G);
 }
 
-// Each wave keeps the indices of the staged records whose footprint rows meet
-// its own pixel rows (ballot compaction), so the blend loop never visits a
-// record that cannot touch the wave.
-template <int TW, int BATCH>
-__device__ __forceinline__ int wave_compact_rows(const float4* s_w0, int nb, int row0, int row1, uint16_t* list) {
+// Lane -> pixel map: the tile is cut into 8x8 pixel blocks, one per wave
+// (wave w is block (w mod TW/8, w div TW/8)); lane l is pixel (l mod 8, l div 8)
+// of its block.  Against a small footprint a square block keeps more of the
+// wave's lanes busy than a row strip of the same 64 pixels.
+template <int TW, int TH>
+struct WaveBlock {
+  int i, j;    // this lane's pixel
+  int x0, y0;  // first pixel of the wave's block
+  __device__ __forceinline__ WaveBlock(int txi, int tyi, int wid) {
+    static_assert(TW % 8 == 0 && TH % 8 == 0, "tiles are whole 8x8 blocks");
+    const int lane = threadIdx.x & 63;
+    x0 = txi * TW + (wid % (TW / 8)) * 8;
+    y0 = tyi * TH + (wid / (TW / 8)) * 8;
+    i = x0 + (lane & 7);
+    j = y0 + (lane >> 3);
+  }
+};
+
+// Each wave keeps the indices of the staged records whose footprint meets its
+// own 8x8 block (ballot compaction), so the blend loop never visits a record
+// that cannot touch the wave.
+__device__ __forceinline__ int wave_compact_block(const float4* s_w0, int nb, int x0, int y0, uint16_t* list) {
   const int lane = threadIdx.x & 63;
   int cnt = 0;
   for (int base = 0; base < nb; base += 64) {
     const int k = base + lane;
     bool hit = false;
     if (k < nb) {
-      const uint32_t py = __float_as_uint(s_w0[k].w);
+      const uint32_t px = __float_as_uint(s_w0[k].z), py = __float_as_uint(s_w0[k].w);
+      const int i0 = (int)(px & 0xFFFFu), i1 = i0 + (int)(px >> 16);
       const int j0 = (int)(py & 0xFFFFu), j1 = j0 + (int)(py >> 16);
-      hit = !(j1 < row0 || j0 > row1);
+      hit = !(i1 < x0 || i0 > x0 + 7 || j1 < y0 || j0 > y0 + 7);
     }
     const uint64_t m = __ballot(hit);
     if (hit) list[cnt + (int)lanemask_lt_count(m)] = (uint16_t)k;
@@ -114,13 +132,10 @@ __device__ __forceinline__ void raster_fwd_tile(const TileArgs& ta, FwdLds<TW, T
   const int view = tile_g / tiles_per_view;
   const int tile = tile_g - view * tiles_per_view;
   const int tyi = tile / tiles_x_n, txi = tile - tyi * tiles_x_n;
-  const int i = txi * TW + (int)(threadIdx.x % TW);
-  const int j = tyi * TH + (int)(threadIdx.x / TW);
-  const bool inside = (i < W) && (j < H);
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  // rows covered by this wave (a wave is 64 consecutive pixels of the row-major tile)
-  const int wave_row0 = tyi * TH + wid * (64 / TW);
-  const int wave_row1 = wave_row0 + 64 / TW - 1;
+  const WaveBlock<TW, TH> wb(txi, tyi, wid);
+  const int i = wb.i, j = wb.j;
+  const bool inside = (i < W) && (j < H);
   const uint32_t start = ranges[2 * tile_g], end = ranges[2 * tile_g + 1];
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
   int last = 0;
@@ -136,7 +151,7 @@ __device__ __forceinline__ void raster_fwd_tile(const TileArgs& ta, FwdLds<TW, T
       s_w2[k] = r[2];
     }
     __syncthreads();
-    const int cnt = wave_compact_rows<TW, BATCH>(s_w0, nb, wave_row0, wave_row1, list);
+    const int cnt = wave_compact_block(s_w0, nb, wb.x0, wb.y0, list);
     const int base_idx = (int)(b - start);
     if (cnt > 0 && __ballot(!done) != 0) {
       int k = __builtin_amdgcn_readfirstlane((int)list[0]);
@@ -265,13 +280,11 @@ __device__ __forceinline__ void raster_bwd_tile(const TileArgs& ta, BwdLds<TW, T
   const int view = tile_g / tiles_per_view;
   const int tile = tile_g - view * tiles_per_view;
   const int tyi = tile / tiles_x_n, txi = tile - tyi * tiles_x_n;
-  const int i = txi * TW + (int)(threadIdx.x % TW);
-  const int j = tyi * TH + (int)(threadIdx.x / TW);
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const WaveBlock<TW, TH> wb(txi, tyi, wid);
+  const int i = wb.i, j = wb.j;
   const bool inside = (i < W) && (j < H);
-  const int wave_row0 = tyi * TH + wid * (64 / TW);
-  const int wave_row1 = wave_row0 + 64 / TW - 1;
   const uint32_t start = ranges[2 * tile_g];
   const int64_t plane = (int64_t)H * W;
   const int64_t pix = (int64_t)j * W + i;
@@ -311,7 +324,7 @@ __device__ __forceinline__ void raster_bwd_tile(const TileArgs& ta, BwdLds<TW, T
     __syncthreads();
     const int base_idx = (int)(b - start);
     const int kmax = min(nb, wave_last - base_idx);  // entries past every lane's n_last are not needed
-    const int cnt = kmax > 0 ? wave_compact_rows<TW, BATCH>(s_w0, kmax, wave_row0, wave_row1, list) : 0;
+    const int cnt = kmax > 0 ? wave_compact_block(s_w0, kmax, wb.x0, wb.y0, list) : 0;
     for (int t = 0; t < cnt; ++t) {
       const int k = __builtin_amdgcn_readfirstlane((int)list[t]);
       const float4 w0 = s_w0[k], w1 = s_w1[k], w2 = s_w2[k];
@@ -378,9 +391,11 @@ struct BwdArgs {
   const int64_t* lvl_off;
   const int8_t* level;
   const int64_t* offsets;
+  const uint32_t* gather;  // point-wise selection: record -> index within its level
   const gs_camera* cams;
   int64_t capacity;
   int32_t B, L, V, W, H, sh_degree;
+  int32_t segs;  // segments per view: B (block-wise) or L (point-wise)
 };
 
 // With one view per call every Gaussian owns at most one record, so its
@@ -605,13 +620,13 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(BwdArgs a, const Re
                                                              const int64_t* __restrict__ counts) {
   int64_t n_rec = counts[GS_COUNT_RECORDS];
   if (n_rec > a.capacity) n_rec = a.capacity;
-  const int nseg = a.V * a.B;
+  const int nseg = a.V * a.segs;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_rec; g += stride) {
     const int p = find_segment(a.offsets, nseg, g);
-    const int v = p / a.B, b = p - v * a.B;
-    const int l = a.level[p];
-    const int64_t gi = a.lvl_off[(int64_t)b * a.L + l] + (g - a.offsets[p]);
+    const int v = p / a.segs, b = p - v * a.segs;
+    const int l = a.gather ? b : a.level[p];
+    const int64_t gi = a.gather ? (int64_t)a.gather[g] : a.lvl_off[(int64_t)b * a.L + l] + (g - a.offsets[p]);
     preprocess_bwd_record<ATOMIC>(a, records, grad2d, g, v, l, gi);
   }
 }
@@ -623,12 +638,12 @@ __global__ void __launch_bounds__(256) preprocess_bwd_shared_kernel(BwdArgs a, c
                                                                     const int64_t* __restrict__ counts) {
   int64_t n_rec = counts[GS_COUNT_RECORDS];
   if (n_rec > a.capacity) n_rec = a.capacity;
-  const int64_t n_view = a.offsets[a.B];
+  const int64_t n_view = a.offsets[a.segs];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_view; i += stride) {
-    const int b = find_segment(a.offsets, a.B, i);
-    const int l = a.level[b];
-    const int64_t gi = a.lvl_off[(int64_t)b * a.L + l] + (i - a.offsets[b]);
+    const int b = find_segment(a.offsets, a.segs, i);
+    const int l = a.gather ? b : a.level[b];
+    const int64_t gi = a.gather ? (int64_t)a.gather[i] : a.lvl_off[(int64_t)b * a.L + l] + (i - a.offsets[b]);
     for (int v = 0; v < a.V; ++v) {
       const int64_t g = (int64_t)v * n_view + i;
       if (g >= n_rec) break;
@@ -722,18 +737,19 @@ extern "C" gs_status gs_rasterize_bwd(const void* records, const uint32_t* pair_
                                       const gs_tuning* tuning, const float* rgb, const float* T_final,
                                       const int32_t* n_last, const float* d_rgb, const gs_gaussians* levels,
                                       const gs_blocks* blocks, const int8_t* level, const int64_t* offsets,
-                                      const gs_camera* cams, int32_t sh_degree, int64_t record_capacity,
+                                      const uint32_t* gather, const gs_camera* cams, int32_t sh_degree,
+                                      int64_t record_capacity,
                                       const int64_t* counts, const gs_gaussian_grads* grads, void* ws,
                                       size_t ws_bytes, void* stream) {
   using namespace gs;
   (void)bg;  // the background enters through the saved forward colour
   if (!records || !pair_records || !tile_ranges || !tuning || !rgb || !T_final || !n_last || !d_rgb || !levels ||
-      !blocks || !level || !offsets || !cams || !counts || !grads || !ws)
+      !blocks || (!level && !gather) || !offsets || !cams || !counts || !grads || !ws)
     return GS_ERR_INVALID_ARG;
   if (n_views <= 0 || width <= 0 || height <= 0 || width > 65535 || height > 65535) return GS_ERR_INVALID_ARG;
   if (sh_degree < 0 || sh_degree > 3 || record_capacity <= 0) return GS_ERR_INVALID_ARG;
-  if (blocks->n_blocks <= 0 || blocks->n_levels <= 0 || blocks->n_levels > kMaxLevels || !blocks->lvl_off)
-    return GS_ERR_INVALID_ARG;
+  if (blocks->n_levels <= 0 || blocks->n_levels > kMaxLevels) return GS_ERR_INVALID_ARG;
+  if (!gather && (blocks->n_blocks <= 0 || !blocks->lvl_off)) return GS_ERR_INVALID_ARG;
   const int tw = tuning->tile_w, th = tuning->tile_h;
   if (!tile_shape_supported(tw, th) || !batch_supported(tuning->batch)) return GS_ERR_UNSUPPORTED;
   if (ws_bytes < rasterize_bwd_ws_bytes(record_capacity)) return GS_ERR_WORKSPACE;
@@ -768,6 +784,8 @@ extern "C" gs_status gs_rasterize_bwd(const void* records, const uint32_t* pair_
   a.lvl_off = blocks->lvl_off;
   a.level = level;
   a.offsets = offsets;
+  a.gather = gather;
+  a.segs = gather ? blocks->n_levels : blocks->n_blocks;
   a.cams = cams;
   a.capacity = record_capacity;
   a.B = blocks->n_blocks;

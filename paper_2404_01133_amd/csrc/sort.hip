@@ -19,32 +19,14 @@
 // wait is still bounded (kSpinLimit) and raises GS_FLAG_WAIT if it gives up.
 // Every device size is read from the counts array, so nothing here needs a
 // host synchronisation and the whole stage can be captured in a HIP graph.
-#include "gs_common.h"
+#include "radix.h"
 
 namespace gs {
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kItems = 8;
-constexpr int kTile = kThreads * kItems;  // 2048 keys per radix / scan tile
-constexpr int kRadix = 256;
 constexpr int kMaxPasses = 8;
-constexpr uint32_t kFlagAgg = 1u << 30;
-constexpr uint32_t kFlagInc = 2u << 30;
-constexpr uint32_t kValMask = (1u << 30) - 1;
-constexpr uint64_t kFlagAgg64 = 1ull << 62;
-constexpr uint64_t kFlagInc64 = 2ull << 62;
-constexpr uint64_t kValMask64 = (1ull << 62) - 1;
 constexpr int kPersistentBlocks = 1024;
-
-__device__ __forceinline__ int64_t count_clamped(const int64_t* counts, int idx, int64_t cap) {
-  int64_t n = counts[idx];
-  return n < cap ? n : cap;
-}
-
-__device__ __forceinline__ void raise_flag(int64_t* counts, int64_t bit) {
-  atomicOr((unsigned long long*)&counts[GS_COUNT_FLAGS], (unsigned long long)bit);
-}
+constexpr int kBigFootprint = 16;  // records touching more tiles are emitted cooperatively
 
 // ---------------------------------------------------------------------------
 // zero fill of the small fixed state and of the look-back words of the scans
@@ -65,60 +47,6 @@ __global__ void clear_front_kernel(uint32_t* __restrict__ fixed, int64_t fixed_w
     else if (i < fixed_words + 2 * scan_words) scan1[i - fixed_words - scan_words] = 0u;
     else dstatus[i - fixed_words - 2 * scan_words] = 0u;
   }
-}
-
-// ---------------------------------------------------------------------------
-// block-level exclusive scan of one u32 per thread (256 threads, 4 waves)
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_wave, uint32_t* total) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  uint32_t inc = x;
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t y = __shfl_up(inc, off, 64);
-    if (lane >= off) inc += y;
-  }
-  if (lane == 63) s_wave[wid] = inc;
-  __syncthreads();
-  uint32_t wave_base = 0, tot = 0;
-  for (int w = 0; w < kThreads / 64; ++w) {
-    const uint32_t s = s_wave[w];
-    if (w < wid) wave_base += s;
-    tot += s;
-  }
-  *total = tot;
-  __syncthreads();
-  return wave_base + inc - x;
-}
-
-// ---------------------------------------------------------------------------
-// decoupled look-back on 64-bit status words (one per scan tile)
-// ---------------------------------------------------------------------------
-__device__ uint64_t lookback64(uint64_t* status, int64_t t, uint64_t aggregate, int64_t* counts) {
-  uint64_t excl = 0;
-  if (t == 0) {
-    store_agent(&status[0], kFlagInc64 | aggregate);
-    return 0;
-  }
-  store_agent(&status[t], kFlagAgg64 | aggregate);
-  int64_t k = t - 1;
-  int64_t spins = 0;
-  while (k >= 0) {
-    const uint64_t s = load_agent(&status[k]);
-    const uint64_t flag = s & ~kValMask64;
-    if (flag == 0) {
-      if (++spins > kSpinLimit) {
-        raise_flag(counts, GS_FLAG_WAIT);
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-      continue;
-    }
-    excl += s & kValMask64;
-    if (flag == kFlagInc64) break;
-    --k;
-  }
-  store_agent(&status[t], kFlagInc64 | (excl + aggregate));
-  return excl;
 }
 
 // ---------------------------------------------------------------------------
@@ -155,10 +83,12 @@ __global__ void __launch_bounds__(kThreads) compact_kernel(const int32_t* __rest
     }
     uint32_t total;
     const uint32_t excl_thread = block_excl_scan(mine, s_wave, &total);
-    if (threadIdx.x == 0) {
-      const uint64_t ex = lookback64(status, t, total, counts);
-      s_excl = ex;
-      if (t == ntiles - 1) counts[GS_COUNT_VISIBLE] = (int64_t)(ex + total);
+    if (threadIdx.x < 64) {
+      const uint64_t ex = lookback64_wave(status, t, total, counts);
+      if (threadIdx.x == 0) {
+        s_excl = ex;
+        if (t == ntiles - 1) counts[GS_COUNT_VISIBLE] = (int64_t)(ex + total);
+      }
     }
     __syncthreads();
     uint64_t pos = s_excl + excl_thread;
@@ -213,13 +143,15 @@ __global__ void __launch_bounds__(kThreads) pair_offsets_kernel(const uint32_t* 
     }
     uint32_t total;
     const uint32_t excl_thread = block_excl_scan(mine, s_wave, &total);
-    if (threadIdx.x == 0) {
-      const uint64_t ex = lookback64(status, t, total, counts);
-      s_excl = ex;
-      if (t == ntiles - 1) {
-        const int64_t m = (int64_t)(ex + total);
-        counts[GS_COUNT_PAIRS] = m;
-        if (m > pair_cap) raise_flag(counts, GS_FLAG_PAIRS);
+    if (threadIdx.x < 64) {
+      const uint64_t ex = lookback64_wave(status, t, total, counts);
+      if (threadIdx.x == 0) {
+        s_excl = ex;
+        if (t == ntiles - 1) {
+          const int64_t m = (int64_t)(ex + total);
+          counts[GS_COUNT_PAIRS] = m;
+          if (m > pair_cap) raise_flag(counts, GS_FLAG_PAIRS);
+        }
       }
     }
     __syncthreads();
@@ -245,7 +177,9 @@ __global__ void __launch_bounds__(kThreads) emit_kernel(const Record* __restrict
                                                         uint32_t* __restrict__ out_tiles,
                                                         uint32_t* __restrict__ out_records, int tpasses,
                                                         uint32_t* __restrict__ hist, uint32_t* __restrict__ pstatus,
-                                                        uint32_t* __restrict__ ranges, int64_t range_words) {
+                                                        uint32_t* __restrict__ ranges, int64_t range_words,
+                                                        uint32_t* __restrict__ big_list,
+                                                        uint32_t* __restrict__ big_count) {
   __shared__ uint32_t s_hist[kMaxPasses][kRadix];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -265,6 +199,11 @@ __global__ void __launch_bounds__(kThreads) emit_kernel(const Record* __restrict
     const uint32_t view = reinterpret_cast<const uint32_t*>(&records[rid])[11];
     const int i0 = (int)(w0.z & 0xFFFFu), i1 = i0 + (int)(w0.z >> 16);
     const int j0 = (int)(w0.w & 0xFFFFu), j1 = j0 + (int)(w0.w >> 16);
+    const int ntx = i1 / tw - i0 / tw + 1, nty = j1 / th - j0 / th + 1;
+    if (ntx * nty > kBigFootprint) {  // many tiles: left to emit_big_kernel
+      big_list[atomicAdd(big_count, 1u)] = (uint32_t)j;
+      continue;
+    }
     int64_t o = pair_off[j];
     const uint32_t vbase = view * (uint32_t)tiles_per_view;
     for (int ty = j0 / th; ty <= j1 / th; ++ty)
@@ -285,130 +224,48 @@ __global__ void __launch_bounds__(kThreads) emit_kernel(const Record* __restrict
   }
 }
 
-// ---------------------------------------------------------------------------
-// one stable LSD pass over 8 bits; the digit histogram of the whole input was
-// accumulated by the kernel that produced the keys
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) radix_pass_kernel(
-    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
-    uint32_t* __restrict__ vals_out, const int64_t* counts_in, int count_idx, int64_t cap, int shift,
-    const uint32_t* __restrict__ hist, uint32_t* status, int64_t status_stride, uint32_t* tile_counter,
-    int64_t* counts) {
-  __shared__ uint32_t s_keys[kTile];
-  __shared__ uint32_t s_vals[kTile];
-  __shared__ uint32_t s_wave_hist[kThreads / 64][kRadix];
-  __shared__ uint32_t s_tile_excl[kRadix];
-  __shared__ uint32_t s_digit_base[kRadix];
-  __shared__ uint32_t s_wave[kThreads / 64];
-  __shared__ uint32_t s_tile;
-  __shared__ uint32_t s_goff[kRadix];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int64_t n = count_clamped(counts_in, count_idx, cap);
-  const int64_t ntiles = (n + kTile - 1) / kTile;
-  if ((int64_t)blockIdx.x >= ntiles) return;
-  {
-    uint32_t tot;
-    s_goff[threadIdx.x] = block_excl_scan(hist[threadIdx.x], s_wave, &tot);  // global digit offsets
+// Records whose footprint covers many tiles (a Gaussian close to the camera):
+// one work-group per record, its tiles strided over the threads, written to
+// the same slots (row-major tile order) the serial loop would use.
+__global__ void __launch_bounds__(kThreads) emit_big_kernel(const Record* __restrict__ records,
+                                                            const uint32_t* __restrict__ sorted_records,
+                                                            const uint32_t* __restrict__ pair_off,
+                                                            const uint32_t* __restrict__ big_list,
+                                                            const uint32_t* __restrict__ big_count, int64_t pair_cap,
+                                                            int tw, int th, int tiles_x_n, int tiles_per_view,
+                                                            uint32_t* __restrict__ out_tiles,
+                                                            uint32_t* __restrict__ out_records, int tpasses,
+                                                            uint32_t* __restrict__ hist) {
+  __shared__ uint32_t s_hist[kMaxPasses][kRadix];
+  for (int i = threadIdx.x; i < tpasses * kRadix; i += kThreads) (&s_hist[0][0])[i] = 0u;
+  __syncthreads();
+  const uint32_t nbig = *big_count;
+  for (uint32_t k = blockIdx.x; k < nbig; k += gridDim.x) {
+    const uint32_t j = big_list[k];
+    const uint32_t rid = sorted_records[j];
+    const uint4 w0 = *reinterpret_cast<const uint4*>(&records[rid]);
+    const uint32_t view = reinterpret_cast<const uint32_t*>(&records[rid])[11];
+    const int i0 = (int)(w0.z & 0xFFFFu), i1 = i0 + (int)(w0.z >> 16);
+    const int j0 = (int)(w0.w & 0xFFFFu), j1 = j0 + (int)(w0.w >> 16);
+    const int tx0 = i0 / tw, ty0 = j0 / th;
+    const int ntx = i1 / tw - tx0 + 1, nty = j1 / th - ty0 + 1;
+    const int64_t o0 = pair_off[j];
+    const uint32_t vbase = view * (uint32_t)tiles_per_view;
+    for (int q = threadIdx.x; q < ntx * nty; q += kThreads) {
+      const int64_t o = o0 + q;
+      if (o < pair_cap) {
+        const int ty = ty0 + q / ntx, tx = tx0 + q % ntx;
+        const uint32_t key = vbase + (uint32_t)(ty * tiles_x_n + tx);
+        out_tiles[o] = key;
+        out_records[o] = rid;
+        for (int p = 0; p < tpasses; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
+      }
+    }
   }
-  for (;;) {
-    if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
-    for (int i = threadIdx.x; i < (kThreads / 64) * kRadix; i += kThreads) (&s_wave_hist[0][0])[i] = 0u;
-    __syncthreads();
-    const int64_t t = s_tile;
-    if (t >= ntiles) break;
-    const int64_t tile_base = t * kTile;
-    const int tile_n = (int)((n - tile_base) < kTile ? (n - tile_base) : kTile);
-    // wave w owns the contiguous slice [w*64*kItems, (w+1)*64*kItems) of the tile;
-    // item k of lane l is element k*64 + l of that slice (coalesced loads)
-    uint32_t key[kItems], val[kItems], rank[kItems];
-    bool valid[kItems];
-    const int slice = wid * 64 * kItems;
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-      const int li = slice + k * 64 + lane;
-      valid[k] = li < tile_n;
-      key[k] = valid[k] ? keys_in[tile_base + li] : 0u;
-      val[k] = valid[k] ? vals_in[tile_base + li] : 0u;
-    }
-    // stable rank inside the wave: items in order k, lanes in order within an item
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-      const uint32_t d = (key[k] >> shift) & 255u;
-      uint64_t peers = __ballot(valid[k]);
-#pragma unroll
-      for (int bit = 0; bit < 8; ++bit) {
-        const bool b = (d >> bit) & 1u;
-        const uint64_t m = __ballot(b);
-        peers &= b ? m : ~m;
-      }
-      uint32_t prev = 0;
-      if (valid[k]) prev = s_wave_hist[wid][d];
-      const uint32_t below = (uint32_t)lanemask_lt_count(peers);
-      rank[k] = prev + below;
-      if (valid[k] && below == 0) s_wave_hist[wid][d] = prev + (uint32_t)__popcll(peers);
-      __builtin_amdgcn_wave_barrier();
-    }
-    __syncthreads();
-    // per digit: exclusive prefix over waves, tile count, tile-local digit prefix
-    const int d = threadIdx.x;
-    uint32_t run = 0;
-#pragma unroll
-    for (int w = 0; w < kThreads / 64; ++w) {
-      const uint32_t c = s_wave_hist[w][d];
-      s_wave_hist[w][d] = run;
-      run += c;
-    }
-    const uint32_t tile_cnt = run;
-    uint32_t tile_total;
-    const uint32_t tile_excl = block_excl_scan(tile_cnt, s_wave, &tile_total);
-    s_tile_excl[d] = tile_excl;
-    // decoupled look-back for digit d
-    uint32_t excl = 0;
-    uint32_t* st = status + t * status_stride + d;
-    if (t == 0) {
-      store_agent(st, kFlagInc | tile_cnt);
-    } else {
-      store_agent(st, kFlagAgg | tile_cnt);
-      int64_t k = t - 1;
-      int64_t spins = 0;
-      while (k >= 0) {
-        const uint32_t s = load_agent(status + k * status_stride + d);
-        const uint32_t flag = s & ~kValMask;
-        if (flag == 0) {
-          if (++spins > kSpinLimit) {
-            raise_flag(counts, GS_FLAG_WAIT);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        excl += s & kValMask;
-        if (flag == kFlagInc) break;
-        --k;
-      }
-      store_agent(st, kFlagInc | (excl + tile_cnt));
-    }
-    s_digit_base[d] = s_goff[d] + excl;
-    __syncthreads();
-    // local scatter by digit, then coalesced write-out
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-      if (valid[k]) {
-        const uint32_t dd = (key[k] >> shift) & 255u;
-        const uint32_t pos = s_tile_excl[dd] + s_wave_hist[wid][dd] + rank[k];
-        s_keys[pos] = key[k];
-        s_vals[pos] = val[k];
-      }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < tile_n; i += kThreads) {
-      const uint32_t kk = s_keys[i];
-      const uint32_t dd = (kk >> shift) & 255u;
-      const uint32_t out = s_digit_base[dd] + ((uint32_t)i - s_tile_excl[dd]);
-      keys_out[out] = kk;
-      vals_out[out] = s_vals[i];
-    }
-    __syncthreads();
+  __syncthreads();
+  for (int i = threadIdx.x; i < tpasses * kRadix; i += kThreads) {
+    const uint32_t c = (&s_hist[0][0])[i];
+    if (c) atomicAdd(&hist[i], c);
   }
 }
 
@@ -485,6 +342,7 @@ struct SortWs {
   uint32_t* dkeys_b;      // [rc]
   uint32_t* dvals_b;      // [rc]
   uint32_t* pair_off;     // [rc]
+  uint32_t* big_list;     // [rc] visible records with large footprints
   uint32_t* ptiles_alt;   // [pc]
   uint32_t* precs_alt;    // [pc]
   uint32_t* fixed;        // counters [64], then hist [2][kMaxPasses][256]
@@ -511,6 +369,7 @@ SortWs sort_ws_layout(char* base, int64_t rc, int64_t pc) {
   w.dkeys_b = (uint32_t*)take(4 * (size_t)rc);
   w.dvals_b = (uint32_t*)take(4 * (size_t)rc);
   w.pair_off = (uint32_t*)take(4 * (size_t)rc);
+  w.big_list = (uint32_t*)take(4 * (size_t)rc);
   w.ptiles_alt = (uint32_t*)take(4 * (size_t)pc);
   w.precs_alt = (uint32_t*)take(4 * (size_t)pc);
   w.fixed = (uint32_t*)take(4 * (size_t)kFixedWords);
@@ -597,9 +456,12 @@ extern "C" gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys
   //    buffer that the last tile pass will read last
   uint32_t* em_tiles = (tpasses % 2 == 0) ? pair_tiles : w.ptiles_alt;
   uint32_t* em_recs = (tpasses % 2 == 0) ? pair_records : w.precs_alt;
+  uint32_t* big_count = counters + 32;
   hipLaunchKernelGGL(emit_kernel, grid_for(record_capacity), blk, 0, s, (const Record*)records, w.dvals_a, w.pair_off,
                      record_capacity, counts, pair_capacity, tw, th, tx_n, (int)tiles_per_view, em_tiles, em_recs,
-                     tpasses, thist, w.pstatus, tile_ranges, 2 * n_tile_ids);
+                     tpasses, thist, w.pstatus, tile_ranges, 2 * n_tile_ids, w.big_list, big_count);
+  hipLaunchKernelGGL(emit_big_kernel, dim3(256), blk, 0, s, (const Record*)records, w.dvals_a, w.pair_off, w.big_list,
+                     big_count, pair_capacity, tw, th, tx_n, (int)tiles_per_view, em_tiles, em_recs, tpasses, thist);
   GS_LAUNCH_CHECK();
   // 5. tile passes
   uint32_t* kin = em_tiles;

@@ -53,7 +53,7 @@ class gs_gaussian_grads(ctypes.Structure):
 
 class gs_blocks(ctypes.Structure):
     _fields_ = [("lo", c_void_p), ("hi", c_void_p), ("cell", c_void_p), ("lvl_off", c_void_p),
-                ("lvl_cnt", c_void_p), ("n_blocks", c_int32), ("n_levels", c_int32)]
+                ("lvl_cnt", c_void_p), ("n_blocks", c_int32), ("n_levels", c_int32), ("contraction", c_void_p)]
 
 
 class gs_tuning(ctypes.Structure):
@@ -69,8 +69,11 @@ _SIGNATURES = {
     "gs_workspace_bytes": (c_size_t, [c_int32, c_int64, c_int64, c_int32, c_int32, c_int32, c_void_p]),
     "gs_lod_select": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
                                 c_void_p]),
-    "gs_preprocess": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32,
-                                c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "gs_points_workspace_bytes": (c_size_t, [c_void_p, c_int32, c_int32]),
+    "gs_lod_select_points": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_int64, c_void_p, c_void_p,
+                                       c_void_p, c_void_p, c_size_t, c_void_p]),
+    "gs_preprocess": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32,
+                                c_int32, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "gs_bin_sort": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_int64, c_int64,
                               c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "gs_rasterize_fwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p,
@@ -78,7 +81,12 @@ _SIGNATURES = {
     "gs_rasterize_bwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p,
                                    c_void_p,
                                    c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
-                                   c_void_p, c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+                                   c_void_p, c_void_p, c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_size_t,
+                                   c_void_p]),
+    "gs_partition_workspace_bytes": (c_size_t, [c_int64]),
+    "gs_partition": (c_int32, [c_void_p, c_int64, c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                               c_void_p, c_size_t, c_void_p]),
+    "gs_gather_gaussians": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
     "gs_mad_workspace_bytes": (c_size_t, [c_int64]),
     "gs_mad_bounds": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int64, c_double, c_void_p,
                                 c_void_p, c_void_p, c_size_t, c_void_p]),
@@ -177,10 +185,10 @@ def grads_struct(gm, gs_, gq, go, gsh) -> gs_gaussian_grads:
     return gs_gaussian_grads(gm.data_ptr(), gs_.data_ptr(), gq.data_ptr(), go.data_ptr(), gsh.data_ptr())
 
 
-def blocks_struct(lo, hi, cell, lvl_off, lvl_cnt) -> gs_blocks:
+def blocks_struct(lo, hi, cell, lvl_off, lvl_cnt, contraction=None) -> gs_blocks:
     B, L = lvl_off.shape
     ptr = lambda t: None if t is None else t.data_ptr()
-    return gs_blocks(ptr(lo), ptr(hi), ptr(cell), lvl_off.data_ptr(), lvl_cnt.data_ptr(), B, L)
+    return gs_blocks(ptr(lo), ptr(hi), ptr(cell), lvl_off.data_ptr(), lvl_cnt.data_ptr(), B, L, ptr(contraction))
 
 
 def tuning_struct(tile_w=16, tile_h=16, batch=256, flags=0) -> gs_tuning:
@@ -196,12 +204,27 @@ def lod_select(blocks: gs_blocks, thresholds, mode, cams_dev, n_views, level, of
                                _p(counts), _stream(stream)), "gs_lod_select")
 
 
-def preprocess(levels, blocks: gs_blocks, level, offsets, cams_dev, n_views, width, height, sh_degree,
-               tuning: gs_tuning, record_capacity, records, depth_keys, tiles_touched, counts, stream=None):
+def points_workspace_bytes(level_sizes, n_views) -> int:
+    sizes = (c_int64 * len(level_sizes))(*[int(x) for x in level_sizes])
+    return int(lib().gs_points_workspace_bytes(sizes, len(level_sizes), n_views))
+
+
+def lod_select_points(levels, thresholds, cams_dev, n_views, record_capacity, gather, offsets, counts, ws,
+                      stream=None):
     arr = (gs_gaussians * len(levels))(*levels)
-    _check(lib().gs_preprocess(arr, ctypes.byref(blocks), _p(level), _p(offsets), _p(cams_dev), n_views, width, height,
-                               sh_degree, ctypes.byref(tuning), record_capacity, _p(records), _p(depth_keys),
-                               _p(tiles_touched), _p(counts), _stream(stream)), "gs_preprocess")
+    thr = (c_double * max(1, len(thresholds)))(*[float(x) for x in thresholds])
+    _check(lib().gs_lod_select_points(arr, len(levels), thr, _p(cams_dev), n_views, record_capacity, _p(gather),
+                                      _p(offsets), _p(counts), _p(ws), ws.numel() * ws.element_size(),
+                                      _stream(stream)), "gs_lod_select_points")
+
+
+def preprocess(levels, blocks: gs_blocks, level, offsets, cams_dev, n_views, width, height, sh_degree,
+               tuning: gs_tuning, record_capacity, records, depth_keys, tiles_touched, counts, stream=None,
+               gather=None):
+    arr = (gs_gaussians * len(levels))(*levels)
+    _check(lib().gs_preprocess(arr, ctypes.byref(blocks), _p(level), _p(offsets), _p(gather), _p(cams_dev), n_views,
+                               width, height, sh_degree, ctypes.byref(tuning), record_capacity, _p(records),
+                               _p(depth_keys), _p(tiles_touched), _p(counts), _stream(stream)), "gs_preprocess")
 
 
 def bin_sort(records, depth_keys, tiles_touched, n_views, width, height, tuning: gs_tuning, record_capacity,
@@ -222,16 +245,32 @@ def rasterize_fwd(records, pair_records, tile_ranges, n_views, width, height, bg
 
 def rasterize_bwd(records, pair_records, tile_ranges, n_views, width, height, bg, tuning: gs_tuning, rgb, T_final,
                   n_last, d_rgb, levels, blocks: gs_blocks, level, offsets, cams_dev, sh_degree, record_capacity,
-                  counts, grads, ws, stream=None, tile_queue=None):
+                  counts, grads, ws, stream=None, tile_queue=None, gather=None):
     bgv = (ctypes.c_float * 3)(*[float(x) for x in bg])
     lv = (gs_gaussians * len(levels))(*levels)
     gr = (gs_gaussian_grads * len(grads))(*grads)
     _check(lib().gs_rasterize_bwd(_p(records), _p(pair_records), _p(tile_ranges), _p(tile_queue), n_views, width,
                                   height, bgv,
                                   ctypes.byref(tuning), _p(rgb), _p(T_final), _p(n_last), _p(d_rgb), lv,
-                                  ctypes.byref(blocks), _p(level), _p(offsets), _p(cams_dev), sh_degree,
+                                  ctypes.byref(blocks), _p(level), _p(offsets), _p(gather), _p(cams_dev), sh_degree,
                                   record_capacity, _p(counts), gr, _p(ws), ws.numel() * ws.element_size(),
                                   _stream(stream)), "gs_rasterize_bwd")
+
+
+def partition_workspace_bytes(n) -> int:
+    return int(lib().gs_partition_workspace_bytes(int(n)))
+
+
+def partition(means, n, xy_box, nx, ny, perm, block_off, ws, block_id=None, cells=None, stream=None):
+    box = (c_double * 4)(*[float(x) for x in xy_box])
+    _check(lib().gs_partition(_p(means), int(n), box, nx, ny, _p(block_id), _p(perm), _p(block_off), _p(cells),
+                              _p(ws), 0 if ws is None else ws.numel() * ws.element_size(), _stream(stream)),
+           "gs_partition")
+
+
+def gather_gaussians(src: gs_gaussians, perm, n, dst: gs_gaussian_grads, stream=None):
+    _check(lib().gs_gather_gaussians(ctypes.byref(src), _p(perm), int(n), ctypes.byref(dst), _stream(stream)),
+           "gs_gather_gaussians")
 
 
 def mad_bounds(finest: gs_gaussians, lvl_off, lvl_cnt, n_mad, lo, hi, max_block_count, ws, stream=None):

@@ -3,6 +3,7 @@ differentiable render (torch.autograd.Function).
 
 A frame is five library calls on one stream (Sec. 3.3.2 then Sec. 3.1):
     lod_select -> preprocess -> bin_sort -> rasterize_fwd  [-> rasterize_bwd]
+(lod_select_points in place of lod_select for the point-wise baseline.)
 Buffers are allocated once per capacity and reused; data-dependent sizes stay
 on the device (the counts array), so a frame issues no host synchronisation
 unless a capacity check is requested.
@@ -16,6 +17,9 @@ import torch
 
 from . import gs
 
+# selection mode of render_frame besides gs.GS_LOD_BLOCKWISE / gs.GS_LOD_ALL_FINEST:
+# the point-wise baseline (gs_lod_select_points)
+LOD_POINTWISE = "pointwise"
 
 # ---------------------------------------------------------------------------
 # scenes
@@ -51,6 +55,7 @@ class DeviceScene:
         self.cells = None if cells is None else torch.as_tensor(np.asarray(cells, np.float64)).to(device)
         self.lo = None if lo is None else torch.as_tensor(np.asarray(lo, np.float64)).to(device)
         self.hi = None if hi is None else torch.as_tensor(np.asarray(hi, np.float64)).to(device)
+        self.contraction = None  # device [6] p_min, p_max of a contracted partition
 
     @property
     def n_blocks(self) -> int:
@@ -93,9 +98,13 @@ class DeviceScene:
         device (level l keeps the Gaussians with u < fractions[l]; coarser
         levels have scales x coarse_scale), so a 20M-Gaussian scene is built
         without host copies of the coarse levels."""
+        fine_dev = DeviceLevel(*(torch.from_numpy(np.ascontiguousarray(a)).to(device) for a in fine.astuple()))
+        return DeviceScene._nested(fine_dev, block_id, u, cells, fractions, coarse_scale, device)
+
+    @staticmethod
+    def _nested(fine_dev, block_id, u, cells, fractions, coarse_scale, device, contraction=None):
         B = cells.shape[0]
         L = len(fractions)
-        fine_dev = DeviceLevel(*(torch.from_numpy(np.ascontiguousarray(a)).to(device) for a in fine.astuple()))
         lvl_cnt = np.zeros((B, L), np.int64)
         levels = []
         for l, frac in enumerate(fractions):
@@ -115,7 +124,41 @@ class DeviceScene:
             del idx
         lvl_off = np.zeros_like(lvl_cnt)
         lvl_off[1:] = np.cumsum(lvl_cnt, axis=0)[:-1]
-        return DeviceScene(levels, lvl_off, lvl_cnt, cells=cells, device=device)
+        scene = DeviceScene(levels, lvl_off, lvl_cnt, cells=cells, device=device)
+        if contraction is not None:
+            scene.contraction = torch.as_tensor(np.asarray(contraction, np.float64)).to(device)
+        return scene
+
+    @staticmethod
+    def from_partition(fine, u, xy_box, nx, ny, fractions=(0.30, 0.50, 1.00), coarse_scale=1.3,
+                       device="cuda") -> "DeviceScene":
+        """Partition a finest-level Gaussian cloud (any order) into an nx x ny grid
+        over the contracted space of Sec. 3.2.2 on the GPU (gs_partition), store
+        it block by block (gs_gather_gaussians) and derive the nested coarser
+        levels as from_finest does.  Cells are the contracted grid cells and the
+        block table carries the contraction, so the camera's block is found in
+        the same space.  Returns (scene, perm) with perm the new order."""
+        n = fine.n
+        src = DeviceLevel(*(torch.from_numpy(np.ascontiguousarray(a)).to(device) for a in fine.astuple()))
+        perm = torch.empty(max(1, n), dtype=torch.int32, device=device)
+        block_off = torch.empty(nx * ny + 1, dtype=torch.int64, device=device)
+        cells = torch.empty((nx * ny, 4), dtype=torch.float64, device=device)
+        ws = torch.empty(max(1, gs.partition_workspace_bytes(n)), dtype=torch.uint8, device=device)
+        gs.partition(src.means, n, xy_box, nx, ny, perm, block_off, ws, cells=cells)
+        dst = DeviceLevel(*(torch.empty_like(t) for t in (src.means, src.scales, src.quats, src.opac, src.sh)))
+        gs.gather_gaussians(src.struct(), perm, n, gs.grads_struct(dst.means, dst.scales, dst.quats, dst.opac,
+                                                                    dst.sh))
+        del src, ws
+        perm_host = perm[:n].cpu().numpy().view(np.uint32).astype(np.int64)
+        counts = np.diff(block_off.cpu().numpy())
+        block_id = np.repeat(np.arange(nx * ny), counts)
+        z = np.asarray(fine.means[2])
+        x0, x1 = sorted((float(xy_box[0]), float(xy_box[2])))
+        y0, y1 = sorted((float(xy_box[1]), float(xy_box[3])))
+        contraction = [x0, y0, float(z.min()), x1, y1, float(z.max())]
+        scene = DeviceScene._nested(dst, block_id, np.asarray(u)[perm_host], cells.cpu().numpy(), fractions,
+                                    coarse_scale, device, contraction)
+        return scene, perm_host
 
     @staticmethod
     def from_block_scene(bs, device="cuda") -> "DeviceScene":
@@ -133,7 +176,7 @@ class DeviceScene:
         return self.lo, self.hi
 
     def blocks_struct(self) -> gs.gs_blocks:
-        return gs.blocks_struct(self.lo, self.hi, self.cells, self.lvl_off, self.lvl_cnt)
+        return gs.blocks_struct(self.lo, self.hi, self.cells, self.lvl_off, self.lvl_cnt, self.contraction)
 
 
 # ---------------------------------------------------------------------------
@@ -163,6 +206,10 @@ class Frame:
         self.tile_queue = torch.zeros(2 + self.n_tiles, dtype=torch.int32, device=d)
         self.record_capacity = 0
         self.pair_capacity = 0
+        self.gather = None        # point-wise selection buffers, made on first use
+        self.pts_offsets = None
+        self.pts_ws = None
+        self.pointwise = False    # selection kind of the last render_frame
         self.reserve(record_capacity, pair_capacity)
 
     def reserve(self, record_capacity, pair_capacity):
@@ -174,6 +221,8 @@ class Frame:
             self.depth_keys = torch.empty(self.record_capacity, dtype=torch.int32, device=d)
             self.tiles_touched = torch.empty(self.record_capacity, dtype=torch.int32, device=d)
             self.bwd_ws = None
+            if self.gather is not None:
+                self.gather = torch.empty(self.record_capacity, dtype=torch.int32, device=d)
         if pair_capacity > self.pair_capacity:
             self.pair_capacity = int(pair_capacity)
             self.pair_tiles = torch.empty(self.pair_capacity, dtype=torch.int32, device=d)
@@ -182,6 +231,23 @@ class Frame:
                                     self.H, self.tuning)
         if getattr(self, "sort_ws", None) is None or self.sort_ws.numel() < nbytes:
             self.sort_ws = torch.empty(nbytes, dtype=torch.uint8, device=d)
+
+    def ensure_pointwise(self, scene):
+        d = self.device
+        L = scene.n_levels
+        if self.gather is None or self.gather.numel() < self.record_capacity:
+            self.gather = torch.empty(max(1, self.record_capacity), dtype=torch.int32, device=d)
+        if self.pts_offsets is None or self.pts_offsets.numel() != self.V * L + 1:
+            self.pts_offsets = torch.empty(self.V * L + 1, dtype=torch.int64, device=d)
+        nbytes = gs.points_workspace_bytes([lv.n for lv in scene.levels], self.V)
+        if self.pts_ws is None or self.pts_ws.numel() < nbytes:
+            self.pts_ws = torch.empty(nbytes, dtype=torch.uint8, device=d)
+
+    def selection(self):
+        """(level, offsets, gather) of the last selection, as gs_preprocess takes them."""
+        if self.pointwise:
+            return None, self.pts_offsets, self.gather
+        return self.level, self.offsets, None
 
     def host_counts(self):
         c = self.counts.cpu().numpy()
@@ -196,10 +262,19 @@ def render_frame(scene: DeviceScene, frame: Frame, cams_dev, mode=gs.GS_LOD_BLOC
     was too small the buffers grow and the frame is rendered again."""
     for _ in range(4):
         blocks = scene.blocks_struct()
-        gs.lod_select(blocks, thresholds, mode, cams_dev, frame.V, frame.level, frame.offsets, frame.counts, stream)
-        gs.preprocess([lv.struct() for lv in scene.levels], blocks, frame.level, frame.offsets, cams_dev, frame.V,
-                      frame.W, frame.H, sh_degree, frame.tuning, frame.record_capacity, frame.records,
-                      frame.depth_keys, frame.tiles_touched, frame.counts, stream)
+        levels = [lv.struct() for lv in scene.levels]
+        frame.pointwise = mode == LOD_POINTWISE
+        if frame.pointwise:
+            frame.ensure_pointwise(scene)
+            gs.lod_select_points(levels, thresholds, cams_dev, frame.V, frame.record_capacity, frame.gather,
+                                 frame.pts_offsets, frame.counts, frame.pts_ws, stream)
+        else:
+            gs.lod_select(blocks, thresholds, mode, cams_dev, frame.V, frame.level, frame.offsets, frame.counts,
+                          stream)
+        level, offsets, gather = frame.selection()
+        gs.preprocess(levels, blocks, level, offsets, cams_dev, frame.V, frame.W, frame.H, sh_degree, frame.tuning,
+                      frame.record_capacity, frame.records, frame.depth_keys, frame.tiles_touched, frame.counts,
+                      stream, gather=gather)
         gs.bin_sort(frame.records, frame.depth_keys, frame.tiles_touched, frame.V, frame.W, frame.H, frame.tuning,
                     frame.record_capacity, frame.pair_capacity, frame.pair_tiles, frame.pair_records,
                     frame.tile_ranges, frame.counts, frame.sort_ws, stream, frame.tile_queue)
@@ -224,12 +299,13 @@ def backward_frame(scene: DeviceScene, frame: Frame, cams_dev, d_rgb, grads, sh_
                                 frame.H, frame.tuning)
     if getattr(frame, "bwd_ws", None) is None or frame.bwd_ws.numel() < nbytes:
         frame.bwd_ws = torch.empty(nbytes, dtype=torch.uint8, device=frame.device)
+    level, offsets, gather = frame.selection()
     gs.rasterize_bwd(frame.records, frame.pair_records, frame.tile_ranges, frame.V, frame.W, frame.H, bg,
                      frame.tuning, frame.rgb, frame.T, frame.n_last, d_rgb.contiguous(),
-                     [lv.struct() for lv in scene.levels], scene.blocks_struct(), frame.level, frame.offsets,
+                     [lv.struct() for lv in scene.levels], scene.blocks_struct(), level, offsets,
                      cams_dev, sh_degree, frame.record_capacity, frame.counts,
                      [gs.grads_struct(g.means, g.scales, g.quats, g.opac, g.sh) for g in grads], frame.bwd_ws, stream,
-                     frame.tile_queue)
+                     frame.tile_queue, gather=gather)
 
 
 # ---------------------------------------------------------------------------

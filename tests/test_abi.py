@@ -58,6 +58,33 @@ def test_invalid_arguments_rejected_before_launch(libgs):
     assert libgs.gs_bin_sort(*([None] * 3), 1, 64, 64, *([None] * 1), ctypes.c_int64(10), ctypes.c_int64(10),
                              *([None] * 6), ctypes.c_size_t(0), None) == -1
     assert libgs.gs_rasterize_fwd(*([None] * 4), 1, 64, 64, *([None] * 6)) == -1
+    assert libgs.gs_lod_select_points(None, 3, None, None, 1, ctypes.c_int64(0), None, None, None, None,
+                                      ctypes.c_size_t(0), None) == -1
+
+
+def test_pointwise_workspace_and_threshold_checks(libgs):
+    libgs.gs_points_workspace_bytes.restype = ctypes.c_size_t
+    sizes = (ctypes.c_int64 * 3)(5000, 0, 2048)
+    a = libgs.gs_points_workspace_bytes(sizes, 3, 1)
+    b = libgs.gs_points_workspace_bytes(sizes, 3, 4)
+    assert 0 < a < b and b - a == 3 * (a - 256)
+    assert libgs.gs_points_workspace_bytes(None, 3, 1) == 0
+
+    class Gaussians(ctypes.Structure):
+        _fields_ = [("means", ctypes.c_void_p), ("scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
+                    ("opac", ctypes.c_void_p), ("sh", ctypes.c_void_p), ("n", ctypes.c_int64)]
+    dummy = 0x1000
+    lv = (Gaussians * 3)(*[Gaussians(dummy, dummy, dummy, dummy, dummy, 10) for _ in range(3)])
+    thr = (ctypes.c_double * 2)(500.0, 200.0)   # descending: rejected
+    r = libgs.gs_lod_select_points(lv, 3, thr, ctypes.c_void_p(dummy), 1, ctypes.c_int64(16), ctypes.c_void_p(dummy),
+                                   ctypes.c_void_p(dummy), ctypes.c_void_p(dummy), ctypes.c_void_p(dummy),
+                                   ctypes.c_size_t(1 << 20), None)
+    assert r == -1
+    thr2 = (ctypes.c_double * 2)(200.0, 500.0)
+    r = libgs.gs_lod_select_points(lv, 3, thr2, ctypes.c_void_p(dummy), 1, ctypes.c_int64(16), ctypes.c_void_p(dummy),
+                                   ctypes.c_void_p(dummy), ctypes.c_void_p(dummy), ctypes.c_void_p(dummy),
+                                   ctypes.c_size_t(8), None)
+    assert r == -3   # workspace too small
 
 
 def test_unsupported_tile_shape_rejected(libgs):

@@ -431,3 +431,221 @@ def test_graph_replay_equals_eager():
         graph.replay()
         torch.cuda.synchronize()
         np.testing.assert_array_equal(frame.rgb.cpu().numpy(), eager[-1].cpu().numpy())
+
+
+# ---------------------------------------------------------------------------
+# point-wise LoD baseline (Sec. 3.3.2 opening, Table 5)
+# ---------------------------------------------------------------------------
+def _points_select(scene, cams, thresholds=(200.0, 500.0), capacity=None):
+    V = len(cams)
+    cams_dev = gs.cameras_to_device(cams)
+    cap = capacity if capacity is not None else V * sum(lv.n for lv in scene.levels)
+    gather = torch.zeros(max(1, cap), dtype=torch.int32, device="cuda")
+    offsets = torch.zeros(V * scene.n_levels + 1, dtype=torch.int64, device="cuda")
+    counts = torch.zeros(gs.GS_COUNT_SLOTS, dtype=torch.int64, device="cuda")
+    ws = torch.empty(gs.points_workspace_bytes([lv.n for lv in scene.levels], V), dtype=torch.uint8, device="cuda")
+    gs.lod_select_points([lv.struct() for lv in scene.levels], thresholds, cams_dev, V, cap, gather, offsets, counts,
+                         ws)
+    torch.cuda.synchronize()
+    return (gather.cpu().numpy().view(np.uint32), offsets.cpu().numpy(), counts.cpu().numpy())
+
+
+def test_pointwise_select_bit_exact_batched_views():
+    bs = scaled_city(150_000, seed=41)
+    scene = render.DeviceScene.from_block_scene(bs)
+    cams = synth.city_views(seed=41, n_xy=3)
+    print("case: pointwise select, %d views" % len(cams), flush=True)
+    gather, offsets, counts = _points_select(scene, cams)
+    off_ref, g_ref = olod.pointwise_select([lv.means for lv in bs.levels], (200.0, 500.0), cams)
+    np.testing.assert_array_equal(offsets, off_ref)
+    np.testing.assert_array_equal(gather[:off_ref[-1]], g_ref)
+    assert counts[gs.GS_COUNT_RECORDS] == off_ref[-1] and counts[gs.GS_COUNT_FLAGS] == 0
+    sizes = np.diff(off_ref).reshape(len(cams), 3)
+    assert (sizes.sum(axis=0) > 0).all()   # every level contributes somewhere
+
+
+def test_pointwise_select_ragged_and_empty_levels():
+    """Level sizes that are not multiples of the work-group tile, an empty level
+    in the middle and at the end, and views that select nothing."""
+    rng = np.random.default_rng(42)
+    sets = []
+    for n in (5000, 0, 3001, 0):
+        g = synth.box_gaussians(n, seed=int(rng.integers(1 << 30)), extent=((-300, 300), (-300, 300), (0, 60)))
+        sets.append(g)
+    scene = render.DeviceScene.from_sets(sets, np.zeros((1, 4), np.int64),
+                                         np.array([[s.n for s in sets]], np.int64))
+    cams = [synth.look_camera((0.0, -250.0, 80.0), 1.5, -0.3, 320, 200),
+            synth.look_camera((0.0, 0.0, 5000.0), 0.0, math.pi / 2, 64, 64),   # looks away: nothing
+            synth.look_camera((100.0, 50.0, 40.0), 3.0, -0.2, 97, 61)]
+    thr = (100.0, 200.0, 350.0)
+    gather, offsets, counts = _points_select(scene, cams, thr)
+    off_ref, g_ref = olod.pointwise_select([s.means for s in sets], thr, cams)
+    np.testing.assert_array_equal(offsets, off_ref)
+    np.testing.assert_array_equal(gather[:off_ref[-1]], g_ref)
+    assert off_ref[-1] > 0 and off_ref[8] - off_ref[4] == 0
+
+
+def test_pointwise_capacity_overflow_sets_flag():
+    bs = scaled_city(60_000, seed=43, grid=(4, 4))
+    scene = render.DeviceScene.from_block_scene(bs)
+    cam = synth.city_views(seed=43, n_xy=2)[1]
+    off_ref, g_ref = olod.pointwise_select([lv.means for lv in bs.levels], (200.0, 500.0), [cam])
+    cap = int(off_ref[-1]) // 2
+    gather, offsets, counts = _points_select(scene, [cam], capacity=cap)
+    assert counts[gs.GS_COUNT_FLAGS] & gs.GS_FLAG_RECORDS
+    assert counts[gs.GS_COUNT_RECORDS] == off_ref[-1]
+    np.testing.assert_array_equal(offsets, off_ref)
+    np.testing.assert_array_equal(gather[:cap], g_ref[:cap])
+
+
+@pytest.mark.parametrize("view_idx", [3, 20, 41])
+def test_pointwise_frame_matches_oracle(view_idx):
+    bs = scaled_city(200_000, seed=44)
+    scene = render.DeviceScene.from_block_scene(bs)
+    cam = synth.city_views(seed=44)[view_idx]
+    print("case: pointwise frame, view", view_idx, flush=True)
+    frame = render.Frame(bs.n_blocks, 1, cam.width, cam.height, scene.max_records_per_view(), 1 << 20)
+    render.render_frame(scene, frame, gs.cameras_to_device([cam]), mode=render.LOD_POINTWISE)
+    off_ref, g_ref = olod.pointwise_select([lv.means for lv in bs.levels], (200.0, 500.0), [cam])
+    sel = olod.gather_selection(bs.levels, off_ref, g_ref, 0, 3)
+    assert frame.host_counts()["records"] == sel.opac.shape[0]
+    check_integer_parity(sel, cam, frame)
+    img, T, _ = image_np(frame)
+    compare_image(img[0], T[0], sel, cam)
+
+
+def test_pointwise_batched_views_equal_single_views():
+    bs = scaled_city(100_000, seed=45)
+    scene = render.DeviceScene.from_block_scene(bs)
+    cams = synth.city_views(seed=45, n_xy=2, width=480, height=270)
+    fb = render.Frame(bs.n_blocks, len(cams), 480, 270, len(cams) * scene.max_records_per_view(), 1 << 20)
+    render.render_frame(scene, fb, gs.cameras_to_device(cams), mode=render.LOD_POINTWISE)
+    batched = fb.rgb.cpu().numpy()
+    for v, cam in enumerate(cams):
+        f1 = render.Frame(bs.n_blocks, 1, 480, 270, scene.max_records_per_view(), 1 << 18)
+        render.render_frame(scene, f1, gs.cameras_to_device([cam]), mode=render.LOD_POINTWISE)
+        np.testing.assert_array_equal(f1.rgb[0].cpu().numpy(), batched[v])
+
+
+def test_pointwise_gradients_match_oracle():
+    """Backward through a point-wise selection: the gradient of each selected
+    Gaussian lands at its index in its level (scattered by the gather list)."""
+    bs = scaled_city(40_000, seed=46, grid=(4, 4))
+    scene = render.DeviceScene.from_block_scene(bs)
+    cam = synth.look_camera((30.0, -20.0, 150.0), 0.4, -math.pi / 3, 200, 120)
+    cams_dev = gs.cameras_to_device([cam])
+    frame = render.Frame(bs.n_blocks, 1, 200, 120, scene.max_records_per_view(), 1 << 20)
+    render.render_frame(scene, frame, cams_dev, mode=render.LOD_POINTWISE)
+    d = np.random.default_rng(7).normal(size=(1, 3, 120, 200)).astype(np.float32)
+    got = _grads_for(scene, frame, cams_dev, torch.from_numpy(d).cuda())
+    off_ref, g_ref = olod.pointwise_select([lv.means for lv in bs.levels], (200.0, 500.0), [cam])
+    sel = olod.gather_selection(bs.levels, off_ref, g_ref, 0, 3)
+    ref = oracle.render_bwd(sel, cam, d[0].astype(np.float64))
+    names = ("means", "scales", "quats", "opac", "sh")
+    for l in range(3):
+        idx = g_ref[off_ref[l]:off_ref[l + 1]].astype(np.int64)
+        want = [np.zeros_like(got[l][k]) for k in range(5)]
+        for k, name in enumerate(names):
+            want[k][..., idx] = ref[name][..., off_ref[l]:off_ref[l + 1]]
+        for k, name in enumerate(names):
+            if np.linalg.norm(want[k]) > 0:
+                err = rel_l2(got[l][k], want[k])
+                print("  level", l, name, "rel L2 %.2e" % err, flush=True)
+                assert err <= GRAD_TOL
+            else:
+                assert not np.any(got[l][k])
+
+
+# ---------------------------------------------------------------------------
+# block partition in contracted space (Sec. 3.2.2, Eq. 2)
+# ---------------------------------------------------------------------------
+from oracle import partition as opart  # noqa: E402
+
+
+def _unbounded_cloud(n, seed):
+    """City-like centres plus a heavy-tailed far field (unbounded background)."""
+    rng = np.random.default_rng(seed)
+    core = np.stack([rng.uniform(-400, 400, n), rng.uniform(-300, 300, n), rng.uniform(0, 60, n)])
+    far = rng.random(n) < 0.2
+    core[0, far] = rng.standard_cauchy(far.sum()) * 500
+    core[1, far] = rng.standard_cauchy(far.sum()) * 500
+    core[2, far] = rng.uniform(0, 200, far.sum())
+    return core.astype(np.float32)
+
+
+@pytest.mark.parametrize("n,nx,ny", [(300_001, 6, 6), (70_000, 20, 17), (1000, 3, 1), (0, 4, 4)])
+def test_partition_bit_exact(n, nx, ny):
+    means = _unbounded_cloud(n, seed=n + nx)
+    box = (-133.0, -100.0, 133.0, 100.0)   # central third of the core, in x and y
+    print("case: partition", n, nx, ny, flush=True)
+    dm = torch.from_numpy(means).cuda()
+    B = nx * ny
+    perm = torch.zeros(max(1, n), dtype=torch.int32, device="cuda")
+    bid = torch.zeros(max(1, n), dtype=torch.int32, device="cuda")
+    off = torch.zeros(B + 1, dtype=torch.int64, device="cuda")
+    cells = torch.zeros((B, 4), dtype=torch.float64, device="cuda")
+    ws = torch.empty(max(1, gs.partition_workspace_bytes(n)), dtype=torch.uint8, device="cuda")
+    gs.partition(dm, n, box, nx, ny, perm, off, ws, block_id=bid, cells=cells)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(cells.cpu().numpy(), opart.contracted_cells(nx, ny))
+    if n == 0:
+        assert (off.cpu().numpy() == 0).all()
+        return
+    p_min, p_max = opart.foreground_box(means, box[:2], box[2:])
+    b_ref, perm_ref, off_ref = opart.partition(means, p_min, p_max, nx, ny)
+    np.testing.assert_array_equal(bid[:n].cpu().numpy(), b_ref)
+    np.testing.assert_array_equal(perm[:n].cpu().numpy(), perm_ref)
+    np.testing.assert_array_equal(off.cpu().numpy(), off_ref)
+
+
+def test_gather_gaussians_is_an_exact_permutation():
+    g = synth.box_gaussians(50_001, seed=3)
+    rng = np.random.default_rng(4)
+    perm = rng.permutation(g.n)[:40_000].astype(np.int32)
+    src = render.DeviceScene.single(g).levels[0]
+    n = perm.shape[0]
+    dst = render.DeviceLevel(torch.zeros((3, n), device="cuda"), torch.zeros((3, n), device="cuda"),
+                             torch.zeros((4, n), device="cuda"), torch.zeros(n, device="cuda"),
+                             torch.zeros((16, 3, n), device="cuda"))
+    gs.gather_gaussians(src.struct(), torch.from_numpy(perm).cuda(), n,
+                        gs.grads_struct(dst.means, dst.scales, dst.quats, dst.opac, dst.sh))
+    torch.cuda.synchronize()
+    ref = g.subset(perm)
+    for a, b in zip((dst.means, dst.scales, dst.quats, dst.opac, dst.sh),
+                    (ref.means, ref.scales, ref.quats, ref.opac, ref.sh)):
+        np.testing.assert_array_equal(a.cpu().numpy(), b)
+
+
+def test_partitioned_scene_lod_select_and_frame():
+    """Cloud -> contracted 6x6 partition -> nested levels -> Eq. 6 boxes ->
+    block-wise LoD with the camera's block found in contracted space -> frame;
+    against the oracle's partition, boxes, selection and render."""
+    fine, _, u, _ = synth.city_finest(240_000, seed=47, area_m2=1.5e6, grid=(8, 8))
+    box = (-204.0, -204.0, 204.0, 204.0)   # central third of the 1225 m square
+    scene, perm = render.DeviceScene.from_partition(fine, u, box, 6, 6)
+    scene.compute_bounds(4.0)
+    p_min, p_max = opart.foreground_box(fine.means, box[:2], box[2:])
+    b_ref, perm_ref, _ = opart.partition(fine.means, p_min, p_max, 6, 6)
+    np.testing.assert_array_equal(perm, perm_ref)
+    bs = synth.block_scene_from_finest(fine, b_ref, opart.contracted_cells(6, 6), u)
+    lo_ref, hi_ref = olod.scene_bounds(bs, 4.0)
+    np.testing.assert_array_equal(scene.lo.cpu().numpy(), lo_ref)
+    np.testing.assert_array_equal(scene.hi.cpu().numpy(), hi_ref)
+    cams = synth.city_views(seed=47, n_xy=3)
+    V = len(cams)
+    frame = render.Frame(scene.n_blocks, V, 1600, 900, V * scene.max_records_per_view(), 1 << 22)
+    cams_dev = gs.cameras_to_device(cams)
+    gs.lod_select(scene.blocks_struct(), (200.0, 500.0), gs.GS_LOD_BLOCKWISE, cams_dev, V, frame.level,
+                  frame.offsets, frame.counts)
+    torch.cuda.synchronize()
+    level_ref, _ = olod.lod_select(lo_ref, hi_ref, bs.cells, (200.0, 500.0), cams, bs.lvl_cnt, (p_min, p_max))
+    np.testing.assert_array_equal(frame.level.cpu().numpy(), level_ref)
+    v = 4
+    f1 = render.Frame(scene.n_blocks, 1, 800, 450, scene.max_records_per_view(), 1 << 20)
+    cam = synth.city_views(seed=47, n_xy=3, width=800, height=450)[v]
+    render.render_frame(scene, f1, gs.cameras_to_device([cam]))
+    lv_ref, _ = olod.lod_select(lo_ref, hi_ref, bs.cells, (200.0, 500.0), [cam], bs.lvl_cnt, (p_min, p_max))
+    agg = olod.aggregate(bs, lv_ref[0])
+    check_integer_parity(agg, cam, f1)
+    img, T, _ = image_np(f1)
+    compare_image(img[0], T[0], agg, cam)

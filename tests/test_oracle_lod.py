@@ -302,3 +302,33 @@ def test_grid_partition_against_bruteforce_boxes():
     # contraction balances the counts better than a plain grid over the points' bounding box
     plain = np.histogram2d(means[0], means[1], bins=(nx, ny))[0]
     assert np.diff(off).max() < plain.max()
+
+
+def test_contracted_cells_reproduce_the_grid_blocks():
+    rng = np.random.default_rng(2)
+    means = np.stack([rng.standard_cauchy(3000) * 300, rng.standard_cauchy(3000) * 300, rng.uniform(0, 50, 3000)])
+    p_min, p_max = opart.foreground_box(means, (-200.0, -150.0), (250.0, 100.0))
+    for nx, ny in ((6, 6), (5, 4), (1, 3)):
+        b = opart.block_ids(means, p_min, p_max, nx, ny)
+        cells = opart.contracted_cells(nx, ny)
+        c = opart.contract(opart.normalise(means, p_min, p_max))
+        for k in range(0, means.shape[1], 11):
+            hit = [blk for blk in range(nx * ny)
+                   if cells[blk, 0] <= c[0, k] < cells[blk, 1] and cells[blk, 2] <= c[1, k] < cells[blk, 3]]
+            assert hit == [b[k]]
+
+
+def test_camera_block_is_found_in_contracted_space():
+    """With a contracted partition, the block "the camera is in" is the block the
+    camera centre would be assigned to as a Gaussian (the pose rule of Eq. 4)."""
+    means = np.array([[-100.0, 100.0], [-100.0, 100.0], [0.0, 40.0]])
+    p_min, p_max = opart.foreground_box(means, (-100.0, -100.0), (100.0, 100.0))
+    cells = opart.contracted_cells(4, 4)
+    cam = synth.look_camera((700.0, 20.0, 30.0), yaw=0.0, pitch=0.0, width=320, height=240)  # looks away (+x)
+    cam_block = opart.block_ids(cam.center[:, None], p_min, p_max, 4, 4)[0]
+    lo = np.array([-90.0, -90.0, 0.0])
+    hi = np.array([-80.0, -80.0, 10.0])          # behind the camera: never visible
+    got = [lod.select_block(lo, hi, cells[b], (200.0, 500.0), cam, 3, (p_min, p_max)) for b in range(16)]
+    assert [b for b in range(16) if got[b] >= 0] == [cam_block]
+    # far outside the foreground box in +x: an outer block of the grid's last column
+    assert cam_block % 4 == 3
