@@ -425,7 +425,7 @@ def pointwise_frames(args, torch, gs, render, scene, cam_slot, thresholds, W, H,
     log("point-wise LoD: %.1f FPS (%.3f ms/frame), selection %.4f ms, %.0f GB/s, %.0f records/view" %
         (pw_fps, 1e3 / pw_fps, ms, gbs, float(np.mean(sel))))
     out = {"fps": pw_fps, "ms_per_frame": 1e3 / pw_fps, "n_sel_mean": float(np.mean(sel)),
-           "select_kernel": "point_select_kernel", "select_ms": ms,
+           "select_kernels": "point_flags_kernel + point_scan_kernel + point_write_kernel", "select_ms": ms,
            "select_roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": nbytes}}
     if blockwise_fps:

@@ -7,23 +7,30 @@
 // guard band for a centred principal point).
 //
 // Output: view v's selection is L segments (level 0 first), each listing the
-// chosen Gaussians' indices within the level in ascending order.  One stable
-// single-pass compaction over the virtual array (view, level, index) writes
-// them: work-group tiles never straddle a (view, level) segment, so the
-// camera and the level are uniform per tile (scalar registers), and the
-// per-element work is three coalesced FP32 loads plus the FP64 tests in the
-// fixed operation order of the block-wise selection.
-#include "scan.h"
+// chosen Gaussians' indices within the level in ascending order.  A stable
+// compaction over the virtual array (view, level, index) in three launches,
+// no inter-work-group waits:
+//   1. flags   one work-group per tile: FP64 tests in the fixed operation
+//              order of the block-wise selection, the tile's selection bit
+//              masks and count (tiles never straddle a (view, level) segment,
+//              so camera and level are uniform per tile: scalar registers)
+//   2. scan    one work-group: exclusive prefix of the tile counts, segment
+//              offsets, record count
+//   3. write   one work-group per tile: gather indices from the bit masks
+#include "gs_common.h"
 
 namespace gs {
 namespace {
 
 constexpr int kPtThreads = 256;
-constexpr int kPtItems = 8;
-constexpr int kPtTile = kPtThreads * kPtItems;
+constexpr int kPtItems = 8;                           // elements per thread per round
+constexpr int kPtRounds = 2;                          // rounds per tile
+constexpr int kPtSlots = kPtRounds * kPtItems;        // (round, item) slots of a tile
+constexpr int kPtWaves = kPtThreads / 64;
+constexpr int kPtTile = kPtThreads * kPtSlots;        // 4096 elements per tile
 constexpr int kPtMaxLevels = 8;
+constexpr int kScanThreads = 1024;
 constexpr double kPointGuard = 0.15;
-constexpr int kPtChunk = 8;  // consecutive tiles claimed per atomic (one shared counter is a serial point)
 
 struct PointArgs {
   const float* means[kPtMaxLevels];  // [3][n_l] per level
@@ -37,16 +44,50 @@ struct PointArgs {
   double thr[kPtMaxLevels - 1];
 };
 
-__global__ void point_clear_kernel(uint64_t* __restrict__ status, int64_t n_status, uint32_t* __restrict__ counter,
-                                   int64_t* __restrict__ counts) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_status; i += stride) status[i] = 0ull;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    *counter = 0u;
-    counts[GS_COUNT_VISIBLE] = 0;
-    counts[GS_COUNT_PAIRS] = 0;
-    counts[GS_COUNT_FLAGS] = 0;
+// (view, level, first element) of tile t, uniform over the work-group
+struct TileRef {
+  int v, l;
+  int64_t i0;
+};
+__device__ __forceinline__ TileRef tile_ref(const PointArgs& a, int64_t t) {
+  TileRef r;
+  r.v = (int)(t / a.tiles_per_view);
+  int64_t tl = t - (int64_t)r.v * a.tiles_per_view;
+  int l = 0;
+  while (tl >= a.tiles[l]) {
+    tl -= a.tiles[l];
+    ++l;
   }
+  r.l = l;
+  r.i0 = tl * kPtTile;
+  return r;
+}
+
+// element of (slot, thread) in a tile: element order is (round, item, wave, lane)
+__device__ __forceinline__ int64_t slot_element(int64_t i0, int slot) {
+  return i0 + (int64_t)(slot / kPtItems) * (kPtThreads * kPtItems) + (slot % kPtItems) * kPtThreads + threadIdx.x;
+}
+
+// exclusive prefix of one u32 per thread over the work-group (thread order)
+template <int NT>
+__device__ __forceinline__ uint64_t block_prefix(uint64_t x, uint64_t* s_wave, uint64_t* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint64_t inc = x;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint64_t y = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += y;
+  }
+  if (lane == 63) s_wave[wid] = inc;
+  __syncthreads();
+  uint64_t base = 0, tot = 0;
+  for (int w = 0; w < NT / 64; ++w) {
+    const uint64_t c = s_wave[w];
+    base += w < wid ? c : 0u;
+    tot += c;
+  }
+  *total = tot;
+  __syncthreads();
+  return base + inc - x;
 }
 
 // nothing to select (every level empty): all offsets and the record count are 0
@@ -60,130 +101,143 @@ __global__ void point_empty_kernel(int64_t* __restrict__ offsets, int64_t n_off,
   }
 }
 
-__global__ void __launch_bounds__(kPtThreads) point_select_kernel(PointArgs a, uint32_t* __restrict__ gather,
-                                                                  int64_t* __restrict__ offsets,
-                                                                  uint64_t* __restrict__ status,
-                                                                  uint32_t* __restrict__ tile_counter,
-                                                                  int64_t* __restrict__ counts) {
-  __shared__ uint32_t s_cnt[kPtItems][kPtThreads / 64];
-  __shared__ uint64_t s_excl;
-  __shared__ uint32_t s_tile;
+__global__ void __launch_bounds__(kPtThreads) point_flags_kernel(PointArgs a, uint64_t* __restrict__ masks,
+                                                                 uint32_t* __restrict__ tile_count) {
+  __shared__ uint32_t s_cnt[kPtSlots * kPtWaves];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  // tiles are claimed kPtChunk at a time, in order, and done in order inside a
-  // chunk, so every predecessor a look-back waits on is owned by a running
-  // work-group that reaches it
-  int64_t t = 0, chunk_end = 0;
-  for (;;) {
-    if (t == chunk_end) {
-      if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
-      __syncthreads();
-      t = (int64_t)__builtin_amdgcn_readfirstlane(s_tile) * kPtChunk;
-      chunk_end = t + kPtChunk;
-      if (chunk_end > a.n_tiles) chunk_end = a.n_tiles;
-    }
-    if (t >= a.n_tiles) break;
-    // (view, level, tile within the level), uniform over the work-group
-    const int v = (int)(t / a.tiles_per_view);
-    int64_t tl = t - (int64_t)v * a.tiles_per_view;
-    int l = 0;
-    while (tl >= a.tiles[l]) {
-      tl -= a.tiles[l];
-      ++l;
-    }
-    const int64_t n = a.n[l];
-    const float* mean = a.means[l];
-    const gs_camera& cam = a.cams[v];
-    const double* R = cam.R;
-    const double* tc = cam.t;
-    const double C0 = -((R[0] * tc[0] + R[3] * tc[1]) + R[6] * tc[2]);
-    const double C1 = -((R[1] * tc[0] + R[4] * tc[1]) + R[7] * tc[2]);
-    const double C2 = -((R[2] * tc[0] + R[5] * tc[1]) + R[8] * tc[2]);
-    const double W = (double)cam.width, H = (double)cam.height;
-    const double ulo = -kPointGuard * W, uhi = (1.0 + kPointGuard) * W;
-    const double vlo = -kPointGuard * H, vhi = (1.0 + kPointGuard) * H;
-    const int64_t i_base = tl * kPtTile;
+  const int64_t t = blockIdx.x;
+  const TileRef tr = tile_ref(a, t);
+  const int l = tr.l;
+  const int64_t n = a.n[l];
+  const float* mean = a.means[l];
+  const gs_camera& cam = a.cams[tr.v];
+  const double* R = cam.R;
+  const double* tc = cam.t;
+  const double C0 = -((R[0] * tc[0] + R[3] * tc[1]) + R[6] * tc[2]);
+  const double C1 = -((R[1] * tc[0] + R[4] * tc[1]) + R[7] * tc[2]);
+  const double C2 = -((R[2] * tc[0] + R[5] * tc[1]) + R[8] * tc[2]);
+  const double W = (double)cam.width, H = (double)cam.height;
+  const double ulo = -kPointGuard * W, uhi = (1.0 + kPointGuard) * W;
+  const double vlo = -kPointGuard * H, vhi = (1.0 + kPointGuard) * H;
+  for (int r = 0; r < kPtRounds; ++r) {
     float px[kPtItems], py[kPtItems], pz[kPtItems];
 #pragma unroll
     for (int k = 0; k < kPtItems; ++k) {
-      const int64_t i = i_base + k * kPtThreads + threadIdx.x;
+      const int64_t i = slot_element(tr.i0, r * kPtItems + k);
       const bool ok = i < n;
       px[k] = ok ? mean[i] : 0.0f;
       py[k] = ok ? mean[n + i] : 0.0f;
       pz[k] = ok ? mean[2 * n + i] : 0.0f;
     }
-    uint64_t mask[kPtItems];
+    // level of every item first (independent chains), then the frustum test
+    // where the level matches
+    bool sel[kPtItems];
 #pragma unroll
     for (int k = 0; k < kPtItems; ++k) {
-      const int64_t i = i_base + k * kPtThreads + threadIdx.x;
-      bool sel = false;
-      if (i < n) {
+      const double dx = (double)px[k] - C0, dy = (double)py[k] - C1, dz = (double)pz[k] - C2;
+      const double d2 = (dx * dx + dy * dy) + dz * dz;
+      int lev = a.L - 1;
+      for (int q = 0; q < a.L - 1; ++q)
+        if (d2 >= a.thr[q] * a.thr[q]) --lev;
+      sel[k] = (lev == l) && (slot_element(tr.i0, r * kPtItems + k) < n);
+    }
+#pragma unroll
+    for (int k = 0; k < kPtItems; ++k) {
+      if (sel[k]) {
         const double x = (double)px[k], y = (double)py[k], z = (double)pz[k];
-        const double dx = x - C0, dy = y - C1, dz = z - C2;
-        const double d2 = (dx * dx + dy * dy) + dz * dz;
-        int lev = a.L - 1;
-        for (int q = 0; q < a.L - 1; ++q)
-          if (d2 >= a.thr[q] * a.thr[q]) --lev;
-        if (lev == l) {
-          const double zc = ((R[6] * x + R[7] * y) + R[8] * z) + tc[2];
-          if (zc > cam.znear) {
-            const double xc = ((R[0] * x + R[1] * y) + R[2] * z) + tc[0];
-            const double yc = ((R[3] * x + R[4] * y) + R[5] * z) + tc[1];
-            const double rz = 1.0 / zc;
-            const double u = cam.fx * (xc * rz) + cam.cx;
-            const double w = cam.fy * (yc * rz) + cam.cy;
-            sel = (u > ulo) && (u < uhi) && (w > vlo) && (w < vhi);
-          }
-        }
+        const double zc = ((R[6] * x + R[7] * y) + R[8] * z) + tc[2];
+        const double xc = ((R[0] * x + R[1] * y) + R[2] * z) + tc[0];
+        const double yc = ((R[3] * x + R[4] * y) + R[5] * z) + tc[1];
+        const double rz = 1.0 / zc;
+        const double u = cam.fx * (xc * rz) + cam.cx;
+        const double w = cam.fy * (yc * rz) + cam.cy;
+        sel[k] = (zc > cam.znear) && (u > ulo) && (u < uhi) && (w > vlo) && (w < vhi);
       }
-      mask[k] = __ballot(sel);
-      if (lane == 0) s_cnt[k][wid] = (uint32_t)__popcll(mask[k]);
     }
-    __syncthreads();
-    // element order inside the tile is (item, wave, lane): the prefix of this
-    // lane's item k counts all earlier items and the earlier waves of item k
-    uint32_t base[kPtItems];
-    uint32_t total = 0;
 #pragma unroll
     for (int k = 0; k < kPtItems; ++k) {
-      uint32_t before = total;
-#pragma unroll
-      for (int w = 0; w < kPtThreads / 64; ++w) {
-        const uint32_t c = s_cnt[k][w];
-        before += w < wid ? c : 0u;
-        total += c;
-      }
-      base[k] = before;
-    }
-    if (threadIdx.x < 64) {
-      const uint64_t ex = lookback64_wave(status, t, total, counts);
-      if (threadIdx.x == 0) {
-        s_excl = ex;
-        if (tl == 0) {  // first tile of segment (v, l): its start, and that of empty segments before it
-          int64_t s = (int64_t)v * a.L + l;
-          offsets[s] = (int64_t)ex;
-          for (--s; s >= 0 && a.n[s % a.L] == 0; --s) offsets[s] = (int64_t)ex;
-        }
-        if (t == a.n_tiles - 1) {
-          const int64_t all = (int64_t)(ex + total);
-          int64_t s = (int64_t)a.V * a.L;
-          offsets[s] = all;
-          for (--s; s >= 0 && a.n[s % a.L] == 0; --s) offsets[s] = all;
-          counts[GS_COUNT_RECORDS] = all;
-          if (all > a.capacity) raise_flag(counts, GS_FLAG_RECORDS);
-        }
+      const uint64_t m = __ballot(sel[k]);
+      const int slot = r * kPtItems + k;
+      if (lane == 0) {
+        masks[((int64_t)t * kPtSlots + slot) * kPtWaves + wid] = m;
+        s_cnt[slot * kPtWaves + wid] = (uint32_t)__popcll(m);
       }
     }
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    uint32_t c = 0;
+    for (int k = threadIdx.x; k < kPtSlots * kPtWaves; k += 64) c += s_cnt[k];
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if (threadIdx.x == 0) tile_count[t] = c;
+  }
+}
+
+// One work-group: exclusive prefix of the tile counts; segment (v, l) starts at
+// its first tile (an empty segment at the next segment's first tile).
+__global__ void __launch_bounds__(kScanThreads) point_scan_kernel(PointArgs a, const uint32_t* __restrict__ tile_count,
+                                                                  uint64_t* __restrict__ tile_off,
+                                                                  int64_t* __restrict__ offsets,
+                                                                  int64_t* __restrict__ counts) {
+  __shared__ uint64_t s_wave[kScanThreads / 64];
+  __shared__ uint64_t s_carry;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < a.n_tiles; base += kScanThreads) {
+    const int64_t t = base + threadIdx.x;
+    const uint64_t c = t < a.n_tiles ? tile_count[t] : 0u;
+    uint64_t tot;
+    const uint64_t ex = block_prefix<kScanThreads>(c, s_wave, &tot);
+    const uint64_t carry = s_carry;
+    if (t < a.n_tiles) tile_off[t] = carry + ex;
     __syncthreads();
-    const uint64_t ex = s_excl;
-#pragma unroll
-    for (int k = 0; k < kPtItems; ++k) {
-      if ((mask[k] >> lane) & 1ull) {
-        const int64_t pos = (int64_t)(ex + base[k] + (uint32_t)lanemask_lt_count(mask[k]));
-        if (pos < a.capacity) gather[pos] = (uint32_t)(i_base + k * kPtThreads + threadIdx.x);
-      }
-    }
+    if (threadIdx.x == 0) s_carry = carry + tot;
     __syncthreads();
-    ++t;
+  }
+  const uint64_t total = s_carry;
+  const int64_t nseg = (int64_t)a.V * a.L;
+  for (int64_t sg = threadIdx.x; sg <= nseg; sg += kScanThreads) {
+    int64_t first = a.n_tiles;
+    if (sg < nseg) {
+      const int v = (int)(sg / a.L), l = (int)(sg - (int64_t)v * a.L);
+      first = (int64_t)v * a.tiles_per_view;
+      for (int q = 0; q < l; ++q) first += a.tiles[q];
+    }
+    offsets[sg] = first < a.n_tiles ? (int64_t)tile_off[first] : (int64_t)total;
+  }
+  if (threadIdx.x == 0) {
+    counts[GS_COUNT_RECORDS] = (int64_t)total;
+    counts[GS_COUNT_VISIBLE] = 0;
+    counts[GS_COUNT_PAIRS] = 0;
+    counts[GS_COUNT_FLAGS] = (int64_t)total > a.capacity ? GS_FLAG_RECORDS : 0;
+  }
+}
+
+__global__ void __launch_bounds__(kPtThreads) point_write_kernel(PointArgs a, const uint64_t* __restrict__ masks,
+                                                                 const uint64_t* __restrict__ tile_off,
+                                                                 uint32_t* __restrict__ gather) {
+  __shared__ uint64_t s_wave[kPtWaves];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t t = blockIdx.x;
+  const TileRef tr = tile_ref(a, t);
+  // thread q owns the (slot, wave) entry q of the tile: counts in element order
+  static_assert(kPtSlots * kPtWaves <= kPtThreads, "one (slot, wave) entry per thread");
+  const int64_t mbase = (int64_t)t * kPtSlots * kPtWaves;
+  const uint64_t mine = threadIdx.x < kPtSlots * kPtWaves ? masks[mbase + threadIdx.x] : 0ull;
+  uint64_t tot;
+  const uint64_t ex = block_prefix<kPtThreads>((uint64_t)__popcll(mine), s_wave, &tot);
+  __shared__ uint64_t s_ex[kPtSlots * kPtWaves];
+  if (threadIdx.x < kPtSlots * kPtWaves) s_ex[threadIdx.x] = ex;
+  __syncthreads();
+  const uint64_t base = tile_off[t];
+#pragma unroll 4
+  for (int slot = 0; slot < kPtSlots; ++slot) {
+    const int e = slot * kPtWaves + wid;
+    const uint64_t m = masks[mbase + e];
+    if ((m >> lane) & 1ull) {
+      const int64_t pos = (int64_t)(base + s_ex[e] + lanemask_lt_count(m));
+      if (pos < a.capacity) gather[pos] = (uint32_t)slot_element(tr.i0, slot);
+    }
   }
 }
 
@@ -195,7 +249,8 @@ extern "C" size_t gs_points_workspace_bytes(const int64_t* level_sizes, int32_t 
   if (!level_sizes || n_levels <= 0 || n_levels > kPtMaxLevels || n_views <= 0) return 0;
   int64_t tpv = 0;
   for (int l = 0; l < n_levels; ++l) tpv += (level_sizes[l] + kPtTile - 1) / kPtTile;
-  return 256 + 8 * (size_t)(tpv * n_views);
+  const size_t nt = (size_t)(tpv * n_views);
+  return 256 + nt * (4 + 8 + 8 * kPtSlots * kPtWaves);  // counts, offsets, masks
 }
 
 extern "C" gs_status gs_lod_select_points(const gs_gaussians* levels, int32_t n_levels, const double* thresholds,
@@ -236,16 +291,18 @@ extern "C" gs_status gs_lod_select_points(const gs_gaussians* levels, int32_t n_
     GS_LAUNCH_CHECK();
     return GS_OK;
   }
-  uint32_t* counter = (uint32_t*)ws;
-  uint64_t* status = (uint64_t*)((char*)ws + 256);
-  const int64_t cg = (a.n_tiles + 255) / 256;
-  hipLaunchKernelGGL(point_clear_kernel, dim3((unsigned)(cg < 1024 ? cg : 1024)), dim3(256), 0, s, status, a.n_tiles,
-                     counter, counts);
+  // workspace: tile counts [n_tiles] u32, tile offsets [n_tiles] u64, masks [n_tiles][slots][waves] u64
+  char* w = (char*)ws;
+  uint64_t* masks = (uint64_t*)w;
+  uint64_t* tile_off = (uint64_t*)(w + (size_t)a.n_tiles * 8 * kPtSlots * kPtWaves);
+  uint32_t* tile_count = (uint32_t*)((char*)tile_off + (size_t)a.n_tiles * 8);
+  hipLaunchKernelGGL(point_flags_kernel, dim3((unsigned)a.n_tiles), dim3(kPtThreads), 0, s, a, masks, tile_count);
   GS_LAUNCH_CHECK();
-  const int64_t chunks = (a.n_tiles + kPtChunk - 1) / kPtChunk;
-  const int64_t grid = chunks < 2048 ? chunks : 2048;
-  hipLaunchKernelGGL(point_select_kernel, dim3((unsigned)grid), dim3(kPtThreads), 0, s, a, gather, offsets, status,
-                     counter, counts);
+  hipLaunchKernelGGL(point_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, a, (const uint32_t*)tile_count, tile_off,
+                     offsets, counts);
+  GS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(point_write_kernel, dim3((unsigned)a.n_tiles), dim3(kPtThreads), 0, s, a,
+                     (const uint64_t*)masks, (const uint64_t*)tile_off, gather);
   GS_LAUNCH_CHECK();
   return GS_OK;
 }
