@@ -64,6 +64,7 @@ def parse():
     ap.add_argument("--bwd-views", type=int, default=12, help="views used for the fwd+bwd timing")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-pointwise", action="store_true", help="skip the point-wise LoD comparator")
+    ap.add_argument("--no-reduced", action="store_true", help="skip the reduced-precision levels variant")
     ap.add_argument("--pointwise-only", action="store_true",
                     help="only the timed point-wise LoD frames (for profilers)")
     ap.add_argument("--no-bwd", action="store_true")
@@ -314,6 +315,11 @@ def workload_lod(args, torch, gs, render, synth):
         out_extra["pointwise"] = pointwise_frames(args, torch, gs, render, scene, cam_slot, thresholds, W, H,
                                                   frame.tuning, stream, fps)
 
+    # ---- reduced-precision coarse levels (binary16 attributes, fewer SH bands) ---------
+    if not args.no_reduced:
+        out_extra["reduced_precision"] = reduced_frames(args, torch, gs, render, scene, cam_slot, thresholds, W, H,
+                                                        frame.tuning, stream, fps)
+
     # ---- fwd + bwd ms/view (L1 loss against a seeded target) --------------------------
     if not args.no_bwd:
         grads = [lv.zeros_like() for lv in scene.levels]
@@ -431,6 +437,49 @@ def pointwise_frames(args, torch, gs, render, scene, cam_slot, thresholds, W, H,
     if blockwise_fps:
         out["blockwise_speedup"] = blockwise_fps / pw_fps
     return out
+
+
+def reduced_frames(args, torch, gs, render, scene, cam_slot, thresholds, W, H, tuning, stream, fp32_fps,
+                   sh_degrees=(1, 2, 3), half_levels=(0, 1)):
+    """The same block-wise LoD frames with the coarse levels stored at reduced
+    precision: binary16 attributes for levels 0 and 1, SH degrees 1 / 2 / 3 for
+    levels 0 / 1 / 2 (Sec. 3.3.1).  A different scene, so a variant beside the
+    headline, not the headline."""
+    dev = "cuda:0"
+    V = len(cam_slot)
+    rs = scene.reduced_precision(sh_degrees, half_levels)
+    f = render.Frame(scene.n_blocks, 1, W, H, scene.max_records_per_view(), 1 << 22, tuning, device=dev)
+    for v in range(V):
+        render.render_frame(rs, f, cam_slot[v], thresholds=thresholds)
+    step = lambda: [render.render_frame(rs, f, cam_slot[v], thresholds=thresholds, check=False) for v in range(V)]
+    g = graph_of(torch, step, stream)
+    step_s = timed_replays(torch, g, max(3, args.steps // 2), 1)
+    del g
+    if f.host_counts()["flags"]:
+        raise RuntimeError("capacity flag raised during the reduced-precision frames: %s" % f.host_counts())
+    blocks = rs.blocks_struct()
+    levels = [lv.struct() for lv in rs.levels]
+    pre_ms = []
+    with torch.cuda.stream(stream):
+        for v in range(V):
+            gs.lod_select(blocks, thresholds, gs.GS_LOD_BLOCKWISE, cam_slot[v], 1, f.level, f.offsets, f.counts,
+                          stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            gs.preprocess(levels, blocks, f.level, f.offsets, cam_slot[v], 1, W, H, 3, f.tuning, f.record_capacity,
+                          f.records, f.depth_keys, f.tiles_touched, f.counts, stream)
+            e1.record(stream)
+            e1.synchronize()
+            pre_ms.append(e0.elapsed_time(e1))
+    fps = V / step_s
+    stored = sum(t.numel() * t.element_size() for lv in rs.levels[:-1]
+                 for t in (lv.means, lv.scales, lv.quats, lv.opac, lv.sh))
+    log("reduced-precision levels: %.1f FPS (%.3f ms/frame), preprocess %.4f ms" %
+        (fps, 1e3 / fps, float(np.mean(pre_ms))))
+    del rs
+    return {"fps": fps, "ms_per_frame": 1e3 / fps, "speedup_vs_fp32_levels": fps / fp32_fps,
+            "preprocess_ms": float(np.mean(pre_ms)), "sh_degrees": list(sh_degrees),
+            "binary16_levels": list(half_levels), "coarse_level_bytes": int(stored)}
 
 
 def cpu_oracle_frame(scene, fine, block_id, u, cells, cams, n_sel, thresholds, synth):

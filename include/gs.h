@@ -73,17 +73,28 @@ typedef struct gs_camera {
   int32_t pad[2];
 } gs_camera;
 
-/* One detail level of the scene: device SoA arrays (see conventions). */
+/* One detail level of the scene: device SoA arrays (see conventions).
+ * Centres are always FP32.  A coarse level may store its other attributes at
+ * lower precision and fewer SH bands (Sec. 3.3.1: distant levels need less
+ * feature dimension and lower data precision):
+ *   attr_half = 1: scales, quats, opac and sh are IEEE binary16 arrays
+ *   sh_degree:     bands stored, 0..3; sh holds (sh_degree + 1)^2 coefficient
+ *                  planes [K][3][n]; a render uses min(its sh_degree, this)
+ * gs_gaussians values of zero for both fields mean FP32 with sh_degree 0, so
+ * callers set sh_degree explicitly (3 for full SH). */
 typedef struct gs_gaussians {
-  const float* means;
-  const float* scales;
-  const float* quats;
-  const float* opac;
-  const float* sh;
+  const float* means; /* [3][n] FP32 */
+  const void* scales; /* [3][n] */
+  const void* quats;  /* [4][n] */
+  const void* opac;   /* [n] */
+  const void* sh;     /* [(sh_degree+1)^2][3][n] */
   int64_t n;
+  int32_t sh_degree;
+  int32_t attr_half;
 } gs_gaussians;
 
-/* Gradient buffers with the same shapes as gs_gaussians (device, accumulated +=). */
+/* Gradient buffers with the shapes of gs_gaussians, always FP32 (device, accumulated +=);
+ * sh has the level's stored (sh_degree+1)^2 planes. */
 typedef struct gs_gaussian_grads {
   float* means;
   float* scales;
@@ -281,7 +292,8 @@ gs_status gs_partition(const float* means, int64_t n, const double* xy_box, int3
 
 /* dst = src[perm]: every attribute array of a Gaussian set gathered into a new
  * order (dst holds n Gaussians; src->n is the source count; perm entries
- * < src->n).  Used to store a partitioned set block by block. */
+ * < src->n).  Used to store a partitioned set block by block.  FP32 sets only
+ * (attr_half = 0, else GS_ERR_UNSUPPORTED); sh_degree planes are gathered. */
 gs_status gs_gather_gaussians(const gs_gaussians* src, const uint32_t* perm, int64_t n,
                               const gs_gaussian_grads* dst, void* stream);
 

@@ -274,14 +274,18 @@ extern "C" gs_status gs_gather_gaussians(const gs_gaussians* src, const uint32_t
   if (!src->means || !src->scales || !src->quats || !src->opac || !src->sh || !dst->means || !dst->scales ||
       !dst->quats || !dst->opac || !dst->sh)
     return GS_ERR_INVALID_ARG;
+  if (src->attr_half != 0) return GS_ERR_UNSUPPORTED;
+  if (src->sh_degree < 0 || src->sh_degree > 3) return GS_ERR_INVALID_ARG;
+  const int planes = (src->sh_degree + 1) * (src->sh_degree + 1);
   hipStream_t s = (hipStream_t)stream;
   const unsigned g = grid_of(n, 8192);
   const int64_t ns = src->n;
   hipLaunchKernelGGL(gather_kernel, dim3(g), dim3(256), 0, s, src->means, dst->means, 3, ns, n, perm);
-  hipLaunchKernelGGL(gather_kernel, dim3(g), dim3(256), 0, s, src->scales, dst->scales, 3, ns, n, perm);
-  hipLaunchKernelGGL(gather_kernel, dim3(g), dim3(256), 0, s, src->quats, dst->quats, 4, ns, n, perm);
-  hipLaunchKernelGGL(gather_kernel, dim3(g), dim3(256), 0, s, src->opac, dst->opac, 1, ns, n, perm);
-  hipLaunchKernelGGL(gather_kernel, dim3(g), dim3(256), 0, s, src->sh, dst->sh, 48, ns, n, perm);
+  hipLaunchKernelGGL(gather_kernel, dim3(g), dim3(256), 0, s, (const float*)src->scales, dst->scales, 3, ns, n, perm);
+  hipLaunchKernelGGL(gather_kernel, dim3(g), dim3(256), 0, s, (const float*)src->quats, dst->quats, 4, ns, n, perm);
+  hipLaunchKernelGGL(gather_kernel, dim3(g), dim3(256), 0, s, (const float*)src->opac, dst->opac, 1, ns, n, perm);
+  hipLaunchKernelGGL(gather_kernel, dim3(g), dim3(256), 0, s, (const float*)src->sh, dst->sh, 3 * planes, ns, n,
+                     perm);
   GS_LAUNCH_CHECK();
   return GS_OK;
 }

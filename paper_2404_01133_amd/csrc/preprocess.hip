@@ -58,10 +58,11 @@ __device__ __forceinline__ void preprocess_record(const PreArgs& a, int64_t g, i
     const double d0 = o.m[0] - C[0], d1 = o.m[1] - C[1], d2 = o.m[2] - C[2];
     const double dn = sqrt((d0 * d0 + d1 * d1) + d2 * d2);
     double Y[16];
-    const int nk = sh_basis(d0 / dn, d1 / dn, d2 / dn, a.sh_degree, Y);
+    const int deg = a.sh_degree < L.sh_deg ? a.sh_degree : L.sh_deg;
+    const int nk = sh_basis(d0 / dn, d1 / dn, d2 / dn, deg, Y);
     double col[3] = {0.0, 0.0, 0.0};
     for (int k = 0; k < nk; ++k)
-      for (int ch = 0; ch < 3; ++ch) col[ch] += Y[k] * (double)L.sh[(int64_t)(3 * k + ch) * L.n + gi];
+      for (int ch = 0; ch < 3; ++ch) col[ch] += Y[k] * (double)attr(L.sh, (int64_t)(3 * k + ch) * L.n + gi, L.half);
     rec.r = (float)dmax_(col[0] + 0.5, 0.0);
     rec.g = (float)dmax_(col[1] + 0.5, 0.0);
     rec.b = (float)dmax_(col[2] + 0.5, 0.0);
@@ -167,7 +168,8 @@ extern "C" gs_status gs_preprocess(const gs_gaussians* levels, const gs_blocks* 
   for (int l = 0; l < blocks->n_levels; ++l) {
     const gs_gaussians& g = levels[l];
     if (g.n < 0 || (g.n > 0 && (!g.means || !g.scales || !g.quats || !g.opac || !g.sh))) return GS_ERR_INVALID_ARG;
-    a.lv[l] = LevelPtrs{g.means, g.scales, g.quats, g.opac, g.sh, g.n};
+    if (g.sh_degree < 0 || g.sh_degree > 3 || (g.attr_half != 0 && g.attr_half != 1)) return GS_ERR_INVALID_ARG;
+    a.lv[l] = level_ptrs(g);
   }
   a.lvl_off = blocks->lvl_off;
   a.level = level;

@@ -13,12 +13,23 @@ constexpr int kMaxLevels = 8;
 
 struct LevelPtrs {
   const float* means;
-  const float* scales;
-  const float* quats;
-  const float* opac;
-  const float* sh;
+  const void* scales;
+  const void* quats;
+  const void* opac;
+  const void* sh;
   int64_t n;
+  int sh_deg;  // SH bands stored
+  bool half;   // attributes other than the centre are binary16
 };
+
+__host__ __forceinline__ LevelPtrs level_ptrs(const gs_gaussians& g) {
+  return LevelPtrs{g.means, g.scales, g.quats, g.opac, g.sh, g.n, g.sh_degree, g.attr_half != 0};
+}
+
+// attribute i of an array stored as FP32 or binary16 (widening is exact)
+__device__ __forceinline__ float attr(const void* p, int64_t i, bool half) {
+  return half ? (float)reinterpret_cast<const _Float16*>(p)[i] : reinterpret_cast<const float*>(p)[i];
+}
 
 __device__ __forceinline__ double dmin_(double a, double b) { return b < a ? b : a; }
 __device__ __forceinline__ double dmax_(double a, double b) { return a < b ? b : a; }
@@ -142,9 +153,11 @@ __device__ __forceinline__ bool project_geo(const LevelPtrs& L, int64_t gi, cons
   o.m[0] = L.means[gi];
   o.m[1] = L.means[n + gi];
   o.m[2] = L.means[2 * n + gi];
-  const float op32 = L.opac[gi];
-  const float q0f = L.quats[gi], q1f = L.quats[n + gi], q2f = L.quats[2 * n + gi], q3f = L.quats[3 * n + gi];
-  const float s0f = L.scales[gi], s1f = L.scales[n + gi], s2f = L.scales[2 * n + gi];
+  const bool h = L.half;
+  const float op32 = attr(L.opac, gi, h);
+  const float q0f = attr(L.quats, gi, h), q1f = attr(L.quats, n + gi, h), q2f = attr(L.quats, 2 * n + gi, h),
+              q3f = attr(L.quats, 3 * n + gi, h);
+  const float s0f = attr(L.scales, gi, h), s1f = attr(L.scales, n + gi, h), s2f = attr(L.scales, 2 * n + gi, h);
   o.tx = ((R[0] * o.m[0] + R[1] * o.m[1]) + R[2] * o.m[2]) + cam.t[0];
   o.ty = ((R[3] * o.m[0] + R[4] * o.m[1]) + R[5] * o.m[2]) + cam.t[1];
   o.tz = ((R[6] * o.m[0] + R[7] * o.m[1]) + R[8] * o.m[2]) + cam.t[2];

@@ -410,12 +410,13 @@ __device__ __forceinline__ void accumulate(float* p, float v) {
 // Adjoint of the SH colour, FP32, one basis term at a time (no basis arrays
 // live): dL/df_{k,c} = Y_k g_c and dL/d(direction) += (sum_c g_c f_{k,c}) grad Y_k.
 template <bool ATOMIC>
-__device__ __forceinline__ void sh_adjoint(float x, float y, float z, int deg, const float* __restrict__ sh, int64_t n,
-                                           int64_t gi, const float g[3], float* __restrict__ dsh, float gdir[3]) {
+__device__ __forceinline__ void sh_adjoint(float x, float y, float z, int deg, const void* __restrict__ sh, bool half,
+                                           int64_t n, int64_t gi, const float g[3], float* __restrict__ dsh,
+                                           float gdir[3]) {
   auto term = [&](int k, float Y, float dx, float dy, float dz) {
-    const float f0 = sh[(int64_t)(3 * k + 0) * n + gi];
-    const float f1 = sh[(int64_t)(3 * k + 1) * n + gi];
-    const float f2 = sh[(int64_t)(3 * k + 2) * n + gi];
+    const float f0 = attr(sh, (int64_t)(3 * k + 0) * n + gi, half);
+    const float f1 = attr(sh, (int64_t)(3 * k + 1) * n + gi, half);
+    const float f2 = attr(sh, (int64_t)(3 * k + 2) * n + gi, half);
     const float w = fmaf(g[0], f0, fmaf(g[1], f1, g[2] * f2));
     gdir[0] = fmaf(w, dx, gdir[0]);
     gdir[1] = fmaf(w, dy, gdir[1]);
@@ -479,7 +480,8 @@ __device__ __forceinline__ void preprocess_bwd_record(const BwdArgs& a, const Re
     const double dn = sqrt((d0 * d0 + d1 * d1) + d2 * d2);
     const float dir[3] = {(float)(d0 / dn), (float)(d1 / dn), (float)(d2 / dn)};
     float gdir[3] = {0.0f, 0.0f, 0.0f};
-    sh_adjoint<ATOMIC>(dir[0], dir[1], dir[2], a.sh_degree, L.sh, n, gi, grgb, G.sh, gdir);
+    sh_adjoint<ATOMIC>(dir[0], dir[1], dir[2], a.sh_degree < L.sh_deg ? a.sh_degree : L.sh_deg, L.sh, L.half, n, gi,
+                       grgb, G.sh, gdir);
     const float gd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
     for (int k = 0; k < 3; ++k) dm_col[k] = (double)(gdir[k] - dir[k] * gd) / dn;
   }
@@ -501,7 +503,8 @@ __device__ __forceinline__ void preprocess_bwd_record(const BwdArgs& a, const Re
 #pragma unroll
   for (int k = 0; k < 9; ++k) Rc[k] = (float)R64[k];
   // rotation of the normalised quaternion, scales
-  const float qa = L.quats[gi], qb = L.quats[n + gi], qc = L.quats[2 * n + gi], qd_ = L.quats[3 * n + gi];
+  const float qa = attr(L.quats, gi, L.half), qb = attr(L.quats, n + gi, L.half),
+              qc = attr(L.quats, 2 * n + gi, L.half), qd_ = attr(L.quats, 3 * n + gi, L.half);
   const float qinv = 1.0f / sqrtf(qa * qa + qb * qb + qc * qc + qd_ * qd_);
   const float w = qa * qinv, x = qb * qinv, y = qc * qinv, z = qd_ * qinv;
   float Rq[3][3];
@@ -514,7 +517,8 @@ __device__ __forceinline__ void preprocess_bwd_record(const BwdArgs& a, const Re
   Rq[2][0] = 2.f * (x * z - w * y);
   Rq[2][1] = 2.f * (y * z + w * x);
   Rq[2][2] = 1.f - 2.f * (x * x + y * y);
-  const float sc[3] = {L.scales[gi], L.scales[n + gi], L.scales[2 * n + gi]};
+  const float sc[3] = {attr(L.scales, gi, L.half), attr(L.scales, n + gi, L.half),
+                       attr(L.scales, 2 * n + gi, L.half)};
   float WL[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -776,7 +780,8 @@ extern "C" gs_status gs_rasterize_bwd(const void* records, const uint32_t* pair_
   BwdArgs a{};
   for (int l = 0; l < blocks->n_levels; ++l) {
     const gs_gaussians& g = levels[l];
-    a.lv[l] = LevelPtrs{g.means, g.scales, g.quats, g.opac, g.sh, g.n};
+    if (g.sh_degree < 0 || g.sh_degree > 3 || (g.attr_half != 0 && g.attr_half != 1)) return GS_ERR_INVALID_ARG;
+    a.lv[l] = level_ptrs(g);
     a.gr[l] = grads[l];
     if (g.n > 0 && (!grads[l].means || !grads[l].scales || !grads[l].quats || !grads[l].opac || !grads[l].sh))
       return GS_ERR_INVALID_ARG;

@@ -25,6 +25,11 @@ namespace gs {
 namespace {
 
 constexpr int kMaxPasses = 8;
+// the two record scans (compaction, pair offsets) use larger tiles than the
+// radix passes: their per-element work is tiny and the look-back chain is
+// (tiles / 64) rounds of device-coherent loads
+constexpr int kScanItems = 32;
+constexpr int kScanTile = kThreads * kScanItems;
 constexpr int kPersistentBlocks = 1024;
 constexpr int kBigFootprint = 16;  // records touching more tiles are emitted cooperatively
 
@@ -63,7 +68,7 @@ __global__ void __launch_bounds__(kThreads) compact_kernel(const int32_t* __rest
   __shared__ uint64_t s_excl;
   __shared__ uint32_t s_hist[4][kRadix];
   const int64_t n = count_clamped(counts, GS_COUNT_RECORDS, cap);
-  const int64_t ntiles = (n + kTile - 1) / kTile;
+  const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
   if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0) counts[GS_COUNT_VISIBLE] = 0;
   if ((int64_t)blockIdx.x >= ntiles) return;  // idle work-groups never touch the tile counter
   for (int i = threadIdx.x; i < 4 * kRadix; i += kThreads) (&s_hist[0][0])[i] = 0u;
@@ -72,11 +77,11 @@ __global__ void __launch_bounds__(kThreads) compact_kernel(const int32_t* __rest
     __syncthreads();
     const int64_t t = s_tile;
     if (t >= ntiles) break;
-    const int64_t base = t * kTile + (int64_t)threadIdx.x * kItems;
-    uint32_t f[kItems];
+    const int64_t base = t * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t f[kScanItems];
     uint32_t mine = 0;
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
+    for (int k = 0; k < kScanItems; ++k) {
       const int64_t idx = base + k;
       f[k] = (idx < n && tiles_touched[idx] > 0) ? 1u : 0u;
       mine += f[k];
@@ -93,7 +98,7 @@ __global__ void __launch_bounds__(kThreads) compact_kernel(const int32_t* __rest
     __syncthreads();
     uint64_t pos = s_excl + excl_thread;
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
+    for (int k = 0; k < kScanItems; ++k) {
       if (f[k]) {
         const int64_t idx = base + k;
         const uint32_t key = depth_keys[idx];
@@ -124,7 +129,7 @@ __global__ void __launch_bounds__(kThreads) pair_offsets_kernel(const uint32_t* 
   __shared__ uint32_t s_tile;
   __shared__ uint64_t s_excl;
   const int64_t n = count_clamped(counts, GS_COUNT_VISIBLE, cap);
-  const int64_t ntiles = (n + kTile - 1) / kTile;
+  const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
   if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0) counts[GS_COUNT_PAIRS] = 0;
   if ((int64_t)blockIdx.x >= ntiles) return;
   for (;;) {
@@ -132,11 +137,11 @@ __global__ void __launch_bounds__(kThreads) pair_offsets_kernel(const uint32_t* 
     __syncthreads();
     const int64_t t = s_tile;
     if (t >= ntiles) break;
-    const int64_t base = t * kTile + (int64_t)threadIdx.x * kItems;
-    uint32_t v[kItems];
+    const int64_t base = t * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
     uint32_t mine = 0;
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
+    for (int k = 0; k < kScanItems; ++k) {
       const int64_t idx = base + k;
       v[k] = idx < n ? (uint32_t)tiles_touched[sorted_records[idx]] : 0u;
       mine += v[k];
@@ -157,7 +162,7 @@ __global__ void __launch_bounds__(kThreads) pair_offsets_kernel(const uint32_t* 
     __syncthreads();
     uint64_t pos = s_excl + excl_thread;
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
+    for (int k = 0; k < kScanItems; ++k) {
       const int64_t idx = base + k;
       if (idx < n) pair_off[idx] = (uint32_t)(pos < 0xFFFFFFFFull ? pos : 0xFFFFFFFFull);
       pos += v[k];

@@ -43,7 +43,7 @@ class gs_camera(ctypes.Structure):
 
 class gs_gaussians(ctypes.Structure):
     _fields_ = [("means", c_void_p), ("scales", c_void_p), ("quats", c_void_p), ("opac", c_void_p),
-                ("sh", c_void_p), ("n", c_int64)]
+                ("sh", c_void_p), ("n", c_int64), ("sh_degree", c_int32), ("attr_half", c_int32)]
 
 
 class gs_gaussian_grads(ctypes.Structure):
@@ -172,16 +172,31 @@ def cameras_to_device(cams, device="cuda") -> torch.Tensor:
     return host.to(device)
 
 
+SH_PLANES = {1: 0, 4: 1, 9: 2, 16: 3}
+
+
 def gaussians_struct(means, scales, quats, opac, sh) -> gs_gaussians:
+    """Centres FP32 [3, n]; the other attributes all float32 or all float16;
+    sh [K, 3, n] with K in (1, 4, 9, 16) coefficient planes (SH degree 0..3)."""
     n = int(opac.shape[0])
-    for t, shape in ((means, (3, n)), (scales, (3, n)), (quats, (4, n)), (opac, (n,)), (sh, (16, 3, n))):
-        if tuple(t.shape) != shape or t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
-            raise ValueError("Gaussian arrays must be contiguous float32 device tensors in SoA layout; got %s %s"
-                             % (tuple(t.shape), t.dtype))
-    return gs_gaussians(means.data_ptr(), scales.data_ptr(), quats.data_ptr(), opac.data_ptr(), sh.data_ptr(), n)
+    half = scales.dtype == torch.float16
+    adt = torch.float16 if half else torch.float32
+    K = int(sh.shape[0])
+    if K not in SH_PLANES:
+        raise ValueError("sh must hold 1, 4, 9 or 16 coefficient planes, got %d" % K)
+    for t, shape, dt in ((means, (3, n), torch.float32), (scales, (3, n), adt), (quats, (4, n), adt),
+                         (opac, (n,), adt), (sh, (K, 3, n), adt)):
+        if tuple(t.shape) != shape or t.dtype != dt or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("Gaussian arrays must be contiguous device tensors in SoA layout (centres float32, "
+                             "other attributes all float32 or all float16); got %s %s" % (tuple(t.shape), t.dtype))
+    return gs_gaussians(means.data_ptr(), scales.data_ptr(), quats.data_ptr(), opac.data_ptr(), sh.data_ptr(), n,
+                        SH_PLANES[K], 1 if half else 0)
 
 
 def grads_struct(gm, gs_, gq, go, gsh) -> gs_gaussian_grads:
+    for t in (gm, gs_, gq, go, gsh):
+        if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("gradient buffers must be contiguous float32 device tensors, got %s" % (t.dtype,))
     return gs_gaussian_grads(gm.data_ptr(), gs_.data_ptr(), gq.data_ptr(), go.data_ptr(), gsh.data_ptr())
 
 

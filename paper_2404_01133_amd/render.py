@@ -40,7 +40,16 @@ class DeviceLevel:
         return gs.gaussians_struct(self.means, self.scales, self.quats, self.opac, self.sh)
 
     def zeros_like(self) -> "DeviceLevel":
-        return DeviceLevel(*(torch.zeros_like(t) for t in (self.means, self.scales, self.quats, self.opac, self.sh)))
+        """FP32 gradient buffers shaped like this level (whatever its storage precision)."""
+        return DeviceLevel(*(torch.zeros(t.shape, dtype=torch.float32, device=t.device)
+                             for t in (self.means, self.scales, self.quats, self.opac, self.sh)))
+
+    def reduced(self, sh_degree: int, half: bool) -> "DeviceLevel":
+        """Copy with `sh_degree` SH bands stored and, if `half`, every attribute but
+        the centre stored as binary16 (the storage of a coarse detail level)."""
+        k = (sh_degree + 1) ** 2
+        cast = (lambda t: t.to(torch.float16).contiguous()) if half else (lambda t: t.contiguous())
+        return DeviceLevel(self.means, cast(self.scales), cast(self.quats), cast(self.opac), cast(self.sh[:k]))
 
 
 class DeviceScene:
@@ -174,6 +183,14 @@ class DeviceScene:
         gs.mad_bounds(self.levels[-1].struct(), self.lvl_off, self.lvl_cnt, n_mad, self.lo, self.hi, max_cnt, ws,
                       stream)
         return self.lo, self.hi
+
+    def reduced_precision(self, sh_degrees=(1, 2, 3), half_levels=(0, 1)) -> "DeviceScene":
+        """Same blocks and centres; level l stores sh_degrees[l] SH bands and, for
+        l in half_levels, binary16 attributes."""
+        levels = [lv.reduced(sh_degrees[l], l in half_levels) for l, lv in enumerate(self.levels)]
+        out = DeviceScene(levels, self.lvl_off.cpu().numpy(), self.lvl_cnt_host, device=self.device)
+        out.cells, out.lo, out.hi, out.contraction = self.cells, self.lo, self.hi, self.contraction
+        return out
 
     def blocks_struct(self) -> gs.gs_blocks:
         return gs.blocks_struct(self.lo, self.hi, self.cells, self.lvl_off, self.lvl_cnt, self.contraction)

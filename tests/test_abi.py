@@ -72,9 +72,10 @@ def test_pointwise_workspace_and_threshold_checks(libgs):
 
     class Gaussians(ctypes.Structure):
         _fields_ = [("means", ctypes.c_void_p), ("scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
-                    ("opac", ctypes.c_void_p), ("sh", ctypes.c_void_p), ("n", ctypes.c_int64)]
+                    ("opac", ctypes.c_void_p), ("sh", ctypes.c_void_p), ("n", ctypes.c_int64),
+                    ("sh_degree", ctypes.c_int32), ("attr_half", ctypes.c_int32)]
     dummy = 0x1000
-    lv = (Gaussians * 3)(*[Gaussians(dummy, dummy, dummy, dummy, dummy, 10) for _ in range(3)])
+    lv = (Gaussians * 3)(*[Gaussians(dummy, dummy, dummy, dummy, dummy, 10, 3, 0) for _ in range(3)])
     thr = (ctypes.c_double * 2)(500.0, 200.0)   # descending: rejected
     r = libgs.gs_lod_select_points(lv, 3, thr, ctypes.c_void_p(dummy), 1, ctypes.c_int64(16), ctypes.c_void_p(dummy),
                                    ctypes.c_void_p(dummy), ctypes.c_void_p(dummy), ctypes.c_void_p(dummy),
@@ -85,6 +86,11 @@ def test_pointwise_workspace_and_threshold_checks(libgs):
                                    ctypes.c_void_p(dummy), ctypes.c_void_p(dummy), ctypes.c_void_p(dummy),
                                    ctypes.c_size_t(8), None)
     assert r == -3   # workspace too small
+    # gathering a binary16 set is not supported
+    half = Gaussians(dummy, dummy, dummy, dummy, dummy, 10, 3, 1)
+    r = libgs.gs_gather_gaussians(ctypes.byref(half), ctypes.c_void_p(dummy), ctypes.c_int64(10),
+                                  ctypes.byref(Gaussians(dummy, dummy, dummy, dummy, dummy, 0, 0, 0)), None)
+    assert r == -2
 
 
 def test_unsupported_tile_shape_rejected(libgs):

@@ -649,3 +649,65 @@ def test_partitioned_scene_lod_select_and_frame():
     check_integer_parity(agg, cam, f1)
     img, T, _ = image_np(f1)
     compare_image(img[0], T[0], agg, cam)
+
+
+# ---------------------------------------------------------------------------
+# reduced-precision coarse levels (Sec. 3.3.1: fewer SH bands, binary16 attributes)
+# ---------------------------------------------------------------------------
+def _host_level(lv):
+    """A device level widened to FP32 on the host (exact), SH zero-padded to 16 planes."""
+    sh = lv.sh.float().cpu().numpy()
+    pad = np.zeros((16,) + sh.shape[1:], np.float32)
+    pad[:sh.shape[0]] = sh
+    return synth.GaussianSet(lv.means.cpu().numpy(), lv.scales.float().cpu().numpy(),
+                             lv.quats.float().cpu().numpy(), lv.opac.float().cpu().numpy(), pad)
+
+
+def _scatter_agg(bs, level_row, ref, names=("means", "scales", "quats", "opac", "sh")):
+    """Per-level arrays of an aggregated-set gradient (blocks in order, chosen level each)."""
+    out = [{k: np.zeros_like(getattr(bs.levels[l], k), dtype=np.float64) for k in names} for l in range(3)]
+    pos = 0
+    for b, l in enumerate(level_row):
+        if l < 0:
+            continue
+        o, c = bs.lvl_off[b, l], bs.lvl_cnt[b, l]
+        for k in names:
+            out[l][k][..., o:o + c] = ref[k][..., pos:pos + c]
+        pos += c
+    return out
+
+
+def test_reduced_precision_levels_frame_and_gradients():
+    bs = scaled_city(60_000, seed=48, grid=(4, 4))
+    scene = render.DeviceScene.from_block_scene(bs)
+    scene.compute_bounds(4.0)
+    rs = scene.reduced_precision(sh_degrees=(1, 2, 3), half_levels=(0, 1))
+    assert rs.levels[0].sh.shape[0] == 4 and rs.levels[0].scales.dtype == torch.float16
+    lo_ref, hi_ref = olod.scene_bounds(bs, 4.0)
+    hb = synth.BlockScene(levels=[_host_level(lv) for lv in rs.levels], lvl_off=bs.lvl_off, lvl_cnt=bs.lvl_cnt,
+                          cells=bs.cells)
+    # a view that selects all three levels
+    cam = synth.look_camera((-150.0, -150.0, 120.0), 0.8, -0.5, 320, 180)
+    level_ref, _ = olod.lod_select(lo_ref, hi_ref, bs.cells, (200.0, 500.0), [cam], bs.lvl_cnt)
+    assert set(level_ref[0][level_ref[0] >= 0].tolist()) == {0, 1, 2}
+    cams_dev = gs.cameras_to_device([cam])
+    frame = render.Frame(bs.n_blocks, 1, 320, 180, scene.max_records_per_view(), 1 << 20)
+    render.render_frame(rs, frame, cams_dev)
+    agg = olod.aggregate(hb, level_ref[0])
+    check_integer_parity(agg, cam, frame)
+    img, T, _ = image_np(frame)
+    compare_image(img[0], T[0], agg, cam)
+    # gradients: binary16 storage, FP32 gradient buffers with the stored SH planes
+    d = np.random.default_rng(8).normal(size=(1, 3, 180, 320)).astype(np.float32)
+    got = _grads_for(rs, frame, cams_dev, torch.from_numpy(d).cuda())
+    ref = _scatter_agg(hb, level_ref[0], oracle.render_bwd(agg, cam, d[0].astype(np.float64)))
+    names = ("means", "scales", "quats", "opac", "sh")
+    for l in range(3):
+        K = rs.levels[l].sh.shape[0]
+        for k, name in enumerate(names):
+            want = ref[l][name][:K] if name == "sh" else ref[l][name]
+            assert got[l][k].shape == want.shape
+            if np.linalg.norm(want) > 0:
+                err = rel_l2(got[l][k], want)
+                print("  level", l, name, "rel L2 %.2e" % err, flush=True)
+                assert err <= GRAD_TOL
