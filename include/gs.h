@@ -297,6 +297,40 @@ gs_status gs_partition(const float* means, int64_t n, const double* xy_box, int3
 gs_status gs_gather_gaussians(const gs_gaussians* src, const uint32_t* perm, int64_t n,
                               const gs_gaussian_grads* dst, void* stream);
 
+/* ---- training-data assignment (Sec. 3.2.2, Eqs. 3-5) ------------------------
+ * Eq. 3 compares, per pose, the render of every block with the render without
+ * block j.  gs_lod_select_exclude selects, for view v, every block at the
+ * finest level except block exclude[v] (device int32[V]; -1 = none), no cull;
+ * outputs as gs_lod_select. */
+gs_status gs_lod_select_exclude(const gs_blocks* blocks /* host struct */, const gs_camera* cams, int32_t n_views,
+                                const int32_t* exclude, int8_t* level, int64_t* offsets, int64_t* counts,
+                                void* stream);
+
+/* Records of each selection segment that survived the preprocess cull
+ * (tiles_touched > 0): visible[p] for segment p of offsets[n_segments + 1]
+ * (device arrays).  A block with no visible record in a pose cannot change its
+ * render, so its leave-one-out render can be skipped (SSIM = 1 exactly). */
+gs_status gs_segment_visible(const int32_t* tiles_touched, const int64_t* offsets, int32_t n_segments,
+                             int64_t record_capacity, int32_t* visible, void* stream);
+
+/* SSIM (Wang et al. 2004) of image pairs: 11 x 11 Gaussian window, std 1.5,
+ * normalised, zero padding outside the image, C1 = 0.01^2, C2 = 0.03^2, mean
+ * over pixels and the three channels.  images: device [n_images][3][H][W]
+ * FP32; pairs: device int32 [n_pairs][2] image indices (an index out of range
+ * gives NaN); ssim: device float[n_pairs].  FP32 filtering, FP64 sums reduced
+ * in a fixed order (deterministic).  ws: gs_ssim_workspace_bytes(). */
+size_t gs_ssim_workspace_bytes(int32_t n_pairs, int32_t width, int32_t height);
+gs_status gs_ssim(const float* images, int32_t n_images, int32_t width, int32_t height, const int32_t* pairs,
+                  int32_t n_pairs, float* ssim, void* ws, size_t ws_bytes, void* stream);
+
+/* Eqs. 3-5 for P poses and the B blocks of `blocks`: B1 = (1 - ssim[p][j]) >
+ * eps (SSIM loss between the full render and the render without block j);
+ * B2 = the pose's camera centre lies in block j's cell (normalised and
+ * contracted first when blocks->contraction is set); B = B1 or B2.
+ * ssim: device float[P][B]; b1, b2 (may be NULL), b: device uint8[P][B]. */
+gs_status gs_assign(const gs_blocks* blocks /* host struct */, const gs_camera* cams, int32_t n_poses,
+                    const float* ssim, double eps, uint8_t* b1, uint8_t* b2, uint8_t* b, void* stream);
+
 /* Name of a status code (static string, or a thread-local buffer after GS_ERR_HIP). */
 const char* gs_status_string(gs_status status);
 

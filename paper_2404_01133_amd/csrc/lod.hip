@@ -19,12 +19,52 @@ struct LodArgs {
   const double* cell;
   const double* contraction;  // NULL, or p_min[3], p_max[3] of a contracted partition
   const int64_t* lvl_cnt;
+  const int32_t* exclude;  // kExcludeMode: per view, the block left out (-1: none)
   int32_t B, L, V, mode;
   double thr[kMaxLevels - 1];
 };
 
-__device__ int select_level(const LodArgs& a, const gs_camera& cam, int b) {
+constexpr int32_t kExcludeMode = 100;  // internal mode of gs_lod_select_exclude
+
+// camera centre of a view
+__device__ __forceinline__ void cam_centre(const gs_camera& cam, double& C0, double& C1, double& C2) {
+  const double* R = cam.R;
+  const double* t = cam.t;
+  C0 = -((R[0] * t[0] + R[3] * t[1]) + R[6] * t[2]);
+  C1 = -((R[1] * t[0] + R[4] * t[1]) + R[7] * t[2]);
+  C2 = -((R[2] * t[0] + R[5] * t[1]) + R[8] * t[2]);
+}
+
+// The camera centre in the coordinates of the block cells: world x, y, or,
+// with a contracted partition, normalised and contracted (Eq. 2) exactly as a
+// Gaussian centre is when it is assigned to a block
+__device__ __forceinline__ void cell_coords(const double* pc, double C0, double C1, double C2, double& X, double& Y) {
+  X = C0;
+  Y = C1;
+  if (!pc) return;
+  const double q0 = (2.0 * (C0 - pc[0])) / (pc[3] - pc[0]) - 1.0;
+  const double q1 = (2.0 * (C1 - pc[1])) / (pc[4] - pc[1]) - 1.0;
+  const double q2 = (2.0 * (C2 - pc[2])) / (pc[5] - pc[2]) - 1.0;
+  const double m0 = fabs(q0), m1 = fabs(q1), m2 = fabs(q2);
+  const bool nan = !(m0 == m0) || !(m1 == m1) || !(m2 == m2);
+  double nrm = m0 > m1 ? m0 : m1;
+  nrm = m2 > nrm ? m2 : nrm;
+  X = q0;
+  Y = q1;
+  if (!nan && nrm > 1.0) {
+    const double sc = 2.0 - 1.0 / nrm;
+    X = sc * (q0 / nrm);
+    Y = sc * (q1 / nrm);
+  }
+}
+
+__device__ __forceinline__ bool in_cell(const double* cl, double X, double Y) {
+  return (cl[0] <= X) && (X < cl[1]) && (cl[2] <= Y) && (Y < cl[3]);
+}
+
+__device__ int select_level(const LodArgs& a, const gs_camera& cam, int v, int b) {
   if (a.mode == GS_LOD_ALL_FINEST) return a.L - 1;
+  if (a.mode == kExcludeMode) return b == a.exclude[v] ? -1 : a.L - 1;
   const double* lo = a.lo + 3 * b;
   const double* hi = a.hi + 3 * b;
   if (!(lo[0] <= hi[0])) return -1;  // empty block
@@ -68,29 +108,11 @@ __device__ int select_level(const LodArgs& a, const gs_camera& cam, int b) {
     visible = (ix1 > ix0) && (iy1 > iy0);
   }
   // "the block where the camera is in": the camera centre's cell, in the
-  // contracted space of the partition when there is one (Eq. 2, as a Gaussian
-  // centre would be assigned)
-  double X = C0, Y = C1;
-  if (a.contraction) {
-    const double* pc = a.contraction;
-    const double q0 = (2.0 * (C0 - pc[0])) / (pc[3] - pc[0]) - 1.0;
-    const double q1 = (2.0 * (C1 - pc[1])) / (pc[4] - pc[1]) - 1.0;
-    const double q2 = (2.0 * (C2 - pc[2])) / (pc[5] - pc[2]) - 1.0;
-    const double m0 = fabs(q0), m1 = fabs(q1), m2 = fabs(q2);
-    const bool nan = !(m0 == m0) || !(m1 == m1) || !(m2 == m2);
-    double nrm = m0 > m1 ? m0 : m1;
-    nrm = m2 > nrm ? m2 : nrm;
-    X = q0;
-    Y = q1;
-    if (!nan && nrm > 1.0) {
-      const double sc = 2.0 - 1.0 / nrm;
-      X = sc * (q0 / nrm);
-      Y = sc * (q1 / nrm);
-    }
-  }
-  const double* cl = a.cell + 4 * b;
-  const bool in_cell = (cl[0] <= X) && (X < cl[1]) && (cl[2] <= Y) && (Y < cl[3]);
-  if (!(visible || in_cell)) return -1;
+  // contracted space of the partition when there is one
+  double X, Y;
+  cell_coords(a.contraction, C0, C1, C2, X, Y);
+  const bool cam_in_cell = in_cell(a.cell + 4 * b, X, Y);
+  if (!(visible || cam_in_cell)) return -1;
   int level = a.L - 1;
   for (int k = 0; k < a.L - 1; ++k)
     if (dmin2 >= a.thr[k] * a.thr[k]) --level;
@@ -113,7 +135,7 @@ __global__ void __launch_bounds__(kLodThreads) lod_select_kernel(LodArgs a, cons
     int64_t cnt = 0;
     if (p < total_pairs) {
       const int v = (int)(p / a.B), b = (int)(p % a.B);
-      const int lv = select_level(a, cams[v], b);
+      const int lv = select_level(a, cams[v], v, b);
       level_out[p] = (int8_t)lv;
       cnt = lv >= 0 ? a.lvl_cnt[(int64_t)b * a.L + lv] : 0;
     }
@@ -150,6 +172,42 @@ __global__ void __launch_bounds__(kLodThreads) lod_select_kernel(LodArgs a, cons
   }
 }
 
+// records of each selection segment that survived the cull (tiles_touched > 0)
+__global__ void __launch_bounds__(256) segment_visible_kernel(const int32_t* __restrict__ tiles_touched,
+                                                             const int64_t* __restrict__ offsets, int32_t n_seg,
+                                                             int64_t capacity, int32_t* __restrict__ visible) {
+  __shared__ int32_t s_sum[4];
+  for (int p = blockIdx.x; p < n_seg; p += gridDim.x) {
+    int64_t lo = offsets[p], hi = offsets[p + 1];
+    hi = hi < capacity ? hi : capacity;
+    int32_t c = 0;
+    for (int64_t g = lo + threadIdx.x; g < hi; g += blockDim.x) c += tiles_touched[g] > 0 ? 1 : 0;
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) visible[p] = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
+    __syncthreads();
+  }
+}
+
+// Eqs. 3-5: B1 = (1 - SSIM) > eps, B2 = the camera centre lies in the block's cell, B = B1 or B2
+__global__ void assign_kernel(const double* __restrict__ cell, const double* __restrict__ contraction, int32_t B,
+                              const gs_camera* __restrict__ cams, int32_t P, const float* __restrict__ ssim,
+                              double eps, uint8_t* __restrict__ b1, uint8_t* __restrict__ b2,
+                              uint8_t* __restrict__ b) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (int64_t)P * B) return;
+  const int p = (int)(k / B), j = (int)(k - (int64_t)p * B);
+  double C0, C1, C2, X, Y;
+  cam_centre(cams[p], C0, C1, C2);
+  cell_coords(contraction, C0, C1, C2, X, Y);
+  const bool a2 = in_cell(cell + 4 * j, X, Y);
+  const bool a1 = (1.0 - (double)ssim[k]) > eps;
+  if (b1) b1[k] = a1;
+  if (b2) b2[k] = a2;
+  b[k] = a1 || a2;
+}
+
 }  // namespace
 }  // namespace gs
 
@@ -184,6 +242,50 @@ extern "C" gs_status gs_lod_select(const gs_blocks* blocks, const double* thresh
   }
   hipLaunchKernelGGL(lod_select_kernel, dim3(1), dim3(kLodThreads), 0, (hipStream_t)stream, a, cams, level,
                      offsets, counts);
+  GS_LAUNCH_CHECK();
+  return GS_OK;
+}
+
+extern "C" gs_status gs_lod_select_exclude(const gs_blocks* blocks, const gs_camera* cams, int32_t n_views,
+                                           const int32_t* exclude, int8_t* level, int64_t* offsets, int64_t* counts,
+                                           void* stream) {
+  using namespace gs;
+  if (!blocks || !cams || !exclude || !level || !offsets || !counts || n_views <= 0) return GS_ERR_INVALID_ARG;
+  if (blocks->n_blocks <= 0 || blocks->n_levels <= 0 || blocks->n_levels > kMaxLevels || !blocks->lvl_cnt)
+    return GS_ERR_INVALID_ARG;
+  LodArgs a{};
+  a.lvl_cnt = blocks->lvl_cnt;
+  a.exclude = exclude;
+  a.B = blocks->n_blocks;
+  a.L = blocks->n_levels;
+  a.V = n_views;
+  a.mode = kExcludeMode;
+  hipLaunchKernelGGL(lod_select_kernel, dim3(1), dim3(kLodThreads), 0, (hipStream_t)stream, a, cams, level,
+                     offsets, counts);
+  GS_LAUNCH_CHECK();
+  return GS_OK;
+}
+
+extern "C" gs_status gs_segment_visible(const int32_t* tiles_touched, const int64_t* offsets, int32_t n_segments,
+                                        int64_t record_capacity, int32_t* visible, void* stream) {
+  using namespace gs;
+  if (!offsets || !visible || n_segments <= 0 || record_capacity < 0 || (record_capacity > 0 && !tiles_touched))
+    return GS_ERR_INVALID_ARG;
+  const int grid = n_segments < 4096 ? n_segments : 4096;
+  hipLaunchKernelGGL(segment_visible_kernel, dim3(grid), dim3(256), 0, (hipStream_t)stream, tiles_touched, offsets,
+                     n_segments, record_capacity, visible);
+  GS_LAUNCH_CHECK();
+  return GS_OK;
+}
+
+extern "C" gs_status gs_assign(const gs_blocks* blocks, const gs_camera* cams, int32_t n_poses, const float* ssim,
+                               double eps, uint8_t* b1, uint8_t* b2, uint8_t* b, void* stream) {
+  using namespace gs;
+  if (!blocks || !blocks->cell || !cams || !ssim || !b || n_poses <= 0 || blocks->n_blocks <= 0)
+    return GS_ERR_INVALID_ARG;
+  const int64_t n = (int64_t)n_poses * blocks->n_blocks;
+  hipLaunchKernelGGL(assign_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                     blocks->cell, blocks->contraction, blocks->n_blocks, cams, n_poses, ssim, eps, b1, b2, b);
   GS_LAUNCH_CHECK();
   return GS_OK;
 }

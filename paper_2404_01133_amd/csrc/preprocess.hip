@@ -18,7 +18,7 @@ namespace gs {
 namespace {
 
 constexpr int kPreThreads = 256;
-constexpr int kLdsOffsets = 4096;
+constexpr int kLdsOffsets = 1024;  // segment offsets staged in LDS up to this many; global memory beyond
 
 struct PreArgs {
   LevelPtrs lv[kMaxLevels];
@@ -57,12 +57,9 @@ __device__ __forceinline__ void preprocess_record(const PreArgs& a, int64_t g, i
     camera_centre(cam, C);
     const double d0 = o.m[0] - C[0], d1 = o.m[1] - C[1], d2 = o.m[2] - C[2];
     const double dn = sqrt((d0 * d0 + d1 * d1) + d2 * d2);
-    double Y[16];
     const int deg = a.sh_degree < L.sh_deg ? a.sh_degree : L.sh_deg;
-    const int nk = sh_basis(d0 / dn, d1 / dn, d2 / dn, deg, Y);
     double col[3] = {0.0, 0.0, 0.0};
-    for (int k = 0; k < nk; ++k)
-      for (int ch = 0; ch < 3; ++ch) col[ch] += Y[k] * (double)attr(L.sh, (int64_t)(3 * k + ch) * L.n + gi, L.half);
+    sh_colour(d0 / dn, d1 / dn, d2 / dn, deg, L.sh, L.half, L.n, gi, col);
     rec.r = (float)dmax_(col[0] + 0.5, 0.0);
     rec.g = (float)dmax_(col[1] + 0.5, 0.0);
     rec.b = (float)dmax_(col[2] + 0.5, 0.0);

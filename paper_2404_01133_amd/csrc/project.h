@@ -44,9 +44,8 @@ __device__ __forceinline__ int find_segment(const int64_t* __restrict__ offsets,
   return lo;
 }
 
-// Real SH basis up to degree 3 (m = -l..l, Condon-Shortley phase kept) at a unit
-// direction, and optionally its gradient with respect to (x, y, z) treated as
-// independent variables.
+// Normalisation constants of the real SH basis up to degree 3 (m = -l..l,
+// Condon-Shortley phase kept), evaluated at a unit direction below.
 constexpr double kSH00 = 0.28209479177387814;
 constexpr double kSH1 = 0.4886025119029199;
 constexpr double kSH2a = 1.0925484305920792;
@@ -58,66 +57,34 @@ constexpr double kSH3c = 0.4570457994644658;
 constexpr double kSH3d = 0.3731763325901154;
 constexpr double kSH3e = 1.445305721320277;
 
-__device__ __forceinline__ int sh_basis(double x, double y, double z, int deg, double Y[16]) {
-  Y[0] = kSH00;
-  if (deg < 1) return 1;
-  Y[1] = -kSH1 * y;
-  Y[2] = kSH1 * z;
-  Y[3] = -kSH1 * x;
-  if (deg < 2) return 4;
-  const double xx = x * x, yy = y * y, zz = z * z;
-  Y[4] = kSH2a * (x * y);
-  Y[5] = -kSH2a * (y * z);
-  Y[6] = kSH2b * (2.0 * zz - xx - yy);
-  Y[7] = -kSH2a * (x * z);
-  Y[8] = kSH2c * (xx - yy);
-  if (deg < 3) return 9;
-  Y[9] = -kSH3a * (y * (3.0 * xx - yy));
-  Y[10] = kSH3b * (x * y * z);
-  Y[11] = -kSH3c * (y * (4.0 * zz - xx - yy));
-  Y[12] = kSH3d * (z * (2.0 * zz - 3.0 * xx - 3.0 * yy));
-  Y[13] = -kSH3c * (x * (4.0 * zz - xx - yy));
-  Y[14] = kSH3e * (z * (xx - yy));
-  Y[15] = -kSH3a * (x * (xx - 3.0 * yy));
-  return 16;
-}
-
-// d Y_k / d(x, y, z) of the polynomial forms above.
-__device__ __forceinline__ void sh_basis_grad(double x, double y, double z, int deg, double dY[16][3]) {
-  dY[0][0] = dY[0][1] = dY[0][2] = 0.0;
+// Colour sum_k Y_k f_k (per channel, k ascending) with the basis terms of
+// sh_basis computed one at a time, so no basis array is live.
+__device__ __forceinline__ void sh_colour(double x, double y, double z, int deg, const void* __restrict__ sh, bool half,
+                                          int64_t n, int64_t gi, double col[3]) {
+  auto term = [&](int k, double Yk) {
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) col[ch] += Yk * (double)attr(sh, (int64_t)(3 * k + ch) * n + gi, half);
+  };
+  term(0, kSH00);
   if (deg < 1) return;
-  dY[1][0] = 0.0;   dY[1][1] = -kSH1; dY[1][2] = 0.0;
-  dY[2][0] = 0.0;   dY[2][1] = 0.0;   dY[2][2] = kSH1;
-  dY[3][0] = -kSH1; dY[3][1] = 0.0;   dY[3][2] = 0.0;
+  term(1, -kSH1 * y);
+  term(2, kSH1 * z);
+  term(3, -kSH1 * x);
   if (deg < 2) return;
-  dY[4][0] = kSH2a * y;          dY[4][1] = kSH2a * x;          dY[4][2] = 0.0;
-  dY[5][0] = 0.0;                dY[5][1] = -kSH2a * z;         dY[5][2] = -kSH2a * y;
-  dY[6][0] = -2.0 * kSH2b * x;   dY[6][1] = -2.0 * kSH2b * y;   dY[6][2] = 4.0 * kSH2b * z;
-  dY[7][0] = -kSH2a * z;         dY[7][1] = 0.0;                dY[7][2] = -kSH2a * x;
-  dY[8][0] = 2.0 * kSH2c * x;    dY[8][1] = -2.0 * kSH2c * y;   dY[8][2] = 0.0;
-  if (deg < 3) return;
   const double xx = x * x, yy = y * y, zz = z * z;
-  dY[9][0] = -6.0 * kSH3a * x * y;
-  dY[9][1] = -3.0 * kSH3a * (xx - yy);
-  dY[9][2] = 0.0;
-  dY[10][0] = kSH3b * y * z;
-  dY[10][1] = kSH3b * x * z;
-  dY[10][2] = kSH3b * x * y;
-  dY[11][0] = 2.0 * kSH3c * x * y;
-  dY[11][1] = -kSH3c * (4.0 * zz - xx - 3.0 * yy);
-  dY[11][2] = -8.0 * kSH3c * y * z;
-  dY[12][0] = -6.0 * kSH3d * x * z;
-  dY[12][1] = -6.0 * kSH3d * y * z;
-  dY[12][2] = kSH3d * (6.0 * zz - 3.0 * xx - 3.0 * yy);
-  dY[13][0] = -kSH3c * (4.0 * zz - 3.0 * xx - yy);
-  dY[13][1] = 2.0 * kSH3c * x * y;
-  dY[13][2] = -8.0 * kSH3c * x * z;
-  dY[14][0] = 2.0 * kSH3e * x * z;
-  dY[14][1] = -2.0 * kSH3e * y * z;
-  dY[14][2] = kSH3e * (xx - yy);
-  dY[15][0] = -3.0 * kSH3a * (xx - yy);
-  dY[15][1] = 6.0 * kSH3a * x * y;
-  dY[15][2] = 0.0;
+  term(4, kSH2a * (x * y));
+  term(5, -kSH2a * (y * z));
+  term(6, kSH2b * (2.0 * zz - xx - yy));
+  term(7, -kSH2a * (x * z));
+  term(8, kSH2c * (xx - yy));
+  if (deg < 3) return;
+  term(9, -kSH3a * (y * (3.0 * xx - yy)));
+  term(10, kSH3b * (x * y * z));
+  term(11, -kSH3c * (y * (4.0 * zz - xx - yy)));
+  term(12, kSH3d * (z * (2.0 * zz - 3.0 * xx - 3.0 * yy)));
+  term(13, -kSH3c * (x * (4.0 * zz - xx - yy)));
+  term(14, kSH3e * (z * (xx - yy)));
+  term(15, -kSH3a * (x * (xx - 3.0 * yy)));
 }
 
 // Everything the forward projection computes for one Gaussian.

@@ -87,6 +87,14 @@ _SIGNATURES = {
     "gs_partition": (c_int32, [c_void_p, c_int64, c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                                c_void_p, c_size_t, c_void_p]),
     "gs_gather_gaussians": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
+    "gs_lod_select_exclude": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                        c_void_p]),
+    "gs_segment_visible": (c_int32, [c_void_p, c_void_p, c_int32, c_int64, c_void_p, c_void_p]),
+    "gs_ssim_workspace_bytes": (c_size_t, [c_int32, c_int32, c_int32]),
+    "gs_ssim": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_size_t,
+                          c_void_p]),
+    "gs_assign": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_double, c_void_p, c_void_p, c_void_p,
+                            c_void_p]),
     "gs_mad_workspace_bytes": (c_size_t, [c_int64]),
     "gs_mad_bounds": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int64, c_double, c_void_p,
                                 c_void_p, c_void_p, c_size_t, c_void_p]),
@@ -286,6 +294,30 @@ def partition(means, n, xy_box, nx, ny, perm, block_off, ws, block_id=None, cell
 def gather_gaussians(src: gs_gaussians, perm, n, dst: gs_gaussian_grads, stream=None):
     _check(lib().gs_gather_gaussians(ctypes.byref(src), _p(perm), int(n), ctypes.byref(dst), _stream(stream)),
            "gs_gather_gaussians")
+
+
+def lod_select_exclude(blocks: gs_blocks, cams_dev, n_views, exclude, level, offsets, counts, stream=None):
+    _check(lib().gs_lod_select_exclude(ctypes.byref(blocks), _p(cams_dev), n_views, _p(exclude), _p(level),
+                                       _p(offsets), _p(counts), _stream(stream)), "gs_lod_select_exclude")
+
+
+def segment_visible(tiles_touched, offsets, n_segments, record_capacity, visible, stream=None):
+    _check(lib().gs_segment_visible(_p(tiles_touched), _p(offsets), n_segments, record_capacity, _p(visible),
+                                    _stream(stream)), "gs_segment_visible")
+
+
+def ssim_workspace_bytes(n_pairs, width, height) -> int:
+    return int(lib().gs_ssim_workspace_bytes(n_pairs, width, height))
+
+
+def ssim(images, n_images, width, height, pairs, n_pairs, out, ws, stream=None):
+    _check(lib().gs_ssim(_p(images), n_images, width, height, _p(pairs), n_pairs, _p(out), _p(ws),
+                         ws.numel() * ws.element_size(), _stream(stream)), "gs_ssim")
+
+
+def assign(blocks: gs_blocks, cams_dev, n_poses, ssim_vals, eps, b, b1=None, b2=None, stream=None):
+    _check(lib().gs_assign(ctypes.byref(blocks), _p(cams_dev), n_poses, _p(ssim_vals), float(eps), _p(b1), _p(b2),
+                           _p(b), _stream(stream)), "gs_assign")
 
 
 def mad_bounds(finest: gs_gaussians, lvl_off, lvl_cnt, n_mad, lo, hi, max_block_count, ws, stream=None):

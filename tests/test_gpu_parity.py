@@ -711,3 +711,75 @@ def test_reduced_precision_levels_frame_and_gradients():
                 err = rel_l2(got[l][k], want)
                 print("  level", l, name, "rel L2 %.2e" % err, flush=True)
                 assert err <= GRAD_TOL
+
+
+# ---------------------------------------------------------------------------
+# training-data assignment (Sec. 3.2.2, Eqs. 3-5)
+# ---------------------------------------------------------------------------
+from oracle import assign as oas  # noqa: E402
+from paper_2404_01133_amd import assignment  # noqa: E402
+
+
+def test_ssim_kernel_matches_oracle():
+    rng = np.random.default_rng(9)
+    W, H = 100, 70          # ragged against the 32 x 32 tiles
+    base = rng.random((3, H, W)).astype(np.float32)
+    imgs = [base, np.clip(base + rng.normal(0, 0.05, base.shape), 0, 1).astype(np.float32),
+            (0.5 * base + 0.3).astype(np.float32), np.zeros_like(base), rng.random((3, H, W)).astype(np.float32)]
+    images = torch.from_numpy(np.stack(imgs)).cuda()
+    pairs_np = np.array([[0, 0], [0, 1], [0, 2], [3, 3], [4, 0], [1, 0], [0, 7]], np.int32)
+    pairs = torch.from_numpy(pairs_np).cuda()
+    out = torch.empty(len(pairs_np), dtype=torch.float32, device="cuda")
+    ws = torch.empty(gs.ssim_workspace_bytes(len(pairs_np), W, H), dtype=torch.uint8, device="cuda")
+    gs.ssim(images, len(imgs), W, H, pairs, len(pairs_np), out, ws)
+    got = out.cpu().numpy()
+    for k, (a, b) in enumerate(pairs_np[:-1]):
+        want = oas.ssim(imgs[a].astype(np.float64), imgs[b].astype(np.float64))
+        assert abs(got[k] - want) <= 2e-5, (k, got[k], want)
+    assert np.isnan(got[-1])          # image index out of range
+    assert got[0] == 1.0 and got[3] == 1.0
+
+
+def _assignment_case():
+    fine, _, u, _ = synth.city_finest(40_000, seed=49, area_m2=1.5e6, grid=(8, 8))
+    box = (-204.0, -204.0, 204.0, 204.0)
+    scene, perm = render.DeviceScene.from_partition(fine, u, box, 3, 3, fractions=(1.0,))
+    p_min, p_max = opart.foreground_box(fine.means, box[:2], box[2:])
+    b_ref, perm_ref, off_ref = opart.partition(fine.means, p_min, p_max, 3, 3)
+    np.testing.assert_array_equal(perm, perm_ref)
+    ordered = fine.subset(perm_ref)
+    cams = [synth.look_camera((x, y, h), yaw, pitch, 160, 120)
+            for (x, y, h, yaw, pitch) in ((0.0, 0.0, 300.0, 0.3, -math.pi / 2), (-250.0, 120.0, 150.0, 1.0, -0.6),
+                                          (400.0, -300.0, 80.0, 2.4, -0.35), (2000.0, 0.0, 200.0, 3.14, -0.2))]
+    return scene, ordered, off_ref, cams, (p_min, p_max)
+
+
+def test_assignment_matches_oracle():
+    scene, ordered, off, cams, box = _assignment_case()
+    eps = 0.05   # Table S3, MatrixCity
+    got = assignment.assign_poses(scene, cams, 160, 120, eps=eps, poses_per_call=2, views_per_call=5)
+    B = 9
+    full = [oracle.render(ordered, cam)[0] for cam in cams]
+    s_ref = np.ones((len(cams), B))
+    for p, cam in enumerate(cams):
+        for j in range(B):
+            keep = np.r_[0:off[j], off[j + 1]:off[-1]]
+            img = oracle.render(ordered.subset(keep), cam)[0]
+            s_ref[p, j] = oas.ssim(full[p], img)
+    cam_block = [opart.block_ids(c.center[:, None], box[0], box[1], 3, 3)[0] for c in cams]
+    b1, b2, b = oas.assign(s_ref, cam_block, B, eps)
+    np.testing.assert_allclose(got["ssim"], s_ref, rtol=0, atol=1e-3)
+    np.testing.assert_array_equal(got["b2"], b2)
+    clear = np.abs((1.0 - s_ref) - eps) > 2e-3
+    np.testing.assert_array_equal(got["b1"][clear], b1[clear])
+    np.testing.assert_array_equal(got["b"][clear], b[clear])
+    assert b1.sum() > 0 and (~b1).sum() > 0      # both outcomes occur
+    assert got["renders"] < len(cams) * B         # blocks without visible records were skipped
+
+
+def test_assignment_skip_equals_full_computation():
+    scene, _, _, cams, _ = _assignment_case()
+    a = assignment.assign_poses(scene, cams, 160, 120, skip_invisible=True)
+    b = assignment.assign_poses(scene, cams, 160, 120, skip_invisible=False)
+    np.testing.assert_array_equal(a["b"], b["b"])
+    np.testing.assert_array_equal(a["ssim"], b["ssim"])
