@@ -389,6 +389,12 @@ def workload_lod(args, torch, gs, render, synth):
     }
     if tune_report:
         result["autotune"] = {k: tune_report[k] for k in ("best", "best_ms", "default_ms", "rejected")}
+        # fastest step per flags value (0 plain, 2 work queue, 4 two-phase, 6 both)
+        by_flags = {}
+        for r in tune_report["results"]:
+            key = str(r["flags"])
+            by_flags[key] = min(by_flags.get(key, float("inf")), r["ms"])
+        result["autotune"]["best_ms_by_flags"] = by_flags
     result.update(out_extra)
     print(json.dumps(result))
 

@@ -18,7 +18,7 @@ constexpr int kRadix = 256;
 constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagInc = 2u << 30;
 constexpr uint32_t kValMask = (1u << 30) - 1;
-constexpr int kLookWindow = 32;  // look-back words read per round by one digit's thread
+constexpr int kLookWindow = 8;  // look-back words read per round by one digit's thread
 
 // ---------------------------------------------------------------------------
 // block-level exclusive scan of one u32 per thread (256 threads, 4 waves)

@@ -25,10 +25,9 @@ namespace gs {
 namespace {
 
 constexpr int kMaxPasses = 8;
-// the two record scans (compaction, pair offsets) use larger tiles than the
-// radix passes: their per-element work is tiny and the look-back chain is
-// (tiles / 64) rounds of device-coherent loads
-constexpr int kScanItems = 32;
+// tiles of the two record scans (compaction, pair offsets); measured: 4x
+// larger tiles were slower (less parallel work), so they match the radix tiles
+constexpr int kScanItems = kItems;
 constexpr int kScanTile = kThreads * kScanItems;
 constexpr int kPersistentBlocks = 1024;
 constexpr int kBigFootprint = 16;  // records touching more tiles are emitted cooperatively

@@ -97,9 +97,12 @@ def test_two_phase_forward_bit_identical(tile, batch, flags):
     """alpha packed over the covered (Gaussian, pixel) pairs, then blended: the same
     image, transmittance and n_last as the one-phase kernel, on a dense small case
     and on LoD city frames (large and tiny footprints, long tile lists)."""
+    # n_last indexes the tile's own list, so the reference is the one-phase kernel
+    # with the same tile shape and batch
+    one = gs.tuning_struct(tile[0], tile[1], batch, flags & ~gs.GS_TUNE_TWO_PHASE)
     g, cam = synth.small_render_case(4096, seed=0)
     print("case: two-phase", tile, batch, flags, flush=True)
-    _, f0, _ = run_single(g, cam)
+    _, f0, _ = run_single(g, cam, tuning=one)
     _, f1, _ = run_single(g, cam, tuning=gs.tuning_struct(tile[0], tile[1], batch, flags))
     for a, b in ((f0.rgb, f1.rgb), (f0.T, f1.T), (f0.n_last, f1.n_last)):
         np.testing.assert_array_equal(b.cpu().numpy(), a.cpu().numpy())
@@ -108,7 +111,7 @@ def test_two_phase_forward_bit_identical(tile, batch, flags):
     scene.compute_bounds(4.0)
     for cam in synth.city_views(seed=50, n_xy=1, width=640, height=360):
         cd = gs.cameras_to_device([cam])
-        fa = render.Frame(bs.n_blocks, 1, 640, 360, scene.max_records_per_view(), 1 << 20)
+        fa = render.Frame(bs.n_blocks, 1, 640, 360, scene.max_records_per_view(), 1 << 20, one)
         fb = render.Frame(bs.n_blocks, 1, 640, 360, scene.max_records_per_view(), 1 << 20,
                           gs.tuning_struct(tile[0], tile[1], batch, flags))
         render.render_frame(scene, fa, cd)
@@ -714,7 +717,7 @@ def test_reduced_precision_levels_frame_and_gradients():
     hb = synth.BlockScene(levels=[_host_level(lv) for lv in rs.levels], lvl_off=bs.lvl_off, lvl_cnt=bs.lvl_cnt,
                           cells=bs.cells)
     # a view that selects all three levels
-    cam = synth.look_camera((-150.0, -150.0, 120.0), 0.8, -0.5, 320, 180)
+    cam = synth.look_camera((-300.0, -300.0, 50.0), 0.8, -0.2, 320, 180)
     level_ref, _ = olod.lod_select(lo_ref, hi_ref, bs.cells, (200.0, 500.0), [cam], bs.lvl_cnt)
     assert set(level_ref[0][level_ref[0] >= 0].tolist()) == {0, 1, 2}
     cams_dev = gs.cameras_to_device([cam])
