@@ -389,7 +389,7 @@ def workload_lod(args, torch, gs, render, synth):
     }
     if tune_report:
         result["autotune"] = {k: tune_report[k] for k in ("best", "best_ms", "default_ms", "rejected")}
-        # fastest step per flags value (0 plain, 2 work queue, 4 two-phase, 6 both)
+        # fastest step per flags value (0: one work-group per tile, 2: work queue)
         by_flags = {}
         for r in tune_report["results"]:
             key = str(r["flags"])

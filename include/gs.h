@@ -139,9 +139,6 @@ typedef struct gs_tuning {
 /* tuning.flags: rasterize_fwd / rasterize_bwd run as persistent kernels that take
  * tiles from a device work queue, longest tile lists first. */
 #define GS_TUNE_WORK_QUEUE 2
-/* tuning.flags: rasterize_fwd evaluates alpha only for the (Gaussian, pixel)
- * pairs each footprint covers, packed across lanes, then blends; same image. */
-#define GS_TUNE_TWO_PHASE 4
 
 /* Size in bytes of one projected record (an opaque device structure). */
 size_t gs_record_bytes(void);

@@ -1,7 +1,6 @@
 """Autotuner for the tile kernels' launch shape.
 
-Searches tile shape x LDS batch depth x work-queue mode x one- or two-phase
-forward compositing for a given workload,
+Searches tile shape x LDS batch depth x work-queue mode for a given workload,
 times every candidate on the device (HIP-graph replays timed with HIP events),
 and accepts a candidate only if its images are bit-identical to those of the
 default shape (the compositing gate makes the image independent of the tile
@@ -21,7 +20,7 @@ from . import gs
 
 TILE_SHAPES = ((16, 16), (8, 8), (16, 8), (32, 8), (32, 16))
 BATCHES = (64, 128, 256)
-QUEUE_FLAGS = (0, gs.GS_TUNE_WORK_QUEUE, gs.GS_TUNE_TWO_PHASE, gs.GS_TUNE_TWO_PHASE | gs.GS_TUNE_WORK_QUEUE)
+QUEUE_FLAGS = (0, gs.GS_TUNE_WORK_QUEUE)
 
 
 @dataclass

@@ -208,178 +208,6 @@ __global__ void __launch_bounds__(TW* TH) raster_fwd_kernel(TileArgs ta, uint32_
 }
 
 // ---------------------------------------------------------------------------
-// Two-phase forward (GS_TUNE_TWO_PHASE).  Small footprints leave most lanes of
-// an 8 x 8 wave block idle when every lane evaluates every record.  Here each
-// wave first evaluates alpha only for the (record, pixel) pairs its records
-// cover, packed 64 to an instruction (phase A, results in LDS), then blends in
-// record order with one lane per pixel, reading alpha where its pixel is
-// covered (phase B).  alpha comes from the same evaluate() on the same inputs
-// and the blend is the same sequence of operations, so every pixel is
-// bit-identical to the one-phase kernel.
-// ---------------------------------------------------------------------------
-constexpr int kEvalCap = 512;  // alpha slots per wave per round of phase A
-
-template <int TW, int TH, int BATCH>
-struct Fwd2Lds {
-  float4 w0[BATCH], w1[BATCH], w2[BATCH];
-  uint16_t list[(TW * TH) / 64][BATCH];
-  float alpha[(TW * TH) / 64][kEvalCap];
-};
-
-// overlap of a record's footprint with the wave block [x0, x0+7] x [y0, y0+7]
-struct Overlap {
-  int rx0, ry0, w, h;
-};
-__device__ __forceinline__ Overlap block_overlap(uint32_t px, uint32_t py, int x0, int y0) {
-  const int i0 = (int)(px & 0xFFFFu), i1 = i0 + (int)(px >> 16);
-  const int j0 = (int)(py & 0xFFFFu), j1 = j0 + (int)(py >> 16);
-  Overlap o;
-  o.rx0 = i0 > x0 ? i0 : x0;
-  o.ry0 = j0 > y0 ? j0 : y0;
-  o.w = (i1 < x0 + 7 ? i1 : x0 + 7) - o.rx0 + 1;
-  o.h = (j1 < y0 + 7 ? j1 : y0 + 7) - o.ry0 + 1;
-  return o;
-}
-
-template <int TW, int TH, int BATCH>
-__device__ __forceinline__ void raster_fwd2_tile(const TileArgs& ta, Fwd2Lds<TW, TH, BATCH>& lds, int tile_g,
-                                                 float bg0, float bg1, float bg2, float* __restrict__ rgb,
-                                                 float* __restrict__ T_final, int32_t* __restrict__ n_last) {
-  constexpr int NT = TW * TH;
-  const Record* __restrict__ records = ta.records;
-  const uint32_t* __restrict__ pair_records = ta.pair_records;
-  const uint32_t* __restrict__ ranges = ta.ranges;
-  const int W = ta.W, H = ta.H, tiles_x_n = ta.tiles_x_n, tiles_per_view = ta.tiles_per_view;
-  float4* s_w0 = lds.w0;
-  float4* s_w1 = lds.w1;
-  float4* s_w2 = lds.w2;
-  const int view = tile_g / tiles_per_view;
-  const int tile = tile_g - view * tiles_per_view;
-  const int tyi = tile / tiles_x_n, txi = tile - tyi * tiles_x_n;
-  const int lane = threadIdx.x & 63;
-  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const WaveBlock<TW, TH> wb(txi, tyi, wid);
-  const int i = wb.i, j = wb.j;
-  const bool inside = (i < W) && (j < H);
-  const uint32_t start = ranges[2 * tile_g], end = ranges[2 * tile_g + 1];
-  float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-  int last = 0;
-  bool done = !inside;
-  uint16_t* list = lds.list[wid];
-  float* s_alpha = lds.alpha[wid];
-  for (uint32_t b = start; b < end; b += BATCH) {
-    if (__syncthreads_and(done)) break;
-    const int nb = (int)min((uint32_t)BATCH, end - b);
-    for (int k = threadIdx.x; k < nb; k += NT) {
-      const float4* r = reinterpret_cast<const float4*>(&records[pair_records[b + k]]);
-      s_w0[k] = r[0];
-      s_w1[k] = r[1];
-      s_w2[k] = r[2];
-    }
-    __syncthreads();
-    const int cnt = wave_compact_block(s_w0, nb, wb.x0, wb.y0, list);
-    const int base_idx = (int)(b - start);
-    int t0 = 0;
-    while (t0 < cnt && __ballot(!done) != 0) {
-      // records t0 .. t0+nfit-1: overlap areas, their prefix, as many as fit in kEvalCap
-      const int tj = t0 + lane;
-      int area = 0;
-      if (tj < cnt) {
-        const float4 w0 = s_w0[list[tj]];
-        const Overlap ov = block_overlap(__float_as_uint(w0.z), __float_as_uint(w0.w), wb.x0, wb.y0);
-        area = ov.w * ov.h;
-      }
-      int inc = area;
-#pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const int y = __shfl_up(inc, off, 64);
-        if (lane >= off) inc += y;
-      }
-      const int pre = inc - area;  // first alpha slot of record tj
-      const int nfit = (int)__popcll(__ballot(tj < cnt && inc <= kEvalCap));  // >= 1: an area is <= 64
-      const int E = __shfl(inc, nfit - 1, 64);
-      // phase A: slot s -> record (binary search over the prefix held by lanes 0..nfit-1) -> pixel -> alpha
-      for (int s0 = 0; s0 < E; s0 += 64) {
-        const int sl = s0 + lane;
-        int lo = 0, hi = nfit;  // record lo starts at or before sl, record hi after
-#pragma unroll
-        for (int step = 0; step < 6; ++step) {
-          const int mid = (lo + hi) >> 1;
-          const int pm = __shfl(pre, mid, 64);
-          if (hi - lo > 1) {
-            if (pm <= sl) lo = mid;
-            else hi = mid;
-          }
-        }
-        const int plo = __shfl(pre, lo, 64);  // all lanes active here: lanes 0..nfit-1 hold the prefix
-        if (sl < E) {
-          const int k = list[t0 + lo];
-          const float4 w0 = s_w0[k], w1 = s_w1[k];
-          const uint32_t px = __float_as_uint(w0.z), py = __float_as_uint(w0.w);
-          const Overlap ov = block_overlap(px, py, wb.x0, wb.y0);
-          const int o = sl - plo;
-          const int oy = (int)((float)o / (float)ov.w);
-          const int ox = o - oy * ov.w;
-          Eval e;
-          evaluate(w0, w1, ov.rx0 + ox - (int)(px & 0xFFFFu), ov.ry0 + oy - (int)(py & 0xFFFFu), e);
-          s_alpha[sl] = e.alpha;
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      // phase B: blend in record order, one lane per pixel
-      for (int t = 0; t < nfit; ++t) {
-        const int k = __builtin_amdgcn_readfirstlane((int)list[t0 + t]);
-        const float4 w0 = s_w0[k], w2 = s_w2[k];
-        const uint32_t px = __float_as_uint(w0.z), py = __float_as_uint(w0.w);
-        int di, dj;
-        const bool in_fp = in_footprint(i, j, px, py, di, dj);
-        const Overlap ov = block_overlap(px, py, wb.x0, wb.y0);
-        const int slot = __builtin_amdgcn_readfirstlane(__shfl(pre, t, 64)) + (j - ov.ry0) * ov.w + (i - ov.rx0);
-        const float alpha = in_fp ? s_alpha[slot] : 0.0f;
-        bool use = !done && in_fp && (alpha >= kAlphaMin);
-        const float Tn = T * (1.0f - alpha);
-        const bool stop = use && (Tn < kTMin);
-        done = done || stop;
-        use = use && !stop;
-        const float aT = alpha * T;
-        C0 = use ? fmaf(w2.x, aT, C0) : C0;
-        C1 = use ? fmaf(w2.y, aT, C1) : C1;
-        C2 = use ? fmaf(w2.z, aT, C2) : C2;
-        T = use ? Tn : T;
-        last = use ? base_idx + k + 1 : last;
-        if (__ballot(!done) == 0) break;
-      }
-      __builtin_amdgcn_wave_barrier();
-      t0 += nfit;
-    }
-    __syncthreads();
-  }
-  if (inside) {
-    const int64_t plane = (int64_t)H * W;
-    const int64_t pix = (int64_t)j * W + i;
-    float* out = rgb + (int64_t)view * 3 * plane + pix;
-    out[0] = fmaf(T, bg0, C0);
-    out[plane] = fmaf(T, bg1, C1);
-    out[2 * plane] = fmaf(T, bg2, C2);
-    T_final[(int64_t)view * plane + pix] = T;
-    n_last[(int64_t)view * plane + pix] = last;
-  }
-}
-
-template <int TW, int TH, int BATCH>
-__global__ void __launch_bounds__(TW* TH) raster_fwd2_kernel(TileArgs ta, uint32_t* queue, float bg0, float bg1,
-                                                             float bg2, float* __restrict__ rgb,
-                                                             float* __restrict__ T_final,
-                                                             int32_t* __restrict__ n_last) {
-  __shared__ Fwd2Lds<TW, TH, BATCH> lds;
-  for_each_tile(ta, queue, 0, [&](int tile_g) {
-    raster_fwd2_tile<TW, TH, BATCH>(ta, lds, tile_g, bg0, bg1, bg2, rgb, T_final, n_last);
-  });
-}
-
-// ---------------------------------------------------------------------------
 // Wave64 sums of nine per-lane values at once.  At butterfly level k (partner
 // lane = lane ^ 2^k) two quantities share one register: lanes with bit k clear
 // keep the first, lanes with bit k set the second, and each lane adds the
@@ -843,22 +671,10 @@ inline dim3 tile_grid(int64_t n_tiles, bool queued) {
 }
 
 template <int TW, int TH>
-void launch_fwd(int batch, bool two_phase, const TileArgs& ta, uint32_t* queue, hipStream_t s, const float* bg,
-                float* rgb, float* T, int32_t* nl) {
+void launch_fwd(int batch, const TileArgs& ta, uint32_t* queue, hipStream_t s, const float* bg, float* rgb, float* T,
+                int32_t* nl) {
   constexpr int NT = TW * TH;
   const dim3 grid = tile_grid(ta.n_tiles, queue != nullptr);
-  if (two_phase) {
-    if (batch == 64)
-      hipLaunchKernelGGL((raster_fwd2_kernel<TW, TH, 64>), grid, dim3(NT), 0, s, ta, queue, bg[0], bg[1], bg[2], rgb,
-                         T, nl);
-    else if (batch == 128)
-      hipLaunchKernelGGL((raster_fwd2_kernel<TW, TH, 128>), grid, dim3(NT), 0, s, ta, queue, bg[0], bg[1], bg[2],
-                         rgb, T, nl);
-    else
-      hipLaunchKernelGGL((raster_fwd2_kernel<TW, TH, 256>), grid, dim3(NT), 0, s, ta, queue, bg[0], bg[1], bg[2],
-                         rgb, T, nl);
-    return;
-  }
   if (batch == 64)
     hipLaunchKernelGGL((raster_fwd_kernel<TW, TH, 64>), grid, dim3(NT), 0, s, ta, queue, bg[0], bg[1], bg[2], rgb, T,
                        nl);
@@ -909,13 +725,12 @@ extern "C" gs_status gs_rasterize_fwd(const void* records, const uint32_t* pair_
   hipStream_t s = (hipStream_t)stream;
   const TileArgs ta{(const Record*)records, pair_records, tile_ranges, width, height, tx, (int)tpv, nblocks};
   uint32_t* q = ((tuning->flags & GS_TUNE_WORK_QUEUE) && tile_queue) ? tile_queue : nullptr;
-  const bool two = (tuning->flags & GS_TUNE_TWO_PHASE) != 0;
   const int b = tuning->batch;
-  if (tw == 16 && th == 16) launch_fwd<16, 16>(b, two, ta, q, s, bg, rgb, T_final, n_last);
-  else if (tw == 8 && th == 8) launch_fwd<8, 8>(b, two, ta, q, s, bg, rgb, T_final, n_last);
-  else if (tw == 16 && th == 8) launch_fwd<16, 8>(b, two, ta, q, s, bg, rgb, T_final, n_last);
-  else if (tw == 32 && th == 8) launch_fwd<32, 8>(b, two, ta, q, s, bg, rgb, T_final, n_last);
-  else launch_fwd<32, 16>(b, two, ta, q, s, bg, rgb, T_final, n_last);
+  if (tw == 16 && th == 16) launch_fwd<16, 16>(b, ta, q, s, bg, rgb, T_final, n_last);
+  else if (tw == 8 && th == 8) launch_fwd<8, 8>(b, ta, q, s, bg, rgb, T_final, n_last);
+  else if (tw == 16 && th == 8) launch_fwd<16, 8>(b, ta, q, s, bg, rgb, T_final, n_last);
+  else if (tw == 32 && th == 8) launch_fwd<32, 8>(b, ta, q, s, bg, rgb, T_final, n_last);
+  else launch_fwd<32, 16>(b, ta, q, s, bg, rgb, T_final, n_last);
   GS_LAUNCH_CHECK();
   return GS_OK;
 }

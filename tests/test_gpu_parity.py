@@ -90,36 +90,6 @@ def test_image_bit_identical_across_tile_shapes_and_batches(tile, batch):
     np.testing.assert_array_equal(f1.T.cpu().numpy(), f0.T.cpu().numpy())
 
 
-@pytest.mark.parametrize("tile,batch,flags", [((16, 16), 256, gs.GS_TUNE_TWO_PHASE), ((8, 8), 64, gs.GS_TUNE_TWO_PHASE),
-                                              ((32, 16), 128, gs.GS_TUNE_TWO_PHASE | gs.GS_TUNE_WORK_QUEUE),
-                                              ((16, 8), 256, gs.GS_TUNE_TWO_PHASE)])
-def test_two_phase_forward_bit_identical(tile, batch, flags):
-    """alpha packed over the covered (Gaussian, pixel) pairs, then blended: the same
-    image, transmittance and n_last as the one-phase kernel, on a dense small case
-    and on LoD city frames (large and tiny footprints, long tile lists)."""
-    # n_last indexes the tile's own list, so the reference is the one-phase kernel
-    # with the same tile shape and batch
-    one = gs.tuning_struct(tile[0], tile[1], batch, flags & ~gs.GS_TUNE_TWO_PHASE)
-    g, cam = synth.small_render_case(4096, seed=0)
-    print("case: two-phase", tile, batch, flags, flush=True)
-    _, f0, _ = run_single(g, cam, tuning=one)
-    _, f1, _ = run_single(g, cam, tuning=gs.tuning_struct(tile[0], tile[1], batch, flags))
-    for a, b in ((f0.rgb, f1.rgb), (f0.T, f1.T), (f0.n_last, f1.n_last)):
-        np.testing.assert_array_equal(b.cpu().numpy(), a.cpu().numpy())
-    bs = scaled_city(200_000, seed=50)
-    scene = render.DeviceScene.from_block_scene(bs)
-    scene.compute_bounds(4.0)
-    for cam in synth.city_views(seed=50, n_xy=1, width=640, height=360):
-        cd = gs.cameras_to_device([cam])
-        fa = render.Frame(bs.n_blocks, 1, 640, 360, scene.max_records_per_view(), 1 << 20, one)
-        fb = render.Frame(bs.n_blocks, 1, 640, 360, scene.max_records_per_view(), 1 << 20,
-                          gs.tuning_struct(tile[0], tile[1], batch, flags))
-        render.render_frame(scene, fa, cd)
-        render.render_frame(scene, fb, cd)
-        for a, b in ((fa.rgb, fb.rgb), (fa.T, fb.T), (fa.n_last, fb.n_last)):
-            np.testing.assert_array_equal(b.cpu().numpy(), a.cpu().numpy())
-
-
 def test_forward_is_deterministic():
     g, cam = synth.small_render_case(4096, seed=5)
     _, f0, _ = run_single(g, cam)
