@@ -48,6 +48,31 @@ VALU_FP32_PEAK_TFLOPS = 78.6
 # alpha*T (1), colour update (3 FMA = 6)
 FLOPS_PER_EVAL = 22
 
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by a 512 MiB copy),
+# valid for the kernel sources with the given fingerprint only (see profiles/, *_hbm_traffic.md)
+MEASURED_TRAFFIC = {
+    "raster_fwd_kernel<16,16,256>": (("raster.hip", "project.h", "gs_common.h"), "83a1330c1258d585", 82.66e6),
+    "preprocess_kernel": (("preprocess.hip", "project.h", "gs_common.h"), "d3db5d1c1346d4a0", 225.97e6),
+}
+
+
+def source_fingerprint(files):
+    import hashlib
+    m = hashlib.sha256()
+    base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2404_01133_amd", "csrc")
+    for f in files:
+        with open(os.path.join(base, f), "rb") as fh:
+            m.update(fh.read())
+    return m.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch, or None if not measured for this kernel or its source changed since."""
+    if kernel not in MEASURED_TRAFFIC:
+        return None
+    files, fp, nbytes = MEASURED_TRAFFIC[kernel]
+    return nbytes if source_fingerprint(files) == fp else None
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
@@ -378,11 +403,14 @@ def workload_lod(args, torch, gs, render, synth):
         "n_sel_mean": float(n_sel.mean()), "n_vis_mean": float(n_vis.mean()), "pairs_mean": float(n_pairs.mean()),
         "roofline": {"bound": "alu", "kernel": "raster_fwd_kernel<%d,%d,%d>" % (tun.tile_w, tun.tile_h, tun.batch),
                      "achieved": ras_tflops, "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": ras_tflops / VALU_FP32_PEAK_TFLOPS, "traffic": None, "avg_launch_ms": ras_ms,
+                     "frac": ras_tflops / VALU_FP32_PEAK_TFLOPS,
+                     "traffic": measured_traffic("raster_fwd_kernel<%d,%d,%d>" % (tun.tile_w, tun.tile_h, tun.batch)),
+                     "avg_launch_ms": ras_ms,
                      "algorithmic_flops_per_launch": ras_flops, "evals_per_launch": float(np.mean(n_eval)),
                      "flops_per_eval": FLOPS_PER_EVAL},
         "roofline_preprocess": {"bound": "hbm", "kernel": "preprocess_kernel", "achieved": pre_gbs,
-                                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": pre_gbs / HBM_PEAK_GBS, "traffic": None,
+                                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": pre_gbs / HBM_PEAK_GBS,
+                                "traffic": measured_traffic("preprocess_kernel"),
                                 "avg_launch_ms": pre_ms, "algorithmic_bytes_per_launch": pre_bytes},
         "kernel_ms": {k: float(np.mean(v)) for k, v in kern_ms.items()},
         "cpu_baseline": cpu,
