@@ -19,7 +19,7 @@ import torch
 from . import gs
 
 TILE_SHAPES = ((16, 16), (8, 8), (16, 8), (32, 8), (32, 16))
-BATCHES = (64, 128, 256)
+BATCHES = (256, 128, 64)  # the first candidate is the library default 16x16 / 256
 QUEUE_FLAGS = (0, gs.GS_TUNE_WORK_QUEUE)
 
 
