@@ -154,12 +154,7 @@ __device__ __forceinline__ void raster_fwd_tile(const TileArgs& ta, FwdLds<TW, T
     const int cnt = wave_compact_block(s_w0, nb, wb.x0, wb.y0, list);
     const int base_idx = (int)(b - start);
     if (cnt > 0 && __ballot(!done) != 0) {
-      int k = __builtin_amdgcn_readfirstlane((int)list[0]);
-      float4 w0 = s_w0[k], w1 = s_w1[k], w2 = s_w2[k];
-      for (int t = 0; t < cnt; ++t) {
-        // prefetch the next compacted record while this one is blended
-        const int kn = __builtin_amdgcn_readfirstlane((int)list[t + 1 < cnt ? t + 1 : t]);
-        const float4 n0 = s_w0[kn], n1 = s_w1[kn], n2 = s_w2[kn];
+      auto blend = [&](int k, const float4& w0, const float4& w1, const float4& w2) {
         int di, dj;
         const bool in_fp = in_footprint(i, j, __float_as_uint(w0.z), __float_as_uint(w0.w), di, dj);
         Eval e;
@@ -175,11 +170,26 @@ __device__ __forceinline__ void raster_fwd_tile(const TileArgs& ta, FwdLds<TW, T
         C2 = use ? fmaf(w2.z, aT, C2) : C2;
         T = use ? Tn : T;
         last = use ? base_idx + k + 1 : last;
+      };
+      // four compacted records per trip: two LDS reads for the four indices,
+      // all records' words in flight together, one termination vote per trip
+      for (int t = 0; t < cnt; t += 4) {
+        const int nr = cnt - t < 4 ? cnt - t : 4;  // wave-uniform
+        const uint2 pr = *reinterpret_cast<const uint2*>(&list[t]);
+        const uint32_t p0 = __builtin_amdgcn_readfirstlane(pr.x), p1 = __builtin_amdgcn_readfirstlane(pr.y);
+        const int k0 = (int)(p0 & 0xFFFFu);
+        const int k1 = nr > 1 ? (int)(p0 >> 16) : k0;
+        const int k2 = nr > 2 ? (int)(p1 & 0xFFFFu) : k0;
+        const int k3 = nr > 3 ? (int)(p1 >> 16) : k0;
+        const float4 a0 = s_w0[k0], a1 = s_w1[k0], a2 = s_w2[k0];
+        const float4 b0 = s_w0[k1], b1 = s_w1[k1], b2 = s_w2[k1];
+        const float4 c0 = s_w0[k2], c1 = s_w1[k2], c2 = s_w2[k2];
+        const float4 d0 = s_w0[k3], d1 = s_w1[k3], d2 = s_w2[k3];
+        blend(k0, a0, a1, a2);
+        if (nr > 1) blend(k1, b0, b1, b2);
+        if (nr > 2) blend(k2, c0, c1, c2);
+        if (nr > 3) blend(k3, d0, d1, d2);
         if (__ballot(!done) == 0) break;
-        k = kn;
-        w0 = n0;
-        w1 = n1;
-        w2 = n2;
       }
     }
     __syncthreads();
