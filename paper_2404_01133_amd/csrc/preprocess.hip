@@ -33,15 +33,16 @@ struct PreArgs {
 };
 
 // One record: Gaussian gi of level l, seen by view v, stored at record index g.
-__device__ __forceinline__ void preprocess_record(const PreArgs& a, int64_t g, int v, int l, int64_t gi,
-                                                  Record* __restrict__ records, uint32_t* __restrict__ depth_keys,
-                                                  int32_t* __restrict__ tiles_touched) {
+template <bool HALF>
+__device__ __forceinline__ void preprocess_record_t(const PreArgs& a, int64_t g, int v, int l, int64_t gi,
+                                                    Record* __restrict__ records, uint32_t* __restrict__ depth_keys,
+                                                    int32_t* __restrict__ tiles_touched) {
   const LevelPtrs& L = a.lv[l];
   const gs_camera& cam = a.cams[v];
   Geo o;
   uint32_t key = kCulledKey;
   int32_t tt = 0;
-  if (project_geo(L, gi, cam, a.W, a.H, o)) {
+  if (project_geo<HALF>(L, gi, cam, a.W, a.H, o)) {
     tt = (o.i1 / a.tw - o.i0 / a.tw + 1) * (o.j1 / a.th - o.j0 / a.th + 1);
     key = __float_as_uint(o.depth);
     Record rec;
@@ -59,7 +60,7 @@ __device__ __forceinline__ void preprocess_record(const PreArgs& a, int64_t g, i
     const double dn = sqrt((d0 * d0 + d1 * d1) + d2 * d2);
     const int deg = a.sh_degree < L.sh_deg ? a.sh_degree : L.sh_deg;
     double col[3] = {0.0, 0.0, 0.0};
-    sh_colour(d0 / dn, d1 / dn, d2 / dn, deg, L.sh, L.half, L.n, gi, col);
+    sh_colour<HALF>(d0 / dn, d1 / dn, d2 / dn, deg, L.sh, L.n, gi, col);
     rec.r = (float)dmax_(col[0] + 0.5, 0.0);
     rec.g = (float)dmax_(col[1] + 0.5, 0.0);
     rec.b = (float)dmax_(col[2] + 0.5, 0.0);
@@ -68,6 +69,13 @@ __device__ __forceinline__ void preprocess_record(const PreArgs& a, int64_t g, i
   }
   depth_keys[g] = key;
   tiles_touched[g] = tt;
+}
+
+__device__ __forceinline__ void preprocess_record(const PreArgs& a, int64_t g, int v, int l, int64_t gi,
+                                                  Record* __restrict__ records, uint32_t* __restrict__ depth_keys,
+                                                  int32_t* __restrict__ tiles_touched) {
+  if (a.lv[l].half) preprocess_record_t<true>(a, g, v, l, gi, records, depth_keys, tiles_touched);
+  else preprocess_record_t<false>(a, g, v, l, gi, records, depth_keys, tiles_touched);
 }
 
 __device__ __forceinline__ int64_t clamp_records(const PreArgs& a, int64_t* counts) {

@@ -26,9 +26,12 @@ __host__ __forceinline__ LevelPtrs level_ptrs(const gs_gaussians& g) {
   return LevelPtrs{g.means, g.scales, g.quats, g.opac, g.sh, g.n, g.sh_degree, g.attr_half != 0};
 }
 
-// attribute i of an array stored as FP32 or binary16 (widening is exact)
-__device__ __forceinline__ float attr(const void* p, int64_t i, bool half) {
-  return half ? (float)reinterpret_cast<const _Float16*>(p)[i] : reinterpret_cast<const float*>(p)[i];
+// attribute i of an array stored as FP32 or binary16 (widening is exact); the
+// storage is a template parameter so each record's code has no per-load branch
+template <bool HALF>
+__device__ __forceinline__ float attr(const void* p, int64_t i) {
+  if constexpr (HALF) return (float)reinterpret_cast<const _Float16*>(p)[i];
+  else return reinterpret_cast<const float*>(p)[i];
 }
 
 __device__ __forceinline__ double dmin_(double a, double b) { return b < a ? b : a; }
@@ -59,11 +62,12 @@ constexpr double kSH3e = 1.445305721320277;
 
 // Colour sum_k Y_k f_k (per channel, k ascending) with the basis terms of
 // sh_basis computed one at a time, so no basis array is live.
-__device__ __forceinline__ void sh_colour(double x, double y, double z, int deg, const void* __restrict__ sh, bool half,
+template <bool HALF>
+__device__ __forceinline__ void sh_colour(double x, double y, double z, int deg, const void* __restrict__ sh,
                                           int64_t n, int64_t gi, double col[3]) {
   auto term = [&](int k, double Yk) {
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) col[ch] += Yk * (double)attr(sh, (int64_t)(3 * k + ch) * n + gi, half);
+    for (int ch = 0; ch < 3; ++ch) col[ch] += Yk * (double)attr<HALF>(sh, (int64_t)(3 * k + ch) * n + gi);
   };
   term(0, kSH00);
   if (deg < 1) return;
@@ -112,6 +116,7 @@ struct Geo {
 // Decides culling and the footprint; returns false if culled.  All 44 bytes of
 // geometry (centre, opacity, rotation, scale) are requested at once so the
 // loads overlap; the SH coefficients are read later, only for survivors.
+template <bool HALF>
 __device__ __forceinline__ bool project_geo(const LevelPtrs& L, int64_t gi, const gs_camera& cam, int W, int H,
                                             Geo& o) {
   const int64_t n = L.n;
@@ -120,11 +125,11 @@ __device__ __forceinline__ bool project_geo(const LevelPtrs& L, int64_t gi, cons
   o.m[0] = L.means[gi];
   o.m[1] = L.means[n + gi];
   o.m[2] = L.means[2 * n + gi];
-  const bool h = L.half;
-  const float op32 = attr(L.opac, gi, h);
-  const float q0f = attr(L.quats, gi, h), q1f = attr(L.quats, n + gi, h), q2f = attr(L.quats, 2 * n + gi, h),
-              q3f = attr(L.quats, 3 * n + gi, h);
-  const float s0f = attr(L.scales, gi, h), s1f = attr(L.scales, n + gi, h), s2f = attr(L.scales, 2 * n + gi, h);
+  const float op32 = attr<HALF>(L.opac, gi);
+  const float q0f = attr<HALF>(L.quats, gi), q1f = attr<HALF>(L.quats, n + gi), q2f = attr<HALF>(L.quats, 2 * n + gi),
+              q3f = attr<HALF>(L.quats, 3 * n + gi);
+  const float s0f = attr<HALF>(L.scales, gi), s1f = attr<HALF>(L.scales, n + gi),
+              s2f = attr<HALF>(L.scales, 2 * n + gi);
   o.tx = ((R[0] * o.m[0] + R[1] * o.m[1]) + R[2] * o.m[2]) + cam.t[0];
   o.ty = ((R[3] * o.m[0] + R[4] * o.m[1]) + R[5] * o.m[2]) + cam.t[1];
   o.tz = ((R[6] * o.m[0] + R[7] * o.m[1]) + R[8] * o.m[2]) + cam.t[2];

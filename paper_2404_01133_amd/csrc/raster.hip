@@ -335,15 +335,13 @@ __device__ __forceinline__ void raster_bwd_tile(const TileArgs& ta, BwdLds<TW, T
     const int base_idx = (int)(b - start);
     const int kmax = min(nb, wave_last - base_idx);  // entries past every lane's n_last are not needed
     const int cnt = kmax > 0 ? wave_compact_block(s_w0, kmax, wb.x0, wb.y0, list) : 0;
-    for (int t = 0; t < cnt; ++t) {
-      const int k = __builtin_amdgcn_readfirstlane((int)list[t]);
-      const float4 w0 = s_w0[k], w1 = s_w1[k], w2 = s_w2[k];
+    auto step = [&](int k, const float4& w0, const float4& w1, const float4& w2) {
       int di, dj;
       const bool in_fp = in_footprint(i, j, __float_as_uint(w0.z), __float_as_uint(w0.w), di, dj);
       Eval e;
       evaluate(w0, w1, di, dj, e);
       const bool use = (base_idx + k < last) && in_fp && (e.alpha >= kAlphaMin);
-      if (__ballot(use) == 0) continue;
+      if (__ballot(use) == 0) return;
       const float aT = e.alpha * T;
       const float nA0 = fmaf(w2.x, aT, A0), nA1 = fmaf(w2.y, aT, A1c), nA2 = fmaf(w2.z, aT, A2c);
       const float inv1ma = 1.0f / (1.0f - e.alpha);
@@ -369,6 +367,17 @@ __device__ __forceinline__ void raster_bwd_tile(const TileArgs& ta, BwdLds<TW, T
       T = use ? T * (1.0f - e.alpha) : T;
       const float sum = wave_sum9(c, lane);
       if (lane < kG && sum != 0.0f) atomicAdd(&s_grad[k * kG + lane], sum);
+    };
+    // two compacted records per trip, indices in one LDS read, words in flight together
+    for (int t = 0; t < cnt; t += 2) {
+      const bool two = t + 1 < cnt;  // wave-uniform
+      const uint32_t pr = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const uint32_t*>(&list[t]));
+      const int ka = (int)(pr & 0xFFFFu);
+      const int kb = two ? (int)(pr >> 16) : ka;
+      const float4 a0 = s_w0[ka], a1 = s_w1[ka], a2 = s_w2[ka];
+      const float4 b0 = s_w0[kb], b1 = s_w1[kb], b2 = s_w2[kb];
+      step(ka, a0, a1, a2);
+      if (two) step(kb, b0, b1, b2);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < nb * kG; t += NT) {
@@ -419,14 +428,13 @@ __device__ __forceinline__ void accumulate(float* p, float v) {
 
 // Adjoint of the SH colour, FP32, one basis term at a time (no basis arrays
 // live): dL/df_{k,c} = Y_k g_c and dL/d(direction) += (sum_c g_c f_{k,c}) grad Y_k.
-template <bool ATOMIC>
-__device__ __forceinline__ void sh_adjoint(float x, float y, float z, int deg, const void* __restrict__ sh, bool half,
-                                           int64_t n, int64_t gi, const float g[3], float* __restrict__ dsh,
-                                           float gdir[3]) {
+template <bool ATOMIC, bool HALF>
+__device__ __forceinline__ void sh_adjoint(float x, float y, float z, int deg, const void* __restrict__ sh, int64_t n,
+                                           int64_t gi, const float g[3], float* __restrict__ dsh, float gdir[3]) {
   auto term = [&](int k, float Y, float dx, float dy, float dz) {
-    const float f0 = attr(sh, (int64_t)(3 * k + 0) * n + gi, half);
-    const float f1 = attr(sh, (int64_t)(3 * k + 1) * n + gi, half);
-    const float f2 = attr(sh, (int64_t)(3 * k + 2) * n + gi, half);
+    const float f0 = attr<HALF>(sh, (int64_t)(3 * k + 0) * n + gi);
+    const float f1 = attr<HALF>(sh, (int64_t)(3 * k + 1) * n + gi);
+    const float f2 = attr<HALF>(sh, (int64_t)(3 * k + 2) * n + gi);
     const float w = fmaf(g[0], f0, fmaf(g[1], f1, g[2] * f2));
     gdir[0] = fmaf(w, dx, gdir[0]);
     gdir[1] = fmaf(w, dy, gdir[1]);
@@ -460,10 +468,10 @@ __device__ __forceinline__ void sh_adjoint(float x, float y, float z, int deg, c
   term(15, -k3a * x * (xx - 3.f * yy), -3.f * k3a * (xx - yy), 6.f * k3a * x * y, 0.f);
 }
 
-template <bool ATOMIC>
-__device__ __forceinline__ void preprocess_bwd_record(const BwdArgs& a, const Record* __restrict__ records,
-                                                      const float* __restrict__ grad2d, int64_t g, int v, int l,
-                                                      int64_t gi) {
+template <bool ATOMIC, bool HALF>
+__device__ __forceinline__ void preprocess_bwd_record_t(const BwdArgs& a, const Record* __restrict__ records,
+                                                        const float* __restrict__ grad2d, int64_t g, int v, int l,
+                                                        int64_t gi) {
   float p2[kG];
   bool any = false;
 #pragma unroll
@@ -490,8 +498,8 @@ __device__ __forceinline__ void preprocess_bwd_record(const BwdArgs& a, const Re
     const double dn = sqrt((d0 * d0 + d1 * d1) + d2 * d2);
     const float dir[3] = {(float)(d0 / dn), (float)(d1 / dn), (float)(d2 / dn)};
     float gdir[3] = {0.0f, 0.0f, 0.0f};
-    sh_adjoint<ATOMIC>(dir[0], dir[1], dir[2], a.sh_degree < L.sh_deg ? a.sh_degree : L.sh_deg, L.sh, L.half, n, gi,
-                       grgb, G.sh, gdir);
+    sh_adjoint<ATOMIC, HALF>(dir[0], dir[1], dir[2], a.sh_degree < L.sh_deg ? a.sh_degree : L.sh_deg, L.sh, n, gi,
+                             grgb, G.sh, gdir);
     const float gd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
     for (int k = 0; k < 3; ++k) dm_col[k] = (double)(gdir[k] - dir[k] * gd) / dn;
   }
@@ -513,8 +521,8 @@ __device__ __forceinline__ void preprocess_bwd_record(const BwdArgs& a, const Re
 #pragma unroll
   for (int k = 0; k < 9; ++k) Rc[k] = (float)R64[k];
   // rotation of the normalised quaternion, scales
-  const float qa = attr(L.quats, gi, L.half), qb = attr(L.quats, n + gi, L.half),
-              qc = attr(L.quats, 2 * n + gi, L.half), qd_ = attr(L.quats, 3 * n + gi, L.half);
+  const float qa = attr<HALF>(L.quats, gi), qb = attr<HALF>(L.quats, n + gi), qc = attr<HALF>(L.quats, 2 * n + gi),
+              qd_ = attr<HALF>(L.quats, 3 * n + gi);
   const float qinv = 1.0f / sqrtf(qa * qa + qb * qb + qc * qc + qd_ * qd_);
   const float w = qa * qinv, x = qb * qinv, y = qc * qinv, z = qd_ * qinv;
   float Rq[3][3];
@@ -527,8 +535,7 @@ __device__ __forceinline__ void preprocess_bwd_record(const BwdArgs& a, const Re
   Rq[2][0] = 2.f * (x * z - w * y);
   Rq[2][1] = 2.f * (y * z + w * x);
   Rq[2][2] = 1.f - 2.f * (x * x + y * y);
-  const float sc[3] = {attr(L.scales, gi, L.half), attr(L.scales, n + gi, L.half),
-                       attr(L.scales, 2 * n + gi, L.half)};
+  const float sc[3] = {attr<HALF>(L.scales, gi), attr<HALF>(L.scales, n + gi), attr<HALF>(L.scales, 2 * n + gi)};
   float WL[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -625,6 +632,14 @@ __device__ __forceinline__ void preprocess_bwd_record(const BwdArgs& a, const Re
   }
   for (int k = 0; k < 4; ++k) accumulate<ATOMIC>(&G.quats[k * n + gi], gq[k]);
   accumulate<ATOMIC>(&G.opac[gi], p2[3]);
+}
+
+template <bool ATOMIC>
+__device__ __forceinline__ void preprocess_bwd_record(const BwdArgs& a, const Record* __restrict__ records,
+                                                      const float* __restrict__ grad2d, int64_t g, int v, int l,
+                                                      int64_t gi) {
+  if (a.lv[l].half) preprocess_bwd_record_t<ATOMIC, true>(a, records, grad2d, g, v, l, gi);
+  else preprocess_bwd_record_t<ATOMIC, false>(a, records, grad2d, g, v, l, gi);
 }
 
 // View-major: records in index order (FP32 atomics when views may share Gaussians).
