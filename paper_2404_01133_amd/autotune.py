@@ -87,13 +87,14 @@ def time_graph(run, reps=3, warmup=1, stream=None) -> float:
     return e0.elapsed_time(e1) / reps
 
 
-def tune(key: str, make_runner, search=None, reps=3, use_cache=True, log=None):
+def tune(key: str, make_runner, search=None, reps=3, use_cache=True, log=None, stream=None):
     """Pick the fastest launch shape for a workload.
 
     make_runner(candidate) -> (run, images): `run()` issues the workload on the
     current stream without host synchronisation; `images()` returns the output
     images (a tensor) after a run.  The first candidate of `search` is the
-    reference for the bit-identity gate.  Returns (best Candidate, report)."""
+    reference for the bit-identity gate.  All candidates are timed on `stream`
+    (one new stream if None).  Returns (best Candidate, report)."""
     dev = torch.cuda.get_device_name(torch.cuda.current_device())
     ckey = "%s|%s" % (dev, key)
     cache = _load_cache() if use_cache else {}
@@ -101,11 +102,12 @@ def tune(key: str, make_runner, search=None, reps=3, use_cache=True, log=None):
         c = cache[ckey]["best"]
         return Candidate(c["tile_w"], c["tile_h"], c["batch"], c["flags"]), cache[ckey]
     search = search or candidates()
+    stream = stream or torch.cuda.Stream()
     ref = None
     results = []
     for cand in search:
         run, images = make_runner(cand)
-        ms = time_graph(run, reps=reps)
+        ms = time_graph(run, reps=reps, stream=stream)
         run()
         torch.cuda.synchronize()
         img = images()
