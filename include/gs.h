@@ -234,7 +234,10 @@ gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys, const int
  * entry that would take the transmittance below 1e-4.
  *   bg: host float[3] background colour.
  *   tile_queue: NULL (one work-group per tile), or the queue gs_bin_sort filled
- *     with GS_TUNE_WORK_QUEUE (persistent work-groups take tiles from it). */
+ *     with GS_TUNE_WORK_QUEUE (persistent work-groups take tiles from it, using
+ *     the first head counter; the last work-group to finish puts it back to
+ *     zero, so the call can be repeated on the same sorted frame).  Two calls
+ *     that share a queue must not overlap in time (same stream, or ordered). */
 gs_status gs_rasterize_fwd(const void* records, const uint32_t* pair_records, const uint32_t* tile_ranges,
                            uint32_t* tile_queue, int32_t n_views, int32_t width, int32_t height, const float* bg,
                            const gs_tuning* tuning, float* rgb, float* T_final, int32_t* n_last, void* stream);
@@ -245,7 +248,8 @@ gs_status gs_rasterize_fwd(const void* records, const uint32_t* pair_records, co
  * blend state of each pixel is recomputed front to back from the saved T_final
  * and n_last, so no per-(pixel, Gaussian) state is stored.  Accumulation uses
  * FP32 atomics: results are reproducible to rounding, not bit for bit.
- * tile_queue: as for gs_rasterize_fwd (uses the second head counter).
+ * tile_queue: as for gs_rasterize_fwd (uses the second head counter, reset the same
+ *   way, so several backward calls may follow one forward).
  * level / offsets / gather: the selection passed to gs_preprocess.
  * ws: at least gs_workspace_bytes(GS_WS_RASTERIZE_BWD, ...). */
 gs_status gs_rasterize_bwd(const void* records, const uint32_t* pair_records, const uint32_t* tile_ranges,

@@ -100,6 +100,12 @@ struct TileArgs {
 // Work distribution shared by the tile kernels: either one work-group per tile
 // (queue == nullptr) or persistent work-groups taking tiles from the device
 // queue built by bin_sort, longest lists first.
+//
+// Every work-group ends on exactly one fetch past the end, so those fetches
+// return n_tiles .. n_tiles + gridDim.x - 1; the work-group that draws the last
+// of them knows no other will read the head again and puts it back to zero.
+// A second launch on the same sorted frame (a repeated forward, a second
+// backward) therefore walks the whole queue again.
 template <class Body>
 __device__ __forceinline__ void for_each_tile(const TileArgs& t, uint32_t* queue, int head, Body body) {
   if (queue == nullptr) {
@@ -112,7 +118,10 @@ __device__ __forceinline__ void for_each_tile(const TileArgs& t, uint32_t* queue
     __syncthreads();
     const uint32_t k = s_next;
     __syncthreads();
-    if ((int64_t)k >= t.n_tiles) break;
+    if ((int64_t)k >= t.n_tiles) {
+      if (threadIdx.x == 0 && (int64_t)k == t.n_tiles + (int64_t)gridDim.x - 1) atomicExch(&queue[head], 0u);
+      break;
+    }
     body((int)queue[2 + k]);
   }
 }
