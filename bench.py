@@ -110,6 +110,7 @@ def parse():
 
 def graph_of(torch, fn, stream):
     g = torch.cuda.CUDAGraph()
+    stream.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(stream):
         fn()
         torch.cuda.synchronize()

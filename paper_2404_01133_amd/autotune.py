@@ -66,8 +66,13 @@ def _store_cache(cache):
 
 
 def time_graph(run, reps=3, warmup=1, stream=None) -> float:
-    """Capture `run()` in a HIP graph and return the mean replay time in ms."""
+    """Capture `run()` in a HIP graph and return the mean replay time in ms.
+
+    `stream` first waits for the caller's current stream, so work still queued
+    there (a copy of the last output, say) finishes before `run()` overwrites
+    the buffers it reads."""
     stream = stream or torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(stream):
         run()  # eager warm-up on the capture stream
         torch.cuda.synchronize()
@@ -116,6 +121,9 @@ def tune(key: str, make_runner, search=None, reps=3, use_cache=True, log=None, s
             ok = True
         else:
             ok = bool(torch.equal(img, ref))
+        # the copies above are queued on the current stream; the next candidate's
+        # runs reuse the frame buffers they read
+        torch.cuda.synchronize()
         results.append(dict(cand.as_dict(), ms=ms, identical=ok))
         if log:
             log("autotune %s: %s %.4f ms %s" % (key, cand.as_dict(), ms, "" if ok else "REJECTED (image differs)"))
