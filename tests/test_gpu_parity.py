@@ -340,6 +340,25 @@ def test_work_queue_image_bit_identical(tile, batch):
     # every tile appears exactly once in the queue
     q = f1.tile_queue.cpu().numpy()[2:]
     assert sorted(q.tolist()) == list(range(f1.n_tiles))
+    # both head counters are back at zero after the persistent kernels drained the queue
+    assert f1.tile_queue[:2].cpu().tolist() == [0, 0]
+    # a repeated forward on the same sorted frame walks the whole queue again
+    f1.rgb.zero_()
+    gs.rasterize_fwd(f1.records, f1.pair_records, f1.tile_ranges, f1.V, f1.W, f1.H, (0.0, 0.0, 0.0), f1.tuning,
+                     f1.rgb, f1.T, f1.n_last, None, f1.tile_queue)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(f1.rgb.cpu().numpy(), f0.rgb.cpu().numpy())
+    # and so do two backward calls after one forward (the second doubles the gradient)
+    d = torch.from_numpy(np.random.default_rng(6).normal(size=(len(cams), 3, 270, 480)).astype(np.float32)).cuda()
+    once = _grads_for(scene, f0, cams_dev, d)
+    grads = [lv.zeros_like() for lv in scene.levels]
+    render.backward_frame(scene, f1, cams_dev, d, grads)
+    render.backward_frame(scene, f1, cams_dev, d, grads)
+    torch.cuda.synchronize()
+    for l, gl in enumerate(grads):
+        for a, b in zip((gl.means, gl.scales, gl.quats, gl.opac, gl.sh), once[l]):
+            if np.linalg.norm(b) > 0:
+                assert rel_l2(a.cpu().numpy(), 2 * b) <= 1e-5
 
 
 def _grads_for(scene, frame, cams_dev, d_rgb):
@@ -419,6 +438,7 @@ def test_graph_replay_equals_eager():
         eager.append(frame.rgb.clone())
     stream = torch.cuda.Stream()
     graph = torch.cuda.CUDAGraph()
+    stream.wait_stream(torch.cuda.current_stream())  # the last eager copy reads frame.rgb
     with torch.cuda.stream(stream):
         render.render_frame(scene, frame, slots[0], check=False)
         torch.cuda.synchronize()
@@ -783,3 +803,254 @@ def test_assignment_skip_equals_full_computation():
     b = assignment.assign_poses(scene, cams, 160, 120, skip_invisible=False)
     np.testing.assert_array_equal(a["b"], b["b"])
     np.testing.assert_array_equal(a["ssim"], b["ssim"])
+
+
+
+# ---------------------------------------------------------------------------
+# full benchmark sizes, in the benchmark's launch configuration
+# ---------------------------------------------------------------------------
+def _city_aggregate(fine, block_id, u, level_row, fractions=(0.30, 0.50, 1.00), coarse_scale=1.3):
+    """Host copy of one view's aggregated selection from the finest level: per
+    selected block (block order) the Gaussians of its level (u < fraction, in
+    storage order), scales x coarse_scale below the finest level."""
+    starts = np.searchsorted(block_id, np.arange(len(level_row) + 1))
+    idx_parts, k_parts = [], []
+    for b, l in enumerate(level_row):
+        if l < 0:
+            continue
+        idx = np.arange(starts[b], starts[b + 1])
+        if fractions[l] < 1.0:
+            idx = idx[u[idx] < fractions[l]]
+        idx_parts.append(idx)
+        k_parts.append(np.full(idx.shape[0], np.float32(1.0 if fractions[l] >= 1.0 else coarse_scale), np.float32))
+    idx = np.concatenate(idx_parts)
+    k = np.concatenate(k_parts)
+    return synth.GaussianSet(fine.means[:, idx], (fine.scales[:, idx] * k).astype(np.float32), fine.quats[:, idx],
+                             fine.opac[idx], fine.sh[:, :, idx])
+
+
+def test_city_20M_lod_frames_full_size():
+    """The headline workload at full size: 20M finest Gaussians over 1.5 km^2,
+    8 x 8 blocks, 3 levels, 1600 x 900, views at 50 m (oblique), 150 m (down)
+    and 400 m (oblique), rendered eagerly and then from one HIP graph with the
+    three frames in flight on three streams (the benchmark's launch).  Graph
+    images equal the eager ones bit for bit; boxes, levels, keys, footprints,
+    pairs and ranges are bit-exact against the oracle on the aggregated set;
+    colour and transmittance within 1e-4 on 3000 sampled pixels per view."""
+    print("case: 20M city, generating", flush=True)
+    fine, block_id, u, cells = synth.city_finest(20_000_000, seed=2)
+    scene = render.DeviceScene.from_finest(fine, block_id, u, cells)
+    scene.compute_bounds(4.0)
+    views = [9, 17, 47]
+    cams = [synth.city_views(seed=2)[v] for v in views]
+    starts = np.searchsorted(block_id, np.arange(scene.n_blocks + 1))
+    lo_ref = np.zeros((scene.n_blocks, 3))
+    hi_ref = np.zeros((scene.n_blocks, 3))
+    for b in range(scene.n_blocks):
+        lo_ref[b], hi_ref[b] = olod.mad_bounds(fine.means[:, starts[b]:starts[b + 1]])
+    np.testing.assert_array_equal(scene.lo.cpu().numpy(), lo_ref)
+    np.testing.assert_array_equal(scene.hi.cpu().numpy(), hi_ref)
+    print("case: 20M city, eager frames", flush=True)
+    rc = scene.max_records_per_view()
+    frames = [render.Frame(scene.n_blocks, 1, 1600, 900, rc, 1 << 22) for _ in cams]
+    slots = [gs.cameras_to_device([c]) for c in cams]
+    for f, c in zip(frames, slots):
+        render.render_frame(scene, f, c)
+    eager = [f.rgb.clone() for f in frames]
+    counts = [f.host_counts() for f in frames]
+    assert all(c["flags"] == 0 for c in counts)
+    print("case: 20M city, in-flight graph", flush=True)
+    main = torch.cuda.Stream()
+    side = [torch.cuda.Stream() for _ in cams[1:]]
+    main.wait_stream(torch.cuda.current_stream())
+
+    def step():
+        cur = torch.cuda.current_stream()
+        for s2 in side:
+            s2.wait_stream(cur)
+        for k, (f, c) in enumerate(zip(frames, slots)):
+            with torch.cuda.stream(([cur] + side)[k]):
+                render.render_frame(scene, f, c, check=False)
+        for s2 in side:
+            cur.wait_stream(s2)
+
+    with torch.cuda.stream(main):
+        step()
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=main):
+            step()
+    torch.cuda.synchronize()
+    for _ in range(2):
+        for f in frames:
+            f.rgb.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        for f, e in zip(frames, eager):
+            assert torch.equal(f.rgb, e)
+    del graph
+    rng = np.random.default_rng(1)
+    levels_seen = set()
+    for k, cam in enumerate(cams):
+        print("case: 20M city view", views[k], counts[k], flush=True)
+        level_ref, _ = olod.lod_select(lo_ref, hi_ref, cells, (200.0, 500.0), [cam], scene.lvl_cnt_host)
+        np.testing.assert_array_equal(frames[k].level.cpu().numpy()[0], level_ref[0])
+        levels_seen |= set(level_ref[0].tolist())
+        agg = _city_aggregate(fine, block_id, u, level_ref[0])
+        assert counts[k]["records"] == agg.opac.shape[0]
+        check_integer_parity(agg, cam, frames[k])
+        pix = rng.choice(1600 * 900, 3000, replace=False)
+        ref, T_ref, _, amb = oracle.render(agg, cam, pixels=pix)
+        ok = amb == 0
+        assert ok.mean() >= 0.99
+        img, T, _ = image_np(frames[k])
+        assert np.abs(img[0].reshape(3, -1)[:, pix] - ref)[:, ok].max() <= COLOUR_TOL
+        assert np.abs(T[0].reshape(-1)[pix] - T_ref)[ok].max() <= COLOUR_TOL
+        del agg
+    assert levels_seen >= {0, 1, 2}
+
+
+def test_batched_training_step_full_size():
+    """Batched training step at full size (one 2M-Gaussian block, 16 orbit views
+    at 1600 x 900, one call with shared selection and the work queue, the
+    benchmark's scene and cameras): images equal single-view renders bit for
+    bit; with the adjoint nonzero only for view 0 the batched gradients match
+    the oracle's FP64 gradients of that view; with every view's adjoint they
+    equal the sum of the single-view gradients (FP32 atomics: to rounding)."""
+    W, H, V = 1600, 900, 16
+    fine, block_id, u, cells = synth.city_finest(2_000_000, seed=3, area_m2=153.1 * 153.1, grid=(1, 1))
+    scene = render.DeviceScene.from_finest(fine, block_id, u, cells, fractions=(1.0,))
+    cams = synth.orbit_views((0.0, 0.0), n_views=V, radius=60.0, height=60.0, width=W, h_px=H)
+    cams_dev = gs.cameras_to_device(cams)
+    print("case: batched 16 x 2M @ 1600x900", flush=True)
+    fb = render.Frame(1, V, W, H, V * scene.n_finest, 1 << 24,
+                      gs.tuning_struct(16, 16, 256, gs.GS_TUNE_SHARED_SELECTION | gs.GS_TUNE_WORK_QUEUE))
+    render.render_frame(scene, fb, cams_dev, mode=gs.GS_LOD_ALL_FINEST, thresholds=())
+    assert fb.host_counts()["flags"] == 0
+    d_np = np.random.default_rng(5).normal(size=(V, 3, H, W)).astype(np.float32)
+    d = torch.from_numpy(d_np).cuda()
+    d0 = torch.zeros_like(d)
+    d0[0] = d[0]
+    got0 = _grads_for(scene, fb, cams_dev, d0)[0]
+    got = _grads_for(scene, fb, cams_dev, d)[0]
+    acc = [scene.levels[0].zeros_like()]
+    f1 = render.Frame(1, 1, W, H, scene.n_finest, 1 << 22)
+    for v in range(V):
+        c1 = cams_dev[v * 152:(v + 1) * 152]
+        render.render_frame(scene, f1, c1, mode=gs.GS_LOD_ALL_FINEST, thresholds=())
+        assert torch.equal(f1.rgb[0], fb.rgb[v])
+        render.backward_frame(scene, f1, c1, d[v:v + 1].contiguous(), acc)
+    torch.cuda.synchronize()
+    a = acc[0]
+    for name, x, y in zip(("means", "scales", "quats", "opac", "sh"), got,
+                          (a.means, a.scales, a.quats, a.opac, a.sh)):
+        err = rel_l2(x, y.cpu().numpy())
+        print("  batched vs summed singles", name, "rel L2 %.2e" % err, flush=True)
+        assert err <= 1e-5, (name, err)
+    print("case: oracle gradients of view 0", flush=True)
+    ref = oracle.render_bwd(fine, cams[0], d_np[0].astype(np.float64))
+    for name, x in zip(("means", "scales", "quats", "opac", "sh"), got0):
+        err = rel_l2(x, ref[name])
+        print("  view 0 grad", name, "rel L2 %.2e" % err, flush=True)
+        assert err <= GRAD_TOL, (name, err)
+
+
+def test_autotuner_gate_accepts_every_candidate():
+    """Every launch shape renders the same image, so the autotuner's bit-identity
+    gate must accept all of them; the gate's reference copy must not be
+    overwritten by the next candidate's runs (which reuse the frame buffers)."""
+    from paper_2404_01133_amd import autotune
+    bs = scaled_city(150_000, seed=38)
+    scene = render.DeviceScene.from_block_scene(bs)
+    scene.compute_bounds(4.0)
+    cams = synth.city_views(seed=38, n_xy=2, width=640, height=360)
+    V = len(cams)
+    cams_dev = gs.cameras_to_device(cams)
+    slots = [cams_dev[v * 152:(v + 1) * 152] for v in range(V)]
+    grads = [lv.zeros_like() for lv in scene.levels]
+    target = torch.rand((1, 3, 360, 640), generator=torch.Generator(device="cuda").manual_seed(8), device="cuda")
+    frames = {}
+
+    def make_runner(cand):
+        key = (cand.tile_w, cand.tile_h)
+        if key not in frames:
+            frames[key] = render.Frame(bs.n_blocks, 1, 640, 360, scene.max_records_per_view(), 1 << 20,
+                                       gs.tuning_struct(*key))
+            for s in slots:
+                render.render_frame(scene, frames[key], s)
+        f = frames[key]
+        f.tuning = cand.tuning()
+
+        def run():
+            for s in slots:
+                render.render_frame(scene, f, s, check=False)
+                render.backward_frame(scene, f, s, torch.sign(f.rgb - target) / f.rgb.numel(), grads)
+
+        def images():
+            out = []
+            for s in (slots[0], slots[-1]):
+                render.render_frame(scene, f, s, check=False)
+                out.append(f.rgb.clone())
+            return torch.cat(out)
+        return run, images
+
+    best, report = autotune.tune("test_gate", make_runner, reps=2, use_cache=False)
+    assert report["results"][0]["tile_w"] == 16 and report["results"][0]["batch"] == 256
+    assert report["rejected"] == 0, [r for r in report["results"] if not r["identical"]]
+    assert len(report["results"]) == len(autotune.candidates())
+
+
+def test_uneven_batch_full_size():
+    """Uneven batch at full size: 32 blocks of 0.2M-3M finest Gaussians (log-uniform),
+    128 views at 30-300 m, 1280 x 720, 16 views per call with the work queue
+    (the benchmark's chunking).  LoD levels of all views bit-exact against the
+    oracle; the first call's images equal single-view renders bit for bit;
+    integers and sampled pixels of two views against the oracle; the call's
+    gradients equal the sum of single-view gradients."""
+    print("case: uneven 32 blocks, generating", flush=True)
+    bs, cams = synth.uneven_block_scene(seed=4)
+    scene = render.DeviceScene.from_block_scene(bs)
+    scene.compute_bounds(4.0)
+    lo_ref, hi_ref = olod.scene_bounds(bs, 4.0)
+    np.testing.assert_array_equal(scene.lo.cpu().numpy(), lo_ref)
+    np.testing.assert_array_equal(scene.hi.cpu().numpy(), hi_ref)
+    W, H, chunk = 1280, 720, 16
+    V = len(cams)
+    cams_dev = gs.cameras_to_device(cams)
+    rc = chunk * scene.max_records_per_view() // 4
+    f = render.Frame(bs.n_blocks, chunk, W, H, rc, 1 << 24, gs.tuning_struct(16, 16, 256, gs.GS_TUNE_WORK_QUEUE))
+    level_ref, _ = olod.lod_select(lo_ref, hi_ref, bs.cells, (200.0, 500.0), cams, bs.lvl_cnt)
+    for k in range(V // chunk):
+        render.render_frame(scene, f, cams_dev[k * chunk * 152:(k + 1) * chunk * 152])
+        np.testing.assert_array_equal(f.level.cpu().numpy(), level_ref[k * chunk:(k + 1) * chunk])
+    print("case: uneven chunk 0 vs single views", flush=True)
+    c0 = cams_dev[:chunk * 152]
+    render.render_frame(scene, f, c0)
+    d = torch.from_numpy(np.random.default_rng(9).normal(size=(chunk, 3, H, W)).astype(np.float32)).cuda()
+    got = _grads_for(scene, f, c0, d)
+    acc = [lv.zeros_like() for lv in scene.levels]
+    f1 = render.Frame(bs.n_blocks, 1, W, H, scene.max_records_per_view(), 1 << 22)
+    for v in range(chunk):
+        c1 = cams_dev[v * 152:(v + 1) * 152]
+        render.render_frame(scene, f1, c1)
+        assert torch.equal(f1.rgb[0], f.rgb[v]), v
+        render.backward_frame(scene, f1, c1, d[v:v + 1].contiguous(), acc)
+    torch.cuda.synchronize()
+    for l in range(len(acc)):
+        a = acc[l]
+        for x, y in zip(got[l], (a.means, a.scales, a.quats, a.opac, a.sh)):
+            yn = y.cpu().numpy()
+            if np.linalg.norm(yn) > 0:
+                assert rel_l2(x, yn) <= 1e-5
+    rng = np.random.default_rng(10)
+    for v in (1, 5):
+        print("case: uneven view", v, "vs oracle", flush=True)
+        render.render_frame(scene, f1, cams_dev[v * 152:(v + 1) * 152])
+        agg = olod.aggregate(bs, level_ref[v])
+        check_integer_parity(agg, cams[v], f1)
+        pix = rng.choice(W * H, 3000, replace=False)
+        ref, T_ref, _, amb = oracle.render(agg, cams[v], pixels=pix)
+        ok = amb == 0
+        img, T, _ = image_np(f1)
+        assert np.abs(img[0].reshape(3, -1)[:, pix] - ref)[:, ok].max() <= COLOUR_TOL
+        assert np.abs(T[0].reshape(-1)[pix] - T_ref)[ok].max() <= COLOUR_TOL
