@@ -1,12 +1,15 @@
 // Per-tile alpha compositing (Eq. 1 of the paper) and its adjoint.
 //
 // Forward: one work-group per (view, tile); one lane per pixel, each wave64 an
-// 8x8 pixel block of the tile (a 16x16 tile is four waves).  The tile's Gaussians are
-// staged through LDS in batches (coalesced gathers of 48-byte records, one per
-// lane); every lane then reads the same LDS record (a broadcast, no bank
-// conflicts).  A lane leaves the loop when its transmittance would drop below
-// 1e-4; a wave leaves when all its lanes have, the work-group when all waves
-// have (block-wide vote before each batch).
+// 8x8 pixel block of the tile (a 16x16 tile is four waves), cut into four 4x4
+// quadrants of 16 lanes.  The tile's Gaussians are staged through LDS in
+// batches (coalesced gathers of 48-byte records, one per lane); each quadrant
+// keeps its own depth-ordered list of the staged records whose footprint meets
+// it, and the four quadrants walk their lists side by side (a lane reads the
+// record of its quadrant), so a small footprint occupies one quadrant's step
+// rather than a whole wave's.  A lane leaves the loop when its transmittance
+// would drop below 1e-4; a wave leaves when all its lanes have, the work-group
+// when all waves have (block-wide vote before each batch).
 //
 // Backward: the same walk, front to back, bounded by each pixel's n_last, with
 // the blend state recomputed (colour in front is accumulated, colour behind =
@@ -83,10 +86,73 @@ __device__ __forceinline__ int wave_compact_block(const float4* s_w0, int nb, in
   return cnt;
 }
 
+// Forward lane -> pixel map: the wave's 8x8 block (placed as in WaveBlock) is
+// cut into 4x4 quadrants; lanes 16q .. 16q+15 hold quadrant q = (q mod 2,
+// q div 2) and lane l is pixel (l mod 4, (l div 4) mod 4) of its quadrant.
+template <int TW, int TH>
+struct QuadBlock {
+  int i, j;    // this lane's pixel
+  int x0, y0;  // first pixel of the wave's block
+  int q;       // this lane's quadrant
+  __device__ __forceinline__ QuadBlock(int txi, int tyi, int wid) {
+    static_assert(TW % 8 == 0 && TH % 8 == 0, "tiles are whole 8x8 blocks");
+    const int lane = threadIdx.x & 63;
+    x0 = txi * TW + (wid % (TW / 8)) * 8;
+    y0 = tyi * TH + (wid / (TW / 8)) * 8;
+    q = lane >> 4;
+    i = x0 + (q & 1) * 4 + (lane & 3);
+    j = y0 + (q >> 1) * 4 + ((lane >> 2) & 3);
+  }
+};
+
+// Quadrant list stride: BATCH bytes plus one dword, so the four lists a wave
+// reads side by side start in different LDS banks.
+template <int BATCH>
+constexpr int kQuadStride = BATCH + 4;
+
+// Per-quadrant ballot compaction: list[q][0 .. cnt[q]) receives, in ascending
+// (= depth) order, the staged records whose footprint rectangle meets quadrant
+// q of the wave's block.
+template <int BATCH>
+__device__ __forceinline__ void wave_compact_quads(const float4* s_w0, int nb, int x0, int y0,
+                                                   uint8_t (*list)[kQuadStride<BATCH>], int cnt[4]) {
+  static_assert(BATCH <= 256, "record indices are bytes");
+  const int lane = threadIdx.x & 63;
+  int c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+  for (int base = 0; base < nb; base += 64) {
+    const int k = base + lane;
+    bool h0 = false, h1 = false, h2 = false, h3 = false;
+    if (k < nb) {
+      const uint32_t px = __float_as_uint(s_w0[k].z), py = __float_as_uint(s_w0[k].w);
+      const int i0 = (int)(px & 0xFFFFu), i1 = i0 + (int)(px >> 16);
+      const int j0 = (int)(py & 0xFFFFu), j1 = j0 + (int)(py >> 16);
+      const bool xa = i0 <= x0 + 3 && i1 >= x0, xb = i0 <= x0 + 7 && i1 >= x0 + 4;
+      const bool ya = j0 <= y0 + 3 && j1 >= y0, yb = j0 <= y0 + 7 && j1 >= y0 + 4;
+      h0 = xa && ya;
+      h1 = xb && ya;
+      h2 = xa && yb;
+      h3 = xb && yb;
+    }
+    const uint64_t m0 = __ballot(h0), m1 = __ballot(h1), m2 = __ballot(h2), m3 = __ballot(h3);
+    if (h0) list[0][c0 + (int)lanemask_lt_count(m0)] = (uint8_t)k;
+    if (h1) list[1][c1 + (int)lanemask_lt_count(m1)] = (uint8_t)k;
+    if (h2) list[2][c2 + (int)lanemask_lt_count(m2)] = (uint8_t)k;
+    if (h3) list[3][c3 + (int)lanemask_lt_count(m3)] = (uint8_t)k;
+    c0 += (int)__popcll(m0);
+    c1 += (int)__popcll(m1);
+    c2 += (int)__popcll(m2);
+    c3 += (int)__popcll(m3);
+  }
+  cnt[0] = c0;
+  cnt[1] = c1;
+  cnt[2] = c2;
+  cnt[3] = c3;
+}
+
 template <int TW, int TH, int BATCH>
 struct FwdLds {
   float4 w0[BATCH], w1[BATCH], w2[BATCH];
-  uint16_t list[(TW * TH) / 64][BATCH];
+  uint8_t list[(TW * TH) / 64][4][kQuadStride<BATCH>];
 };
 
 struct TileArgs {
@@ -142,14 +208,15 @@ __device__ __forceinline__ void raster_fwd_tile(const TileArgs& ta, FwdLds<TW, T
   const int tile = tile_g - view * tiles_per_view;
   const int tyi = tile / tiles_x_n, txi = tile - tyi * tiles_x_n;
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const WaveBlock<TW, TH> wb(txi, tyi, wid);
-  const int i = wb.i, j = wb.j;
+  const QuadBlock<TW, TH> qb(txi, tyi, wid);
+  const int i = qb.i, j = qb.j;
   const bool inside = (i < W) && (j < H);
   const uint32_t start = ranges[2 * tile_g], end = ranges[2 * tile_g + 1];
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
   int last = 0;
   bool done = !inside;
-  uint16_t* list = lds.list[wid];
+  uint8_t(*lists)[kQuadStride<BATCH>] = lds.list[wid];
+  const uint8_t* my_list = lists[qb.q];
   for (uint32_t b = start; b < end; b += BATCH) {
     if (__syncthreads_and(done)) break;
     const int nb = (int)min((uint32_t)BATCH, end - b);
@@ -160,46 +227,45 @@ __device__ __forceinline__ void raster_fwd_tile(const TileArgs& ta, FwdLds<TW, T
       s_w2[k] = r[2];
     }
     __syncthreads();
-    const int cnt = wave_compact_block(s_w0, nb, wb.x0, wb.y0, list);
+    int cnt[4];
+    wave_compact_quads<BATCH>(s_w0, nb, qb.x0, qb.y0, lists, cnt);
+    const int max_cnt = max(max(cnt[0], cnt[1]), max(cnt[2], cnt[3]));
+    const int my_cnt = qb.q == 0 ? cnt[0] : qb.q == 1 ? cnt[1] : qb.q == 2 ? cnt[2] : cnt[3];
     const int base_idx = (int)(b - start);
-    if (cnt > 0 && __ballot(!done) != 0) {
-      auto blend = [&](int k, const float4& w0, const float4& w1, const float4& w2) {
-        int di, dj;
-        const bool in_fp = in_footprint(i, j, __float_as_uint(w0.z), __float_as_uint(w0.w), di, dj);
-        Eval e;
-        evaluate(w0, w1, di, dj, e);
-        bool use = !done && in_fp && (e.alpha >= kAlphaMin);
-        const float Tn = T * (1.0f - e.alpha);
-        const bool stop = use && (Tn < kTMin);
-        done = done || stop;
-        use = use && !stop;
-        const float aT = e.alpha * T;
-        C0 = use ? fmaf(w2.x, aT, C0) : C0;
-        C1 = use ? fmaf(w2.y, aT, C1) : C1;
-        C2 = use ? fmaf(w2.z, aT, C2) : C2;
-        T = use ? Tn : T;
-        last = use ? base_idx + k + 1 : last;
-      };
-      // four compacted records per trip: two LDS reads for the four indices,
-      // all records' words in flight together, one termination vote per trip
-      for (int t = 0; t < cnt; t += 4) {
-        const int nr = cnt - t < 4 ? cnt - t : 4;  // wave-uniform
-        const uint2 pr = *reinterpret_cast<const uint2*>(&list[t]);
-        const uint32_t p0 = __builtin_amdgcn_readfirstlane(pr.x), p1 = __builtin_amdgcn_readfirstlane(pr.y);
-        const int k0 = (int)(p0 & 0xFFFFu);
-        const int k1 = nr > 1 ? (int)(p0 >> 16) : k0;
-        const int k2 = nr > 2 ? (int)(p1 & 0xFFFFu) : k0;
-        const int k3 = nr > 3 ? (int)(p1 >> 16) : k0;
-        const float4 a0 = s_w0[k0], a1 = s_w1[k0], a2 = s_w2[k0];
-        const float4 b0 = s_w0[k1], b1 = s_w1[k1], b2 = s_w2[k1];
-        const float4 c0 = s_w0[k2], c1 = s_w1[k2], c2 = s_w2[k2];
-        const float4 d0 = s_w0[k3], d1 = s_w1[k3], d2 = s_w2[k3];
-        blend(k0, a0, a1, a2);
-        if (nr > 1) blend(k1, b0, b1, b2);
-        if (nr > 2) blend(k2, c0, c1, c2);
-        if (nr > 3) blend(k3, d0, d1, d2);
-        if (__ballot(!done) == 0) break;
-      }
+    auto blend = [&](int k, bool valid, const float4& w0, const float4& w1, const float4& w2) {
+      int di, dj;
+      const bool in_fp = in_footprint(i, j, __float_as_uint(w0.z), __float_as_uint(w0.w), di, dj);
+      Eval e;
+      evaluate(w0, w1, di, dj, e);
+      bool use = valid && !done && in_fp && (e.alpha >= kAlphaMin);
+      const float Tn = T * (1.0f - e.alpha);
+      const bool stop = use && (Tn < kTMin);
+      done = done || stop;
+      use = use && !stop;
+      const float aT = e.alpha * T;
+      C0 = use ? fmaf(w2.x, aT, C0) : C0;
+      C1 = use ? fmaf(w2.y, aT, C1) : C1;
+      C2 = use ? fmaf(w2.z, aT, C2) : C2;
+      T = use ? Tn : T;
+      last = use ? base_idx + k + 1 : last;
+    };
+    // four entries of the lane's quadrant list per trip: one LDS read for the
+    // four byte indices, all records' words in flight together, one vote per
+    // trip (entries past the quadrant's count are read from stale list bytes,
+    // masked into the staged range and not used)
+    for (int t = 0; t < max_cnt; t += 4) {
+      if (__ballot(!done && t < my_cnt) == 0) break;
+      const uint32_t pk = *reinterpret_cast<const uint32_t*>(&my_list[t]);
+      const int k0 = (int)(pk & (BATCH - 1)), k1 = (int)((pk >> 8) & (BATCH - 1));
+      const int k2 = (int)((pk >> 16) & (BATCH - 1)), k3 = (int)((pk >> 24) & (BATCH - 1));
+      const float4 a0 = s_w0[k0], a1 = s_w1[k0], a2 = s_w2[k0];
+      const float4 b0 = s_w0[k1], b1 = s_w1[k1], b2 = s_w2[k1];
+      const float4 c0 = s_w0[k2], c1 = s_w1[k2], c2 = s_w2[k2];
+      const float4 d0 = s_w0[k3], d1 = s_w1[k3], d2 = s_w2[k3];
+      blend(k0, t < my_cnt, a0, a1, a2);
+      blend(k1, t + 1 < my_cnt, b0, b1, b2);
+      blend(k2, t + 2 < my_cnt, c0, c1, c2);
+      blend(k3, t + 3 < my_cnt, d0, d1, d2);
     }
     __syncthreads();
   }
