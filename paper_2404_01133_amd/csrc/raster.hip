@@ -46,49 +46,12 @@ __device__ __forceinline__ void evaluate(const float4& w0, const float4& w1, int
   e.alpha = fminf(kAlphaMax, w1.w * e.G);
 }
 
-// Lane -> pixel map: the tile is cut into 8x8 pixel blocks, one per wave
-// (wave w is block (w mod TW/8, w div TW/8)); lane l is pixel (l mod 8, l div 8)
-// of its block.  Against a small footprint a square block keeps more of the
-// wave's lanes busy than a row strip of the same 64 pixels.
-template <int TW, int TH>
-struct WaveBlock {
-  int i, j;    // this lane's pixel
-  int x0, y0;  // first pixel of the wave's block
-  __device__ __forceinline__ WaveBlock(int txi, int tyi, int wid) {
-    static_assert(TW % 8 == 0 && TH % 8 == 0, "tiles are whole 8x8 blocks");
-    const int lane = threadIdx.x & 63;
-    x0 = txi * TW + (wid % (TW / 8)) * 8;
-    y0 = tyi * TH + (wid / (TW / 8)) * 8;
-    i = x0 + (lane & 7);
-    j = y0 + (lane >> 3);
-  }
-};
-
-// Each wave keeps the indices of the staged records whose footprint meets its
-// own 8x8 block (ballot compaction), so the blend loop never visits a record
-// that cannot touch the wave.
-__device__ __forceinline__ int wave_compact_block(const float4* s_w0, int nb, int x0, int y0, uint16_t* list) {
-  const int lane = threadIdx.x & 63;
-  int cnt = 0;
-  for (int base = 0; base < nb; base += 64) {
-    const int k = base + lane;
-    bool hit = false;
-    if (k < nb) {
-      const uint32_t px = __float_as_uint(s_w0[k].z), py = __float_as_uint(s_w0[k].w);
-      const int i0 = (int)(px & 0xFFFFu), i1 = i0 + (int)(px >> 16);
-      const int j0 = (int)(py & 0xFFFFu), j1 = j0 + (int)(py >> 16);
-      hit = !(i1 < x0 || i0 > x0 + 7 || j1 < y0 || j0 > y0 + 7);
-    }
-    const uint64_t m = __ballot(hit);
-    if (hit) list[cnt + (int)lanemask_lt_count(m)] = (uint16_t)k;
-    cnt += (int)__popcll(m);
-  }
-  return cnt;
-}
-
-// Forward lane -> pixel map: the wave's 8x8 block (placed as in WaveBlock) is
-// cut into 4x4 quadrants; lanes 16q .. 16q+15 hold quadrant q = (q mod 2,
+// Lane -> pixel map of both tile kernels: the tile is cut into 8x8 pixel
+// blocks, one per wave (wave w is block (w mod TW/8, w div TW/8)); each block
+// is cut into 4x4 quadrants, lanes 16q .. 16q+15 hold quadrant q = (q mod 2,
 // q div 2) and lane l is pixel (l mod 4, (l div 4) mod 4) of its quadrant.
+// Against small footprints square blocks and quadrants keep more lanes busy
+// than row strips of the same size.
 template <int TW, int TH>
 struct QuadBlock {
   int i, j;    // this lane's pixel
@@ -293,12 +256,12 @@ __global__ void __launch_bounds__(TW* TH) raster_fwd_kernel(TileArgs ta, uint32_
 }
 
 // ---------------------------------------------------------------------------
-// Wave64 sums of nine per-lane values at once.  At butterfly level k (partner
-// lane = lane ^ 2^k) two quantities share one register: lanes with bit k clear
-// keep the first, lanes with bit k set the second, and each lane adds the
-// partner's copy of the quantity it keeps.  Nine registers become one after
-// four levels; two plain levels finish the sum.  On return lane q (q < 8)
-// holds the total of value q and lanes 8..15 the total of value 8.
+// Sums of nine per-lane values over each 16-lane quadrant, all at once.  At
+// butterfly level k (partner lane = lane ^ 2^k, k = 0..3) two quantities share
+// one register: lanes with bit k clear keep the first, lanes with bit k set the
+// second, and each lane adds the partner's copy of the quantity it keeps.  Nine
+// registers become one after the four levels; on return lane 16p + r of
+// quadrant p holds the quadrant's total of value min(r, 8).
 // ---------------------------------------------------------------------------
 template <int CTRL>
 __device__ __forceinline__ float dpp_mov(float v) {
@@ -315,7 +278,7 @@ __device__ __forceinline__ float pack_add2(bool hi, float a, float b) {  // part
   return (hi ? b : a) + dpp_mov<0x4E>(hi ? a : b);                      // quad_perm [2,3,0,1]
 }
 
-__device__ __forceinline__ float wave_sum9(const float v[9], int lane) {
+__device__ __forceinline__ float quad_sum9(const float v[9], int lane) {
   const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4, b3 = lane & 8;
   const float r0 = pack_add1(b0, v[0], v[1]);
   const float r1 = pack_add1(b0, v[2], v[3]);
@@ -328,10 +291,7 @@ __device__ __forceinline__ float wave_sum9(const float v[9], int lane) {
   // ds_swizzle bit-mask mode (and 0x1F, xor m) exchanges with lane ^ m inside 32 lanes
   const float u0 = (b2 ? s1 : s0) + swz<0x101F>(b2 ? s0 : s1);
   const float u1 = s2 + swz<0x101F>(s2);
-  float x = (b3 ? u1 : u0) + swz<0x201F>(b3 ? u0 : u1);
-  x += swz<0x401F>(x);
-  x += __shfl_xor(x, 32, 64);
-  return x;
+  return (b3 ? u1 : u0) + swz<0x201F>(b3 ? u0 : u1);
 }
 
 constexpr int kG = 9;  // partials per Gaussian: r, g, b, opacity, A1, A2, Axx, Axy, Ayy
@@ -341,7 +301,7 @@ struct BwdLds {
   float4 w0[BATCH], w1[BATCH], w2[BATCH];
   uint32_t rec[BATCH];
   float grad[BATCH * kG];
-  uint16_t list[(TW * TH) / 64][BATCH];
+  uint8_t list[(TW * TH) / 64][4][kQuadStride<BATCH>];
   int wave_last[(TW * TH) / 64];
 };
 
@@ -367,8 +327,8 @@ __device__ __forceinline__ void raster_bwd_tile(const TileArgs& ta, BwdLds<TW, T
   const int tyi = tile / tiles_x_n, txi = tile - tyi * tiles_x_n;
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const WaveBlock<TW, TH> wb(txi, tyi, wid);
-  const int i = wb.i, j = wb.j;
+  const QuadBlock<TW, TH> qb(txi, tyi, wid);
+  const int i = qb.i, j = qb.j;
   const bool inside = (i < W) && (j < H);
   const uint32_t start = ranges[2 * tile_g];
   const int64_t plane = (int64_t)H * W;
@@ -393,29 +353,37 @@ __device__ __forceinline__ void raster_bwd_tile(const TileArgs& ta, BwdLds<TW, T
   int tile_last = 0;
   for (int w = 0; w < NW; ++w) tile_last = max(tile_last, s_wave_last[w]);
   const int wave_last = __builtin_amdgcn_readfirstlane(s_wave_last[wid]);
-  uint16_t* list = lds.list[wid];
+  uint8_t(*lists)[kQuadStride<BATCH>] = lds.list[wid];
+  const uint8_t* my_list = lists[qb.q];
+  const int r = lane & 15;  // lane within the quadrant
   float T = 1.0f, A0 = 0.f, A1c = 0.f, A2c = 0.f;  // transmittance and colour accumulated in front
   for (uint32_t b = start; b < start + (uint32_t)tile_last; b += BATCH) {
     const int nb = (int)min((uint32_t)BATCH, start + (uint32_t)tile_last - b);
     for (int k = threadIdx.x; k < nb; k += NT) {
       const uint32_t rid = pair_records[b + k];
-      const float4* r = reinterpret_cast<const float4*>(&records[rid]);
-      s_w0[k] = r[0];
-      s_w1[k] = r[1];
-      s_w2[k] = r[2];
+      const float4* rp = reinterpret_cast<const float4*>(&records[rid]);
+      s_w0[k] = rp[0];
+      s_w1[k] = rp[1];
+      s_w2[k] = rp[2];
       s_rec[k] = rid;
     }
     for (int k = threadIdx.x; k < nb * kG; k += NT) s_grad[k] = 0.0f;
     __syncthreads();
     const int base_idx = (int)(b - start);
     const int kmax = min(nb, wave_last - base_idx);  // entries past every lane's n_last are not needed
-    const int cnt = kmax > 0 ? wave_compact_block(s_w0, kmax, wb.x0, wb.y0, list) : 0;
-    auto step = [&](int k, const float4& w0, const float4& w1, const float4& w2) {
+    int cnt[4] = {0, 0, 0, 0};
+    if (kmax > 0) wave_compact_quads<BATCH>(s_w0, kmax, qb.x0, qb.y0, lists, cnt);
+    const int max_cnt = max(max(cnt[0], cnt[1]), max(cnt[2], cnt[3]));
+    const int my_cnt = qb.q == 0 ? cnt[0] : qb.q == 1 ? cnt[1] : qb.q == 2 ? cnt[2] : cnt[3];
+    // one entry of each quadrant's list: the four quadrants step (possibly
+    // different) records side by side; partials are summed per quadrant and
+    // added into the record's LDS slots (two quadrants on one record add twice)
+    auto step = [&](int k, bool valid, const float4& w0, const float4& w1, const float4& w2) {
       int di, dj;
       const bool in_fp = in_footprint(i, j, __float_as_uint(w0.z), __float_as_uint(w0.w), di, dj);
       Eval e;
       evaluate(w0, w1, di, dj, e);
-      const bool use = (base_idx + k < last) && in_fp && (e.alpha >= kAlphaMin);
+      const bool use = valid && (base_idx + k < last) && in_fp && (e.alpha >= kAlphaMin);
       if (__ballot(use) == 0) return;
       const float aT = e.alpha * T;
       const float nA0 = fmaf(w2.x, aT, A0), nA1 = fmaf(w2.y, aT, A1c), nA2 = fmaf(w2.z, aT, A2c);
@@ -440,19 +408,18 @@ __device__ __forceinline__ void raster_bwd_tile(const TileArgs& ta, BwdLds<TW, T
       A1c = use ? nA1 : A1c;
       A2c = use ? nA2 : A2c;
       T = use ? T * (1.0f - e.alpha) : T;
-      const float sum = wave_sum9(c, lane);
-      if (lane < kG && sum != 0.0f) atomicAdd(&s_grad[k * kG + lane], sum);
+      const float sum = quad_sum9(c, lane);
+      if (valid && r < kG && sum != 0.0f) atomicAdd(&s_grad[k * kG + r], sum);
     };
-    // two compacted records per trip, indices in one LDS read, words in flight together
-    for (int t = 0; t < cnt; t += 2) {
-      const bool two = t + 1 < cnt;  // wave-uniform
-      const uint32_t pr = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const uint32_t*>(&list[t]));
-      const int ka = (int)(pr & 0xFFFFu);
-      const int kb = two ? (int)(pr >> 16) : ka;
+    // two entries of the lane's quadrant list per trip, byte indices in one LDS
+    // read (entries past the quadrant's count: stale bytes, masked, not used)
+    for (int t = 0; t < max_cnt; t += 2) {
+      const uint32_t pk = *reinterpret_cast<const uint16_t*>(&my_list[t]);
+      const int ka = (int)(pk & (BATCH - 1)), kb = (int)((pk >> 8) & (BATCH - 1));
       const float4 a0 = s_w0[ka], a1 = s_w1[ka], a2 = s_w2[ka];
       const float4 b0 = s_w0[kb], b1 = s_w1[kb], b2 = s_w2[kb];
-      step(ka, a0, a1, a2);
-      if (two) step(kb, b0, b1, b2);
+      step(ka, t < my_cnt, a0, a1, a2);
+      step(kb, t + 1 < my_cnt, b0, b1, b2);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < nb * kG; t += NT) {
