@@ -459,9 +459,12 @@ struct BwdArgs {
   int32_t segs;  // segments per view: B (block-wise) or L (point-wise)
 };
 
-// With one view per call every Gaussian owns at most one record, so its
-// gradient is a plain read-modify-write; with several views records of the
-// same Gaussian may run concurrently and FP32 atomics are used.
+// ATOMIC: a no-return FP32 atomic add (records of one Gaussian may run
+// concurrently when views share it; with one view each address receives one
+// add, so the result is the plain sum).  The adds do not wait for memory, so a
+// record's 59 updates are all in flight together; a read-modify-write waits for
+// each load, since the compiler must keep the updates in order.  !ATOMIC: plain
+// read-modify-write, for a thread that owns every record of its Gaussian.
 template <bool ATOMIC>
 __device__ __forceinline__ void accumulate(float* p, float v) {
   if (ATOMIC) unsafeAtomicAdd(p, v);
@@ -684,8 +687,7 @@ __device__ __forceinline__ void preprocess_bwd_record(const BwdArgs& a, const Re
   else preprocess_bwd_record_t<ATOMIC, false>(a, records, grad2d, g, v, l, gi);
 }
 
-// View-major: records in index order (FP32 atomics when views may share Gaussians).
-template <bool ATOMIC>
+// View-major: records in index order, gradients added with no-return atomics.
 __global__ void __launch_bounds__(256) preprocess_bwd_kernel(BwdArgs a, const Record* __restrict__ records,
                                                              const float* __restrict__ grad2d,
                                                              const int64_t* __restrict__ counts) {
@@ -698,7 +700,7 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(BwdArgs a, const Re
     const int v = p / a.segs, b = p - v * a.segs;
     const int l = a.gather ? b : a.level[p];
     const int64_t gi = a.gather ? (int64_t)a.gather[g] : a.lvl_off[(int64_t)b * a.L + l] + (g - a.offsets[p]);
-    preprocess_bwd_record<ATOMIC>(a, records, grad2d, g, v, l, gi);
+    preprocess_bwd_record<true>(a, records, grad2d, g, v, l, gi);
   }
 }
 
@@ -872,10 +874,8 @@ extern "C" gs_status gs_rasterize_bwd(const void* records, const uint32_t* pair_
     int64_t pv = (record_capacity / n_views + 255) / 256;
     const dim3 gs_grid((unsigned)(pv < 8192 ? (pv < 1 ? 1 : pv) : 8192));
     hipLaunchKernelGGL(preprocess_bwd_shared_kernel, gs_grid, dim3(256), 0, s, a, rec, grad2d, counts);
-  } else if (n_views == 1) {
-    hipLaunchKernelGGL(preprocess_bwd_kernel<false>, gbg, dim3(256), 0, s, a, rec, grad2d, counts);
   } else {
-    hipLaunchKernelGGL(preprocess_bwd_kernel<true>, gbg, dim3(256), 0, s, a, rec, grad2d, counts);
+    hipLaunchKernelGGL(preprocess_bwd_kernel, gbg, dim3(256), 0, s, a, rec, grad2d, counts);
   }
   GS_LAUNCH_CHECK();
   return GS_OK;
