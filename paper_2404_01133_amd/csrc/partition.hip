@@ -180,7 +180,7 @@ PartWs part_ws_layout(char* base, int64_t n) {
     off += (bytes + 255) & ~(size_t)255;
     return p;
   };
-  const int64_t ntiles = (n + kTile - 1) / kTile;
+  const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
   w.n_words = 8 + 2 * kRadix + 2 * ntiles * kRadix;
   w.words = (uint32_t*)take(4 * (size_t)w.n_words);
   w.hist = w.words ? w.words + 8 : nullptr;
@@ -240,7 +240,7 @@ extern "C" gs_status gs_partition(const float* means, int64_t n, const double* x
   PartWs w = part_ws_layout((char*)ws, n);
   a.zr = w.words;
   const int passes = B > kRadix ? 2 : 1;
-  const int64_t ntiles = (n + kTile - 1) / kTile;
+  const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
   hipLaunchKernelGGL(part_clear_kernel, dim3(grid_of(w.n_words, 2048)), dim3(256), 0, s, w.words, w.n_words,
                      w.counts, n);
   hipLaunchKernelGGL(zrange_kernel, dim3(grid_of(n, 1024)), dim3(256), 0, s, means + 2 * n, n, w.words);

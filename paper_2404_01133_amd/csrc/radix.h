@@ -1,6 +1,6 @@
 // Stable single-pass LSD radix pass over 8-bit digits (onesweep style), shared
 // by the tile binning and the block partition.  Work-groups take tiles of
-// kTile keys from an atomic counter in launch order, rank their keys with
+// kRadixTile keys from an atomic counter in launch order, rank their keys with
 // wave64 ballot multisplit, publish per-digit tile counts and walk back over
 // the predecessors' published counts (decoupled look-back), then scatter
 // through LDS so the global writes of each digit run are contiguous.
@@ -13,7 +13,9 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kItems = 8;
-constexpr int kTile = kThreads * kItems;  // 2048 keys per radix / scan tile
+constexpr int kTile = kThreads * kItems;  // 2048 elements per scan tile
+constexpr int kRadixItems = 16;
+constexpr int kRadixTile = kThreads * kRadixItems;  // 4096 keys per radix tile
 constexpr int kRadix = 256;
 constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagInc = 2u << 30;
@@ -52,8 +54,8 @@ __global__ void __launch_bounds__(kThreads) radix_pass_kernel(
     uint32_t* __restrict__ vals_out, const int64_t* counts_in, int count_idx, int64_t cap, int shift,
     const uint32_t* __restrict__ hist, uint32_t* status, int64_t status_stride, uint32_t* tile_counter,
     int64_t* counts) {
-  __shared__ uint32_t s_keys[kTile];
-  __shared__ uint32_t s_vals[kTile];
+  __shared__ uint32_t s_keys[kRadixTile];
+  __shared__ uint32_t s_vals[kRadixTile];
   __shared__ uint32_t s_wave_hist[kThreads / 64][kRadix];
   __shared__ uint32_t s_tile_excl[kRadix];
   __shared__ uint32_t s_digit_base[kRadix];
@@ -62,7 +64,7 @@ __global__ void __launch_bounds__(kThreads) radix_pass_kernel(
   __shared__ uint32_t s_goff[kRadix];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int64_t n = count_clamped(counts_in, count_idx, cap);
-  const int64_t ntiles = (n + kTile - 1) / kTile;
+  const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
   if ((int64_t)blockIdx.x >= ntiles) return;
   {
     uint32_t tot;
@@ -74,15 +76,15 @@ __global__ void __launch_bounds__(kThreads) radix_pass_kernel(
     __syncthreads();
     const int64_t t = s_tile;
     if (t >= ntiles) break;
-    const int64_t tile_base = t * kTile;
-    const int tile_n = (int)((n - tile_base) < kTile ? (n - tile_base) : kTile);
-    // wave w owns the contiguous slice [w*64*kItems, (w+1)*64*kItems) of the tile;
+    const int64_t tile_base = t * kRadixTile;
+    const int tile_n = (int)((n - tile_base) < kRadixTile ? (n - tile_base) : kRadixTile);
+    // wave w owns the contiguous slice [w*64*kRadixItems, (w+1)*64*kRadixItems) of the tile;
     // item k of lane l is element k*64 + l of that slice (coalesced loads)
-    uint32_t key[kItems], val[kItems], rank[kItems];
-    bool valid[kItems];
-    const int slice = wid * 64 * kItems;
+    uint32_t key[kRadixItems], val[kRadixItems], rank[kRadixItems];
+    bool valid[kRadixItems];
+    const int slice = wid * 64 * kRadixItems;
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
+    for (int k = 0; k < kRadixItems; ++k) {
       const int li = slice + k * 64 + lane;
       valid[k] = li < tile_n;
       key[k] = valid[k] ? keys_in[tile_base + li] : 0u;
@@ -90,7 +92,7 @@ __global__ void __launch_bounds__(kThreads) radix_pass_kernel(
     }
     // stable rank inside the wave: items in order k, lanes in order within an item
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
+    for (int k = 0; k < kRadixItems; ++k) {
       const uint32_t d = (key[k] >> shift) & 255u;
       uint64_t peers = __ballot(valid[k]);
 #pragma unroll
@@ -167,7 +169,7 @@ __global__ void __launch_bounds__(kThreads) radix_pass_kernel(
     __syncthreads();
     // local scatter by digit, then coalesced write-out
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
+    for (int k = 0; k < kRadixItems; ++k) {
       if (valid[k]) {
         const uint32_t dd = (key[k] >> shift) & 255u;
         const uint32_t pos = s_tile_excl[dd] + s_wave_hist[wid][dd] + rank[k];

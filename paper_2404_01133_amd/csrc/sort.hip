@@ -42,7 +42,7 @@ __global__ void clear_front_kernel(uint32_t* __restrict__ fixed, int64_t fixed_w
   const int64_t n = count_clamped(counts, GS_COUNT_RECORDS, cap);
   const int64_t ntiles = (n + kTile - 1) / kTile;
   const int64_t scan_words = 2 * (ntiles + 1);  // one u64 status per scan tile
-  const int64_t dwords = ntiles * 4 * kRadix;   // [ntiles][4 passes][256]
+  const int64_t dwords = ((n + kRadixTile - 1) / kRadixTile) * 4 * kRadix;  // [radix tiles][4 passes][256]
   const int64_t total = fixed_words + 2 * scan_words + dwords;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(kThreads) emit_kernel(const Record* __restrict
   // zero the look-back words of the tile passes (sized by the pair count) and the ranges
   {
     const int64_t m = count_clamped(counts, GS_COUNT_PAIRS, pair_cap);
-    const int64_t words = ((m + kTile - 1) / kTile) * (int64_t)tpasses * kRadix;
+    const int64_t words = ((m + kRadixTile - 1) / kRadixTile) * (int64_t)tpasses * kRadix;
     for (int64_t i = gtid; i < words; i += stride) pstatus[i] = 0u;
     for (int64_t i = gtid; i < range_words; i += stride) ranges[i] = 0u;
   }
@@ -351,7 +351,7 @@ struct SortWs {
   uint32_t* precs_alt;    // [pc]
   uint32_t* fixed;        // counters [64], then hist [2][kMaxPasses][256]
   uint64_t* scan_status;  // [2][rtiles]
-  uint32_t* dstatus;      // [rtiles][4][256]   (tile-major so a prefix covers every pass)
+  uint32_t* dstatus;      // [radix tiles][4][256] (tile-major so a prefix covers every pass)
   uint32_t* pstatus;      // [ptiles][kMaxPasses][256]
   size_t bytes;
 };
@@ -366,8 +366,9 @@ SortWs sort_ws_layout(char* base, int64_t rc, int64_t pc) {
     off = align_up(off + bytes);
     return p;
   };
-  const int64_t rtiles = (rc + kTile - 1) / kTile + 1;
-  const int64_t ptiles = (pc + kTile - 1) / kTile + 1;
+  const int64_t rtiles = (rc + kTile - 1) / kTile + 1;            // scan tiles
+  const int64_t drtiles = (rc + kRadixTile - 1) / kRadixTile + 1;  // radix tiles over records
+  const int64_t ptiles = (pc + kRadixTile - 1) / kRadixTile + 1;   // radix tiles over pairs
   w.dkeys_a = (uint32_t*)take(4 * (size_t)rc);
   w.dvals_a = (uint32_t*)take(4 * (size_t)rc);
   w.dkeys_b = (uint32_t*)take(4 * (size_t)rc);
@@ -379,7 +380,7 @@ SortWs sort_ws_layout(char* base, int64_t rc, int64_t pc) {
   w.fixed = (uint32_t*)take(4 * (size_t)kFixedWords);
   // the two scan status arrays are adjacent: [rtiles] then [rtiles]
   w.scan_status = (uint64_t*)take(8 * 2 * (size_t)rtiles);
-  w.dstatus = (uint32_t*)take(4 * 4 * (size_t)rtiles * kRadix);
+  w.dstatus = (uint32_t*)take(4 * 4 * (size_t)drtiles * kRadix);
   w.pstatus = (uint32_t*)take(4 * (size_t)kMaxPasses * (size_t)ptiles * kRadix);
   w.bytes = off;
   return w;
@@ -431,11 +432,16 @@ extern "C" gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys
     int64_t g = (cap + kTile - 1) / kTile;
     return dim3((unsigned)(g < 1 ? 1 : (g > kPersistentBlocks ? kPersistentBlocks : g)));
   };
+  auto persistent_radix = [](int64_t cap) {
+    int64_t g = (cap + kRadixTile - 1) / kRadixTile;
+    return dim3((unsigned)(g < 1 ? 1 : (g > kPersistentBlocks ? kPersistentBlocks : g)));
+  };
   uint32_t* counters = w.fixed;
   uint32_t* dhist = w.fixed + 64;
   uint32_t* thist = w.fixed + 64 + kMaxPasses * kRadix;
   // 0. zero the counters, histograms and the look-back words of the record-sized stages
-  hipLaunchKernelGGL(clear_front_kernel, grid_for(kFixedWords + 4 * rtiles + 4 * rtiles * kRadix), blk, 0, s,
+  const int64_t drtiles = (record_capacity + kRadixTile - 1) / kRadixTile;
+  hipLaunchKernelGGL(clear_front_kernel, grid_for(kFixedWords + 4 * rtiles + 4 * drtiles * kRadix), blk, 0, s,
                      w.fixed, kFixedWords, (uint32_t*)w.scan_status, (uint32_t*)(w.scan_status + rtiles), w.dstatus,
                      counts, record_capacity);
   GS_LAUNCH_CHECK();
@@ -446,7 +452,7 @@ extern "C" gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys
   // 2. depth sort, 4 passes of 8 bits: a -> b -> a -> b -> a
   for (int p = 0; p < 4; ++p) {
     const bool even = (p % 2) == 0;
-    hipLaunchKernelGGL(radix_pass_kernel, persistent(record_capacity), blk, 0, s, even ? w.dkeys_a : w.dkeys_b,
+    hipLaunchKernelGGL(radix_pass_kernel, persistent_radix(record_capacity), blk, 0, s, even ? w.dkeys_a : w.dkeys_b,
                        even ? w.dvals_a : w.dvals_b, even ? w.dkeys_b : w.dkeys_a, even ? w.dvals_b : w.dvals_a,
                        counts, GS_COUNT_VISIBLE, record_capacity, 8 * p, dhist + p * kRadix, w.dstatus + p * kRadix,
                        (int64_t)4 * kRadix, counters + 1 + p, counts);
@@ -473,7 +479,7 @@ extern "C" gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys
   for (int p = 0; p < tpasses; ++p) {
     uint32_t* kout = (kin == pair_tiles) ? w.ptiles_alt : pair_tiles;
     uint32_t* vout = (vin == pair_records) ? w.precs_alt : pair_records;
-    hipLaunchKernelGGL(radix_pass_kernel, persistent(pair_capacity), blk, 0, s, kin, vin, kout, vout, counts,
+    hipLaunchKernelGGL(radix_pass_kernel, persistent_radix(pair_capacity), blk, 0, s, kin, vin, kout, vout, counts,
                        GS_COUNT_PAIRS, pair_capacity, 8 * p, thist + p * kRadix, w.pstatus + p * kRadix,
                        (int64_t)tpasses * kRadix, counters + 16 + p, counts);
     GS_LAUNCH_CHECK();
