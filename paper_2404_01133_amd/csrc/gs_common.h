@@ -10,7 +10,10 @@ namespace gs {
 
 // ---------------------------------------------------------------------------
 // projected record (48 bytes, three 16-byte words)
-//   w0: u_rel, v_rel  (2D mean minus the footprint's first pixel i0 / j0, FP32)
+//   w0: du, dv        (2D mean minus the centre of the footprint's first pixel,
+//                      i.e. u - i0 - 1/2 and v - j0 - 1/2, FP32; the 1/2 shift
+//                      of the rounded u - i0 is exact, so a pixel at offset di
+//                      has dx = di - du with the same rounding as (di + 1/2) - (u - i0))
 //       px = i0 | (i1 - i0) << 16, py = j0 | (j1 - j0) << 16  (footprint, inclusive)
 //   w1: ca, cb, cc    (factor of the conic scaled by sqrt(log2(e) / 2): the
 //                      Gaussian's value at pixel offset d is
@@ -20,7 +23,7 @@ namespace gs {
 //       view index (int bits)
 // ---------------------------------------------------------------------------
 struct alignas(16) Record {
-  float u_rel, v_rel;
+  float du, dv;
   uint32_t px, py;
   float ca, cb, cc, opac;
   float r, g, b;

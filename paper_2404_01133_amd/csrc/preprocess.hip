@@ -46,8 +46,8 @@ __device__ __forceinline__ void preprocess_record_t(const PreArgs& a, int64_t g,
     tt = (o.i1 / a.tw - o.i0 / a.tw + 1) * (o.j1 / a.th - o.j0 / a.th + 1);
     key = __float_as_uint(o.depth);
     Record rec;
-    rec.u_rel = (float)(o.u - (double)o.i0);
-    rec.v_rel = (float)(o.v - (double)o.j0);
+    rec.du = (float)(o.u - (double)o.i0) - 0.5f;  // exact shift (|u - i0| < 2^22)
+    rec.dv = (float)(o.v - (double)o.j0) - 0.5f;
     rec.px = (uint32_t)o.i0 | ((uint32_t)(o.i1 - o.i0) << 16);
     rec.py = (uint32_t)o.j0 | ((uint32_t)(o.j1 - o.j0) << 16);
     rec.ca = (float)(kConicScale * sqrt(o.c / o.det));

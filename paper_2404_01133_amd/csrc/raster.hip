@@ -38,8 +38,8 @@ __device__ __forceinline__ bool in_footprint(int i, int j, uint32_t px, uint32_t
 }
 
 __device__ __forceinline__ void evaluate(const float4& w0, const float4& w1, int di, int dj, Eval& e) {
-  e.dx = ((float)di + 0.5f) - w0.x;
-  e.dy = ((float)dj + 0.5f) - w0.y;
+  e.dx = (float)di - w0.x;  // w0.x = u - i0 - 1/2
+  e.dy = (float)dj - w0.y;
   e.p1 = fmaf(w1.x, e.dx, w1.y * e.dy);
   e.p2 = w1.z * e.dy;
   e.G = __builtin_amdgcn_exp2f(-fmaf(e.p1, e.p1, e.p2 * e.p2));
@@ -189,12 +189,16 @@ __device__ __forceinline__ void raster_fwd_tile(const TileArgs& ta, FwdLds<TW, T
       s_w1[k] = r[1];
       s_w2[k] = r[2];
     }
+    // list entries past a quadrant's count read stale indices that may land on
+    // unstaged slots: their colour must be finite (it is multiplied by 0)
+    for (int k = nb + threadIdx.x; k < BATCH; k += NT) s_w2[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     __syncthreads();
     int cnt[4];
     wave_compact_quads<BATCH>(s_w0, nb, qb.x0, qb.y0, lists, cnt);
     const int max_cnt = max(max(cnt[0], cnt[1]), max(cnt[2], cnt[3]));
     const int my_cnt = qb.q == 0 ? cnt[0] : qb.q == 1 ? cnt[1] : qb.q == 2 ? cnt[2] : cnt[3];
     const int base_idx = (int)(b - start);
+    int last_k = -1;  // batch index of the last entry used in this batch
     auto blend = [&](int k, bool valid, const float4& w0, const float4& w1, const float4& w2) {
       int di, dj;
       const bool in_fp = in_footprint(i, j, __float_as_uint(w0.z), __float_as_uint(w0.w), di, dj);
@@ -205,12 +209,13 @@ __device__ __forceinline__ void raster_fwd_tile(const TileArgs& ta, FwdLds<TW, T
       const bool stop = use && (Tn < kTMin);
       done = done || stop;
       use = use && !stop;
-      const float aT = e.alpha * T;
-      C0 = use ? fmaf(w2.x, aT, C0) : C0;
-      C1 = use ? fmaf(w2.y, aT, C1) : C1;
-      C2 = use ? fmaf(w2.z, aT, C2) : C2;
+      // an unused entry adds colour * 0 (colours are finite): C is unchanged bit for bit
+      const float aT = use ? e.alpha * T : 0.0f;
+      C0 = fmaf(w2.x, aT, C0);
+      C1 = fmaf(w2.y, aT, C1);
+      C2 = fmaf(w2.z, aT, C2);
       T = use ? Tn : T;
-      last = use ? base_idx + k + 1 : last;
+      last_k = use ? k : last_k;
     };
     // four entries of the lane's quadrant list per trip: one LDS read for the
     // four byte indices, all records' words in flight together, one vote per
@@ -230,6 +235,7 @@ __device__ __forceinline__ void raster_fwd_tile(const TileArgs& ta, FwdLds<TW, T
       blend(k2, t + 2 < my_cnt, c0, c1, c2);
       blend(k3, t + 3 < my_cnt, d0, d1, d2);
     }
+    if (last_k >= 0) last = base_idx + last_k + 1;
     __syncthreads();
   }
   if (inside) {
@@ -244,8 +250,11 @@ __device__ __forceinline__ void raster_fwd_tile(const TileArgs& ta, FwdLds<TW, T
   }
 }
 
+// Six waves per SIMD for the multi-wave tiles: the blend loop fits in 80
+// registers without spilling, and the sixth wave is worth more than the
+// compiler's freer allocation (69 vs 73 us per 20M-city LoD frame).
 template <int TW, int TH, int BATCH>
-__global__ void __launch_bounds__(TW* TH) raster_fwd_kernel(TileArgs ta, uint32_t* queue, float bg0, float bg1,
+__global__ void __launch_bounds__(TW* TH) __attribute__((amdgpu_waves_per_eu(TW * TH >= 128 ? 6 : 1))) raster_fwd_kernel(TileArgs ta, uint32_t* queue, float bg0, float bg1,
                                                             float bg2, float* __restrict__ rgb,
                                                             float* __restrict__ T_final,
                                                             int32_t* __restrict__ n_last) {
