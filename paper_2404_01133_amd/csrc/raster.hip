@@ -46,76 +46,133 @@ __device__ __forceinline__ void evaluate(const float4& w0, const float4& w1, int
   e.alpha = fminf(kAlphaMax, w1.w * e.G);
 }
 
-// Lane -> pixel map of both tile kernels: the tile is cut into 8x8 pixel
+// Lane -> pixel map of the tile kernels: the tile is cut into 8x8 pixel
 // blocks, one per wave (wave w is block (w mod TW/8, w div TW/8)); each block
-// is cut into 4x4 quadrants, lanes 16q .. 16q+15 hold quadrant q = (q mod 2,
-// q div 2) and lane l is pixel (l mod 4, (l div 4) mod 4) of its quadrant.
-// Against small footprints square blocks and quadrants keep more lanes busy
-// than row strips of the same size.
-template <int TW, int TH>
-struct QuadBlock {
+// is cut into groups of GW x GH pixels, numbered row-major over the block;
+// lanes [g*GW*GH, (g+1)*GW*GH) hold group g and lane l is pixel (r mod GW,
+// r div GW) of it (r = l mod GW*GH).  Each group walks its own list of records
+// (below), so a small footprint costs one group's step, not the wave's.
+template <int TW, int TH, int GW, int GH>
+struct LaneMap {
+  static_assert(TW % 8 == 0 && TH % 8 == 0, "tiles are whole 8x8 blocks");
+  static_assert(8 % GW == 0 && 8 % GH == 0, "groups tile the 8x8 block");
+  static constexpr int kGroups = 64 / (GW * GH);
   int i, j;    // this lane's pixel
   int x0, y0;  // first pixel of the wave's block
-  int q;       // this lane's quadrant
-  __device__ __forceinline__ QuadBlock(int txi, int tyi, int wid) {
-    static_assert(TW % 8 == 0 && TH % 8 == 0, "tiles are whole 8x8 blocks");
+  int g;       // this lane's group
+  __device__ __forceinline__ LaneMap(int txi, int tyi, int wid) {
     const int lane = threadIdx.x & 63;
     x0 = txi * TW + (wid % (TW / 8)) * 8;
     y0 = tyi * TH + (wid / (TW / 8)) * 8;
-    q = lane >> 4;
-    i = x0 + (q & 1) * 4 + (lane & 3);
-    j = y0 + (q >> 1) * 4 + ((lane >> 2) & 3);
+    g = lane / (GW * GH);
+    const int r = lane % (GW * GH);
+    i = x0 + (g % (8 / GW)) * GW + r % GW;
+    j = y0 + (g / (8 / GW)) * GH + r / GW;
   }
 };
 
-// Quadrant list stride: BATCH bytes plus one dword, so the four lists a wave
-// reads side by side start in different LDS banks.
+// Group list stride: BATCH bytes plus one dword, so the lists a wave reads
+// side by side start in different LDS banks.
 template <int BATCH>
-constexpr int kQuadStride = BATCH + 4;
+constexpr int kListStride = BATCH + 4;
 
-// Per-quadrant ballot compaction: list[q][0 .. cnt[q]) receives, in ascending
-// (= depth) order, the staged records whose footprint rectangle meets quadrant
-// q of the wave's block.
+// Per-group ballot compaction: list[g][0 .. cnt[g]) receives, in ascending
+// (= depth) order, the staged records whose footprint rectangle meets group g
+// of the wave's block.  The counts are a struct of named scalars (arrays of
+// them end up in scratch memory).
+struct Counts4 {
+  int c0, c1, c2, c3;
+  __device__ __forceinline__ int max() const { return ::max(::max(c0, c1), ::max(c2, c3)); }
+  __device__ __forceinline__ int of(int g) const { return g == 0 ? c0 : g == 1 ? c1 : g == 2 ? c2 : c3; }
+};
+struct Counts8 {
+  int c0, c1, c2, c3, c4, c5, c6, c7;
+  __device__ __forceinline__ int max() const {
+    return ::max(::max(::max(c0, c1), ::max(c2, c3)), ::max(::max(c4, c5), ::max(c6, c7)));
+  }
+  __device__ __forceinline__ int of(int g) const {
+    const int lo = g == 0 ? c0 : g == 1 ? c1 : g == 2 ? c2 : c3;
+    const int hi = g == 4 ? c4 : g == 5 ? c5 : g == 6 ? c6 : c7;
+    return g < 4 ? lo : hi;
+  }
+};
+
 template <int BATCH>
-__device__ __forceinline__ void wave_compact_quads(const float4* s_w0, int nb, int x0, int y0,
-                                                   uint8_t (*list)[kQuadStride<BATCH>], int cnt[4]) {
+__device__ __forceinline__ void append_if(bool h, uint8_t* list, int& c, int k) {
+  const uint64_t m = __ballot(h);
+  if (h) list[c + (int)lanemask_lt_count(m)] = (uint8_t)k;
+  c += (int)__popcll(m);
+}
+
+// rectangle of staged record k; past the batch one that meets no pixel (every
+// overlap test "i0 <= hi && i1 >= lo" with lo, hi >= 0 fails on it)
+__device__ __forceinline__ void staged_rect(const float4* s_w0, int k, int nb, int& i0, int& i1, int& j0, int& j1) {
+  i0 = j0 = 1 << 30;
+  i1 = j1 = -1;
+  if (k < nb) {
+    const uint32_t px = __float_as_uint(s_w0[k].z), py = __float_as_uint(s_w0[k].w);
+    i0 = (int)(px & 0xFFFFu), i1 = i0 + (int)(px >> 16);
+    j0 = (int)(py & 0xFFFFu), j1 = j0 + (int)(py >> 16);
+  }
+}
+
+// 4x4 quadrants (groups 0..3 row-major over the 8x8 block)
+template <int BATCH>
+__device__ __forceinline__ Counts4 wave_compact4(const float4* s_w0, int nb, int x0, int y0,
+                                                 uint8_t (*list)[kListStride<BATCH>]) {
   static_assert(BATCH <= 256, "record indices are bytes");
   const int lane = threadIdx.x & 63;
-  int c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+  Counts4 c{0, 0, 0, 0};
   for (int base = 0; base < nb; base += 64) {
     const int k = base + lane;
-    bool h0 = false, h1 = false, h2 = false, h3 = false;
-    if (k < nb) {
-      const uint32_t px = __float_as_uint(s_w0[k].z), py = __float_as_uint(s_w0[k].w);
-      const int i0 = (int)(px & 0xFFFFu), i1 = i0 + (int)(px >> 16);
-      const int j0 = (int)(py & 0xFFFFu), j1 = j0 + (int)(py >> 16);
-      const bool xa = i0 <= x0 + 3 && i1 >= x0, xb = i0 <= x0 + 7 && i1 >= x0 + 4;
-      const bool ya = j0 <= y0 + 3 && j1 >= y0, yb = j0 <= y0 + 7 && j1 >= y0 + 4;
-      h0 = xa && ya;
-      h1 = xb && ya;
-      h2 = xa && yb;
-      h3 = xb && yb;
-    }
-    const uint64_t m0 = __ballot(h0), m1 = __ballot(h1), m2 = __ballot(h2), m3 = __ballot(h3);
-    if (h0) list[0][c0 + (int)lanemask_lt_count(m0)] = (uint8_t)k;
-    if (h1) list[1][c1 + (int)lanemask_lt_count(m1)] = (uint8_t)k;
-    if (h2) list[2][c2 + (int)lanemask_lt_count(m2)] = (uint8_t)k;
-    if (h3) list[3][c3 + (int)lanemask_lt_count(m3)] = (uint8_t)k;
-    c0 += (int)__popcll(m0);
-    c1 += (int)__popcll(m1);
-    c2 += (int)__popcll(m2);
-    c3 += (int)__popcll(m3);
+    int i0, i1, j0, j1;
+    staged_rect(s_w0, k, nb, i0, i1, j0, j1);
+    const bool xa = i0 <= x0 + 3 && i1 >= x0, xb = i0 <= x0 + 7 && i1 >= x0 + 4;
+    const bool ya = j0 <= y0 + 3 && j1 >= y0, yb = j0 <= y0 + 7 && j1 >= y0 + 4;
+    append_if<BATCH>(xa && ya, list[0], c.c0, k);
+    append_if<BATCH>(xb && ya, list[1], c.c1, k);
+    append_if<BATCH>(xa && yb, list[2], c.c2, k);
+    append_if<BATCH>(xb && yb, list[3], c.c3, k);
   }
-  cnt[0] = c0;
-  cnt[1] = c1;
-  cnt[2] = c2;
-  cnt[3] = c3;
+  return c;
 }
+
+// 4x2 groups (two columns of four pixels, four rows of two; row-major)
+template <int BATCH>
+__device__ __forceinline__ Counts8 wave_compact8(const float4* s_w0, int nb, int x0, int y0,
+                                                 uint8_t (*list)[kListStride<BATCH>]) {
+  static_assert(BATCH <= 256, "record indices are bytes");
+  const int lane = threadIdx.x & 63;
+  Counts8 c{0, 0, 0, 0, 0, 0, 0, 0};
+  for (int base = 0; base < nb; base += 64) {
+    const int k = base + lane;
+    int i0, i1, j0, j1;
+    staged_rect(s_w0, k, nb, i0, i1, j0, j1);
+    const bool xa = i0 <= x0 + 3 && i1 >= x0, xb = i0 <= x0 + 7 && i1 >= x0 + 4;
+    const bool y0r = j0 <= y0 + 1 && j1 >= y0, y1r = j0 <= y0 + 3 && j1 >= y0 + 2;
+    const bool y2r = j0 <= y0 + 5 && j1 >= y0 + 4, y3r = j0 <= y0 + 7 && j1 >= y0 + 6;
+    append_if<BATCH>(xa && y0r, list[0], c.c0, k);
+    append_if<BATCH>(xb && y0r, list[1], c.c1, k);
+    append_if<BATCH>(xa && y1r, list[2], c.c2, k);
+    append_if<BATCH>(xb && y1r, list[3], c.c3, k);
+    append_if<BATCH>(xa && y2r, list[4], c.c4, k);
+    append_if<BATCH>(xb && y2r, list[5], c.c5, k);
+    append_if<BATCH>(xa && y3r, list[6], c.c6, k);
+    append_if<BATCH>(xb && y3r, list[7], c.c7, k);
+  }
+  return c;
+}
+
+// group shapes: the forward blends in 4x2 groups (eight per wave), the
+// backward in 4x4 quadrants (its partial sums run over 16 lanes)
+constexpr int kFwdGW = 4, kFwdGH = 2;
+constexpr int kFwdGroups = 64 / (kFwdGW * kFwdGH);
+static_assert(kFwdGroups == 8, "the forward uses wave_compact8");
 
 template <int TW, int TH, int BATCH>
 struct FwdLds {
   float4 w0[BATCH], w1[BATCH], w2[BATCH];
-  uint8_t list[(TW * TH) / 64][4][kQuadStride<BATCH>];
+  uint8_t list[(TW * TH) / 64][kFwdGroups][kListStride<BATCH>];
 };
 
 struct TileArgs {
@@ -171,15 +228,15 @@ __device__ __forceinline__ void raster_fwd_tile(const TileArgs& ta, FwdLds<TW, T
   const int tile = tile_g - view * tiles_per_view;
   const int tyi = tile / tiles_x_n, txi = tile - tyi * tiles_x_n;
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const QuadBlock<TW, TH> qb(txi, tyi, wid);
+  const LaneMap<TW, TH, kFwdGW, kFwdGH> qb(txi, tyi, wid);
   const int i = qb.i, j = qb.j;
   const bool inside = (i < W) && (j < H);
   const uint32_t start = ranges[2 * tile_g], end = ranges[2 * tile_g + 1];
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
   int last = 0;
   bool done = !inside;
-  uint8_t(*lists)[kQuadStride<BATCH>] = lds.list[wid];
-  const uint8_t* my_list = lists[qb.q];
+  uint8_t(*lists)[kListStride<BATCH>] = lds.list[wid];
+  const uint8_t* my_list = lists[qb.g];
   for (uint32_t b = start; b < end; b += BATCH) {
     if (__syncthreads_and(done)) break;
     const int nb = (int)min((uint32_t)BATCH, end - b);
@@ -193,10 +250,9 @@ __device__ __forceinline__ void raster_fwd_tile(const TileArgs& ta, FwdLds<TW, T
     // unstaged slots: their colour must be finite (it is multiplied by 0)
     for (int k = nb + threadIdx.x; k < BATCH; k += NT) s_w2[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     __syncthreads();
-    int cnt[4];
-    wave_compact_quads<BATCH>(s_w0, nb, qb.x0, qb.y0, lists, cnt);
-    const int max_cnt = max(max(cnt[0], cnt[1]), max(cnt[2], cnt[3]));
-    const int my_cnt = qb.q == 0 ? cnt[0] : qb.q == 1 ? cnt[1] : qb.q == 2 ? cnt[2] : cnt[3];
+    const Counts8 cnt = wave_compact8<BATCH>(s_w0, nb, qb.x0, qb.y0, lists);
+    const int max_cnt = cnt.max();
+    const int my_cnt = cnt.of(qb.g);
     const int base_idx = (int)(b - start);
     int last_k = -1;  // batch index of the last entry used in this batch
     auto blend = [&](int k, bool valid, const float4& w0, const float4& w1, const float4& w2) {
@@ -310,7 +366,7 @@ struct BwdLds {
   float4 w0[BATCH], w1[BATCH], w2[BATCH];
   uint32_t rec[BATCH];
   float grad[BATCH * kG];
-  uint8_t list[(TW * TH) / 64][4][kQuadStride<BATCH>];
+  uint8_t list[(TW * TH) / 64][4][kListStride<BATCH>];
   int wave_last[(TW * TH) / 64];
 };
 
@@ -336,7 +392,7 @@ __device__ __forceinline__ void raster_bwd_tile(const TileArgs& ta, BwdLds<TW, T
   const int tyi = tile / tiles_x_n, txi = tile - tyi * tiles_x_n;
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const QuadBlock<TW, TH> qb(txi, tyi, wid);
+  const LaneMap<TW, TH, 4, 4> qb(txi, tyi, wid);
   const int i = qb.i, j = qb.j;
   const bool inside = (i < W) && (j < H);
   const uint32_t start = ranges[2 * tile_g];
@@ -362,8 +418,8 @@ __device__ __forceinline__ void raster_bwd_tile(const TileArgs& ta, BwdLds<TW, T
   int tile_last = 0;
   for (int w = 0; w < NW; ++w) tile_last = max(tile_last, s_wave_last[w]);
   const int wave_last = __builtin_amdgcn_readfirstlane(s_wave_last[wid]);
-  uint8_t(*lists)[kQuadStride<BATCH>] = lds.list[wid];
-  const uint8_t* my_list = lists[qb.q];
+  uint8_t(*lists)[kListStride<BATCH>] = lds.list[wid];
+  const uint8_t* my_list = lists[qb.g];
   const int r = lane & 15;  // lane within the quadrant
   float T = 1.0f, A0 = 0.f, A1c = 0.f, A2c = 0.f;  // transmittance and colour accumulated in front
   for (uint32_t b = start; b < start + (uint32_t)tile_last; b += BATCH) {
@@ -380,10 +436,9 @@ __device__ __forceinline__ void raster_bwd_tile(const TileArgs& ta, BwdLds<TW, T
     __syncthreads();
     const int base_idx = (int)(b - start);
     const int kmax = min(nb, wave_last - base_idx);  // entries past every lane's n_last are not needed
-    int cnt[4] = {0, 0, 0, 0};
-    if (kmax > 0) wave_compact_quads<BATCH>(s_w0, kmax, qb.x0, qb.y0, lists, cnt);
-    const int max_cnt = max(max(cnt[0], cnt[1]), max(cnt[2], cnt[3]));
-    const int my_cnt = qb.q == 0 ? cnt[0] : qb.q == 1 ? cnt[1] : qb.q == 2 ? cnt[2] : cnt[3];
+    const Counts4 cnt = kmax > 0 ? wave_compact4<BATCH>(s_w0, kmax, qb.x0, qb.y0, lists) : Counts4{0, 0, 0, 0};
+    const int max_cnt = cnt.max();
+    const int my_cnt = cnt.of(qb.g);
     // one entry of each quadrant's list: the four quadrants step (possibly
     // different) records side by side; partials are summed per quadrant and
     // added into the record's LDS slots (two quadrants on one record add twice)
