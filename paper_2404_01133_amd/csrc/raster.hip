@@ -1,22 +1,22 @@
 // Per-tile alpha compositing (Eq. 1 of the paper) and its adjoint.
 //
 // Forward: one work-group per (view, tile); one lane per pixel, each wave64 an
-// 8x8 pixel block of the tile (a 16x16 tile is four waves), cut into four 4x4
-// quadrants of 16 lanes.  The tile's Gaussians are staged through LDS in
-// batches (coalesced gathers of 48-byte records, one per lane); each quadrant
+// 8x8 pixel block of the tile (a 16x16 tile is four waves), cut into eight
+// 4x2 pixel groups of 8 lanes.  The tile's Gaussians are staged through LDS in
+// batches (coalesced gathers of 48-byte records, one per lane); each group
 // keeps its own depth-ordered list of the staged records whose footprint meets
-// it, and the four quadrants walk their lists side by side (a lane reads the
-// record of its quadrant), so a small footprint occupies one quadrant's step
-// rather than a whole wave's.  A lane leaves the loop when its transmittance
-// would drop below 1e-4; a wave leaves when all its lanes have, the work-group
-// when all waves have (block-wide vote before each batch).
+// it, and the groups walk their lists side by side (a lane reads the record of
+// its group), so a small footprint occupies one group's step rather than a
+// whole wave's.  A lane leaves the loop when its transmittance would drop below
+// 1e-4; a wave leaves when all its lanes have, the work-group when all waves
+// have (block-wide vote before each batch).
 //
-// Backward: the same walk, front to back, bounded by each pixel's n_last, with
-// the blend state recomputed (colour in front is accumulated, colour behind =
-// final colour - accumulated), so nothing per (pixel, Gaussian) is stored.
-// The nine per-Gaussian partial gradients of a wave are summed with DPP row
-// operations, added into LDS across the tile's waves, and flushed with one
-// FP32 atomic per (tile, Gaussian, quantity).
+// Backward: the same walk on 4x4 quadrants of 16 lanes, front to back, bounded
+// by each pixel's n_last, with the blend state recomputed (colour in front is
+// accumulated, colour behind = final colour - accumulated), so nothing per
+// (pixel, Gaussian) is stored.  The nine per-Gaussian partial gradients of a
+// quadrant are summed with DPP row operations, added into LDS across the
+// tile's waves, and flushed with one FP32 atomic per (tile, Gaussian, quantity).
 //
 // Compiled with -ffp-contract=off: alpha is computed by exactly the same
 // operations in both kernels (explicit fmaf), so the backward's recomputed
@@ -246,7 +246,7 @@ __device__ __forceinline__ void raster_fwd_tile(const TileArgs& ta, FwdLds<TW, T
       s_w1[k] = r[1];
       s_w2[k] = r[2];
     }
-    // list entries past a quadrant's count read stale indices that may land on
+    // list entries past a group's count read stale indices that may land on
     // unstaged slots: their colour must be finite (it is multiplied by 0)
     for (int k = nb + threadIdx.x; k < BATCH; k += NT) s_w2[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     __syncthreads();
@@ -273,9 +273,9 @@ __device__ __forceinline__ void raster_fwd_tile(const TileArgs& ta, FwdLds<TW, T
       T = use ? Tn : T;
       last_k = use ? k : last_k;
     };
-    // four entries of the lane's quadrant list per trip: one LDS read for the
+    // four entries of the lane's group list per trip: one LDS read for the
     // four byte indices, all records' words in flight together, one vote per
-    // trip (entries past the quadrant's count are read from stale list bytes,
+    // trip (entries past the group's count are read from stale list bytes,
     // masked into the staged range and not used)
     for (int t = 0; t < max_cnt; t += 4) {
       if (__ballot(!done && t < my_cnt) == 0) break;
