@@ -451,7 +451,9 @@ __device__ __forceinline__ void raster_bwd_tile(const TileArgs& ta, BwdLds<TW, T
       if (__ballot(use) == 0) return;
       const float aT = e.alpha * T;
       const float nA0 = fmaf(w2.x, aT, A0), nA1 = fmaf(w2.y, aT, A1c), nA2 = fmaf(w2.z, aT, A2c);
-      const float inv1ma = 1.0f / (1.0f - e.alpha);
+      // hardware reciprocal (1 ulp): a correctly rounded division costs ~10 instructions
+      // here and the gradient is not bit-compared
+      const float inv1ma = __builtin_amdgcn_rcpf(1.0f - e.alpha);
       // dL/dalpha = sum_c g_c (colour_c T - (colour behind)_c / (1 - alpha))
       const float dalpha = g0 * (w2.x * T - (out0 - nA0) * inv1ma) + g1 * (w2.y * T - (out1 - nA1) * inv1ma) +
                            g2 * (w2.z * T - (out2 - nA2) * inv1ma);
