@@ -54,8 +54,8 @@ FLOPS_PER_EVAL = 22
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by a 512 MiB copy),
 # valid for the kernel sources with the given fingerprint only (see profiles/, *_hbm_traffic.md)
 MEASURED_TRAFFIC = {
-    "raster_fwd_kernel<16,16,256>": (("raster.hip", "project.h", "gs_common.h"), "1cbe68f36c8b84f3", 82.23e6),
-    "preprocess_kernel": (("preprocess.hip", "project.h", "gs_common.h"), "1df5a32e59f9f2dd", 224.87e6),
+    "raster_fwd_kernel<16,16,256>": (("raster.hip", "tile.h", "project.h", "gs_common.h"), "2e688001e55c660d", 82.23e6),
+    "preprocess_kernel": (("preprocess.hip", "project.h", "gs_common.h"), "1df5a32e59f9f2dd", 224.86e6),
 }
 
 

@@ -1,8 +1,8 @@
-// Per-tile alpha compositing (Eq. 1 of the paper) and its adjoint.
+// Per-tile alpha compositing (Eq. 1 of the paper), forward.
 //
-// Forward: one work-group per (view, tile); one lane per pixel, each wave64 an
-// 8x8 pixel block of the tile (a 16x16 tile is four waves), cut into eight
-// 4x2 pixel groups of 8 lanes.  The tile's Gaussians are staged through LDS in
+// One work-group per (view, tile); one lane per pixel, each wave64 an 8x8
+// pixel block of the tile (a 16x16 tile is four waves), cut into eight 4x2
+// pixel groups of 8 lanes.  The tile's Gaussians are staged through LDS in
 // batches (coalesced gathers of 48-byte records, one per lane); each group
 // keeps its own depth-ordered list of the staged records whose footprint meets
 // it, and the groups walk their lists side by side (a lane reads the record of
@@ -11,157 +11,13 @@
 // 1e-4; a wave leaves when all its lanes have, the work-group when all waves
 // have (block-wide vote before each batch).
 //
-// Backward: the same walk on 4x4 quadrants of 16 lanes, front to back, bounded
-// by each pixel's n_last, with the blend state recomputed (colour in front is
-// accumulated, colour behind = final colour - accumulated), so nothing per
-// (pixel, Gaussian) is stored.  The nine per-Gaussian partial gradients of a
-// quadrant are summed with DPP row operations, added into LDS across the
-// tile's waves, and flushed with one FP32 atomic per (tile, Gaussian, quantity).
-//
 // Compiled with -ffp-contract=off: alpha is computed by exactly the same
-// operations in both kernels (explicit fmaf), so the backward's recomputed
+// operations as in the adjoint (explicit fmaf), so the backward's recomputed
 // decisions match the forward's.
-#include "project.h"
+#include "tile.h"
 
 namespace gs {
 namespace {
-
-// Value of a projected Gaussian at pixel offset (dx, dy): exp2(-(p1^2 + p2^2)).
-struct Eval {
-  float dx, dy, p1, p2, G, alpha;
-};
-
-__device__ __forceinline__ bool in_footprint(int i, int j, uint32_t px, uint32_t py, int& di, int& dj) {
-  di = i - (int)(px & 0xFFFFu);
-  dj = j - (int)(py & 0xFFFFu);
-  return ((uint32_t)di <= (px >> 16)) && ((uint32_t)dj <= (py >> 16));
-}
-
-__device__ __forceinline__ void evaluate(const float4& w0, const float4& w1, int di, int dj, Eval& e) {
-  e.dx = (float)di - w0.x;  // w0.x = u - i0 - 1/2
-  e.dy = (float)dj - w0.y;
-  e.p1 = fmaf(w1.x, e.dx, w1.y * e.dy);
-  e.p2 = w1.z * e.dy;
-  e.G = __builtin_amdgcn_exp2f(-fmaf(e.p1, e.p1, e.p2 * e.p2));
-  e.alpha = fminf(kAlphaMax, w1.w * e.G);
-}
-
-// Lane -> pixel map of the tile kernels: the tile is cut into 8x8 pixel
-// blocks, one per wave (wave w is block (w mod TW/8, w div TW/8)); each block
-// is cut into groups of GW x GH pixels, numbered row-major over the block;
-// lanes [g*GW*GH, (g+1)*GW*GH) hold group g and lane l is pixel (r mod GW,
-// r div GW) of it (r = l mod GW*GH).  Each group walks its own list of records
-// (below), so a small footprint costs one group's step, not the wave's.
-template <int TW, int TH, int GW, int GH>
-struct LaneMap {
-  static_assert(TW % 8 == 0 && TH % 8 == 0, "tiles are whole 8x8 blocks");
-  static_assert(8 % GW == 0 && 8 % GH == 0, "groups tile the 8x8 block");
-  static constexpr int kGroups = 64 / (GW * GH);
-  int i, j;    // this lane's pixel
-  int x0, y0;  // first pixel of the wave's block
-  int g;       // this lane's group
-  __device__ __forceinline__ LaneMap(int txi, int tyi, int wid) {
-    const int lane = threadIdx.x & 63;
-    x0 = txi * TW + (wid % (TW / 8)) * 8;
-    y0 = tyi * TH + (wid / (TW / 8)) * 8;
-    g = lane / (GW * GH);
-    const int r = lane % (GW * GH);
-    i = x0 + (g % (8 / GW)) * GW + r % GW;
-    j = y0 + (g / (8 / GW)) * GH + r / GW;
-  }
-};
-
-// Group list stride: BATCH bytes plus one dword, so the lists a wave reads
-// side by side start in different LDS banks.
-template <int BATCH>
-constexpr int kListStride = BATCH + 4;
-
-// Per-group ballot compaction: list[g][0 .. cnt[g]) receives, in ascending
-// (= depth) order, the staged records whose footprint rectangle meets group g
-// of the wave's block.  The counts are a struct of named scalars (arrays of
-// them end up in scratch memory).
-struct Counts4 {
-  int c0, c1, c2, c3;
-  __device__ __forceinline__ int max() const { return ::max(::max(c0, c1), ::max(c2, c3)); }
-  __device__ __forceinline__ int of(int g) const { return g == 0 ? c0 : g == 1 ? c1 : g == 2 ? c2 : c3; }
-};
-struct Counts8 {
-  int c0, c1, c2, c3, c4, c5, c6, c7;
-  __device__ __forceinline__ int max() const {
-    return ::max(::max(::max(c0, c1), ::max(c2, c3)), ::max(::max(c4, c5), ::max(c6, c7)));
-  }
-  __device__ __forceinline__ int of(int g) const {
-    const int lo = g == 0 ? c0 : g == 1 ? c1 : g == 2 ? c2 : c3;
-    const int hi = g == 4 ? c4 : g == 5 ? c5 : g == 6 ? c6 : c7;
-    return g < 4 ? lo : hi;
-  }
-};
-
-template <int BATCH>
-__device__ __forceinline__ void append_if(bool h, uint8_t* list, int& c, int k) {
-  const uint64_t m = __ballot(h);
-  if (h) list[c + (int)lanemask_lt_count(m)] = (uint8_t)k;
-  c += (int)__popcll(m);
-}
-
-// rectangle of staged record k; past the batch one that meets no pixel (every
-// overlap test "i0 <= hi && i1 >= lo" with lo, hi >= 0 fails on it)
-__device__ __forceinline__ void staged_rect(const float4* s_w0, int k, int nb, int& i0, int& i1, int& j0, int& j1) {
-  i0 = j0 = 1 << 30;
-  i1 = j1 = -1;
-  if (k < nb) {
-    const uint32_t px = __float_as_uint(s_w0[k].z), py = __float_as_uint(s_w0[k].w);
-    i0 = (int)(px & 0xFFFFu), i1 = i0 + (int)(px >> 16);
-    j0 = (int)(py & 0xFFFFu), j1 = j0 + (int)(py >> 16);
-  }
-}
-
-// 4x4 quadrants (groups 0..3 row-major over the 8x8 block)
-template <int BATCH>
-__device__ __forceinline__ Counts4 wave_compact4(const float4* s_w0, int nb, int x0, int y0,
-                                                 uint8_t (*list)[kListStride<BATCH>]) {
-  static_assert(BATCH <= 256, "record indices are bytes");
-  const int lane = threadIdx.x & 63;
-  Counts4 c{0, 0, 0, 0};
-  for (int base = 0; base < nb; base += 64) {
-    const int k = base + lane;
-    int i0, i1, j0, j1;
-    staged_rect(s_w0, k, nb, i0, i1, j0, j1);
-    const bool xa = i0 <= x0 + 3 && i1 >= x0, xb = i0 <= x0 + 7 && i1 >= x0 + 4;
-    const bool ya = j0 <= y0 + 3 && j1 >= y0, yb = j0 <= y0 + 7 && j1 >= y0 + 4;
-    append_if<BATCH>(xa && ya, list[0], c.c0, k);
-    append_if<BATCH>(xb && ya, list[1], c.c1, k);
-    append_if<BATCH>(xa && yb, list[2], c.c2, k);
-    append_if<BATCH>(xb && yb, list[3], c.c3, k);
-  }
-  return c;
-}
-
-// 4x2 groups (two columns of four pixels, four rows of two; row-major)
-template <int BATCH>
-__device__ __forceinline__ Counts8 wave_compact8(const float4* s_w0, int nb, int x0, int y0,
-                                                 uint8_t (*list)[kListStride<BATCH>]) {
-  static_assert(BATCH <= 256, "record indices are bytes");
-  const int lane = threadIdx.x & 63;
-  Counts8 c{0, 0, 0, 0, 0, 0, 0, 0};
-  for (int base = 0; base < nb; base += 64) {
-    const int k = base + lane;
-    int i0, i1, j0, j1;
-    staged_rect(s_w0, k, nb, i0, i1, j0, j1);
-    const bool xa = i0 <= x0 + 3 && i1 >= x0, xb = i0 <= x0 + 7 && i1 >= x0 + 4;
-    const bool y0r = j0 <= y0 + 1 && j1 >= y0, y1r = j0 <= y0 + 3 && j1 >= y0 + 2;
-    const bool y2r = j0 <= y0 + 5 && j1 >= y0 + 4, y3r = j0 <= y0 + 7 && j1 >= y0 + 6;
-    append_if<BATCH>(xa && y0r, list[0], c.c0, k);
-    append_if<BATCH>(xb && y0r, list[1], c.c1, k);
-    append_if<BATCH>(xa && y1r, list[2], c.c2, k);
-    append_if<BATCH>(xb && y1r, list[3], c.c3, k);
-    append_if<BATCH>(xa && y2r, list[4], c.c4, k);
-    append_if<BATCH>(xb && y2r, list[5], c.c5, k);
-    append_if<BATCH>(xa && y3r, list[6], c.c6, k);
-    append_if<BATCH>(xb && y3r, list[7], c.c7, k);
-  }
-  return c;
-}
 
 // group shapes: the forward blends in 4x2 groups (eight per wave), the
 // backward in 4x4 quadrants (its partial sums run over 16 lanes)
@@ -174,43 +30,6 @@ struct FwdLds {
   float4 w0[BATCH], w1[BATCH], w2[BATCH];
   uint8_t list[(TW * TH) / 64][kFwdGroups][kListStride<BATCH>];
 };
-
-struct TileArgs {
-  const Record* records;
-  const uint32_t* pair_records;
-  const uint32_t* ranges;
-  int W, H, tiles_x_n, tiles_per_view;
-  int64_t n_tiles;
-};
-
-// Work distribution shared by the tile kernels: either one work-group per tile
-// (queue == nullptr) or persistent work-groups taking tiles from the device
-// queue built by bin_sort, longest lists first.
-//
-// Every work-group ends on exactly one fetch past the end, so those fetches
-// return n_tiles .. n_tiles + gridDim.x - 1; the work-group that draws the last
-// of them knows no other will read the head again and puts it back to zero.
-// A second launch on the same sorted frame (a repeated forward, a second
-// backward) therefore walks the whole queue again.
-template <class Body>
-__device__ __forceinline__ void for_each_tile(const TileArgs& t, uint32_t* queue, int head, Body body) {
-  if (queue == nullptr) {
-    body((int)blockIdx.x);
-    return;
-  }
-  __shared__ uint32_t s_next;
-  for (;;) {
-    if (threadIdx.x == 0) s_next = atomicAdd(&queue[head], 1u);
-    __syncthreads();
-    const uint32_t k = s_next;
-    __syncthreads();
-    if ((int64_t)k >= t.n_tiles) {
-      if (threadIdx.x == 0 && (int64_t)k == t.n_tiles + (int64_t)gridDim.x - 1) atomicExch(&queue[head], 0u);
-      break;
-    }
-    body((int)queue[2 + k]);
-  }
-}
 
 template <int TW, int TH, int BATCH>
 __device__ __forceinline__ void raster_fwd_tile(const TileArgs& ta, FwdLds<TW, TH, BATCH>& lds, int tile_g,
@@ -320,491 +139,6 @@ __global__ void __launch_bounds__(TW* TH) __attribute__((amdgpu_waves_per_eu(TW 
   });
 }
 
-// ---------------------------------------------------------------------------
-// Sums of nine per-lane values over each 16-lane quadrant, all at once.  At
-// butterfly level k (partner lane = lane ^ 2^k, k = 0..3) two quantities share
-// one register: lanes with bit k clear keep the first, lanes with bit k set the
-// second, and each lane adds the partner's copy of the quantity it keeps.  Nine
-// registers become one after the four levels; on return lane 16p + r of
-// quadrant p holds the quadrant's total of value min(r, 8).
-// ---------------------------------------------------------------------------
-template <int CTRL>
-__device__ __forceinline__ float dpp_mov(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-template <int PATTERN>
-__device__ __forceinline__ float swz(float v) {
-  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), PATTERN));
-}
-__device__ __forceinline__ float pack_add1(bool hi, float a, float b) {  // partner lane ^ 1
-  return (hi ? b : a) + dpp_mov<0xB1>(hi ? a : b);                      // quad_perm [1,0,3,2]
-}
-__device__ __forceinline__ float pack_add2(bool hi, float a, float b) {  // partner lane ^ 2
-  return (hi ? b : a) + dpp_mov<0x4E>(hi ? a : b);                      // quad_perm [2,3,0,1]
-}
-
-__device__ __forceinline__ float quad_sum9(const float v[9], int lane) {
-  const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4, b3 = lane & 8;
-  const float r0 = pack_add1(b0, v[0], v[1]);
-  const float r1 = pack_add1(b0, v[2], v[3]);
-  const float r2 = pack_add1(b0, v[4], v[5]);
-  const float r3 = pack_add1(b0, v[6], v[7]);
-  const float r4 = v[8] + dpp_mov<0xB1>(v[8]);
-  const float s0 = pack_add2(b1, r0, r1);
-  const float s1 = pack_add2(b1, r2, r3);
-  const float s2 = r4 + dpp_mov<0x4E>(r4);
-  // ds_swizzle bit-mask mode (and 0x1F, xor m) exchanges with lane ^ m inside 32 lanes
-  const float u0 = (b2 ? s1 : s0) + swz<0x101F>(b2 ? s0 : s1);
-  const float u1 = s2 + swz<0x101F>(s2);
-  return (b3 ? u1 : u0) + swz<0x201F>(b3 ? u0 : u1);
-}
-
-constexpr int kG = 9;  // partials per Gaussian: r, g, b, opacity, A1, A2, Axx, Axy, Ayy
-
-template <int TW, int TH, int BATCH>
-struct BwdLds {
-  float4 w0[BATCH], w1[BATCH], w2[BATCH];
-  uint32_t rec[BATCH];
-  float grad[BATCH * kG];
-  uint8_t list[(TW * TH) / 64][4][kListStride<BATCH>];
-  int wave_last[(TW * TH) / 64];
-};
-
-template <int TW, int TH, int BATCH>
-__device__ __forceinline__ void raster_bwd_tile(const TileArgs& ta, BwdLds<TW, TH, BATCH>& lds, int tile_g,
-                                                const float* __restrict__ rgb, const float* __restrict__ T_final,
-                                                const int32_t* __restrict__ n_last, const float* __restrict__ d_rgb,
-                                                float* __restrict__ grad2d) {
-  constexpr int NT = TW * TH;
-  constexpr int NW = NT / 64;
-  const Record* __restrict__ records = ta.records;
-  const uint32_t* __restrict__ pair_records = ta.pair_records;
-  const uint32_t* __restrict__ ranges = ta.ranges;
-  const int W = ta.W, H = ta.H, tiles_x_n = ta.tiles_x_n, tiles_per_view = ta.tiles_per_view;
-  float4* s_w0 = lds.w0;
-  float4* s_w1 = lds.w1;
-  float4* s_w2 = lds.w2;
-  uint32_t* s_rec = lds.rec;
-  float* s_grad = lds.grad;
-  int* s_wave_last = lds.wave_last;
-  const int view = tile_g / tiles_per_view;
-  const int tile = tile_g - view * tiles_per_view;
-  const int tyi = tile / tiles_x_n, txi = tile - tyi * tiles_x_n;
-  const int lane = threadIdx.x & 63;
-  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const LaneMap<TW, TH, 4, 4> qb(txi, tyi, wid);
-  const int i = qb.i, j = qb.j;
-  const bool inside = (i < W) && (j < H);
-  const uint32_t start = ranges[2 * tile_g];
-  const int64_t plane = (int64_t)H * W;
-  const int64_t pix = (int64_t)j * W + i;
-  float g0 = 0.f, g1 = 0.f, g2 = 0.f, out0 = 0.f, out1 = 0.f, out2 = 0.f;
-  int last = 0;
-  if (inside) {
-    const int64_t o = (int64_t)view * 3 * plane + pix;
-    g0 = d_rgb[o];
-    g1 = d_rgb[o + plane];
-    g2 = d_rgb[o + 2 * plane];
-    out0 = rgb[o];
-    out1 = rgb[o + plane];
-    out2 = rgb[o + 2 * plane];
-    last = n_last[(int64_t)view * plane + pix];
-  }
-  // entries this wave / the tile must walk
-  int wl = last;
-  for (int off = 32; off > 0; off >>= 1) wl = max(wl, __shfl_xor(wl, off, 64));
-  if (lane == 0) s_wave_last[wid] = wl;
-  __syncthreads();
-  int tile_last = 0;
-  for (int w = 0; w < NW; ++w) tile_last = max(tile_last, s_wave_last[w]);
-  const int wave_last = __builtin_amdgcn_readfirstlane(s_wave_last[wid]);
-  uint8_t(*lists)[kListStride<BATCH>] = lds.list[wid];
-  const uint8_t* my_list = lists[qb.g];
-  const int r = lane & 15;  // lane within the quadrant
-  float T = 1.0f, A0 = 0.f, A1c = 0.f, A2c = 0.f;  // transmittance and colour accumulated in front
-  for (uint32_t b = start; b < start + (uint32_t)tile_last; b += BATCH) {
-    const int nb = (int)min((uint32_t)BATCH, start + (uint32_t)tile_last - b);
-    for (int k = threadIdx.x; k < nb; k += NT) {
-      const uint32_t rid = pair_records[b + k];
-      const float4* rp = reinterpret_cast<const float4*>(&records[rid]);
-      s_w0[k] = rp[0];
-      s_w1[k] = rp[1];
-      s_w2[k] = rp[2];
-      s_rec[k] = rid;
-    }
-    for (int k = threadIdx.x; k < nb * kG; k += NT) s_grad[k] = 0.0f;
-    __syncthreads();
-    const int base_idx = (int)(b - start);
-    const int kmax = min(nb, wave_last - base_idx);  // entries past every lane's n_last are not needed
-    const Counts4 cnt = kmax > 0 ? wave_compact4<BATCH>(s_w0, kmax, qb.x0, qb.y0, lists) : Counts4{0, 0, 0, 0};
-    const int max_cnt = cnt.max();
-    const int my_cnt = cnt.of(qb.g);
-    // one entry of each quadrant's list: the four quadrants step (possibly
-    // different) records side by side; partials are summed per quadrant and
-    // added into the record's LDS slots (two quadrants on one record add twice)
-    auto step = [&](int k, bool valid, const float4& w0, const float4& w1, const float4& w2) {
-      int di, dj;
-      const bool in_fp = in_footprint(i, j, __float_as_uint(w0.z), __float_as_uint(w0.w), di, dj);
-      Eval e;
-      evaluate(w0, w1, di, dj, e);
-      const bool use = valid && (base_idx + k < last) && in_fp && (e.alpha >= kAlphaMin);
-      if (__ballot(use) == 0) return;
-      const float aT = e.alpha * T;
-      const float nA0 = fmaf(w2.x, aT, A0), nA1 = fmaf(w2.y, aT, A1c), nA2 = fmaf(w2.z, aT, A2c);
-      // hardware reciprocal (1 ulp): a correctly rounded division costs ~10 instructions
-      // here and the gradient is not bit-compared
-      const float inv1ma = __builtin_amdgcn_rcpf(1.0f - e.alpha);
-      // dL/dalpha = sum_c g_c (colour_c T - (colour behind)_c / (1 - alpha))
-      const float dalpha = g0 * (w2.x * T - (out0 - nA0) * inv1ma) + g1 * (w2.y * T - (out1 - nA1) * inv1ma) +
-                           g2 * (w2.z * T - (out2 - nA2) * inv1ma);
-      const bool unclamped = use && (w1.w * e.G <= kAlphaMax);
-      // dL/dQ with G = exp2(-Q): dG/dQ = -ln2 G
-      const float gQ = unclamped ? -0.69314718055994531f * dalpha * w1.w * e.G : 0.0f;
-      float c[kG];
-      c[0] = use ? aT * g0 : 0.0f;
-      c[1] = use ? aT * g1 : 0.0f;
-      c[2] = use ? aT * g2 : 0.0f;
-      c[3] = unclamped ? dalpha * e.G : 0.0f;
-      c[4] = gQ * e.p1;
-      c[5] = gQ * e.p2;
-      c[6] = gQ * e.dx * e.dx;
-      c[7] = gQ * e.dx * e.dy;
-      c[8] = gQ * e.dy * e.dy;
-      A0 = use ? nA0 : A0;
-      A1c = use ? nA1 : A1c;
-      A2c = use ? nA2 : A2c;
-      T = use ? T * (1.0f - e.alpha) : T;
-      const float sum = quad_sum9(c, lane);
-      if (valid && r < kG && sum != 0.0f) atomicAdd(&s_grad[k * kG + r], sum);
-    };
-    // two entries of the lane's quadrant list per trip, byte indices in one LDS
-    // read (entries past the quadrant's count: stale bytes, masked, not used)
-    for (int t = 0; t < max_cnt; t += 2) {
-      const uint32_t pk = *reinterpret_cast<const uint16_t*>(&my_list[t]);
-      const int ka = (int)(pk & (BATCH - 1)), kb = (int)((pk >> 8) & (BATCH - 1));
-      const float4 a0 = s_w0[ka], a1 = s_w1[ka], a2 = s_w2[ka];
-      const float4 b0 = s_w0[kb], b1 = s_w1[kb], b2 = s_w2[kb];
-      step(ka, t < my_cnt, a0, a1, a2);
-      step(kb, t + 1 < my_cnt, b0, b1, b2);
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < nb * kG; t += NT) {
-      const float v = s_grad[t];
-      if (v != 0.0f) unsafeAtomicAdd(&grad2d[(int64_t)s_rec[t / kG] * kG + (t % kG)], v);
-    }
-    __syncthreads();
-  }
-}
-
-template <int TW, int TH, int BATCH>
-__global__ void __launch_bounds__(TW* TH) raster_bwd_kernel(TileArgs ta, uint32_t* queue,
-                                                            const float* __restrict__ rgb,
-                                                            const float* __restrict__ T_final,
-                                                            const int32_t* __restrict__ n_last,
-                                                            const float* __restrict__ d_rgb,
-                                                            float* __restrict__ grad2d) {
-  __shared__ BwdLds<TW, TH, BATCH> lds;
-  for_each_tile(ta, queue, 1, [&](int tile_g) {
-    raster_bwd_tile<TW, TH, BATCH>(ta, lds, tile_g, rgb, T_final, n_last, d_rgb, grad2d);
-  });
-}
-
-// ---------------------------------------------------------------------------
-// preprocess adjoint: per record, chain the 2D partials back to the parameters
-// ---------------------------------------------------------------------------
-struct BwdArgs {
-  LevelPtrs lv[kMaxLevels];
-  gs_gaussian_grads gr[kMaxLevels];
-  const int64_t* lvl_off;
-  const int8_t* level;
-  const int64_t* offsets;
-  const uint32_t* gather;  // point-wise selection: record -> index within its level
-  const gs_camera* cams;
-  int64_t capacity;
-  int32_t B, L, V, W, H, sh_degree;
-  int32_t segs;  // segments per view: B (block-wise) or L (point-wise)
-};
-
-// ATOMIC: a no-return FP32 atomic add (records of one Gaussian may run
-// concurrently when views share it; with one view each address receives one
-// add, so the result is the plain sum).  The adds do not wait for memory, so a
-// record's 59 updates are all in flight together; a read-modify-write waits for
-// each load, since the compiler must keep the updates in order.  !ATOMIC: plain
-// read-modify-write, for a thread that owns every record of its Gaussian.
-template <bool ATOMIC>
-__device__ __forceinline__ void accumulate(float* p, float v) {
-  if (ATOMIC) unsafeAtomicAdd(p, v);
-  else *p += v;
-}
-
-// Adjoint of the SH colour, FP32, one basis term at a time (no basis arrays
-// live): dL/df_{k,c} = Y_k g_c and dL/d(direction) += (sum_c g_c f_{k,c}) grad Y_k.
-template <bool ATOMIC, bool HALF>
-__device__ __forceinline__ void sh_adjoint(float x, float y, float z, int deg, const void* __restrict__ sh, int64_t n,
-                                           int64_t gi, const float g[3], float* __restrict__ dsh, float gdir[3]) {
-  auto term = [&](int k, float Y, float dx, float dy, float dz) {
-    const float f0 = attr<HALF>(sh, (int64_t)(3 * k + 0) * n + gi);
-    const float f1 = attr<HALF>(sh, (int64_t)(3 * k + 1) * n + gi);
-    const float f2 = attr<HALF>(sh, (int64_t)(3 * k + 2) * n + gi);
-    const float w = fmaf(g[0], f0, fmaf(g[1], f1, g[2] * f2));
-    gdir[0] = fmaf(w, dx, gdir[0]);
-    gdir[1] = fmaf(w, dy, gdir[1]);
-    gdir[2] = fmaf(w, dz, gdir[2]);
-    if (g[0] != 0.0f) accumulate<ATOMIC>(&dsh[(int64_t)(3 * k + 0) * n + gi], Y * g[0]);
-    if (g[1] != 0.0f) accumulate<ATOMIC>(&dsh[(int64_t)(3 * k + 1) * n + gi], Y * g[1]);
-    if (g[2] != 0.0f) accumulate<ATOMIC>(&dsh[(int64_t)(3 * k + 2) * n + gi], Y * g[2]);
-  };
-  const float k1 = (float)kSH1, k2a = (float)kSH2a, k2b = (float)kSH2b, k2c = (float)kSH2c;
-  const float k3a = (float)kSH3a, k3b = (float)kSH3b, k3c = (float)kSH3c, k3d = (float)kSH3d, k3e = (float)kSH3e;
-  term(0, (float)kSH00, 0.f, 0.f, 0.f);
-  if (deg < 1) return;
-  term(1, -k1 * y, 0.f, -k1, 0.f);
-  term(2, k1 * z, 0.f, 0.f, k1);
-  term(3, -k1 * x, -k1, 0.f, 0.f);
-  if (deg < 2) return;
-  const float xx = x * x, yy = y * y, zz = z * z;
-  term(4, k2a * x * y, k2a * y, k2a * x, 0.f);
-  term(5, -k2a * y * z, 0.f, -k2a * z, -k2a * y);
-  term(6, k2b * (2.f * zz - xx - yy), -2.f * k2b * x, -2.f * k2b * y, 4.f * k2b * z);
-  term(7, -k2a * x * z, -k2a * z, 0.f, -k2a * x);
-  term(8, k2c * (xx - yy), 2.f * k2c * x, -2.f * k2c * y, 0.f);
-  if (deg < 3) return;
-  term(9, -k3a * y * (3.f * xx - yy), -6.f * k3a * x * y, -3.f * k3a * (xx - yy), 0.f);
-  term(10, k3b * x * y * z, k3b * y * z, k3b * x * z, k3b * x * y);
-  term(11, -k3c * y * (4.f * zz - xx - yy), 2.f * k3c * x * y, -k3c * (4.f * zz - xx - 3.f * yy), -8.f * k3c * y * z);
-  term(12, k3d * z * (2.f * zz - 3.f * xx - 3.f * yy), -6.f * k3d * x * z, -6.f * k3d * y * z,
-       k3d * (6.f * zz - 3.f * xx - 3.f * yy));
-  term(13, -k3c * x * (4.f * zz - xx - yy), -k3c * (4.f * zz - 3.f * xx - yy), 2.f * k3c * x * y, -8.f * k3c * x * z);
-  term(14, k3e * z * (xx - yy), 2.f * k3e * x * z, -2.f * k3e * y * z, k3e * (xx - yy));
-  term(15, -k3a * x * (xx - 3.f * yy), -3.f * k3a * (xx - yy), 6.f * k3a * x * y, 0.f);
-}
-
-template <bool ATOMIC, bool HALF>
-__device__ __forceinline__ void preprocess_bwd_record_t(const BwdArgs& a, const Record* __restrict__ records,
-                                                        const float* __restrict__ grad2d, int64_t g, int v, int l,
-                                                        int64_t gi) {
-  float p2[kG];
-  bool any = false;
-#pragma unroll
-  for (int q = 0; q < kG; ++q) {
-    p2[q] = grad2d[g * kG + q];
-    any |= p2[q] != 0.0f;
-  }
-  if (!any) return;
-  const LevelPtrs& L = a.lv[l];
-  const gs_gaussian_grads& G = a.gr[l];
-  const int64_t n = L.n;
-  const gs_camera& cam = a.cams[v];
-  // A record with a non-zero 2D gradient was visible in the forward pass, so
-  // the projection below (same code, same inputs) takes the same decisions.
-  // ---- colour first (FP32): clamped channels (record colour exactly 0) pass no gradient
-  double dm_col[3];
-  {
-    const float4 w2 = reinterpret_cast<const float4*>(&records[g])[2];
-    const float grgb[3] = {w2.x > 0.0f ? p2[0] : 0.0f, w2.y > 0.0f ? p2[1] : 0.0f, w2.z > 0.0f ? p2[2] : 0.0f};
-    double C[3];
-    camera_centre(cam, C);
-    const double d0 = (double)L.means[gi] - C[0], d1 = (double)L.means[n + gi] - C[1],
-                 d2 = (double)L.means[2 * n + gi] - C[2];
-    const double dn = sqrt((d0 * d0 + d1 * d1) + d2 * d2);
-    const float dir[3] = {(float)(d0 / dn), (float)(d1 / dn), (float)(d2 / dn)};
-    float gdir[3] = {0.0f, 0.0f, 0.0f};
-    sh_adjoint<ATOMIC, HALF>(dir[0], dir[1], dir[2], a.sh_degree < L.sh_deg ? a.sh_degree : L.sh_deg, L.sh, n, gi,
-                             grgb, G.sh, gdir);
-    const float gd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
-    for (int k = 0; k < 3; ++k) dm_col[k] = (double)(gdir[k] - dir[k] * gd) / dn;
-  }
-  // ---- geometry adjoint (FP32); the guard-band clamp is decided in FP64 exactly as in the forward pass
-  const double* R64 = cam.R;
-  const double m0 = L.means[gi], m1 = L.means[n + gi], m2 = L.means[2 * n + gi];
-  const double tx64 = ((R64[0] * m0 + R64[1] * m1) + R64[2] * m2) + cam.t[0];
-  const double ty64 = ((R64[3] * m0 + R64[4] * m1) + R64[5] * m2) + cam.t[1];
-  const double tz64 = ((R64[6] * m0 + R64[7] * m1) + R64[8] * m2) + cam.t[2];
-  const double rz64 = 1.0 / tz64;
-  const double ux64 = tx64 * rz64, uy64 = ty64 * rz64;
-  const double limx = 1.3 * ((0.5 * a.W) / cam.fx), limy = 1.3 * ((0.5 * a.H) / cam.fy);
-  const double uxc64 = dmin_(limx, dmax_(-limx, ux64)), uyc64 = dmin_(limy, dmax_(-limy, uy64));
-  const bool clamp_x = uxc64 != ux64, clamp_y = uyc64 != uy64;
-  const float tx = (float)tx64, ty = (float)ty64, rz = (float)rz64;
-  const float uxc = (float)uxc64, uyc = (float)uyc64;
-  const float fx = (float)cam.fx, fy = (float)cam.fy;
-  float Rc[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) Rc[k] = (float)R64[k];
-  // rotation of the normalised quaternion, scales
-  const float qa = attr<HALF>(L.quats, gi), qb = attr<HALF>(L.quats, n + gi), qc = attr<HALF>(L.quats, 2 * n + gi),
-              qd_ = attr<HALF>(L.quats, 3 * n + gi);
-  const float qinv = 1.0f / sqrtf(qa * qa + qb * qb + qc * qc + qd_ * qd_);
-  const float w = qa * qinv, x = qb * qinv, y = qc * qinv, z = qd_ * qinv;
-  float Rq[3][3];
-  Rq[0][0] = 1.f - 2.f * (y * y + z * z);
-  Rq[0][1] = 2.f * (x * y - w * z);
-  Rq[0][2] = 2.f * (x * z + w * y);
-  Rq[1][0] = 2.f * (x * y + w * z);
-  Rq[1][1] = 1.f - 2.f * (x * x + z * z);
-  Rq[1][2] = 2.f * (y * z - w * x);
-  Rq[2][0] = 2.f * (x * z - w * y);
-  Rq[2][1] = 2.f * (y * z + w * x);
-  Rq[2][2] = 1.f - 2.f * (x * x + y * y);
-  const float sc[3] = {attr<HALF>(L.scales, gi), attr<HALF>(L.scales, n + gi), attr<HALF>(L.scales, 2 * n + gi)};
-  float WL[3][3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-      WL[i][j] = (Rc[3 * i] * Rq[0][j] + Rc[3 * i + 1] * Rq[1][j] + Rc[3 * i + 2] * Rq[2][j]) * sc[j];
-  const float J00 = fx * rz, J02 = -(fx * uxc) * rz, J11 = fy * rz, J12 = -(fy * uyc) * rz;
-  float M[2][3];
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    M[0][j] = J00 * WL[0][j] + J02 * WL[2][j];
-    M[1][j] = J11 * WL[1][j] + J12 * WL[2][j];
-  }
-  const float n0 = M[0][0] * M[0][0] + M[0][1] * M[0][1] + M[0][2] * M[0][2];
-  const float n1 = M[1][0] * M[1][0] + M[1][1] * M[1][1] + M[1][2] * M[1][2];
-  const float sb = M[0][0] * M[1][0] + M[0][1] * M[1][1] + M[0][2] * M[1][2];
-  const float sa = n0 + 0.3f, sc2 = n1 + 0.3f;
-  const float cr0 = M[0][1] * M[1][2] - M[0][2] * M[1][1];
-  const float cr1 = M[0][2] * M[1][0] - M[0][0] * M[1][2];
-  const float cr2 = M[0][0] * M[1][1] - M[0][1] * M[1][0];
-  const float det = cr0 * cr0 + cr1 * cr1 + cr2 * cr2 + 0.3f * (n0 + n1) + 0.09f;
-  // ---- 2D mean and conic partials ----
-  const float kS = (float)kConicScale, kS2 = (float)kConicScale2;
-  const float ca = kS * sqrtf(sc2 / det);
-  const float cb = -kS * sb / sqrtf(sc2 * det);
-  const float cc = kS / sqrtf(sc2);
-  const float gu = -2.0f * ca * p2[4];
-  const float gv = -2.0f * (cb * p2[4] + cc * p2[5]);
-  const float gA = kS2 * p2[6], gB = 2.0f * kS2 * p2[7], gC = kS2 * p2[8];
-  // conic K = Sigma2D^-1;  dL/dSigma = -K Gk K with Gk = [[gA, gB/2], [gB/2, gC]]
-  const float KA = sc2 / det, KB = -sb / det, KC = sa / det;
-  const float h = 0.5f * gB;
-  const float t00 = gA * KA + h * KB, t01 = gA * KB + h * KC;
-  const float t10 = h * KA + gC * KB, t11 = h * KB + gC * KC;
-  const float S00 = -(KA * t00 + KB * t10);
-  const float S01 = -(KA * t01 + KB * t11);
-  const float S11 = -(KB * t01 + KC * t11);
-  // Sigma2D = M M^T + 0.3 I -> dL/dM = 2 Gs M; M = J WL; WL = R_cam Rq diag(s), one column at a time
-  float dJ00 = 0.f, dJ02 = 0.f, dJ11 = 0.f, dJ12 = 0.f;
-  float ds[3], dRq[3][3];
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    const float dM0 = 2.0f * (S00 * M[0][j] + S01 * M[1][j]);
-    const float dM1 = 2.0f * (S01 * M[0][j] + S11 * M[1][j]);
-    dJ00 += dM0 * WL[0][j];
-    dJ02 += dM0 * WL[2][j];
-    dJ11 += dM1 * WL[1][j];
-    dJ12 += dM1 * WL[2][j];
-    const float dW0 = J00 * dM0, dW1 = J11 * dM1, dW2 = J02 * dM0 + J12 * dM1;
-    float acc = 0.f;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const float dLm = Rc[i] * dW0 + Rc[3 + i] * dW1 + Rc[6 + i] * dW2;  // (R_cam^T dWL)[i][j]
-      acc += Rq[i][j] * dLm;
-      dRq[i][j] = sc[j] * dLm;
-    }
-    ds[j] = acc;
-  }
-  float dq[4];
-  dq[0] = 2.f * (-z * dRq[0][1] + y * dRq[0][2] + z * dRq[1][0] - x * dRq[1][2] - y * dRq[2][0] + x * dRq[2][1]);
-  dq[1] = 2.f * (y * dRq[0][1] + z * dRq[0][2] + y * dRq[1][0] - w * dRq[1][2] + z * dRq[2][0] + w * dRq[2][1]) -
-          4.f * x * (dRq[1][1] + dRq[2][2]);
-  dq[2] = 2.f * (x * dRq[0][1] + w * dRq[0][2] + x * dRq[1][0] + z * dRq[1][2] - w * dRq[2][0] + z * dRq[2][1]) -
-          4.f * y * (dRq[0][0] + dRq[2][2]);
-  dq[3] = 2.f * (-w * dRq[0][1] + x * dRq[0][2] + w * dRq[1][0] + y * dRq[1][2] + x * dRq[2][0] + y * dRq[2][1]) -
-          4.f * z * (dRq[0][0] + dRq[1][1]);
-  const float qdot = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
-  const float qn[4] = {w, x, y, z};
-  float gq[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) gq[k] = (dq[k] - qn[k] * qdot) * qinv;
-  // J(t) and (u, v)(t)
-  const float rz2 = rz * rz;
-  float dt0 = gu * fx * rz, dt1 = gv * fy * rz;
-  float dt2 = -gu * fx * tx * rz2 - gv * fy * ty * rz2 - dJ00 * fx * rz2 - dJ11 * fy * rz2;
-  if (!clamp_x) {
-    dt0 += -dJ02 * fx * rz2;
-    dt2 += dJ02 * 2.0f * fx * tx * rz2 * rz;
-  } else {
-    dt2 += dJ02 * fx * uxc * rz2;
-  }
-  if (!clamp_y) {
-    dt1 += -dJ12 * fy * rz2;
-    dt2 += dJ12 * 2.0f * fy * ty * rz2 * rz;
-  } else {
-    dt2 += dJ12 * fy * uyc * rz2;
-  }
-  float dm[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) dm[k] = Rc[k] * dt0 + Rc[3 + k] * dt1 + Rc[6 + k] * dt2 + (float)dm_col[k];
-  for (int k = 0; k < 3; ++k) {
-    accumulate<ATOMIC>(&G.means[k * n + gi], dm[k]);
-    accumulate<ATOMIC>(&G.scales[k * n + gi], ds[k]);
-  }
-  for (int k = 0; k < 4; ++k) accumulate<ATOMIC>(&G.quats[k * n + gi], gq[k]);
-  accumulate<ATOMIC>(&G.opac[gi], p2[3]);
-}
-
-template <bool ATOMIC>
-__device__ __forceinline__ void preprocess_bwd_record(const BwdArgs& a, const Record* __restrict__ records,
-                                                      const float* __restrict__ grad2d, int64_t g, int v, int l,
-                                                      int64_t gi) {
-  if (a.lv[l].half) preprocess_bwd_record_t<ATOMIC, true>(a, records, grad2d, g, v, l, gi);
-  else preprocess_bwd_record_t<ATOMIC, false>(a, records, grad2d, g, v, l, gi);
-}
-
-// View-major: records in index order, gradients added with no-return atomics.
-__global__ void __launch_bounds__(256) preprocess_bwd_kernel(BwdArgs a, const Record* __restrict__ records,
-                                                             const float* __restrict__ grad2d,
-                                                             const int64_t* __restrict__ counts) {
-  int64_t n_rec = counts[GS_COUNT_RECORDS];
-  if (n_rec > a.capacity) n_rec = a.capacity;
-  const int nseg = a.V * a.segs;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_rec; g += stride) {
-    const int p = find_segment(a.offsets, nseg, g);
-    const int v = p / a.segs, b = p - v * a.segs;
-    const int l = a.gather ? b : a.level[p];
-    const int64_t gi = a.gather ? (int64_t)a.gather[g] : a.lvl_off[(int64_t)b * a.L + l] + (g - a.offsets[p]);
-    preprocess_bwd_record<true>(a, records, grad2d, g, v, l, gi);
-  }
-}
-
-// Gaussian-major (every view selected the same records): one thread owns a
-// Gaussian's records in all views, so its gradient is accumulated in place.
-__global__ void __launch_bounds__(256) preprocess_bwd_shared_kernel(BwdArgs a, const Record* __restrict__ records,
-                                                                    const float* __restrict__ grad2d,
-                                                                    const int64_t* __restrict__ counts) {
-  int64_t n_rec = counts[GS_COUNT_RECORDS];
-  if (n_rec > a.capacity) n_rec = a.capacity;
-  const int64_t n_view = a.offsets[a.segs];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_view; i += stride) {
-    const int b = find_segment(a.offsets, a.segs, i);
-    const int l = a.gather ? b : a.level[b];
-    const int64_t gi = a.gather ? (int64_t)a.gather[i] : a.lvl_off[(int64_t)b * a.L + l] + (i - a.offsets[b]);
-    for (int v = 0; v < a.V; ++v) {
-      const int64_t g = (int64_t)v * n_view + i;
-      if (g >= n_rec) break;
-      preprocess_bwd_record<false>(a, records, grad2d, g, v, l, gi);
-    }
-  }
-}
-
-__global__ void clear_floats_kernel(float* __restrict__ p, const int64_t* counts, int64_t cap, int per_record) {
-  int64_t n = counts[GS_COUNT_RECORDS];
-  if (n > cap) n = cap;
-  const int64_t words = n * per_record;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < words; k += stride) p[k] = 0.0f;
-}
-
-// Persistent grid for the queue mode: enough work-groups to fill every CU a few times over.
-inline dim3 tile_grid(int64_t n_tiles, bool queued) {
-  const int64_t cap = 256 * 8;
-  return dim3((unsigned)(queued ? (n_tiles < cap ? (n_tiles > 0 ? n_tiles : 1) : cap) : n_tiles));
-}
-
 template <int TW, int TH>
 void launch_fwd(int batch, const TileArgs& ta, uint32_t* queue, hipStream_t s, const float* bg, float* rgb, float* T,
                 int32_t* nl) {
@@ -821,25 +155,7 @@ void launch_fwd(int batch, const TileArgs& ta, uint32_t* queue, hipStream_t s, c
                        T, nl);
 }
 
-template <int TW, int TH>
-void launch_bwd(int batch, const TileArgs& ta, uint32_t* queue, hipStream_t s, const float* rgb, const float* T,
-                const int32_t* nl, const float* drgb, float* g2d) {
-  constexpr int NT = TW * TH;
-  const dim3 grid = tile_grid(ta.n_tiles, queue != nullptr);
-  if (batch == 64)
-    hipLaunchKernelGGL((raster_bwd_kernel<TW, TH, 64>), grid, dim3(NT), 0, s, ta, queue, rgb, T, nl, drgb, g2d);
-  else if (batch == 128)
-    hipLaunchKernelGGL((raster_bwd_kernel<TW, TH, 128>), grid, dim3(NT), 0, s, ta, queue, rgb, T, nl, drgb, g2d);
-  else
-    hipLaunchKernelGGL((raster_bwd_kernel<TW, TH, 256>), grid, dim3(NT), 0, s, ta, queue, rgb, T, nl, drgb, g2d);
-}
-
-bool batch_supported(int b) { return b == 64 || b == 128 || b == 256; }
-
 }  // namespace
-
-size_t rasterize_bwd_ws_bytes(int64_t rc) { return (size_t)rc * kG * sizeof(float) + 256; }
-
 }  // namespace gs
 
 extern "C" gs_status gs_rasterize_fwd(const void* records, const uint32_t* pair_records, const uint32_t* tile_ranges,
@@ -870,79 +186,3 @@ extern "C" gs_status gs_rasterize_fwd(const void* records, const uint32_t* pair_
   return GS_OK;
 }
 
-extern "C" gs_status gs_rasterize_bwd(const void* records, const uint32_t* pair_records, const uint32_t* tile_ranges,
-                                      uint32_t* tile_queue, int32_t n_views, int32_t width, int32_t height,
-                                      const float* bg,
-                                      const gs_tuning* tuning, const float* rgb, const float* T_final,
-                                      const int32_t* n_last, const float* d_rgb, const gs_gaussians* levels,
-                                      const gs_blocks* blocks, const int8_t* level, const int64_t* offsets,
-                                      const uint32_t* gather, const gs_camera* cams, int32_t sh_degree,
-                                      int64_t record_capacity,
-                                      const int64_t* counts, const gs_gaussian_grads* grads, void* ws,
-                                      size_t ws_bytes, void* stream) {
-  using namespace gs;
-  (void)bg;  // the background enters through the saved forward colour
-  if (!records || !pair_records || !tile_ranges || !tuning || !rgb || !T_final || !n_last || !d_rgb || !levels ||
-      !blocks || (!level && !gather) || !offsets || !cams || !counts || !grads || !ws)
-    return GS_ERR_INVALID_ARG;
-  if (n_views <= 0 || width <= 0 || height <= 0 || width > 65535 || height > 65535) return GS_ERR_INVALID_ARG;
-  if (sh_degree < 0 || sh_degree > 3 || record_capacity <= 0) return GS_ERR_INVALID_ARG;
-  if (blocks->n_levels <= 0 || blocks->n_levels > kMaxLevels) return GS_ERR_INVALID_ARG;
-  if (!gather && (blocks->n_blocks <= 0 || !blocks->lvl_off)) return GS_ERR_INVALID_ARG;
-  const int tw = tuning->tile_w, th = tuning->tile_h;
-  if (!tile_shape_supported(tw, th) || !batch_supported(tuning->batch)) return GS_ERR_UNSUPPORTED;
-  if (ws_bytes < rasterize_bwd_ws_bytes(record_capacity)) return GS_ERR_WORKSPACE;
-  float* grad2d = (float*)ws;
-  const int tx = tiles_x(width, tw), ty = tiles_y(height, th);
-  const int64_t tpv = (int64_t)tx * ty;
-  const int64_t nblocks = tpv * n_views;
-  if (nblocks >= ((int64_t)1 << 31)) return GS_ERR_INVALID_ARG;
-  hipStream_t s = (hipStream_t)stream;
-  int64_t cg = (record_capacity * kG + 255) / 256;
-  hipLaunchKernelGGL(clear_floats_kernel, dim3((unsigned)(cg < 4096 ? (cg < 1 ? 1 : cg) : 4096)), dim3(256), 0, s,
-                     grad2d, counts, record_capacity, kG);
-  GS_LAUNCH_CHECK();
-  const Record* rec = (const Record*)records;
-  const TileArgs ta{rec, pair_records, tile_ranges, width, height, tx, (int)tpv, nblocks};
-  uint32_t* q = ((tuning->flags & GS_TUNE_WORK_QUEUE) && tile_queue) ? tile_queue : nullptr;
-  const int b = tuning->batch;
-  if (tw == 16 && th == 16) launch_bwd<16, 16>(b, ta, q, s, rgb, T_final, n_last, d_rgb, grad2d);
-  else if (tw == 8 && th == 8) launch_bwd<8, 8>(b, ta, q, s, rgb, T_final, n_last, d_rgb, grad2d);
-  else if (tw == 16 && th == 8) launch_bwd<16, 8>(b, ta, q, s, rgb, T_final, n_last, d_rgb, grad2d);
-  else if (tw == 32 && th == 8) launch_bwd<32, 8>(b, ta, q, s, rgb, T_final, n_last, d_rgb, grad2d);
-  else launch_bwd<32, 16>(b, ta, q, s, rgb, T_final, n_last, d_rgb, grad2d);
-  GS_LAUNCH_CHECK();
-  BwdArgs a{};
-  for (int l = 0; l < blocks->n_levels; ++l) {
-    const gs_gaussians& g = levels[l];
-    if (g.sh_degree < 0 || g.sh_degree > 3 || (g.attr_half != 0 && g.attr_half != 1)) return GS_ERR_INVALID_ARG;
-    a.lv[l] = level_ptrs(g);
-    a.gr[l] = grads[l];
-    if (g.n > 0 && (!grads[l].means || !grads[l].scales || !grads[l].quats || !grads[l].opac || !grads[l].sh))
-      return GS_ERR_INVALID_ARG;
-  }
-  a.lvl_off = blocks->lvl_off;
-  a.level = level;
-  a.offsets = offsets;
-  a.gather = gather;
-  a.segs = gather ? blocks->n_levels : blocks->n_blocks;
-  a.cams = cams;
-  a.capacity = record_capacity;
-  a.B = blocks->n_blocks;
-  a.L = blocks->n_levels;
-  a.V = n_views;
-  a.W = width;
-  a.H = height;
-  a.sh_degree = sh_degree;
-  int64_t gb = (record_capacity + 255) / 256;
-  const dim3 gbg((unsigned)(gb < 8192 ? (gb < 1 ? 1 : gb) : 8192));
-  if ((tuning->flags & GS_TUNE_SHARED_SELECTION) && n_views > 1) {
-    int64_t pv = (record_capacity / n_views + 255) / 256;
-    const dim3 gs_grid((unsigned)(pv < 8192 ? (pv < 1 ? 1 : pv) : 8192));
-    hipLaunchKernelGGL(preprocess_bwd_shared_kernel, gs_grid, dim3(256), 0, s, a, rec, grad2d, counts);
-  } else {
-    hipLaunchKernelGGL(preprocess_bwd_kernel, gbg, dim3(256), 0, s, a, rec, grad2d, counts);
-  }
-  GS_LAUNCH_CHECK();
-  return GS_OK;
-}
