@@ -311,10 +311,15 @@ __global__ void queue_hist_kernel(const uint32_t* __restrict__ ranges, int64_t n
     if (s_h[i]) atomicAdd(&qhist[i], s_h[i]);
 }
 
+// Each work-group ranks its tiles inside their bins with LDS atomics, then takes
+// one range per non-empty bin from the global cursors: one global atomic per
+// (work-group, bin) instead of one per tile (same-address atomics serialise).
 __global__ void queue_scatter_kernel(const uint32_t* __restrict__ ranges, int64_t n_tiles,
                                      const uint32_t* __restrict__ qhist, uint32_t* __restrict__ qcur,
                                      uint32_t* __restrict__ queue) {
   __shared__ uint32_t s_base[kQueueBins];
+  __shared__ uint32_t s_cnt[kQueueBins];
+  __shared__ uint32_t s_off[kQueueBins];
   if (threadIdx.x == 0) {
     uint32_t acc = 0;
     for (int i = 0; i < kQueueBins; ++i) {
@@ -326,11 +331,19 @@ __global__ void queue_scatter_kernel(const uint32_t* __restrict__ ranges, int64_
       queue[1] = 0u;
     }
   }
-  __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles; t += stride) {
-    const int bin = queue_bin(ranges, t);
-    queue[2 + s_base[bin] + atomicAdd(&qcur[bin], 1u)] = (uint32_t)t;
+  for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x; t0 < n_tiles; t0 += stride) {
+    for (int i = threadIdx.x; i < kQueueBins; i += blockDim.x) s_cnt[i] = 0u;
+    __syncthreads();
+    const int64_t t = t0 + threadIdx.x;
+    const int bin = t < n_tiles ? queue_bin(ranges, t) : 0;
+    const uint32_t rank = t < n_tiles ? atomicAdd(&s_cnt[bin], 1u) : 0u;
+    __syncthreads();
+    for (int i = threadIdx.x; i < kQueueBins; i += blockDim.x)
+      if (s_cnt[i]) s_off[i] = atomicAdd(&qcur[i], s_cnt[i]);
+    __syncthreads();
+    if (t < n_tiles) queue[2 + s_base[bin] + s_off[bin] + rank] = (uint32_t)t;
+    __syncthreads();
   }
 }
 
