@@ -219,23 +219,64 @@ struct BwdArgs {
   int32_t segs;  // segments per view: B (block-wise) or L (point-wise)
 };
 
-// ATOMIC: a no-return FP32 atomic add (records of one Gaussian may run
-// concurrently when views share it; with one view each address receives one
-// add, so the result is the plain sum).  The adds do not wait for memory, so a
-// record's 59 updates are all in flight together; a read-modify-write waits for
-// each load, since the compiler must keep the updates in order.  !ATOMIC: plain
-// read-modify-write, for a thread that owns every record of its Gaussian.
-template <bool ATOMIC>
-__device__ __forceinline__ void accumulate(float* p, float v) {
-  if (ATOMIC) unsafeAtomicAdd(p, v);
-  else *p += v;
-}
+// Destinations of a record's parameter gradients.
+//
+// AtomicSink adds into the level's gradient arrays with no-return FP32 atomics
+// (records of one Gaussian may run concurrently when views share it; with one
+// view each address receives one add, so the result is the plain sum).  The
+// adds do not wait for memory, so a record's 59 updates are all in flight
+// together, where a read-modify-write chain would wait for each load.
+struct AtomicSink {
+  const gs_gaussian_grads& G;
+  int64_t n, gi;
+  __device__ __forceinline__ void sh(int idx, float v) const {
+    if (v != 0.0f) unsafeAtomicAdd(&G.sh[(int64_t)idx * n + gi], v);
+  }
+  __device__ __forceinline__ void mean(int k, float v) const { unsafeAtomicAdd(&G.means[k * n + gi], v); }
+  __device__ __forceinline__ void scale(int k, float v) const { unsafeAtomicAdd(&G.scales[k * n + gi], v); }
+  __device__ __forceinline__ void quat(int k, float v) const { unsafeAtomicAdd(&G.quats[k * n + gi], v); }
+  __device__ __forceinline__ void opac(float v) const { unsafeAtomicAdd(&G.opac[gi], v); }
+};
+
+// RegisterSink sums the gradients of all records of one Gaussian (a thread
+// that owns them, views in order) and adds the totals to memory once.
+struct RegisterSink {
+  float shv[48], m[3], s[3], q[4], o;
+  __device__ __forceinline__ RegisterSink() {
+#pragma unroll
+    for (int i = 0; i < 48; ++i) shv[i] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) m[i] = s[i] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q[i] = 0.0f;
+    o = 0.0f;
+  }
+  __device__ __forceinline__ void sh(int idx, float v) { shv[idx] += v; }
+  __device__ __forceinline__ void mean(int k, float v) { m[k] += v; }
+  __device__ __forceinline__ void scale(int k, float v) { s[k] += v; }
+  __device__ __forceinline__ void quat(int k, float v) { q[k] += v; }
+  __device__ __forceinline__ void opac(float v) { o += v; }
+  // planes: coefficient planes stored per colour channel ((sh_degree + 1)^2)
+  __device__ __forceinline__ void flush(const gs_gaussian_grads& G, int64_t n, int64_t gi, int planes) const {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      G.means[k * n + gi] += m[k];
+      G.scales[k * n + gi] += s[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) G.quats[k * n + gi] += q[k];
+    G.opac[gi] += o;
+#pragma unroll
+    for (int i = 0; i < 48; ++i)
+      if (i < 3 * planes && shv[i] != 0.0f) G.sh[(int64_t)i * n + gi] += shv[i];
+  }
+};
 
 // Adjoint of the SH colour, FP32, one basis term at a time (no basis arrays
 // live): dL/df_{k,c} = Y_k g_c and dL/d(direction) += (sum_c g_c f_{k,c}) grad Y_k.
-template <bool ATOMIC, bool HALF>
+template <bool HALF, class Sink>
 __device__ __forceinline__ void sh_adjoint(float x, float y, float z, int deg, const void* __restrict__ sh, int64_t n,
-                                           int64_t gi, const float g[3], float* __restrict__ dsh, float gdir[3]) {
+                                           int64_t gi, const float g[3], Sink& sink, float gdir[3]) {
   auto term = [&](int k, float Y, float dx, float dy, float dz) {
     const float f0 = attr<HALF>(sh, (int64_t)(3 * k + 0) * n + gi);
     const float f1 = attr<HALF>(sh, (int64_t)(3 * k + 1) * n + gi);
@@ -244,9 +285,9 @@ __device__ __forceinline__ void sh_adjoint(float x, float y, float z, int deg, c
     gdir[0] = fmaf(w, dx, gdir[0]);
     gdir[1] = fmaf(w, dy, gdir[1]);
     gdir[2] = fmaf(w, dz, gdir[2]);
-    if (g[0] != 0.0f) accumulate<ATOMIC>(&dsh[(int64_t)(3 * k + 0) * n + gi], Y * g[0]);
-    if (g[1] != 0.0f) accumulate<ATOMIC>(&dsh[(int64_t)(3 * k + 1) * n + gi], Y * g[1]);
-    if (g[2] != 0.0f) accumulate<ATOMIC>(&dsh[(int64_t)(3 * k + 2) * n + gi], Y * g[2]);
+    sink.sh(3 * k + 0, Y * g[0]);
+    sink.sh(3 * k + 1, Y * g[1]);
+    sink.sh(3 * k + 2, Y * g[2]);
   };
   const float k1 = (float)kSH1, k2a = (float)kSH2a, k2b = (float)kSH2b, k2c = (float)kSH2c;
   const float k3a = (float)kSH3a, k3b = (float)kSH3b, k3c = (float)kSH3c, k3d = (float)kSH3d, k3e = (float)kSH3e;
@@ -273,10 +314,12 @@ __device__ __forceinline__ void sh_adjoint(float x, float y, float z, int deg, c
   term(15, -k3a * x * (xx - 3.f * yy), -3.f * k3a * (xx - yy), 6.f * k3a * x * y, 0.f);
 }
 
-template <bool ATOMIC, bool HALF>
-__device__ __forceinline__ void preprocess_bwd_record_t(const BwdArgs& a, const Record* __restrict__ records,
+// One record's adjoint; returns false (and adds nothing) for a record whose 2D
+// gradient is zero.
+template <bool HALF, class Sink>
+__device__ __forceinline__ bool preprocess_bwd_record_t(const BwdArgs& a, const Record* __restrict__ records,
                                                         const float* __restrict__ grad2d, int64_t g, int v, int l,
-                                                        int64_t gi) {
+                                                        int64_t gi, Sink& sink) {
   float p2[kG];
   bool any = false;
 #pragma unroll
@@ -284,9 +327,8 @@ __device__ __forceinline__ void preprocess_bwd_record_t(const BwdArgs& a, const 
     p2[q] = grad2d[g * kG + q];
     any |= p2[q] != 0.0f;
   }
-  if (!any) return;
+  if (!any) return false;
   const LevelPtrs& L = a.lv[l];
-  const gs_gaussian_grads& G = a.gr[l];
   const int64_t n = L.n;
   const gs_camera& cam = a.cams[v];
   // A record with a non-zero 2D gradient was visible in the forward pass, so
@@ -303,8 +345,8 @@ __device__ __forceinline__ void preprocess_bwd_record_t(const BwdArgs& a, const 
     const double dn = sqrt((d0 * d0 + d1 * d1) + d2 * d2);
     const float dir[3] = {(float)(d0 / dn), (float)(d1 / dn), (float)(d2 / dn)};
     float gdir[3] = {0.0f, 0.0f, 0.0f};
-    sh_adjoint<ATOMIC, HALF>(dir[0], dir[1], dir[2], a.sh_degree < L.sh_deg ? a.sh_degree : L.sh_deg, L.sh, n, gi,
-                             grgb, G.sh, gdir);
+    sh_adjoint<HALF>(dir[0], dir[1], dir[2], a.sh_degree < L.sh_deg ? a.sh_degree : L.sh_deg, L.sh, n, gi, grgb, sink,
+                     gdir);
     const float gd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
     for (int k = 0; k < 3; ++k) dm_col[k] = (double)(gdir[k] - dir[k] * gd) / dn;
   }
@@ -431,20 +473,39 @@ __device__ __forceinline__ void preprocess_bwd_record_t(const BwdArgs& a, const 
   float dm[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) dm[k] = Rc[k] * dt0 + Rc[3 + k] * dt1 + Rc[6 + k] * dt2 + (float)dm_col[k];
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
-    accumulate<ATOMIC>(&G.means[k * n + gi], dm[k]);
-    accumulate<ATOMIC>(&G.scales[k * n + gi], ds[k]);
+    sink.mean(k, dm[k]);
+    sink.scale(k, ds[k]);
   }
-  for (int k = 0; k < 4; ++k) accumulate<ATOMIC>(&G.quats[k * n + gi], gq[k]);
-  accumulate<ATOMIC>(&G.opac[gi], p2[3]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) sink.quat(k, gq[k]);
+  sink.opac(p2[3]);
+  return true;
 }
 
-template <bool ATOMIC>
 __device__ __forceinline__ void preprocess_bwd_record(const BwdArgs& a, const Record* __restrict__ records,
                                                       const float* __restrict__ grad2d, int64_t g, int v, int l,
                                                       int64_t gi) {
-  if (a.lv[l].half) preprocess_bwd_record_t<ATOMIC, true>(a, records, grad2d, g, v, l, gi);
-  else preprocess_bwd_record_t<ATOMIC, false>(a, records, grad2d, g, v, l, gi);
+  AtomicSink sink{a.gr[l], a.lv[l].n, gi};
+  if (a.lv[l].half) preprocess_bwd_record_t<true>(a, records, grad2d, g, v, l, gi, sink);
+  else preprocess_bwd_record_t<false>(a, records, grad2d, g, v, l, gi, sink);
+}
+
+// All records of Gaussian gi (index i in every view's selection), views in
+// order, summed in registers and added to memory once.
+template <bool HALF>
+__device__ __forceinline__ void preprocess_bwd_gaussian(const BwdArgs& a, const Record* __restrict__ records,
+                                                        const float* __restrict__ grad2d, int64_t n_rec,
+                                                        int64_t n_view, int64_t i, int l, int64_t gi) {
+  RegisterSink acc;
+  bool any = false;
+  for (int v = 0; v < a.V; ++v) {
+    const int64_t g = (int64_t)v * n_view + i;
+    if (g >= n_rec) break;
+    any |= preprocess_bwd_record_t<HALF>(a, records, grad2d, g, v, l, gi, acc);
+  }
+  if (any) acc.flush(a.gr[l], a.lv[l].n, gi, (a.lv[l].sh_deg + 1) * (a.lv[l].sh_deg + 1));
 }
 
 // View-major: records in index order, gradients added with no-return atomics.
@@ -460,12 +521,12 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(BwdArgs a, const Re
     const int v = p / a.segs, b = p - v * a.segs;
     const int l = a.gather ? b : a.level[p];
     const int64_t gi = a.gather ? (int64_t)a.gather[g] : a.lvl_off[(int64_t)b * a.L + l] + (g - a.offsets[p]);
-    preprocess_bwd_record<true>(a, records, grad2d, g, v, l, gi);
+    preprocess_bwd_record(a, records, grad2d, g, v, l, gi);
   }
 }
 
 // Gaussian-major (every view selected the same records): one thread owns a
-// Gaussian's records in all views, so its gradient is accumulated in place.
+// Gaussian's records in all views and sums its gradient in registers.
 __global__ void __launch_bounds__(256) preprocess_bwd_shared_kernel(BwdArgs a, const Record* __restrict__ records,
                                                                     const float* __restrict__ grad2d,
                                                                     const int64_t* __restrict__ counts) {
@@ -477,11 +538,8 @@ __global__ void __launch_bounds__(256) preprocess_bwd_shared_kernel(BwdArgs a, c
     const int b = find_segment(a.offsets, a.segs, i);
     const int l = a.gather ? b : a.level[b];
     const int64_t gi = a.gather ? (int64_t)a.gather[i] : a.lvl_off[(int64_t)b * a.L + l] + (i - a.offsets[b]);
-    for (int v = 0; v < a.V; ++v) {
-      const int64_t g = (int64_t)v * n_view + i;
-      if (g >= n_rec) break;
-      preprocess_bwd_record<false>(a, records, grad2d, g, v, l, gi);
-    }
+    if (a.lv[l].half) preprocess_bwd_gaussian<true>(a, records, grad2d, n_rec, n_view, i, l, gi);
+    else preprocess_bwd_gaussian<false>(a, records, grad2d, n_rec, n_view, i, l, gi);
   }
 }
 
