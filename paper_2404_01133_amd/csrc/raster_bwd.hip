@@ -256,19 +256,32 @@ struct RegisterSink {
   __device__ __forceinline__ void scale(int k, float v) { s[k] += v; }
   __device__ __forceinline__ void quat(int k, float v) { q[k] += v; }
   __device__ __forceinline__ void opac(float v) { o += v; }
-  // planes: coefficient planes stored per colour channel ((sh_degree + 1)^2)
+  // planes: coefficient planes stored per colour channel ((sh_degree + 1)^2).
+  // Every current value is loaded before the first store, so the loads are in
+  // flight together (in a += chain each load would wait for the previous store).
   __device__ __forceinline__ void flush(const gs_gaussian_grads& G, int64_t n, int64_t gi, int planes) const {
+    float cm[3], cs[3], cq[4], csh[48];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      G.means[k * n + gi] += m[k];
-      G.scales[k * n + gi] += s[k];
+      cm[k] = G.means[k * n + gi];
+      cs[k] = G.scales[k * n + gi];
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) G.quats[k * n + gi] += q[k];
-    G.opac[gi] += o;
+    for (int k = 0; k < 4; ++k) cq[k] = G.quats[k * n + gi];
+    const float co = G.opac[gi];
+#pragma unroll
+    for (int i = 0; i < 48; ++i) csh[i] = i < 3 * planes ? G.sh[(int64_t)i * n + gi] : 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      G.means[k * n + gi] = cm[k] + m[k];
+      G.scales[k * n + gi] = cs[k] + s[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) G.quats[k * n + gi] = cq[k] + q[k];
+    G.opac[gi] = co + o;
 #pragma unroll
     for (int i = 0; i < 48; ++i)
-      if (i < 3 * planes && shv[i] != 0.0f) G.sh[(int64_t)i * n + gi] += shv[i];
+      if (i < 3 * planes) G.sh[(int64_t)i * n + gi] = csh[i] + shv[i];
   }
 };
 
@@ -484,12 +497,20 @@ __device__ __forceinline__ bool preprocess_bwd_record_t(const BwdArgs& a, const 
   return true;
 }
 
+template <bool SINGLE>
 __device__ __forceinline__ void preprocess_bwd_record(const BwdArgs& a, const Record* __restrict__ records,
                                                       const float* __restrict__ grad2d, int64_t g, int v, int l,
                                                       int64_t gi) {
-  AtomicSink sink{a.gr[l], a.lv[l].n, gi};
-  if (a.lv[l].half) preprocess_bwd_record_t<true>(a, records, grad2d, g, v, l, gi, sink);
-  else preprocess_bwd_record_t<false>(a, records, grad2d, g, v, l, gi, sink);
+  if constexpr (SINGLE) {
+    RegisterSink acc;
+    const bool any = a.lv[l].half ? preprocess_bwd_record_t<true>(a, records, grad2d, g, v, l, gi, acc)
+                                  : preprocess_bwd_record_t<false>(a, records, grad2d, g, v, l, gi, acc);
+    if (any) acc.flush(a.gr[l], a.lv[l].n, gi, (a.lv[l].sh_deg + 1) * (a.lv[l].sh_deg + 1));
+  } else {
+    AtomicSink sink{a.gr[l], a.lv[l].n, gi};
+    if (a.lv[l].half) preprocess_bwd_record_t<true>(a, records, grad2d, g, v, l, gi, sink);
+    else preprocess_bwd_record_t<false>(a, records, grad2d, g, v, l, gi, sink);
+  }
 }
 
 // All records of Gaussian gi (index i in every view's selection), views in
@@ -508,7 +529,10 @@ __device__ __forceinline__ void preprocess_bwd_gaussian(const BwdArgs& a, const 
   if (any) acc.flush(a.gr[l], a.lv[l].n, gi, (a.lv[l].sh_deg + 1) * (a.lv[l].sh_deg + 1));
 }
 
-// View-major: records in index order, gradients added with no-return atomics.
+// View-major: records in index order, gradients added with no-return atomics
+// (SINGLE: one view, each Gaussian has at most one record: register sums
+// flushed with all loads ahead of the stores).
+template <bool SINGLE>
 __global__ void __launch_bounds__(256) preprocess_bwd_kernel(BwdArgs a, const Record* __restrict__ records,
                                                              const float* __restrict__ grad2d,
                                                              const int64_t* __restrict__ counts) {
@@ -521,7 +545,7 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(BwdArgs a, const Re
     const int v = p / a.segs, b = p - v * a.segs;
     const int l = a.gather ? b : a.level[p];
     const int64_t gi = a.gather ? (int64_t)a.gather[g] : a.lvl_off[(int64_t)b * a.L + l] + (g - a.offsets[p]);
-    preprocess_bwd_record(a, records, grad2d, g, v, l, gi);
+    preprocess_bwd_record<SINGLE>(a, records, grad2d, g, v, l, gi);
   }
 }
 
@@ -640,8 +664,10 @@ extern "C" gs_status gs_rasterize_bwd(const void* records, const uint32_t* pair_
     int64_t pv = (record_capacity / n_views + 255) / 256;
     const dim3 gs_grid((unsigned)(pv < 8192 ? (pv < 1 ? 1 : pv) : 8192));
     hipLaunchKernelGGL(preprocess_bwd_shared_kernel, gs_grid, dim3(256), 0, s, a, rec, grad2d, counts);
+  } else if (n_views == 1) {
+    hipLaunchKernelGGL(preprocess_bwd_kernel<true>, gbg, dim3(256), 0, s, a, rec, grad2d, counts);
   } else {
-    hipLaunchKernelGGL(preprocess_bwd_kernel, gbg, dim3(256), 0, s, a, rec, grad2d, counts);
+    hipLaunchKernelGGL(preprocess_bwd_kernel<false>, gbg, dim3(256), 0, s, a, rec, grad2d, counts);
   }
   GS_LAUNCH_CHECK();
   return GS_OK;
