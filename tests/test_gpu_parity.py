@@ -733,6 +733,36 @@ def test_reduced_precision_levels_frame_and_gradients():
                 assert err <= GRAD_TOL
 
 
+def test_shared_selection_gradients_reduced_precision():
+    """Gaussian-major adjoint (shared selection: one thread per Gaussian sums its
+    views in registers) on a binary16 level with 9 SH planes: images equal the
+    single-view renders and gradients equal the sum of single-view gradients."""
+    g = synth.box_gaussians(20_000, seed=49, extent=((-20, 20), (-20, 20), (0, 8)))
+    scene = render.DeviceScene.single(g).reduced_precision(sh_degrees=(2,), half_levels=(0,))
+    assert scene.levels[0].sh.shape[0] == 9 and scene.levels[0].scales.dtype == torch.float16
+    cams = synth.orbit_views((0.0, 0.0), n_views=3, radius=30.0, height=25.0, width=160, h_px=96)
+    V = len(cams)
+    cams_dev = gs.cameras_to_device(cams)
+    fb = render.Frame(1, V, 160, 96, V * scene.n_finest, 1 << 20,
+                      gs.tuning_struct(16, 16, 256, gs.GS_TUNE_SHARED_SELECTION | gs.GS_TUNE_WORK_QUEUE))
+    render.render_frame(scene, fb, cams_dev, mode=gs.GS_LOD_ALL_FINEST, thresholds=())
+    d = torch.from_numpy(np.random.default_rng(9).normal(size=(V, 3, 96, 160)).astype(np.float32)).cuda()
+    got = _grads_for(scene, fb, cams_dev, d)[0]
+    acc = [scene.levels[0].zeros_like()]
+    for v in range(V):
+        c1 = cams_dev[v * 152:(v + 1) * 152]
+        f1 = render.Frame(1, 1, 160, 96, scene.n_finest, 1 << 18)
+        render.render_frame(scene, f1, c1, mode=gs.GS_LOD_ALL_FINEST, thresholds=())
+        assert torch.equal(f1.rgb[0], fb.rgb[v])
+        render.backward_frame(scene, f1, c1, d[v:v + 1].contiguous(), acc)
+    torch.cuda.synchronize()
+    a = acc[0]
+    for x, y in zip(got, (a.means, a.scales, a.quats, a.opac, a.sh)):
+        yn = y.cpu().numpy()
+        assert x.shape == yn.shape
+        assert np.linalg.norm(yn) > 0 and rel_l2(x, yn) <= 1e-5
+
+
 # ---------------------------------------------------------------------------
 # training-data assignment (Sec. 3.2.2, Eqs. 3-5)
 # ---------------------------------------------------------------------------
