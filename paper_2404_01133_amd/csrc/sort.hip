@@ -31,6 +31,14 @@ constexpr int kScanItems = kItems;
 constexpr int kScanTile = kThreads * kScanItems;
 constexpr int kPersistentBlocks = 1024;
 constexpr int kBigFootprint = 16;  // records touching more tiles are emitted cooperatively
+// emit_kernel's work-groups all finish at about the same time and each adds its
+// tile-digit histogram to device memory, so a single copy would take ~2000
+// same-address atomics per word in a row.  They add into kTileHistCopies
+// partial copies instead (copy blockIdx.x mod kTileHistCopies; copy 0 is the
+// histogram the radix passes read), and emit_big_kernel, which runs next, folds
+// copies 1.. into copy 0.
+constexpr int kTileHistCopies = 8;
+constexpr int64_t kTileHistWords = kMaxPasses * kRadix;  // one copy
 
 // ---------------------------------------------------------------------------
 // zero fill of the small fixed state and of the look-back words of the scans
@@ -183,7 +191,8 @@ __global__ void __launch_bounds__(kThreads) emit_kernel(const Record* __restrict
                                                         uint32_t* __restrict__ hist, uint32_t* __restrict__ pstatus,
                                                         uint32_t* __restrict__ ranges, int64_t range_words,
                                                         uint32_t* __restrict__ big_list,
-                                                        uint32_t* __restrict__ big_count) {
+                                                        uint32_t* __restrict__ big_count,
+                                                        uint32_t* __restrict__ hist_extra) {
   __shared__ uint32_t s_hist[kMaxPasses][kRadix];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -222,9 +231,11 @@ __global__ void __launch_bounds__(kThreads) emit_kernel(const Record* __restrict
       }
   }
   __syncthreads();
+  const int copy = (int)(blockIdx.x % kTileHistCopies);
+  uint32_t* h = copy == 0 ? hist : hist_extra + (int64_t)(copy - 1) * kTileHistWords;
   for (int i = threadIdx.x; i < tpasses * kRadix; i += kThreads) {
     const uint32_t c = (&s_hist[0][0])[i];
-    if (c) atomicAdd(&hist[i], c);
+    if (c) atomicAdd(&h[i], c);
   }
 }
 
@@ -239,9 +250,22 @@ __global__ void __launch_bounds__(kThreads) emit_big_kernel(const Record* __rest
                                                             int tw, int th, int tiles_x_n, int tiles_per_view,
                                                             uint32_t* __restrict__ out_tiles,
                                                             uint32_t* __restrict__ out_records, int tpasses,
-                                                            uint32_t* __restrict__ hist) {
+                                                            uint32_t* __restrict__ hist,
+                                                            const uint32_t* __restrict__ hist_extra) {
   __shared__ uint32_t s_hist[kMaxPasses][kRadix];
   for (int i = threadIdx.x; i < tpasses * kRadix; i += kThreads) (&s_hist[0][0])[i] = 0u;
+  // emit_kernel has finished (same stream): its partial histograms are final
+  if (blockIdx.x == 0) {
+    for (int i = threadIdx.x; i < tpasses * kRadix; i += kThreads) {
+      uint32_t part[kTileHistCopies - 1];
+#pragma unroll
+      for (int c = 0; c < kTileHistCopies - 1; ++c) part[c] = hist_extra[c * kTileHistWords + i];
+      uint32_t sum = 0;
+#pragma unroll
+      for (int c = 0; c < kTileHistCopies - 1; ++c) sum += part[c];
+      if (sum) atomicAdd(&hist[i], sum);
+    }
+  }
   __syncthreads();
   const uint32_t nbig = *big_count;
   for (uint32_t k = blockIdx.x; k < nbig; k += gridDim.x) {
@@ -351,7 +375,9 @@ __global__ void queue_scatter_kernel(const uint32_t* __restrict__ ranges, int64_
 // workspace layout
 // ---------------------------------------------------------------------------
 // tile counters [64], depth + tile digit histograms [2][kMaxPasses][256], queue histogram and cursors
-constexpr int64_t kFixedWords = 64 + 2 * kMaxPasses * kRadix + 2 * 40;
+// [2][40], partial tile-digit histograms of emit_kernel [kTileHistCopies - 1][kMaxPasses][256]
+constexpr int64_t kQueueWords = 2 * 40;
+constexpr int64_t kFixedWords = 64 + 2 * kMaxPasses * kRadix + kQueueWords + (kTileHistCopies - 1) * kTileHistWords;
 
 struct SortWs {
   uint32_t* dkeys_a;      // [rc]
@@ -362,7 +388,7 @@ struct SortWs {
   uint32_t* big_list;     // [rc] visible records with large footprints
   uint32_t* ptiles_alt;   // [pc]
   uint32_t* precs_alt;    // [pc]
-  uint32_t* fixed;        // counters [64], then hist [2][kMaxPasses][256]
+  uint32_t* fixed;        // counters [64], hist [2][kMaxPasses][256], queue words, partial tile hists
   uint64_t* scan_status;  // [2][rtiles]
   uint32_t* dstatus;      // [radix tiles][4][256] (tile-major so a prefix covers every pass)
   uint32_t* pstatus;      // [ptiles][kMaxPasses][256]
@@ -480,11 +506,13 @@ extern "C" gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys
   uint32_t* em_tiles = (tpasses % 2 == 0) ? pair_tiles : w.ptiles_alt;
   uint32_t* em_recs = (tpasses % 2 == 0) ? pair_records : w.precs_alt;
   uint32_t* big_count = counters + 32;
+  uint32_t* thist_extra = w.fixed + 64 + 2 * kMaxPasses * kRadix + kQueueWords;
   hipLaunchKernelGGL(emit_kernel, grid_for(record_capacity), blk, 0, s, (const Record*)records, w.dvals_a, w.pair_off,
                      record_capacity, counts, pair_capacity, tw, th, tx_n, (int)tiles_per_view, em_tiles, em_recs,
-                     tpasses, thist, w.pstatus, tile_ranges, 2 * n_tile_ids, w.big_list, big_count);
+                     tpasses, thist, w.pstatus, tile_ranges, 2 * n_tile_ids, w.big_list, big_count, thist_extra);
   hipLaunchKernelGGL(emit_big_kernel, dim3(256), blk, 0, s, (const Record*)records, w.dvals_a, w.pair_off, w.big_list,
-                     big_count, pair_capacity, tw, th, tx_n, (int)tiles_per_view, em_tiles, em_recs, tpasses, thist);
+                     big_count, pair_capacity, tw, th, tx_n, (int)tiles_per_view, em_tiles, em_recs, tpasses, thist,
+                     thist_extra);
   GS_LAUNCH_CHECK();
   // 5. tile passes
   uint32_t* kin = em_tiles;
