@@ -62,65 +62,132 @@ __global__ void clear_front_kernel(uint32_t* __restrict__ fixed, int64_t fixed_w
 }
 
 // ---------------------------------------------------------------------------
-// 1. compaction of visible records
+// 1. compaction of visible records, in three launches (count, scan, write).
+//    Each scan tile's work is small and all tiles are in flight at once, so a
+//    single pass with decoupled look-back spends most of its time in look-back
+//    rounds and in the same-address tile counter; here tile t's offset is the
+//    prefix of the tile counts, computed by one work-group.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) compact_kernel(const int32_t* __restrict__ tiles_touched,
-                                                           const uint32_t* __restrict__ depth_keys, int64_t cap,
-                                                           uint32_t* __restrict__ keys_out,
-                                                           uint32_t* __restrict__ vals_out, uint64_t* status,
-                                                           uint32_t* tile_counter, uint32_t* __restrict__ hist,
-                                                           int64_t* counts) {
+constexpr int kDepthHistCopies = 8;  // partial depth-digit histograms of the count launch (folded by the scan)
+constexpr int64_t kDepthHistWords = 4 * kRadix;
+
+__device__ __forceinline__ int64_t scan_tiles_of(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
+
+// per tile: number of visible records; depth-digit histograms of their keys
+__global__ void __launch_bounds__(kThreads) compact_count_kernel(const int32_t* __restrict__ tiles_touched,
+                                                                 const uint32_t* __restrict__ depth_keys, int64_t cap,
+                                                                 const int64_t* counts,
+                                                                 uint32_t* __restrict__ tile_count,
+                                                                 uint32_t* __restrict__ hist,
+                                                                 uint32_t* __restrict__ hist_extra) {
   __shared__ uint32_t s_wave[kThreads / 64];
-  __shared__ uint32_t s_tile;
-  __shared__ uint64_t s_excl;
   __shared__ uint32_t s_hist[4][kRadix];
   const int64_t n = count_clamped(counts, GS_COUNT_RECORDS, cap);
-  const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
-  if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0) counts[GS_COUNT_VISIBLE] = 0;
-  if ((int64_t)blockIdx.x >= ntiles) return;  // idle work-groups never touch the tile counter
+  const int64_t ntiles = scan_tiles_of(n);
+  if ((int64_t)blockIdx.x >= ntiles) return;
   for (int i = threadIdx.x; i < 4 * kRadix; i += kThreads) (&s_hist[0][0])[i] = 0u;
-  for (;;) {
-    if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
-    __syncthreads();
-    const int64_t t = s_tile;
-    if (t >= ntiles) break;
+  __syncthreads();
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t base = t * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    uint32_t f[kScanItems];
     uint32_t mine = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
       const int64_t idx = base + k;
-      f[k] = (idx < n && tiles_touched[idx] > 0) ? 1u : 0u;
-      mine += f[k];
-    }
-    uint32_t total;
-    const uint32_t excl_thread = block_excl_scan(mine, s_wave, &total);
-    if (threadIdx.x < 64) {
-      const uint64_t ex = lookback64_wave(status, t, total, counts);
-      if (threadIdx.x == 0) {
-        s_excl = ex;
-        if (t == ntiles - 1) counts[GS_COUNT_VISIBLE] = (int64_t)(ex + total);
-      }
-    }
-    __syncthreads();
-    uint64_t pos = s_excl + excl_thread;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-      if (f[k]) {
-        const int64_t idx = base + k;
+      if (idx < n && tiles_touched[idx] > 0) {
+        ++mine;
         const uint32_t key = depth_keys[idx];
-        keys_out[pos] = key;
-        vals_out[pos] = (uint32_t)idx;
-        ++pos;
 #pragma unroll
         for (int p = 0; p < 4; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
       }
     }
-    __syncthreads();
+    uint32_t total;
+    block_excl_scan(mine, s_wave, &total);
+    if (threadIdx.x == 0) tile_count[t] = total;
   }
+  __syncthreads();
+  // the work-groups finish together: spread their histogram atomics over the copies
+  const int copy = (int)(blockIdx.x % kDepthHistCopies);
+  uint32_t* h = copy == 0 ? hist : hist_extra + (int64_t)(copy - 1) * kDepthHistWords;
   for (int i = threadIdx.x; i < 4 * kRadix; i += kThreads) {
     const uint32_t c = (&s_hist[0][0])[i];
-    if (c) atomicAdd(&hist[i], c);
+    if (c) atomicAdd(&h[i], c);
+  }
+}
+
+// one work-group: exclusive prefix of the tile counts, the visible count, and
+// the partial depth histograms folded into the one the radix passes read
+__global__ void __launch_bounds__(kThreads) compact_scan_kernel(int64_t cap, int64_t* counts,
+                                                                const uint32_t* __restrict__ tile_count,
+                                                                uint32_t* __restrict__ tile_off,
+                                                                uint32_t* __restrict__ hist,
+                                                                const uint32_t* __restrict__ hist_extra) {
+  constexpr int kPer = 4;  // consecutive tiles per thread and round
+  __shared__ uint32_t s_wave[kThreads / 64];
+  const int64_t n = count_clamped(counts, GS_COUNT_RECORDS, cap);
+  const int64_t ntiles = scan_tiles_of(n);
+  uint32_t carry = 0;
+  for (int64_t b = 0; b < ntiles; b += (int64_t)kThreads * kPer) {
+    const int64_t t0 = b + (int64_t)threadIdx.x * kPer;
+    uint32_t c[kPer], mine = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      c[k] = (t0 + k < ntiles) ? tile_count[t0 + k] : 0u;
+      mine += c[k];
+    }
+    uint32_t tot;
+    uint32_t off = carry + block_excl_scan(mine, s_wave, &tot);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      if (t0 + k < ntiles) tile_off[t0 + k] = off;
+      off += c[k];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) counts[GS_COUNT_VISIBLE] = (int64_t)carry;
+  // the count launch has finished (same stream): its partial histograms are final
+  for (int i = threadIdx.x; i < kDepthHistWords; i += kThreads) {
+    uint32_t part[kDepthHistCopies - 1];
+#pragma unroll
+    for (int k = 0; k < kDepthHistCopies - 1; ++k) part[k] = hist_extra[k * kDepthHistWords + i];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kDepthHistCopies - 1; ++k) sum += part[k];
+    hist[i] += sum;
+  }
+}
+
+// per tile: visible records' (depth key, record index) at the tile's offset, in index order
+__global__ void __launch_bounds__(kThreads) compact_write_kernel(const int32_t* __restrict__ tiles_touched,
+                                                                 const uint32_t* __restrict__ depth_keys, int64_t cap,
+                                                                 const int64_t* counts,
+                                                                 const uint32_t* __restrict__ tile_off,
+                                                                 uint32_t* __restrict__ keys_out,
+                                                                 uint32_t* __restrict__ vals_out) {
+  __shared__ uint32_t s_wave[kThreads / 64];
+  const int64_t n = count_clamped(counts, GS_COUNT_RECORDS, cap);
+  const int64_t ntiles = scan_tiles_of(n);
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t base = t * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    const uint32_t tbase = tile_off[t];
+    bool f[kScanItems];
+    uint32_t mine = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      const int64_t idx = base + k;
+      f[k] = idx < n && tiles_touched[idx] > 0;
+      mine += f[k] ? 1u : 0u;
+    }
+    uint32_t total;
+    uint32_t pos = tbase + block_excl_scan(mine, s_wave, &total);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      if (f[k]) {
+        const int64_t idx = base + k;
+        keys_out[pos] = depth_keys[idx];
+        vals_out[pos] = (uint32_t)idx;
+        ++pos;
+      }
+    }
   }
 }
 
@@ -375,9 +442,12 @@ __global__ void queue_scatter_kernel(const uint32_t* __restrict__ ranges, int64_
 // workspace layout
 // ---------------------------------------------------------------------------
 // tile counters [64], depth + tile digit histograms [2][kMaxPasses][256], queue histogram and cursors
-// [2][40], partial tile-digit histograms of emit_kernel [kTileHistCopies - 1][kMaxPasses][256]
+// [2][40], partial tile-digit histograms of emit_kernel [kTileHistCopies - 1][kMaxPasses][256], partial
+// depth-digit histograms of compact_count_kernel [kDepthHistCopies - 1][4][256]
 constexpr int64_t kQueueWords = 2 * 40;
-constexpr int64_t kFixedWords = 64 + 2 * kMaxPasses * kRadix + kQueueWords + (kTileHistCopies - 1) * kTileHistWords;
+constexpr int64_t kTileExtraAt = 64 + 2 * kMaxPasses * kRadix + kQueueWords;
+constexpr int64_t kDepthExtraAt = kTileExtraAt + (kTileHistCopies - 1) * kTileHistWords;
+constexpr int64_t kFixedWords = kDepthExtraAt + (kDepthHistCopies - 1) * kDepthHistWords;
 
 struct SortWs {
   uint32_t* dkeys_a;      // [rc]
@@ -389,7 +459,7 @@ struct SortWs {
   uint32_t* ptiles_alt;   // [pc]
   uint32_t* precs_alt;    // [pc]
   uint32_t* fixed;        // counters [64], hist [2][kMaxPasses][256], queue words, partial tile hists
-  uint64_t* scan_status;  // [2][rtiles]
+  uint64_t* scan_status;  // [2][rtiles]: compaction tile counts and offsets (u32), pair-offset look-back
   uint32_t* dstatus;      // [radix tiles][4][256] (tile-major so a prefix covers every pass)
   uint32_t* pstatus;      // [ptiles][kMaxPasses][256]
   size_t bytes;
@@ -485,8 +555,18 @@ extern "C" gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys
                      counts, record_capacity);
   GS_LAUNCH_CHECK();
   // 1. compaction (+ histograms of the four depth digits)
-  hipLaunchKernelGGL(compact_kernel, persistent(record_capacity), blk, 0, s, tiles_touched, depth_keys,
-                     record_capacity, w.dkeys_a, w.dvals_a, w.scan_status, counters + 0, dhist, counts);
+  {
+    uint32_t* tile_count = (uint32_t*)w.scan_status;  // [rtiles], then tile_off [rtiles]
+    uint32_t* tile_off = tile_count + rtiles;
+    uint32_t* dhist_extra = w.fixed + kDepthExtraAt;
+    const dim3 cgrid = grid_for((int64_t)kThreads * ((record_capacity + kScanTile - 1) / kScanTile));
+    hipLaunchKernelGGL(compact_count_kernel, cgrid, blk, 0, s, tiles_touched, depth_keys, record_capacity, counts,
+                       tile_count, dhist, dhist_extra);
+    hipLaunchKernelGGL(compact_scan_kernel, dim3(1), blk, 0, s, record_capacity, counts, tile_count, tile_off, dhist,
+                       dhist_extra);
+    hipLaunchKernelGGL(compact_write_kernel, cgrid, blk, 0, s, tiles_touched, depth_keys, record_capacity, counts,
+                       tile_off, w.dkeys_a, w.dvals_a);
+  }
   GS_LAUNCH_CHECK();
   // 2. depth sort, 4 passes of 8 bits: a -> b -> a -> b -> a
   for (int p = 0; p < 4; ++p) {
@@ -506,7 +586,7 @@ extern "C" gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys
   uint32_t* em_tiles = (tpasses % 2 == 0) ? pair_tiles : w.ptiles_alt;
   uint32_t* em_recs = (tpasses % 2 == 0) ? pair_records : w.precs_alt;
   uint32_t* big_count = counters + 32;
-  uint32_t* thist_extra = w.fixed + 64 + 2 * kMaxPasses * kRadix + kQueueWords;
+  uint32_t* thist_extra = w.fixed + kTileExtraAt;
   hipLaunchKernelGGL(emit_kernel, grid_for(record_capacity), blk, 0, s, (const Record*)records, w.dvals_a, w.pair_off,
                      record_capacity, counts, pair_capacity, tw, th, tx_n, (int)tiles_per_view, em_tiles, em_recs,
                      tpasses, thist, w.pstatus, tile_ranges, 2 * n_tile_ids, w.big_list, big_count, thist_extra);
