@@ -41,24 +41,13 @@ constexpr int kTileHistCopies = 8;
 constexpr int64_t kTileHistWords = kMaxPasses * kRadix;  // one copy
 
 // ---------------------------------------------------------------------------
-// zero fill of the small fixed state and of the look-back words of the scans
-// and depth passes, sized by the selected record count
+// zero fill of the small fixed state (counters, histograms); the look-back
+// words of the pair-offset scan and the depth passes are cleared by
+// compact_write_kernel, sized by the visible count
 // ---------------------------------------------------------------------------
-__global__ void clear_front_kernel(uint32_t* __restrict__ fixed, int64_t fixed_words, uint32_t* __restrict__ scan0,
-                                   uint32_t* __restrict__ scan1, uint32_t* __restrict__ dstatus,
-                                   const int64_t* counts, int64_t cap) {
-  const int64_t n = count_clamped(counts, GS_COUNT_RECORDS, cap);
-  const int64_t ntiles = (n + kTile - 1) / kTile;
-  const int64_t scan_words = 2 * (ntiles + 1);  // one u64 status per scan tile
-  const int64_t dwords = ((n + kRadixTile - 1) / kRadixTile) * 4 * kRadix;  // [radix tiles][4 passes][256]
-  const int64_t total = fixed_words + 2 * scan_words + dwords;
+__global__ void clear_front_kernel(uint32_t* __restrict__ fixed, int64_t fixed_words) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-    if (i < fixed_words) fixed[i] = 0u;
-    else if (i < fixed_words + scan_words) scan0[i - fixed_words] = 0u;
-    else if (i < fixed_words + 2 * scan_words) scan1[i - fixed_words - scan_words] = 0u;
-    else dstatus[i - fixed_words - 2 * scan_words] = 0u;
-  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < fixed_words; i += stride) fixed[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -162,10 +151,24 @@ __global__ void __launch_bounds__(kThreads) compact_write_kernel(const int32_t* 
                                                                  const int64_t* counts,
                                                                  const uint32_t* __restrict__ tile_off,
                                                                  uint32_t* __restrict__ keys_out,
-                                                                 uint32_t* __restrict__ vals_out) {
+                                                                 uint32_t* __restrict__ vals_out,
+                                                                 uint32_t* __restrict__ poff_status,
+                                                                 uint32_t* __restrict__ dstatus) {
   __shared__ uint32_t s_wave[kThreads / 64];
   const int64_t n = count_clamped(counts, GS_COUNT_RECORDS, cap);
   const int64_t ntiles = scan_tiles_of(n);
+  {
+    // look-back words of the stages that run over the visible records: the
+    // pair-offset scan (one u64 per scan tile, + 1) and the four depth passes
+    const int64_t nv = count_clamped(counts, GS_COUNT_VISIBLE, cap);
+    const int64_t pwords = 2 * (scan_tiles_of(nv) + 1);
+    const int64_t dwords = ((nv + kRadixTile - 1) / kRadixTile) * 4 * kRadix;  // [radix tiles][4 passes][256]
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < pwords + dwords; i += stride) {
+      if (i < pwords) poff_status[i] = 0u;
+      else dstatus[i - pwords] = 0u;
+    }
+  }
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t base = t * kScanTile + (int64_t)threadIdx.x * kScanItems;
     const uint32_t tbase = tile_off[t];
@@ -548,11 +551,8 @@ extern "C" gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys
   uint32_t* counters = w.fixed;
   uint32_t* dhist = w.fixed + 64;
   uint32_t* thist = w.fixed + 64 + kMaxPasses * kRadix;
-  // 0. zero the counters, histograms and the look-back words of the record-sized stages
-  const int64_t drtiles = (record_capacity + kRadixTile - 1) / kRadixTile;
-  hipLaunchKernelGGL(clear_front_kernel, grid_for(kFixedWords + 4 * rtiles + 4 * drtiles * kRadix), blk, 0, s,
-                     w.fixed, kFixedWords, (uint32_t*)w.scan_status, (uint32_t*)(w.scan_status + rtiles), w.dstatus,
-                     counts, record_capacity);
+  // 0. zero the counters and histograms
+  hipLaunchKernelGGL(clear_front_kernel, grid_for(kFixedWords), blk, 0, s, w.fixed, kFixedWords);
   GS_LAUNCH_CHECK();
   // 1. compaction (+ histograms of the four depth digits)
   {
@@ -565,7 +565,7 @@ extern "C" gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys
     hipLaunchKernelGGL(compact_scan_kernel, dim3(1), blk, 0, s, record_capacity, counts, tile_count, tile_off, dhist,
                        dhist_extra);
     hipLaunchKernelGGL(compact_write_kernel, cgrid, blk, 0, s, tiles_touched, depth_keys, record_capacity, counts,
-                       tile_off, w.dkeys_a, w.dvals_a);
+                       tile_off, w.dkeys_a, w.dvals_a, (uint32_t*)(w.scan_status + rtiles), w.dstatus);
   }
   GS_LAUNCH_CHECK();
   // 2. depth sort, 4 passes of 8 bits: a -> b -> a -> b -> a
