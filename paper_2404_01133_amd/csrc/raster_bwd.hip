@@ -54,6 +54,7 @@ __device__ __forceinline__ float quad_sum9(const float v[9], int lane) {
 }
 
 constexpr int kG = 9;  // partials per Gaussian: r, g, b, opacity, A1, A2, Axx, Axy, Ayy
+constexpr int kBwdLdsOffsets = 1024;  // segment offsets staged in LDS by the view-major adjoint up to this many
 
 template <int TW, int TH, int BATCH>
 struct BwdLds {
@@ -327,20 +328,23 @@ __device__ __forceinline__ void sh_adjoint(float x, float y, float z, int deg, c
   term(15, -k3a * x * (xx - 3.f * yy), -3.f * k3a * (xx - yy), 6.f * k3a * x * y, 0.f);
 }
 
-// One record's adjoint; returns false (and adds nothing) for a record whose 2D
-// gradient is zero.
-template <bool HALF, class Sink>
-__device__ __forceinline__ bool preprocess_bwd_record_t(const BwdArgs& a, const Record* __restrict__ records,
-                                                        const float* __restrict__ grad2d, int64_t g, int v, int l,
-                                                        int64_t gi, Sink& sink) {
-  float p2[kG];
+// Record g's 2D gradient (colour, opacity, conic and mean partials); false if
+// it is all zero (a culled record, or one no pixel's loss depends on).
+__device__ __forceinline__ bool load_grad2d(const float* __restrict__ grad2d, int64_t g, float (&p2)[kG]) {
   bool any = false;
 #pragma unroll
   for (int q = 0; q < kG; ++q) {
     p2[q] = grad2d[g * kG + q];
     any |= p2[q] != 0.0f;
   }
-  if (!any) return false;
+  return any;
+}
+
+// One record's adjoint, for a record whose 2D gradient p2 is not all zero.
+template <bool HALF, class Sink>
+__device__ __forceinline__ void preprocess_bwd_record_t(const BwdArgs& a, const Record* __restrict__ records,
+                                                        const float (&p2)[kG], int64_t g, int v, int l, int64_t gi,
+                                                        Sink& sink) {
   const LevelPtrs& L = a.lv[l];
   const int64_t n = L.n;
   const gs_camera& cam = a.cams[v];
@@ -494,22 +498,20 @@ __device__ __forceinline__ bool preprocess_bwd_record_t(const BwdArgs& a, const 
 #pragma unroll
   for (int k = 0; k < 4; ++k) sink.quat(k, gq[k]);
   sink.opac(p2[3]);
-  return true;
 }
 
 template <bool SINGLE>
 __device__ __forceinline__ void preprocess_bwd_record(const BwdArgs& a, const Record* __restrict__ records,
-                                                      const float* __restrict__ grad2d, int64_t g, int v, int l,
-                                                      int64_t gi) {
+                                                      const float (&p2)[kG], int64_t g, int v, int l, int64_t gi) {
   if constexpr (SINGLE) {
     RegisterSink acc;
-    const bool any = a.lv[l].half ? preprocess_bwd_record_t<true>(a, records, grad2d, g, v, l, gi, acc)
-                                  : preprocess_bwd_record_t<false>(a, records, grad2d, g, v, l, gi, acc);
-    if (any) acc.flush(a.gr[l], a.lv[l].n, gi, (a.lv[l].sh_deg + 1) * (a.lv[l].sh_deg + 1));
+    if (a.lv[l].half) preprocess_bwd_record_t<true>(a, records, p2, g, v, l, gi, acc);
+    else preprocess_bwd_record_t<false>(a, records, p2, g, v, l, gi, acc);
+    acc.flush(a.gr[l], a.lv[l].n, gi, (a.lv[l].sh_deg + 1) * (a.lv[l].sh_deg + 1));
   } else {
     AtomicSink sink{a.gr[l], a.lv[l].n, gi};
-    if (a.lv[l].half) preprocess_bwd_record_t<true>(a, records, grad2d, g, v, l, gi, sink);
-    else preprocess_bwd_record_t<false>(a, records, grad2d, g, v, l, gi, sink);
+    if (a.lv[l].half) preprocess_bwd_record_t<true>(a, records, p2, g, v, l, gi, sink);
+    else preprocess_bwd_record_t<false>(a, records, p2, g, v, l, gi, sink);
   }
 }
 
@@ -524,7 +526,10 @@ __device__ __forceinline__ void preprocess_bwd_gaussian(const BwdArgs& a, const 
   for (int v = 0; v < a.V; ++v) {
     const int64_t g = (int64_t)v * n_view + i;
     if (g >= n_rec) break;
-    any |= preprocess_bwd_record_t<HALF>(a, records, grad2d, g, v, l, gi, acc);
+    float p2[kG];
+    if (!load_grad2d(grad2d, g, p2)) continue;
+    preprocess_bwd_record_t<HALF>(a, records, p2, g, v, l, gi, acc);
+    any = true;
   }
   if (any) acc.flush(a.gr[l], a.lv[l].n, gi, (a.lv[l].sh_deg + 1) * (a.lv[l].sh_deg + 1));
 }
@@ -539,13 +544,23 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(BwdArgs a, const Re
   int64_t n_rec = counts[GS_COUNT_RECORDS];
   if (n_rec > a.capacity) n_rec = a.capacity;
   const int nseg = a.V * a.segs;
+  // segment offsets staged in LDS when they fit; a record is looked up only
+  // once its 2D gradient is known to be non-zero (most selected records were culled)
+  __shared__ int64_t s_off[kBwdLdsOffsets];
+  const bool lds_off = nseg < kBwdLdsOffsets;
+  if (lds_off)
+    for (int k = threadIdx.x; k <= nseg; k += blockDim.x) s_off[k] = a.offsets[k];
+  __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_rec; g += stride) {
-    const int p = find_segment(a.offsets, nseg, g);
+    float p2[kG];
+    if (!load_grad2d(grad2d, g, p2)) continue;
+    const int p = lds_off ? find_segment(s_off, nseg, g) : find_segment(a.offsets, nseg, g);
     const int v = p / a.segs, b = p - v * a.segs;
     const int l = a.gather ? b : a.level[p];
-    const int64_t gi = a.gather ? (int64_t)a.gather[g] : a.lvl_off[(int64_t)b * a.L + l] + (g - a.offsets[p]);
-    preprocess_bwd_record<SINGLE>(a, records, grad2d, g, v, l, gi);
+    const int64_t seg0 = lds_off ? s_off[p] : a.offsets[p];
+    const int64_t gi = a.gather ? (int64_t)a.gather[g] : a.lvl_off[(int64_t)b * a.L + l] + (g - seg0);
+    preprocess_bwd_record<SINGLE>(a, records, p2, g, v, l, gi);
   }
 }
 
