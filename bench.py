@@ -43,8 +43,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# FP32 VALU peak without packed-FP32 instructions (which this build does not
-# emit): 256 CUs x 64 FMA lanes per clock x 2 flops x 2.4 GHz
+# FP32 VALU peak without packed-FP32 instructions (the library is compiled with
+# them disabled): 256 CUs x 64 FMA lanes per clock x 2 flops x 2.4 GHz
 VALU_FP32_PEAK_TFLOPS = 78.6
 # algorithmic FP32 work of one (pixel, Gaussian) evaluation inside the footprint:
 # offset (4), conic quadratic form (7), exp (1), alpha (1), transmittance (2),
@@ -789,7 +789,7 @@ def workload_assign(args, torch, gs, render, synth):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+        print("bench.py measures one GPU: the library has no multi-GPU path (--gpus %d requested)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     import torch
