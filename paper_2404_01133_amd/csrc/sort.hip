@@ -5,6 +5,7 @@
 // the tile, so those passes run once per visible record, before the pairs are
 // duplicated; only the tile digits run over the pairs.  Stages:
 //   1. compact   visible records -> (depth bits, record id), record order kept
+//                (per-tile counts, one-work-group scan, write: three launches)
 //   2. 4 passes  stable radix sort by the 32-bit depth key (ties keep record order)
 //   3. scan      pair offsets = exclusive prefix of tiles_touched in depth order
 //   4. emit      one (view*tiles + tile, record) pair per tile of each footprint
@@ -12,9 +13,10 @@
 //   6. ranges    [start, end) of every tile
 // The result equals a sort by (tile, depth, record id).
 //
-// Scans and radix passes are single-pass with decoupled look-back: work-groups
-// take tile ids from an atomic counter in launch order, publish their local
-// aggregate, then walk back over predecessors' published values.  A work-group
+// The pair-offset scan and the radix passes are single-pass with decoupled
+// look-back: work-groups take tile ids from an atomic counter in launch order,
+// publish their local aggregate, then walk back over predecessors' published
+// values.  A work-group
 // only waits on tiles claimed before its own, so the waits always end; each
 // wait is still bounded (kSpinLimit) and raises GS_FLAG_WAIT if it gives up.
 // Every device size is read from the counts array, so nothing here needs a
