@@ -46,7 +46,7 @@ def lib():
         i32 = ctypes.c_int
         L.orc_project.argtypes = [i64, P, P, P, P, P, i32, P, P, i32, i32, P, P, P, P, P, P, P, P, P, P]
         L.orc_project.restype = i32
-        L.orc_render.argtypes = [i64, P, P, P, P, P, i32, P, P, P, P, i64, P, P, P, P]
+        L.orc_render.argtypes = [i64, P, P, P, P, P, i32, P, P, P, P, i64, P, P, P, P, P, P, P]
         L.orc_render.restype = i32
         L.orc_render_tiled.argtypes = [i64, P, P, P, P, P, i32, P, P, P, i32, i32, P, P, P]
         L.orc_render_tiled.restype = i32
@@ -96,6 +96,23 @@ def project(g, cam, sh_degree=3, tile=(16, 16)):
 
 def render(g, cam, sh_degree=3, bg=(0.0, 0.0, 0.0), pixels=None):
     """Untiled FP64 render.  Returns (img [3,H,W] or [3,npix], T_final, n_contrib, ambiguous)."""
+    r = render_branches(g, cam, sh_degree, bg, pixels, branches=False)
+    return r["img"], r["T"], r["n_contrib"], r["ambiguous"]
+
+
+def render_branches(g, cam, sh_degree=3, bg=(0.0, 0.0, 0.0), pixels=None, branches=True):
+    """Untiled FP64 render with the bookkeeping of threshold decisions.
+
+    Returns a dict (shapes [3,H,W] / [H,W], or [3,npix] / [npix] for a pixel list):
+      img, T, n_contrib  the render;
+      ambiguous          image decisions that fall inside a threshold band (the
+                         skip of alpha < 1/255, the stop before T < 1e-4);
+      img_alt, T_alt     (branches=True) the result with the other branch taken at
+                         a pixel's only ambiguous decision (equal to img, T elsewhere):
+                         both are correct results, a pixel with two or more such
+                         decisions has more than two;
+      grad_ambiguous     contributing entries whose raw alpha lies in the band of the
+                         0.99 clamp (image continuous, gradient not)."""
     n, arrs = _params(g)
     cd, ci = _cam_arrays(cam)
     bgv = np.asarray(bg, np.float64)
@@ -109,12 +126,17 @@ def render(g, cam, sh_degree=3, bg=(0.0, 0.0, 0.0), pixels=None):
     T = np.zeros(P)
     nc = np.zeros(P, np.int32)
     amb = np.zeros(P, np.int32)
+    gamb = np.zeros(P, np.int32)
+    img_alt = np.zeros((3, P)) if branches else None
+    T_alt = np.zeros(P) if branches else None
     lib().orc_render(n, *[_ptr(a) for a in arrs], sh_degree, _ptr(cd), _ptr(ci), _ptr(bgv), _ptr(pix),
-                     0 if pix is None else P, _ptr(img), _ptr(T), _ptr(nc), _ptr(amb))
+                     0 if pix is None else P, _ptr(img), _ptr(T), _ptr(nc), _ptr(amb), _ptr(img_alt), _ptr(T_alt),
+                     _ptr(gamb))
+    out = dict(img=img, T=T, n_contrib=nc, ambiguous=amb, grad_ambiguous=gamb, img_alt=img_alt, T_alt=T_alt)
     if pixels is None:
         H, W = cam.height, cam.width
-        return img.reshape(3, H, W), T.reshape(H, W), nc.reshape(H, W), amb.reshape(H, W)
-    return img, T, nc, amb
+        out = {k: (None if v is None else v.reshape((3, H, W) if v.ndim == 2 else (H, W))) for k, v in out.items()}
+    return out
 
 
 def render_tiled(g, cam, sh_degree=3, bg=(0.0, 0.0, 0.0), tile=(16, 16)):

@@ -13,8 +13,9 @@ Follows Sec. 3.3.2 of the paper step by step:
 Readings of points the paper leaves open (also listed in the design notes):
   * median of an even count = the lower middle element (rank floor((n-1)/2));
   * distance intervals are half-open [t_k, t_{k+1});
-  * "in front of the camera" means camera-space z > znear;
-  * "the block where the camera is in" is the block's half-open xy cell;
+  * a corner counts as in front of the camera when its camera-space z > znear;
+  * the block that contains the camera is the one whose half-open xy cell holds
+    the camera centre;
   * levels are indexed 0 (coarsest) .. L-1 (finest); a near block gets L-1.
 """
 from __future__ import annotations
@@ -164,7 +165,7 @@ def aggregate(scene, level_row):
 #   * distance = Euclidean distance from the Gaussian centre to the camera
 #     centre, same intervals and the same level numbering as the block-wise
 #     selection;
-#   * "in the frustum" = camera-space z > znear and the projected centre inside
+#   * in the frustum: camera-space z > znear and the projected centre inside
 #     the screen widened by POINT_GUARD of its size on every side (the 1.3x
 #     guard band of the rasterizer's projection for a centred principal point),
 #     so Gaussians centred just off screen still reach the rasterizer;

@@ -319,31 +319,50 @@ struct PixelResult {
   double C[3];
   double T;
   int32_t n_contrib;
+  // decisions of the image that fall inside a band: the skip of alpha below
+  // 1/255 and the stop before T drops below 1e-4 (either choice is a correct
+  // result of the method at that precision)
   int32_t ambiguous;
+  // entries whose raw alpha o * G lies inside the band around the 0.99 clamp:
+  // the image is continuous there, its gradient with respect to o and the
+  // footprint is not
+  int32_t grad_ambiguous;
 };
 
 // Composite one pixel over a depth-sorted candidate list (entries whose
-// footprint does not hold the pixel are skipped).
+// footprint does not hold the pixel are skipped).  flip >= 0 takes the other
+// branch at the flip-th ambiguous decision (0 = the first), which gives the
+// second correct result of a pixel with one such decision.
 PixelResult composite(const std::vector<const Splat*>& list, int i, int j, const double bg[3],
-                      std::vector<const Splat*>* contrib, std::vector<double>* alphas, std::vector<double>* Ts) {
+                      std::vector<const Splat*>* contrib, std::vector<double>* alphas, std::vector<double>* Ts,
+                      int flip = -1) {
   PixelResult r;
   r.C[0] = r.C[1] = r.C[2] = 0.0;
   r.T = 1.0;
   r.n_contrib = 0;
   r.ambiguous = 0;
+  r.grad_ambiguous = 0;
   double px = i + 0.5, py = j + 0.5;
   for (const Splat* s : list) {
     if (i < s->i0 || i > s->i1 || j < s->j0 || j > s->j1) continue;
     double dx = px - s->u, dy = py - s->v;
     double power = -0.5 * (s->A * dx * dx + s->C * dy * dy) - s->B * dx * dy;
     double raw = s->o * std::exp(power);
-    if (std::fabs(raw - kAlphaMax) <= kBand * kAlphaMax) r.ambiguous++;
     double alpha = std::min(kAlphaMax, raw);
-    if (std::fabs(alpha - kAlphaMin) <= kBand * kAlphaMin) r.ambiguous++;
-    if (alpha < kAlphaMin) continue;
+    bool skip = alpha < kAlphaMin;
+    if (std::fabs(alpha - kAlphaMin) <= kBand * kAlphaMin) {
+      if (r.ambiguous == flip) skip = !skip;
+      r.ambiguous++;
+    }
+    if (skip) continue;
     double Tn = r.T * (1.0 - alpha);
-    if (std::fabs(Tn - kTMin) <= kBand * kTMin) r.ambiguous++;
-    if (Tn < kTMin) break;
+    bool stop = Tn < kTMin;
+    if (std::fabs(Tn - kTMin) <= kBand * kTMin) {
+      if (r.ambiguous == flip) stop = !stop;
+      r.ambiguous++;
+    }
+    if (stop) break;
+    if (std::fabs(raw - kAlphaMax) <= kBand * kAlphaMax) r.grad_ambiguous++;
     if (contrib) {
       contrib->push_back(s);
       alphas->push_back(alpha);
@@ -429,10 +448,14 @@ int orc_project(int64_t n, const double* means, const double* scales, const doub
 
 // Untiled render.  If pix != NULL only the listed pixels (index j*W + i) are
 // rendered and outputs are [3][npix], [npix]; otherwise the whole image.
+// ambiguous = number of image decisions inside a threshold band; img_alt and
+// T_alt (may be NULL) hold the result with the other branch taken at a pixel's
+// only ambiguous decision; grad_ambiguous counts entries whose raw alpha lies
+// inside the band of the 0.99 clamp.
 int orc_render(int64_t n, const double* means, const double* scales, const double* quats, const double* opac,
                const double* sh, int deg, const double* cam_d, const int32_t* cam_i, const double* bg,
                const int64_t* pix, int64_t npix, double* img, double* T_final, int32_t* n_contrib,
-               int32_t* ambiguous) {
+               int32_t* ambiguous, double* img_alt, double* T_alt, int32_t* grad_ambiguous) {
   Cam cam = to_cam(cam_d, cam_i);
   Inputs in{n, means, scales, quats, opac, sh, deg};
   std::vector<Splat> splats;
@@ -455,6 +478,15 @@ int orc_render(int64_t n, const double* means, const double* scales, const doubl
     if (T_final) T_final[k] = r.T;
     if (n_contrib) n_contrib[k] = r.n_contrib;
     if (ambiguous) ambiguous[k] = r.ambiguous;
+    if (grad_ambiguous) grad_ambiguous[k] = r.grad_ambiguous;
+    if (img_alt || T_alt) {
+      // second correct result of a pixel with exactly one ambiguous decision;
+      // elsewhere the alternative equals the primary result
+      PixelResult a = r.ambiguous == 1 ? composite(rows[j], i, j, bg, nullptr, nullptr, nullptr, 0) : r;
+      if (img_alt)
+        for (int ch = 0; ch < 3; ++ch) img_alt[ch * P + k] = a.C[ch];
+      if (T_alt) T_alt[k] = a.T;
+    }
   }
   return 0;
 }

@@ -72,3 +72,54 @@ def test_camera_block_by_contraction():
     assert opart.block_ids(far, p_min, p_max, 6, 6)[0] % 6 == 5
     centre = np.array([[1.0], [1.0], [20.0]])
     assert opart.block_ids(centre, p_min, p_max, 6, 6)[0] in (2 * 6 + 3, 3 * 6 + 3)
+
+
+# ---------------------------------------------------------------------------
+# SSIM against closed forms with the constants written out (C1 = 0.01^2 =
+# 0.0001, C2 = 0.03^2 = 0.0009) and window moments from SciPy's filter, so the
+# oracle's own constants and formula are not reused
+# ---------------------------------------------------------------------------
+def _scipy_moments(x):
+    f = lambda a: scipy.ndimage.gaussian_filter(a, sigma=1.5, mode="constant", cval=0.0, truncate=5.0 / 1.5)
+    mu = f(x)
+    return mu, f(x * x) - mu * mu
+
+
+def test_ssim_constant_images_literal_constants():
+    H, W = 40, 40
+    for c1, c2 in ((0.7, 0.4), (0.05, 0.0), (0.3, 0.3)):
+        m = oas.ssim_map(np.full((H, W), c1), np.full((H, W), c2))
+        want = (2 * c1 * c2 + 0.0001) / (c1 * c1 + c2 * c2 + 0.0001)
+        np.testing.assert_allclose(m[5:-5, 5:-5], want, rtol=1e-12)
+
+
+def test_ssim_affine_copy_closed_form_literal_constants():
+    # y = a x + b: sigma_xy = a sigma^2, sigma_y^2 = a^2 sigma^2 per window (interior), so
+    # SSIM = (2 mx my + 0.0001)/(mx^2 + my^2 + 0.0001) * (2 a s^2 + 0.0009)/((1 + a^2) s^2 + 0.0009)
+    rng = np.random.default_rng(3)
+    x = rng.random((36, 36))
+    mx, s2 = _scipy_moments(x)
+    inner = (slice(5, -5), slice(5, -5))
+    for a, b in ((0.5, 0.2), (1.0, 0.0), (-1.0, 1.0), (2.0, -0.3)):
+        y = a * x + b
+        my = a * mx + b
+        want = ((2 * mx * my + 0.0001) / (mx * mx + my * my + 0.0001)) * \
+               ((2 * a * s2 + 0.0009) / ((1 + a * a) * s2 + 0.0009))
+        np.testing.assert_allclose(oas.ssim_map(x, y)[inner], want[inner], rtol=1e-9, atol=1e-12)
+
+
+def test_ssim_anticorrelated_pair_separates_covariance_from_product_of_deviations():
+    # y = 1 - x: sigma_xy = -sigma^2 while sigma_x sigma_y = +sigma^2, so the structure
+    # term is (0.0009 - 2 s^2) / (2 s^2 + 0.0009) < 0 where the variance is large
+    rng = np.random.default_rng(4)
+    x = rng.random((36, 36))
+    y = 1.0 - x
+    mx, s2 = _scipy_moments(x)
+    inner = (slice(5, -5), slice(5, -5))
+    my = 1.0 - mx
+    lum = (2 * mx * my + 0.0001) / (mx * mx + my * my + 0.0001)
+    cs = (0.0009 - 2 * s2) / (2 * s2 + 0.0009)
+    m = oas.ssim_map(x, y)
+    np.testing.assert_allclose(m[inner], (lum * cs)[inner], rtol=1e-9, atol=1e-12)
+    assert (m[inner] < 0).all()
+    assert oas.ssim(np.stack([x] * 3), np.stack([y] * 3)) < 0

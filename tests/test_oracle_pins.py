@@ -380,3 +380,197 @@ def test_lone_gaussian_opacity_and_colour_gradient_closed_form():
     np.testing.assert_allclose(out["opac"][0], rgb[0] * G, rtol=1e-12)
     # colour enters through SH degree 0 with weight Y00
     np.testing.assert_allclose(out["sh"][0, 0, 0], Y00 * o * G, rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# guard band: the Jacobian is taken at the tangent clamped to 1.3x the half
+# field of view (x from the width, y from the height), so a Gaussian beyond it
+# has a 2D covariance that does not depend on its centre's x (or y)
+# ---------------------------------------------------------------------------
+def _hand_cov2d(mean, scale, quat, fx, fy, limx, limy):
+    """J(x~) Sigma J(x~)^T + 0.3 I for an identity camera, written out."""
+    x, y, z = mean
+    xt = z * min(limx, max(-limx, x / z))
+    yt = z * min(limy, max(-limy, y / z))
+    J = np.array([[fx / z, 0.0, -fx * xt / z ** 2], [0.0, fy / z, -fy * yt / z ** 2]])
+    Rq = Rotation.from_quat([quat[1], quat[2], quat[3], quat[0]]).as_matrix()
+    Sig = Rq @ np.diag(np.asarray(scale) ** 2) @ Rq.T
+    return J @ Sig @ J.T + 0.3 * np.eye(2), J
+
+
+@pytest.mark.parametrize("tan_xy,scale", [((2.0, 0.0), 1.0),     # x/z twice the x limit
+                                          ((0.0, 0.6), 0.3),     # y beyond the y limit, inside the x limit
+                                          ((-1.3, -0.7), 0.8)])  # both clamped, negative side
+def test_guard_band_clamp_covariance(tan_xy, scale):
+    W, H, fx = 64, 40, 50.0
+    cam = identity_cam(W, H, fx)
+    limx, limy = 1.3 * (W / 2) / fx, 1.3 * (H / 2) / fx   # 0.832, 0.52
+    z = 2.0
+    tx, ty = tan_xy
+    if tx:
+        tx = tx * limx if abs(tx) > 1.5 else tx
+    mean = np.array([tx * z, ty * z, z])
+    quat = np.array([0.8, 0.3, -0.4, 0.33])
+    quat = quat / np.linalg.norm(quat)
+    s = np.array([scale, 0.7 * scale, 1.2 * scale])
+    g = make_set(mean.reshape(3, 1), s.reshape(3, 1), quat.reshape(4, 1), [0.5], np.zeros((1, 3, 1)), np.float64)
+    pr = oracle.project(g, cam, 0)
+    assert pr["visible"][0], "the footprint must reach the image for the covariance to be reported"
+    got = np.array([[pr["cov2d"][0, 0], pr["cov2d"][0, 1]], [pr["cov2d"][0, 1], pr["cov2d"][0, 2]]])
+    want, _ = _hand_cov2d(mean, s, quat, fx, fx, limx, limy)
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-12)
+    # the unclamped Jacobian (or one with the limits swapped) gives a visibly different covariance
+    unclamped, _ = _hand_cov2d(mean, s, quat, fx, fx, 1e9, 1e9)
+    swapped, _ = _hand_cov2d(mean, s, quat, fx, fx, limy, limx)
+    assert np.abs(unclamped - want).max() > 1e-3 * np.abs(want).max()
+    assert np.abs(swapped - want).max() > 1e-3 * np.abs(want).max()
+    # the 2D mean is the unclamped pinhole projection
+    np.testing.assert_allclose(pr["uv"][0], [fx * mean[0] / z + W / 2, fx * mean[1] / z + H / 2], rtol=1e-13)
+    # a small move of the centre along a clamped axis leaves the covariance bit for bit unchanged
+    for axis, clamped in ((0, abs(mean[0] / z) > limx), (1, abs(mean[1] / z) > limy)):
+        if not clamped:
+            continue
+        g2 = make_set(mean.reshape(3, 1), s.reshape(3, 1), quat.reshape(4, 1), [0.5], np.zeros((1, 3, 1)), np.float64)
+        g2.means[axis, 0] += 1e-3
+        np.testing.assert_array_equal(oracle.project(g2, cam, 0)["cov2d"], pr["cov2d"])
+
+
+def test_guard_band_gradients_match_finite_differences():
+    # Gaussians whose centres lie beyond the guard band on x, y or both, with
+    # footprints reaching into the image: the exact gradient (dual numbers with
+    # the clamp held) must equal central differences of the FP64 render
+    W, H, fx = 64, 40, 50.0
+    cam = identity_cam(W, H, fx)
+    limx, limy = 1.3 * (W / 2) / fx, 1.3 * (H / 2) / fx
+    z = np.array([2.0, 2.2, 1.9, 2.5])
+    tan = np.array([[1.4 * limx, 0.0], [0.0, 1.25 * limy], [-1.2 * limx, -1.2 * limy], [0.1, 0.05]])
+    n = 4
+    means = np.vstack([tan[:, 0] * z, tan[:, 1] * z, z])
+    rng = np.random.default_rng(11)
+    scales = np.array([[0.9, 0.35, 0.8, 0.05], [0.7, 0.3, 0.6, 0.04], [1.0, 0.4, 0.9, 0.06]])
+    q = rng.normal(size=(4, n))
+    opac = np.array([0.6, 0.7, 0.5, 0.8])
+    sh = rng.normal(0, 0.3, (16, 3, n))
+    g = make_set(means, scales, q, opac, sh, np.float64)
+    pr = oracle.project(g, cam, 3)
+    assert pr["visible"].all()
+    dimg = rng.normal(size=(3, H, W))
+    grads = oracle.render_bwd(g, cam, dimg, 3)
+    sig0 = _signature(g, cam, 3)
+
+    def loss(gg):
+        img, _, _, _ = oracle.render(gg, cam, 3)
+        return float((img * dimg).sum())
+
+    checked = 0
+    for name in ("means", "scales", "quats"):
+        a = getattr(g, name)
+        for p in range(a.size):
+            h = 1e-6 * max(1.0, abs(a.reshape(-1)[p]))
+            gp = SimpleNamespace(**{k: getattr(g, k).copy() for k in ("means", "scales", "quats", "opac", "sh")})
+            gm = SimpleNamespace(**{k: getattr(g, k).copy() for k in ("means", "scales", "quats", "opac", "sh")})
+            getattr(gp, name).reshape(-1)[p] += h
+            getattr(gm, name).reshape(-1)[p] -= h
+            if not (_same(_signature(gp, cam, 3), sig0) and _same(_signature(gm, cam, 3), sig0)):
+                continue
+            fd = (loss(gp) - loss(gm)) / (2 * h)
+            got = grads[name].reshape(-1)[p]
+            assert abs(got - fd) <= 1e-6 * max(1.0, abs(fd)), (name, p, got, fd)
+            checked += 1
+    assert checked >= 30
+
+
+# ---------------------------------------------------------------------------
+# the 0.99 alpha clamp and the rgb >= 0 clamp, with their gradients
+# ---------------------------------------------------------------------------
+def test_alpha_clamp_value_and_gradient():
+    # o = 0.995 centred on a pixel centre: raw alpha 0.995 there, clamped to 0.99
+    W, H, fx = 33, 33, 40.0                  # principal point 16.5: the centre of pixel (16, 16)
+    cam = identity_cam(W, H, fx)
+    rgb = np.array([0.6, 0.3, 0.9])
+    o = 0.995
+    s, z = 0.1, 2.0
+    g = make_set([[0.0], [0.0], [z]], [[s], [s], [s]], [[1.0], [0], [0], [0]], [o], grey_sh(rgb, 1), np.float64)
+    img, T, nc, _ = oracle.render(g, cam, 0)
+    np.testing.assert_allclose(img[:, 16, 16], 0.99 * rgb, rtol=0, atol=1e-15)
+    assert abs(T[16, 16] - 0.01) < 1e-15
+    sig2 = (fx * s / z) ** 2 + 0.3
+    G1 = math.exp(-0.5 / sig2)               # one pixel to the side: o * G1 < 0.99, unclamped
+    assert o * G1 < 0.99
+    np.testing.assert_allclose(img[:, 16, 17], o * G1 * rgb, rtol=1e-13)
+    for (i, j), want in (((16, 16), 0.0), ((17, 16), rgb[0] * G1)):
+        dimg = np.zeros((3, H, W))
+        dimg[0, j, i] = 1.0
+        out = oracle.render_bwd(g, cam, dimg, 0)
+        assert abs(out["opac"][0] - want) <= 1e-13, ((i, j), out["opac"][0], want)
+        if want == 0.0:
+            # clamped: no gradient reaches the footprint either
+            assert np.abs(out["g2d"][0, :6]).max() == 0.0
+            assert np.abs(out["means"][:, 0]).max() == 0.0 and np.abs(out["scales"][:, 0]).max() == 0.0
+    fl = oracle.render_branches(g, cam, 0)
+    assert fl["grad_ambiguous"].max() == 0 and fl["ambiguous"].max() == 0
+
+
+def test_rgb_clamp_value_and_gradient():
+    # a negative DC term: red = max(0, -0.2) = 0, with no gradient into red's SH;
+    # green and blue stay linear in their coefficients
+    W, H = 33, 33
+    cam = identity_cam(W, H, 40.0)
+    rgb = np.array([-0.2, 0.4, 0.7])
+    g = make_set([[0.0], [0.0], [2.0]], [[0.1], [0.1], [0.1]], [[1.0], [0], [0], [0]], [0.6], grey_sh(rgb, 1),
+                 np.float64)
+    pr = oracle.project(g, cam, 0)
+    np.testing.assert_array_equal(pr["rgb_clamped"][0], [1, 0, 0])
+    assert pr["rgb"][0, 0] == 0.0 and abs(pr["rgb"][0, 1] - 0.4) < 1e-15
+    img, _, _, _ = oracle.render(g, cam, 0)
+    assert np.abs(img[0]).max() == 0.0 and img[1].max() > 0.1
+    dimg = np.ones((3, H, W))
+    out = oracle.render_bwd(g, cam, dimg, 0)
+    assert out["sh"][0, 0, 0] == 0.0 and out["g2d"][0, 6] != 0.0   # dL/d rgb_r exists, dL/d f_r does not
+    alpha_sum = img[1].sum() / 0.4                                 # sum over pixels of alpha * T
+    np.testing.assert_allclose(out["sh"][0, 1, 0], Y00 * alpha_sum, rtol=1e-12)
+    np.testing.assert_allclose(out["sh"][0, 2, 0], Y00 * alpha_sum, rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# decisions inside a threshold band: both branches are reported
+# ---------------------------------------------------------------------------
+def test_both_branches_at_the_alpha_threshold():
+    # lone isotropic Gaussian on the axis (principal point on a pixel corner) with
+    # o chosen so that alpha at the four central pixels is 1/255 (1 + 1e-7)
+    W, H, fx = 32, 32, 40.0
+    cam = identity_cam(W, H, fx)
+    s, z = 0.1, 2.0
+    sig2 = (fx * s / z) ** 2 + 0.3
+    o = (1.0 / 255.0) * math.exp(0.5 * 0.5 / sig2) * (1.0 + 1e-7)   # d^2 = 0.5^2 + 0.5^2
+    rgb = np.array([0.5, 0.8, 0.2])
+    g = make_set([[0.0], [0.0], [z]], [[s], [s], [s]], [[1.0], [0], [0], [0]], [o], grey_sh(rgb, 1), np.float64)
+    r = oracle.render_branches(g, cam, 0)
+    centre = (slice(15, 17), slice(15, 17))
+    assert (r["ambiguous"][centre] == 1).all()
+    assert r["ambiguous"].sum() == 4
+    alpha = o * math.exp(-0.5 * 0.5 / sig2)
+    for ch in range(3):
+        np.testing.assert_allclose(r["img"][ch][centre], rgb[ch] * alpha, rtol=1e-12)   # included
+        assert (r["img_alt"][ch][centre] == 0.0).all()                                   # skipped
+    np.testing.assert_allclose(r["T_alt"][centre], 1.0, rtol=0, atol=0)
+    off = r["ambiguous"] == 0
+    np.testing.assert_array_equal(r["img_alt"][:, off], r["img"][:, off])
+
+
+def test_both_branches_at_the_transmittance_threshold():
+    # equal-alpha stack centred on a pixel: (1 - alpha)^14 = 1e-4 (1 + 1e-7), so the
+    # 14th entry is taken in one branch and stopped before in the other
+    W, H = 65, 49
+    cam = identity_cam(W, H, 50.0)
+    n = 20
+    a = 1.0 - (1e-4 * (1.0 + 1e-7)) ** (1.0 / 14.0)
+    z = 2.0 + 0.01 * np.arange(n)
+    rgb = np.array([0.8, 0.5, 0.25])
+    g = make_set(np.vstack([np.zeros((2, n)), z[None]]), np.full((3, n), 0.3), np.tile([[1.0], [0], [0], [0]], n),
+                 np.full(n, a), grey_sh(rgb, n), np.float64)
+    r = oracle.render_branches(g, cam, 0)
+    assert r["ambiguous"][24, 32] == 1 and r["n_contrib"][24, 32] == 14
+    np.testing.assert_allclose(r["img"][:, 24, 32], rgb * (1 - (1 - a) ** 14), rtol=1e-12)
+    np.testing.assert_allclose(r["img_alt"][:, 24, 32], rgb * (1 - (1 - a) ** 13), rtol=1e-12)
+    np.testing.assert_allclose(r["T_alt"][24, 32], (1 - a) ** 13, rtol=1e-12)
