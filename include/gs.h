@@ -56,11 +56,14 @@ typedef int32_t gs_status;
 #define GS_COUNT_VISIBLE 1 /* records that survived culling, written by gs_bin_sort */
 #define GS_COUNT_PAIRS 2   /* (tile, record) pairs, written by gs_bin_sort */
 #define GS_COUNT_FLAGS 3   /* bit 0: record capacity exceeded; bit 1: pair capacity exceeded;
-                              bit 2: a device-side wait gave up (see GS_FLAG_WAIT) */
+                              bit 2: a device-side wait gave up (see GS_FLAG_WAIT);
+                              bit 3: GS_TUNE_SHARED_SELECTION was set but the views did not
+                              select the same records (see GS_FLAG_SELECTION) */
 #define GS_COUNT_SLOTS 8
 #define GS_FLAG_RECORDS 1
 #define GS_FLAG_PAIRS 2
 #define GS_FLAG_WAIT 4
+#define GS_FLAG_SELECTION 8
 
 /* Camera (device array [V] of these; 152 bytes, 8-byte aligned). */
 typedef struct gs_camera {
@@ -134,7 +137,13 @@ typedef struct gs_tuning {
  * GS_LOD_ALL_FINEST mode, e.g. several training views of one block).  preprocess and
  * rasterize_bwd then iterate Gaussian-major: one thread handles a Gaussian for all
  * views, reading its parameters from HBM once and accumulating its gradient without
- * atomics.  Segments and levels of view 0 are used for every view. */
+ * atomics.  Segments and levels of view 0 are used for every view.  gs_preprocess
+ * checks this on the device: if the record count is not V times view 0's, or a
+ * view's segment offsets or levels differ from view 0's (shifted by its first
+ * record), it raises GS_FLAG_SELECTION, marks every record culled (tiles_touched
+ * 0) and projects nothing, so the frame is empty; gs_rasterize_bwd then adds
+ * nothing.  Block-wise selections only (with a point-wise gather list the flag
+ * returns GS_ERR_UNSUPPORTED). */
 #define GS_TUNE_SHARED_SELECTION 1
 /* tuning.flags: rasterize_fwd / rasterize_bwd run as persistent kernels that take
  * tiles from a device work queue, longest tile lists first. */
@@ -212,10 +221,21 @@ gs_status gs_preprocess(const gs_gaussians* levels, const gs_blocks* blocks, con
                         void* records, uint32_t* depth_keys, int32_t* tiles_touched, int64_t* counts,
                         void* stream);
 
-/* Tile binning: one (tile, record) pair per tile under each visible record's
- * footprint, sorted by (view*tiles + tile, depth, record index) with a stable
- * LSD radix sort (depth digits on the visible records, tile digits on the
- * pairs), so ties go to the lower record index.
+/* Tile binning (Sec. 3.1, Eq. 1): the colour of a pixel blends the Gaussians
+ * that cover it in depth order, front to back; this call lists, per screen
+ * tile, the visible records whose footprint meets the tile in that order.
+ * One (tile, record) pair per tile under each visible record's footprint,
+ * sorted by (view*tiles + tile, depth, record index) with a stable LSD radix
+ * sort (depth digits on the visible records, tile digits on the pairs), so
+ * ties go to the lower record index.
+ * Inputs: records, depth_keys and tiles_touched as written by gs_preprocess
+ * (record_capacity entries; counts[GS_COUNT_RECORDS] of them are read).
+ * Writes counts[GS_COUNT_VISIBLE] and counts[GS_COUNT_PAIRS]; raises
+ * GS_FLAG_PAIRS (pairs beyond pair_capacity are dropped, the frame is
+ * invalid) and GS_FLAG_WAIT.  Errors: GS_ERR_INVALID_ARG for NULL pointers,
+ * non-positive sizes or capacities of 2^30 and more; GS_ERR_UNSUPPORTED for a
+ * tile shape outside the supported list; GS_ERR_WORKSPACE when ws_bytes is too
+ * small.
  *   pair_tiles / pair_records [pair_capacity] u32: sorted pairs
  *   tile_ranges [V*tiles][2] u32: [start, end) of each tile in the sorted pairs
  *   tile_queue: NULL, or u32[2 + V*tiles]; with GS_TUNE_WORK_QUEUE it receives the

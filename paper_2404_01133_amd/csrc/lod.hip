@@ -107,7 +107,7 @@ __device__ int select_level(const LodArgs& a, const gs_camera& cam, int v, int b
     const double iy1 = vmax < H ? vmax : H, iy0 = vmin > 0.0 ? vmin : 0.0;
     visible = (ix1 > ix0) && (iy1 > iy0);
   }
-  // "the block where the camera is in": the camera centre's cell, in the
+  // the block whose cell holds the camera centre (Sec. 3.3.2), taken in the
   // contracted space of the partition when there is one
   double X, Y;
   cell_coords(a.contraction, C0, C1, C2, X, Y);

@@ -120,6 +120,24 @@ __global__ void __launch_bounds__(kPreThreads) preprocess_kernel(PreArgs a, Reco
   }
 }
 
+// Shared-selection precondition, checked by one work-group before the
+// Gaussian-major kernel: V times view 0's records, and every view's segment
+// offsets and levels equal to view 0's (offsets shifted by v times view 0's
+// count).  A violation raises GS_FLAG_SELECTION, which the Gaussian-major
+// kernels read before doing anything else.
+__global__ void __launch_bounds__(kPreThreads) shared_selection_check_kernel(PreArgs a, int64_t* __restrict__ counts) {
+  const int64_t n_view = a.offsets[a.segs];
+  bool bad = counts[GS_COUNT_RECORDS] != (int64_t)a.V * n_view;
+  const int64_t nseg = (int64_t)a.V * a.segs;
+  for (int64_t idx = threadIdx.x; idx <= nseg; idx += blockDim.x) {
+    const int64_t v = idx / a.segs, k = idx - v * a.segs;
+    bad |= a.offsets[idx] != a.offsets[k] + v * n_view;
+    if (idx < nseg) bad |= a.level[idx] != a.level[k];
+  }
+  if (__syncthreads_or(bad) && threadIdx.x == 0)
+    atomicOr((unsigned long long*)&counts[GS_COUNT_FLAGS], (unsigned long long)GS_FLAG_SELECTION);
+}
+
 // Gaussian-major, for batches in which every view selected the same records
 // (view v's records are [v * n_view, (v + 1) * n_view)): one thread projects a
 // Gaussian for all views in turn, so its parameters come from HBM once and
@@ -129,6 +147,15 @@ __global__ void __launch_bounds__(kPreThreads) preprocess_shared_kernel(PreArgs 
                                                                         int32_t* __restrict__ tiles_touched,
                                                                         int64_t* __restrict__ counts) {
   const int64_t n_rec = clamp_records(a, counts);
+  if (counts[GS_COUNT_FLAGS] & GS_FLAG_SELECTION) {
+    // the views did not select the same records: an empty frame, nothing projected
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_rec; g += stride) {
+      depth_keys[g] = kCulledKey;
+      tiles_touched[g] = 0;
+    }
+    return;
+  }
   __shared__ int64_t s_off[kLdsOffsets];
   const bool lds_off = a.segs < kLdsOffsets;
   if (lds_off)
@@ -194,6 +221,8 @@ extern "C" gs_status gs_preprocess(const gs_gaussians* levels, const gs_blocks* 
   int64_t blocks_needed = (record_capacity + kPreThreads - 1) / kPreThreads;
   int grid = (int)(blocks_needed < 8192 ? (blocks_needed > 0 ? blocks_needed : 1) : 8192);
   if ((tuning->flags & GS_TUNE_SHARED_SELECTION) && n_views > 1) {
+    if (gather) return GS_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL(shared_selection_check_kernel, dim3(1), dim3(kPreThreads), 0, (hipStream_t)stream, a, counts);
     int64_t per_view = (record_capacity / n_views + kPreThreads - 1) / kPreThreads;
     int g2 = (int)(per_view < 8192 ? (per_view > 0 ? per_view : 1) : 8192);
     hipLaunchKernelGGL(preprocess_shared_kernel, dim3(g2), dim3(kPreThreads), 0, (hipStream_t)stream, a,

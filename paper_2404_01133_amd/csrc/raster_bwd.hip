@@ -569,6 +569,7 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(BwdArgs a, const Re
 __global__ void __launch_bounds__(256) preprocess_bwd_shared_kernel(BwdArgs a, const Record* __restrict__ records,
                                                                     const float* __restrict__ grad2d,
                                                                     const int64_t* __restrict__ counts) {
+  if (counts[GS_COUNT_FLAGS] & GS_FLAG_SELECTION) return;  // the forward projected nothing
   int64_t n_rec = counts[GS_COUNT_RECORDS];
   if (n_rec > a.capacity) n_rec = a.capacity;
   const int64_t n_view = a.offsets[a.segs];
@@ -676,6 +677,7 @@ extern "C" gs_status gs_rasterize_bwd(const void* records, const uint32_t* pair_
   int64_t gb = (record_capacity + 255) / 256;
   const dim3 gbg((unsigned)(gb < 8192 ? (gb < 1 ? 1 : gb) : 8192));
   if ((tuning->flags & GS_TUNE_SHARED_SELECTION) && n_views > 1) {
+    if (gather) return GS_ERR_UNSUPPORTED;
     int64_t pv = (record_capacity / n_views + 255) / 256;
     const dim3 gs_grid((unsigned)(pv < 8192 ? (pv < 1 ? 1 : pv) : 8192));
     hipLaunchKernelGGL(preprocess_bwd_shared_kernel, gs_grid, dim3(256), 0, s, a, rec, grad2d, counts);

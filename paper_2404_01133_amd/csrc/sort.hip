@@ -373,11 +373,12 @@ __global__ void __launch_bounds__(kThreads) emit_big_kernel(const Record* __rest
 // 6. tile ranges
 // ---------------------------------------------------------------------------
 __global__ void ranges_kernel(const uint32_t* __restrict__ tiles, const int64_t* counts, int64_t pair_cap,
-                              uint32_t* __restrict__ ranges) {
+                              int64_t n_tile_ids, uint32_t* __restrict__ ranges) {
   const int64_t m = count_clamped(counts, GS_COUNT_PAIRS, pair_cap);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) {
     const uint32_t k = tiles[j];
+    if ((int64_t)k >= n_tile_ids) continue;  // never produced by emission; kept off the ranges array
     if (j == 0 || tiles[j - 1] != k) ranges[2 * (int64_t)k] = (uint32_t)j;
     if (j == m - 1 || tiles[j + 1] != k) ranges[2 * (int64_t)k + 1] = (uint32_t)(j + 1);
   }
@@ -610,7 +611,8 @@ extern "C" gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys
     vin = vout;
   }
   // 6. ranges
-  hipLaunchKernelGGL(ranges_kernel, dim3(2048), blk, 0, s, pair_tiles, counts, pair_capacity, tile_ranges);
+  hipLaunchKernelGGL(ranges_kernel, dim3(2048), blk, 0, s, pair_tiles, counts, pair_capacity, n_tile_ids,
+                     tile_ranges);
   GS_LAUNCH_CHECK();
   // 7. work queue
   if ((tuning->flags & GS_TUNE_WORK_QUEUE) && tile_queue) {

@@ -26,7 +26,7 @@ GS_ERR_HIP = -5
 
 GS_COUNT_RECORDS, GS_COUNT_VISIBLE, GS_COUNT_PAIRS, GS_COUNT_FLAGS = 0, 1, 2, 3
 GS_COUNT_SLOTS = 8
-GS_FLAG_RECORDS, GS_FLAG_PAIRS, GS_FLAG_WAIT = 1, 2, 4
+GS_FLAG_RECORDS, GS_FLAG_PAIRS, GS_FLAG_WAIT, GS_FLAG_SELECTION = 1, 2, 4, 8
 GS_WS_BIN_SORT, GS_WS_RASTERIZE_BWD = 1, 2
 GS_LOD_BLOCKWISE, GS_LOD_ALL_FINEST = 0, 1
 GS_TUNE_SHARED_SELECTION, GS_TUNE_WORK_QUEUE = 1, 2

@@ -302,6 +302,9 @@ def render_frame(scene: DeviceScene, frame: Frame, cams_dev, mode=gs.GS_LOD_BLOC
         c = frame.host_counts()
         if c["flags"] & gs.GS_FLAG_WAIT:
             raise RuntimeError("a device-side wait gave up during the frame (counts=%s)" % c)
+        if c["flags"] & gs.GS_FLAG_SELECTION:
+            raise RuntimeError("GS_TUNE_SHARED_SELECTION was set but the views selected different records "
+                               "(counts=%s)" % c)
         if c["flags"] == 0:
             return frame.rgb
         frame.reserve(max(frame.record_capacity, int(c["records"] * 1.1) + 1024),

@@ -319,7 +319,7 @@ def test_contracted_cells_reproduce_the_grid_blocks():
 
 
 def test_camera_block_is_found_in_contracted_space():
-    """With a contracted partition, the block "the camera is in" is the block the
+    """With a contracted partition, the block holding the camera is the block the
     camera centre would be assigned to as a Gaussian (the pose rule of Eq. 4)."""
     means = np.array([[-100.0, 100.0], [-100.0, 100.0], [0.0, 40.0]])
     p_min, p_max = opart.foreground_box(means, (-100.0, -100.0), (100.0, 100.0))
