@@ -50,6 +50,7 @@ typedef int32_t gs_status;
 #define GS_ERR_WORKSPACE (-3)
 #define GS_ERR_CAPACITY (-4)
 #define GS_ERR_HIP (-5)
+#define GS_ERR_SCRATCH (-6) /* capacities need more scratch than GS_STATIC_SCRATCH_BYTES */
 
 /* indices into the device int64 counts[8] array */
 #define GS_COUNT_RECORDS 0 /* selected (view, Gaussian) records, written by gs_lod_select */
@@ -247,6 +248,30 @@ gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys, const int
                       int64_t record_capacity, int64_t pair_capacity, uint32_t* pair_tiles,
                       uint32_t* pair_records, uint32_t* tile_ranges, uint32_t* tile_queue, int64_t* counts,
                       void* ws, size_t ws_bytes, void* stream);
+
+/* For callers that cannot allocate device memory at all (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): gs_bin_sort
+ * with its workspace taken from a library-owned device array of
+ * GS_STATIC_SCRATCH_BYTES (64 MiB), one copy per GPU, held from the library's
+ * first call on that GPU until the process ends.  Same arguments, outputs,
+ * flags and errors as gs_bin_sort, without ws / ws_bytes, plus:
+ *   GS_ERR_SCRATCH when gs_workspace_bytes(GS_WS_BIN_SORT, record_capacity,
+ *     pair_capacity, ...) exceeds GS_STATIC_SCRATCH_BYTES (about 25 B per
+ *     record of capacity plus 10 B per pair of capacity; e.g. 1M records with
+ *     4M pairs fit); nothing is launched.
+ *   GS_ERR_HIP if the array's device address cannot be obtained.
+ * It calls no allocating routine.  The array is looked up for the device that is
+ * current at the call, which must be the device of `stream`.  Every call on one
+ * GPU uses the same array and leaves its contents behind (each call clears what
+ * it needs first): two calls that overlap in time on one GPU (different
+ * streams, or different host threads, without ordering) race and give wrong
+ * results. */
+#define GS_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+gs_status gs_bin_sort_static(const void* records, const uint32_t* depth_keys, const int32_t* tiles_touched,
+                             int32_t n_views, int32_t width, int32_t height, const gs_tuning* tuning,
+                             int64_t record_capacity, int64_t pair_capacity, uint32_t* pair_tiles,
+                             uint32_t* pair_records, uint32_t* tile_ranges, uint32_t* tile_queue, int64_t* counts,
+                             void* stream);
 
 /* Per-tile front-to-back alpha compositing of Eq. 1: for each pixel, walk its
  * tile's list; skip entries whose footprint does not hold the pixel; alpha =

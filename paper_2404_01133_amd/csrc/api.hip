@@ -39,6 +39,8 @@ extern "C" const char* gs_status_string(gs_status status) {
     case GS_ERR_WORKSPACE: return "GS_ERR_WORKSPACE: workspace smaller than gs_workspace_bytes()";
     case GS_ERR_CAPACITY: return "GS_ERR_CAPACITY: a record or pair capacity was exceeded";
     case GS_ERR_HIP: return gs::g_err[0] ? gs::g_err : "GS_ERR_HIP";
+    case GS_ERR_SCRATCH:
+      return "GS_ERR_SCRATCH: the capacities need more workspace than the static scratch array holds";
     default: return "unknown gs_status";
   }
 }

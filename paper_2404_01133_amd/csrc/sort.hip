@@ -21,6 +21,8 @@
 // wait is still bounded (kSpinLimit) and raises GS_FLAG_WAIT if it gives up.
 // Every device size is read from the counts array, so nothing here needs a
 // host synchronisation and the whole stage can be captured in a HIP graph.
+#include <mutex>
+
 #include "radix.h"
 
 namespace gs {
@@ -624,4 +626,60 @@ extern "C" gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys
     GS_LAUNCH_CHECK();
   }
   return GS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Variant of gs_bin_sort for callers that cannot allocate: its workspace is a
+// file-scope device array.  Host code only ever uses the address that
+// hipGetSymbolAddress reports for the current device (the array's own name is
+// a host-side stand-in, not a device address).
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[GS_STATIC_SCRATCH_BYTES];
+
+namespace gs {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's copy of `scratch`, looked up once per device.
+gs_status static_scratch(void** out) {
+  int dev = -1;
+  GS_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return GS_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    GS_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return GS_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return GS_OK;
+}
+
+}  // namespace
+}  // namespace gs
+
+extern "C" gs_status gs_bin_sort_static(const void* records, const uint32_t* depth_keys,
+                                        const int32_t* tiles_touched, int32_t n_views, int32_t width, int32_t height,
+                                        const gs_tuning* tuning, int64_t record_capacity, int64_t pair_capacity,
+                                        uint32_t* pair_tiles, uint32_t* pair_records, uint32_t* tile_ranges,
+                                        uint32_t* tile_queue, int64_t* counts, void* stream) {
+  // the checks gs_bin_sort makes without a workspace come first, so a bad call
+  // fails the same way before the scratch array is looked up
+  if (!records || !depth_keys || !tiles_touched || !tuning || !pair_tiles || !pair_records || !tile_ranges ||
+      !counts)
+    return GS_ERR_INVALID_ARG;
+  if (record_capacity <= 0 || pair_capacity <= 0) return GS_ERR_INVALID_ARG;
+  if (record_capacity >= ((int64_t)1 << 30) || pair_capacity >= ((int64_t)1 << 30)) return GS_ERR_INVALID_ARG;
+  if (gs::bin_sort_ws_bytes(record_capacity, pair_capacity) > (size_t)GS_STATIC_SCRATCH_BYTES)
+    return GS_ERR_SCRATCH;
+  void* ws = nullptr;
+  const gs_status st = gs::static_scratch(&ws);
+  if (st != GS_OK) return st;
+  return gs_bin_sort(records, depth_keys, tiles_touched, n_views, width, height, tuning, record_capacity,
+                     pair_capacity, pair_tiles, pair_records, tile_ranges, tile_queue, counts, ws,
+                     (size_t)GS_STATIC_SCRATCH_BYTES, stream);
 }

@@ -23,6 +23,8 @@ GS_ERR_UNSUPPORTED = -2
 GS_ERR_WORKSPACE = -3
 GS_ERR_CAPACITY = -4
 GS_ERR_HIP = -5
+GS_ERR_SCRATCH = -6
+GS_STATIC_SCRATCH_BYTES = 64 << 20
 
 GS_COUNT_RECORDS, GS_COUNT_VISIBLE, GS_COUNT_PAIRS, GS_COUNT_FLAGS = 0, 1, 2, 3
 GS_COUNT_SLOTS = 8
@@ -76,6 +78,8 @@ _SIGNATURES = {
                                 c_int32, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "gs_bin_sort": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_int64, c_int64,
                               c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "gs_bin_sort_static": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_int64,
+                                     c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "gs_rasterize_fwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p,
                                    c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "gs_rasterize_bwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p,
@@ -256,6 +260,15 @@ def bin_sort(records, depth_keys, tiles_touched, n_views, width, height, tuning:
                              ctypes.byref(tuning), record_capacity, pair_capacity, _p(pair_tiles), _p(pair_records),
                              _p(tile_ranges), _p(tile_queue), _p(counts), _p(ws), ws.numel() * ws.element_size(),
                              _stream(stream)), "gs_bin_sort")
+
+
+def bin_sort_static(records, depth_keys, tiles_touched, n_views, width, height, tuning: gs_tuning, record_capacity,
+                    pair_capacity, pair_tiles, pair_records, tile_ranges, counts, stream=None, tile_queue=None):
+    """gs_bin_sort with the library's static scratch array as workspace (no allocation)."""
+    _check(lib().gs_bin_sort_static(_p(records), _p(depth_keys), _p(tiles_touched), n_views, width, height,
+                                    ctypes.byref(tuning), record_capacity, pair_capacity, _p(pair_tiles),
+                                    _p(pair_records), _p(tile_ranges), _p(tile_queue), _p(counts), _stream(stream)),
+           "gs_bin_sort_static")
 
 
 def rasterize_fwd(records, pair_records, tile_ranges, n_views, width, height, bg, tuning: gs_tuning, rgb, T_final,

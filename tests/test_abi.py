@@ -102,3 +102,25 @@ def test_unsupported_tile_shape_rejected(libgs):
     bg = (ctypes.c_float * 3)(0, 0, 0)
     r = libgs.gs_rasterize_fwd(dummy, dummy, dummy, None, 1, 64, 64, bg, ctypes.byref(t), dummy, dummy, dummy, None)
     assert r == -2
+
+
+def test_static_scratch_variant_checks_before_any_device_call(libgs):
+    # gs_bin_sort_static rejects NULL buffers and capacities whose workspace exceeds
+    # the static array (GS_ERR_SCRATCH) before it looks the array up on a device
+    P = ctypes.c_void_p
+    f = libgs.gs_bin_sort_static
+    f.restype = ctypes.c_int32
+    f.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int64, ctypes.c_int64,
+                  P, P, P, P, P, P]
+
+    class Tuning(ctypes.Structure):
+        _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("batch", ctypes.c_int32),
+                    ("flags", ctypes.c_int32)]
+
+    t = Tuning(16, 16, 256, 0)
+    one = P(1)  # never dereferenced: the call returns before any launch
+    assert f(None, None, None, 1, 64, 64, None, 10, 10, None, None, None, None, None, None) == -1
+    assert f(one, one, one, 1, 64, 64, ctypes.byref(t), 0, 10, one, one, one, None, one, None) == -1
+    assert f(one, one, one, 1, 64, 64, ctypes.byref(t), 1 << 22, 1 << 24, one, one, one, None, one, None) == -6
+    libgs.gs_status_string.restype = ctypes.c_char_p
+    assert libgs.gs_status_string(-6).decode().startswith("GS_ERR_SCRATCH")
