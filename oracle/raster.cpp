@@ -335,7 +335,7 @@ struct PixelResult {
 // second correct result of a pixel with one such decision.
 PixelResult composite(const std::vector<const Splat*>& list, int i, int j, const double bg[3],
                       std::vector<const Splat*>* contrib, std::vector<double>* alphas, std::vector<double>* Ts,
-                      int flip = -1) {
+                      int flip = -1, std::vector<const Splat*>* near = nullptr, double near_band = 0.0) {
   PixelResult r;
   r.C[0] = r.C[1] = r.C[2] = 0.0;
   r.T = 1.0;
@@ -349,6 +349,7 @@ PixelResult composite(const std::vector<const Splat*>& list, int i, int j, const
     double power = -0.5 * (s->A * dx * dx + s->C * dy * dy) - s->B * dx * dy;
     double raw = s->o * std::exp(power);
     double alpha = std::min(kAlphaMax, raw);
+    if (near && std::fabs(alpha - kAlphaMin) <= near_band * kAlphaMin) near->push_back(s);
     bool skip = alpha < kAlphaMin;
     if (std::fabs(alpha - kAlphaMin) <= kBand * kAlphaMin) {
       if (r.ambiguous == flip) skip = !skip;
@@ -356,6 +357,7 @@ PixelResult composite(const std::vector<const Splat*>& list, int i, int j, const
     }
     if (skip) continue;
     double Tn = r.T * (1.0 - alpha);
+    if (near && std::fabs(Tn - kTMin) <= near_band * kTMin) near->push_back(s);
     bool stop = Tn < kTMin;
     if (std::fabs(Tn - kTMin) <= kBand * kTMin) {
       if (r.ambiguous == flip) stop = !stop;
@@ -363,6 +365,7 @@ PixelResult composite(const std::vector<const Splat*>& list, int i, int j, const
     }
     if (stop) break;
     if (std::fabs(raw - kAlphaMax) <= kBand * kAlphaMax) r.grad_ambiguous++;
+    if (near && std::fabs(raw - kAlphaMax) <= near_band * kAlphaMax) near->push_back(s);
     if (contrib) {
       contrib->push_back(s);
       alphas->push_back(alpha);
@@ -556,10 +559,22 @@ int64_t orc_pairs(int64_t n, const double* means, const double* scales, const do
 // Exact FP64 gradient of sum(dimg * img) with respect to every parameter.
 //   dimg: [3][H][W]; g2d (optional): [n][9] = dL/d(u, v, A, B, C, opacity, r, g, b)
 //   with (A, B, C) the conic entries; outputs [3][n], [3][n], [4][n], [n], [16][3][n].
+//   abs_out (optional, [59][n]: means, scales, quats, opac, sh): the same chain
+//   applied to the sums of the magnitudes of the per-pixel terms, a bound on
+//   what a gradient entry's summands add up to before they cancel (the scale
+//   of the rounding error of any evaluation that sums them in another order).
+//   The colour behind an entry counts with the magnitude of the pixel's final
+//   colour: an adjoint that walks front to back forms it as the final colour
+//   minus the colour in front, a difference of numbers of that size.
+//   near_out (optional, [n], zeroed by the caller): set to 1 for every Gaussian
+//   with a decision at some pixel within a relative near_band of its threshold
+//   (alpha vs 1/255, T vs 1e-4, raw alpha vs 0.99).  The gradient is piecewise
+//   smooth with jumps at these decisions, so such a Gaussian's gradient may
+//   legitimately take another value at a slightly different precision.
 int orc_render_bwd(int64_t n, const double* means, const double* scales, const double* quats, const double* opac,
                    const double* sh, int deg, const double* cam_d, const int32_t* cam_i, const double* bg,
                    const double* dimg, double* g2d_out, double* dmeans, double* dscales, double* dquats,
-                   double* dopac, double* dsh) {
+                   double* dopac, double* dsh, double near_band, int32_t* near_out, double* abs_out) {
   Cam cam = to_cam(cam_d, cam_i);
   Inputs in{n, means, scales, quats, opac, sh, deg};
   std::vector<Splat> splats;
@@ -571,16 +586,22 @@ int orc_render_bwd(int64_t n, const double* means, const double* scales, const d
   row_lists(splats, H, rows, nullptr);
   // per-pixel adjoint of Eq. 1, accumulated per Gaussian (per-thread buffers)
   std::vector<double> g2d((size_t)n * 9, 0.0);
+  // sums of the magnitudes of the same per-pixel terms (abs_out only)
+  std::vector<double> g2d_abs(abs_out ? (size_t)n * 9 : 0, 0.0);
 #pragma omp parallel
   {
     std::vector<double> loc((size_t)n * 9, 0.0);
-    std::vector<const Splat*> contrib;
+    std::vector<double> loc_abs(abs_out ? (size_t)n * 9 : 0, 0.0);
+    std::vector<const Splat*> contrib, near;
+    std::vector<char> loc_near(near_out ? (size_t)n : 0, 0);
     std::vector<double> alphas, Ts;
 #pragma omp for schedule(dynamic, 64)
     for (int64_t p = 0; p < P; ++p) {
       int i = (int)(p % W), j = (int)(p / W);
-      contrib.clear(); alphas.clear(); Ts.clear();
-      PixelResult r = composite(rows[j], i, j, bg, &contrib, &alphas, &Ts);
+      contrib.clear(); alphas.clear(); Ts.clear(); near.clear();
+      PixelResult r = composite(rows[j], i, j, bg, &contrib, &alphas, &Ts, -1, near_out ? &near : nullptr,
+                                near_band);
+      for (const Splat* s : near) loc_near[(size_t)s->index] = 1;
       double gC[3] = {dimg[p], dimg[P + p], dimg[2 * P + p]};
       // R = colour accumulated behind entry k, including the background
       double Racc[3] = {r.T * bg[0], r.T * bg[1], r.T * bg[2]};
@@ -588,15 +609,32 @@ int orc_render_bwd(int64_t n, const double* means, const double* scales, const d
         const Splat* s = contrib[k];
         double a = alphas[k], T = Ts[k];
         double* G = &loc[(size_t)s->index * 9];
-        double dalpha = 0.0;
+        double dalpha = 0.0, dalpha_abs = 0.0;
         for (int ch = 0; ch < 3; ++ch) {
           G[6 + ch] += gC[ch] * a * T;
           dalpha += gC[ch] * (s->rgb[ch] * T - Racc[ch] / (1.0 - a));
+          // magnitude of the operands of the colour behind the entry when it is
+          // formed as (final colour - colour up to and including the entry), the
+          // form a front-to-back adjoint evaluates: both are at most r.C
+          dalpha_abs += std::fabs(gC[ch]) * (s->rgb[ch] * T + r.C[ch] / (1.0 - a));
           Racc[ch] += s->rgb[ch] * a * T;
         }
         double dx = (i + 0.5) - s->u, dy = (j + 0.5) - s->v;
         double power = -0.5 * (s->A * dx * dx + s->C * dy * dy) - s->B * dx * dy;
         double Gv = std::exp(power);
+        if (abs_out) {
+          double* Ga = &loc_abs[(size_t)s->index * 9];
+          for (int ch = 0; ch < 3; ++ch) Ga[6 + ch] += std::fabs(gC[ch]) * a * T;
+          if (!(s->o * Gv > kAlphaMax)) {
+            double pa = dalpha_abs * s->o * Gv;
+            Ga[5] += dalpha_abs * Gv;
+            Ga[0] += pa * (std::fabs(s->A * dx) + std::fabs(s->B * dy));
+            Ga[1] += pa * (std::fabs(s->C * dy) + std::fabs(s->B * dx));
+            Ga[2] += pa * 0.5 * dx * dx;
+            Ga[3] += pa * std::fabs(dx * dy);
+            Ga[4] += pa * 0.5 * dy * dy;
+          }
+        }
         if (s->o * Gv > kAlphaMax) continue;  // clamped: no gradient to o or the footprint
         G[5] += dalpha * Gv;
         double dpow = dalpha * s->o * Gv;
@@ -608,7 +646,12 @@ int orc_render_bwd(int64_t n, const double* means, const double* scales, const d
       }
     }
 #pragma omp critical
-    for (size_t k = 0; k < g2d.size(); ++k) g2d[k] += loc[k];
+    {
+      for (size_t k = 0; k < g2d.size(); ++k) g2d[k] += loc[k];
+      for (size_t k = 0; k < g2d_abs.size(); ++k) g2d_abs[k] += loc_abs[k];
+      if (near_out)
+        for (int64_t k = 0; k < n; ++k) near_out[k] |= loc_near[(size_t)k];
+    }
   }
   if (g2d_out) std::memcpy(g2d_out, g2d.data(), g2d.size() * sizeof(double));
   // per-Gaussian chain rule, exact via dual numbers over the projection
@@ -618,10 +661,24 @@ int orc_render_bwd(int64_t n, const double* means, const double* scales, const d
     for (int k = 0; k < 4; ++k) dquats[k * n + g] = 0;
     dopac[g] = 0;
     for (int k = 0; k < 48; ++k) dsh[(size_t)k * n + g] = 0;
+    // abs_out layout: means [3][n], scales [3][n], quats [4][n], opac [n], sh [48][n]
+    double* am = abs_out ? abs_out : nullptr;
+    double* as = abs_out ? abs_out + 3 * n : nullptr;
+    double* aq = abs_out ? abs_out + 6 * n : nullptr;
+    double* ao = abs_out ? abs_out + 10 * n : nullptr;
+    double* ash = abs_out ? abs_out + 11 * n : nullptr;
+    if (abs_out) {
+      for (int k = 0; k < 3; ++k) am[k * n + g] = as[k * n + g] = 0;
+      for (int k = 0; k < 4; ++k) aq[k * n + g] = 0;
+      ao[g] = 0;
+      for (int k = 0; k < 48; ++k) ash[(size_t)k * n + g] = 0;
+    }
     const Decisions& dec = decs[g];
     if (!dec.visible) continue;
     const double* G = &g2d[(size_t)g * 9];
+    const double* Ga = abs_out ? &g2d_abs[(size_t)g * 9] : nullptr;
     dopac[g] = G[5];
+    if (abs_out) ao[g] = Ga[5];
     double m[3], s[3], q[4], shv[48];
     load_params(in, g, m, s, q, shv);
     // SH coefficients enter the colour linearly: d rgb_ch / d f_{k,ch} = Y_k(dir)
@@ -636,7 +693,10 @@ int orc_render_bwd(int64_t n, const double* means, const double* scales, const d
       int nk = (deg + 1) * (deg + 1);
       for (int k = 0; k < nk; ++k)
         for (int ch = 0; ch < 3; ++ch)
-          if (!dec.rgb_clamped[ch]) dsh[(size_t)(k * 3 + ch) * n + g] = Y[k] * G[6 + ch];
+          if (!dec.rgb_clamped[ch]) {
+            dsh[(size_t)(k * 3 + ch) * n + g] = Y[k] * G[6 + ch];
+            if (abs_out) ash[(size_t)(k * 3 + ch) * n + g] = std::fabs(Y[k]) * Ga[6 + ch];
+          }
     }
     // geometry parameters: 3 means, 3 scales, 4 quaternion entries
     for (int dir = 0; dir < 10; ++dir) {
@@ -652,6 +712,14 @@ int orc_render_bwd(int64_t n, const double* means, const double* scales, const d
       if (dir < 3) dmeans[dir * n + g] = gsum;
       else if (dir < 6) dscales[(dir - 3) * n + g] = gsum;
       else dquats[(dir - 6) * n + g] = gsum;
+      if (abs_out) {
+        double asum = Ga[0] * std::fabs(Pd.u.d) + Ga[1] * std::fabs(Pd.v.d) + Ga[2] * std::fabs(Pd.A.d) +
+                      Ga[3] * std::fabs(Pd.B.d) + Ga[4] * std::fabs(Pd.C.d);
+        for (int ch = 0; ch < 3; ++ch) asum += Ga[6 + ch] * std::fabs(Pd.rgb[ch].d);
+        if (dir < 3) am[dir * n + g] = asum;
+        else if (dir < 6) as[(dir - 3) * n + g] = asum;
+        else aq[(dir - 6) * n + g] = asum;
+      }
     }
   }
   return 0;

@@ -574,3 +574,45 @@ def test_both_branches_at_the_transmittance_threshold():
     np.testing.assert_allclose(r["img"][:, 24, 32], rgb * (1 - (1 - a) ** 14), rtol=1e-12)
     np.testing.assert_allclose(r["img_alt"][:, 24, 32], rgb * (1 - (1 - a) ** 13), rtol=1e-12)
     np.testing.assert_allclose(r["T_alt"][24, 32], (1 - a) ** 13, rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# bookkeeping of the backward used by the GPU gradient comparison: magnitude
+# sums bound the gradient (triangle inequality) and equal it where no term
+# cancels; near-threshold flags mark exactly the Gaussians at a decision band
+# ---------------------------------------------------------------------------
+def test_gradient_magnitudes_bound_and_match_without_cancellation():
+    g, cam = synth.small_render_case(300, seed=4, width=64, height=48)
+    rng = np.random.default_rng(5)
+    dimg = rng.normal(size=(3, cam.height, cam.width))
+    out = oracle.render_bwd(g, cam, dimg, 3, magnitudes=True)
+    for name in ("means", "scales", "quats", "opac", "sh"):
+        assert (np.abs(out[name]) <= out["abs:" + name] * (1 + 1e-12) + 1e-300).all(), name
+    # a lone Gaussian under a positive uniform adjoint: the colour terms alpha T
+    # are all positive, so the SH-coefficient magnitudes equal the gradient (up
+    # to the sign of Y_k)
+    W, H = 33, 33
+    cam1 = identity_cam(W, H, 40.0)
+    g1 = make_set([[0.0], [0.0], [2.0]], [[0.1], [0.1], [0.1]], [[1.0], [0], [0], [0]], [0.6],
+                  grey_sh(np.array([0.3, 0.5, 0.7]), 1), np.float64)
+    o1 = oracle.render_bwd(g1, cam1, np.ones((3, H, W)), 0, magnitudes=True)
+    np.testing.assert_allclose(o1["abs:sh"][0, :, 0], np.abs(o1["sh"][0, :, 0]), rtol=1e-12)
+    np.testing.assert_allclose(o1["abs:opac"][0], abs(o1["opac"][0]), rtol=1e-12)
+
+
+def test_near_threshold_flags_mark_the_gaussian_at_the_band():
+    # two Gaussians side by side; the first, on the optical axis (principal point
+    # on a pixel corner), has alpha 1/255 (1 + 1e-7) at its four central pixels:
+    # only it is flagged at band 1e-6, neither at 1e-9
+    W, H, fx = 64, 32, 40.0
+    cam = identity_cam(W, H, fx)
+    s, z = 0.1, 2.0
+    sig2 = (fx * s / z) ** 2 + 0.3
+    o_near = (1.0 / 255.0) * math.exp(0.5 * 0.5 / sig2) * (1.0 + 1e-7)
+    xl = 0.0
+    xr = 16.0 * z / fx           # 16 px right of the principal point
+    g = make_set([[xl, xr], [0.0, 0.0], [z, z]], [[s, s], [s, s], [s, s]], [[1.0, 1.0], [0, 0], [0, 0], [0, 0]],
+                 [o_near, 0.5], grey_sh(np.array([0.5, 0.8, 0.2]), 2), np.float64)
+    dimg = np.ones((3, H, W))
+    assert oracle.render_bwd(g, cam, dimg, 0, near_band=1e-6)["near"].tolist() == [True, False]
+    assert oracle.render_bwd(g, cam, dimg, 0, near_band=1e-9)["near"].tolist() == [False, False]
