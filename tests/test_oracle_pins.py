@@ -588,16 +588,32 @@ def test_gradient_magnitudes_bound_and_match_without_cancellation():
     out = oracle.render_bwd(g, cam, dimg, 3, magnitudes=True)
     for name in ("means", "scales", "quats", "opac", "sh"):
         assert (np.abs(out[name]) <= out["abs:" + name] * (1 + 1e-12) + 1e-300).all(), name
-    # a lone Gaussian under a positive uniform adjoint: the colour terms alpha T
-    # are all positive, so the SH-coefficient magnitudes equal the gradient (up
-    # to the sign of Y_k)
-    W, H = 33, 33
-    cam1 = identity_cam(W, H, 40.0)
-    g1 = make_set([[0.0], [0.0], [2.0]], [[0.1], [0.1], [0.1]], [[1.0], [0], [0], [0]], [0.6],
-                  grey_sh(np.array([0.3, 0.5, 0.7]), 1), np.float64)
+    # a lone isotropic Gaussian on the axis under a uniform adjoint of 1: the
+    # colour terms alpha T are all positive, so the SH-coefficient magnitudes
+    # equal the gradient; the opacity magnitude counts, per pixel, G times
+    # sum_c (rgb_c T + C_c / (1 - alpha)) with T = 1 and the pixel's final colour
+    # C_c = rgb_c alpha (black background), written out here from the closed form
+    W, H, fx, s1, z1, o = 33, 33, 40.0, 0.1, 2.0, 0.6
+    rgb = np.array([0.3, 0.5, 0.7])
+    cam1 = identity_cam(W, H, fx)
+    g1 = make_set([[0.0], [0.0], [z1]], [[s1], [s1], [s1]], [[1.0], [0], [0], [0]], [o], grey_sh(rgb, 1), np.float64)
     o1 = oracle.render_bwd(g1, cam1, np.ones((3, H, W)), 0, magnitudes=True)
     np.testing.assert_allclose(o1["abs:sh"][0, :, 0], np.abs(o1["sh"][0, :, 0]), rtol=1e-12)
-    np.testing.assert_allclose(o1["abs:opac"][0], abs(o1["opac"][0]), rtol=1e-12)
+    sig2 = (fx * s1 / z1) ** 2 + 0.3
+    r = math.ceil(3.0 * math.sqrt(sig2))
+    c = W / 2.0                                                # principal point: the centre of pixel 16
+    want = 0.0
+    for j in range(H):
+        for i in range(W):
+            dx, dy = i + 0.5 - c, j + 0.5 - c
+            if abs(i + 0.5 - c) > r or abs(j + 0.5 - c) > r:   # the 3-sigma pixel rectangle
+                continue
+            G = math.exp(-0.5 * (dx * dx + dy * dy) / sig2)
+            a = o * G
+            if a < 1.0 / 255.0:
+                continue
+            want += G * float(np.sum(rgb + rgb * a / (1.0 - a)))
+    np.testing.assert_allclose(o1["abs:opac"][0], want, rtol=1e-10)
 
 
 def test_near_threshold_flags_mark_the_gaussian_at_the_band():
