@@ -149,11 +149,25 @@ typedef struct gs_tuning {
 /* tuning.flags: rasterize_fwd / rasterize_bwd run as persistent kernels that take
  * tiles from a device work queue, longest tile lists first. */
 #define GS_TUNE_WORK_QUEUE 2
+/* tuning.flags: bit-reproducible gradients from gs_rasterize_bwd (Sec. 3.1, the
+ * adjoint of Eq. 1 summed over pixels, tiles and views).  Without it partial
+ * sums are added with FP32 atomics, whose order varies from run to run.  With
+ * it every sum has a fixed order: within a tile, per-quadrant sums are added in
+ * quadrant order; each (tile, record) partial goes to its own workspace slot
+ * and a record's slots are summed in ascending tile order; a Gaussian's
+ * records are summed in view order.  Costs a larger workspace (36 bytes per
+ * pair of capacity, see gs_workspace_bytes) and time.  Supported for one view,
+ * for GS_TUNE_SHARED_SELECTION, and for several block-wise views (then each
+ * level must store its blocks in ascending block order); several point-wise
+ * views return GS_ERR_UNSUPPORTED.  Ignored by the other entry points. */
+#define GS_TUNE_DETERMINISTIC 4
 
 /* Size in bytes of one projected record (an opaque device structure). */
 size_t gs_record_bytes(void);
 
-/* Workspace needed by gs_bin_sort / gs_rasterize_bwd for the given capacities. */
+/* Workspace needed by gs_bin_sort / gs_rasterize_bwd for the given capacities
+ * (for gs_rasterize_bwd with GS_TUNE_DETERMINISTIC in tuning->flags, size it
+ * with the pair capacity given to gs_bin_sort: it holds one slot per pair). */
 #define GS_WS_BIN_SORT 1
 #define GS_WS_RASTERIZE_BWD 2
 size_t gs_workspace_bytes(int32_t which, int64_t record_capacity, int64_t pair_capacity, int32_t n_views,
@@ -292,7 +306,10 @@ gs_status gs_rasterize_fwd(const void* records, const uint32_t* pair_records, co
  * grads[n_levels] (host array of device buffers shaped like the levels).  The
  * blend state of each pixel is recomputed front to back from the saved T_final
  * and n_last, so no per-(pixel, Gaussian) state is stored.  Accumulation uses
- * FP32 atomics: results are reproducible to rounding, not bit for bit.
+ * FP32 atomics: results are reproducible to rounding, not bit for bit, unless
+ * tuning->flags holds GS_TUNE_DETERMINISTIC (then bit for bit; the workspace
+ * then holds one slot per pair: pairs beyond the slots it has are not summed,
+ * so it must be sized with the pair capacity the frame was binned with).
  * tile_queue: as for gs_rasterize_fwd (uses the second head counter, reset the same
  *   way, so several backward calls may follow one forward).
  * level / offsets / gather: the selection passed to gs_preprocess.

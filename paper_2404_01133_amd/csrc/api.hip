@@ -6,7 +6,7 @@
 namespace gs {
 
 size_t bin_sort_ws_bytes(int64_t rc, int64_t pc);
-size_t rasterize_bwd_ws_bytes(int64_t rc);
+size_t rasterize_bwd_ws_bytes(int64_t rc, int64_t pc, bool det);
 
 static thread_local char g_err[256];
 
@@ -24,10 +24,11 @@ extern "C" size_t gs_workspace_bytes(int32_t which, int64_t record_capacity, int
   (void)n_views;
   (void)width;
   (void)height;
-  (void)tuning;
   if (record_capacity < 0 || pair_capacity < 0) return 0;
   if (which == GS_WS_BIN_SORT) return gs::bin_sort_ws_bytes(record_capacity, pair_capacity);
-  if (which == GS_WS_RASTERIZE_BWD) return gs::rasterize_bwd_ws_bytes(record_capacity);
+  if (which == GS_WS_RASTERIZE_BWD)
+    return gs::rasterize_bwd_ws_bytes(record_capacity, pair_capacity,
+                                      tuning && (tuning->flags & GS_TUNE_DETERMINISTIC) != 0);
   return 0;
 }
 

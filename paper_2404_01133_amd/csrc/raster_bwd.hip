@@ -56,20 +56,44 @@ __device__ __forceinline__ float quad_sum9(const float v[9], int lane) {
 constexpr int kG = 9;  // partials per Gaussian: r, g, b, opacity, A1, A2, Axx, Axy, Ayy
 constexpr int kBwdLdsOffsets = 1024;  // segment offsets staged in LDS by the view-major adjoint up to this many
 
-template <int TW, int TH, int BATCH>
+// DET: each quadrant of the tile stores its sums for the staged records in its
+// own slots (grad[quadrant][record][9], plain stores: a quadrant's list holds a
+// record at most once); the slots are then summed in quadrant order.
+// Otherwise grad[record][9] receives LDS atomic adds.
+template <int TW, int TH, int BATCH, bool DET>
 struct BwdLds {
+  static constexpr int kQuads = DET ? (TW * TH) / 16 : 1;
   float4 w0[BATCH], w1[BATCH], w2[BATCH];
   uint32_t rec[BATCH];
-  float grad[BATCH * kG];
+  float grad[kQuads * BATCH * kG];
   uint8_t list[(TW * TH) / 64][4][kListStride<BATCH>];
   int wave_last[(TW * TH) / 64];
 };
 
-template <int TW, int TH, int BATCH>
-__device__ __forceinline__ void raster_bwd_tile(const TileArgs& ta, BwdLds<TW, TH, BATCH>& lds, int tile_g,
+// Deterministic mode: per-(tile, record) partials are stored at slot
+// base[record] + (the tile's row-major index within the record's footprint
+// tiles), so a record's partials lie contiguous in ascending tile order and
+// are summed in that order afterwards.
+struct DetArgs {
+  float* partial;        // [slots][kG]
+  const uint32_t* base;  // [records]: first slot of each record
+  int64_t slots;         // slots the workspace holds
+};
+
+template <int TW, int TH>
+__device__ __forceinline__ int64_t det_slot(const DetArgs& d, uint32_t rid, uint32_t px, uint32_t py, int txi,
+                                            int tyi) {
+  const int i0 = (int)(px & 0xFFFFu), i1 = i0 + (int)(px >> 16);
+  const int j0 = (int)(py & 0xFFFFu);
+  const int tx0 = i0 / TW, ntx = i1 / TW - tx0 + 1, ty0 = j0 / TH;
+  return (int64_t)d.base[rid] + (int64_t)(tyi - ty0) * ntx + (txi - tx0);
+}
+
+template <int TW, int TH, int BATCH, bool DET>
+__device__ __forceinline__ void raster_bwd_tile(const TileArgs& ta, BwdLds<TW, TH, BATCH, DET>& lds, int tile_g,
                                                 const float* __restrict__ rgb, const float* __restrict__ T_final,
                                                 const int32_t* __restrict__ n_last, const float* __restrict__ d_rgb,
-                                                float* __restrict__ grad2d) {
+                                                float* __restrict__ grad2d, const DetArgs& det) {
   constexpr int NT = TW * TH;
   constexpr int NW = NT / 64;
   const Record* __restrict__ records = ta.records;
@@ -127,7 +151,7 @@ __device__ __forceinline__ void raster_bwd_tile(const TileArgs& ta, BwdLds<TW, T
       s_w2[k] = rp[2];
       s_rec[k] = rid;
     }
-    for (int k = threadIdx.x; k < nb * kG; k += NT) s_grad[k] = 0.0f;
+    for (int k = threadIdx.x; k < lds.kQuads * BATCH * kG; k += NT) s_grad[k] = 0.0f;
     __syncthreads();
     const int base_idx = (int)(b - start);
     const int kmax = min(nb, wave_last - base_idx);  // entries past every lane's n_last are not needed
@@ -170,7 +194,11 @@ __device__ __forceinline__ void raster_bwd_tile(const TileArgs& ta, BwdLds<TW, T
       A2c = use ? nA2 : A2c;
       T = use ? T * (1.0f - e.alpha) : T;
       const float sum = quad_sum9(c, lane);
-      if (valid && r < kG && sum != 0.0f) atomicAdd(&s_grad[k * kG + r], sum);
+      if constexpr (DET) {
+        if (valid && r < kG) s_grad[((wid * 4 + qb.g) * BATCH + k) * kG + r] = sum;
+      } else {
+        if (valid && r < kG && sum != 0.0f) atomicAdd(&s_grad[k * kG + r], sum);
+      }
     };
     // two entries of the lane's quadrant list per trip, byte indices in one LDS
     // read (entries past the quadrant's count: stale bytes, masked, not used)
@@ -183,25 +211,131 @@ __device__ __forceinline__ void raster_bwd_tile(const TileArgs& ta, BwdLds<TW, T
       step(kb, t + 1 < my_cnt, b0, b1, b2);
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < nb * kG; t += NT) {
-      const float v = s_grad[t];
-      if (v != 0.0f) unsafeAtomicAdd(&grad2d[(int64_t)s_rec[t / kG] * kG + (t % kG)], v);
+    if constexpr (DET) {
+      for (int t = threadIdx.x; t < nb * kG; t += NT) {
+        float v = 0.0f;
+        for (int q = 0; q < lds.kQuads; ++q) v += s_grad[q * BATCH * kG + t];
+        const int k = t / kG;
+        const int64_t slot = det_slot<TW, TH>(det, s_rec[k], __float_as_uint(s_w0[k].z),
+                                              __float_as_uint(s_w0[k].w), txi, tyi);
+        if (slot < det.slots) det.partial[slot * kG + (t - k * kG)] = v;
+      }
+    } else {
+      for (int t = threadIdx.x; t < nb * kG; t += NT) {
+        const float v = s_grad[t];
+        if (v != 0.0f) unsafeAtomicAdd(&grad2d[(int64_t)s_rec[t / kG] * kG + (t % kG)], v);
+      }
     }
     __syncthreads();
   }
+  if constexpr (DET) {
+    // entries behind every pixel's last one were not walked: their slots get zeros
+    const uint32_t len = ranges[2 * tile_g + 1] - start;
+    for (uint32_t k = (uint32_t)tile_last + threadIdx.x; k < len; k += NT) {
+      const uint32_t rid = pair_records[start + k];
+      const uint4 w0 = *reinterpret_cast<const uint4*>(&records[rid]);
+      const int64_t slot = det_slot<TW, TH>(det, rid, w0.z, w0.w, txi, tyi);
+      if (slot < det.slots)
+#pragma unroll
+        for (int q = 0; q < kG; ++q) det.partial[slot * kG + q] = 0.0f;
+    }
+  }
 }
 
-template <int TW, int TH, int BATCH>
+template <int TW, int TH, int BATCH, bool DET>
 __global__ void __launch_bounds__(TW* TH) raster_bwd_kernel(TileArgs ta, uint32_t* queue,
                                                             const float* __restrict__ rgb,
                                                             const float* __restrict__ T_final,
                                                             const int32_t* __restrict__ n_last,
                                                             const float* __restrict__ d_rgb,
-                                                            float* __restrict__ grad2d) {
-  __shared__ BwdLds<TW, TH, BATCH> lds;
+                                                            float* __restrict__ grad2d, DetArgs det) {
+  __shared__ BwdLds<TW, TH, BATCH, DET> lds;
   for_each_tile(ta, queue, 1, [&](int tile_g) {
-    raster_bwd_tile<TW, TH, BATCH>(ta, lds, tile_g, rgb, T_final, n_last, d_rgb, grad2d);
+    raster_bwd_tile<TW, TH, BATCH, DET>(ta, lds, tile_g, rgb, T_final, n_last, d_rgb, grad2d, det);
   });
+}
+
+// ---------------------------------------------------------------------------
+// deterministic mode: slots per record, then per-record sums in tile order
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t det_pairs(const int64_t* counts, int64_t slots) {
+  const int64_t m = counts[GS_COUNT_PAIRS];
+  return m < slots ? m : slots;
+}
+
+// cnt[r] = 0 for every record, and the slot cursor
+__global__ void det_clear_kernel(uint32_t* __restrict__ cnt, uint32_t* __restrict__ cursor, const int64_t* counts,
+                                 int64_t cap) {
+  int64_t n = counts[GS_COUNT_RECORDS];
+  if (n > cap) n = cap;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t0 == 0) *cursor = 0u;
+  for (int64_t k = t0; k < n; k += stride) cnt[k] = 0u;
+}
+
+// cnt[r] = number of (tile, record) pairs of record r (integer adds: exact in any order)
+__global__ void det_count_kernel(const uint32_t* __restrict__ pair_records, const int64_t* counts, int64_t slots,
+                                 uint32_t* __restrict__ cnt) {
+  const int64_t m = det_pairs(counts, slots);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += stride)
+    atomicAdd(&cnt[pair_records[p]], 1u);
+}
+
+// base[r]: a contiguous run of cnt[r] slots per record.  Where a run lies does
+// not change any sum, so work-groups take their ranges with one atomic each.
+__global__ void __launch_bounds__(256) det_base_kernel(const uint32_t* __restrict__ cnt, const int64_t* counts,
+                                                       int64_t cap, uint32_t* __restrict__ cursor,
+                                                       uint32_t* __restrict__ base) {
+  __shared__ uint32_t s_wave[4];
+  __shared__ uint32_t s_start;
+  int64_t n = counts[GS_COUNT_RECORDS];
+  if (n > cap) n = cap;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int64_t r0 = (int64_t)blockIdx.x * 256; r0 < n; r0 += (int64_t)gridDim.x * 256) {
+    const int64_t r = r0 + threadIdx.x;
+    const uint32_t c = r < n ? cnt[r] : 0u;
+    uint32_t inc = c;
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += y;
+    }
+    if (lane == 63) s_wave[wid] = inc;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (int w = 0; w < 4; ++w) {
+      before += w < wid ? s_wave[w] : 0u;
+      total += s_wave[w];
+    }
+    if (threadIdx.x == 0) s_start = total ? atomicAdd(cursor, total) : 0u;
+    __syncthreads();
+    if (r < n) base[r] = s_start + before + inc - c;
+    __syncthreads();
+  }
+}
+
+// grad2d[r] = sum of record r's slots, in ascending tile order
+__global__ void det_reduce_kernel(const float* __restrict__ partial, const uint32_t* __restrict__ cnt,
+                                  const uint32_t* __restrict__ base, const int64_t* counts, int64_t cap,
+                                  int64_t slots, float* __restrict__ grad2d) {
+  int64_t n = counts[GS_COUNT_RECORDS];
+  if (n > cap) n = cap;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+    const uint32_t c = cnt[r];
+    if (c == 0) continue;
+    const int64_t b = base[r];
+    if (b + c > slots) continue;  // the workspace holds fewer slots than pairs
+    float acc[kG];
+#pragma unroll
+    for (int q = 0; q < kG; ++q) acc[q] = 0.0f;
+    for (uint32_t k = 0; k < c; ++k)
+#pragma unroll
+      for (int q = 0; q < kG; ++q) acc[q] += partial[(b + k) * kG + q];
+#pragma unroll
+    for (int q = 0; q < kG; ++q) grad2d[r * kG + q] = acc[q];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -211,6 +345,7 @@ struct BwdArgs {
   LevelPtrs lv[kMaxLevels];
   gs_gaussian_grads gr[kMaxLevels];
   const int64_t* lvl_off;
+  const int64_t* lvl_cnt;
   const int8_t* level;
   const int64_t* offsets;
   const uint32_t* gather;  // point-wise selection: record -> index within its level
@@ -583,6 +718,49 @@ __global__ void __launch_bounds__(256) preprocess_bwd_shared_kernel(BwdArgs a, c
   }
 }
 
+// Deterministic mode with several views that selected different blocks or
+// levels (block-wise): one thread per stored Gaussian of every level sums its
+// records over the views in view order (record of view v: the view chose the
+// Gaussian's block at the Gaussian's level) and adds the total once.
+__global__ void __launch_bounds__(256) preprocess_bwd_det_kernel(BwdArgs a, const Record* __restrict__ records,
+                                                                 const float* __restrict__ grad2d,
+                                                                 const int64_t* __restrict__ counts,
+                                                                 int64_t n_stored) {
+  int64_t n_rec = counts[GS_COUNT_RECORDS];
+  if (n_rec > a.capacity) n_rec = a.capacity;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_stored; t += stride) {
+    int l = 0;
+    int64_t gi = t;
+    while (l < a.L - 1 && gi >= a.lv[l].n) gi -= a.lv[l++].n;
+    // block of gi in level l: blocks are stored in block order, so the last block
+    // whose first index is <= gi (then checked against its count)
+    int lo = 0, hi = a.B - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.lvl_off[(int64_t)mid * a.L + l] <= gi) lo = mid;
+      else hi = mid - 1;
+    }
+    const int b = lo;
+    const int64_t first = a.lvl_off[(int64_t)b * a.L + l];
+    if (gi < first || gi >= first + a.lvl_cnt[(int64_t)b * a.L + l]) continue;
+    RegisterSink acc;
+    bool any = false;
+    for (int v = 0; v < a.V; ++v) {
+      const int64_t p = (int64_t)v * a.B + b;
+      if (a.level[p] != l) continue;
+      const int64_t g = a.offsets[p] + (gi - first);
+      if (g >= n_rec) continue;
+      float p2[kG];
+      if (!load_grad2d(grad2d, g, p2)) continue;
+      if (a.lv[l].half) preprocess_bwd_record_t<true>(a, records, p2, g, v, l, gi, acc);
+      else preprocess_bwd_record_t<false>(a, records, p2, g, v, l, gi, acc);
+      any = true;
+    }
+    if (any) acc.flush(a.gr[l], a.lv[l].n, gi, (a.lv[l].sh_deg + 1) * (a.lv[l].sh_deg + 1));
+  }
+}
+
 __global__ void clear_floats_kernel(float* __restrict__ p, const int64_t* counts, int64_t cap, int per_record) {
   int64_t n = counts[GS_COUNT_RECORDS];
   if (n > cap) n = cap;
@@ -592,21 +770,65 @@ __global__ void clear_floats_kernel(float* __restrict__ p, const int64_t* counts
 }
 
 template <int TW, int TH>
-void launch_bwd(int batch, const TileArgs& ta, uint32_t* queue, hipStream_t s, const float* rgb, const float* T,
-                const int32_t* nl, const float* drgb, float* g2d) {
+void launch_bwd(int batch, bool det, const TileArgs& ta, uint32_t* queue, hipStream_t s, const float* rgb,
+                const float* T, const int32_t* nl, const float* drgb, float* g2d, const DetArgs& d) {
   constexpr int NT = TW * TH;
   const dim3 grid = tile_grid(ta.n_tiles, queue != nullptr);
-  if (batch == 64)
-    hipLaunchKernelGGL((raster_bwd_kernel<TW, TH, 64>), grid, dim3(NT), 0, s, ta, queue, rgb, T, nl, drgb, g2d);
-  else if (batch == 128)
-    hipLaunchKernelGGL((raster_bwd_kernel<TW, TH, 128>), grid, dim3(NT), 0, s, ta, queue, rgb, T, nl, drgb, g2d);
-  else
-    hipLaunchKernelGGL((raster_bwd_kernel<TW, TH, 256>), grid, dim3(NT), 0, s, ta, queue, rgb, T, nl, drgb, g2d);
+  if (det) {
+    // per-quadrant slots: 64 staged records per round (32 for the largest tile), under 40 KB of LDS
+    constexpr int DB = TW * TH > 256 ? 32 : 64;
+    hipLaunchKernelGGL((raster_bwd_kernel<TW, TH, DB, true>), grid, dim3(NT), 0, s, ta, queue, rgb, T, nl, drgb, g2d,
+                       d);
+  } else if (batch == 64) {
+    hipLaunchKernelGGL((raster_bwd_kernel<TW, TH, 64, false>), grid, dim3(NT), 0, s, ta, queue, rgb, T, nl, drgb,
+                       g2d, d);
+  } else if (batch == 128) {
+    hipLaunchKernelGGL((raster_bwd_kernel<TW, TH, 128, false>), grid, dim3(NT), 0, s, ta, queue, rgb, T, nl, drgb,
+                       g2d, d);
+  } else {
+    hipLaunchKernelGGL((raster_bwd_kernel<TW, TH, 256, false>), grid, dim3(NT), 0, s, ta, queue, rgb, T, nl, drgb,
+                       g2d, d);
+  }
+}
+
+// workspace: grad2d [rc][kG]; deterministic mode adds cnt [rc], base [rc], a
+// cursor and partial [slots][kG] with one slot per pair of pair capacity
+struct BwdWs {
+  float* grad2d;
+  uint32_t* cnt;
+  uint32_t* base;
+  uint32_t* cursor;
+  float* partial;
+  size_t fixed_bytes;  // everything but the slots
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+BwdWs bwd_ws_layout(char* p, int64_t rc, bool det) {
+  BwdWs w{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* q = p ? p + off : nullptr;
+    off = align256(off + bytes);
+    return q;
+  };
+  w.grad2d = (float*)take((size_t)rc * kG * sizeof(float));
+  if (det) {
+    w.cnt = (uint32_t*)take((size_t)rc * 4);
+    w.base = (uint32_t*)take((size_t)rc * 4);
+    w.cursor = (uint32_t*)take(4);
+    w.partial = (float*)(p ? p + off : nullptr);
+  }
+  w.fixed_bytes = off;
+  return w;
 }
 
 }  // namespace
 
-size_t rasterize_bwd_ws_bytes(int64_t rc) { return (size_t)rc * kG * sizeof(float) + 256; }
+size_t rasterize_bwd_ws_bytes(int64_t rc, int64_t pc, bool det) {
+  const size_t fixed = bwd_ws_layout(nullptr, rc, det).fixed_bytes;
+  return det ? fixed + (size_t)pc * kG * sizeof(float) : fixed + 256;
+}
 
 }  // namespace gs
 
@@ -631,8 +853,17 @@ extern "C" gs_status gs_rasterize_bwd(const void* records, const uint32_t* pair_
   if (!gather && (blocks->n_blocks <= 0 || !blocks->lvl_off)) return GS_ERR_INVALID_ARG;
   const int tw = tuning->tile_w, th = tuning->tile_h;
   if (!tile_shape_supported(tw, th) || !batch_supported(tuning->batch)) return GS_ERR_UNSUPPORTED;
-  if (ws_bytes < rasterize_bwd_ws_bytes(record_capacity)) return GS_ERR_WORKSPACE;
-  float* grad2d = (float*)ws;
+  const bool det = (tuning->flags & GS_TUNE_DETERMINISTIC) != 0;
+  if (det && gather && n_views > 1 && !(tuning->flags & GS_TUNE_SHARED_SELECTION)) return GS_ERR_UNSUPPORTED;
+  if (ws_bytes < rasterize_bwd_ws_bytes(record_capacity, 0, det)) return GS_ERR_WORKSPACE;
+  const BwdWs w = bwd_ws_layout((char*)ws, record_capacity, det);
+  float* grad2d = w.grad2d;
+  DetArgs d{};
+  if (det) {
+    d.partial = w.partial;
+    d.base = w.base;
+    d.slots = (int64_t)((ws_bytes - w.fixed_bytes) / (kG * sizeof(float)));
+  }
   const int tx = tiles_x(width, tw), ty = tiles_y(height, th);
   const int64_t tpv = (int64_t)tx * ty;
   const int64_t nblocks = tpv * n_views;
@@ -642,16 +873,30 @@ extern "C" gs_status gs_rasterize_bwd(const void* records, const uint32_t* pair_
   hipLaunchKernelGGL(clear_floats_kernel, dim3((unsigned)(cg < 4096 ? (cg < 1 ? 1 : cg) : 4096)), dim3(256), 0, s,
                      grad2d, counts, record_capacity, kG);
   GS_LAUNCH_CHECK();
+  const unsigned rg = (unsigned)(cg < 4096 ? (cg < 1 ? 1 : cg) : 4096);
+  if (det) {
+    // slots: count each record's pairs, then give each record a run of that many
+    hipLaunchKernelGGL(det_clear_kernel, dim3(rg), dim3(256), 0, s, w.cnt, w.cursor, counts, record_capacity);
+    hipLaunchKernelGGL(det_count_kernel, dim3(4096), dim3(256), 0, s, pair_records, counts, d.slots, w.cnt);
+    hipLaunchKernelGGL(det_base_kernel, dim3(2048), dim3(256), 0, s, w.cnt, counts, record_capacity, w.cursor,
+                       w.base);
+    GS_LAUNCH_CHECK();
+  }
   const Record* rec = (const Record*)records;
   const TileArgs ta{rec, pair_records, tile_ranges, width, height, tx, (int)tpv, nblocks};
   uint32_t* q = ((tuning->flags & GS_TUNE_WORK_QUEUE) && tile_queue) ? tile_queue : nullptr;
   const int b = tuning->batch;
-  if (tw == 16 && th == 16) launch_bwd<16, 16>(b, ta, q, s, rgb, T_final, n_last, d_rgb, grad2d);
-  else if (tw == 8 && th == 8) launch_bwd<8, 8>(b, ta, q, s, rgb, T_final, n_last, d_rgb, grad2d);
-  else if (tw == 16 && th == 8) launch_bwd<16, 8>(b, ta, q, s, rgb, T_final, n_last, d_rgb, grad2d);
-  else if (tw == 32 && th == 8) launch_bwd<32, 8>(b, ta, q, s, rgb, T_final, n_last, d_rgb, grad2d);
-  else launch_bwd<32, 16>(b, ta, q, s, rgb, T_final, n_last, d_rgb, grad2d);
+  if (tw == 16 && th == 16) launch_bwd<16, 16>(b, det, ta, q, s, rgb, T_final, n_last, d_rgb, grad2d, d);
+  else if (tw == 8 && th == 8) launch_bwd<8, 8>(b, det, ta, q, s, rgb, T_final, n_last, d_rgb, grad2d, d);
+  else if (tw == 16 && th == 8) launch_bwd<16, 8>(b, det, ta, q, s, rgb, T_final, n_last, d_rgb, grad2d, d);
+  else if (tw == 32 && th == 8) launch_bwd<32, 8>(b, det, ta, q, s, rgb, T_final, n_last, d_rgb, grad2d, d);
+  else launch_bwd<32, 16>(b, det, ta, q, s, rgb, T_final, n_last, d_rgb, grad2d, d);
   GS_LAUNCH_CHECK();
+  if (det) {
+    hipLaunchKernelGGL(det_reduce_kernel, dim3(rg), dim3(256), 0, s, w.partial, w.cnt, w.base, counts,
+                       record_capacity, d.slots, grad2d);
+    GS_LAUNCH_CHECK();
+  }
   BwdArgs a{};
   for (int l = 0; l < blocks->n_levels; ++l) {
     const gs_gaussians& g = levels[l];
@@ -662,6 +907,7 @@ extern "C" gs_status gs_rasterize_bwd(const void* records, const uint32_t* pair_
       return GS_ERR_INVALID_ARG;
   }
   a.lvl_off = blocks->lvl_off;
+  a.lvl_cnt = blocks->lvl_cnt;
   a.level = level;
   a.offsets = offsets;
   a.gather = gather;
@@ -683,6 +929,13 @@ extern "C" gs_status gs_rasterize_bwd(const void* records, const uint32_t* pair_
     hipLaunchKernelGGL(preprocess_bwd_shared_kernel, gs_grid, dim3(256), 0, s, a, rec, grad2d, counts);
   } else if (n_views == 1) {
     hipLaunchKernelGGL(preprocess_bwd_kernel<true>, gbg, dim3(256), 0, s, a, rec, grad2d, counts);
+  } else if (det) {
+    if (!blocks->lvl_cnt) return GS_ERR_INVALID_ARG;
+    int64_t n_stored = 0;
+    for (int l = 0; l < blocks->n_levels; ++l) n_stored += levels[l].n;
+    int64_t sb = (n_stored + 255) / 256;
+    const dim3 sg((unsigned)(sb < 8192 ? (sb < 1 ? 1 : sb) : 8192));
+    hipLaunchKernelGGL(preprocess_bwd_det_kernel, sg, dim3(256), 0, s, a, rec, grad2d, counts, n_stored);
   } else {
     hipLaunchKernelGGL(preprocess_bwd_kernel<false>, gbg, dim3(256), 0, s, a, rec, grad2d, counts);
   }

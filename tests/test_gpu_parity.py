@@ -747,6 +747,68 @@ def test_graph_captured_training_step_equals_eager():
     del graph
 
 
+def _level_grads(scene, frame, cams_dev, d, flags):
+    frame.tuning = gs.tuning_struct(frame.tuning.tile_w, frame.tuning.tile_h, frame.tuning.batch, flags)
+    frame.bwd_ws = None  # the deterministic workspace is larger
+    return _grads_for(scene, frame, cams_dev, d)
+
+
+@pytest.mark.parametrize("case", ["single_view", "lod_views", "shared_queue", "tile8x8", "tile32x16"])
+def test_deterministic_backward_is_bit_reproducible(case):
+    """GS_TUNE_DETERMINISTIC: two backward runs give bit-identical gradients,
+    equal to the atomic path to FP32 rounding; the single view also against
+    the oracle element by element."""
+    if case in ("single_view", "lod_views", "tile8x8", "tile32x16"):
+        bs = scaled_city(100_000, seed=44)
+        scene = render.DeviceScene.from_block_scene(bs)
+        scene.compute_bounds(4.0)
+        cams = synth.city_views(seed=44, n_xy=1, width=320, height=180)
+        if case != "lod_views":
+            cams = [cams[3]]
+        tile = {"tile8x8": (8, 8), "tile32x16": (32, 16)}.get(case, (16, 16))
+        base_flags = 0
+        frame = render.Frame(bs.n_blocks, len(cams), 320, 180, len(cams) * scene.max_records_per_view(), 1 << 20,
+                             gs.tuning_struct(tile[0], tile[1], 256, base_flags))
+        render.render_frame(scene, frame, gs.cameras_to_device(cams))
+    else:
+        bs = None
+        g = synth.box_gaussians(20_000, seed=45, extent=((-20, 20), (-20, 20), (0, 8)))
+        scene = render.DeviceScene.single(g)
+        cams = synth.orbit_views((0.0, 0.0), n_views=4, radius=30.0, height=25.0, width=160, h_px=96)
+        base_flags = gs.GS_TUNE_SHARED_SELECTION | gs.GS_TUNE_WORK_QUEUE
+        frame = render.Frame(1, len(cams), 160, 96, len(cams) * scene.n_finest, 1 << 20,
+                             gs.tuning_struct(16, 16, 256, base_flags))
+        render.render_frame(scene, frame, gs.cameras_to_device(cams), mode=gs.GS_LOD_ALL_FINEST, thresholds=())
+    cams_dev = gs.cameras_to_device(cams)
+    V, W, H = frame.V, frame.W, frame.H
+    assert frame.host_counts()["flags"] == 0
+    print("case:", case, V, "views", frame.host_counts(), flush=True)
+    d = torch.from_numpy(np.random.default_rng(46).normal(size=(V, 3, H, W)).astype(np.float32)).cuda()
+    det = base_flags | gs.GS_TUNE_DETERMINISTIC
+    a = _level_grads(scene, frame, cams_dev, d, det)
+    b = _level_grads(scene, frame, cams_dev, d, det)
+    ref = _level_grads(scene, frame, cams_dev, d, base_flags)
+    names = ("means", "scales", "quats", "opac", "sh")
+    for l in range(len(a)):
+        for k, name in enumerate(names):
+            assert np.array_equal(a[l][k].view(np.uint32), b[l][k].view(np.uint32)), (case, l, name)
+            if np.linalg.norm(ref[l][k]) > 0:
+                check_grad(name, a[l][k], ref[l][k], l2_tol=SUM_L2_TOL, elem_tol=SUM_ELEM_TOL,
+                           what="(%s, level %d: deterministic vs atomic)" % (case, l))
+            else:
+                assert not np.any(a[l][k])
+    if case == "single_view":
+        lo_ref, hi_ref = olod.scene_bounds(bs, 4.0)
+        level_ref, _ = olod.lod_select(lo_ref, hi_ref, bs.cells, (200.0, 500.0), cams, bs.lvl_cnt)
+        agg = olod.aggregate(bs, level_ref[0])
+        want = _scatter_agg(bs, level_ref[0], oracle_grads(agg, cams[0], d[0].cpu().numpy().astype(np.float64)))
+        for l in range(len(a)):
+            for k, name in enumerate(names):
+                if np.linalg.norm(want[l][name]) > 0:
+                    check_grad(name, a[l][k], want[l][name], mag=want[l]["abs:" + name], near=want[l]["near"] > 0,
+                               what="(deterministic, level %d)" % l)
+
+
 # ---------------------------------------------------------------------------
 # point-wise LoD baseline (Sec. 3.3.2 opening, Table 5)
 # ---------------------------------------------------------------------------
