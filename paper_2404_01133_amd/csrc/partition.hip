@@ -254,9 +254,10 @@ extern "C" gs_status gs_partition(const float* means, int64_t n, const double* x
     const bool last = p == passes - 1;
     uint32_t* kout = (p % 2 == 0) ? w.k1 : w.k0;
     uint32_t* vout = last ? perm : ((p % 2 == 0) ? w.v1 : w.v0);
-    hipLaunchKernelGGL(radix_pass_kernel, dim3(rgrid), dim3(kThreads), 0, s, kin, vin, kout, vout,
+    hipLaunchKernelGGL((radix_pass_kernel<kPassPlain>), dim3(rgrid), dim3(kThreads), 0, s, kin, vin, kout, vout,
                        (const int64_t*)w.counts, GS_COUNT_RECORDS, n, 8 * p, w.hist + p * kRadix,
-                       w.status + (int64_t)p * ntiles * kRadix, (int64_t)kRadix, w.words + 2 + p, w.counts);
+                       w.status + (int64_t)p * ntiles * kRadix, (int64_t)kRadix, w.words + 2 + p, w.counts,
+                       PairPass{});
     GS_LAUNCH_CHECK();
     kin = kout;
     vin = vout;

@@ -45,15 +45,76 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_wave
   return wave_base + inc - x;
 }
 
+// saturating u32 sum (values past 2^32 - 1 only ever mean "beyond every capacity")
+__device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
+  const uint32_t c = a + b;
+  return c < a ? 0xFFFFFFFFu : c;
+}
+__device__ __forceinline__ uint32_t sat_u32(uint64_t v) { return v > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)v; }
+
+// block-level exclusive scan of one u64 per thread (256 threads, 4 waves)
+__device__ __forceinline__ uint64_t block_excl_scan64(uint64_t x, uint64_t* s_wave64, uint64_t* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint64_t inc = x;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint64_t y = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += y;
+  }
+  if (lane == 63) s_wave64[wid] = inc;
+  __syncthreads();
+  uint64_t wave_base = 0, tot = 0;
+  for (int w = 0; w < kThreads / 64; ++w) {
+    const uint64_t v = s_wave64[w];
+    if (w < wid) wave_base += v;
+    tot += v;
+  }
+  *total = tot;
+  __syncthreads();
+  return wave_base + inc - x;
+}
+
+// Variants of a pass (template argument MODE):
+//   kPassPlain    sort (key, value) pairs
+//   kPassPairs    the most significant depth pass of the binning: besides the
+//                 sorted record ids it writes each record's first pair slot, the
+//                 exclusive prefix of tiles_touched in the sorted order
+//                 (saturating at 2^32 - 1).  Per (radix tile, digit) one 64-bit
+//                 look-back word carries both the record count (bits 32..61) and
+//                 the pair sum (bits 0..31, saturating).  whist holds `copies`
+//                 partial histograms of tiles_touched by this digit (u64).
+//   kPassCompact  the least significant depth pass: reads every selected record's
+//                 depth key, keeps those with tiles_touched > 0 (values = record
+//                 index, in index order) and writes the visible count.
+// hist_extra: `hist_copies` further partial copies of the digit histogram
+// (stride hist_stride) that the pass adds to `hist` itself.
+constexpr int kPassPlain = 0;
+constexpr int kPassPairs = 1;
+constexpr int kPassCompact = 2;
+struct PairPass {
+  const int32_t* tiles_touched;
+  const uint64_t* whist;
+  int copies;
+  uint64_t* status;  // [radix tiles][256]
+  uint32_t* pair_off;
+  int64_t pair_cap;
+  const uint32_t* hist_extra;
+  int hist_copies;
+  int64_t hist_stride;
+};
+constexpr uint64_t kPFlagAgg = 1ull << 62;
+constexpr uint64_t kPFlagInc = 2ull << 62;
+constexpr uint64_t kPFlagMask = 3ull << 62;
+
 // ---------------------------------------------------------------------------
 // one stable LSD pass over 8 bits; the digit histogram of the whole input was
 // accumulated by the kernel that produced the keys
 // ---------------------------------------------------------------------------
+template <int MODE = kPassPlain>
 __global__ void __launch_bounds__(kThreads) radix_pass_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, const int64_t* counts_in, int count_idx, int64_t cap, int shift,
     const uint32_t* __restrict__ hist, uint32_t* status, int64_t status_stride, uint32_t* tile_counter,
-    int64_t* counts) {
+    int64_t* counts, PairPass pp) {
   __shared__ uint32_t s_keys[kRadixTile];
   __shared__ uint32_t s_vals[kRadixTile];
   __shared__ uint32_t s_wave_hist[kThreads / 64][kRadix];
@@ -62,13 +123,53 @@ __global__ void __launch_bounds__(kThreads) radix_pass_kernel(
   __shared__ uint32_t s_wave[kThreads / 64];
   __shared__ uint32_t s_tile;
   __shared__ uint32_t s_goff[kRadix];
+  // kPassPairs only (sized 1 otherwise): tiles_touched, then its exclusive prefix, in LDS
+  // order; the first pair slot of each digit's run of this tile; the prefix at each run start
+  __shared__ uint32_t s_pfx[MODE == kPassPairs ? kRadixTile : 1];
+  __shared__ uint32_t s_pbase[MODE == kPassPairs ? kRadix : 1];
+  __shared__ uint32_t s_pfx_start[MODE == kPassPairs ? kRadix : 1];
+  __shared__ uint64_t s_wave64[MODE == kPassPairs ? kThreads / 64 : 1];
+  __shared__ uint32_t s_ptotal;
+  constexpr bool PAIRS = MODE == kPassPairs;
+  constexpr bool COMPACT = MODE == kPassCompact;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int64_t n = count_clamped(counts_in, count_idx, cap);
   const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
+  // this digit's count over the whole input: `hist` plus the partial copies
+  uint32_t hist_d = hist[threadIdx.x];
+  for (int c = 0; c < pp.hist_copies; ++c) hist_d += pp.hist_extra[c * pp.hist_stride + threadIdx.x];
+  if constexpr (COMPACT) {
+    // the visible count = the digit histogram's total (taken by the later passes)
+    if (blockIdx.x == 0) {
+      uint32_t tot;
+      block_excl_scan(hist_d, s_wave, &tot);
+      if (threadIdx.x == 0) counts[GS_COUNT_VISIBLE] = (int64_t)tot;
+    }
+  }
+  if constexpr (PAIRS) {
+    // the pair count M = sum of tiles_touched over the visible records, from the weighted histogram
+    if (blockIdx.x == 0) {
+      uint64_t w = 0;
+      for (int c = 0; c < pp.copies; ++c) w += pp.whist[c * kRadix + threadIdx.x];
+      uint64_t tot;
+      block_excl_scan64(w, s_wave64, &tot);
+      if (threadIdx.x == 0) {
+        counts[GS_COUNT_PAIRS] = (int64_t)tot;
+        if ((int64_t)tot > pp.pair_cap) raise_flag(counts, GS_FLAG_PAIRS);
+      }
+    }
+  }
   if ((int64_t)blockIdx.x >= ntiles) return;
   {
     uint32_t tot;
-    s_goff[threadIdx.x] = block_excl_scan(hist[threadIdx.x], s_wave, &tot);  // global digit offsets
+    s_goff[threadIdx.x] = block_excl_scan(hist_d, s_wave, &tot);  // global digit offsets
+  }
+  uint32_t pair_goff = 0;  // PAIRS: pairs of all records with a smaller digit (saturating)
+  if constexpr (PAIRS) {
+    uint64_t w = 0;
+    for (int c = 0; c < pp.copies; ++c) w += pp.whist[c * kRadix + threadIdx.x];
+    uint64_t tot;
+    pair_goff = sat_u32(block_excl_scan64(w, s_wave64, &tot));
   }
   for (;;) {
     if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
@@ -81,14 +182,28 @@ __global__ void __launch_bounds__(kThreads) radix_pass_kernel(
     // wave w owns the contiguous slice [w*64*kRadixItems, (w+1)*64*kRadixItems) of the tile;
     // item k of lane l is element k*64 + l of that slice (coalesced loads)
     uint32_t key[kRadixItems], val[kRadixItems], rank[kRadixItems];
+    uint32_t ttv[PAIRS ? kRadixItems : 1];
     bool valid[kRadixItems];
     const int slice = wid * 64 * kRadixItems;
 #pragma unroll
     for (int k = 0; k < kRadixItems; ++k) {
       const int li = slice + k * 64 + lane;
-      valid[k] = li < tile_n;
-      key[k] = valid[k] ? keys_in[tile_base + li] : 0u;
-      val[k] = valid[k] ? vals_in[tile_base + li] : 0u;
+      if constexpr (COMPACT) {
+        valid[k] = li < tile_n && pp.tiles_touched[tile_base + li] > 0;
+        key[k] = valid[k] ? keys_in[tile_base + li] : 0u;
+        val[k] = (uint32_t)(tile_base + li);
+      } else {
+        valid[k] = li < tile_n;
+        key[k] = valid[k] ? keys_in[tile_base + li] : 0u;
+        val[k] = valid[k] ? vals_in[tile_base + li] : 0u;
+      }
+    }
+    if constexpr (PAIRS) {
+#pragma unroll
+      for (int k = 0; k < kRadixItems; ++k) {
+        const int32_t t = valid[k] ? pp.tiles_touched[val[k]] : 0;
+        ttv[k] = t > 0 ? (uint32_t)t : 0u;
+      }
     }
     // stable rank inside the wave: items in order k, lanes in order within an item
 #pragma unroll
@@ -122,8 +237,87 @@ __global__ void __launch_bounds__(kThreads) radix_pass_kernel(
     uint32_t tile_total;
     const uint32_t tile_excl = block_excl_scan(tile_cnt, s_wave, &tile_total);
     s_tile_excl[d] = tile_excl;
-    // decoupled look-back for digit d
     uint32_t excl = 0;
+    if constexpr (PAIRS) {
+      // local scatter of tiles_touched into the tile's digit order, then its
+      // exclusive prefix there (16 consecutive positions per thread)
+      __syncthreads();  // s_tile_excl of every digit
+#pragma unroll
+      for (int k = 0; k < kRadixItems; ++k) {
+        if (valid[k]) {
+          const uint32_t dd = (key[k] >> shift) & 255u;
+          s_pfx[s_tile_excl[dd] + s_wave_hist[wid][dd] + rank[k]] = ttv[k];
+        }
+      }
+      __syncthreads();
+      uint32_t loc[kRadixItems];
+      uint64_t mine = 0;
+#pragma unroll
+      for (int k = 0; k < kRadixItems; ++k) {
+        const int i = threadIdx.x * kRadixItems + k;
+        loc[k] = i < (int)tile_total ? s_pfx[i] : 0u;
+        mine += loc[k];
+      }
+      uint64_t tsum;
+      uint64_t run64 = block_excl_scan64(mine, s_wave64, &tsum);
+#pragma unroll
+      for (int k = 0; k < kRadixItems; ++k) {
+        const int i = threadIdx.x * kRadixItems + k;
+        if (i < (int)tile_total) s_pfx[i] = sat_u32(run64);
+        run64 += loc[k];
+      }
+      if (threadIdx.x == 0) s_ptotal = sat_u32(tsum);
+      __syncthreads();
+      // pairs of this tile's digit-d run; one 64-bit look-back word per digit
+      // carries the record count (bits 32..61) and the pair sum (bits 0..31)
+      const uint32_t rs = tile_excl, re = tile_excl + tile_cnt;
+      const uint32_t ps = rs < tile_total ? s_pfx[rs] : s_ptotal;
+      const uint32_t pe = re < tile_total ? s_pfx[re] : s_ptotal;
+      const uint32_t tpairs = pe - ps;
+      s_pfx_start[d] = ps;
+      uint32_t excl_pairs = 0;
+      uint64_t* st = pp.status + t * kRadix + d;
+      if (t == 0) {
+        store_agent(st, kPFlagInc | ((uint64_t)tile_cnt << 32) | tpairs);
+      } else {
+        store_agent(st, kPFlagAgg | ((uint64_t)tile_cnt << 32) | tpairs);
+        int64_t k = t - 1;
+        int64_t spins = 0;
+        for (;;) {
+          uint64_t sv[kLookWindow];
+#pragma unroll
+          for (int i = 0; i < kLookWindow; ++i)
+            sv[i] = (k - i >= 0) ? load_agent(pp.status + (k - i) * kRadix + d) : kPFlagInc;
+          int used = 0;
+          bool done = false, stalled = false;
+#pragma unroll
+          for (int i = 0; i < kLookWindow; ++i) {
+            if (done || stalled) continue;
+            const uint64_t flag = sv[i] & kPFlagMask;
+            if (flag == 0) {
+              stalled = true;
+              continue;
+            }
+            excl += (uint32_t)(sv[i] >> 32) & kValMask;
+            excl_pairs = sat_add(excl_pairs, (uint32_t)sv[i]);
+            ++used;
+            done = flag == kPFlagInc;
+          }
+          if (done) break;
+          k -= used;
+          if (stalled) {
+            if (++spins > kSpinLimit) {
+              raise_flag(counts, GS_FLAG_WAIT);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+          }
+        }
+        store_agent(st, kPFlagInc | ((uint64_t)(excl + tile_cnt) << 32) | sat_add(excl_pairs, tpairs));
+      }
+      s_pbase[d] = sat_add(pair_goff, excl_pairs);
+    } else {
+    // decoupled look-back for digit d
     uint32_t* st = status + t * status_stride + d;
     if (t == 0) {
       store_agent(st, kFlagInc | tile_cnt);
@@ -165,6 +359,7 @@ __global__ void __launch_bounds__(kThreads) radix_pass_kernel(
       }
       store_agent(st, kFlagInc | (excl + tile_cnt));
     }
+    }
     s_digit_base[d] = s_goff[d] + excl;
     __syncthreads();
     // local scatter by digit, then coalesced write-out
@@ -178,12 +373,17 @@ __global__ void __launch_bounds__(kThreads) radix_pass_kernel(
       }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < tile_n; i += kThreads) {
+    // (valid items only: tile_total = tile_n except in the compacting pass)
+    for (int i = threadIdx.x; i < (int)tile_total; i += kThreads) {
       const uint32_t kk = s_keys[i];
       const uint32_t dd = (kk >> shift) & 255u;
       const uint32_t out = s_digit_base[dd] + ((uint32_t)i - s_tile_excl[dd]);
-      keys_out[out] = kk;
       vals_out[out] = s_vals[i];
+      if constexpr (PAIRS) {
+        pp.pair_off[out] = sat_add(s_pbase[dd], s_pfx[i] - s_pfx_start[dd]);
+      } else {
+        keys_out[out] = kk;
+      }
     }
     __syncthreads();
   }

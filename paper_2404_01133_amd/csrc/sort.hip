@@ -4,16 +4,19 @@
 // least-significant-digit radix sort.  Its low (depth) digits do not depend on
 // the tile, so those passes run once per visible record, before the pairs are
 // duplicated; only the tile digits run over the pairs.  Stages:
-//   1. compact   visible records -> (depth bits, record id), record order kept
-//                (per-tile counts, one-work-group scan, write: three launches)
-//   2. 4 passes  stable radix sort by the 32-bit depth key (ties keep record order)
-//   3. scan      pair offsets = exclusive prefix of tiles_touched in depth order
-//   4. emit      one (view*tiles + tile, record) pair per tile of each footprint
-//   5. passes    stable radix sort by tile id (ceil(bits / 8) passes)
-//   6. ranges    [start, end) of every tile
+//   1. hist      digit histograms of the visible records' depth keys, and the
+//                pairs (tiles_touched) per top digit
+//   2. 4 passes  stable radix sort by the 32-bit depth key (ties keep record order);
+//                the first one reads every selected record and keeps the visible
+//                ones (compaction), the last one also writes the pair offsets, the
+//                exclusive prefix of tiles_touched in depth order (its look-back
+//                carries both sums)
+//   3. emit      one (view*tiles + tile, record) pair per tile of each footprint
+//   4. passes    stable radix sort by tile id (ceil(bits / 8) passes)
+//   5. ranges    [start, end) of every tile
 // The result equals a sort by (tile, depth, record id).
 //
-// The pair-offset scan and the radix passes are single-pass with decoupled
+// The radix passes are single-pass with decoupled
 // look-back: work-groups take tile ids from an atomic counter in launch order,
 // publish their local aggregate, then walk back over predecessors' published
 // values.  A work-group
@@ -29,10 +32,6 @@ namespace gs {
 namespace {
 
 constexpr int kMaxPasses = 8;
-// tiles of the two record scans (compaction, pair offsets): 2048 records;
-// measured, 4x larger tiles were slower (less parallel work)
-constexpr int kScanItems = kItems;
-constexpr int kScanTile = kThreads * kScanItems;
 constexpr int kPersistentBlocks = 1024;
 constexpr int kBigFootprint = 16;  // records touching more tiles are emitted cooperatively
 // emit_kernel's work-groups all finish at about the same time and each adds its
@@ -49,211 +48,72 @@ constexpr int64_t kTileHistWords = kMaxPasses * kRadix;  // one copy
 // words of the pair-offset scan and the depth passes are cleared by
 // compact_write_kernel, sized by the visible count
 // ---------------------------------------------------------------------------
-__global__ void clear_front_kernel(uint32_t* __restrict__ fixed, int64_t fixed_words) {
+// zero fill of the small fixed state (counters, histograms) and of the look-back
+// words of the four depth passes, sized by the selected records (the compacting
+// first pass runs over all of them; the later ones over the visible ones):
+// u32 [radix tiles][4][256] and the last pass's u64 [radix tiles][256]
+__global__ void clear_front_kernel(uint32_t* __restrict__ fixed, int64_t fixed_words, const int64_t* counts,
+                                   int64_t cap, uint32_t* __restrict__ dstatus, uint64_t* __restrict__ pstatus) {
+  const int64_t n = count_clamped(counts, GS_COUNT_RECORDS, cap);
+  const int64_t rt = (n + kRadixTile - 1) / kRadixTile;
+  const int64_t dwords = rt * 4 * kRadix, pwords = rt * kRadix;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < fixed_words; i += stride) fixed[i] = 0u;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < fixed_words + dwords + pwords; i += stride) {
+    if (i < fixed_words) fixed[i] = 0u;
+    else if (i < fixed_words + dwords) dstatus[i - fixed_words] = 0u;
+    else pstatus[i - fixed_words - dwords] = 0ull;
+  }
 }
 
 // ---------------------------------------------------------------------------
-// 1. compaction of visible records, in three launches (count, scan, write).
-//    Each scan tile's work is small and all tiles are in flight at once, so a
-//    single pass with decoupled look-back spends most of its time in look-back
-//    rounds and in the same-address tile counter; here tile t's offset is the
-//    prefix of the tile counts, computed by one work-group.
+// 1. histograms of the visible records' depth digits (all four passes) and of
+//    their pairs by the top digit; the work-groups finish together, so their
+//    device atomics are spread over kDepthHistCopies partial copies (copy 0 is
+//    the histogram itself; each pass adds the others to its digit)
 // ---------------------------------------------------------------------------
-constexpr int kDepthHistCopies = 8;  // partial depth-digit histograms of the count launch (folded by the scan)
+constexpr int kDepthHistCopies = 8;
 constexpr int64_t kDepthHistWords = 4 * kRadix;
 
-__device__ __forceinline__ int64_t scan_tiles_of(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
-
-// per tile: number of visible records; depth-digit histograms of their keys
-__global__ void __launch_bounds__(kThreads) compact_count_kernel(const int32_t* __restrict__ tiles_touched,
-                                                                 const uint32_t* __restrict__ depth_keys, int64_t cap,
-                                                                 const int64_t* counts,
-                                                                 uint32_t* __restrict__ tile_count,
-                                                                 uint32_t* __restrict__ hist,
-                                                                 uint32_t* __restrict__ hist_extra) {
-  __shared__ uint32_t s_wave[kThreads / 64];
+__global__ void __launch_bounds__(kThreads) depth_hist_kernel(const int32_t* __restrict__ tiles_touched,
+                                                              const uint32_t* __restrict__ depth_keys, int64_t cap,
+                                                              const int64_t* counts, uint32_t* __restrict__ hist,
+                                                              uint32_t* __restrict__ hist_extra,
+                                                              uint64_t* __restrict__ whist) {
   __shared__ uint32_t s_hist[4][kRadix];
+  __shared__ uint64_t s_whist[kRadix];  // tiles_touched summed by the top depth digit
   const int64_t n = count_clamped(counts, GS_COUNT_RECORDS, cap);
-  const int64_t ntiles = scan_tiles_of(n);
-  if ((int64_t)blockIdx.x >= ntiles) return;
+  const int64_t per_block = (int64_t)kThreads * kItems;
+  const int64_t nblocks = (n + per_block - 1) / per_block;
+  if ((int64_t)blockIdx.x >= nblocks) return;
   for (int i = threadIdx.x; i < 4 * kRadix; i += kThreads) (&s_hist[0][0])[i] = 0u;
+  s_whist[threadIdx.x] = 0ull;
   __syncthreads();
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int64_t base = t * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    uint32_t mine = 0;
+  for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-      const int64_t idx = base + k;
-      if (idx < n && tiles_touched[idx] > 0) {
-        ++mine;
+    for (int k = 0; k < kItems; ++k) {
+      const int64_t idx = b * per_block + (int64_t)k * kThreads + threadIdx.x;  // coalesced
+      const int32_t tt = idx < n ? tiles_touched[idx] : 0;
+      if (tt > 0) {
         const uint32_t key = depth_keys[idx];
 #pragma unroll
         for (int p = 0; p < 4; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
+        atomicAdd((unsigned long long*)&s_whist[key >> 24], (unsigned long long)tt);
       }
     }
-    uint32_t total;
-    block_excl_scan(mine, s_wave, &total);
-    if (threadIdx.x == 0) tile_count[t] = total;
   }
   __syncthreads();
-  // the work-groups finish together: spread their histogram atomics over the copies
   const int copy = (int)(blockIdx.x % kDepthHistCopies);
   uint32_t* h = copy == 0 ? hist : hist_extra + (int64_t)(copy - 1) * kDepthHistWords;
   for (int i = threadIdx.x; i < 4 * kRadix; i += kThreads) {
     const uint32_t c = (&s_hist[0][0])[i];
     if (c) atomicAdd(&h[i], c);
   }
-}
-
-// one work-group: exclusive prefix of the tile counts, the visible count, and
-// the partial depth histograms folded into the one the radix passes read
-__global__ void __launch_bounds__(kThreads) compact_scan_kernel(int64_t cap, int64_t* counts,
-                                                                const uint32_t* __restrict__ tile_count,
-                                                                uint32_t* __restrict__ tile_off,
-                                                                uint32_t* __restrict__ hist,
-                                                                const uint32_t* __restrict__ hist_extra) {
-  constexpr int kPer = 4;  // consecutive tiles per thread and round
-  __shared__ uint32_t s_wave[kThreads / 64];
-  const int64_t n = count_clamped(counts, GS_COUNT_RECORDS, cap);
-  const int64_t ntiles = scan_tiles_of(n);
-  uint32_t carry = 0;
-  for (int64_t b = 0; b < ntiles; b += (int64_t)kThreads * kPer) {
-    const int64_t t0 = b + (int64_t)threadIdx.x * kPer;
-    uint32_t c[kPer], mine = 0;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      c[k] = (t0 + k < ntiles) ? tile_count[t0 + k] : 0u;
-      mine += c[k];
-    }
-    uint32_t tot;
-    uint32_t off = carry + block_excl_scan(mine, s_wave, &tot);
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      if (t0 + k < ntiles) tile_off[t0 + k] = off;
-      off += c[k];
-    }
-    carry += tot;
-  }
-  if (threadIdx.x == 0) counts[GS_COUNT_VISIBLE] = (int64_t)carry;
-  // the count launch has finished (same stream): its partial histograms are final
-  for (int i = threadIdx.x; i < kDepthHistWords; i += kThreads) {
-    uint32_t part[kDepthHistCopies - 1];
-#pragma unroll
-    for (int k = 0; k < kDepthHistCopies - 1; ++k) part[k] = hist_extra[k * kDepthHistWords + i];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int k = 0; k < kDepthHistCopies - 1; ++k) sum += part[k];
-    hist[i] += sum;
-  }
-}
-
-// per tile: visible records' (depth key, record index) at the tile's offset, in index order
-__global__ void __launch_bounds__(kThreads) compact_write_kernel(const int32_t* __restrict__ tiles_touched,
-                                                                 const uint32_t* __restrict__ depth_keys, int64_t cap,
-                                                                 const int64_t* counts,
-                                                                 const uint32_t* __restrict__ tile_off,
-                                                                 uint32_t* __restrict__ keys_out,
-                                                                 uint32_t* __restrict__ vals_out,
-                                                                 uint32_t* __restrict__ poff_status,
-                                                                 uint32_t* __restrict__ dstatus) {
-  __shared__ uint32_t s_wave[kThreads / 64];
-  const int64_t n = count_clamped(counts, GS_COUNT_RECORDS, cap);
-  const int64_t ntiles = scan_tiles_of(n);
-  {
-    // look-back words of the stages that run over the visible records: the
-    // pair-offset scan (one u64 per scan tile, + 1) and the four depth passes
-    const int64_t nv = count_clamped(counts, GS_COUNT_VISIBLE, cap);
-    const int64_t pwords = 2 * (scan_tiles_of(nv) + 1);
-    const int64_t dwords = ((nv + kRadixTile - 1) / kRadixTile) * 4 * kRadix;  // [radix tiles][4 passes][256]
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < pwords + dwords; i += stride) {
-      if (i < pwords) poff_status[i] = 0u;
-      else dstatus[i - pwords] = 0u;
-    }
-  }
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int64_t base = t * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    const uint32_t tbase = tile_off[t];
-    bool f[kScanItems];
-    uint32_t mine = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-      const int64_t idx = base + k;
-      f[k] = idx < n && tiles_touched[idx] > 0;
-      mine += f[k] ? 1u : 0u;
-    }
-    uint32_t total;
-    uint32_t pos = tbase + block_excl_scan(mine, s_wave, &total);
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-      if (f[k]) {
-        const int64_t idx = base + k;
-        keys_out[pos] = depth_keys[idx];
-        vals_out[pos] = (uint32_t)idx;
-        ++pos;
-      }
-    }
-  }
+  const uint64_t wv = s_whist[threadIdx.x];
+  if (wv) atomicAdd((unsigned long long*)&whist[copy * kRadix + threadIdx.x], (unsigned long long)wv);
 }
 
 // ---------------------------------------------------------------------------
-// 3. pair offsets: exclusive prefix of tiles_touched in depth order
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) pair_offsets_kernel(const uint32_t* __restrict__ sorted_records,
-                                                                const int32_t* __restrict__ tiles_touched,
-                                                                int64_t cap, uint32_t* __restrict__ pair_off,
-                                                                uint64_t* status, uint32_t* tile_counter,
-                                                                int64_t* counts, int64_t pair_cap) {
-  __shared__ uint32_t s_wave[kThreads / 64];
-  __shared__ uint32_t s_tile;
-  __shared__ uint64_t s_excl;
-  const int64_t n = count_clamped(counts, GS_COUNT_VISIBLE, cap);
-  const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
-  if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0) counts[GS_COUNT_PAIRS] = 0;
-  if ((int64_t)blockIdx.x >= ntiles) return;
-  for (;;) {
-    if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
-    __syncthreads();
-    const int64_t t = s_tile;
-    if (t >= ntiles) break;
-    const int64_t base = t * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    uint32_t v[kScanItems];
-    uint32_t mine = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-      const int64_t idx = base + k;
-      v[k] = idx < n ? (uint32_t)tiles_touched[sorted_records[idx]] : 0u;
-      mine += v[k];
-    }
-    uint32_t total;
-    const uint32_t excl_thread = block_excl_scan(mine, s_wave, &total);
-    if (threadIdx.x < 64) {
-      const uint64_t ex = lookback64_wave(status, t, total, counts);
-      if (threadIdx.x == 0) {
-        s_excl = ex;
-        if (t == ntiles - 1) {
-          const int64_t m = (int64_t)(ex + total);
-          counts[GS_COUNT_PAIRS] = m;
-          if (m > pair_cap) raise_flag(counts, GS_FLAG_PAIRS);
-        }
-      }
-    }
-    __syncthreads();
-    uint64_t pos = s_excl + excl_thread;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-      const int64_t idx = base + k;
-      if (idx < n) pair_off[idx] = (uint32_t)(pos < 0xFFFFFFFFull ? pos : 0xFFFFFFFFull);
-      pos += v[k];
-    }
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
-// 4. pair emission
+// 3. pair emission
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kThreads) emit_kernel(const Record* __restrict__ records,
                                                         const uint32_t* __restrict__ sorted_records,
@@ -372,7 +232,7 @@ __global__ void __launch_bounds__(kThreads) emit_big_kernel(const Record* __rest
 }
 
 // ---------------------------------------------------------------------------
-// 6. tile ranges
+// 5. tile ranges
 // ---------------------------------------------------------------------------
 __global__ void ranges_kernel(const uint32_t* __restrict__ tiles, const int64_t* counts, int64_t pair_cap,
                               int64_t n_tile_ids, uint32_t* __restrict__ ranges) {
@@ -387,7 +247,7 @@ __global__ void ranges_kernel(const uint32_t* __restrict__ tiles, const int64_t*
 }
 
 // ---------------------------------------------------------------------------
-// 7. work queue for the persistent tile kernels: tiles ordered by decreasing
+// 6. work queue for the persistent tile kernels: tiles ordered by decreasing
 //    list length, bucketed by floor(log2(length)) (empty tiles last); the order
 //    inside a bucket is irrelevant because tiles are independent
 // ---------------------------------------------------------------------------
@@ -455,7 +315,10 @@ __global__ void queue_scatter_kernel(const uint32_t* __restrict__ ranges, int64_
 constexpr int64_t kQueueWords = 2 * 40;
 constexpr int64_t kTileExtraAt = 64 + 2 * kMaxPasses * kRadix + kQueueWords;
 constexpr int64_t kDepthExtraAt = kTileExtraAt + (kTileHistCopies - 1) * kTileHistWords;
-constexpr int64_t kFixedWords = kDepthExtraAt + (kDepthHistCopies - 1) * kDepthHistWords;
+// partial histograms of tiles_touched by the top depth digit, u64 [kDepthHistCopies][256] (the last
+// depth pass sums the copies)
+constexpr int64_t kWhistAt = ((kDepthExtraAt + (kDepthHistCopies - 1) * kDepthHistWords) + 1) & ~(int64_t)1;
+constexpr int64_t kFixedWords = kWhistAt + 2 * kDepthHistCopies * kRadix;
 
 struct SortWs {
   uint32_t* dkeys_a;      // [rc]
@@ -467,8 +330,8 @@ struct SortWs {
   uint32_t* ptiles_alt;   // [pc]
   uint32_t* precs_alt;    // [pc]
   uint32_t* fixed;        // counters [64], hist [2][kMaxPasses][256], queue words, partial tile hists
-  uint64_t* scan_status;  // [2][rtiles]: compaction tile counts and offsets (u32), pair-offset look-back
-  uint32_t* dstatus;      // [radix tiles][4][256] (tile-major so a prefix covers every pass)
+  uint32_t* dstatus;      // [radix tiles][4][256] (tile-major so a prefix covers every pass; slot 3 unused)
+  uint64_t* p3status;     // [radix tiles][256]: last depth pass, record count and pair sum per word
   uint32_t* pstatus;      // [ptiles][kMaxPasses][256]
   size_t bytes;
 };
@@ -483,7 +346,6 @@ SortWs sort_ws_layout(char* base, int64_t rc, int64_t pc) {
     off = align_up(off + bytes);
     return p;
   };
-  const int64_t rtiles = (rc + kTile - 1) / kTile + 1;            // scan tiles
   const int64_t drtiles = (rc + kRadixTile - 1) / kRadixTile + 1;  // radix tiles over records
   const int64_t ptiles = (pc + kRadixTile - 1) / kRadixTile + 1;   // radix tiles over pairs
   w.dkeys_a = (uint32_t*)take(4 * (size_t)rc);
@@ -495,9 +357,8 @@ SortWs sort_ws_layout(char* base, int64_t rc, int64_t pc) {
   w.ptiles_alt = (uint32_t*)take(4 * (size_t)pc);
   w.precs_alt = (uint32_t*)take(4 * (size_t)pc);
   w.fixed = (uint32_t*)take(4 * (size_t)kFixedWords);
-  // the two scan status arrays are adjacent: [rtiles] then [rtiles]
-  w.scan_status = (uint64_t*)take(8 * 2 * (size_t)rtiles);
   w.dstatus = (uint32_t*)take(4 * 4 * (size_t)drtiles * kRadix);
+  w.p3status = (uint64_t*)take(8 * (size_t)drtiles * kRadix);
   w.pstatus = (uint32_t*)take(4 * (size_t)kMaxPasses * (size_t)ptiles * kRadix);
   w.bytes = off;
   return w;
@@ -539,15 +400,10 @@ extern "C" gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys
   const int tbits = tile_bits(n_tile_ids);
   const int tpasses = tbits == 0 ? 0 : (tbits + 7) / 8;
   hipStream_t s = (hipStream_t)stream;
-  const int64_t rtiles = (record_capacity + kTile - 1) / kTile + 1;
   const dim3 blk(kThreads);
   auto grid_for = [](int64_t items) {
     int64_t g = (items + kThreads - 1) / kThreads;
     return dim3((unsigned)(g < 1 ? 1 : (g > 2048 ? 2048 : g)));
-  };
-  auto persistent = [](int64_t cap) {
-    int64_t g = (cap + kTile - 1) / kTile;
-    return dim3((unsigned)(g < 1 ? 1 : (g > kPersistentBlocks ? kPersistentBlocks : g)));
   };
   auto persistent_radix = [](int64_t cap) {
     int64_t g = (cap + kRadixTile - 1) / kRadixTile;
@@ -556,37 +412,43 @@ extern "C" gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys
   uint32_t* counters = w.fixed;
   uint32_t* dhist = w.fixed + 64;
   uint32_t* thist = w.fixed + 64 + kMaxPasses * kRadix;
-  // 0. zero the counters and histograms
-  hipLaunchKernelGGL(clear_front_kernel, grid_for(kFixedWords), blk, 0, s, w.fixed, kFixedWords);
-  GS_LAUNCH_CHECK();
-  // 1. compaction (+ histograms of the four depth digits)
+  uint64_t* whist = (uint64_t*)(w.fixed + kWhistAt);
+  uint32_t* dhist_extra = w.fixed + kDepthExtraAt;
+  // 0. zero the counters, histograms and the depth passes' look-back words
   {
-    uint32_t* tile_count = (uint32_t*)w.scan_status;  // [rtiles], then tile_off [rtiles]
-    uint32_t* tile_off = tile_count + rtiles;
-    uint32_t* dhist_extra = w.fixed + kDepthExtraAt;
-    const dim3 cgrid = grid_for((int64_t)kThreads * ((record_capacity + kScanTile - 1) / kScanTile));
-    hipLaunchKernelGGL(compact_count_kernel, cgrid, blk, 0, s, tiles_touched, depth_keys, record_capacity, counts,
-                       tile_count, dhist, dhist_extra);
-    hipLaunchKernelGGL(compact_scan_kernel, dim3(1), blk, 0, s, record_capacity, counts, tile_count, tile_off, dhist,
-                       dhist_extra);
-    hipLaunchKernelGGL(compact_write_kernel, cgrid, blk, 0, s, tiles_touched, depth_keys, record_capacity, counts,
-                       tile_off, w.dkeys_a, w.dvals_a, (uint32_t*)(w.scan_status + rtiles), w.dstatus);
+    const int64_t drt = (record_capacity + kRadixTile - 1) / kRadixTile;
+    hipLaunchKernelGGL(clear_front_kernel, grid_for(kFixedWords + drt * 5 * kRadix), blk, 0, s, w.fixed,
+                       kFixedWords, counts, record_capacity, w.dstatus, w.p3status);
   }
   GS_LAUNCH_CHECK();
-  // 2. depth sort, 4 passes of 8 bits: a -> b -> a -> b -> a
-  for (int p = 0; p < 4; ++p) {
-    const bool even = (p % 2) == 0;
-    hipLaunchKernelGGL(radix_pass_kernel, persistent_radix(record_capacity), blk, 0, s, even ? w.dkeys_a : w.dkeys_b,
-                       even ? w.dvals_a : w.dvals_b, even ? w.dkeys_b : w.dkeys_a, even ? w.dvals_b : w.dvals_a,
-                       counts, GS_COUNT_VISIBLE, record_capacity, 8 * p, dhist + p * kRadix, w.dstatus + p * kRadix,
-                       (int64_t)4 * kRadix, counters + 1 + p, counts);
-    GS_LAUNCH_CHECK();
-  }
-  // 3. pair offsets in depth order
-  hipLaunchKernelGGL(pair_offsets_kernel, persistent(record_capacity), blk, 0, s, w.dvals_a, tiles_touched,
-                     record_capacity, w.pair_off, w.scan_status + rtiles, counters + 8, counts, pair_capacity);
+  // 1. histograms of the four depth digits and of the pairs by the top digit
+  hipLaunchKernelGGL(depth_hist_kernel, grid_for((record_capacity + kItems - 1) / kItems), blk, 0, s, tiles_touched,
+                     depth_keys, record_capacity, counts, dhist, dhist_extra, whist);
   GS_LAUNCH_CHECK();
-  // 4. emission (+ tile-digit histograms, + zeroing of the tile-pass state and ranges), into the
+  // 2. depth sort, 4 passes of 8 bits: selected records -> b -> a -> b -> a.  The first pass keeps
+  //    the visible records (index order within a digit) and writes counts[GS_COUNT_VISIBLE]; the
+  //    last also writes the pair offsets (exclusive prefix of tiles_touched in depth order) and
+  //    counts[GS_COUNT_PAIRS].  Each pass adds the partial copies of its digit histogram.
+  auto extra = [&](int p, const uint64_t* wh, uint64_t* pst, uint32_t* poff) {
+    return PairPass{tiles_touched, wh, kDepthHistCopies, pst, poff, pair_capacity, dhist_extra + p * kRadix,
+                    kDepthHistCopies - 1, kDepthHistWords};
+  };
+  hipLaunchKernelGGL((radix_pass_kernel<kPassCompact>), persistent_radix(record_capacity), blk, 0, s, depth_keys,
+                     nullptr, w.dkeys_b, w.dvals_b, counts, GS_COUNT_RECORDS, record_capacity, 0, dhist,
+                     w.dstatus, (int64_t)4 * kRadix, counters + 1, counts, extra(0, nullptr, nullptr, nullptr));
+  hipLaunchKernelGGL((radix_pass_kernel<kPassPlain>), persistent_radix(record_capacity), blk, 0, s, w.dkeys_b,
+                     w.dvals_b, w.dkeys_a, w.dvals_a, counts, GS_COUNT_VISIBLE, record_capacity, 8, dhist + kRadix,
+                     w.dstatus + kRadix, (int64_t)4 * kRadix, counters + 2, counts, extra(1, nullptr, nullptr, nullptr));
+  hipLaunchKernelGGL((radix_pass_kernel<kPassPlain>), persistent_radix(record_capacity), blk, 0, s, w.dkeys_a,
+                     w.dvals_a, w.dkeys_b, w.dvals_b, counts, GS_COUNT_VISIBLE, record_capacity, 16,
+                     dhist + 2 * kRadix, w.dstatus + 2 * kRadix, (int64_t)4 * kRadix, counters + 3, counts,
+                     extra(2, nullptr, nullptr, nullptr));
+  hipLaunchKernelGGL((radix_pass_kernel<kPassPairs>), persistent_radix(record_capacity), blk, 0, s, w.dkeys_b,
+                     w.dvals_b, w.dkeys_a, w.dvals_a, counts, GS_COUNT_VISIBLE, record_capacity, 24,
+                     dhist + 3 * kRadix, nullptr, (int64_t)0, counters + 4, counts,
+                     extra(3, whist, w.p3status, w.pair_off));
+  GS_LAUNCH_CHECK();
+  // 3. emission (+ tile-digit histograms, + zeroing of the tile-pass state and ranges), into the
   //    buffer that the last tile pass will read last
   uint32_t* em_tiles = (tpasses % 2 == 0) ? pair_tiles : w.ptiles_alt;
   uint32_t* em_recs = (tpasses % 2 == 0) ? pair_records : w.precs_alt;
@@ -599,24 +461,24 @@ extern "C" gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys
                      big_count, pair_capacity, tw, th, tx_n, (int)tiles_per_view, em_tiles, em_recs, tpasses, thist,
                      thist_extra);
   GS_LAUNCH_CHECK();
-  // 5. tile passes
+  // 4. tile passes
   uint32_t* kin = em_tiles;
   uint32_t* vin = em_recs;
   for (int p = 0; p < tpasses; ++p) {
     uint32_t* kout = (kin == pair_tiles) ? w.ptiles_alt : pair_tiles;
     uint32_t* vout = (vin == pair_records) ? w.precs_alt : pair_records;
-    hipLaunchKernelGGL(radix_pass_kernel, persistent_radix(pair_capacity), blk, 0, s, kin, vin, kout, vout, counts,
-                       GS_COUNT_PAIRS, pair_capacity, 8 * p, thist + p * kRadix, w.pstatus + p * kRadix,
-                       (int64_t)tpasses * kRadix, counters + 16 + p, counts);
+    hipLaunchKernelGGL((radix_pass_kernel<kPassPlain>), persistent_radix(pair_capacity), blk, 0, s, kin, vin, kout, vout,
+                       counts, GS_COUNT_PAIRS, pair_capacity, 8 * p, thist + p * kRadix, w.pstatus + p * kRadix,
+                       (int64_t)tpasses * kRadix, counters + 16 + p, counts, PairPass{});
     GS_LAUNCH_CHECK();
     kin = kout;
     vin = vout;
   }
-  // 6. ranges
+  // 5. ranges
   hipLaunchKernelGGL(ranges_kernel, dim3(2048), blk, 0, s, pair_tiles, counts, pair_capacity, n_tile_ids,
                      tile_ranges);
   GS_LAUNCH_CHECK();
-  // 7. work queue
+  // 6. work queue
   if ((tuning->flags & GS_TUNE_WORK_QUEUE) && tile_queue) {
     uint32_t* qhist = w.fixed + 64 + 2 * kMaxPasses * kRadix;
     uint32_t* qcur = qhist + 40;
