@@ -52,7 +52,8 @@ def lib():
         L.orc_render_tiled.restype = i32
         L.orc_pairs.argtypes = [i64, P, P, P, P, P, i32, P, P, i32, i32, i64, P, P]
         L.orc_pairs.restype = i64
-        L.orc_render_bwd.argtypes = [i64, P, P, P, P, P, i32, P, P, P, P, P, P, P, P, P, P, ctypes.c_double, P, P]
+        L.orc_render_bwd.argtypes = [i64, P, P, P, P, P, i32, P, P, P, P, P, P, P, P, P, P, ctypes.c_double, P, P,
+                                     ctypes.c_double]
         L.orc_render_bwd.restype = i32
         _lib = L
     return _lib
@@ -172,17 +173,20 @@ def tile_ranges(tile_ids, n_tiles):
     return np.stack([starts, ends], axis=1).astype(np.uint32)
 
 
-def render_bwd(g, cam, dimg, sh_degree=3, bg=(0.0, 0.0, 0.0), near_band=None, magnitudes=False):
+def render_bwd(g, cam, dimg, sh_degree=3, bg=(0.0, 0.0, 0.0), near_band=None, magnitudes=False, mag_offset=1.0):
     """Exact FP64 gradient of sum(dimg * render(g)) w.r.t. every parameter.
 
     Returns dict(means [3,n], scales [3,n], quats [4,n], opac [n], sh [16,3,n],
     g2d [n,9] = d/d(u, v, conicA, conicB, conicC, opacity, r, g, b)).  With
-    near_band, also near [n] (bool): the Gaussians with a decision at some pixel
-    within that relative distance of its threshold (alpha vs 1/255, T vs 1e-4,
-    raw alpha vs 0.99), where the gradient jumps.  With magnitudes=True, also
+    near_band, also near [n] (bool): the Gaussians that contribute to a pixel
+    with a decision within that relative distance of its threshold (alpha vs
+    1/255, T vs 1e-4, raw alpha vs 0.99), and those at the band: the gradient
+    jumps there.  With magnitudes=True, also
     abs:<name> (same shapes): the chain rule applied to the sums of the
-    magnitudes of the per-pixel terms (the size of what each entry's summands
-    add up to before they cancel)."""
+    magnitudes of the per-pixel terms, each weighted by (k + mag_offset) for an
+    entry with k contributors in front of it at that pixel (the size of what
+    each entry's summands add up to before they cancel, scaled by how the
+    rounding of a front-to-back evaluation grows along the list)."""
     n, arrs = _params(g)
     cd, ci = _cam_arrays(cam)
     bgv = np.asarray(bg, np.float64)
@@ -194,7 +198,7 @@ def render_bwd(g, cam, dimg, sh_degree=3, bg=(0.0, 0.0, 0.0), near_band=None, ma
     mag = np.zeros(59 * n) if magnitudes else None
     lib().orc_render_bwd(n, *[_ptr(a) for a in arrs], sh_degree, _ptr(cd), _ptr(ci), _ptr(bgv), _ptr(d),
                          *[_ptr(out[k]) for k in ("g2d", "means", "scales", "quats", "opac", "sh")],
-                         0.0 if near_band is None else float(near_band), _ptr(near), _ptr(mag))
+                         0.0 if near_band is None else float(near_band), _ptr(near), _ptr(mag), float(mag_offset))
     if near is not None:
         out["near"] = near > 0
     if mag is not None:

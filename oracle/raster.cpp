@@ -565,16 +565,22 @@ int64_t orc_pairs(int64_t n, const double* means, const double* scales, const do
 //   of the rounding error of any evaluation that sums them in another order).
 //   The colour behind an entry counts with the magnitude of the pixel's final
 //   colour: an adjoint that walks front to back forms it as the final colour
-//   minus the colour in front, a difference of numbers of that size.
+//   minus the colour in front, a difference of numbers of that size.  Each
+//   per-pixel term is weighted by k + mag_offset, k the number of contributors
+//   in front of the entry at that pixel: the rounding of its transmittance and
+//   of the colour in front grows with k, the rest of a term's rounding does not.
 //   near_out (optional, [n], zeroed by the caller): set to 1 for every Gaussian
-//   with a decision at some pixel within a relative near_band of its threshold
-//   (alpha vs 1/255, T vs 1e-4, raw alpha vs 0.99).  The gradient is piecewise
-//   smooth with jumps at these decisions, so such a Gaussian's gradient may
+//   that contributes to a pixel with a decision within a relative near_band of
+//   its threshold (alpha vs 1/255, T vs 1e-4, raw alpha vs 0.99), and for the
+//   entries at the band.  The gradient is piecewise smooth with jumps at these
+//   decisions (one of them changes the transmittance behind it and the colour
+//   behind the entries in front), so such a Gaussian's gradient may
 //   legitimately take another value at a slightly different precision.
 int orc_render_bwd(int64_t n, const double* means, const double* scales, const double* quats, const double* opac,
                    const double* sh, int deg, const double* cam_d, const int32_t* cam_i, const double* bg,
                    const double* dimg, double* g2d_out, double* dmeans, double* dscales, double* dquats,
-                   double* dopac, double* dsh, double near_band, int32_t* near_out, double* abs_out) {
+                   double* dopac, double* dsh, double near_band, int32_t* near_out, double* abs_out,
+                   double mag_offset) {
   Cam cam = to_cam(cam_d, cam_i);
   Inputs in{n, means, scales, quats, opac, sh, deg};
   std::vector<Splat> splats;
@@ -601,7 +607,13 @@ int orc_render_bwd(int64_t n, const double* means, const double* scales, const d
       contrib.clear(); alphas.clear(); Ts.clear(); near.clear();
       PixelResult r = composite(rows[j], i, j, bg, &contrib, &alphas, &Ts, -1, near_out ? &near : nullptr,
                                 near_band);
-      for (const Splat* s : near) loc_near[(size_t)s->index] = 1;
+      // a decision near its threshold changes the transmittance of every entry
+      // behind it and the colour behind every entry in front: all of the
+      // pixel's contributors are marked, with the entries at the band
+      if (!near.empty()) {
+        for (const Splat* s : near) loc_near[(size_t)s->index] = 1;
+        for (const Splat* s : contrib) loc_near[(size_t)s->index] = 1;
+      }
       double gC[3] = {dimg[p], dimg[P + p], dimg[2 * P + p]};
       // R = colour accumulated behind entry k, including the background
       double Racc[3] = {r.T * bg[0], r.T * bg[1], r.T * bg[2]};
@@ -623,11 +635,14 @@ int orc_render_bwd(int64_t n, const double* means, const double* scales, const d
         double power = -0.5 * (s->A * dx * dx + s->C * dy * dy) - s->B * dx * dy;
         double Gv = std::exp(power);
         if (abs_out) {
+          // weight k + mag_offset: the entry's transmittance and the colour in
+          // front are products and sums over the k contributors in front of it
+          const double wk = (double)k + mag_offset;
           double* Ga = &loc_abs[(size_t)s->index * 9];
-          for (int ch = 0; ch < 3; ++ch) Ga[6 + ch] += std::fabs(gC[ch]) * a * T;
+          for (int ch = 0; ch < 3; ++ch) Ga[6 + ch] += wk * std::fabs(gC[ch]) * a * T;
           if (!(s->o * Gv > kAlphaMax)) {
-            double pa = dalpha_abs * s->o * Gv;
-            Ga[5] += dalpha_abs * Gv;
+            double pa = wk * dalpha_abs * s->o * Gv;
+            Ga[5] += wk * dalpha_abs * Gv;
             Ga[0] += pa * (std::fabs(s->A * dx) + std::fabs(s->B * dy));
             Ga[1] += pa * (std::fabs(s->C * dy) + std::fabs(s->B * dx));
             Ga[2] += pa * 0.5 * dx * dx;

@@ -29,20 +29,25 @@ GRAD_TOL = 1e-3
 NAMES = ("means", "scales", "quats", "opac", "sh")
 # Element-wise bound of the FP32 adjoint against the FP64 oracle:
 #   |g - g_ref| <= ELEM_REL |g_ref| + ABS_ULPS * 2^-24 * m + ELEM_FLOOR max|g_ref|
-# with m the oracle's sum of the magnitudes of the entry's per-pixel terms (the
-# entry before cancellation: rounding of any order of summation, and of terms
-# each carried with FP32 relative error, scales with it).  A term of an entry
-# that n entries precede in its pixel's list carries about 2n roundings: the
-# transmittance product and the colour accumulated in front, from which the
-# front-to-back adjoint forms the colour behind as final colour minus colour in
-# front (the oracle counts that term with the final colour's magnitude).  Tile
-# lists here hold at most about 2000 entries, so ABS_ULPS = 4096.
-# Gaussians with a decision within NEAR_BAND of a threshold at some pixel
-# (alpha vs 1/255, T vs 1e-4, raw alpha vs 0.99) are excluded from the
-# element-wise bound and counted: the gradient jumps there, and an FP32
-# evaluation may take the other side.  Both enter the relative L2 error.
+# with m the oracle's sum over pixels of the magnitudes of the entry's per-pixel
+# terms (its value before cancellation), each weighted by k + MAG_OFFSET for an
+# entry with k contributors in front of it at that pixel: a linear model of the
+# rounding each term carries in a front-to-back FP32 evaluation, ABS_ULPS units
+# per contributor in front (the transmittance is a product over them; the colour
+# behind is formed as final colour minus colour in front, which the oracle
+# counts with the final colour's magnitude) plus a fixed ABS_ULPS * MAG_OFFSET
+# units (exponential, reciprocal, adjoint chain).  The fixed part is set from
+# the worst entry measured at full size (about 1900 units, a 1M-Gaussian
+# 1920x1080 view) with a factor two; 64 units per contributor is twice the two
+# roundings per multiply-and-subtract step.
+# Gaussians that contribute to a pixel with a decision within NEAR_BAND of a
+# threshold (alpha vs 1/255, T vs 1e-4, raw alpha vs 0.99) are excluded from the
+# element-wise bound and counted: the gradient jumps there (a skipped entry
+# changes the transmittance behind it by up to 1/255), and an FP32 evaluation
+# may take the other side.  Both enter the relative L2 error.
 ELEM_REL = 1e-3
-ABS_ULPS = 4096.0
+ABS_ULPS = 64.0
+MAG_OFFSET = 64.0
 ELEM_FLOOR = 1e-6
 NEAR_BAND = 1e-4
 # reported: the largest relative error over entries above 1e-3 of the tensor's
@@ -58,7 +63,7 @@ def oracle_grads(g, cam, dimg, sh_degree=3, bg=(0.0, 0.0, 0.0)):
     """Oracle gradients with the magnitude sums (abs:<name>) and the Gaussians
     near a threshold decision (near)."""
     return oracle.render_bwd(g, cam, np.asarray(dimg, np.float64), sh_degree, bg, near_band=NEAR_BAND,
-                             magnitudes=True)
+                             magnitudes=True, mag_offset=MAG_OFFSET)
 
 
 GRAD_KEYS = NAMES + tuple("abs:" + n for n in NAMES)

@@ -632,3 +632,23 @@ def test_near_threshold_flags_mark_the_gaussian_at_the_band():
     dimg = np.ones((3, H, W))
     assert oracle.render_bwd(g, cam, dimg, 0, near_band=1e-6)["near"].tolist() == [True, False]
     assert oracle.render_bwd(g, cam, dimg, 0, near_band=1e-9)["near"].tolist() == [False, False]
+
+
+def test_gradient_magnitude_weights_count_the_contributors_in_front():
+    # magnitudes are linear in the weight offset w: sum over terms of (k + w)|t|.
+    # A lone Gaussian has k = 0 everywhere (weight w only); the back Gaussian of a
+    # pair whose front one covers all of its contributing pixels has k = 1 there
+    W, H, fx = 41, 41, 40.0
+    cam = identity_cam(W, H, fx)
+    rgb = grey_sh(np.array([0.6, 0.4, 0.2]), 2)
+    g = make_set([[0.0, 0.0], [0.0, 0.0], [2.0, 4.0]], [[0.3, 0.1], [0.3, 0.1], [0.3, 0.1]],
+                 [[1.0, 1.0], [0, 0], [0, 0], [0, 0]], [0.5, 0.5], rgb, np.float64)
+    dimg = np.random.default_rng(3).normal(size=(3, H, W))
+    m0 = oracle.render_bwd(g, cam, dimg, 0, magnitudes=True, mag_offset=0.0)
+    m1 = oracle.render_bwd(g, cam, dimg, 0, magnitudes=True, mag_offset=1.0)
+    m5 = oracle.render_bwd(g, cam, dimg, 0, magnitudes=True, mag_offset=5.0)
+    for name in ("means", "scales", "quats", "opac", "sh"):
+        a0, a1, a5 = m0["abs:" + name], m1["abs:" + name], m5["abs:" + name]
+        np.testing.assert_allclose(a5 - a1, 4.0 * (a1 - a0), rtol=1e-12, atol=1e-300)   # linear in w
+        assert np.abs(a0[..., 0]).max() == 0.0                                          # front: k = 0
+        np.testing.assert_allclose(a0[..., 1], a1[..., 1] / 2.0, rtol=1e-12)             # back: k = 1
