@@ -43,13 +43,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# FP32 VALU peak without packed-FP32 instructions (the library is compiled with
-# them disabled): 256 CUs x 64 FMA lanes per clock x 2 flops x 2.4 GHz
-VALU_FP32_PEAK_TFLOPS = 78.6
-# algorithmic FP32 work of one (pixel, Gaussian) evaluation inside the footprint:
-# offset (4), conic quadratic form (7), exp (1), alpha (1), transmittance (2),
-# alpha*T (1), colour update (3 FMA = 6)
-FLOPS_PER_EVAL = 22
+BIN_SORT_KERNELS = ("clear_front, depth_hist, radix_pass<compact>, 2 radix_pass, radix_pass<pairs>, emit, emit_big, "
+                    "2 tile radix_pass, ranges")
+# published FP32 vector peak of MI355X (packed FP32); the library is compiled
+# without packed-FP32 instructions, whose ceiling is half of it: 256 CUs x 64 FMA
+# lanes per clock x 2 flops x 2.4 GHz = 78.6 TFLOP/s
+VALU_FP32_PEAK_TFLOPS = 157.3
+VALU_FP32_UNPACKED_TFLOPS = 78.6
+# algorithmic work of one evaluated (pixel, Gaussian) entry of the forward
+# compositing: 14 FP32 operations and one exponential, counted as 15
+FLOPS_PER_EVAL = 15
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by a 512 MiB copy),
 # valid for the kernel sources with the given fingerprint only (see profiles/, *_hbm_traffic.md)
@@ -86,7 +89,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=("lod", "batched", "uneven", "assign"), default="lod")
+    ap.add_argument("--workload", choices=("lod", "small", "single", "batched", "uneven", "assign"), default="lod")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="headline LoD line only (skip the small, single-view, batched, uneven and assignment legs)")
     ap.add_argument("--n", type=int, default=20_000_000, help="finest-level Gaussians (lod workload)")
     ap.add_argument("--n-xy", type=int, default=8, help="camera positions per height")
     ap.add_argument("--bwd-views", type=int, default=12, help="views used for the fwd+bwd timing")
@@ -106,6 +111,43 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run three 512 MiB device-to-device copies (reference for HBM byte counters)")
     return ap.parse_args()
+
+
+def evals_to_termination(torch, frame, chunk=1 << 16):
+    """E of one rendered single-view frame: the (pixel, Gaussian) entries the
+    compositing evaluates, i.e. for every pixel the entries of its tile list
+    before its termination (n_last) whose footprint rectangle holds the pixel.
+    (The same set for every tile shape: a record whose rectangle holds a pixel is
+    in that pixel's tile list.)"""
+    tw, th = frame.tuning.tile_w, frame.tuning.tile_h
+    W, H = frame.W, frame.H
+    tx_n, ty_n = frame.tiles_x, frame.tiles_y
+    m = frame.host_counts()["pairs"]
+    if m == 0:
+        return 0
+    nl = torch.zeros((ty_n * th, tx_n * tw), dtype=torch.int32, device=frame.device)
+    nl[:H, :W] = frame.n_last[0]
+    nl = nl.view(ty_n, th, tx_n, tw).permute(0, 2, 1, 3).reshape(ty_n * tx_n, th, tw)
+    tiles = frame.pair_tiles[:m].to(torch.int64)
+    recs = frame.pair_records[:m].to(torch.int64)
+    start = frame.tile_ranges[:, 0].to(torch.int64)
+    raw = frame.records.view(torch.int32).view(-1, 12)
+    ax = torch.arange(tw, device=frame.device)
+    ay = torch.arange(th, device=frame.device)
+    total = 0
+    for c0 in range(0, m, chunk):
+        t = tiles[c0:c0 + chunk]
+        k = torch.arange(c0, min(m, c0 + chunk), device=frame.device, dtype=torch.int64) - start[t]
+        r = raw[recs[c0:c0 + chunk]]
+        px, py = r[:, 2].to(torch.int64) & 0xFFFFFFFF, r[:, 3].to(torch.int64) & 0xFFFFFFFF
+        i0, j0 = px & 0xFFFF, py & 0xFFFF
+        i1, j1 = i0 + (px >> 16), j0 + (py >> 16)
+        ox, oy = (t % tx_n) * tw, (t // tx_n) * th
+        mx = ((ax[None] + ox[:, None]) >= i0[:, None]) & ((ax[None] + ox[:, None]) <= i1[:, None])
+        my = ((ay[None] + oy[:, None]) >= j0[:, None]) & ((ay[None] + oy[:, None]) <= j1[:, None])
+        walked = nl[t] > k[:, None, None]
+        total += int((walked & my[:, :, None] & mx[:, None, :]).sum().item())
+    return total
 
 
 def graph_of(torch, fn, stream):
@@ -163,16 +205,14 @@ def workload_lod(args, torch, gs, render, synth):
         render.render_frame(scene, frame, cam_slot[v], thresholds=thresholds)
         c = frame.host_counts()
         stats.append(c)
-        # (pixel, Gaussian) evaluations the compositing must do: sum of the visible footprints' areas
-        nr = c["records"]
-        rec = frame.records[: nr * gs.record_bytes()].view(torch.int32).view(nr, 12)
-        w = ((rec[:, 2] >> 16) & 0xFFFF).to(torch.int64) + 1
-        h = ((rec[:, 3] >> 16) & 0xFFFF).to(torch.int64) + 1
-        evals.append(int(((w * h) * (frame.tiles_touched[:nr] > 0)).sum().item()))
+        # (pixel, Gaussian) entries the compositing evaluates, up to each pixel's termination
+        # (torch kernels, outside every timed region; skipped in the profiler-only modes)
+        if not (args.frames_only or args.bwd_only or args.pointwise_only):
+            evals.append(evals_to_termination(torch, frame))
     n_sel = np.array([s["records"] for s in stats])
     n_vis = np.array([s["visible"] for s in stats])
     n_pairs = np.array([s["pairs"] for s in stats])
-    n_eval = np.array(evals, dtype=np.float64)
+    n_eval = np.array(evals if evals else [0.0], dtype=np.float64)
     log("per view: N_sel mean %.0f (max %d), N_vis mean %.0f, pairs mean %.0f (max %d), evals mean %.0f" %
         (n_sel.mean(), n_sel.max(), n_vis.mean(), n_pairs.mean(), n_pairs.max(), n_eval.mean()))
     # every stream of the step is made here, before anything else makes streams, so
@@ -318,7 +358,17 @@ def workload_lod(args, torch, gs, render, synth):
         del gv
     fps_views = 1e3 / np.array(per_view_ms)
 
-    # ---- kernels timed with HIP events on the stream they run on ---------------------
+    # ---- per-height / per-pitch FPS (the paper's Fig. 5 reports mean and minimum
+    #      FPS per camera height for looking-down cameras) ---------------------------
+    heights, pitches = (50.0, 150.0, 400.0), (-90.0, -45.0)
+    per_group = {}
+    for hi, h in enumerate(heights):
+        for pi, p in enumerate(pitches):
+            sel = fps_views[(hi * len(pitches) + pi) * args.n_xy:(hi * len(pitches) + pi + 1) * args.n_xy]
+            per_group["%dm_pitch%d" % (h, p)] = {"fps_mean": float(sel.mean()), "fps_min": float(sel.min()),
+                                                 "views": int(sel.size)}
+
+    # ---- stages timed with HIP events on the stream they run on ---------------------
     kern_ms = {"preprocess": [], "rasterize_fwd": [], "bin_sort": []}
     blocks = scene.blocks_struct()
     with torch.cuda.stream(stream):
@@ -344,15 +394,47 @@ def workload_lod(args, torch, gs, render, synth):
             kern_ms["bin_sort"].append(ev[1].elapsed_time(ev[2]))
             kern_ms["rasterize_fwd"].append(ev[2].elapsed_time(ev[3]))
     pre_ms = float(np.mean(kern_ms["preprocess"]))
-    # preprocess algorithmic bytes per launch: 12 B centre + 8 B (depth key, tiles touched) per selected record,
-    # 224 B (rotation, scale, opacity, SH) read + 48 B record written per visible record
-    pre_bytes = float(np.mean(20.0 * n_sel + 272.0 * n_vis))
-    pre_gbs = pre_bytes / (pre_ms * 1e-3) / 1e9
+    bin_ms = float(np.mean(kern_ms["bin_sort"]))
     ras_ms = float(np.mean(kern_ms["rasterize_fwd"]))
+    log("stage ms (mean over views): preprocess %.4f, bin_sort %.4f, rasterize_fwd %.4f" % (pre_ms, bin_ms, ras_ms))
+    P = float(W * H)
+    # preprocess: 12 B centre + 8 B (depth key, tiles touched) per selected record; 224 B (rotation,
+    # scale, opacity, SH) read + 48 B record written per visible record
+    pre_bytes = float(np.mean(20.0 * n_sel + 272.0 * n_vis))
+    # binning, one-pass lower bound: pairs written once and read once (24 B per pair) + the range scan (8 B)
+    bin_bytes = float(np.mean(32.0 * n_pairs))
+    # forward compositing: 15 operations per evaluated entry (14 FP32 + one exponential)
     ras_flops = float(np.mean(n_eval)) * FLOPS_PER_EVAL
-    ras_tflops = ras_flops / (ras_ms * 1e-3) / 1e12
-    log("kernel ms (mean over views): preprocess %.4f, bin_sort %.4f, rasterize_fwd %.4f" %
-        (pre_ms, np.mean(kern_ms["bin_sort"]), ras_ms))
+    stage = {
+        "preprocess": {"bound": "hbm", "kernel": "preprocess_kernel", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                       "achieved": pre_bytes / (pre_ms * 1e-3) / 1e9, "avg_launch_ms": pre_ms,
+                       "algorithmic_bytes_per_launch": pre_bytes,
+                       "traffic": measured_traffic("preprocess_kernel")},
+        "bin_sort": {"bound": "hbm", "kernel": "bin_sort stage (%s)" % BIN_SORT_KERNELS, "unit": "GB/s",
+                     "peak": HBM_PEAK_GBS, "achieved": bin_bytes / (bin_ms * 1e-3) / 1e9, "avg_launch_ms": bin_ms,
+                     "algorithmic_bytes_per_launch": bin_bytes, "bytes_per_pair": 32,
+                     "traffic": measured_traffic("bin_sort")},
+        "rasterize_fwd": {"bound": "alu",
+                          "kernel": "raster_fwd_kernel<%d,%d,%d>" % (tun.tile_w, tun.tile_h, tun.batch),
+                          "unit": "TFLOP/s", "peak": VALU_FP32_PEAK_TFLOPS,
+                          "achieved": ras_flops / (ras_ms * 1e-3) / 1e12, "avg_launch_ms": ras_ms,
+                          "algorithmic_flops_per_launch": ras_flops, "evals_per_launch": float(np.mean(n_eval)),
+                          "flops_per_eval": FLOPS_PER_EVAL,
+                          "frac_of_unpacked_fp32_ceiling": None,
+                          "traffic": measured_traffic("raster_fwd_kernel<%d,%d,%d>" % (tun.tile_w, tun.tile_h,
+                                                                                         tun.batch))},
+    }
+    for k, r in stage.items():
+        r["frac"] = r["achieved"] / r["peak"]
+    stage["rasterize_fwd"]["frac_of_unpacked_fp32_ceiling"] = \
+        stage["rasterize_fwd"]["achieved"] / VALU_FP32_UNPACKED_TFLOPS
+    dominant = max(stage, key=lambda k: stage[k]["avg_launch_ms"])
+    # whole frame against HBM: the algorithmic bytes of one forward frame (N_sel centres and
+    # tiles touched, N_vis parameters and records, pairs written/read/scanned/gathered, image, T, n_last)
+    b_fwd = float(np.mean(24.0 * n_sel + 276.0 * n_vis + 72.0 * n_pairs)) + 20.0 * P
+    frame_hbm = {"bytes_per_frame": b_fwd,
+                 "frac_one_frame_in_flight": b_fwd * fps_seq / (HBM_PEAK_GBS * 1e9),
+                 "frac_frames_in_flight": b_fwd * fps / (HBM_PEAK_GBS * 1e9)}
 
     out_extra = {}
     # ---- plain comparator: LoD off, every block at the finest level, eager, 16x16 ----
@@ -420,7 +502,8 @@ def workload_lod(args, torch, gs, render, synth):
     # ---- CPU oracle on a bounded sample: one full LoD frame ---------------------------
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_oracle_frame(scene, fine, block_id, u, cells, cams, n_sel, thresholds, synth)
+        cpu = cpu_oracle_frames(scene, fine, block_id, u, cells, cams, args.n_xy, thresholds, synth)
+    del scene, fine
 
     result = {
         "metric": "FPS @1600x900 on 20M-Gaussian LoD scene",
@@ -449,17 +532,10 @@ def workload_lod(args, torch, gs, render, synth):
         "default_tuning_fps": (V / (default_step_ms * 1e-3)) if default_step_ms else None,
         "gaussians_per_s": float(n_sel.mean() * fps),
         "n_sel_mean": float(n_sel.mean()), "n_vis_mean": float(n_vis.mean()), "pairs_mean": float(n_pairs.mean()),
-        "roofline": {"bound": "alu", "kernel": "raster_fwd_kernel<%d,%d,%d>" % (tun.tile_w, tun.tile_h, tun.batch),
-                     "achieved": ras_tflops, "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": ras_tflops / VALU_FP32_PEAK_TFLOPS,
-                     "traffic": measured_traffic("raster_fwd_kernel<%d,%d,%d>" % (tun.tile_w, tun.tile_h, tun.batch)),
-                     "avg_launch_ms": ras_ms,
-                     "algorithmic_flops_per_launch": ras_flops, "evals_per_launch": float(np.mean(n_eval)),
-                     "flops_per_eval": FLOPS_PER_EVAL},
-        "roofline_preprocess": {"bound": "hbm", "kernel": "preprocess_kernel", "achieved": pre_gbs,
-                                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": pre_gbs / HBM_PEAK_GBS,
-                                "traffic": measured_traffic("preprocess_kernel"),
-                                "avg_launch_ms": pre_ms, "algorithmic_bytes_per_launch": pre_bytes},
+        "roofline": dict(stage[dominant], stage=dominant),
+        "rooflines": stage,
+        "frame_hbm": frame_hbm,
+        "per_height_pitch": per_group,
         "kernel_ms": {k: float(np.mean(v)) for k, v in kern_ms.items()},
         "cpu_baseline": cpu,
     }
@@ -472,7 +548,7 @@ def workload_lod(args, torch, gs, render, synth):
             by_flags[key] = min(by_flags.get(key, float("inf")), r["ms"])
         result["autotune"]["best_ms_by_flags"] = by_flags
     result.update(out_extra)
-    print(json.dumps(result))
+    return result
 
 
 def pointwise_frames(args, torch, gs, render, scene, cam_slot, thresholds, W, H, tuning, stream, blockwise_fps):
@@ -566,47 +642,147 @@ def reduced_frames(args, torch, gs, render, scene, cam_slot, thresholds, W, H, t
             "binary16_levels": list(half_levels), "coarse_level_bytes": int(stored)}
 
 
-def cpu_oracle_frame(scene, fine, block_id, u, cells, cams, n_sel, thresholds, synth):
-    """Time the oracle on one full LoD frame of a 150 m view (selection by the oracle's own LoD code)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_threads():
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def cpu_oracle_frames(scene, fine, block_id, u, cells, cams, n_xy, thresholds, synth):
+    """The oracle (FP64, untiled, OpenMP over pixels) on six seeded LoD views of
+    the city, two per height (first position at each pitch), each a full
+    1600x900 frame on its oracle-selected aggregated set; the per-scene MAD
+    boxes are computed once and not counted."""
     import oracle
     from oracle import lod as olod
     oracle.build(force=False)
-    V = len(cams)
-    mid = n_sel[V // 3:2 * V // 3]
-    vi = int(np.argsort(mid)[len(mid) // 2]) + V // 3
-    cam = cams[vi]
     fractions = (0.30, 0.50, 1.00)
     memb = synth.level_membership(block_id, u, scene.n_blocks, fractions)
     lvl_cnt = np.stack([m[1] for m in memb], axis=1)
     bounds = np.concatenate([[0], np.cumsum(lvl_cnt[:, -1])])
     lo = np.zeros((scene.n_blocks, 3))
     hi = np.zeros((scene.n_blocks, 3))
-    t_c0 = time.perf_counter()
     for b in range(scene.n_blocks):
         lo[b], hi[b] = olod.mad_bounds(fine.means[:, bounds[b]:bounds[b + 1]])
-    level_ref, _ = olod.lod_select(lo, hi, cells, thresholds, [cam], lvl_cnt)
-    t_lod = time.perf_counter() - t_c0
-    sel = []
-    for b in range(scene.n_blocks):
-        l = level_ref[0, b]
-        if l < 0:
-            continue
-        idx = memb[l][0]
-        idx = idx[(idx >= bounds[b]) & (idx < bounds[b + 1])]
-        sel.append((idx, l))
-    idx_all = np.concatenate([s[0] for s in sel])
-    scale_k = np.concatenate([np.full(len(s[0]), 1.0 if s[1] == 2 else 1.3, np.float32) for s in sel])
-    agg = synth.GaussianSet(fine.means[:, idx_all], (fine.scales[:, idx_all] * scale_k).astype(np.float32),
-                            fine.quats[:, idx_all], fine.opac[idx_all], fine.sh[:, :, idx_all])
-    tc = time.perf_counter()
-    oracle.render(agg, cam)
-    t_render = time.perf_counter() - tc
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    log("cpu oracle: %.2f s/frame on %d threads" % (t_render, cores))
-    return {"value": 1.0 / t_render, "unit": "frames/s", "cores": cores, "kind": "oracle",
-            "sample": "one full 1600x900 LoD frame (view %d, 150 m, %d selected Gaussians): FP64 projection + "
-                      "untiled per-pixel compositing; the per-scene MAD boxes and selection (%.1fs) are not "
-                      "counted" % (vi, agg.opac.shape[0], t_lod)}
+    views = [(hi_ * 2 + pi) * n_xy for hi_ in range(3) for pi in range(2)]
+    times, n_agg = [], []
+    for vi in views:
+        cam = cams[vi]
+        level_ref, _ = olod.lod_select(lo, hi, cells, thresholds, [cam], lvl_cnt)
+        sel = []
+        for b in range(scene.n_blocks):
+            l = level_ref[0, b]
+            if l < 0:
+                continue
+            idx = memb[l][0]
+            idx = idx[(idx >= bounds[b]) & (idx < bounds[b + 1])]
+            sel.append((idx, l))
+        idx_all = np.concatenate([s_[0] for s_ in sel])
+        scale_k = np.concatenate([np.full(len(s_[0]), 1.0 if s_[1] == 2 else 1.3, np.float32) for s_ in sel])
+        agg = synth.GaussianSet(fine.means[:, idx_all], (fine.scales[:, idx_all] * scale_k).astype(np.float32),
+                                fine.quats[:, idx_all], fine.opac[idx_all], fine.sh[:, :, idx_all])
+        tc = time.perf_counter()
+        oracle.render(agg, cam)
+        times.append(time.perf_counter() - tc)
+        n_agg.append(agg.opac.shape[0])
+    t = float(np.mean(times))
+    log("cpu oracle (city LoD frames): %.2f s/frame on %d threads" % (t, cpu_threads()))
+    return {"value": 1.0 / t, "unit": "frames/s", "cores": cpu_threads(), "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": "six full 1600x900 LoD frames of the 20M city (views %s: two per height 50/150/400 m, pitch "
+                      "-90 and -45), each on its oracle-selected set (%d Gaussians on average): FP64 projection + "
+                      "untiled per-pixel compositing; per-scene MAD boxes not counted" %
+                      (views, int(np.mean(n_agg))),
+            "ms_per_view": [1e3 * x for x in times]}
+
+
+def cpu_oracle_views(g_list, cams, dimgs, fwd_only=False):
+    """Wall-clock of the oracle per view: forward render and (unless fwd_only) its exact backward."""
+    import oracle
+    oracle.build(force=False)
+    fwd, bwd = [], []
+    for g, cam, d in zip(g_list, cams, dimgs):
+        t0 = time.perf_counter()
+        oracle.render(g, cam)
+        fwd.append(time.perf_counter() - t0)
+        if not fwd_only:
+            t0 = time.perf_counter()
+            oracle.render_bwd(g, cam, d)
+            bwd.append(time.perf_counter() - t0)
+    out = {"fwd_ms_per_view": 1e3 * float(np.mean(fwd)), "views": len(fwd)}
+    if bwd:
+        out["fwd_bwd_ms_per_view"] = 1e3 * float(np.mean(np.array(fwd) + np.array(bwd)))
+    return out
+
+
+def timed_ms(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / reps
+
+
+def single_set_case(args, torch, gs, render, g, cam, target, reps, tag, cpu):
+    """One Gaussian set, one view, LoD off (every Gaussian): forward and forward +
+    L1 backward latency, eager and from a HIP graph; optionally the oracle."""
+    dev = "cuda:0"
+    scene = render.DeviceScene.single(g, device=dev)
+    cams_dev = gs.cameras_to_device([cam], dev)
+    n = scene.n_finest
+    f = render.Frame(1, 1, cam.width, cam.height, n, max(1 << 16, 4 * n), device=dev)
+    render.render_frame(scene, f, cams_dev, mode=gs.GS_LOD_ALL_FINEST, thresholds=())
+    grads = [scene.levels[0].zeros_like()]
+    tgt = torch.from_numpy(target[None]).to(dev)
+
+    def fwd():
+        render.render_frame(scene, f, cams_dev, mode=gs.GS_LOD_ALL_FINEST, thresholds=(), check=False)
+
+    def fwd_bwd():
+        fwd()
+        render.backward_frame(scene, f, cams_dev, torch.sign(f.rgb - tgt) / f.rgb.numel(), grads)
+
+    stream = torch.cuda.Stream()
+    out = {"n_gaussians": n, "width": cam.width, "height": cam.height, "counts": f.host_counts(),
+           "fwd_ms_eager": timed_ms(torch, fwd, reps), "fwd_bwd_ms_eager": timed_ms(torch, fwd_bwd, reps)}
+    for key, fn in (("fwd_ms_graph", fwd), ("fwd_bwd_ms_graph", fwd_bwd)):
+        gph = graph_of(torch, fn, stream)
+        out[key] = 1e3 * timed_replays(torch, gph, reps, 2)
+        del gph
+    if f.host_counts()["flags"]:
+        raise RuntimeError("capacity flag raised in the %s case: %s" % (tag, f.host_counts()))
+    log("%s: fwd %.3f ms (graph %.3f), fwd+bwd %.3f ms (graph %.3f)" %
+        (tag, out["fwd_ms_eager"], out["fwd_ms_graph"], out["fwd_bwd_ms_eager"], out["fwd_bwd_ms_graph"]))
+    if cpu:
+        img = f.rgb[0].cpu().numpy()
+        d = (np.sign(img - target) / img.size).astype(np.float64)
+        out["cpu_oracle"] = cpu_oracle_views([g], [cam], [d])
+        log("%s cpu oracle: %s" % (tag, out["cpu_oracle"]))
+    return out
+
+
+def workload_small(args, torch, gs, render, synth, cpu=True):
+    """4096 Gaussians in [-1,1]^3 at 256x256 (seed 0): absolute latency."""
+    g, cam = synth.small_render_case(4096, seed=0)
+    target = np.random.default_rng(0).uniform(size=(3, cam.height, cam.width)).astype(np.float32)
+    return single_set_case(args, torch, gs, render, g, cam, target, 50, "small render 4096 @ 256x256", cpu)
+
+
+def workload_single(args, torch, gs, render, synth, cpu=True):
+    """1M Gaussians over a 200 x 200 x 40 m box, one 1920x1080 view (seed 1), L1 against U[0,1]."""
+    g, cam, target = synth.single_view_training_case()
+    return single_set_case(args, torch, gs, render, g, cam, target, 10, "single view 1M @ 1920x1080", cpu)
 
 
 # -------------------------------------------------------------------------------------------
@@ -655,25 +831,37 @@ def workload_batched(args, torch, gs, render, synth):
         plain()
     torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t0) / reps
-    print(json.dumps({"metric": "fwd+bwd ms/view, 16 views of one 2M-Gaussian block, batched vs plain",
-                      "value": 1e3 * t_batched / V, "unit": "ms/view", "higher_is_better": False,
-                      "plain_ms_per_view": 1e3 * t_plain / V, "speedup_vs_plain": t_plain / t_batched,
-                      "views": V, "n_gaussians": scene.n_finest, "width": W, "height": H,
-                      "launch": "one batched call per step, hipGraph; shared selection + work queue",
-                      "records": counts["records"], "visible": counts["visible"], "pairs": counts["pairs"],
-                      "dtype": "f32", "data": "synthetic"}))
+    out = {"metric": "fwd+bwd ms/view, 16 views of one 2M-Gaussian block, batched vs plain",
+           "value": 1e3 * t_batched / V, "unit": "ms/view", "higher_is_better": False,
+           "plain_ms_per_view": 1e3 * t_plain / V, "speedup_vs_plain": t_plain / t_batched,
+           "views": V, "n_gaussians": scene.n_finest, "width": W, "height": H,
+           "launch": "one batched call per step, hipGraph; shared selection + work queue",
+           "records": counts["records"], "visible": counts["visible"], "pairs": counts["pairs"],
+           "dtype": "f32", "data": "synthetic"}
+    log("batched 16 x 2M: %.3f ms/view (plain %.3f)" % (out["value"], out["plain_ms_per_view"]))
+    if not args.no_cpu:
+        vv = [0, 4, 8, 12]
+        render.render_frame(scene, fb, cams_dev, mode=gs.GS_LOD_ALL_FINEST, thresholds=())
+        img = fb.rgb.cpu().numpy()
+        tg = target.cpu().numpy()
+        ds = [(np.sign(img[v] - tg[v]) / fb.rgb.numel()).astype(np.float64) for v in vv]
+        out["cpu_oracle"] = cpu_oracle_views([fine] * len(vv), [cams[v] for v in vv], ds)
+        log("batched cpu oracle: %s" % out["cpu_oracle"])
+    return out
 
 
-def workload_uneven(args, torch, gs, render, synth):
-    """32 uneven blocks x 4 views at 1280x720: LoD select + fwd + bwd batched, autotuned."""
+def workload_uneven(args, torch, gs, render, synth, tune=True):
+    """32 uneven blocks x 4 views at 1280x720: LoD select + fwd + bwd batched
+    (autotuned launch shape, or the library default with the work queue)."""
     from paper_2404_01133_amd import autotune
     dev = "cuda:0"
     W, H = 1280, 720
     thresholds = (200.0, 500.0)
-    bs, cams = synth.uneven_block_scene(seed=4)
-    scene = render.DeviceScene.from_block_scene(bs, device=dev)
-    del bs
+    t_gen = time.time()
+    fine, block_id, u, cells, cams = synth.uneven_finest(seed=4)
+    scene = render.DeviceScene.from_finest(fine, block_id, u, cells, device=dev)
     scene.compute_bounds(4.0)
+    log("uneven scene: %d finest Gaussians, %d blocks (%.1fs)" % (fine.n, scene.n_blocks, time.time() - t_gen))
     V = len(cams)
     chunk = 16  # views per batched call (bounds the record and pair buffers)
     cams_dev = gs.cameras_to_device(cams, dev)
@@ -711,9 +899,17 @@ def workload_uneven(args, torch, gs, render, synth):
             return f.rgb.clone()
         return step_with(f), images
 
-    best, report = autotune.tune("uneven_32blocks_%dviews_%dx%d" % (V, W, H), make_runner, use_cache=False, log=log)
-    f = get_frame(best.tile_w, best.tile_h)
-    f.tuning = best.tuning()
+    if tune:
+        best, report = autotune.tune("uneven_32blocks_%dviews_%dx%d" % (V, W, H), make_runner, use_cache=False,
+                                     log=log)
+        f = get_frame(best.tile_w, best.tile_h)
+        f.tuning = best.tuning()
+        tuned = {k: report[k] for k in ("best", "best_ms", "default_ms", "rejected")}
+    else:
+        f = get_frame(16, 16)
+        f.tuning = gs.tuning_struct(16, 16, 256, gs.GS_TUNE_WORK_QUEUE)
+        tuned = {"best": {"tile_w": 16, "tile_h": 16, "batch": 256, "flags": gs.GS_TUNE_WORK_QUEUE},
+                 "autotuned": False}
     stream = torch.cuda.Stream()
     g = graph_of(torch, step_with(f), stream)
     t_batched = timed_replays(torch, g, max(2, args.steps // 4), 1)
@@ -736,12 +932,46 @@ def workload_uneven(args, torch, gs, render, synth):
     plain()
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
-    print(json.dumps({"metric": "LoD fwd+bwd ms/view, 32 uneven blocks x 4 views, batched + autotuned vs per-view",
-                      "value": 1e3 * t_batched / V, "unit": "ms/view", "higher_is_better": False,
-                      "per_view_default_ms_per_view": 1e3 * t_plain / V, "speedup": t_plain / t_batched,
-                      "views": V, "views_per_call": chunk, "width": W, "height": H,
-                      "autotune": {k: report[k] for k in ("best", "best_ms", "default_ms", "rejected")},
-                      "n_finest": scene.n_finest, "dtype": "f32", "data": "synthetic"}))
+    out = {"metric": "LoD fwd+bwd ms/view, 32 uneven blocks x 4 views, batched vs per-view",
+           "value": 1e3 * t_batched / V, "unit": "ms/view", "higher_is_better": False,
+           "per_view_default_ms_per_view": 1e3 * t_plain / V, "speedup": t_plain / t_batched,
+           "views": V, "views_per_call": chunk, "width": W, "height": H, "tuning": tuned,
+           "n_finest": scene.n_finest, "dtype": "f32", "data": "synthetic"}
+    log("uneven 32 blocks x 4 views: %.3f ms/view (per-view calls %.3f)" % (out["value"],
+                                                                          out["per_view_default_ms_per_view"]))
+    if not args.no_cpu:
+        from oracle import lod as olod
+        vv = [0, 37, 74, 111]
+        fractions = (0.30, 0.50, 1.00)
+        memb = synth.level_membership(block_id, u, scene.n_blocks, fractions)
+        lvl_cnt = np.stack([m[1] for m in memb], axis=1)
+        bounds = np.concatenate([[0], np.cumsum(lvl_cnt[:, -1])])
+        lo = np.zeros((scene.n_blocks, 3))
+        hi = np.zeros((scene.n_blocks, 3))
+        for b in range(scene.n_blocks):
+            lo[b], hi[b] = olod.mad_bounds(fine.means[:, bounds[b]:bounds[b + 1]])
+        level_ref, _ = olod.lod_select(lo, hi, cells, thresholds, [cams[v] for v in vv], lvl_cnt)
+        aggs, ds = [], []
+        tg = target.cpu().numpy()
+        for k, v in enumerate(vv):
+            parts = []
+            for b in range(scene.n_blocks):
+                l = level_ref[k, b]
+                if l < 0:
+                    continue
+                idx = memb[l][0]
+                parts.append((idx[(idx >= bounds[b]) & (idx < bounds[b + 1])], l))
+            idx_all = np.concatenate([p_[0] for p_ in parts])
+            sk = np.concatenate([np.full(len(p_[0]), 1.0 if p_[1] == 2 else 1.3, np.float32) for p_ in parts])
+            aggs.append(synth.GaussianSet(fine.means[:, idx_all], (fine.scales[:, idx_all] * sk).astype(np.float32),
+                                          fine.quats[:, idx_all], fine.opac[idx_all], fine.sh[:, :, idx_all]))
+            render.render_frame(scene, f1, slots[v], thresholds=thresholds)
+            img = f1.rgb[0].cpu().numpy()
+            ds.append((np.sign(img - tg[v % chunk]) / img.size).astype(np.float64))
+        out["cpu_oracle"] = cpu_oracle_views(aggs, [cams[v] for v in vv], ds)
+        out["cpu_oracle"]["selected_gaussians_mean"] = float(np.mean([a_.n for a_ in aggs]))
+        log("uneven cpu oracle: %s" % out["cpu_oracle"])
+    return out
 
 
 def workload_assign(args, torch, gs, render, synth):
@@ -777,13 +1007,13 @@ def workload_assign(args, torch, gs, render, synth):
     assert (rn["b"] == r["b"]).all()
     log("assignment: %.2f ms/pose (%d leave-one-out renders), all renders %.2f ms/pose (%d)" %
         (1e3 * best / P, r["renders"], 1e3 * tn / P, rn["renders"]))
-    print(json.dumps({"metric": "data assignment ms/pose, 6x6 contracted blocks of a 3M-Gaussian prior, 960x540",
-                      "value": 1e3 * best / P, "unit": "ms/pose", "higher_is_better": False,
-                      "all_renders_ms_per_pose": 1e3 * tn / P, "speedup_vs_all_renders": tn / best,
-                      "poses": P, "blocks": scene.n_blocks, "leave_one_out_renders": r["renders"],
-                      "leave_one_out_renders_all": rn["renders"], "assigned_pairs": int(r["b"].sum()),
-                      "b1_pairs": int(r["b1"].sum()), "b2_pairs": int(r["b2"].sum()), "eps": 0.05,
-                      "dtype": "f32", "data": "synthetic"}))
+    return {"metric": "data assignment ms/pose, 6x6 contracted blocks of a 3M-Gaussian prior, 960x540",
+            "value": 1e3 * best / P, "unit": "ms/pose", "higher_is_better": False,
+            "all_renders_ms_per_pose": 1e3 * tn / P, "speedup_vs_all_renders": tn / best,
+            "poses": P, "blocks": scene.n_blocks, "leave_one_out_renders": r["renders"],
+            "leave_one_out_renders_all": rn["renders"], "assigned_pairs": int(r["b"].sum()),
+            "b1_pairs": int(r["b1"].sum()), "b2_pairs": int(r["b2"].sum()), "eps": 0.05,
+            "dtype": "f32", "data": "synthetic"}
 
 
 def main():
@@ -798,13 +1028,39 @@ def main():
 
     torch.cuda.set_device(0)
     if args.workload == "lod":
-        workload_lod(args, torch, gs, render, synth)
+        result = workload_lod(args, torch, gs, render, synth)
+        if result is None:  # a profiler-only mode printed its own line
+            return
+        if not args.no_extra:
+            # the other configurations of the scope table, timed in the same run (their own keys)
+            cpu = result.get("cpu_baseline")
+            plan = {}
+            for key, fn in (("small_render", workload_small), ("single_view", workload_single)):
+                r = fn(args, torch, gs, render, synth, cpu=not args.no_cpu)
+                if "cpu_oracle" in r:
+                    plan[key] = r.pop("cpu_oracle")
+                result[key] = r
+            for key, fn in (("batched", workload_batched),
+                            ("uneven", lambda *a: workload_uneven(*a, tune=False)),
+                            ("assignment", workload_assign)):
+                r = fn(args, torch, gs, render, synth)
+                if "cpu_oracle" in r:
+                    plan[key] = r.pop("cpu_oracle")
+                result[key] = r
+                torch.cuda.empty_cache()
+            if cpu is not None:
+                cpu["other_configs"] = plan
+        print(json.dumps(result))
+    elif args.workload == "small":
+        print(json.dumps(workload_small(args, torch, gs, render, synth, cpu=not args.no_cpu)))
+    elif args.workload == "single":
+        print(json.dumps(workload_single(args, torch, gs, render, synth, cpu=not args.no_cpu)))
     elif args.workload == "batched":
-        workload_batched(args, torch, gs, render, synth)
+        print(json.dumps(workload_batched(args, torch, gs, render, synth)))
     elif args.workload == "uneven":
-        workload_uneven(args, torch, gs, render, synth)
+        print(json.dumps(workload_uneven(args, torch, gs, render, synth)))
     else:
-        workload_assign(args, torch, gs, render, synth)
+        print(json.dumps(workload_assign(args, torch, gs, render, synth)))
 
 
 if __name__ == "__main__":

@@ -352,9 +352,9 @@ def orbit_views(center, n_views=16, radius=60.0, height=60.0, width=1600, h_px=9
     return cams
 
 
-def uneven_block_scene(seed=4, grid=(8, 4), cell=153.1, n_min=200_000, n_max=3_000_000,
-                       fractions=(0.30, 0.50, 1.00)):
-    """Blocks with log-uniform Gaussian counts; returns the scene and 4 views per block."""
+def uneven_finest(seed=4, grid=(8, 4), cell=153.1, n_min=200_000, n_max=3_000_000):
+    """Finest level of the uneven scene (blocks with log-uniform Gaussian counts),
+    in block order, and 4 views per block: (fine, block_id, u, cells, cams)."""
     rng = np.random.default_rng(seed)
     nx, ny = grid
     counts = np.exp(rng.uniform(math.log(n_min), math.log(n_max), size=nx * ny)).astype(np.int64)
@@ -365,12 +365,11 @@ def uneven_block_scene(seed=4, grid=(8, 4), cell=153.1, n_min=200_000, n_max=3_0
     for b in range(nx * ny):
         parts.append(city_points(rng, int(counts[b]), cells[b, 0], cells[b, 2], cell, cell))
     means = np.concatenate(parts, axis=1).astype(np.float32)
+    del parts
     n = means.shape[1]
     block_id = np.repeat(np.arange(nx * ny), counts)
     scales, quats, opac, sh = draw_attributes(rng, n)
     u = rng.uniform(size=n)
-    scene = block_scene_from_finest(GaussianSet(means, scales, quats, opac, sh), block_id, cells, u,
-                                    fractions)
     cams = []
     for b in range(nx * ny):
         for _ in range(4):
@@ -380,4 +379,11 @@ def uneven_block_scene(seed=4, grid=(8, 4), cell=153.1, n_min=200_000, n_max=3_0
             pitch = math.radians(rng.uniform(-90.0, -30.0))
             yaw = rng.uniform(0.0, 2 * math.pi)
             cams.append(look_camera((x, y, h), yaw, pitch, 1280, 720))
-    return scene, cams
+    return GaussianSet(means, scales, quats, opac, sh), block_id, u, cells, cams
+
+
+def uneven_block_scene(seed=4, grid=(8, 4), cell=153.1, n_min=200_000, n_max=3_000_000,
+                       fractions=(0.30, 0.50, 1.00)):
+    """Blocks with log-uniform Gaussian counts; returns the scene and 4 views per block."""
+    fine, block_id, u, cells, cams = uneven_finest(seed, grid, cell, n_min, n_max)
+    return block_scene_from_finest(fine, block_id, cells, u, fractions), cams
