@@ -10,24 +10,28 @@ namespace gs {
 
 // ---------------------------------------------------------------------------
 // projected record (48 bytes, three 16-byte words)
-//   w0: du, dv        (2D mean minus the centre of the footprint's first pixel,
-//                      i.e. u - i0 - 1/2 and v - j0 - 1/2, FP32; the 1/2 shift
-//                      of the rounded u - i0 is exact, so a pixel at offset di
-//                      has dx = di - du with the same rounding as (di + 1/2) - (u - i0))
+//   w0: du            (2D mean minus the centre of the footprint's first pixel,
+//                      i.e. u - i0 - 1/2, FP32; the 1/2 shift of the rounded
+//                      u - i0 is exact, so a pixel at offset di has dx = di - du
+//                      with the same rounding as (di + 1/2) - (u - i0); dv, the
+//                      same for v, is the last word of w2)
+//       view index (int bits)
 //       px = i0 | (i1 - i0) << 16, py = j0 | (j1 - j0) << 16  (footprint, inclusive)
+//       (w0 holds everything the binning reads: one 16-byte load per record)
 //   w1: ca, cb, cc    (factor of the conic scaled by sqrt(log2(e) / 2): the
 //                      Gaussian's value at pixel offset d is
 //                      exp2(-((ca dx + cb dy)^2 + (cc dy)^2)))
 //       opacity
 //   w2: r, g, b       (SH colour, clamped at 0)
-//       view index (int bits)
+//       dv
 // ---------------------------------------------------------------------------
 struct alignas(16) Record {
-  float du, dv;
+  float du;
+  uint32_t view;
   uint32_t px, py;
   float ca, cb, cc, opac;
   float r, g, b;
-  uint32_t view;
+  float dv;
 };
 static_assert(sizeof(Record) == 48, "record layout");
 

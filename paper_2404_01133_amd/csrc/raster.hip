@@ -78,7 +78,7 @@ __device__ __forceinline__ void raster_fwd_tile(const TileArgs& ta, FwdLds<TW, T
       int di, dj;
       const bool in_fp = in_footprint(i, j, __float_as_uint(w0.z), __float_as_uint(w0.w), di, dj);
       Eval e;
-      evaluate(w0, w1, di, dj, e);
+      evaluate(w0, w1, w2, di, dj, e);
       bool use = valid && !done && in_fp && (e.alpha >= kAlphaMin);
       const float Tn = T * (1.0f - e.alpha);
       const bool stop = use && (Tn < kTMin);

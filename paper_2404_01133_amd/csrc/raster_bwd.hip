@@ -165,7 +165,7 @@ __device__ __forceinline__ void raster_bwd_tile(const TileArgs& ta, BwdLds<TW, T
       int di, dj;
       const bool in_fp = in_footprint(i, j, __float_as_uint(w0.z), __float_as_uint(w0.w), di, dj);
       Eval e;
-      evaluate(w0, w1, di, dj, e);
+      evaluate(w0, w1, w2, di, dj, e);
       const bool use = valid && (base_idx + k < last) && in_fp && (e.alpha >= kAlphaMin);
       if (__ballot(use) == 0) return;
       const float aT = e.alpha * T;

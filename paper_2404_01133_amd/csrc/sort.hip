@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(kThreads) emit_kernel(const Record* __restrict
   for (int64_t j = gtid; j < n; j += stride) {
     const uint32_t rid = sorted_records[j];
     const uint4 w0 = *reinterpret_cast<const uint4*>(&records[rid]);
-    const uint32_t view = reinterpret_cast<const uint32_t*>(&records[rid])[11];
+    const uint32_t view = w0.y;
     const int i0 = (int)(w0.z & 0xFFFFu), i1 = i0 + (int)(w0.z >> 16);
     const int j0 = (int)(w0.w & 0xFFFFu), j1 = j0 + (int)(w0.w >> 16);
     const int ntx = i1 / tw - i0 / tw + 1, nty = j1 / th - j0 / th + 1;
@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(kThreads) emit_big_kernel(const Record* __rest
     const uint32_t j = big_list[k];
     const uint32_t rid = sorted_records[j];
     const uint4 w0 = *reinterpret_cast<const uint4*>(&records[rid]);
-    const uint32_t view = reinterpret_cast<const uint32_t*>(&records[rid])[11];
+    const uint32_t view = w0.y;
     const int i0 = (int)(w0.z & 0xFFFFu), i1 = i0 + (int)(w0.z >> 16);
     const int j0 = (int)(w0.w & 0xFFFFu), j1 = j0 + (int)(w0.w >> 16);
     const int tx0 = i0 / tw, ty0 = j0 / th;

@@ -21,9 +21,10 @@ __device__ __forceinline__ bool in_footprint(int i, int j, uint32_t px, uint32_t
   return ((uint32_t)di <= (px >> 16)) && ((uint32_t)dj <= (py >> 16));
 }
 
-__device__ __forceinline__ void evaluate(const float4& w0, const float4& w1, int di, int dj, Eval& e) {
+__device__ __forceinline__ void evaluate(const float4& w0, const float4& w1, const float4& w2, int di, int dj,
+                                         Eval& e) {
   e.dx = (float)di - w0.x;  // w0.x = u - i0 - 1/2
-  e.dy = (float)dj - w0.y;
+  e.dy = (float)dj - w2.w;  // w2.w = v - j0 - 1/2
   e.p1 = fmaf(w1.x, e.dx, w1.y * e.dy);
   e.p2 = w1.z * e.dy;
   e.G = __builtin_amdgcn_exp2f(-fmaf(e.p1, e.p1, e.p2 * e.p2));

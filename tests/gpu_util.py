@@ -26,8 +26,8 @@ def records_np(frame, n):
     i0 = (px & 0xFFFF).astype(np.int64)
     j0 = (py & 0xFFFF).astype(np.int64)
     rect = np.stack([i0, i0 + (px >> 16), j0, j0 + (py >> 16)], axis=1)
-    return dict(u=f[:, 0] + i0 + 0.5, v=f[:, 1] + j0 + 0.5, rect=rect, conic_factor=f[:, 4:7], opac=f[:, 7], rgb=f[:, 8:11],
-                view=raw[:, 11])
+    return dict(u=f[:, 0] + i0 + 0.5, v=f[:, 11] + j0 + 0.5, rect=rect, conic_factor=f[:, 4:7], opac=f[:, 7],
+                rgb=f[:, 8:11], view=raw[:, 1])
 
 
 def frame_pairs(frame):
