@@ -113,21 +113,30 @@ struct Geo {
   double opac;
 };
 
-// Decides culling and the footprint; returns false if culled.  All 44 bytes of
-// geometry (centre, opacity, rotation, scale) are requested at once so the
-// loads overlap; the SH coefficients are read later, only for survivors.
+// Decides culling and the footprint; returns false if culled.  Two rounds of
+// loads: centre, scale and opacity first (28 B), which decide most culls — the
+// near plane, the opacity threshold, and a footprint that certainly misses the
+// image (below) — and the rotation (16 B) only for the Gaussians left; the SH
+// coefficients are read later, by the caller, only for survivors.
+//
+// Early footprint test: the projected covariance is J W Rq diag(s)^2 Rq^T W^T J^T
+// with W and Rq rotations, so its trace is at most |J|_F^2 s_max^2, and the
+// larger eigenvalue of the dilated matrix is below that trace + 0.6.  With |J|_F^2
+// bounded through the guard-band limits of x/z and y/z, 3 sqrt(bound) + 2 px is
+// more than the radius ceil(3 sqrt(lmax)) computed below (the relative slack of
+// 1e-6 covers the rounding of both sides), and u, v are computed by the same
+// operations as below, so a centre farther than that outside the image is one
+// the exact test would cull too.  Non-finite values fail every comparison and
+// take the exact path.
 template <bool HALF>
 __device__ __forceinline__ bool project_geo(const LevelPtrs& L, int64_t gi, const gs_camera& cam, int W, int H,
                                             Geo& o) {
   const int64_t n = L.n;
   const double* R = cam.R;
-  // every geometry load is issued before the first cull, so they overlap
   o.m[0] = L.means[gi];
   o.m[1] = L.means[n + gi];
   o.m[2] = L.means[2 * n + gi];
   const float op32 = attr<HALF>(L.opac, gi);
-  const float q0f = attr<HALF>(L.quats, gi), q1f = attr<HALF>(L.quats, n + gi), q2f = attr<HALF>(L.quats, 2 * n + gi),
-              q3f = attr<HALF>(L.quats, 3 * n + gi);
   const float s0f = attr<HALF>(L.scales, gi), s1f = attr<HALF>(L.scales, n + gi),
               s2f = attr<HALF>(L.scales, 2 * n + gi);
   o.tx = ((R[0] * o.m[0] + R[1] * o.m[1]) + R[2] * o.m[2]) + cam.t[0];
@@ -137,6 +146,24 @@ __device__ __forceinline__ bool project_geo(const LevelPtrs& L, int64_t gi, cons
   o.opac = op32;
   if (!(o.opac >= 1.0 / 255.0)) return false;
   o.depth = (float)o.tz;
+  o.rz = 1.0 / o.tz;
+  o.ux = o.tx * o.rz;
+  o.uy = o.ty * o.rz;
+  o.u = cam.fx * o.ux + cam.cx;
+  o.v = cam.fy * o.uy + cam.cy;
+  const double tanx = (0.5 * W) / cam.fx, tany = (0.5 * H) / cam.fy;
+  const double limx = 1.3 * tanx, limy = 1.3 * tany;
+  {
+    const double smax = dmax_(fabs((double)s0f), dmax_(fabs((double)s1f), fabs((double)s2f)));
+    const double jx = cam.fx * o.rz, jy = cam.fy * o.rz;
+    const double jf2 = jx * jx * (1.0 + limx * limx) + jy * jy * (1.0 + limy * limy);
+    const double rb = 3.0 * sqrt((jf2 * (smax * smax) + 0.6) * (1.0 + 1e-6)) + 2.0;
+    if ((o.u + rb) - 0.5 < 0.0 || (o.u - rb) - 0.5 > (double)(W - 1) || (o.v + rb) - 0.5 < 0.0 ||
+        (o.v - rb) - 0.5 > (double)(H - 1))
+      return false;
+  }
+  const float q0f = attr<HALF>(L.quats, gi), q1f = attr<HALF>(L.quats, n + gi), q2f = attr<HALF>(L.quats, 2 * n + gi),
+              q3f = attr<HALF>(L.quats, 3 * n + gi);
   const double q0 = q0f, q1 = q1f, q2 = q2f, q3 = q3f;
   const double qn2 = ((q0 * q0 + q1 * q1) + q2 * q2) + q3 * q3;
   if (!(qn2 > 0.0 && qn2 <= 1.0e300)) return false;
@@ -160,11 +187,6 @@ __device__ __forceinline__ bool project_geo(const LevelPtrs& L, int64_t gi, cons
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j)
       o.WL[i][j] = (R[3 * i + 0] * o.Lm[0][j] + R[3 * i + 1] * o.Lm[1][j]) + R[3 * i + 2] * o.Lm[2][j];
-  o.rz = 1.0 / o.tz;
-  o.ux = o.tx * o.rz;
-  o.uy = o.ty * o.rz;
-  const double tanx = (0.5 * W) / cam.fx, tany = (0.5 * H) / cam.fy;
-  const double limx = 1.3 * tanx, limy = 1.3 * tany;
   o.uxc = dmin_(limx, dmax_(-limx, o.ux));
   o.uyc = dmin_(limy, dmax_(-limy, o.uy));
   o.clamp_x = o.uxc != o.ux;
@@ -186,8 +208,6 @@ __device__ __forceinline__ bool project_geo(const LevelPtrs& L, int64_t gi, cons
   const double cr1 = o.M[0][2] * o.M[1][0] - o.M[0][0] * o.M[1][2];
   const double cr2 = o.M[0][0] * o.M[1][1] - o.M[0][1] * o.M[1][0];
   o.det = (((cr0 * cr0 + cr1 * cr1) + cr2 * cr2) + 0.3 * (o.n0 + o.n1)) + 0.09;
-  o.u = cam.fx * o.ux + cam.cx;
-  o.v = cam.fy * o.uy + cam.cy;
   if (!(o.det > 0.0 && o.det <= 1.0e300)) return false;
   const double hd = 0.5 * (o.a - o.c);
   const double lmax = 0.5 * (o.a + o.c) + sqrt(hd * hd + o.b * o.b);

@@ -74,6 +74,44 @@ __global__ void clear_front_kernel(uint32_t* __restrict__ fixed, int64_t fixed_w
 constexpr int kDepthHistCopies = 8;
 constexpr int64_t kDepthHistWords = 4 * kRadix;
 
+// Histogram adds of a wave whose lanes often share a digit.  Depth keys are
+// float bits and a wave holds neighbouring Gaussians, so the top digit (sign and
+// exponent) and the next one take a few values per wave; plain LDS atomics on
+// them serialise on one address.  match_add: each lane finds the lanes with its
+// digit with eight ballots (a fixed cost whatever the distribution) and the
+// lowest of them adds their count.  top_add: one round per distinct top digit
+// in the wave (sign and exponent of depths within a wave: one or two values),
+// adding the lanes' count and their tiles_touched sum.
+__device__ __forceinline__ void match_add(bool valid, uint32_t d, uint32_t* h) {
+  uint64_t peers = __ballot(valid);
+#pragma unroll
+  for (int bit = 0; bit < 8; ++bit) {
+    const bool b = (d >> bit) & 1u;
+    const uint64_t m = __ballot(b);
+    peers &= b ? m : ~m;
+  }
+  if (valid && lanemask_lt_count(peers) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+}
+
+__device__ __forceinline__ void top_add(bool valid, uint32_t d, uint32_t tt, uint32_t* h, uint64_t* wh) {
+  const int lane = threadIdx.x & 63;
+  uint64_t left = __ballot(valid);
+  while (left) {
+    const int leader = (int)__builtin_ctzll(left);
+    const uint32_t dl = (uint32_t)__builtin_amdgcn_readlane((int)d, leader);
+    const bool mine = valid && d == dl;
+    const uint64_t m = __ballot(mine);
+    uint64_t v = mine ? (uint64_t)tt : 0ull;  // 64 lanes of tiles_touched may pass 2^32
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == leader) {
+      atomicAdd(&h[dl], (uint32_t)__popcll(m));
+      atomicAdd((unsigned long long*)&wh[dl], (unsigned long long)v);
+    }
+    left &= ~m;
+  }
+}
+
 __global__ void __launch_bounds__(kThreads) depth_hist_kernel(const int32_t* __restrict__ tiles_touched,
                                                               const uint32_t* __restrict__ depth_keys, int64_t cap,
                                                               const int64_t* counts, uint32_t* __restrict__ hist,
@@ -93,12 +131,14 @@ __global__ void __launch_bounds__(kThreads) depth_hist_kernel(const int32_t* __r
     for (int k = 0; k < kItems; ++k) {
       const int64_t idx = b * per_block + (int64_t)k * kThreads + threadIdx.x;  // coalesced
       const int32_t tt = idx < n ? tiles_touched[idx] : 0;
-      if (tt > 0) {
-        const uint32_t key = depth_keys[idx];
-#pragma unroll
-        for (int p = 0; p < 4; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
-        atomicAdd((unsigned long long*)&s_whist[key >> 24], (unsigned long long)tt);
+      const bool vis = tt > 0;
+      const uint32_t key = vis ? depth_keys[idx] : 0u;
+      if (vis) {
+        atomicAdd(&s_hist[0][key & 255u], 1u);
+        atomicAdd(&s_hist[1][(key >> 8) & 255u], 1u);
       }
+      match_add(vis, (key >> 16) & 255u, s_hist[2]);
+      top_add(vis, key >> 24, vis ? (uint32_t)tt : 0u, s_hist[3], s_whist);
     }
   }
   __syncthreads();
