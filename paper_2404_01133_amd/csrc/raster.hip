@@ -28,6 +28,7 @@ static_assert(kFwdGroups == 8, "the forward uses wave_compact8");
 template <int TW, int TH, int BATCH>
 struct FwdLds {
   float4 w0[BATCH], w1[BATCH], w2[BATCH];
+  float4 f[BATCH];  // footprint as floats: i0, j0, i1 - i0, j1 - j0
   uint8_t list[(TW * TH) / 64][kFwdGroups][kListStride<BATCH>];
 };
 
@@ -43,12 +44,14 @@ __device__ __forceinline__ void raster_fwd_tile(const TileArgs& ta, FwdLds<TW, T
   float4* s_w0 = lds.w0;
   float4* s_w1 = lds.w1;
   float4* s_w2 = lds.w2;
+  float4* s_f = lds.f;
   const int view = tile_g / tiles_per_view;
   const int tile = tile_g - view * tiles_per_view;
   const int tyi = tile / tiles_x_n, txi = tile - tyi * tiles_x_n;
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const LaneMap<TW, TH, kFwdGW, kFwdGH> qb(txi, tyi, wid);
   const int i = qb.i, j = qb.j;
+  const float fi = (float)i, fj = (float)j;
   const bool inside = (i < W) && (j < H);
   const uint32_t start = ranges[2 * tile_g], end = ranges[2 * tile_g + 1];
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
@@ -61,9 +64,12 @@ __device__ __forceinline__ void raster_fwd_tile(const TileArgs& ta, FwdLds<TW, T
     const int nb = (int)min((uint32_t)BATCH, end - b);
     for (int k = threadIdx.x; k < nb; k += NT) {
       const float4* r = reinterpret_cast<const float4*>(&records[pair_records[b + k]]);
-      s_w0[k] = r[0];
+      const float4 a = r[0];
+      s_w0[k] = a;
       s_w1[k] = r[1];
       s_w2[k] = r[2];
+      const uint32_t px = __float_as_uint(a.z), py = __float_as_uint(a.w);
+      s_f[k] = make_float4((float)(px & 0xFFFFu), (float)(py & 0xFFFFu), (float)(px >> 16), (float)(py >> 16));
     }
     // list entries past a group's count read stale indices that may land on
     // unstaged slots: their colour must be finite (it is multiplied by 0)
@@ -74,11 +80,9 @@ __device__ __forceinline__ void raster_fwd_tile(const TileArgs& ta, FwdLds<TW, T
     const int my_cnt = cnt.of(qb.g);
     const int base_idx = (int)(b - start);
     int last_k = -1;  // batch index of the last entry used in this batch
-    auto blend = [&](int k, bool valid, const float4& w0, const float4& w1, const float4& w2) {
-      int di, dj;
-      const bool in_fp = in_footprint(i, j, __float_as_uint(w0.z), __float_as_uint(w0.w), di, dj);
+    auto blend = [&](int k, bool valid, float du, const float4& f, const float4& w1, const float4& w2) {
       Eval e;
-      evaluate(w0, w1, w2, di, dj, e);
+      const bool in_fp = evaluate_f(fi, fj, f, du, w2.w, w1, e);
       bool use = valid && !done && in_fp && (e.alpha >= kAlphaMin);
       const float Tn = T * (1.0f - e.alpha);
       const bool stop = use && (Tn < kTMin);
@@ -101,14 +105,15 @@ __device__ __forceinline__ void raster_fwd_tile(const TileArgs& ta, FwdLds<TW, T
       const uint32_t pk = *reinterpret_cast<const uint32_t*>(&my_list[t]);
       const int k0 = (int)(pk & (BATCH - 1)), k1 = (int)((pk >> 8) & (BATCH - 1));
       const int k2 = (int)((pk >> 16) & (BATCH - 1)), k3 = (int)((pk >> 24) & (BATCH - 1));
-      const float4 a0 = s_w0[k0], a1 = s_w1[k0], a2 = s_w2[k0];
-      const float4 b0 = s_w0[k1], b1 = s_w1[k1], b2 = s_w2[k1];
-      const float4 c0 = s_w0[k2], c1 = s_w1[k2], c2 = s_w2[k2];
-      const float4 d0 = s_w0[k3], d1 = s_w1[k3], d2 = s_w2[k3];
-      blend(k0, t < my_cnt, a0, a1, a2);
-      blend(k1, t + 1 < my_cnt, b0, b1, b2);
-      blend(k2, t + 2 < my_cnt, c0, c1, c2);
-      blend(k3, t + 3 < my_cnt, d0, d1, d2);
+      const float au = s_w0[k0].x, bu = s_w0[k1].x, cu = s_w0[k2].x, du = s_w0[k3].x;
+      const float4 af = s_f[k0], a1 = s_w1[k0], a2 = s_w2[k0];
+      const float4 bf = s_f[k1], b1 = s_w1[k1], b2 = s_w2[k1];
+      const float4 cf = s_f[k2], c1 = s_w1[k2], c2 = s_w2[k2];
+      const float4 df = s_f[k3], d1 = s_w1[k3], d2 = s_w2[k3];
+      blend(k0, t < my_cnt, au, af, a1, a2);
+      blend(k1, t + 1 < my_cnt, bu, bf, b1, b2);
+      blend(k2, t + 2 < my_cnt, cu, cf, c1, c2);
+      blend(k3, t + 3 < my_cnt, du, df, d1, d2);
     }
     if (last_k >= 0) last = base_idx + last_k + 1;
     __syncthreads();

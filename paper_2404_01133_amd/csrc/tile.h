@@ -21,15 +21,35 @@ __device__ __forceinline__ bool in_footprint(int i, int j, uint32_t px, uint32_t
   return ((uint32_t)di <= (px >> 16)) && ((uint32_t)dj <= (py >> 16));
 }
 
-__device__ __forceinline__ void evaluate(const float4& w0, const float4& w1, const float4& w2, int di, int dj,
-                                         Eval& e) {
-  e.dx = (float)di - w0.x;  // w0.x = u - i0 - 1/2
-  e.dy = (float)dj - w2.w;  // w2.w = v - j0 - 1/2
+// Gaussian and alpha at offset (dx, dy) from the projected mean
+__device__ __forceinline__ void evaluate_at(const float4& w1, Eval& e) {
   e.p1 = fmaf(w1.x, e.dx, w1.y * e.dy);
   e.p2 = w1.z * e.dy;
   e.G = __builtin_amdgcn_exp2f(-fmaf(e.p1, e.p1, e.p2 * e.p2));
   e.alpha = fminf(kAlphaMax, w1.w * e.G);
 }
+
+__device__ __forceinline__ void evaluate(const float4& w0, const float4& w1, const float4& w2, int di, int dj,
+                                         Eval& e) {
+  e.dx = (float)di - w0.x;  // w0.x = u - i0 - 1/2
+  e.dy = (float)dj - w2.w;  // w2.w = v - j0 - 1/2
+  evaluate_at(w1, e);
+}
+
+// The same with the footprint given as floats f = (i0, j0, i1 - i0, j1 - j0),
+// for a pixel (fi, fj) as floats: fi - i0 is exact (integers below 2^24), so dx
+// equals the value above bit for bit, and the footprint test is one unsigned
+// compare of float bits per axis (a non-negative float's bits grow with its
+// value; a negative difference has the sign bit set and fails).
+__device__ __forceinline__ bool evaluate_f(float fi, float fj, const float4& f, float du, float dv,
+                                           const float4& w1, Eval& e) {
+  const float fdi = fi - f.x, fdj = fj - f.y;
+  e.dx = fdi - du;
+  e.dy = fdj - dv;
+  evaluate_at(w1, e);
+  return (__float_as_uint(fdi) <= __float_as_uint(f.z)) && (__float_as_uint(fdj) <= __float_as_uint(f.w));
+}
+
 
 // Lane -> pixel map of the tile kernels: the tile is cut into 8x8 pixel
 // blocks, one per wave (wave w is block (w mod TW/8, w div TW/8)); each block
