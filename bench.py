@@ -1,31 +1,33 @@
 """Benchmark of the MI355X rendering path.
 
-Default workload (the headline line): block-wise LoD render of a 20M-Gaussian
-synthetic city at 1600x900.  One step = every evaluation view rendered once
-(48 views: heights 50/150/400 m, 8 positions each, pitch -90 and -45 degrees),
-each frame  lod_select -> preprocess -> bin_sort -> rasterize_fwd, replayed
-from a HIP graph, with the tile launch shape chosen by the autotuner
-(bit-identical images required).  Four frames are in flight (frame v on stream
-v mod 4, each with its own buffers), so the latency-bound binning of one frame
-overlaps the compositing of another; `value` = frames per second over the step,
-and `fps_one_frame_in_flight` the same step with one frame at a time.
+Headline (one JSON line): block-wise LoD render of a 20M-Gaussian synthetic city
+at 1600x900.  One step = every evaluation view rendered once (48 views: heights
+50/150/400 m, 8 positions each, pitch -90 and -45 degrees), each frame
+lod_select -> preprocess -> bin_sort -> rasterize_fwd, replayed from a HIP
+graph, with the tile launch shape chosen by the autotuner (bit-identical images
+required).  Each call renders several views in one batched pass (--views-per-call,
+default 8: one record space, one binning, one compositing launch over all their
+tiles) and calls are kept in flight on separate streams with their own buffers
+(--in-flight, default 4), so the latency-bound binning of one call overlaps the
+compositing of another; `value` = frames per second over the step,
+`fps_one_frame_in_flight` the same step one view per call, one call at a time
+(--flight-sweep times every pairing of --sweep-calls and --sweep-views).
 
-Also reported: per-view FPS distribution (mean / median / min), the plain
-comparator (same library, LoD off: every block at the finest level, eager
-launches, default 16x16 tiles), the point-wise LoD comparator (every Gaussian
-of every level tested on its own, HIP graph, same launch shape; the baseline
-of the block-wise strategy in the paper's LoD ablation), fwd+bwd ms/view for
-LoD and plain, the
-roofline of the dominant kernel measured with HIP events, the preprocess HBM
-roofline, and the CPU oracle's frame time on a bounded sample.
+In the same line: per-view FPS (mean / median / min, and per height and pitch:
+the paper's Fig. 5 split), the plain comparator (LoD off: every block at the
+finest level, eager, default 16x16 tiles), the point-wise LoD comparator, the
+reduced-precision levels, fwd+bwd ms/view for LoD and plain, rooflines of the
+three stages timed with HIP events (the longest one is `roofline`), the
+whole-frame HBM fraction, the CPU oracle on a bounded sample (six city frames;
+the other configurations' oracle times under cpu_baseline.other_configs), and
+the other configurations as their own keys: small_render (4096 Gaussians,
+256x256), single_view (1M Gaussians, 1920x1080, fwd and fwd+bwd), batched (16
+views of one 2M-Gaussian block, fwd+L1+bwd in one call), uneven (32 blocks of
+0.2M-3M Gaussians, 4 views each at 1280x720, LoD + fwd + bwd), assignment
+(Eqs. 3-5 for 32 poses).
 
-Other workloads (their own JSON line, not the headline):
-  --workload batched   16 training views of one 2M-Gaussian block at 1600x900 in one
-                       call (shared selection, persistent work queue), fwd+L1+bwd
-                       captured in a HIP graph, vs 16 separate plain fwd+bwd calls
-  --workload uneven    32 blocks of 0.2M-3M Gaussians, 4 views each at 1280x720:
-                       LoD select + fwd + bwd batched, autotuned launch shape, vs
-                       per-view calls with the default shape
+--workload small|single|batched|uneven|assign prints one of those alone (uneven
+then autotunes its launch shape).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 20000000] [--workload lod]
 """
@@ -54,11 +56,14 @@ VALU_FP32_UNPACKED_TFLOPS = 78.6
 # compositing: 14 FP32 operations and one exponential, counted as 15
 FLOPS_PER_EVAL = 15
 
-# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by a 512 MiB copy),
-# valid for the kernel sources with the given fingerprint only (see profiles/, *_hbm_traffic.md)
+# HBM bytes per launch (the binning: its 11 launches) from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of
+# `bench.py --stages-only` scaled by a 512 MiB copy, for launches of the given views per call, valid for
+# the kernel sources with the given fingerprint only
 MEASURED_TRAFFIC = {
-    "raster_fwd_kernel<16,16,256>": (("raster.hip", "tile.h", "project.h", "gs_common.h"), "2e688001e55c660d", 82.23e6),
-    "preprocess_kernel": (("preprocess.hip", "project.h", "gs_common.h"), "1df5a32e59f9f2dd", 224.86e6),
+    "preprocess_kernel": (("preprocess.hip", "project.h", "gs_common.h"), "c26d8eaed24310d8", 8, 1652.82e6),
+    "raster_fwd_kernel<16,16,256>": (("raster.hip", "tile.h", "project.h", "gs_common.h"), "fb896b71fa3cb949", 8,
+                                     667.93e6),
+    "bin_sort": (("sort.hip", "radix.h", "scan.h", "gs_common.h"), "529be3f41e4e5ec9", 8, 1535.73e6),
 }
 
 
@@ -72,12 +77,12 @@ def source_fingerprint(files):
     return m.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch, or None if not measured for this kernel or its source changed since."""
+def measured_traffic(kernel, views_per_launch):
+    """HBM bytes per launch, or None if not measured for this kernel and call shape or its source changed since."""
     if kernel not in MEASURED_TRAFFIC:
         return None
-    files, fp, nbytes = MEASURED_TRAFFIC[kernel]
-    return nbytes if source_fingerprint(files) == fp else None
+    files, fp, views, nbytes = MEASURED_TRAFFIC[kernel]
+    return nbytes if views == views_per_launch and source_fingerprint(files) == fp else None
 
 
 def log(*a):
@@ -96,7 +101,13 @@ def parse():
     ap.add_argument("--n-xy", type=int, default=8, help="camera positions per height")
     ap.add_argument("--bwd-views", type=int, default=12, help="views used for the fwd+bwd timing")
     ap.add_argument("--in-flight", type=int, default=4,
-                    help="frames rendered concurrently in the timed graph (own buffers and stream each)")
+                    help="calls rendered concurrently in the timed graph (own buffers and stream each)")
+    ap.add_argument("--views-per-call", type=int, default=8,
+                    help="views rendered by one batched call in the timed graph (divides the view count)")
+    ap.add_argument("--sweep-calls", default="1,2,4,8", help="calls in flight tried by --flight-sweep")
+    ap.add_argument("--sweep-views", default="1,2,4,8", help="views per call tried by --flight-sweep")
+    ap.add_argument("--flight-sweep", action="store_true",
+                    help="time calls in flight 1/2/4/8 x views per call 1/2/4/8 and print them (no headline)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-pointwise", action="store_true", help="skip the point-wise LoD comparator")
     ap.add_argument("--no-reduced", action="store_true", help="skip the reduced-precision levels variant")
@@ -107,6 +118,8 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--frames-only", action="store_true", help="only the timed LoD frames (for profilers)")
     ap.add_argument("--bwd-only", action="store_true", help="only the LoD fwd+bwd loop (for profilers)")
+    ap.add_argument("--stages-only", action="store_true",
+                    help="only the HIP-event stage timing of the LoD calls (for profilers)")
     ap.add_argument("--tuning", default=None, help="tile_w,tile_h,batch,flags instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run three 512 MiB device-to-device copies (reference for HBM byte counters)")
@@ -207,7 +220,7 @@ def workload_lod(args, torch, gs, render, synth):
         stats.append(c)
         # (pixel, Gaussian) entries the compositing evaluates, up to each pixel's termination
         # (torch kernels, outside every timed region; skipped in the profiler-only modes)
-        if not (args.frames_only or args.bwd_only or args.pointwise_only):
+        if not (args.frames_only or args.bwd_only or args.pointwise_only or args.stages_only):
             evals.append(evals_to_termination(torch, frame))
     n_sel = np.array([s["records"] for s in stats])
     n_vis = np.array([s["visible"] for s in stats])
@@ -219,7 +232,7 @@ def workload_lod(args, torch, gs, render, synth):
     # the K streams of the in-flight graph land on distinct hardware queues
     K = max(1, args.in_flight)
     stream = torch.cuda.Stream()
-    side = [torch.cuda.Stream() for _ in range(K - 1)]
+    side = [torch.cuda.Stream() for _ in range(max(K, 8 if args.flight_sweep else 1) - 1)]
 
     def lod_step(f):
         return lambda: [render.render_frame(scene, f, cam_slot[v], thresholds=thresholds, check=False)
@@ -247,7 +260,7 @@ def workload_lod(args, torch, gs, render, synth):
     if args.tuning:
         tw, th, b, fl = (int(x) for x in args.tuning.split(","))
         frame = new_frame(tw, th, b, fl)
-    elif not (args.no_autotune or args.frames_only):
+    elif not (args.no_autotune or args.frames_only or args.stages_only):
         from paper_2404_01133_amd import autotune
         frames = {(16, 16): frame}
         gate_views = [0, V // 3, 2 * V // 3, V - 1]
@@ -282,6 +295,132 @@ def workload_lod(args, torch, gs, render, synth):
     tun = frame.tuning
     tuning_desc = dict(tile_w=tun.tile_w, tile_h=tun.tile_h, batch=tun.batch, flags=tun.flags)
 
+    # ---- stages timed with HIP events on the stream they run on, in the call shape of
+    #      the timed step (P_ views per call), one call at a time; work per launch is
+    #      the sum over the call's views -------------------------------------------------
+    def time_stages(P_):
+        if V % P_:
+            raise ValueError("views per call must divide the %d views" % V)
+        sf = frame if P_ == 1 else render.Frame(scene.n_blocks, P_, W, H, P_ * rc, P_ * frame.pair_capacity,
+                                                gs.tuning_struct(tun.tile_w, tun.tile_h, tun.batch, tun.flags),
+                                                device=dev)
+        n_calls = V // P_
+        calls = [cams_all[c * P_ * 152:(c + 1) * P_ * 152] for c in range(n_calls)]
+        for c in range(n_calls):  # capacities, and the counts of a call equal the sums over its views
+            render.render_frame(scene, sf, calls[c], thresholds=thresholds)
+            hc = sf.host_counts()
+            want = (int(n_sel[c * P_:(c + 1) * P_].sum()), int(n_vis[c * P_:(c + 1) * P_].sum()),
+                    int(n_pairs[c * P_:(c + 1) * P_].sum()))
+            if (hc["records"], hc["visible"], hc["pairs"]) != want:
+                raise RuntimeError("call %d counts %s differ from the sums over its views %s" % (c, hc, want))
+        kms = {"preprocess": [], "rasterize_fwd": [], "bin_sort": []}
+        blocks = scene.blocks_struct()
+        levels = [lv.struct() for lv in scene.levels]
+        with torch.cuda.stream(stream):
+            for rep in range(2):  # the first round warms up
+                for c in range(n_calls):
+                    cc = calls[c]
+                    gs.lod_select(blocks, thresholds, gs.GS_LOD_BLOCKWISE, cc, P_, sf.level, sf.offsets, sf.counts,
+                                  stream)
+                    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+                    ev[0].record(stream)
+                    gs.preprocess(levels, blocks, sf.level, sf.offsets, cc, P_, W, H, 3, sf.tuning,
+                                  sf.record_capacity, sf.records, sf.depth_keys, sf.tiles_touched, sf.counts, stream)
+                    ev[1].record(stream)
+                    gs.bin_sort(sf.records, sf.depth_keys, sf.tiles_touched, P_, W, H, sf.tuning, sf.record_capacity,
+                                sf.pair_capacity, sf.pair_tiles, sf.pair_records, sf.tile_ranges, sf.counts,
+                                sf.sort_ws, stream, sf.tile_queue)
+                    ev[2].record(stream)
+                    gs.rasterize_fwd(sf.records, sf.pair_records, sf.tile_ranges, P_, W, H, (0.0, 0.0, 0.0),
+                                     sf.tuning, sf.rgb, sf.T, sf.n_last, stream, sf.tile_queue)
+                    ev[3].record(stream)
+                    ev[3].synchronize()
+                    if rep:
+                        kms["preprocess"].append(ev[0].elapsed_time(ev[1]))
+                        kms["bin_sort"].append(ev[1].elapsed_time(ev[2]))
+                        kms["rasterize_fwd"].append(ev[2].elapsed_time(ev[3]))
+        if sf.host_counts()["flags"]:
+            raise RuntimeError("capacity flag raised during the stage timing: %s" % sf.host_counts())
+        del sf
+        pre_ms = float(np.mean(kms["preprocess"]))
+        bin_ms = float(np.mean(kms["bin_sort"]))
+        ras_ms = float(np.mean(kms["rasterize_fwd"]))
+        log("stage ms per call of %d views (mean over %d calls): preprocess %.4f, bin_sort %.4f, rasterize_fwd %.4f"
+            % (P_, n_calls, pre_ms, bin_ms, ras_ms))
+        per_call = lambda a: a.reshape(n_calls, P_).sum(axis=1).astype(np.float64)
+        c_sel, c_vis, c_pairs = per_call(n_sel), per_call(n_vis), per_call(n_pairs)
+        c_eval = per_call(n_eval) if n_eval.size == V else np.zeros(n_calls)
+        # preprocess: 12 B centre + 8 B (depth key, tiles touched) per selected record; 224 B (rotation,
+        # scale, opacity, SH) read + 48 B record written per visible record
+        pre_bytes = float(np.mean(20.0 * c_sel + 272.0 * c_vis))
+        # binning, one-pass lower bound: pairs written once and read once (24 B per pair) + the range scan (8 B)
+        bin_bytes = float(np.mean(32.0 * c_pairs))
+        # what the sort's own passes move at 24 B per element per pass: four depth passes (the first over
+        # every selected record, the others over the visible ones) and ceil(tile bits / 8) tile passes
+        n_tile_ids = frame.tiles_x * frame.tiles_y * P_
+        tbits = max(0, int(n_tile_ids - 1).bit_length())
+        tpasses = (tbits + 7) // 8
+        sort_bytes = float(np.mean(24.0 * (c_sel + 3.0 * c_vis + tpasses * c_pairs)))
+        # forward compositing: 15 operations per evaluated entry (14 FP32 + one exponential)
+        ras_flops = float(np.mean(c_eval)) * FLOPS_PER_EVAL
+        ras_name = "raster_fwd_kernel<%d,%d,%d>" % (tun.tile_w, tun.tile_h, tun.batch)
+        st = {
+            "preprocess": {"bound": "hbm", "kernel": "preprocess_kernel", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                           "achieved": pre_bytes / (pre_ms * 1e-3) / 1e9, "avg_launch_ms": pre_ms,
+                           "algorithmic_bytes_per_launch": pre_bytes,
+                           "traffic": measured_traffic("preprocess_kernel", P_)},
+            "bin_sort": {"bound": "hbm", "kernel": "bin_sort stage (%s)" % BIN_SORT_KERNELS, "unit": "GB/s",
+                         "peak": HBM_PEAK_GBS, "achieved": bin_bytes / (bin_ms * 1e-3) / 1e9,
+                         "avg_launch_ms": bin_ms, "algorithmic_bytes_per_launch": bin_bytes, "bytes_per_pair": 32,
+                         "sort_design_bytes": sort_bytes,
+                         "sort_design_frac": sort_bytes / (bin_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "tile_passes": tpasses, "traffic": measured_traffic("bin_sort", P_)},
+            "rasterize_fwd": {"bound": "alu", "kernel": ras_name, "unit": "TFLOP/s", "peak": VALU_FP32_PEAK_TFLOPS,
+                              "achieved": ras_flops / (ras_ms * 1e-3) / 1e12, "avg_launch_ms": ras_ms,
+                              "algorithmic_flops_per_launch": ras_flops, "evals_per_launch": float(np.mean(c_eval)),
+                              "flops_per_eval": FLOPS_PER_EVAL, "frac_of_unpacked_fp32_ceiling": None,
+                              "traffic": measured_traffic(ras_name, P_)},
+        }
+        for r in st.values():
+            r["frac"] = r["achieved"] / r["peak"]
+            r["views_per_launch"] = P_
+        st["rasterize_fwd"]["frac_of_unpacked_fp32_ceiling"] = \
+            st["rasterize_fwd"]["achieved"] / VALU_FP32_UNPACKED_TFLOPS
+        return st, max(st, key=lambda k: st[k]["avg_launch_ms"]), kms
+
+    def copy_calibration():
+        # a plain 512 MiB device copy, for scaling the HBM counters of a profiler run
+        src = torch.ones(128 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    def copy_rate_gbs():
+        # measured ceiling beside the published one: a plain 512 MiB device-to-device copy
+        # (read + write bytes over its HIP-event time, best of five)
+        src = torch.ones(128 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        best = float("inf")
+        with torch.cuda.stream(stream):
+            for _ in range(6):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                dst.copy_(src)
+                e1.record(stream)
+                e1.synchronize()
+                best = min(best, e0.elapsed_time(e1))
+        del src, dst
+        return 2.0 * (512 << 20) / (best * 1e-3) / 1e9
+
+    if args.stages_only:
+        st, dom, _ = time_stages(max(1, args.views_per_call))
+        if args.copy_calibration:
+            copy_calibration()
+        print(json.dumps({"stages_only": True, "roofline": dict(st[dom], stage=dom), "rooflines": st}))
+        return
+
     # ---- HIP graph of one step (all views, one frame each) ---------------------------
     # one frame at a time on one stream ...
     graph = graph_of(torch, lod_step(frame), stream)
@@ -291,47 +430,69 @@ def workload_lod(args, torch, gs, render, synth):
     if frame.host_counts()["flags"]:
         raise RuntimeError("capacity flag raised during the timed frames: %s" % frame.host_counts())
     log("LoD graph, one frame in flight (%s): %.3f ms/step, %.1f FPS" % (tuning_desc, 1e3 * seq_s, fps_seq))
-    # ... and K frames in flight: frame v on stream v mod K with its own buffers, so the
-    # latency-bound binning of one frame overlaps the compositing of another
-    if K > 1:
-        flight = [frame] + [new_frame(tun.tile_w, tun.tile_h, tun.batch, tun.flags) for _ in range(K - 1)]
+    # ... and K calls in flight, each rendering P views (one batched call: one record space,
+    # one binning, one compositing launch over all P views' tiles): call c takes views
+    # [cP, (c+1)P) on stream c mod K with its own buffers, so the latency-bound binning of
+    # one call overlaps the compositing of another and is shared by P views
+    def in_flight_fps(K_, P_):
+        if V % P_:
+            raise ValueError("views per call must divide the %d views" % V)
+        K_ = min(K_, V // P_)  # no more buffers than calls
+        if K_ == 1 and P_ == 1:
+            return seq_s
+        flight = [frame if P_ == 1 and k == 0 else
+                  render.Frame(scene.n_blocks, P_, W, H, P_ * rc, P_ * frame.pair_capacity,
+                               gs.tuning_struct(tun.tile_w, tun.tile_h, tun.batch, tun.flags), device=dev)
+                  for k in range(K_)]
+        calls = [cams_all[c * P_ * 152:(c + 1) * P_ * 152] for c in range(V // P_)]
+        for c in range(V // P_):
+            render.render_frame(scene, flight[c % K_], calls[c], thresholds=thresholds)
 
         def pipelined_step():
             cur = torch.cuda.current_stream()
-            for s2 in side:
+            for s2 in side[:K_ - 1]:
                 s2.wait_stream(cur)
-            streams = [cur] + side
-            for v in range(V):
-                with torch.cuda.stream(streams[v % K]):
-                    render.render_frame(scene, flight[v % K], cam_slot[v], thresholds=thresholds, check=False)
-            for s2 in side:
+            streams = [cur] + side[:K_ - 1]
+            for c in range(V // P_):
+                with torch.cuda.stream(streams[c % K_]):
+                    render.render_frame(scene, flight[c % K_], calls[c], thresholds=thresholds, check=False)
+            for s2 in side[:K_ - 1]:
                 cur.wait_stream(s2)
 
         graph = graph_of(torch, pipelined_step, stream)
-        step_s = timed_replays(torch, graph, args.steps, args.warmup)
+        t = timed_replays(torch, graph, args.steps, args.warmup)
         del graph
         for f in flight:
             if f.host_counts()["flags"]:
                 raise RuntimeError("capacity flag raised during the timed frames: %s" % f.host_counts())
-        # every in-flight frame buffer holds the same images as the one-at-a-time path
-        for k in range(1, K):
-            v = (V - 1) - ((V - 1 - k) % K)  # last view rendered into buffer k
-            render.render_frame(scene, frame, cam_slot[v], thresholds=thresholds)
-            if not torch.equal(frame.rgb, flight[k].rgb):
-                raise RuntimeError("in-flight frame %d differs from the sequential render of view %d" % (k, v))
+        # every buffer holds the same images as the one-at-a-time path (its last call's views)
+        for k in range(K_):
+            c = (V // P_ - 1) - ((V // P_ - 1 - k) % K_)
+            for p_ in range(P_):
+                render.render_frame(scene, frame, cam_slot[c * P_ + p_], thresholds=thresholds)
+                if not torch.equal(frame.rgb[0], flight[k].rgb[p_]):
+                    raise RuntimeError("in-flight buffer %d differs from the sequential render of view %d" %
+                                       (k, c * P_ + p_))
         del flight
-    else:
-        step_s = seq_s
+        return t
+
+    P = max(1, args.views_per_call)
+    if args.flight_sweep:
+        sweep = {}
+        for K_ in (int(x) for x in args.sweep_calls.split(",")):
+            for P_ in (int(x) for x in args.sweep_views.split(",")):
+                if K_ - 1 <= len(side) and V % P_ == 0:
+                    t = in_flight_fps(K_, P_)
+                    sweep["%dx%d" % (K_, P_)] = V / t
+                    log("calls in flight %d x views per call %d: %.1f FPS" % (K_, P_, V / t))
+        print(json.dumps({"flight_sweep": sweep}))
+        return None
+    step_s = in_flight_fps(K, P)
     ms_per_step = 1e3 * step_s
     fps = V / step_s
-    log("LoD graph, %d frames in flight: %.3f ms/step, %.1f FPS" % (K, ms_per_step, fps))
+    log("LoD graph, %d calls in flight x %d views per call: %.3f ms/step, %.1f FPS" % (K, P, ms_per_step, fps))
     if args.copy_calibration:
-        src = torch.ones(128 << 20, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_calibration()
     if args.frames_only:
         print(json.dumps({"metric": "FPS", "value": fps, "fps_one_frame_in_flight": fps_seq,
                           "ms_per_step": ms_per_step, "tuning": tuning_desc,
@@ -368,73 +529,20 @@ def workload_lod(args, torch, gs, render, synth):
             per_group["%dm_pitch%d" % (h, p)] = {"fps_mean": float(sel.mean()), "fps_min": float(sel.min()),
                                                  "views": int(sel.size)}
 
-    # ---- stages timed with HIP events on the stream they run on ---------------------
-    kern_ms = {"preprocess": [], "rasterize_fwd": [], "bin_sort": []}
-    blocks = scene.blocks_struct()
-    with torch.cuda.stream(stream):
-        for v in range(V):
-            c = cam_slot[v]
-            gs.lod_select(blocks, thresholds, gs.GS_LOD_BLOCKWISE, c, 1, frame.level, frame.offsets, frame.counts,
-                          stream)
-            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-            ev[0].record(stream)
-            gs.preprocess([lv.struct() for lv in scene.levels], blocks, frame.level, frame.offsets, c, 1, W, H, 3,
-                          frame.tuning, frame.record_capacity, frame.records, frame.depth_keys, frame.tiles_touched,
-                          frame.counts, stream)
-            ev[1].record(stream)
-            gs.bin_sort(frame.records, frame.depth_keys, frame.tiles_touched, 1, W, H, frame.tuning,
-                        frame.record_capacity, frame.pair_capacity, frame.pair_tiles, frame.pair_records,
-                        frame.tile_ranges, frame.counts, frame.sort_ws, stream, frame.tile_queue)
-            ev[2].record(stream)
-            gs.rasterize_fwd(frame.records, frame.pair_records, frame.tile_ranges, 1, W, H, (0.0, 0.0, 0.0),
-                             frame.tuning, frame.rgb, frame.T, frame.n_last, stream, frame.tile_queue)
-            ev[3].record(stream)
-            ev[3].synchronize()
-            kern_ms["preprocess"].append(ev[0].elapsed_time(ev[1]))
-            kern_ms["bin_sort"].append(ev[1].elapsed_time(ev[2]))
-            kern_ms["rasterize_fwd"].append(ev[2].elapsed_time(ev[3]))
-    pre_ms = float(np.mean(kern_ms["preprocess"]))
-    bin_ms = float(np.mean(kern_ms["bin_sort"]))
-    ras_ms = float(np.mean(kern_ms["rasterize_fwd"]))
-    log("stage ms (mean over views): preprocess %.4f, bin_sort %.4f, rasterize_fwd %.4f" % (pre_ms, bin_ms, ras_ms))
-    P = float(W * H)
-    # preprocess: 12 B centre + 8 B (depth key, tiles touched) per selected record; 224 B (rotation,
-    # scale, opacity, SH) read + 48 B record written per visible record
-    pre_bytes = float(np.mean(20.0 * n_sel + 272.0 * n_vis))
-    # binning, one-pass lower bound: pairs written once and read once (24 B per pair) + the range scan (8 B)
-    bin_bytes = float(np.mean(32.0 * n_pairs))
-    # forward compositing: 15 operations per evaluated entry (14 FP32 + one exponential)
-    ras_flops = float(np.mean(n_eval)) * FLOPS_PER_EVAL
-    stage = {
-        "preprocess": {"bound": "hbm", "kernel": "preprocess_kernel", "unit": "GB/s", "peak": HBM_PEAK_GBS,
-                       "achieved": pre_bytes / (pre_ms * 1e-3) / 1e9, "avg_launch_ms": pre_ms,
-                       "algorithmic_bytes_per_launch": pre_bytes,
-                       "traffic": measured_traffic("preprocess_kernel")},
-        "bin_sort": {"bound": "hbm", "kernel": "bin_sort stage (%s)" % BIN_SORT_KERNELS, "unit": "GB/s",
-                     "peak": HBM_PEAK_GBS, "achieved": bin_bytes / (bin_ms * 1e-3) / 1e9, "avg_launch_ms": bin_ms,
-                     "algorithmic_bytes_per_launch": bin_bytes, "bytes_per_pair": 32,
-                     "traffic": measured_traffic("bin_sort")},
-        "rasterize_fwd": {"bound": "alu",
-                          "kernel": "raster_fwd_kernel<%d,%d,%d>" % (tun.tile_w, tun.tile_h, tun.batch),
-                          "unit": "TFLOP/s", "peak": VALU_FP32_PEAK_TFLOPS,
-                          "achieved": ras_flops / (ras_ms * 1e-3) / 1e12, "avg_launch_ms": ras_ms,
-                          "algorithmic_flops_per_launch": ras_flops, "evals_per_launch": float(np.mean(n_eval)),
-                          "flops_per_eval": FLOPS_PER_EVAL,
-                          "frac_of_unpacked_fp32_ceiling": None,
-                          "traffic": measured_traffic("raster_fwd_kernel<%d,%d,%d>" % (tun.tile_w, tun.tile_h,
-                                                                                         tun.batch))},
-    }
-    for k, r in stage.items():
-        r["frac"] = r["achieved"] / r["peak"]
-    stage["rasterize_fwd"]["frac_of_unpacked_fp32_ceiling"] = \
-        stage["rasterize_fwd"]["achieved"] / VALU_FP32_UNPACKED_TFLOPS
-    dominant = max(stage, key=lambda k: stage[k]["avg_launch_ms"])
+    stage, dominant, kern_ms = time_stages(P)
     # whole frame against HBM: the algorithmic bytes of one forward frame (N_sel centres and
     # tiles touched, N_vis parameters and records, pairs written/read/scanned/gathered, image, T, n_last)
-    b_fwd = float(np.mean(24.0 * n_sel + 276.0 * n_vis + 72.0 * n_pairs)) + 20.0 * P
+    b_fwd = float(np.mean(24.0 * n_sel + 276.0 * n_vis + 72.0 * n_pairs)) + 20.0 * W * H
+    copy_gbs = copy_rate_gbs()
+    log("device copy: %.0f GB/s (read + write)" % copy_gbs)
+    for r in stage.values():
+        if r["bound"] == "hbm":
+            r["frac_of_measured_copy"] = r["achieved"] / copy_gbs
     frame_hbm = {"bytes_per_frame": b_fwd,
                  "frac_one_frame_in_flight": b_fwd * fps_seq / (HBM_PEAK_GBS * 1e9),
-                 "frac_frames_in_flight": b_fwd * fps / (HBM_PEAK_GBS * 1e9)}
+                 "frac_frames_in_flight": b_fwd * fps / (HBM_PEAK_GBS * 1e9),
+                 "measured_copy_gbs": copy_gbs,
+                 "frac_frames_in_flight_of_measured_copy": b_fwd * fps / (copy_gbs * 1e9)}
 
     out_extra = {}
     # ---- plain comparator: LoD off, every block at the finest level, eager, 16x16 ----
@@ -523,7 +631,8 @@ def workload_lod(args, torch, gs, render, synth):
                                (args.n, n_stored, V),
                    "n_gaussians": args.n, "width": W, "height": H, "views_per_step": V,
                    "distance_thresholds_m": list(thresholds),
-                   "launch": "hipGraph of the 48 frames, %d in flight on %d streams" % (K, K),
+                   "launch": "hipGraph of the %d views: %d calls in flight on %d streams, %d views per call" %
+                             (V, K, K, P),
                    "tuning": tuning_desc},
         "fps_one_frame_in_flight": fps_seq,
         "fps_mean_view": float(fps_views.mean()),
@@ -536,7 +645,8 @@ def workload_lod(args, torch, gs, render, synth):
         "rooflines": stage,
         "frame_hbm": frame_hbm,
         "per_height_pitch": per_group,
-        "kernel_ms": {k: float(np.mean(v)) for k, v in kern_ms.items()},
+        "stage_ms_per_call": {k: float(np.mean(v)) for k, v in kern_ms.items()},
+        "stage_ms_per_view": {k: float(np.mean(v)) / P for k, v in kern_ms.items()},
         "cpu_baseline": cpu,
     }
     if tune_report:
