@@ -189,8 +189,11 @@ __global__ void __launch_bounds__(kThreads) radix_pass_kernel(
     for (int k = 0; k < kRadixItems; ++k) {
       const int li = slice + k * 64 + lane;
       if constexpr (COMPACT) {
-        valid[k] = li < tile_n && pp.tiles_touched[tile_base + li] > 0;
-        key[k] = valid[k] ? keys_in[tile_base + li] : 0u;
+        // both loads issued together (a culled record's key is read and dropped)
+        const bool in_tile = li < tile_n;
+        const int32_t tt = in_tile ? pp.tiles_touched[tile_base + li] : 0;
+        key[k] = in_tile ? keys_in[tile_base + li] : 0u;
+        valid[k] = tt > 0;
         val[k] = (uint32_t)(tile_base + li);
       } else {
         valid[k] = li < tile_n;
@@ -210,6 +213,10 @@ __global__ void __launch_bounds__(kThreads) radix_pass_kernel(
     for (int k = 0; k < kRadixItems; ++k) {
       const uint32_t d = (key[k] >> shift) & 255u;
       uint64_t peers = __ballot(valid[k]);
+      if (peers == 0) {  // no valid item in the wave (the compacting pass: a run of culled records)
+        rank[k] = 0;
+        continue;
+      }
 #pragma unroll
       for (int bit = 0; bit < 8; ++bit) {
         const bool b = (d >> bit) & 1u;

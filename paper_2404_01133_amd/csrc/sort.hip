@@ -132,6 +132,7 @@ __global__ void __launch_bounds__(kThreads) depth_hist_kernel(const int32_t* __r
       const int64_t idx = b * per_block + (int64_t)k * kThreads + threadIdx.x;  // coalesced
       const int32_t tt = idx < n ? tiles_touched[idx] : 0;
       const bool vis = tt > 0;
+      if (__ballot(vis) == 0) continue;  // a wave of culled records (neighbours are culled together)
       const uint32_t key = vis ? depth_keys[idx] : 0u;
       if (vis) {
         atomicAdd(&s_hist[0][key & 255u], 1u);
