@@ -244,7 +244,10 @@ gs_status gs_preprocess(const gs_gaussians* levels, const gs_blocks* blocks, con
  * sort (depth digits on the visible records, tile digits on the pairs), so
  * ties go to the lower record index.
  * Inputs: records, depth_keys and tiles_touched as written by gs_preprocess
- * (record_capacity entries; counts[GS_COUNT_RECORDS] of them are read).
+ * with the same width, height and tile shape (record_capacity entries;
+ * counts[GS_COUNT_RECORDS] of them are read; tiles_touched must equal the
+ * tiles under each record's footprint, which the binning also derives from the
+ * record itself).
  * Writes counts[GS_COUNT_VISIBLE] and counts[GS_COUNT_PAIRS]; raises
  * GS_FLAG_PAIRS (pairs beyond pair_capacity are dropped, the frame is
  * invalid) and GS_FLAG_WAIT.  Errors: GS_ERR_INVALID_ARG for NULL pointers,

@@ -34,6 +34,7 @@ struct alignas(16) Record {
   float dv;
 };
 static_assert(sizeof(Record) == 48, "record layout");
+constexpr int kRecordWords = sizeof(Record) / 16;  // 16-byte words per record; the first is du, view, px, py
 
 constexpr uint32_t kCulledKey = 0xFFFFFFFFu;
 

@@ -82,6 +82,12 @@ __device__ __forceinline__ uint64_t block_excl_scan64(uint64_t x, uint64_t* s_wa
 //                 look-back word carries both the record count (bits 32..61) and
 //                 the pair sum (bits 0..31, saturating).  whist holds `copies`
 //                 partial histograms of tiles_touched by this digit (u64).
+//                 A record's tile rectangle comes from its footprint word (the
+//                 first 16 bytes of its record, gathered once here): the pass
+//                 also writes, in the sorted order, its first tile id (view *
+//                 tiles per view + row * tiles_x + column) and its extent in
+//                 tiles (columns | rows << 16), so the emission reads them in
+//                 order instead of gathering every record again.
 //   kPassCompact  the least significant depth pass: reads every selected record's
 //                 depth key, keeps those with tiles_touched > 0 (values = record
 //                 index, in index order) and writes the visible count.
@@ -91,7 +97,12 @@ constexpr int kPassPlain = 0;
 constexpr int kPassPairs = 1;
 constexpr int kPassCompact = 2;
 struct PairPass {
-  const int32_t* tiles_touched;
+  const int32_t* tiles_touched;  // kPassCompact
+  const uint4* rec_words;        // kPassPairs: records as 16-byte words, kRecordWords per record
+  int tw_shift, th_shift;        // log2 of the tile shape (every supported shape is a power of two)
+  int tiles_x, tiles_per_view;
+  uint32_t* tile_first;          // [visible] first tile id, sorted order
+  uint32_t* tile_extent;         // [visible] columns | rows << 16, sorted order
   const uint64_t* whist;
   int copies;
   uint64_t* status;  // [radix tiles][256]
@@ -201,11 +212,19 @@ __global__ void __launch_bounds__(kThreads) radix_pass_kernel(
         val[k] = valid[k] ? vals_in[tile_base + li] : 0u;
       }
     }
+    uint32_t tfirst[PAIRS ? kRadixItems : 1], textent[PAIRS ? kRadixItems : 1];
     if constexpr (PAIRS) {
 #pragma unroll
       for (int k = 0; k < kRadixItems; ++k) {
-        const int32_t t = valid[k] ? pp.tiles_touched[val[k]] : 0;
-        ttv[k] = t > 0 ? (uint32_t)t : 0u;
+        uint4 w0 = make_uint4(0u, 0u, 0u, 0u);
+        if (valid[k]) w0 = pp.rec_words[(size_t)kRecordWords * val[k]];
+        const uint32_t i0 = w0.z & 0xFFFFu, i1 = i0 + (w0.z >> 16);
+        const uint32_t j0 = w0.w & 0xFFFFu, j1 = j0 + (w0.w >> 16);
+        const uint32_t tx0 = i0 >> pp.tw_shift, ty0 = j0 >> pp.th_shift;
+        const uint32_t ntx = (i1 >> pp.tw_shift) - tx0 + 1u, nty = (j1 >> pp.th_shift) - ty0 + 1u;
+        ttv[k] = valid[k] ? ntx * nty : 0u;
+        tfirst[k] = w0.y * (uint32_t)pp.tiles_per_view + ty0 * (uint32_t)pp.tiles_x + tx0;
+        textent[k] = ntx | (nty << 16);
       }
     }
     // stable rank inside the wave: items in order k, lanes in order within an item
@@ -369,6 +388,20 @@ __global__ void __launch_bounds__(kThreads) radix_pass_kernel(
     }
     s_digit_base[d] = s_goff[d] + excl;
     __syncthreads();
+    if constexpr (PAIRS) {
+      // each item's tile rectangle straight to its sorted slot: for one item k, the
+      // lanes of a digit land on consecutive slots (and the top depth digit takes
+      // few values), so these stores stay close to contiguous
+#pragma unroll
+      for (int k = 0; k < kRadixItems; ++k) {
+        if (valid[k]) {
+          const uint32_t dd = (key[k] >> shift) & 255u;
+          const uint32_t out = s_digit_base[dd] + s_wave_hist[wid][dd] + rank[k];
+          pp.tile_first[out] = tfirst[k];
+          pp.tile_extent[out] = textent[k];
+        }
+      }
+    }
     // local scatter by digit, then coalesced write-out
 #pragma unroll
     for (int k = 0; k < kRadixItems; ++k) {

@@ -156,7 +156,8 @@ __global__ void __launch_bounds__(kThreads) depth_hist_kernel(const int32_t* __r
 // ---------------------------------------------------------------------------
 // 3. pair emission
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) emit_kernel(const Record* __restrict__ records,
+__global__ void __launch_bounds__(kThreads) emit_kernel(const uint32_t* __restrict__ tile_first,
+                                                        const uint32_t* __restrict__ tile_extent,
                                                         const uint32_t* __restrict__ sorted_records,
                                                         const uint32_t* __restrict__ pair_off, int64_t cap,
                                                         const int64_t* counts, int64_t pair_cap, int tw, int th,
@@ -182,22 +183,19 @@ __global__ void __launch_bounds__(kThreads) emit_kernel(const Record* __restrict
   __syncthreads();
   const int64_t n = count_clamped(counts, GS_COUNT_VISIBLE, cap);
   for (int64_t j = gtid; j < n; j += stride) {
-    const uint32_t rid = sorted_records[j];
-    const uint4 w0 = *reinterpret_cast<const uint4*>(&records[rid]);
-    const uint32_t view = w0.y;
-    const int i0 = (int)(w0.z & 0xFFFFu), i1 = i0 + (int)(w0.z >> 16);
-    const int j0 = (int)(w0.w & 0xFFFFu), j1 = j0 + (int)(w0.w >> 16);
-    const int ntx = i1 / tw - i0 / tw + 1, nty = j1 / th - j0 / th + 1;
+    // the record's tile rectangle, written in this (depth) order by the last depth pass
+    const uint32_t first = tile_first[j], ext = tile_extent[j];
+    const int ntx = (int)(ext & 0xFFFFu), nty = (int)(ext >> 16);
     if (ntx * nty > kBigFootprint) {  // many tiles: left to emit_big_kernel
       big_list[atomicAdd(big_count, 1u)] = (uint32_t)j;
       continue;
     }
+    const uint32_t rid = sorted_records[j];
     int64_t o = pair_off[j];
-    const uint32_t vbase = view * (uint32_t)tiles_per_view;
-    for (int ty = j0 / th; ty <= j1 / th; ++ty)
-      for (int tx = i0 / tw; tx <= i1 / tw; ++tx) {
+    for (int ty = 0; ty < nty; ++ty)
+      for (int tx = 0; tx < ntx; ++tx) {
         if (o < pair_cap) {
-          const uint32_t key = vbase + (uint32_t)(ty * tiles_x_n + tx);
+          const uint32_t key = first + (uint32_t)(ty * tiles_x_n + tx);
           out_tiles[o] = key;
           out_records[o] = rid;
           for (int p = 0; p < tpasses; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
@@ -217,7 +215,8 @@ __global__ void __launch_bounds__(kThreads) emit_kernel(const Record* __restrict
 // Records whose footprint covers many tiles (a Gaussian close to the camera):
 // one work-group per record, its tiles strided over the threads, written to
 // the same slots (row-major tile order) the serial loop would use.
-__global__ void __launch_bounds__(kThreads) emit_big_kernel(const Record* __restrict__ records,
+__global__ void __launch_bounds__(kThreads) emit_big_kernel(const uint32_t* __restrict__ tile_first,
+                                                            const uint32_t* __restrict__ tile_extent,
                                                             const uint32_t* __restrict__ sorted_records,
                                                             const uint32_t* __restrict__ pair_off,
                                                             const uint32_t* __restrict__ big_list,
@@ -246,19 +245,14 @@ __global__ void __launch_bounds__(kThreads) emit_big_kernel(const Record* __rest
   for (uint32_t k = blockIdx.x; k < nbig; k += gridDim.x) {
     const uint32_t j = big_list[k];
     const uint32_t rid = sorted_records[j];
-    const uint4 w0 = *reinterpret_cast<const uint4*>(&records[rid]);
-    const uint32_t view = w0.y;
-    const int i0 = (int)(w0.z & 0xFFFFu), i1 = i0 + (int)(w0.z >> 16);
-    const int j0 = (int)(w0.w & 0xFFFFu), j1 = j0 + (int)(w0.w >> 16);
-    const int tx0 = i0 / tw, ty0 = j0 / th;
-    const int ntx = i1 / tw - tx0 + 1, nty = j1 / th - ty0 + 1;
+    const uint32_t first = tile_first[j], ext = tile_extent[j];
+    const int ntx = (int)(ext & 0xFFFFu), nty = (int)(ext >> 16);
     const int64_t o0 = pair_off[j];
-    const uint32_t vbase = view * (uint32_t)tiles_per_view;
     for (int q = threadIdx.x; q < ntx * nty; q += kThreads) {
       const int64_t o = o0 + q;
       if (o < pair_cap) {
-        const int ty = ty0 + q / ntx, tx = tx0 + q % ntx;
-        const uint32_t key = vbase + (uint32_t)(ty * tiles_x_n + tx);
+        const int ty = q / ntx, tx = q % ntx;
+        const uint32_t key = first + (uint32_t)(ty * tiles_x_n + tx);
         out_tiles[o] = key;
         out_records[o] = rid;
         for (int p = 0; p < tpasses; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
@@ -368,6 +362,8 @@ struct SortWs {
   uint32_t* dvals_b;      // [rc]
   uint32_t* pair_off;     // [rc]
   uint32_t* big_list;     // [rc] visible records with large footprints
+  uint32_t* tile_extent;  // [rc] tile columns | rows << 16 per visible record, depth order
+                          // (its first tile id goes to dkeys_a, free in the last depth pass)
   uint32_t* ptiles_alt;   // [pc]
   uint32_t* precs_alt;    // [pc]
   uint32_t* fixed;        // counters [64], hist [2][kMaxPasses][256], queue words, partial tile hists
@@ -395,6 +391,7 @@ SortWs sort_ws_layout(char* base, int64_t rc, int64_t pc) {
   w.dvals_b = (uint32_t*)take(4 * (size_t)rc);
   w.pair_off = (uint32_t*)take(4 * (size_t)rc);
   w.big_list = (uint32_t*)take(4 * (size_t)rc);
+  w.tile_extent = (uint32_t*)take(4 * (size_t)rc);
   w.ptiles_alt = (uint32_t*)take(4 * (size_t)pc);
   w.precs_alt = (uint32_t*)take(4 * (size_t)pc);
   w.fixed = (uint32_t*)take(4 * (size_t)kFixedWords);
@@ -470,9 +467,11 @@ extern "C" gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys
   //    the visible records (index order within a digit) and writes counts[GS_COUNT_VISIBLE]; the
   //    last also writes the pair offsets (exclusive prefix of tiles_touched in depth order) and
   //    counts[GS_COUNT_PAIRS].  Each pass adds the partial copies of its digit histogram.
+  const int tw_shift = __builtin_ctz((unsigned)tw), th_shift = __builtin_ctz((unsigned)th);  // powers of two
   auto extra = [&](int p, const uint64_t* wh, uint64_t* pst, uint32_t* poff) {
-    return PairPass{tiles_touched, wh, kDepthHistCopies, pst, poff, pair_capacity, dhist_extra + p * kRadix,
-                    kDepthHistCopies - 1, kDepthHistWords};
+    return PairPass{tiles_touched, (const uint4*)records, tw_shift, th_shift, tx_n, (int)tiles_per_view,
+                    w.dkeys_a, w.tile_extent, wh, kDepthHistCopies, pst, poff, pair_capacity,
+                    dhist_extra + p * kRadix, kDepthHistCopies - 1, kDepthHistWords};
   };
   hipLaunchKernelGGL((radix_pass_kernel<kPassCompact>), persistent_radix(record_capacity), blk, 0, s, depth_keys,
                      nullptr, w.dkeys_b, w.dvals_b, counts, GS_COUNT_RECORDS, record_capacity, 0, dhist,
@@ -495,10 +494,10 @@ extern "C" gs_status gs_bin_sort(const void* records, const uint32_t* depth_keys
   uint32_t* em_recs = (tpasses % 2 == 0) ? pair_records : w.precs_alt;
   uint32_t* big_count = counters + 32;
   uint32_t* thist_extra = w.fixed + kTileExtraAt;
-  hipLaunchKernelGGL(emit_kernel, grid_for(record_capacity), blk, 0, s, (const Record*)records, w.dvals_a, w.pair_off,
+  hipLaunchKernelGGL(emit_kernel, grid_for(record_capacity), blk, 0, s, w.dkeys_a, w.tile_extent, w.dvals_a, w.pair_off,
                      record_capacity, counts, pair_capacity, tw, th, tx_n, (int)tiles_per_view, em_tiles, em_recs,
                      tpasses, thist, w.pstatus, tile_ranges, 2 * n_tile_ids, w.big_list, big_count, thist_extra);
-  hipLaunchKernelGGL(emit_big_kernel, dim3(256), blk, 0, s, (const Record*)records, w.dvals_a, w.pair_off, w.big_list,
+  hipLaunchKernelGGL(emit_big_kernel, dim3(256), blk, 0, s, w.dkeys_a, w.tile_extent, w.dvals_a, w.pair_off, w.big_list,
                      big_count, pair_capacity, tw, th, tx_n, (int)tiles_per_view, em_tiles, em_recs, tpasses, thist,
                      thist_extra);
   GS_LAUNCH_CHECK();
