@@ -60,10 +60,10 @@ FLOPS_PER_EVAL = 15
 # `bench.py --stages-only` scaled by a 512 MiB copy, for launches of the given views per call, valid for
 # the kernel sources with the given fingerprint only
 MEASURED_TRAFFIC = {
-    "preprocess_kernel": (("preprocess.hip", "project.h", "gs_common.h"), "c26d8eaed24310d8", 8, 1652.82e6),
-    "raster_fwd_kernel<16,16,256>": (("raster.hip", "tile.h", "project.h", "gs_common.h"), "fb896b71fa3cb949", 8,
+    "preprocess_kernel": (("preprocess.hip", "project.h", "gs_common.h"), "3073003407bccdee", 8, 1652.76e6),
+    "raster_fwd_kernel<16,16,256>": (("raster.hip", "tile.h", "project.h", "gs_common.h"), "bfe2dbdee6dbb606", 8,
                                      667.93e6),
-    "bin_sort": (("sort.hip", "radix.h", "scan.h", "gs_common.h"), "529be3f41e4e5ec9", 8, 1535.73e6),
+    "bin_sort": (("sort.hip", "radix.h", "scan.h", "gs_common.h"), "4bfc8bb191b27445", 8, 1409.31e6),
 }
 
 
