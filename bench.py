@@ -63,7 +63,7 @@ MEASURED_TRAFFIC = {
     "preprocess_kernel": (("preprocess.hip", "project.h", "gs_common.h"), "3073003407bccdee", 8, 1652.76e6),
     "raster_fwd_kernel<16,16,256>": (("raster.hip", "tile.h", "project.h", "gs_common.h"), "bfe2dbdee6dbb606", 8,
                                      667.93e6),
-    "bin_sort": (("sort.hip", "radix.h", "scan.h", "gs_common.h"), "4bfc8bb191b27445", 8, 1409.31e6),
+    "bin_sort": (("sort.hip", "radix.h", "scan.h", "gs_common.h"), "7c172e1976d40684", 8, 1409.31e6),
 }
 
 

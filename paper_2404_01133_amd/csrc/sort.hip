@@ -8,10 +8,12 @@
 //                pairs (tiles_touched) per top digit
 //   2. 4 passes  stable radix sort by the 32-bit depth key (ties keep record order);
 //                the first one reads every selected record and keeps the visible
-//                ones (compaction), the last one also writes the pair offsets, the
-//                exclusive prefix of tiles_touched in depth order (its look-back
-//                carries both sums)
-//   3. emit      one (view*tiles + tile, record) pair per tile of each footprint
+//                ones (compaction), the last one gathers each record's footprint
+//                word, writes its tile rectangle (first tile id, extent) and the
+//                pair offsets, the exclusive prefix of the tile counts in depth
+//                order (its look-back carries both sums)
+//   3. emit      one (view*tiles + tile, record) pair per tile of each footprint,
+//                reading the rectangles in depth order
 //   4. passes    stable radix sort by tile id (ceil(bits / 8) passes)
 //   5. ranges    [start, end) of every tile
 // The result equals a sort by (tile, depth, record id).
@@ -43,10 +45,6 @@ constexpr int kBigFootprint = 16;  // records touching more tiles are emitted co
 constexpr int kTileHistCopies = 8;
 constexpr int64_t kTileHistWords = kMaxPasses * kRadix;  // one copy
 
-// ---------------------------------------------------------------------------
-// zero fill of the small fixed state (counters, histograms); the look-back
-// words of the pair-offset scan and the depth passes are cleared by
-// compact_write_kernel, sized by the visible count
 // ---------------------------------------------------------------------------
 // zero fill of the small fixed state (counters, histograms) and of the look-back
 // words of the four depth passes, sized by the selected records (the compacting
@@ -346,7 +344,7 @@ __global__ void queue_scatter_kernel(const uint32_t* __restrict__ ranges, int64_
 // ---------------------------------------------------------------------------
 // tile counters [64], depth + tile digit histograms [2][kMaxPasses][256], queue histogram and cursors
 // [2][40], partial tile-digit histograms of emit_kernel [kTileHistCopies - 1][kMaxPasses][256], partial
-// depth-digit histograms of compact_count_kernel [kDepthHistCopies - 1][4][256]
+// depth-digit histograms of depth_hist_kernel [kDepthHistCopies - 1][4][256]
 constexpr int64_t kQueueWords = 2 * 40;
 constexpr int64_t kTileExtraAt = 64 + 2 * kMaxPasses * kRadix + kQueueWords;
 constexpr int64_t kDepthExtraAt = kTileExtraAt + (kTileHistCopies - 1) * kTileHistWords;
