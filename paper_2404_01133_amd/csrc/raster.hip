@@ -79,7 +79,7 @@ __device__ __forceinline__ void raster_fwd_tile(const TileArgs& ta, FwdLds<TW, T
     const int max_cnt = cnt.max();
     const int my_cnt = cnt.of(qb.g);
     const int base_idx = (int)(b - start);
-    int last_k = -1;  // batch index of the last entry used in this batch
+    int last_k = -1;  // 16 x the batch index of the last entry used in this batch
     auto blend = [&](int k, bool valid, float du, const float4& f, const float4& w1, const float4& w2) {
       Eval e;
       const bool in_fp = evaluate_f(fi, fj, f, du, w2.w, w1, e);
@@ -102,20 +102,27 @@ __device__ __forceinline__ void raster_fwd_tile(const TileArgs& ta, FwdLds<TW, T
     // masked into the staged range and not used)
     for (int t = 0; t < max_cnt; t += 4) {
       if (__ballot(!done && t < my_cnt) == 0) break;
+      // byte offsets (index * 16) of the four entries into the staged arrays
       const uint32_t pk = *reinterpret_cast<const uint32_t*>(&my_list[t]);
-      const int k0 = (int)(pk & (BATCH - 1)), k1 = (int)((pk >> 8) & (BATCH - 1));
-      const int k2 = (int)((pk >> 16) & (BATCH - 1)), k3 = (int)((pk >> 24) & (BATCH - 1));
-      const float au = s_w0[k0].x, bu = s_w0[k1].x, cu = s_w0[k2].x, du = s_w0[k3].x;
-      const float4 af = s_f[k0], a1 = s_w1[k0], a2 = s_w2[k0];
-      const float4 bf = s_f[k1], b1 = s_w1[k1], b2 = s_w2[k1];
-      const float4 cf = s_f[k2], c1 = s_w1[k2], c2 = s_w2[k2];
-      const float4 df = s_f[k3], d1 = s_w1[k3], d2 = s_w2[k3];
-      blend(k0, t < my_cnt, au, af, a1, a2);
-      blend(k1, t + 1 < my_cnt, bu, bf, b1, b2);
-      blend(k2, t + 2 < my_cnt, cu, cf, c1, c2);
-      blend(k3, t + 3 < my_cnt, du, df, d1, d2);
+      const uint32_t o0 = (pk & (BATCH - 1)) << 4, o1 = ((pk >> 8) & (BATCH - 1)) << 4;
+      const uint32_t o2 = ((pk >> 16) & (BATCH - 1)) << 4, o3 = ((pk >> 24) & (BATCH - 1)) << 4;
+      auto at = [](const float4* a, uint32_t o) {
+        return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(a) + o);
+      };
+      auto at_x = [](const float4* a, uint32_t o) {
+        return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(a) + o);
+      };
+      const float au = at_x(s_w0, o0), bu = at_x(s_w0, o1), cu = at_x(s_w0, o2), du = at_x(s_w0, o3);
+      const float4 af = at(s_f, o0), a1 = at(s_w1, o0), a2 = at(s_w2, o0);
+      const float4 bf = at(s_f, o1), b1 = at(s_w1, o1), b2 = at(s_w2, o1);
+      const float4 cf = at(s_f, o2), c1 = at(s_w1, o2), c2 = at(s_w2, o2);
+      const float4 df = at(s_f, o3), d1 = at(s_w1, o3), d2 = at(s_w2, o3);
+      blend((int)o0, t < my_cnt, au, af, a1, a2);
+      blend((int)o1, t + 1 < my_cnt, bu, bf, b1, b2);
+      blend((int)o2, t + 2 < my_cnt, cu, cf, c1, c2);
+      blend((int)o3, t + 3 < my_cnt, du, df, d1, d2);
     }
-    if (last_k >= 0) last = base_idx + last_k + 1;
+    if (last_k >= 0) last = base_idx + (last_k >> 4) + 1;
     __syncthreads();
   }
   if (inside) {
