@@ -60,10 +60,10 @@ FLOPS_PER_EVAL = 15
 # `bench.py --stages-only` scaled by a 512 MiB copy, for launches of the given views per call, valid for
 # the kernel sources with the given fingerprint only
 MEASURED_TRAFFIC = {
-    "preprocess_kernel": (("preprocess.hip", "project.h", "gs_common.h"), "3073003407bccdee", 8, 1652.76e6),
-    "raster_fwd_kernel<16,16,256>": (("raster.hip", "tile.h", "project.h", "gs_common.h"), "bfe2dbdee6dbb606", 8,
-                                     667.93e6),
-    "bin_sort": (("sort.hip", "radix.h", "scan.h", "gs_common.h"), "7c172e1976d40684", 8, 1409.31e6),
+    "preprocess_kernel": (("preprocess.hip", "project.h", "gs_common.h"), "3073003407bccdee", 8, 1652.66e6),
+    "raster_fwd_kernel<16,16,256>": (("raster.hip", "tile.h", "project.h", "gs_common.h"), "11dda1d1949f6681", 8,
+                                     667.94e6),
+    "bin_sort": (("sort.hip", "radix.h", "scan.h", "gs_common.h"), "7c172e1976d40684", 8, 1407.59e6),
 }
 
 
