@@ -47,6 +47,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BIN_SORT_KERNELS = ("clear_front, depth_hist, radix_pass<compact>, 2 radix_pass, radix_pass<pairs>, emit, emit_big, "
                     "2 tile radix_pass, ranges")
+REFINE_KERNELS = "refine_clear, refine_test, refine_scan, refine_views, refine_expand"
 # published FP32 vector peak of MI355X (packed FP32); the library is compiled
 # without packed-FP32 instructions, whose ceiling is half of it: 256 CUs x 64 FMA
 # lanes per clock x 2 flops x 2.4 GHz = 78.6 TFLOP/s
@@ -108,6 +109,8 @@ def parse():
     ap.add_argument("--sweep-views", default="1,2,4,8", help="views per call tried by --flight-sweep")
     ap.add_argument("--flight-sweep", action="store_true",
                     help="time calls in flight 1/2/4/8 x views per call 1/2/4/8 and print them (no headline)")
+    ap.add_argument("--no-refine", action="store_true",
+                    help="time the LoD frames without the chunk refinement (gs_lod_refine)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-pointwise", action="store_true", help="skip the point-wise LoD comparator")
     ap.add_argument("--no-reduced", action="store_true", help="skip the reduced-precision levels variant")
@@ -204,11 +207,13 @@ def workload_lod(args, torch, gs, render, synth):
     cams_all = gs.cameras_to_device(cams, dev)
     cam_slot = [cams_all[v * 152:(v + 1) * 152] for v in range(V)]
     rc = scene.max_records_per_view()
+    # chunk refinement between the selection and the projection (same images, fewer records)
+    refine = not args.no_refine
 
     def new_frame(tw=16, th=16, batch=256, flags=0):
         f = render.Frame(scene.n_blocks, 1, W, H, rc, 1 << 22, gs.tuning_struct(tw, th, batch, flags), device=dev)
         for v in range(V):  # grow the pair capacity to fit every view
-            render.render_frame(scene, f, cam_slot[v], thresholds=thresholds)
+            render.render_frame(scene, f, cam_slot[v], thresholds=thresholds, refine=refine)
         return f
 
     # ---- capacities and per-view statistics from one eager pass ----------------------
@@ -228,6 +233,20 @@ def workload_lod(args, torch, gs, render, synth):
     n_eval = np.array(evals if evals else [0.0], dtype=np.float64)
     log("per view: N_sel mean %.0f (max %d), N_vis mean %.0f, pairs mean %.0f (max %d), evals mean %.0f" %
         (n_sel.mean(), n_sel.max(), n_vis.mean(), n_pairs.mean(), n_pairs.max(), n_eval.mean()))
+    # records left per view after the chunk refinement (the same visible records and pairs)
+    n_rec = n_sel
+    if refine:
+        refd = []
+        for v in range(V):
+            render.render_frame(scene, frame, cam_slot[v], thresholds=thresholds, refine=True)
+            c = frame.host_counts()
+            if (c["visible"], c["pairs"]) != (int(n_vis[v]), int(n_pairs[v])):
+                raise RuntimeError("view %d: refined counts %s differ from the selection's" % (v, c))
+            refd.append(c["records"])
+        n_rec = np.array(refd)
+        log("chunk refinement: records mean %.0f of %.0f selected (%.1f %%), %d chunks" %
+            (n_rec.mean(), n_sel.mean(), 100.0 * n_rec.mean() / max(1.0, n_sel.mean()),
+             int(scene.chunk_off[-1].item())))
     # every stream of the step is made here, before anything else makes streams, so
     # the K streams of the in-flight graph land on distinct hardware queues
     K = max(1, args.in_flight)
@@ -235,7 +254,7 @@ def workload_lod(args, torch, gs, render, synth):
     side = [torch.cuda.Stream() for _ in range(max(K, 8 if args.flight_sweep else 1) - 1)]
 
     def lod_step(f):
-        return lambda: [render.render_frame(scene, f, cam_slot[v], thresholds=thresholds, check=False)
+        return lambda: [render.render_frame(scene, f, cam_slot[v], thresholds=thresholds, check=False, refine=refine)
                         for v in range(V)]
 
     if args.pointwise_only:
@@ -275,7 +294,7 @@ def workload_lod(args, torch, gs, render, synth):
             def images():
                 out = []
                 for v in gate_views:
-                    render.render_frame(scene, f, cam_slot[v], thresholds=thresholds, check=False)
+                    render.render_frame(scene, f, cam_slot[v], thresholds=thresholds, check=False, refine=refine)
                     out.append(f.rgb.clone())
                 return torch.cat(out)
             return lod_step(f), images
@@ -307,13 +326,15 @@ def workload_lod(args, torch, gs, render, synth):
         n_calls = V // P_
         calls = [cams_all[c * P_ * 152:(c + 1) * P_ * 152] for c in range(n_calls)]
         for c in range(n_calls):  # capacities, and the counts of a call equal the sums over its views
-            render.render_frame(scene, sf, calls[c], thresholds=thresholds)
+            render.render_frame(scene, sf, calls[c], thresholds=thresholds, refine=refine)
             hc = sf.host_counts()
-            want = (int(n_sel[c * P_:(c + 1) * P_].sum()), int(n_vis[c * P_:(c + 1) * P_].sum()),
+            want = (int(n_rec[c * P_:(c + 1) * P_].sum()), int(n_vis[c * P_:(c + 1) * P_].sum()),
                     int(n_pairs[c * P_:(c + 1) * P_].sum()))
             if (hc["records"], hc["visible"], hc["pairs"]) != want:
                 raise RuntimeError("call %d counts %s differ from the sums over its views %s" % (c, hc, want))
         kms = {"preprocess": [], "rasterize_fwd": [], "bin_sort": []}
+        if refine:
+            kms["lod_refine"] = []
         blocks = scene.blocks_struct()
         levels = [lv.struct() for lv in scene.levels]
         with torch.cuda.stream(stream):
@@ -322,37 +343,49 @@ def workload_lod(args, torch, gs, render, synth):
                     cc = calls[c]
                     gs.lod_select(blocks, thresholds, gs.GS_LOD_BLOCKWISE, cc, P_, sf.level, sf.offsets, sf.counts,
                                   stream)
-                    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+                    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
                     ev[0].record(stream)
-                    gs.preprocess(levels, blocks, sf.level, sf.offsets, cc, P_, W, H, 3, sf.tuning,
-                                  sf.record_capacity, sf.records, sf.depth_keys, sf.tiles_touched, sf.counts, stream)
+                    if refine:
+                        r = sf.refined
+                        gs.lod_refine(blocks, sf.level, cc, P_, W, H, scene.chunk_off, scene.chunk_bounds,
+                                      scene.max_chunks, sf.record_capacity, r["gather"], r["view_off"], sf.counts,
+                                      r["ws"], stream)
                     ev[1].record(stream)
+                    level, offsets, gather = sf.selection()
+                    gs.preprocess(levels, blocks, level, offsets, cc, P_, W, H, 3, sf.pre_tuning(),
+                                  sf.record_capacity, sf.records, sf.depth_keys, sf.tiles_touched, sf.counts, stream,
+                                  gather=gather)
+                    ev[2].record(stream)
                     gs.bin_sort(sf.records, sf.depth_keys, sf.tiles_touched, P_, W, H, sf.tuning, sf.record_capacity,
                                 sf.pair_capacity, sf.pair_tiles, sf.pair_records, sf.tile_ranges, sf.counts,
                                 sf.sort_ws, stream, sf.tile_queue)
-                    ev[2].record(stream)
+                    ev[3].record(stream)
                     gs.rasterize_fwd(sf.records, sf.pair_records, sf.tile_ranges, P_, W, H, (0.0, 0.0, 0.0),
                                      sf.tuning, sf.rgb, sf.T, sf.n_last, stream, sf.tile_queue)
-                    ev[3].record(stream)
-                    ev[3].synchronize()
+                    ev[4].record(stream)
+                    ev[4].synchronize()
                     if rep:
-                        kms["preprocess"].append(ev[0].elapsed_time(ev[1]))
-                        kms["bin_sort"].append(ev[1].elapsed_time(ev[2]))
-                        kms["rasterize_fwd"].append(ev[2].elapsed_time(ev[3]))
+                        if refine:
+                            kms["lod_refine"].append(ev[0].elapsed_time(ev[1]))
+                        kms["preprocess"].append(ev[1].elapsed_time(ev[2]))
+                        kms["bin_sort"].append(ev[2].elapsed_time(ev[3]))
+                        kms["rasterize_fwd"].append(ev[3].elapsed_time(ev[4]))
         if sf.host_counts()["flags"]:
             raise RuntimeError("capacity flag raised during the stage timing: %s" % sf.host_counts())
         del sf
         pre_ms = float(np.mean(kms["preprocess"]))
         bin_ms = float(np.mean(kms["bin_sort"]))
         ras_ms = float(np.mean(kms["rasterize_fwd"]))
-        log("stage ms per call of %d views (mean over %d calls): preprocess %.4f, bin_sort %.4f, rasterize_fwd %.4f"
-            % (P_, n_calls, pre_ms, bin_ms, ras_ms))
+        ref_ms = float(np.mean(kms["lod_refine"])) if refine else 0.0
+        log("stage ms per call of %d views (mean over %d calls): %spreprocess %.4f, bin_sort %.4f, "
+            "rasterize_fwd %.4f" % (P_, n_calls, "lod_refine %.4f, " % ref_ms if refine else "", pre_ms, bin_ms,
+                                    ras_ms))
         per_call = lambda a: a.reshape(n_calls, P_).sum(axis=1).astype(np.float64)
-        c_sel, c_vis, c_pairs = per_call(n_sel), per_call(n_vis), per_call(n_pairs)
+        c_rec, c_vis, c_pairs = per_call(n_rec), per_call(n_vis), per_call(n_pairs)
         c_eval = per_call(n_eval) if n_eval.size == V else np.zeros(n_calls)
-        # preprocess: 12 B centre + 8 B (depth key, tiles touched) per selected record; 224 B (rotation,
-        # scale, opacity, SH) read + 48 B record written per visible record
-        pre_bytes = float(np.mean(20.0 * c_sel + 272.0 * c_vis))
+        # preprocess: 12 B centre + 8 B (depth key, tiles touched) per record (+ 4 B gather entry after
+        # the refinement); 224 B (rotation, scale, opacity, SH) read + 48 B record written per visible record
+        pre_bytes = float(np.mean((24.0 if refine else 20.0) * c_rec + 272.0 * c_vis))
         # binning, one-pass lower bound: pairs written once and read once (24 B per pair) + the range scan (8 B)
         bin_bytes = float(np.mean(32.0 * c_pairs))
         # what the sort's own passes move at 24 B per element per pass: four depth passes (the first over
@@ -360,7 +393,7 @@ def workload_lod(args, torch, gs, render, synth):
         n_tile_ids = frame.tiles_x * frame.tiles_y * P_
         tbits = max(0, int(n_tile_ids - 1).bit_length())
         tpasses = (tbits + 7) // 8
-        sort_bytes = float(np.mean(24.0 * (c_sel + 3.0 * c_vis + tpasses * c_pairs)))
+        sort_bytes = float(np.mean(24.0 * (c_rec + 3.0 * c_vis + tpasses * c_pairs)))
         # forward compositing: 15 operations per evaluated entry (14 FP32 + one exponential)
         ras_flops = float(np.mean(c_eval)) * FLOPS_PER_EVAL
         ras_name = "raster_fwd_kernel<%d,%d,%d>" % (tun.tile_w, tun.tile_h, tun.batch)
@@ -381,6 +414,15 @@ def workload_lod(args, torch, gs, render, synth):
                               "flops_per_eval": FLOPS_PER_EVAL, "frac_of_unpacked_fp32_ceiling": None,
                               "traffic": measured_traffic(ras_name, P_)},
         }
+        if refine:
+            # per (view, chunk): the 32 B box read, a size written and read twice, an offset written
+            # and read (20 B); 4 B gather entry written per record kept
+            n_chunks = int(scene.chunk_off[-1].item())
+            ref_bytes = float(np.mean(P_ * n_chunks * 52.0 + 4.0 * c_rec))
+            st["lod_refine"] = {"bound": "hbm", "kernel": "lod_refine stage (%s)" % REFINE_KERNELS, "unit": "GB/s",
+                                "peak": HBM_PEAK_GBS, "achieved": ref_bytes / (ref_ms * 1e-3) / 1e9,
+                                "avg_launch_ms": ref_ms, "algorithmic_bytes_per_launch": ref_bytes,
+                                "chunks": n_chunks, "traffic": None}
         for r in st.values():
             r["frac"] = r["achieved"] / r["peak"]
             r["views_per_launch"] = P_
@@ -446,7 +488,7 @@ def workload_lod(args, torch, gs, render, synth):
                   for k in range(K_)]
         calls = [cams_all[c * P_ * 152:(c + 1) * P_ * 152] for c in range(V // P_)]
         for c in range(V // P_):
-            render.render_frame(scene, flight[c % K_], calls[c], thresholds=thresholds)
+            render.render_frame(scene, flight[c % K_], calls[c], thresholds=thresholds, refine=refine)
 
         def pipelined_step():
             cur = torch.cuda.current_stream()
@@ -455,7 +497,8 @@ def workload_lod(args, torch, gs, render, synth):
             streams = [cur] + side[:K_ - 1]
             for c in range(V // P_):
                 with torch.cuda.stream(streams[c % K_]):
-                    render.render_frame(scene, flight[c % K_], calls[c], thresholds=thresholds, check=False)
+                    render.render_frame(scene, flight[c % K_], calls[c], thresholds=thresholds, check=False,
+                                        refine=refine)
             for s2 in side[:K_ - 1]:
                 cur.wait_stream(s2)
 
@@ -465,7 +508,8 @@ def workload_lod(args, torch, gs, render, synth):
         for f in flight:
             if f.host_counts()["flags"]:
                 raise RuntimeError("capacity flag raised during the timed frames: %s" % f.host_counts())
-        # every buffer holds the same images as the one-at-a-time path (its last call's views)
+        # every buffer holds the same images as the one-at-a-time path (its last call's views),
+        # which renders here without the chunk refinement
         for k in range(K_):
             c = (V // P_ - 1) - ((V // P_ - 1 - k) % K_)
             for p_ in range(P_):
@@ -504,7 +548,7 @@ def workload_lod(args, torch, gs, render, synth):
     per_view_ms = []
     for v in range(V):
         gv = graph_of(torch, lambda: render.render_frame(scene, frame, cam_slot[v], thresholds=thresholds,
-                                                         check=False), stream)
+                                                         check=False, refine=refine), stream)
         with torch.cuda.stream(stream):
             for _ in range(2):
                 gv.replay()
@@ -532,7 +576,7 @@ def workload_lod(args, torch, gs, render, synth):
     stage, dominant, kern_ms = time_stages(P)
     # whole frame against HBM: the algorithmic bytes of one forward frame (N_sel centres and
     # tiles touched, N_vis parameters and records, pairs written/read/scanned/gathered, image, T, n_last)
-    b_fwd = float(np.mean(24.0 * n_sel + 276.0 * n_vis + 72.0 * n_pairs)) + 20.0 * W * H
+    b_fwd = float(np.mean((28.0 if refine else 24.0) * n_rec + 276.0 * n_vis + 72.0 * n_pairs)) + 20.0 * W * H
     copy_gbs = copy_rate_gbs()
     log("device copy: %.0f GB/s (read + write)" % copy_gbs)
     for r in stage.values():
@@ -631,8 +675,8 @@ def workload_lod(args, torch, gs, render, synth):
                                (args.n, n_stored, V),
                    "n_gaussians": args.n, "width": W, "height": H, "views_per_step": V,
                    "distance_thresholds_m": list(thresholds),
-                   "launch": "hipGraph of the %d views: %d calls in flight on %d streams, %d views per call" %
-                             (V, K, K, P),
+                   "launch": "hipGraph of the %d views: %d calls in flight on %d streams, %d views per call%s" %
+                             (V, K, K, P, ", chunk refinement" if refine else ""),
                    "tuning": tuning_desc},
         "fps_one_frame_in_flight": fps_seq,
         "fps_mean_view": float(fps_views.mean()),
@@ -641,6 +685,7 @@ def workload_lod(args, torch, gs, render, synth):
         "default_tuning_fps": (V / (default_step_ms * 1e-3)) if default_step_ms else None,
         "gaussians_per_s": float(n_sel.mean() * fps),
         "n_sel_mean": float(n_sel.mean()), "n_vis_mean": float(n_vis.mean()), "pairs_mean": float(n_pairs.mean()),
+        "n_records_mean": float(n_rec.mean()), "chunk_refinement": refine,
         "roofline": dict(stage[dominant], stage=dominant),
         "rooflines": stage,
         "frame_hbm": frame_hbm,

@@ -161,6 +161,11 @@ typedef struct gs_tuning {
  * level must store its blocks in ascending block order); several point-wise
  * views return GS_ERR_UNSUPPORTED.  Ignored by the other entry points. */
 #define GS_TUNE_DETERMINISTIC 4
+/* tuning.flags, gs_preprocess only: the selection is a packed gather list from
+ * gs_lod_refine (entries level << GS_PACKED_INDEX_BITS | index within the level,
+ * offsets [V+1] per view, level unused).  gs_rasterize_bwd returns
+ * GS_ERR_UNSUPPORTED with it (the refinement serves rendering). */
+#define GS_TUNE_PACKED_SELECTION 8
 
 /* Size in bytes of one projected record (an opaque device structure). */
 size_t gs_record_bytes(void);
@@ -216,6 +221,40 @@ gs_status gs_lod_select_points(const gs_gaussians* levels, int32_t n_levels, con
                                const gs_camera* cams, int32_t n_views, int64_t record_capacity, uint32_t* gather,
                                int64_t* offsets, int64_t* counts, void* ws, size_t ws_bytes, void* stream);
 
+/* Chunk refinement of a block-wise selection (between the selection of Sec.
+ * 3.3.2 and the projection of Eq. 1; it changes no rendered value).  Every
+ * (block, level) run is cut into chunks of GS_CHUNK Gaussians in storage order.
+ * gs_chunk_bounds (once per scene) keeps per chunk the box of its centres and
+ * its largest scale component; gs_lod_refine drops, per view, the chunks of the
+ * selected runs that the projection would cull whole (the box behind the near
+ * plane, or its projection farther outside the image than a bound on the
+ * 3-sigma radius of any Gaussian of the chunk) and lists the records left, in
+ * the block-wise order, so gs_preprocess (with GS_TUNE_PACKED_SELECTION), the
+ * binning and the compositing give the same images as with the unrefined
+ * selection.
+ *   gs_chunk_capacity: host helper, entries to allocate for chunk tables (-1 on
+ *     bad arguments); levels host [n_levels]
+ *   gs_chunk_bounds: chunk_off [B*L + 1] int64 (first chunk of run b*L + l, then
+ *     the total), bounds [max_chunks][8] f32 (lo xyz, hi xyz, largest |scale|,
+ *     0); GS_ERR_CAPACITY if max_chunks < gs_chunk_capacity
+ *   gs_lod_refine: level from gs_lod_select; gather [record_capacity] u32
+ *     (level << GS_PACKED_INDEX_BITS | index); view_offsets [V + 1] int64;
+ *     counts[GS_COUNT_RECORDS] = records kept; GS_FLAG_RECORDS is raised (and
+ *     the list truncated) past record_capacity or if the chunk table holds more
+ *     than max_chunks; ws / ws_bytes: at least gs_refine_workspace_bytes(V,
+ *     max_chunks).  Levels must hold fewer than 2^GS_PACKED_INDEX_BITS
+ *     Gaussians. */
+#define GS_CHUNK 4096
+#define GS_PACKED_INDEX_BITS 29
+int64_t gs_chunk_capacity(const gs_gaussians* levels /* host [n_levels] */, const gs_blocks* blocks /* host */);
+gs_status gs_chunk_bounds(const gs_gaussians* levels, const gs_blocks* blocks, int64_t* chunk_off, float* bounds,
+                          int64_t max_chunks, void* stream);
+size_t gs_refine_workspace_bytes(int32_t n_views, int64_t max_chunks);
+gs_status gs_lod_refine(const gs_blocks* blocks, const int8_t* level, const gs_camera* cams, int32_t n_views,
+                        int32_t width, int32_t height, const int64_t* chunk_off, const float* bounds,
+                        int64_t max_chunks, int64_t record_capacity, uint32_t* gather, int64_t* view_offsets,
+                        int64_t* counts, void* ws, size_t ws_bytes, void* stream);
+
 /* Projection of every selected record (Sec. 3.1, "proj" in Eq. 1, following
  * 3DGS): EWA splat of the 3D covariance R S S^T R^T through the pinhole
  * Jacobian (guard band 1.3x the half field of view) with a 0.3 px^2 dilation,
@@ -225,7 +264,9 @@ gs_status gs_lod_select_points(const gs_gaussians* levels, int32_t n_levels, con
  *   levels: host array [n_levels] of device Gaussian sets
  *   selection: gather == NULL: block-wise, from gs_lod_select (level, offsets
  *     [V*B+1]); gather != NULL: point-wise, from gs_lod_select_points (offsets
- *     [V*L+1], level unused and may be NULL, blocks only supplies n_levels)
+ *     [V*L+1], level unused and may be NULL, blocks only supplies n_levels);
+ *     with GS_TUNE_PACKED_SELECTION: refined, from gs_lod_refine (packed
+ *     gather, offsets [V+1])
  *   records [record_capacity] of gs_record_bytes(); depth_keys [record_capacity]
  *   u32 (float bits of depth; 0xFFFFFFFF if culled); tiles_touched
  *   [record_capacity] int32 (0 if culled). */

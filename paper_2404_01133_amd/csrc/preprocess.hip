@@ -29,7 +29,8 @@ struct PreArgs {
   const gs_camera* cams;
   int64_t capacity;
   int32_t B, L, V, W, H, tw, th, sh_degree;
-  int32_t segs;  // segments per view: B (block-wise) or L (point-wise)
+  int32_t segs;    // segments per view: B (block-wise), L (point-wise) or 1 (packed)
+  int32_t packed;  // gather entries are level << GS_PACKED_INDEX_BITS | index (refined selection)
 };
 
 // One record: Gaussian gi of level l, seen by view v, stored at record index g.
@@ -109,7 +110,16 @@ __global__ void __launch_bounds__(kPreThreads) preprocess_kernel(PreArgs a, Reco
     const int v = p / a.segs, b = p - v * a.segs;
     int l;
     int64_t gi;
-    if (a.gather) {
+    if (a.packed) {
+      const uint32_t e = a.gather[g];
+      l = (int)(e >> GS_PACKED_INDEX_BITS);
+      gi = (int64_t)(e & ((1u << GS_PACKED_INDEX_BITS) - 1u));
+      if (l >= a.L || gi >= a.lv[l].n) {  // not a stored Gaussian: nothing to project
+        depth_keys[g] = kCulledKey;
+        tiles_touched[g] = 0;
+        continue;
+      }
+    } else if (a.gather) {
       l = b;
       gi = a.gather[g];
     } else {
@@ -193,7 +203,9 @@ extern "C" gs_status gs_preprocess(const gs_gaussians* levels, const gs_blocks* 
   if (!tile_shape_supported(tuning->tile_w, tuning->tile_h)) return GS_ERR_UNSUPPORTED;
   if (record_capacity < 0 || (record_capacity > 0 && (!records || !depth_keys || !tiles_touched)))
     return GS_ERR_INVALID_ARG;
-  const int32_t segs = gather ? blocks->n_levels : blocks->n_blocks;
+  const bool packed = (tuning->flags & GS_TUNE_PACKED_SELECTION) != 0;
+  if (packed && !gather) return GS_ERR_INVALID_ARG;
+  const int32_t segs = packed ? 1 : gather ? blocks->n_levels : blocks->n_blocks;
   if ((int64_t)n_views * segs > (int64_t)1 << 30) return GS_ERR_INVALID_ARG;
   if (record_capacity >= ((int64_t)1 << 32)) return GS_ERR_INVALID_ARG;  // record ids are u32
   PreArgs a{};
@@ -208,6 +220,7 @@ extern "C" gs_status gs_preprocess(const gs_gaussians* levels, const gs_blocks* 
   a.offsets = offsets;
   a.gather = gather;
   a.segs = segs;
+  a.packed = packed ? 1 : 0;
   a.cams = cams;
   a.capacity = record_capacity;
   a.B = blocks->n_blocks;
@@ -221,7 +234,7 @@ extern "C" gs_status gs_preprocess(const gs_gaussians* levels, const gs_blocks* 
   int64_t blocks_needed = (record_capacity + kPreThreads - 1) / kPreThreads;
   int grid = (int)(blocks_needed < 8192 ? (blocks_needed > 0 ? blocks_needed : 1) : 8192);
   if ((tuning->flags & GS_TUNE_SHARED_SELECTION) && n_views > 1) {
-    if (gather) return GS_ERR_UNSUPPORTED;
+    if (gather || packed) return GS_ERR_UNSUPPORTED;
     hipLaunchKernelGGL(shared_selection_check_kernel, dim3(1), dim3(kPreThreads), 0, (hipStream_t)stream, a, counts);
     int64_t per_view = (record_capacity / n_views + kPreThreads - 1) / kPreThreads;
     int g2 = (int)(per_view < 8192 ? (per_view > 0 ? per_view : 1) : 8192);

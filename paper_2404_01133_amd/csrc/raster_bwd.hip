@@ -853,6 +853,7 @@ extern "C" gs_status gs_rasterize_bwd(const void* records, const uint32_t* pair_
   if (!gather && (blocks->n_blocks <= 0 || !blocks->lvl_off)) return GS_ERR_INVALID_ARG;
   const int tw = tuning->tile_w, th = tuning->tile_h;
   if (!tile_shape_supported(tw, th) || !batch_supported(tuning->batch)) return GS_ERR_UNSUPPORTED;
+  if (tuning->flags & GS_TUNE_PACKED_SELECTION) return GS_ERR_UNSUPPORTED;
   const bool det = (tuning->flags & GS_TUNE_DETERMINISTIC) != 0;
   if (det && gather && n_views > 1 && !(tuning->flags & GS_TUNE_SHARED_SELECTION)) return GS_ERR_UNSUPPORTED;
   if (ws_bytes < rasterize_bwd_ws_bytes(record_capacity, 0, det)) return GS_ERR_WORKSPACE;

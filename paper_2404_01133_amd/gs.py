@@ -31,7 +31,8 @@ GS_COUNT_SLOTS = 8
 GS_FLAG_RECORDS, GS_FLAG_PAIRS, GS_FLAG_WAIT, GS_FLAG_SELECTION = 1, 2, 4, 8
 GS_WS_BIN_SORT, GS_WS_RASTERIZE_BWD = 1, 2
 GS_LOD_BLOCKWISE, GS_LOD_ALL_FINEST = 0, 1
-GS_TUNE_SHARED_SELECTION, GS_TUNE_WORK_QUEUE, GS_TUNE_DETERMINISTIC = 1, 2, 4
+GS_TUNE_SHARED_SELECTION, GS_TUNE_WORK_QUEUE, GS_TUNE_DETERMINISTIC, GS_TUNE_PACKED_SELECTION = 1, 2, 4, 8
+GS_CHUNK, GS_PACKED_INDEX_BITS = 4096, 29
 
 c_double, c_int32, c_int64, c_void_p, c_size_t = (ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
                                                   ctypes.c_size_t)
@@ -102,6 +103,11 @@ _SIGNATURES = {
     "gs_mad_workspace_bytes": (c_size_t, [c_int64]),
     "gs_mad_bounds": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int64, c_double, c_void_p,
                                 c_void_p, c_void_p, c_size_t, c_void_p]),
+    "gs_chunk_capacity": (c_int64, [c_void_p, c_void_p]),
+    "gs_chunk_bounds": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_void_p]),
+    "gs_refine_workspace_bytes": (c_size_t, [c_int32, c_int64]),
+    "gs_lod_refine": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_int64,
+                                c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "gs_status_string": (ctypes.c_char_p, [c_int32]),
 }
 
@@ -229,6 +235,31 @@ def lod_select(blocks: gs_blocks, thresholds, mode, cams_dev, n_views, level, of
     thr = (c_double * max(1, len(thresholds)))(*[float(x) for x in thresholds])
     _check(lib().gs_lod_select(ctypes.byref(blocks), thr, mode, _p(cams_dev), n_views, _p(level), _p(offsets),
                                _p(counts), _stream(stream)), "gs_lod_select")
+
+
+def chunk_capacity(levels, blocks: gs_blocks) -> int:
+    arr = (gs_gaussians * len(levels))(*levels)
+    c = int(lib().gs_chunk_capacity(arr, ctypes.byref(blocks)))
+    if c < 0:
+        raise GsError(GS_ERR_INVALID_ARG, "gs_chunk_capacity")
+    return c
+
+
+def chunk_bounds(levels, blocks: gs_blocks, chunk_off, bounds, max_chunks, stream=None):
+    arr = (gs_gaussians * len(levels))(*levels)
+    _check(lib().gs_chunk_bounds(arr, ctypes.byref(blocks), _p(chunk_off), _p(bounds), max_chunks, _stream(stream)),
+           "gs_chunk_bounds")
+
+
+def refine_workspace_bytes(n_views, max_chunks) -> int:
+    return int(lib().gs_refine_workspace_bytes(n_views, max_chunks))
+
+
+def lod_refine(blocks: gs_blocks, level, cams_dev, n_views, width, height, chunk_off, bounds, max_chunks,
+               record_capacity, gather, view_offsets, counts, ws, stream=None):
+    _check(lib().gs_lod_refine(ctypes.byref(blocks), _p(level), _p(cams_dev), n_views, width, height, _p(chunk_off),
+                               _p(bounds), max_chunks, record_capacity, _p(gather), _p(view_offsets), _p(counts),
+                               _p(ws), ws.numel() * ws.element_size(), _stream(stream)), "gs_lod_refine")
 
 
 def points_workspace_bytes(level_sizes, n_views) -> int:

@@ -3,7 +3,9 @@ differentiable render (torch.autograd.Function).
 
 A frame is five library calls on one stream (Sec. 3.3.2 then Sec. 3.1):
     lod_select -> preprocess -> bin_sort -> rasterize_fwd  [-> rasterize_bwd]
-(lod_select_points in place of lod_select for the point-wise baseline.)
+(lod_select_points in place of lod_select for the point-wise baseline; with
+refine=True, lod_refine between lod_select and preprocess drops the chunks the
+projection would cull whole, with identical images.)
 Buffers are allocated once per capacity and reused; data-dependent sizes stay
 on the device (the counts array), so a frame issues no host synchronisation
 unless a capacity check is requested.
@@ -65,6 +67,9 @@ class DeviceScene:
         self.lo = None if lo is None else torch.as_tensor(np.asarray(lo, np.float64)).to(device)
         self.hi = None if hi is None else torch.as_tensor(np.asarray(hi, np.float64)).to(device)
         self.contraction = None  # device [6] p_min, p_max of a contracted partition
+        self.chunk_off = None    # chunk tables of the refinement, made on first use
+        self.chunk_bounds = None
+        self.max_chunks = 0
 
     @property
     def n_blocks(self) -> int:
@@ -195,6 +200,22 @@ class DeviceScene:
     def blocks_struct(self) -> gs.gs_blocks:
         return gs.blocks_struct(self.lo, self.hi, self.cells, self.lvl_off, self.lvl_cnt, self.contraction)
 
+    def ensure_chunks(self, stream=None):
+        """Chunk boxes of every (block, level) run (gs_chunk_bounds), once per scene;
+        call invalidate_chunks() after moving or rescaling Gaussians."""
+        if self.chunk_off is not None:
+            return
+        levels = [lv.struct() for lv in self.levels]
+        blocks = self.blocks_struct()
+        self.max_chunks = gs.chunk_capacity(levels, blocks)
+        self.chunk_off = torch.empty(self.n_blocks * self.n_levels + 1, dtype=torch.int64, device=self.device)
+        self.chunk_bounds = torch.empty((self.max_chunks, 8), dtype=torch.float32, device=self.device)
+        gs.chunk_bounds(levels, blocks, self.chunk_off, self.chunk_bounds, self.max_chunks, stream)
+
+    def invalidate_chunks(self):
+        self.chunk_off = self.chunk_bounds = None
+        self.max_chunks = 0
+
 
 # ---------------------------------------------------------------------------
 # frame buffers
@@ -227,6 +248,8 @@ class Frame:
         self.pts_offsets = None
         self.pts_ws = None
         self.pointwise = False    # selection kind of the last render_frame
+        self.refined = None       # refined selection (gather, view offsets, workspace), made on first use
+        self.refined_last = False  # whether the last render_frame used it
         self.reserve(record_capacity, pair_capacity)
 
     def reserve(self, record_capacity, pair_capacity):
@@ -240,6 +263,8 @@ class Frame:
             self.bwd_ws = None
             if self.gather is not None:
                 self.gather = torch.empty(self.record_capacity, dtype=torch.int32, device=d)
+            if self.refined is not None:
+                self.refined["gather"] = torch.empty(self.record_capacity, dtype=torch.int32, device=d)
         if pair_capacity > self.pair_capacity:
             self.pair_capacity = int(pair_capacity)
             self.pair_tiles = torch.empty(self.pair_capacity, dtype=torch.int32, device=d)
@@ -260,8 +285,29 @@ class Frame:
         if self.pts_ws is None or self.pts_ws.numel() < nbytes:
             self.pts_ws = torch.empty(nbytes, dtype=torch.uint8, device=d)
 
+    def ensure_refined(self, scene, stream=None):
+        scene.ensure_chunks(stream)
+        d = self.device
+        nbytes = gs.refine_workspace_bytes(self.V, scene.max_chunks)
+        r = self.refined
+        if r is None or r["ws"].numel() < nbytes:
+            self.refined = r = dict(gather=torch.empty(max(1, self.record_capacity), dtype=torch.int32, device=d),
+                                    view_off=torch.empty(self.V + 1, dtype=torch.int64, device=d),
+                                    ws=torch.empty(nbytes, dtype=torch.uint8, device=d))
+        return r
+
+    def pre_tuning(self):
+        """Tuning gs_preprocess takes for the last selection."""
+        if not self.refined_last:
+            return self.tuning
+        t = gs.tuning_struct(self.tuning.tile_w, self.tuning.tile_h, self.tuning.batch, self.tuning.flags)
+        t.flags |= gs.GS_TUNE_PACKED_SELECTION
+        return t
+
     def selection(self):
         """(level, offsets, gather) of the last selection, as gs_preprocess takes them."""
+        if self.refined_last:
+            return None, self.refined["view_off"], self.refined["gather"]
         if self.pointwise:
             return None, self.pts_offsets, self.gather
         return self.level, self.offsets, None
@@ -272,15 +318,20 @@ class Frame:
 
 
 def render_frame(scene: DeviceScene, frame: Frame, cams_dev, mode=gs.GS_LOD_BLOCKWISE, thresholds=(200.0, 500.0),
-                 sh_degree=3, bg=(0.0, 0.0, 0.0), stream=None, check=True):
+                 sh_degree=3, bg=(0.0, 0.0, 0.0), stream=None, check=True, refine=False):
     """LoD select + preprocess + bin/sort + composite for every view of `frame`.
 
     With check=True the counts are read back once (a host sync); if a capacity
-    was too small the buffers grow and the frame is rendered again."""
+    was too small the buffers grow and the frame is rendered again.  refine=True
+    (block-wise selections only) adds the chunk refinement (gs_lod_refine); the
+    images are the same, the frame cannot be differentiated (backward_frame)."""
+    if refine and mode == LOD_POINTWISE:
+        raise ValueError("the chunk refinement applies to block-wise selections")
     for _ in range(4):
         blocks = scene.blocks_struct()
         levels = [lv.struct() for lv in scene.levels]
         frame.pointwise = mode == LOD_POINTWISE
+        frame.refined_last = False
         if frame.pointwise:
             frame.ensure_pointwise(scene)
             gs.lod_select_points(levels, thresholds, cams_dev, frame.V, frame.record_capacity, frame.gather,
@@ -288,9 +339,15 @@ def render_frame(scene: DeviceScene, frame: Frame, cams_dev, mode=gs.GS_LOD_BLOC
         else:
             gs.lod_select(blocks, thresholds, mode, cams_dev, frame.V, frame.level, frame.offsets, frame.counts,
                           stream)
+            if refine:
+                r = frame.ensure_refined(scene, stream)
+                gs.lod_refine(blocks, frame.level, cams_dev, frame.V, frame.W, frame.H, scene.chunk_off,
+                              scene.chunk_bounds, scene.max_chunks, frame.record_capacity, r["gather"],
+                              r["view_off"], frame.counts, r["ws"], stream)
+                frame.refined_last = True
         level, offsets, gather = frame.selection()
-        gs.preprocess(levels, blocks, level, offsets, cams_dev, frame.V, frame.W, frame.H, sh_degree, frame.tuning,
-                      frame.record_capacity, frame.records, frame.depth_keys, frame.tiles_touched, frame.counts,
+        gs.preprocess(levels, blocks, level, offsets, cams_dev, frame.V, frame.W, frame.H, sh_degree,
+                      frame.pre_tuning(), frame.record_capacity, frame.records, frame.depth_keys, frame.tiles_touched, frame.counts,
                       stream, gather=gather)
         gs.bin_sort(frame.records, frame.depth_keys, frame.tiles_touched, frame.V, frame.W, frame.H, frame.tuning,
                     frame.record_capacity, frame.pair_capacity, frame.pair_tiles, frame.pair_records,
@@ -315,6 +372,8 @@ def render_frame(scene: DeviceScene, frame: Frame, cams_dev, mode=gs.GS_LOD_BLOC
 def backward_frame(scene: DeviceScene, frame: Frame, cams_dev, d_rgb, grads, sh_degree=3, bg=(0.0, 0.0, 0.0),
                    stream=None):
     """Accumulate dL/d(parameters) of every level into `grads` (list of DeviceLevel)."""
+    if frame.refined_last:
+        raise ValueError("a frame rendered with refine=True cannot be differentiated; render it without")
     nbytes = gs.workspace_bytes(gs.GS_WS_RASTERIZE_BWD, frame.record_capacity, frame.pair_capacity, frame.V, frame.W,
                                 frame.H, frame.tuning)
     if getattr(frame, "bwd_ws", None) is None or frame.bwd_ws.numel() < nbytes:

@@ -124,3 +124,64 @@ def test_static_scratch_variant_checks_before_any_device_call(libgs):
     assert f(one, one, one, 1, 64, 64, ctypes.byref(t), 1 << 22, 1 << 24, one, one, one, None, one, None) == -6
     libgs.gs_status_string.restype = ctypes.c_char_p
     assert libgs.gs_status_string(-6).decode().startswith("GS_ERR_SCRATCH")
+
+
+def test_chunk_refinement_sizes_and_checks(libgs):
+    # chunk table sizes and the argument checks of gs_chunk_bounds / gs_lod_refine,
+    # all decided on the host before any launch
+    class Gaussians(ctypes.Structure):
+        _fields_ = [("means", ctypes.c_void_p), ("scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
+                    ("opac", ctypes.c_void_p), ("sh", ctypes.c_void_p), ("n", ctypes.c_int64),
+                    ("sh_degree", ctypes.c_int32), ("attr_half", ctypes.c_int32)]
+
+    class Blocks(ctypes.Structure):
+        _fields_ = [("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p), ("cell", ctypes.c_void_p),
+                    ("lvl_off", ctypes.c_void_p), ("lvl_cnt", ctypes.c_void_p), ("n_blocks", ctypes.c_int32),
+                    ("n_levels", ctypes.c_int32), ("contraction", ctypes.c_void_p)]
+
+    P = ctypes.c_void_p
+    dummy = 0x1000
+    sizes = (5000, 4096, 4097 * 3)
+    lv = (Gaussians * 3)(*[Gaussians(dummy, dummy, dummy, dummy, dummy, n, 3, 0) for n in sizes])
+    blk = Blocks(dummy, dummy, dummy, dummy, dummy, 4, 3, None)
+    cap = libgs.gs_chunk_capacity
+    cap.restype = ctypes.c_int64
+    cap.argtypes = [P, P]
+    # per level ceil(n / GS_CHUNK) chunks, plus one partial chunk per (block, level) run
+    assert cap(lv, ctypes.byref(blk)) == 4 * 3 + (2 + 1 + 4)
+    assert cap(None, ctypes.byref(blk)) == -1
+    assert cap(lv, ctypes.byref(Blocks(dummy, dummy, dummy, dummy, dummy, 4, 0, None))) == -1
+
+    wsb = libgs.gs_refine_workspace_bytes
+    wsb.restype = ctypes.c_size_t
+    wsb.argtypes = [ctypes.c_int32, ctypes.c_int64]
+    a, b = wsb(1, 1000), wsb(8, 1000)
+    assert 0 < a < b and b >= 8 * 1000 * 8   # a size and an offset per (view, chunk)
+    assert wsb(0, 1000) == 0 and wsb(1, 0) == 0
+
+    cb = libgs.gs_chunk_bounds
+    cb.restype = ctypes.c_int32
+    cb.argtypes = [P, P, P, P, ctypes.c_int64, P]
+    assert cb(None, None, None, None, 10, None) == -1
+    assert cb(lv, ctypes.byref(blk), P(dummy), P(dummy), 5, None) == -4   # fewer entries than chunks
+
+    rf = libgs.gs_lod_refine
+    rf.restype = ctypes.c_int32
+    rf.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_int64, ctypes.c_int64,
+                   P, P, P, P, ctypes.c_size_t, P]
+    one = P(dummy)
+    assert rf(None, *([None] * 2), 1, 64, 64, *([None] * 2), 10, 10, *([None] * 4), 0, None) == -1
+    ok_args = (ctypes.byref(blk), one, one, 2, 64, 64, one, one, 19, 1000, one, one, one, one)
+    assert rf(*ok_args, ctypes.c_size_t(16), None) == -3                       # workspace too small
+    bad_cap = ok_args[:9] + (1 << 32,) + ok_args[10:]
+    assert rf(*bad_cap, ctypes.c_size_t(wsb(2, 19)), None) == -1               # record ids are u32
+    bad_size = ok_args[:3] + (2, 0, 64) + ok_args[6:]
+    assert rf(*bad_size, ctypes.c_size_t(wsb(2, 19)), None) == -1
+
+
+def test_refinement_constants_match_the_header():
+    import paper_2404_01133_amd.gs as gsmod
+    text = open(HEADER).read()
+    for name, value in (("GS_TUNE_PACKED_SELECTION", 8), ("GS_CHUNK", 4096), ("GS_PACKED_INDEX_BITS", 29)):
+        assert re.search(r"#define %s %d\b" % (name, value), text)
+        assert getattr(gsmod, name) == value

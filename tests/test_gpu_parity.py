@@ -1450,3 +1450,179 @@ def test_uneven_batch_full_size():
                 else:
                     assert not np.any(got_v[l][k])
         del agg
+
+
+# ---------------------------------------------------------------------------
+# chunk refinement (gs_chunk_bounds / gs_lod_refine): same images, fewer records
+# ---------------------------------------------------------------------------
+def _host_chunk_tables(scene):
+    """Per (block, level) run, chunks of GS_CHUNK Gaussians in storage order:
+    first chunk of each run, and per chunk the box of the centres and the
+    largest |scale| component (float32 min/max are exact)."""
+    B, L = scene.n_blocks, scene.n_levels
+    cnt = scene.lvl_cnt_host
+    off = scene.lvl_off.cpu().numpy()
+    per = (cnt + gs.GS_CHUNK - 1) // gs.GS_CHUNK
+    chunk_off = np.concatenate([[0], np.cumsum(per.reshape(-1))])
+    means = [lv.means.cpu().numpy() for lv in scene.levels]
+    scales = [np.abs(lv.scales.float().cpu().numpy()) for lv in scene.levels]
+    rows = []
+    for b in range(B):
+        for l in range(L):
+            for c in range(per[b, l]):
+                s = off[b, l] + c * gs.GS_CHUNK
+                e = min(off[b, l] + cnt[b, l], s + gs.GS_CHUNK)
+                m = means[l][:, s:e]
+                rows.append(np.concatenate([m.min(axis=1), m.max(axis=1), [scales[l][:, s:e].max()], [0.0]]))
+    return chunk_off, np.asarray(rows, np.float32).reshape(-1, 8)
+
+
+def _keys_unrefined(frame, scene):
+    """(view, level, index) of every record of a block-wise selection, packed as
+    view << 34 | level << 29 | index, in record order."""
+    level = frame.level.cpu().numpy().astype(np.int64)
+    off = frame.offsets.cpu().numpy()
+    lvl_off = scene.lvl_off.cpu().numpy()
+    V, B = level.shape
+    n = int(off[-1])
+    seg = np.repeat(np.arange(V * B), np.diff(off))
+    v, b = seg // B, seg % B
+    l = level.reshape(-1)[seg]
+    gi = lvl_off[b, l] + (np.arange(n) - off[seg])
+    return (v << 34) | (l << gs.GS_PACKED_INDEX_BITS) | gi
+
+
+def _keys_refined(frame):
+    r = frame.refined
+    vo = r["view_off"].cpu().numpy()
+    e = r["gather"][: int(vo[-1])].cpu().numpy().view(np.uint32).astype(np.int64)
+    v = np.repeat(np.arange(frame.V, dtype=np.int64), np.diff(vo))
+    return (v << 34) | e
+
+
+def _compare_refined(scene, cams, thresholds, rec_cap=None, what=""):
+    """Render `cams` in one call with and without the refinement; the images,
+    transmittance, last contributor, visible and pair counts and the sorted
+    pairs (records named by (view, level, index)) must be identical, the refined
+    records an order-preserving subset of the selection, and every record it
+    drops one the projection culls."""
+    V, W, H = len(cams), cams[0].width, cams[0].height
+    cams_dev = gs.cameras_to_device(cams)
+    cap = V * scene.max_records_per_view()
+    fu = render.Frame(scene.n_blocks, V, W, H, max(1, cap), 1 << 22)
+    fr = render.Frame(scene.n_blocks, V, W, H, rec_cap or max(1, cap), 1 << 22)
+    render.render_frame(scene, fu, cams_dev, thresholds=thresholds)
+    render.render_frame(scene, fr, cams_dev, thresholds=thresholds, refine=True)
+    torch.cuda.synchronize()
+    cu, cr = fu.host_counts(), fr.host_counts()
+    print("case: refine", what, "unrefined", cu, "refined", cr, flush=True)
+    assert cu["flags"] == 0 and cr["flags"] == 0
+    assert cr["visible"] == cu["visible"] and cr["pairs"] == cu["pairs"]
+    assert torch.equal(fr.rgb, fu.rgb), what
+    assert torch.equal(fr.T, fu.T), what
+    assert torch.equal(fr.n_last, fu.n_last), what
+    ku, kr = _keys_unrefined(fu, scene), _keys_refined(fr)
+    assert cr["records"] == kr.shape[0] <= cu["records"] == ku.shape[0]
+    order = np.argsort(ku, kind="stable")
+    pos = np.searchsorted(ku[order], kr)
+    assert np.all(pos < ku.shape[0])
+    pos = order[pos]
+    np.testing.assert_array_equal(ku[pos], kr)
+    assert np.all(np.diff(pos) > 0), "refined records out of selection order"
+    dropped = np.ones(ku.shape[0], bool)
+    dropped[pos] = False
+    n = cu["records"]
+    dk = fu.depth_keys[:n].cpu().numpy().view(np.uint32)
+    tt = fu.tiles_touched[:n].cpu().numpy()
+    assert np.all(dk[dropped] == 0xFFFFFFFF) and np.all(tt[dropped] == 0), "a dropped record was visible"
+    tu, ru = frame_pairs(fu)
+    tr, rr = frame_pairs(fr)
+    np.testing.assert_array_equal(tr, tu)
+    np.testing.assert_array_equal(kr[rr.astype(np.int64)], ku[ru.astype(np.int64)])
+    return cu, cr
+
+
+def test_chunk_bounds_bit_exact():
+    fine, block_id, u, cells = synth.city_finest(600_000, seed=50, grid=(4, 4))
+    scene = render.DeviceScene.from_finest(fine, block_id, u, cells)
+    scene.ensure_chunks()
+    torch.cuda.synchronize()
+    chunk_off, bounds = _host_chunk_tables(scene)
+    np.testing.assert_array_equal(scene.chunk_off.cpu().numpy(), chunk_off)
+    C = int(chunk_off[-1])
+    assert C <= scene.max_chunks
+    np.testing.assert_array_equal(scene.chunk_bounds[:C].cpu().numpy(), bounds)
+
+
+def test_refined_city_frames_equal_unrefined():
+    fine, block_id, u, cells = synth.city_finest(2_000_000, seed=51)
+    scene = render.DeviceScene.from_finest(fine, block_id, u, cells)
+    scene.compute_bounds(4.0)
+    cams = synth.city_views(seed=51, n_xy=4)
+    kept = 0
+    for c0 in range(0, len(cams), 8):
+        cu, cr = _compare_refined(scene, cams[c0:c0 + 8], (200.0, 500.0), what="city views %d.." % c0)
+        kept += cr["records"] / max(1, cu["records"])
+    assert kept / 3 < 0.9   # the refinement drops a part of the selection here
+
+
+def _ragged_block_scene(seed=53):
+    """Eight 50 m cells with 0, 1, 4095, 4096, 4097, 8192, 12289 and 30000
+    finest Gaussians (runs of every remainder against GS_CHUNK, empty ones
+    included), three nested levels, cell boxes as block bounds."""
+    sizes = [0, 1, 4095, 4096, 4097, 8192, 12289, 30000]
+    cells = synth.grid_cells(-100.0, -50.0, 50.0, 4, 2)
+    parts = [synth.box_gaussians(n, seed + b, extent=((cells[b, 0], cells[b, 1]), (cells[b, 2], cells[b, 3]),
+                                                       (0.0, 20.0))) for b, n in enumerate(sizes)]
+    fine = synth.GaussianSet(*(np.ascontiguousarray(np.concatenate([getattr(p, k) for p in parts], axis=-1))
+                               for k in ("means", "scales", "quats", "opac", "sh")))
+    block_id = np.repeat(np.arange(len(sizes)), sizes)
+    u = np.random.default_rng(seed).uniform(size=block_id.shape[0])
+    bs = synth.block_scene_from_finest(fine, block_id, cells, u)
+    lo = np.stack([cells[:, 0], cells[:, 2], np.zeros(len(sizes))], axis=1)
+    hi = np.stack([cells[:, 1], cells[:, 3], np.full(len(sizes), 20.0)], axis=1)
+    return render.DeviceScene.from_sets(bs.levels, bs.lvl_off, bs.lvl_cnt, cells=cells, lo=lo, hi=hi)
+
+
+def test_refined_ragged_runs_near_plane_and_empty_views():
+    scene = _ragged_block_scene()
+    W, H = 333, 197
+    cams = [synth.look_camera((0.0, 0.0, 10.0), 0.3, 0.0, W, H),               # inside: boxes straddle the near plane
+            synth.look_camera((0.0, 0.0, 30.0), 0.0, math.radians(80.0), W, H),  # sky: nothing visible
+            synth.look_camera((-150.0, 0.0, 60.0), 0.0, math.radians(-20.0), W, H),
+            synth.look_camera((0.0, 0.0, 150.0), 0.0, math.radians(-90.0), W, H),
+            synth.look_camera((40.0, -20.0, 2.0), 2.5, math.radians(-5.0), W, H)]
+    cu, cr = _compare_refined(scene, cams, (30.0, 80.0), what="ragged")
+    assert cr["records"] < cu["records"]
+    # the sky view alone: every chunk dropped, an empty frame
+    cu, cr = _compare_refined(scene, cams[1:2], (30.0, 80.0), what="sky")
+    assert cr["records"] == 0 and cu["visible"] == 0
+
+
+def test_refined_record_capacity_overflow_regrows():
+    scene = _ragged_block_scene(seed=54)
+    cams = [synth.look_camera((-150.0, 0.0, 60.0), 0.0, math.radians(-20.0), 256, 160),
+            synth.look_camera((0.0, 0.0, 10.0), 1.3, 0.0, 256, 160)]
+    # 64 records: gs_lod_refine raises GS_FLAG_RECORDS, the frame grows and renders again
+    _compare_refined(scene, cams, (30.0, 80.0), rec_cap=64, what="regrow")
+
+
+def test_refined_frame_cannot_be_differentiated():
+    scene = _ragged_block_scene(seed=55)
+    cam = synth.look_camera((-150.0, 0.0, 60.0), 0.0, math.radians(-20.0), 128, 96)
+    cams_dev = gs.cameras_to_device([cam])
+    f = render.Frame(scene.n_blocks, 1, 128, 96, scene.max_records_per_view(), 1 << 20)
+    render.render_frame(scene, f, cams_dev, thresholds=(30.0, 80.0), refine=True)
+    grads = [lv.zeros_like() for lv in scene.levels]
+    with pytest.raises(ValueError):
+        render.backward_frame(scene, f, cams_dev, torch.zeros_like(f.rgb), grads)
+    # the C ABI refuses the packed selection in the backward as well
+    t = gs.tuning_struct(16, 16, 256, gs.GS_TUNE_PACKED_SELECTION)
+    level, offsets, gather = f.selection()
+    with pytest.raises(gs.GsError) as err:
+        gs.rasterize_bwd(f.records, f.pair_records, f.tile_ranges, 1, 128, 96, (0.0, 0.0, 0.0), t, f.rgb, f.T,
+                         f.n_last, torch.zeros_like(f.rgb), [lv.struct() for lv in scene.levels],
+                         scene.blocks_struct(), level, offsets, cams_dev, 3, f.record_capacity, f.counts,
+                         [gs.grads_struct(g.means, g.scales, g.quats, g.opac, g.sh) for g in grads],
+                         torch.empty(1 << 20, dtype=torch.uint8, device="cuda"), None, f.tile_queue, gather=gather)
+    assert err.value.status == gs.GS_ERR_UNSUPPORTED
