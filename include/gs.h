@@ -244,7 +244,7 @@ gs_status gs_lod_select_points(const gs_gaussians* levels, int32_t n_levels, con
  *     than max_chunks; ws / ws_bytes: at least gs_refine_workspace_bytes(V,
  *     max_chunks).  Levels must hold fewer than 2^GS_PACKED_INDEX_BITS
  *     Gaussians. */
-#define GS_CHUNK 4096
+#define GS_CHUNK 2048
 #define GS_PACKED_INDEX_BITS 29
 int64_t gs_chunk_capacity(const gs_gaussians* levels /* host [n_levels] */, const gs_blocks* blocks /* host */);
 gs_status gs_chunk_bounds(const gs_gaussians* levels, const gs_blocks* blocks, int64_t* chunk_off, float* bounds,

@@ -176,23 +176,16 @@ __device__ __forceinline__ int64_t table_chunks(const RefineArgs& a) {
   return c < a.max_chunks ? c : a.max_chunks;
 }
 
-__global__ void __launch_bounds__(256) refine_test_kernel(RefineArgs a, uint32_t* __restrict__ sizes) {
-  const int BL = a.B * a.L;
-  const int64_t C = table_chunks(a);
-  const int64_t total = (int64_t)a.V * C;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int v = (int)(e / C);
-    const int64_t k = e - (int64_t)v * C;
-    const int p = run_of_chunk(a.chunk_off, BL, k);
-    const int b = p / a.L, l = p - b * a.L;
-    uint32_t keep = 0;
-    if (a.level[(int64_t)v * a.B + b] == l) {
-      const int64_t c = k - a.chunk_off[p];
-      const int64_t n = min((int64_t)kChunk, a.lvl_cnt[p] - c * kChunk);
-      if (!chunk_culled(a.bounds + k * 8, a.cams[v], a.W, a.H)) keep = (uint32_t)n;
-    }
-    sizes[e] = keep;
-  }
+// entry e = v * C + k (view v, chunk k of C)
+__device__ __forceinline__ uint32_t entry_keep(const RefineArgs& a, int64_t e, int64_t C) {
+  const int v = (int)(e / C);
+  const int64_t k = e - (int64_t)v * C;
+  const int p = run_of_chunk(a.chunk_off, a.B * a.L, k);
+  const int b = p / a.L, l = p - b * a.L;
+  if (a.level[(int64_t)v * a.B + b] != l) return 0u;
+  const int64_t c = k - a.chunk_off[p];
+  const int64_t n = min((int64_t)kChunk, a.lvl_cnt[p] - c * kChunk);
+  return chunk_culled(a.bounds + k * 8, a.cams[v], a.W, a.H) ? 0u : (uint32_t)n;
 }
 
 __global__ void refine_clear_kernel(uint64_t* __restrict__ status, int64_t words, uint32_t* __restrict__ counter) {
@@ -201,15 +194,16 @@ __global__ void refine_clear_kernel(uint64_t* __restrict__ status, int64_t words
   if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0u;
 }
 
-// exclusive prefix of the sizes in (view, chunk) order: one pass, tiles claimed in order,
-// decoupled look-back over one count per tile
-__global__ void __launch_bounds__(256) refine_scan_kernel(RefineArgs a, const uint32_t* __restrict__ sizes,
+// per entry the records kept (the test) and their exclusive prefix in (view, chunk) order: one
+// pass, tiles claimed in order, decoupled look-back over one count per tile
+__global__ void __launch_bounds__(256) refine_scan_kernel(RefineArgs a, uint32_t* __restrict__ sizes,
                                                           uint32_t* __restrict__ offs, uint64_t* __restrict__ status,
                                                           uint32_t* __restrict__ counter, int64_t* counts) {
   __shared__ uint64_t s_wave64[4];
   __shared__ uint32_t s_tile;
   __shared__ uint64_t s_base;
-  const int64_t total = (int64_t)a.V * table_chunks(a);
+  const int64_t C = table_chunks(a);
+  const int64_t total = (int64_t)a.V * C;
   const int64_t ntiles = (total + kScanTile - 1) / kScanTile;
   for (;;) {
     if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1u);
@@ -220,7 +214,8 @@ __global__ void __launch_bounds__(256) refine_scan_kernel(RefineArgs a, const ui
     uint64_t loc[kScanItems], mine = 0;
 #pragma unroll
     for (int q = 0; q < kScanItems; ++q) {
-      loc[q] = e0 + q < total ? sizes[e0 + q] : 0u;
+      loc[q] = e0 + q < total ? entry_keep(a, e0 + q, C) : 0u;
+      if (e0 + q < total) sizes[e0 + q] = (uint32_t)loc[q];
       mine += loc[q];
     }
     uint64_t tile_total;
@@ -240,9 +235,10 @@ __global__ void __launch_bounds__(256) refine_scan_kernel(RefineArgs a, const ui
   }
 }
 
-// view offsets and the record count; raises GS_FLAG_RECORDS past the capacity
-__global__ void refine_views_kernel(RefineArgs a, const uint32_t* __restrict__ sizes, const uint32_t* __restrict__ offs,
-                                    int64_t capacity, int64_t* __restrict__ view_off, int64_t* counts) {
+// view offsets and the record count (by one work-group); raises GS_FLAG_RECORDS past the capacity
+__device__ __forceinline__ void refine_views(const RefineArgs& a, const uint32_t* __restrict__ sizes,
+                                             const uint32_t* __restrict__ offs, int64_t capacity,
+                                             int64_t* __restrict__ view_off, int64_t* counts) {
   const int64_t C = table_chunks(a);
   const int64_t total_e = (int64_t)a.V * C;
   for (int v = threadIdx.x; v <= a.V; v += blockDim.x) {
@@ -258,11 +254,14 @@ __global__ void refine_views_kernel(RefineArgs a, const uint32_t* __restrict__ s
   }
 }
 
-// the kept chunks' records: level << GS_PACKED_INDEX_BITS | index within the level
+// the kept chunks' records: level << GS_PACKED_INDEX_BITS | index within the level; work-group 0
+// also writes the view offsets and the record count
 __global__ void __launch_bounds__(256) refine_expand_kernel(RefineArgs a, const int64_t* __restrict__ lvl_off,
                                                             const uint32_t* __restrict__ sizes,
                                                             const uint32_t* __restrict__ offs, int64_t capacity,
-                                                            uint32_t* __restrict__ gather) {
+                                                            uint32_t* __restrict__ gather, int64_t* __restrict__ view_off,
+                                                            int64_t* counts) {
+  if (blockIdx.x == 0) refine_views(a, sizes, offs, capacity, view_off, counts);
   const int BL = a.B * a.L;
   const int64_t C = table_chunks(a);
   const int64_t total = (int64_t)a.V * C;
@@ -388,13 +387,11 @@ extern "C" gs_status gs_lod_refine(const gs_blocks* blocks, const int8_t* level,
   };
   hipLaunchKernelGGL(refine_clear_kernel, grid(w.status_words, 256), dim3(256), 0, s, w.status, w.status_words,
                      w.counter);
-  hipLaunchKernelGGL(refine_test_kernel, grid(entries, 4096), dim3(256), 0, s, a, w.sizes);
   hipLaunchKernelGGL(refine_scan_kernel, grid(entries / kScanItems, 1024), dim3(256), 0, s, a, w.sizes, w.offs,
                      w.status, w.counter, counts);
-  hipLaunchKernelGGL(refine_views_kernel, dim3(1), dim3(256), 0, s, a, w.sizes, w.offs, record_capacity,
-                     view_offsets, counts);
   hipLaunchKernelGGL(refine_expand_kernel, dim3((unsigned)(entries < 2048 ? (entries > 0 ? entries : 1) : 2048)),
-                     dim3(256), 0, s, a, blocks->lvl_off, w.sizes, w.offs, record_capacity, gather);
+                     dim3(256), 0, s, a, blocks->lvl_off, w.sizes, w.offs, record_capacity, gather, view_offsets,
+                     counts);
   GS_LAUNCH_CHECK();
   return GS_OK;
 }

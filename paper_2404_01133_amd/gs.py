@@ -32,7 +32,7 @@ GS_FLAG_RECORDS, GS_FLAG_PAIRS, GS_FLAG_WAIT, GS_FLAG_SELECTION = 1, 2, 4, 8
 GS_WS_BIN_SORT, GS_WS_RASTERIZE_BWD = 1, 2
 GS_LOD_BLOCKWISE, GS_LOD_ALL_FINEST = 0, 1
 GS_TUNE_SHARED_SELECTION, GS_TUNE_WORK_QUEUE, GS_TUNE_DETERMINISTIC, GS_TUNE_PACKED_SELECTION = 1, 2, 4, 8
-GS_CHUNK, GS_PACKED_INDEX_BITS = 4096, 29
+GS_CHUNK, GS_PACKED_INDEX_BITS = 2048, 29
 
 c_double, c_int32, c_int64, c_void_p, c_size_t = (ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
                                                   ctypes.c_size_t)

@@ -148,7 +148,8 @@ def test_chunk_refinement_sizes_and_checks(libgs):
     cap.restype = ctypes.c_int64
     cap.argtypes = [P, P]
     # per level ceil(n / GS_CHUNK) chunks, plus one partial chunk per (block, level) run
-    assert cap(lv, ctypes.byref(blk)) == 4 * 3 + (2 + 1 + 4)
+    ch = 2048
+    assert cap(lv, ctypes.byref(blk)) == 4 * 3 + sum((n + ch - 1) // ch for n in sizes)
     assert cap(None, ctypes.byref(blk)) == -1
     assert cap(lv, ctypes.byref(Blocks(dummy, dummy, dummy, dummy, dummy, 4, 0, None))) == -1
 
@@ -182,6 +183,6 @@ def test_chunk_refinement_sizes_and_checks(libgs):
 def test_refinement_constants_match_the_header():
     import paper_2404_01133_amd.gs as gsmod
     text = open(HEADER).read()
-    for name, value in (("GS_TUNE_PACKED_SELECTION", 8), ("GS_CHUNK", 4096), ("GS_PACKED_INDEX_BITS", 29)):
+    for name, value in (("GS_TUNE_PACKED_SELECTION", 8), ("GS_CHUNK", 2048), ("GS_PACKED_INDEX_BITS", 29)):
         assert re.search(r"#define %s %d\b" % (name, value), text)
         assert getattr(gsmod, name) == value

@@ -1287,6 +1287,15 @@ def test_city_20M_lod_frames_full_size():
         for f, e in zip(frames, eager):
             assert torch.equal(f.rgb, e)
     del graph
+    print("case: 20M city, refined batched call", flush=True)
+    fb = render.Frame(scene.n_blocks, len(cams), 1600, 900, len(cams) * rc, 1 << 23)
+    render.render_frame(scene, fb, gs.cameras_to_device(cams), refine=True)
+    cb = fb.host_counts()
+    assert cb["flags"] == 0 and cb["records"] < sum(c["records"] for c in counts)
+    assert cb["pairs"] == sum(c["pairs"] for c in counts)
+    for k, e in enumerate(eager):
+        assert torch.equal(fb.rgb[k], e[0])
+    del fb
     levels_seen = set()
     for k, cam in enumerate(cams):
         print("case: 20M city view", views[k], counts[k], flush=True)
