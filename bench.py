@@ -47,7 +47,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BIN_SORT_KERNELS = ("clear_front, depth_hist, radix_pass<compact>, 2 radix_pass, radix_pass<pairs>, emit, emit_big, "
                     "2 tile radix_pass, ranges")
-REFINE_KERNELS = "refine_clear, refine_scan, refine_expand"
+REFINE_KERNELS = "refine_clear, refine_test, refine_scan, refine_expand"
 # published FP32 vector peak of MI355X (packed FP32); the library is compiled
 # without packed-FP32 instructions, whose ceiling is half of it: 256 CUs x 64 FMA
 # lanes per clock x 2 flops x 2.4 GHz = 78.6 TFLOP/s
@@ -415,10 +415,10 @@ def workload_lod(args, torch, gs, render, synth):
                               "traffic": measured_traffic(ras_name, P_)},
         }
         if refine:
-            # per (view, chunk): the 32 B box read, a size and an offset written and read (16 B);
-            # 4 B gather entry written per record kept
+            # per (view, chunk): the 32 B box read, a size written and read twice, an offset written
+            # and read (20 B); 4 B gather entry written per record kept
             n_chunks = int(scene.chunk_off[-1].item())
-            ref_bytes = float(np.mean(P_ * n_chunks * 48.0 + 4.0 * c_rec))
+            ref_bytes = float(np.mean(P_ * n_chunks * 52.0 + 4.0 * c_rec))
             st["lod_refine"] = {"bound": "hbm", "kernel": "lod_refine stage (%s)" % REFINE_KERNELS, "unit": "GB/s",
                                 "peak": HBM_PEAK_GBS, "achieved": ref_bytes / (ref_ms * 1e-3) / 1e9,
                                 "avg_launch_ms": ref_ms, "algorithmic_bytes_per_launch": ref_bytes,

@@ -236,14 +236,15 @@ gs_status gs_lod_select_points(const gs_gaussians* levels, int32_t n_levels, con
  *     bad arguments); levels host [n_levels]
  *   gs_chunk_bounds: chunk_off [B*L + 1] int64 (first chunk of run b*L + l, then
  *     the total), bounds [max_chunks][8] f32 (lo xyz, hi xyz, largest |scale|,
- *     0); GS_ERR_CAPACITY if max_chunks < gs_chunk_capacity
+ *     the run b*L + l as int32 bits); GS_ERR_CAPACITY if max_chunks <
+ *     gs_chunk_capacity, GS_ERR_UNSUPPORTED if a level holds 2^GS_PACKED_INDEX_BITS
+ *     Gaussians or more
  *   gs_lod_refine: level from gs_lod_select; gather [record_capacity] u32
  *     (level << GS_PACKED_INDEX_BITS | index); view_offsets [V + 1] int64;
  *     counts[GS_COUNT_RECORDS] = records kept; GS_FLAG_RECORDS is raised (and
  *     the list truncated) past record_capacity or if the chunk table holds more
  *     than max_chunks; ws / ws_bytes: at least gs_refine_workspace_bytes(V,
- *     max_chunks).  Levels must hold fewer than 2^GS_PACKED_INDEX_BITS
- *     Gaussians. */
+ *     max_chunks); chunk_off and bounds as gs_chunk_bounds wrote them. */
 #define GS_CHUNK 2048
 #define GS_PACKED_INDEX_BITS 29
 int64_t gs_chunk_capacity(const gs_gaussians* levels /* host [n_levels] */, const gs_blocks* blocks /* host */);

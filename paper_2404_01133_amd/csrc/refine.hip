@@ -25,8 +25,9 @@ namespace gs {
 namespace {
 
 constexpr int kChunk = GS_CHUNK;
-constexpr int kScanItems = 4;
+constexpr int kScanItems = 16;
 constexpr int kScanTile = 256 * kScanItems;  // entries per look-back tile of the count scan
+constexpr int kExpandBatch = 256;            // entries per work-group round of the expansion
 
 // first chunk of each (block, level) run, chunk_off[b * L + l]; chunk_off[B * L] = all chunks
 __global__ void __launch_bounds__(256) chunk_offsets_kernel(const int64_t* __restrict__ lvl_cnt, int BL,
@@ -117,7 +118,7 @@ __global__ void __launch_bounds__(256) chunk_bounds_kernel(ChunkArgs a, int64_t 
       for (int w = 1; w < 4; ++w) x = q < 3 ? fminf(x, s_red[q][w]) : fmaxf(x, s_red[q][w]);
       bounds[k * 8 + q] = x;
     }
-    if (threadIdx.x == 7) bounds[k * 8 + 7] = 0.0f;
+    if (threadIdx.x == 7) bounds[k * 8 + 7] = __int_as_float(p);  // the chunk's run, b * L + l
     __syncthreads();
   }
 }
@@ -180,7 +181,8 @@ __device__ __forceinline__ int64_t table_chunks(const RefineArgs& a) {
 __device__ __forceinline__ uint32_t entry_keep(const RefineArgs& a, int64_t e, int64_t C) {
   const int v = (int)(e / C);
   const int64_t k = e - (int64_t)v * C;
-  const int p = run_of_chunk(a.chunk_off, a.B * a.L, k);
+  const int p = __float_as_int(a.bounds[k * 8 + 7]);
+  if ((unsigned)p >= (unsigned)(a.B * a.L)) return 0u;  // not a table written by gs_chunk_bounds
   const int b = p / a.L, l = p - b * a.L;
   if (a.level[(int64_t)v * a.B + b] != l) return 0u;
   const int64_t c = k - a.chunk_off[p];
@@ -194,9 +196,17 @@ __global__ void refine_clear_kernel(uint64_t* __restrict__ status, int64_t words
   if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0u;
 }
 
-// per entry the records kept (the test) and their exclusive prefix in (view, chunk) order: one
-// pass, tiles claimed in order, decoupled look-back over one count per tile
-__global__ void __launch_bounds__(256) refine_scan_kernel(RefineArgs a, uint32_t* __restrict__ sizes,
+// per entry the records kept (0 if the view did not select the chunk's level or the chunk is culled)
+__global__ void __launch_bounds__(256) refine_test_kernel(RefineArgs a, uint32_t* __restrict__ sizes) {
+  const int64_t C = table_chunks(a);
+  const int64_t total = (int64_t)a.V * C;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+    sizes[e] = entry_keep(a, e, C);
+}
+
+// exclusive prefix of the sizes in (view, chunk) order: one pass, tiles claimed in order (few, large
+// tiles: each claim is an atomic on one counter), decoupled look-back over one count per tile
+__global__ void __launch_bounds__(256) refine_scan_kernel(RefineArgs a, const uint32_t* __restrict__ sizes,
                                                           uint32_t* __restrict__ offs, uint64_t* __restrict__ status,
                                                           uint32_t* __restrict__ counter, int64_t* counts) {
   __shared__ uint64_t s_wave64[4];
@@ -211,13 +221,20 @@ __global__ void __launch_bounds__(256) refine_scan_kernel(RefineArgs a, uint32_t
     const int64_t t = s_tile;
     if (t >= ntiles) break;
     const int64_t e0 = t * kScanTile + (int64_t)threadIdx.x * kScanItems;  // consecutive entries per thread
-    uint64_t loc[kScanItems], mine = 0;
+    uint32_t loc[kScanItems];
+    if (e0 + kScanItems <= total) {  // 64 B aligned: the workspace arrays start on 256 B
 #pragma unroll
-    for (int q = 0; q < kScanItems; ++q) {
-      loc[q] = e0 + q < total ? entry_keep(a, e0 + q, C) : 0u;
-      if (e0 + q < total) sizes[e0 + q] = (uint32_t)loc[q];
-      mine += loc[q];
+      for (int q = 0; q < kScanItems; q += 4) {
+        const uint4 x = *reinterpret_cast<const uint4*>(sizes + e0 + q);
+        loc[q] = x.x, loc[q + 1] = x.y, loc[q + 2] = x.z, loc[q + 3] = x.w;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < kScanItems; ++q) loc[q] = e0 + q < total ? sizes[e0 + q] : 0u;
     }
+    uint64_t mine = 0;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) mine += loc[q];
     uint64_t tile_total;
     uint64_t run = block_excl_scan64(mine, s_wave64, &tile_total);
     if (threadIdx.x < 64) {
@@ -226,10 +243,20 @@ __global__ void __launch_bounds__(256) refine_scan_kernel(RefineArgs a, uint32_t
     }
     __syncthreads();
     run += s_base;
+    uint32_t out[kScanItems];
 #pragma unroll
     for (int q = 0; q < kScanItems; ++q) {
-      if (e0 + q < total) offs[e0 + q] = (uint32_t)min(run, (uint64_t)0xFFFFFFFFu);
+      out[q] = (uint32_t)min(run, (uint64_t)0xFFFFFFFFu);
       run += loc[q];
+    }
+    if (e0 + kScanItems <= total) {
+#pragma unroll
+      for (int q = 0; q < kScanItems; q += 4)
+        *reinterpret_cast<uint4*>(offs + e0 + q) = make_uint4(out[q], out[q + 1], out[q + 2], out[q + 3]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < kScanItems; ++q)
+        if (e0 + q < total) offs[e0 + q] = out[q];
     }
     __syncthreads();  // s_tile and s_base are rewritten next round
   }
@@ -254,28 +281,46 @@ __device__ __forceinline__ void refine_views(const RefineArgs& a, const uint32_t
   }
 }
 
-// the kept chunks' records: level << GS_PACKED_INDEX_BITS | index within the level; work-group 0
-// also writes the view offsets and the record count
+// the kept chunks' records: level << GS_PACKED_INDEX_BITS | index within the level.  A work-group
+// takes kExpandBatch entries at a time, one per thread, strided by the grid (kept chunks come in long
+// runs of consecutive entries, so this spreads them over the work-groups; most entries are empty:
+// chunks at levels the view did not select, or culled), lists the non-empty ones in LDS and writes
+// their records together.  Work-group 0 also writes the view offsets and the record count.
 __global__ void __launch_bounds__(256) refine_expand_kernel(RefineArgs a, const int64_t* __restrict__ lvl_off,
                                                             const uint32_t* __restrict__ sizes,
                                                             const uint32_t* __restrict__ offs, int64_t capacity,
                                                             uint32_t* __restrict__ gather, int64_t* __restrict__ view_off,
                                                             int64_t* counts) {
+  __shared__ uint32_t s_n[kExpandBatch], s_head[kExpandBatch], s_off[kExpandBatch];
+  __shared__ int s_cnt;
   if (blockIdx.x == 0) refine_views(a, sizes, offs, capacity, view_off, counts);
-  const int BL = a.B * a.L;
   const int64_t C = table_chunks(a);
   const int64_t total = (int64_t)a.V * C;
-  for (int64_t e = blockIdx.x; e < total; e += gridDim.x) {
-    const uint32_t n = sizes[e];
-    if (n == 0) continue;
-    const int v = (int)(e / C);
-    const int64_t k = e - (int64_t)v * C;
-    const int p = run_of_chunk(a.chunk_off, BL, k);
-    const int l = p % a.L;
-    const int64_t start = lvl_off[p] + (k - a.chunk_off[p]) * kChunk;
-    const int64_t o = offs[e];
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
-      if (o + i < capacity) gather[o + i] = ((uint32_t)l << GS_PACKED_INDEX_BITS) | (uint32_t)(start + i);
+  const int64_t G = gridDim.x;
+  for (int64_t r0 = 0; r0 * G + blockIdx.x < total; r0 += kExpandBatch) {
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    const int64_t e = (r0 + threadIdx.x) * G + blockIdx.x;
+    const uint32_t n = e < total ? sizes[e] : 0u;
+    if (n) {
+      const int64_t k = e - (e / C) * C;
+      const int p = __float_as_int(a.bounds[k * 8 + 7]);  // a valid run: the scan kept the entry
+      const int l = p % a.L;
+      const int64_t start = lvl_off[p] + (k - a.chunk_off[p]) * kChunk;
+      const int slot = atomicAdd(&s_cnt, 1);
+      s_n[slot] = n;
+      s_head[slot] = ((uint32_t)l << GS_PACKED_INDEX_BITS) | (uint32_t)start;
+      s_off[slot] = offs[e];
+    }
+    __syncthreads();
+    const int cnt = s_cnt;
+    for (int j = 0; j < cnt; ++j) {
+      const uint32_t nj = s_n[j], hj = s_head[j];
+      const int64_t oj = s_off[j];
+      for (uint32_t i = threadIdx.x; i < nj; i += blockDim.x)
+        if (oj + i < capacity) gather[oj + i] = hj + i;
+    }
+    __syncthreads();  // s_cnt and the lists are rewritten next round
   }
 }
 
@@ -330,6 +375,7 @@ extern "C" gs_status gs_chunk_bounds(const gs_gaussians* levels, const gs_blocks
     const gs_gaussians& g = levels[l];
     if (g.n < 0 || (g.n > 0 && (!g.means || !g.scales))) return GS_ERR_INVALID_ARG;
     if (g.attr_half != 0 && g.attr_half != 1) return GS_ERR_INVALID_ARG;
+    if (g.n >= ((int64_t)1 << GS_PACKED_INDEX_BITS)) return GS_ERR_UNSUPPORTED;  // packed gather entries
     a.lv[l] = level_ptrs(g);
   }
   a.lvl_off = blocks->lvl_off;
@@ -387,9 +433,11 @@ extern "C" gs_status gs_lod_refine(const gs_blocks* blocks, const int8_t* level,
   };
   hipLaunchKernelGGL(refine_clear_kernel, grid(w.status_words, 256), dim3(256), 0, s, w.status, w.status_words,
                      w.counter);
+  hipLaunchKernelGGL(refine_test_kernel, grid(entries, 4096), dim3(256), 0, s, a, w.sizes);
   hipLaunchKernelGGL(refine_scan_kernel, grid(entries / kScanItems, 1024), dim3(256), 0, s, a, w.sizes, w.offs,
                      w.status, w.counter, counts);
-  hipLaunchKernelGGL(refine_expand_kernel, dim3((unsigned)(entries < 2048 ? (entries > 0 ? entries : 1) : 2048)),
+  const int64_t batches = (entries + kExpandBatch - 1) / kExpandBatch;
+  hipLaunchKernelGGL(refine_expand_kernel, dim3((unsigned)(batches < 2048 ? (batches > 0 ? batches : 1) : 2048)),
                      dim3(256), 0, s, a, blocks->lvl_off, w.sizes, w.offs, record_capacity, gather, view_offsets,
                      counts);
   GS_LAUNCH_CHECK();

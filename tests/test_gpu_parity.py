@@ -1466,8 +1466,9 @@ def test_uneven_batch_full_size():
 # ---------------------------------------------------------------------------
 def _host_chunk_tables(scene):
     """Per (block, level) run, chunks of GS_CHUNK Gaussians in storage order:
-    first chunk of each run, and per chunk the box of the centres and the
-    largest |scale| component (float32 min/max are exact)."""
+    first chunk of each run, and per chunk the box of the centres, the largest
+    |scale| component (float32 min/max are exact) and the run b * L + l (int32
+    bits in the last slot)."""
     B, L = scene.n_blocks, scene.n_levels
     cnt = scene.lvl_cnt_host
     off = scene.lvl_off.cpu().numpy()
@@ -1475,7 +1476,7 @@ def _host_chunk_tables(scene):
     chunk_off = np.concatenate([[0], np.cumsum(per.reshape(-1))])
     means = [lv.means.cpu().numpy() for lv in scene.levels]
     scales = [np.abs(lv.scales.float().cpu().numpy()) for lv in scene.levels]
-    rows = []
+    rows, runs = [], []
     for b in range(B):
         for l in range(L):
             for c in range(per[b, l]):
@@ -1483,7 +1484,10 @@ def _host_chunk_tables(scene):
                 e = min(off[b, l] + cnt[b, l], s + gs.GS_CHUNK)
                 m = means[l][:, s:e]
                 rows.append(np.concatenate([m.min(axis=1), m.max(axis=1), [scales[l][:, s:e].max()], [0.0]]))
-    return chunk_off, np.asarray(rows, np.float32).reshape(-1, 8)
+                runs.append(b * L + l)
+    table = np.asarray(rows, np.float32).reshape(-1, 8)
+    table[:, 7] = np.asarray(runs, np.int32).view(np.float32)
+    return chunk_off, table
 
 
 def _keys_unrefined(frame, scene):
@@ -1560,7 +1564,7 @@ def test_chunk_bounds_bit_exact():
     np.testing.assert_array_equal(scene.chunk_off.cpu().numpy(), chunk_off)
     C = int(chunk_off[-1])
     assert C <= scene.max_chunks
-    np.testing.assert_array_equal(scene.chunk_bounds[:C].cpu().numpy(), bounds)
+    np.testing.assert_array_equal(scene.chunk_bounds[:C].cpu().numpy().view(np.int32), bounds.view(np.int32))
 
 
 def test_refined_city_frames_equal_unrefined():
