@@ -57,14 +57,15 @@ VALU_FP32_UNPACKED_TFLOPS = 78.6
 # compositing: 14 FP32 operations and one exponential, counted as 15
 FLOPS_PER_EVAL = 15
 
-# HBM bytes per launch (the binning: its 11 launches) from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of
-# `bench.py --stages-only` scaled by a 512 MiB copy, for launches of the given views per call, valid for
-# the kernel sources with the given fingerprint only
+# HBM bytes per launch (the binning: its 11 launches; the refinement: its 4) from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE runs of `bench.py --stages-only` scaled by a 512 MiB copy, for launches of the given views
+# per call, valid for the kernel sources with the given fingerprint only
 MEASURED_TRAFFIC = {
-    "preprocess_kernel": (("preprocess.hip", "project.h", "gs_common.h"), "3073003407bccdee", 8, 1652.66e6),
+    "preprocess_kernel": (("preprocess.hip", "project.h", "gs_common.h"), "2f2db44ee46c9077", 8, 1411.33e6),
     "raster_fwd_kernel<16,16,256>": (("raster.hip", "tile.h", "project.h", "gs_common.h"), "11dda1d1949f6681", 8,
-                                     667.94e6),
-    "bin_sort": (("sort.hip", "radix.h", "scan.h", "gs_common.h"), "7c172e1976d40684", 8, 1407.59e6),
+                                     667.98e6),
+    "bin_sort": (("sort.hip", "radix.h", "scan.h", "gs_common.h"), "7c172e1976d40684", 8, 1281.02e6),
+    "lod_refine": (("refine.hip", "radix.h", "scan.h", "project.h", "gs_common.h"), "5ebcb2e4d9c74c9b", 8, 35.5e6),
 }
 
 
@@ -422,7 +423,7 @@ def workload_lod(args, torch, gs, render, synth):
             st["lod_refine"] = {"bound": "hbm", "kernel": "lod_refine stage (%s)" % REFINE_KERNELS, "unit": "GB/s",
                                 "peak": HBM_PEAK_GBS, "achieved": ref_bytes / (ref_ms * 1e-3) / 1e9,
                                 "avg_launch_ms": ref_ms, "algorithmic_bytes_per_launch": ref_bytes,
-                                "chunks": n_chunks, "traffic": None}
+                                "chunks": n_chunks, "traffic": measured_traffic("lod_refine", P_)}
         for r in st.values():
             r["frac"] = r["achieved"] / r["peak"]
             r["views_per_launch"] = P_

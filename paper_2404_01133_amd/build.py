@@ -17,8 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgs.so")
-SOURCES = ["api.hip", "lod.hip", "lod_points.hip", "refine.hip", "partition.hip", "ssim.hip", "preprocess.hip", "sort.hip",
-           "raster.hip", "raster_bwd.hip"]
+SOURCES = ["api.hip", "lod.hip", "lod_points.hip", "refine.hip", "partition.hip", "ssim.hip", "preprocess.hip",
+           "sort.hip", "raster.hip", "raster_bwd.hip"]
 ARCH = os.environ.get("GS_OFFLOAD_ARCH", "gfx950")
 
 

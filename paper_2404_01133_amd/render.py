@@ -347,8 +347,8 @@ def render_frame(scene: DeviceScene, frame: Frame, cams_dev, mode=gs.GS_LOD_BLOC
                 frame.refined_last = True
         level, offsets, gather = frame.selection()
         gs.preprocess(levels, blocks, level, offsets, cams_dev, frame.V, frame.W, frame.H, sh_degree,
-                      frame.pre_tuning(), frame.record_capacity, frame.records, frame.depth_keys, frame.tiles_touched, frame.counts,
-                      stream, gather=gather)
+                      frame.pre_tuning(), frame.record_capacity, frame.records, frame.depth_keys, frame.tiles_touched,
+                      frame.counts, stream, gather=gather)
         gs.bin_sort(frame.records, frame.depth_keys, frame.tiles_touched, frame.V, frame.W, frame.H, frame.tuning,
                     frame.record_capacity, frame.pair_capacity, frame.pair_tiles, frame.pair_records,
                     frame.tile_ranges, frame.counts, frame.sort_ws, stream, frame.tile_queue)
