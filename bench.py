@@ -632,20 +632,21 @@ def workload_lod(args, torch, gs, render, synth):
         target = torch.rand((1, 3, H, W), generator=torch.Generator(device=dev).manual_seed(3), device=dev)
         views = list(range(0, V, max(1, V // args.bwd_views)))[: args.bwd_views]
 
-        def fwd_bwd(fr, mode, thr):
+        def fwd_bwd(fr, mode, thr, ref):
             for v in views:
-                render.render_frame(scene, fr, cam_slot[v], mode=mode, thresholds=thr, check=False)
+                render.render_frame(scene, fr, cam_slot[v], mode=mode, thresholds=thr, check=False, refine=ref)
                 d = torch.sign(fr.rgb - target) / fr.rgb.numel()
                 render.backward_frame(scene, fr, cam_slot[v], d, grads)
 
-        for fr, mode, thr, key in ((frame, gs.GS_LOD_BLOCKWISE, thresholds, "lod"),
-                                   (pframe, gs.GS_LOD_ALL_FINEST, (), "plain")):
+        # the plain comparator renders the whole finest level, unrefined
+        for fr, mode, thr, ref, key in ((frame, gs.GS_LOD_BLOCKWISE, thresholds, refine, "lod"),
+                                        (pframe, gs.GS_LOD_ALL_FINEST, (), False, "plain")):
             if fr is None:
                 continue
-            fwd_bwd(fr, mode, thr)
+            fwd_bwd(fr, mode, thr, ref)
             torch.cuda.synchronize()
             tb = time.perf_counter()
-            fwd_bwd(fr, mode, thr)
+            fwd_bwd(fr, mode, thr, ref)
             torch.cuda.synchronize()
             out_extra["fwd_bwd_ms_per_view_" + key] = 1e3 * (time.perf_counter() - tb) / len(views)
         log("fwd+bwd ms/view: %s" % {k: v for k, v in out_extra.items() if k.startswith("fwd_bwd")})
@@ -1024,6 +1025,7 @@ def workload_uneven(args, torch, gs, render, synth, tune=True):
     target = torch.rand((chunk, 3, H, W), generator=torch.Generator(device=dev).manual_seed(4), device=dev)
     grads = [lv.zeros_like() for lv in scene.levels]
     rc = chunk * scene.max_records_per_view() // 4
+    refine = not args.no_refine  # chunk refinement in the batched and the per-view steps
 
     def chunk_slot(k):
         return cams_dev[k * chunk * 152:(k + 1) * chunk * 152]
@@ -1034,14 +1036,14 @@ def workload_uneven(args, torch, gs, render, synth, tune=True):
         if (tw, th) not in frames:
             f = render.Frame(scene.n_blocks, chunk, W, H, rc, 1 << 24, gs.tuning_struct(tw, th, 256), device=dev)
             for k in range(V // chunk):
-                render.render_frame(scene, f, chunk_slot(k), thresholds=thresholds)
+                render.render_frame(scene, f, chunk_slot(k), thresholds=thresholds, refine=refine)
             frames[(tw, th)] = f
         return frames[(tw, th)]
 
     def step_with(f):
         def run():
             for k in range(V // chunk):
-                render.render_frame(scene, f, chunk_slot(k), thresholds=thresholds, check=False)
+                render.render_frame(scene, f, chunk_slot(k), thresholds=thresholds, check=False, refine=refine)
                 d = torch.sign(f.rgb - target) / f.rgb.numel()
                 render.backward_frame(scene, f, chunk_slot(k), d, grads)
         return run
@@ -1051,7 +1053,7 @@ def workload_uneven(args, torch, gs, render, synth, tune=True):
         f.tuning = cand.tuning()
 
         def images():
-            render.render_frame(scene, f, chunk_slot(0), thresholds=thresholds, check=False)
+            render.render_frame(scene, f, chunk_slot(0), thresholds=thresholds, check=False, refine=refine)
             return f.rgb.clone()
         return step_with(f), images
 
@@ -1074,11 +1076,11 @@ def workload_uneven(args, torch, gs, render, synth, tune=True):
     f1 = render.Frame(scene.n_blocks, 1, W, H, scene.max_records_per_view(), 1 << 22, device=dev)
     slots = [cams_dev[v * 152:(v + 1) * 152] for v in range(V)]
     for v in range(V):
-        render.render_frame(scene, f1, slots[v], thresholds=thresholds)
+        render.render_frame(scene, f1, slots[v], thresholds=thresholds, refine=refine)
 
     def plain():
         for v in range(V):
-            render.render_frame(scene, f1, slots[v], thresholds=thresholds, check=False)
+            render.render_frame(scene, f1, slots[v], thresholds=thresholds, check=False, refine=refine)
             d = torch.sign(f1.rgb - target[v % chunk:v % chunk + 1]) / f1.rgb.numel()
             render.backward_frame(scene, f1, slots[v], d, grads)
 
@@ -1092,7 +1094,7 @@ def workload_uneven(args, torch, gs, render, synth, tune=True):
            "value": 1e3 * t_batched / V, "unit": "ms/view", "higher_is_better": False,
            "per_view_default_ms_per_view": 1e3 * t_plain / V, "speedup": t_plain / t_batched,
            "views": V, "views_per_call": chunk, "width": W, "height": H, "tuning": tuned,
-           "n_finest": scene.n_finest, "dtype": "f32", "data": "synthetic"}
+           "n_finest": scene.n_finest, "chunk_refinement": refine, "dtype": "f32", "data": "synthetic"}
     log("uneven 32 blocks x 4 views: %.3f ms/view (per-view calls %.3f)" % (out["value"],
                                                                           out["per_view_default_ms_per_view"]))
     if not args.no_cpu:

@@ -161,10 +161,11 @@ typedef struct gs_tuning {
  * level must store its blocks in ascending block order); several point-wise
  * views return GS_ERR_UNSUPPORTED.  Ignored by the other entry points. */
 #define GS_TUNE_DETERMINISTIC 4
-/* tuning.flags, gs_preprocess only: the selection is a packed gather list from
- * gs_lod_refine (entries level << GS_PACKED_INDEX_BITS | index within the level,
- * offsets [V+1] per view, level unused).  gs_rasterize_bwd returns
- * GS_ERR_UNSUPPORTED with it (the refinement serves rendering). */
+/* tuning.flags, gs_preprocess and gs_rasterize_bwd: the selection is a packed
+ * gather list from gs_lod_refine (entries level << GS_PACKED_INDEX_BITS | index
+ * within the level, offsets [V+1] per view, level unused).  gs_rasterize_bwd
+ * returns GS_ERR_UNSUPPORTED for it with GS_TUNE_SHARED_SELECTION, or with
+ * GS_TUNE_DETERMINISTIC and several views. */
 #define GS_TUNE_PACKED_SELECTION 8
 
 /* Size in bytes of one projected record (an opaque device structure). */
@@ -357,7 +358,8 @@ gs_status gs_rasterize_fwd(const void* records, const uint32_t* pair_records, co
  * so it must be sized with the pair capacity the frame was binned with).
  * tile_queue: as for gs_rasterize_fwd (uses the second head counter, reset the same
  *   way, so several backward calls may follow one forward).
- * level / offsets / gather: the selection passed to gs_preprocess.
+ * level / offsets / gather: the selection passed to gs_preprocess (a refined one
+ *   with GS_TUNE_PACKED_SELECTION in tuning->flags, as there).
  * ws: at least gs_workspace_bytes(GS_WS_RASTERIZE_BWD, ...). */
 gs_status gs_rasterize_bwd(const void* records, const uint32_t* pair_records, const uint32_t* tile_ranges,
                            uint32_t* tile_queue, int32_t n_views, int32_t width, int32_t height, const float* bg,

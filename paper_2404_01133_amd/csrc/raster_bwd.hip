@@ -348,11 +348,12 @@ struct BwdArgs {
   const int64_t* lvl_cnt;
   const int8_t* level;
   const int64_t* offsets;
-  const uint32_t* gather;  // point-wise selection: record -> index within its level
+  const uint32_t* gather;  // point-wise selection: record -> index within its level (packed: see below)
   const gs_camera* cams;
   int64_t capacity;
   int32_t B, L, V, W, H, sh_degree;
-  int32_t segs;  // segments per view: B (block-wise) or L (point-wise)
+  int32_t segs;    // segments per view: B (block-wise), L (point-wise) or 1 (packed)
+  int32_t packed;  // gather entries are level << GS_PACKED_INDEX_BITS | index (refined selection)
 };
 
 // Destinations of a record's parameter gradients.
@@ -692,9 +693,18 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(BwdArgs a, const Re
     if (!load_grad2d(grad2d, g, p2)) continue;
     const int p = lds_off ? find_segment(s_off, nseg, g) : find_segment(a.offsets, nseg, g);
     const int v = p / a.segs, b = p - v * a.segs;
-    const int l = a.gather ? b : a.level[p];
-    const int64_t seg0 = lds_off ? s_off[p] : a.offsets[p];
-    const int64_t gi = a.gather ? (int64_t)a.gather[g] : a.lvl_off[(int64_t)b * a.L + l] + (g - seg0);
+    int l;
+    int64_t gi;
+    if (a.packed) {  // refined selection: the entry names the level and the index
+      const uint32_t e = a.gather[g];
+      l = (int)(e >> GS_PACKED_INDEX_BITS);
+      gi = (int64_t)(e & ((1u << GS_PACKED_INDEX_BITS) - 1u));
+      if (l >= a.L || gi >= a.lv[l].n) continue;  // not a stored Gaussian (the forward culled it)
+    } else {
+      l = a.gather ? b : a.level[p];
+      const int64_t seg0 = lds_off ? s_off[p] : a.offsets[p];
+      gi = a.gather ? (int64_t)a.gather[g] : a.lvl_off[(int64_t)b * a.L + l] + (g - seg0);
+    }
     preprocess_bwd_record<SINGLE>(a, records, p2, g, v, l, gi);
   }
 }
@@ -853,9 +863,15 @@ extern "C" gs_status gs_rasterize_bwd(const void* records, const uint32_t* pair_
   if (!gather && (blocks->n_blocks <= 0 || !blocks->lvl_off)) return GS_ERR_INVALID_ARG;
   const int tw = tuning->tile_w, th = tuning->tile_h;
   if (!tile_shape_supported(tw, th) || !batch_supported(tuning->batch)) return GS_ERR_UNSUPPORTED;
-  if (tuning->flags & GS_TUNE_PACKED_SELECTION) return GS_ERR_UNSUPPORTED;
+  const bool packed = (tuning->flags & GS_TUNE_PACKED_SELECTION) != 0;
+  if (packed && !gather) return GS_ERR_INVALID_ARG;
   const bool det = (tuning->flags & GS_TUNE_DETERMINISTIC) != 0;
-  if (det && gather && n_views > 1 && !(tuning->flags & GS_TUNE_SHARED_SELECTION)) return GS_ERR_UNSUPPORTED;
+  const bool shared = (tuning->flags & GS_TUNE_SHARED_SELECTION) && n_views > 1;
+  // decided before any launch: the Gaussian-major adjoint takes block-wise selections only, and the
+  // deterministic adjoint of several different selections needs the block-wise level table
+  if (shared && gather) return GS_ERR_UNSUPPORTED;
+  if (det && gather && n_views > 1 && !shared) return GS_ERR_UNSUPPORTED;
+  if (det && !shared && n_views > 1 && !blocks->lvl_cnt) return GS_ERR_INVALID_ARG;
   if (ws_bytes < rasterize_bwd_ws_bytes(record_capacity, 0, det)) return GS_ERR_WORKSPACE;
   const BwdWs w = bwd_ws_layout((char*)ws, record_capacity, det);
   float* grad2d = w.grad2d;
@@ -912,7 +928,8 @@ extern "C" gs_status gs_rasterize_bwd(const void* records, const uint32_t* pair_
   a.level = level;
   a.offsets = offsets;
   a.gather = gather;
-  a.segs = gather ? blocks->n_levels : blocks->n_blocks;
+  a.segs = packed ? 1 : gather ? blocks->n_levels : blocks->n_blocks;
+  a.packed = packed ? 1 : 0;
   a.cams = cams;
   a.capacity = record_capacity;
   a.B = blocks->n_blocks;

@@ -324,7 +324,8 @@ def render_frame(scene: DeviceScene, frame: Frame, cams_dev, mode=gs.GS_LOD_BLOC
     With check=True the counts are read back once (a host sync); if a capacity
     was too small the buffers grow and the frame is rendered again.  refine=True
     (block-wise selections only) adds the chunk refinement (gs_lod_refine); the
-    images are the same, the frame cannot be differentiated (backward_frame)."""
+    images are the same, and backward_frame takes the refined selection (not with
+    GS_TUNE_SHARED_SELECTION, nor GS_TUNE_DETERMINISTIC over several views)."""
     if refine and mode == LOD_POINTWISE:
         raise ValueError("the chunk refinement applies to block-wise selections")
     for _ in range(4):
@@ -372,15 +373,14 @@ def render_frame(scene: DeviceScene, frame: Frame, cams_dev, mode=gs.GS_LOD_BLOC
 def backward_frame(scene: DeviceScene, frame: Frame, cams_dev, d_rgb, grads, sh_degree=3, bg=(0.0, 0.0, 0.0),
                    stream=None):
     """Accumulate dL/d(parameters) of every level into `grads` (list of DeviceLevel)."""
-    if frame.refined_last:
-        raise ValueError("a frame rendered with refine=True cannot be differentiated; render it without")
+    tuning = frame.pre_tuning()  # with the packed-selection flag after a refined render
     nbytes = gs.workspace_bytes(gs.GS_WS_RASTERIZE_BWD, frame.record_capacity, frame.pair_capacity, frame.V, frame.W,
-                                frame.H, frame.tuning)
+                                frame.H, tuning)
     if getattr(frame, "bwd_ws", None) is None or frame.bwd_ws.numel() < nbytes:
         frame.bwd_ws = torch.empty(nbytes, dtype=torch.uint8, device=frame.device)
     level, offsets, gather = frame.selection()
     gs.rasterize_bwd(frame.records, frame.pair_records, frame.tile_ranges, frame.V, frame.W, frame.H, bg,
-                     frame.tuning, frame.rgb, frame.T, frame.n_last, d_rgb.contiguous(),
+                     tuning, frame.rgb, frame.T, frame.n_last, d_rgb.contiguous(),
                      [lv.struct() for lv in scene.levels], scene.blocks_struct(), level, offsets,
                      cams_dev, sh_degree, frame.record_capacity, frame.counts,
                      [gs.grads_struct(g.means, g.scales, g.quats, g.opac, g.sh) for g in grads], frame.bwd_ws, stream,

@@ -165,6 +165,10 @@ def test_chunk_refinement_sizes_and_checks(libgs):
     cb.argtypes = [P, P, P, P, ctypes.c_int64, P]
     assert cb(None, None, None, None, 10, None) == -1
     assert cb(lv, ctypes.byref(blk), P(dummy), P(dummy), 5, None) == -4   # fewer entries than chunks
+    # a level too large for the packed gather entries (index bits) is refused before any launch
+    big = (Gaussians * 3)(*[Gaussians(dummy, dummy, dummy, dummy, dummy, n, 3, 0) for n in (10, 10, 1 << 29)])
+    need = cap(big, ctypes.byref(blk))
+    assert cb(big, ctypes.byref(blk), P(dummy), P(dummy), need, None) == -2
 
     rf = libgs.gs_lod_refine
     rf.restype = ctypes.c_int32

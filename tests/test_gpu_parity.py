@@ -1513,7 +1513,7 @@ def _keys_refined(frame):
     return (v << 34) | e
 
 
-def _compare_refined(scene, cams, thresholds, rec_cap=None, what=""):
+def _compare_refined(scene, cams, thresholds, rec_cap=None, what="", mode=gs.GS_LOD_BLOCKWISE):
     """Render `cams` in one call with and without the refinement; the images,
     transmittance, last contributor, visible and pair counts and the sorted
     pairs (records named by (view, level, index)) must be identical, the refined
@@ -1524,8 +1524,8 @@ def _compare_refined(scene, cams, thresholds, rec_cap=None, what=""):
     cap = V * scene.max_records_per_view()
     fu = render.Frame(scene.n_blocks, V, W, H, max(1, cap), 1 << 22)
     fr = render.Frame(scene.n_blocks, V, W, H, rec_cap or max(1, cap), 1 << 22)
-    render.render_frame(scene, fu, cams_dev, thresholds=thresholds)
-    render.render_frame(scene, fr, cams_dev, thresholds=thresholds, refine=True)
+    render.render_frame(scene, fu, cams_dev, mode=mode, thresholds=thresholds)
+    render.render_frame(scene, fr, cams_dev, mode=mode, thresholds=thresholds, refine=True)
     torch.cuda.synchronize()
     cu, cr = fu.host_counts(), fr.host_counts()
     print("case: refine", what, "unrefined", cu, "refined", cr, flush=True)
@@ -1620,22 +1620,66 @@ def test_refined_record_capacity_overflow_regrows():
     _compare_refined(scene, cams, (30.0, 80.0), rec_cap=64, what="regrow")
 
 
-def test_refined_frame_cannot_be_differentiated():
-    scene = _ragged_block_scene(seed=55)
-    cam = synth.look_camera((-150.0, 0.0, 60.0), 0.0, math.radians(-20.0), 128, 96)
-    cams_dev = gs.cameras_to_device([cam])
-    f = render.Frame(scene.n_blocks, 1, 128, 96, scene.max_records_per_view(), 1 << 20)
-    render.render_frame(scene, f, cams_dev, thresholds=(30.0, 80.0), refine=True)
-    grads = [lv.zeros_like() for lv in scene.levels]
-    with pytest.raises(ValueError):
-        render.backward_frame(scene, f, cams_dev, torch.zeros_like(f.rgb), grads)
-    # the C ABI refuses the packed selection in the backward as well
-    t = gs.tuning_struct(16, 16, 256, gs.GS_TUNE_PACKED_SELECTION)
-    level, offsets, gather = f.selection()
-    with pytest.raises(gs.GsError) as err:
-        gs.rasterize_bwd(f.records, f.pair_records, f.tile_ranges, 1, 128, 96, (0.0, 0.0, 0.0), t, f.rgb, f.T,
-                         f.n_last, torch.zeros_like(f.rgb), [lv.struct() for lv in scene.levels],
-                         scene.blocks_struct(), level, offsets, cams_dev, 3, f.record_capacity, f.counts,
-                         [gs.grads_struct(g.means, g.scales, g.quats, g.opac, g.sh) for g in grads],
-                         torch.empty(1 << 20, dtype=torch.uint8, device="cuda"), None, f.tile_queue, gather=gather)
-    assert err.value.status == gs.GS_ERR_UNSUPPORTED
+def test_refined_frame_gradients_equal_unrefined():
+    """The adjoint through the refined (packed) selection: with one view and the
+    deterministic flag the gradients equal the unrefined frame's bit for bit;
+    with several views (FP32 atomics) within rounding; the modes that need the
+    block-wise table refuse it before any launch."""
+    fine, block_id, u, cells = synth.city_finest(600_000, seed=57, grid=(4, 4))
+    scene = render.DeviceScene.from_finest(fine, block_id, u, cells)
+    scene.compute_bounds(4.0)
+    cams = synth.city_views(seed=57, n_xy=1, width=320, height=180)[:3]
+    rc = scene.max_records_per_view()
+    rng = np.random.default_rng(57)
+
+    def grads(views, flags, refine):
+        f = render.Frame(scene.n_blocks, len(views), 320, 180, len(views) * rc, 1 << 21,
+                         gs.tuning_struct(16, 16, 256, flags))
+        cd = gs.cameras_to_device(views)
+        render.render_frame(scene, f, cd, refine=refine)
+        c = f.host_counts()
+        return f, cd, c, _grads_for(scene, f, cd, d[: len(views)])
+
+    d = torch.from_numpy(rng.normal(size=(3, 3, 180, 320)).astype(np.float32)).cuda()
+    for v in range(3):
+        fu, _, cu, gu = grads(cams[v:v + 1], gs.GS_TUNE_DETERMINISTIC, False)
+        fr, _, cr, gr = grads(cams[v:v + 1], gs.GS_TUNE_DETERMINISTIC, True)
+        print("case: refined gradients, view", v, cu, cr, flush=True)
+        assert cr["records"] < cu["records"] and cr["visible"] == cu["visible"]
+        assert torch.equal(fr.rgb, fu.rgb)
+        for l in range(3):
+            for k in range(5):
+                np.testing.assert_array_equal(gr[l][k], gu[l][k])
+    fu, _, _, gu = grads(cams, 0, False)
+    fr, cd, _, gr = grads(cams, 0, True)
+    assert torch.equal(fr.rgb, fu.rgb)
+    for l in range(3):
+        for k in range(5):
+            if np.linalg.norm(gu[l][k]) > 0:
+                assert rel_l2(gr[l][k], gu[l][k]) <= SUM_L2_TOL, (l, k)
+    # several views: the Gaussian-major and the deterministic adjoints need the block-wise table
+    for flags in (gs.GS_TUNE_SHARED_SELECTION, gs.GS_TUNE_DETERMINISTIC):
+        fr.tuning = gs.tuning_struct(16, 16, 256, flags)
+        fr.bwd_ws = None
+        with pytest.raises(gs.GsError) as err:
+            render.backward_frame(scene, fr, cd, d, [lv.zeros_like() for lv in scene.levels])
+        assert err.value.status == gs.GS_ERR_UNSUPPORTED
+
+
+def test_refined_binary16_levels_and_all_finest_mode():
+    """The refinement over binary16 levels (the largest |scale| read from half
+    storage) and with every block at the finest level (LoD off)."""
+    fine, block_id, u, cells = synth.city_finest(800_000, seed=56, grid=(4, 4))
+    scene = render.DeviceScene.from_finest(fine, block_id, u, cells)
+    scene.compute_bounds(4.0)
+    rs = scene.reduced_precision(sh_degrees=(1, 2, 3), half_levels=(0, 1))
+    assert rs.levels[0].scales.dtype == torch.float16
+    rs.ensure_chunks()
+    torch.cuda.synchronize()
+    chunk_off, bounds = _host_chunk_tables(rs)
+    np.testing.assert_array_equal(rs.chunk_off.cpu().numpy(), chunk_off)
+    C = int(chunk_off[-1])
+    np.testing.assert_array_equal(rs.chunk_bounds[:C].cpu().numpy().view(np.int32), bounds.view(np.int32))
+    cams = synth.city_views(seed=56, n_xy=2, width=640, height=360)
+    _compare_refined(rs, cams, (200.0, 500.0), what="binary16 levels")
+    _compare_refined(scene, cams[:6], (), what="all finest", mode=gs.GS_LOD_ALL_FINEST)
