@@ -65,7 +65,7 @@ MEASURED_TRAFFIC = {
     "raster_fwd_kernel<16,16,256>": (("raster.hip", "tile.h", "project.h", "gs_common.h"), "11dda1d1949f6681", 8,
                                      667.98e6),
     "bin_sort": (("sort.hip", "radix.h", "scan.h", "gs_common.h"), "7c172e1976d40684", 8, 1281.02e6),
-    "lod_refine": (("refine.hip", "radix.h", "scan.h", "project.h", "gs_common.h"), "5ebcb2e4d9c74c9b", 8, 35.5e6),
+    "lod_refine": (("refine.hip", "radix.h", "scan.h", "project.h", "gs_common.h"), "d204861f3281dbaa", 8, 35.5e6),
 }
 
 

@@ -12,9 +12,9 @@
 // bound on the 3-sigma radius of any of its Gaussians.  The bound is the one the
 // projection's own early test uses for one Gaussian: the trace of the projected
 // covariance is at most |J|_F^2 s^2, |J|_F^2 is largest at the smallest depth
-// over the box, s at most the chunk's largest scale; so a Gaussian of a dropped
-// chunk is one the exact test culls too, and the records left produce the same
-// visible set.  The survivors are listed as records in the block-wise order (per
+// over the box, s at most the chunk's largest scale (and one pixel more covers
+// the rounding of the corners' projections); so a Gaussian of a dropped chunk is
+// one the exact test culls too, and the records left produce the same visible set.  The survivors are listed as records in the block-wise order (per
 // view: blocks in order, chunks and Gaussians in storage order), so the depth
 // order and its ties among the visible records are unchanged and the images are
 // identical bit for bit.
@@ -74,13 +74,14 @@ struct ChunkArgs {
   int32_t B, L;
 };
 
-// one work-group per chunk: box of the centres (lo xyz, hi xyz) and the largest |scale|
+// largest |scale| component of Gaussian gi
 template <bool HALF>
 __device__ __forceinline__ float chunk_scale(const LevelPtrs& L, int64_t gi) {
   return fmaxf(fabsf(attr<HALF>(L.scales, gi)),
                fmaxf(fabsf(attr<HALF>(L.scales, L.n + gi)), fabsf(attr<HALF>(L.scales, 2 * L.n + gi))));
 }
 
+// one work-group per chunk: box of the centres (lo xyz, hi xyz), the largest |scale| and the run
 __global__ void __launch_bounds__(256) chunk_bounds_kernel(ChunkArgs a, int64_t max_chunks,
                                                            float* __restrict__ bounds) {
   __shared__ float s_red[7][4];
@@ -169,15 +170,15 @@ struct RefineArgs {
   int32_t B, L, V, W, H;
 };
 
-// per (view, chunk): the records the chunk keeps (0 if not selected for the view or culled)
 // chunks in the table, at most max_chunks (the entries the workspace holds); a larger table
-// raises GS_FLAG_RECORDS in refine_views_kernel and the frame is invalid
+// raises GS_FLAG_RECORDS when the view offsets are written, and the frame is invalid
 __device__ __forceinline__ int64_t table_chunks(const RefineArgs& a) {
   const int64_t c = a.chunk_off[a.B * a.L];
   return c < a.max_chunks ? c : a.max_chunks;
 }
 
-// entry e = v * C + k (view v, chunk k of C)
+// records kept by entry e = v * C + k (view v, chunk k of C): 0 if the view did not select the
+// chunk's level or the chunk is culled, else the chunk's size
 __device__ __forceinline__ uint32_t entry_keep(const RefineArgs& a, int64_t e, int64_t C) {
   const int v = (int)(e / C);
   const int64_t k = e - (int64_t)v * C;
