@@ -267,7 +267,7 @@ def workload_lod(args, torch, gs, render, synth):
         target = torch.rand((1, 3, H, W), generator=torch.Generator(device=dev).manual_seed(3), device=dev)
         for _ in range(2):
             for v in range(0, V, max(1, V // args.bwd_views)):
-                render.render_frame(scene, frame, cam_slot[v], thresholds=thresholds, check=False)
+                render.render_frame(scene, frame, cam_slot[v], thresholds=thresholds, check=False, refine=refine)
                 d = torch.sign(frame.rgb - target) / frame.rgb.numel()
                 render.backward_frame(scene, frame, cam_slot[v], d, grads)
         torch.cuda.synchronize()
