@@ -325,7 +325,10 @@ def render_frame(scene: DeviceScene, frame: Frame, cams_dev, mode=gs.GS_LOD_BLOC
     was too small the buffers grow and the frame is rendered again.  refine=True
     (block-wise selections only) adds the chunk refinement (gs_lod_refine); the
     images are the same, and backward_frame takes the refined selection (not with
-    GS_TUNE_SHARED_SELECTION, nor GS_TUNE_DETERMINISTIC over several views)."""
+    GS_TUNE_SHARED_SELECTION, nor GS_TUNE_DETERMINISTIC over several views).  The
+    chunk boxes are made once per scene: after moving or rescaling Gaussians (an
+    optimiser step) call scene.invalidate_chunks(), or the refinement may drop
+    Gaussians that have become visible."""
     if refine and mode == LOD_POINTWISE:
         raise ValueError("the chunk refinement applies to block-wise selections")
     for _ in range(4):
