@@ -3,9 +3,10 @@
 Headline (one JSON line): block-wise LoD render of a 20M-Gaussian synthetic city
 at 1600x900.  One step = every evaluation view rendered once (48 views: heights
 50/150/400 m, 8 positions each, pitch -90 and -45 degrees), each frame
-lod_select -> preprocess -> bin_sort -> rasterize_fwd, replayed from a HIP
-graph, with the tile launch shape chosen by the autotuner (bit-identical images
-required).  Each call renders several views in one batched pass (--views-per-call,
+lod_select -> lod_refine -> preprocess -> bin_sort -> rasterize_fwd (the chunk
+refinement drops the chunks the projection would cull whole, images unchanged;
+--no-refine leaves it out), replayed from a HIP graph, with the tile launch
+shape chosen by the autotuner (bit-identical images required).  Each call renders several views in one batched pass (--views-per-call,
 default 8: one record space, one binning, one compositing launch over all their
 tiles) and calls are kept in flight on separate streams with their own buffers
 (--in-flight, default 4), so the latency-bound binning of one call overlaps the
@@ -17,7 +18,7 @@ In the same line: per-view FPS (mean / median / min, and per height and pitch:
 the paper's Fig. 5 split), the plain comparator (LoD off: every block at the
 finest level, eager, default 16x16 tiles), the point-wise LoD comparator, the
 reduced-precision levels, fwd+bwd ms/view for LoD and plain, rooflines of the
-three stages timed with HIP events (the longest one is `roofline`), the
+stages timed with HIP events (the longest one is `roofline`), the
 whole-frame HBM fraction, the CPU oracle on a bounded sample (six city frames;
 the other configurations' oracle times under cpu_baseline.other_configs), and
 the other configurations as their own keys: small_render (4096 Gaussians,
