@@ -63,7 +63,7 @@ FLOPS_PER_EVAL = 15
 # per call, valid for the kernel sources with the given fingerprint only
 MEASURED_TRAFFIC = {
     "preprocess_kernel": (("preprocess.hip", "project.h", "gs_common.h"), "2f2db44ee46c9077", 8, 1411.33e6),
-    "raster_fwd_kernel<16,16,256>": (("raster.hip", "tile.h", "project.h", "gs_common.h"), "11dda1d1949f6681", 8,
+    "raster_fwd_kernel<16,16,256>": (("raster.hip", "tile.h", "project.h", "gs_common.h"), "6ead4438b5cf0fa1", 8,
                                      667.98e6),
     "bin_sort": (("sort.hip", "radix.h", "scan.h", "gs_common.h"), "7c172e1976d40684", 8, 1281.02e6),
     "lod_refine": (("refine.hip", "radix.h", "scan.h", "project.h", "gs_common.h"), "d204861f3281dbaa", 8, 35.5e6),
