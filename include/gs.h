@@ -245,7 +245,13 @@ gs_status gs_lod_select_points(const gs_gaussians* levels, int32_t n_levels, con
  *     counts[GS_COUNT_RECORDS] = records kept; GS_FLAG_RECORDS is raised (and
  *     the list truncated) past record_capacity or if the chunk table holds more
  *     than max_chunks; ws / ws_bytes: at least gs_refine_workspace_bytes(V,
- *     max_chunks); chunk_off and bounds as gs_chunk_bounds wrote them. */
+ *     max_chunks); chunk_off and bounds as gs_chunk_bounds wrote them.
+ * All arrays are caller-owned device memory except the host structures noted;
+ * calls are ordered on `stream`.  The tables describe the Gaussians as they were
+ * when gs_chunk_bounds ran: rebuild them after moving or rescaling Gaussians,
+ * or visible Gaussians may be dropped.  Errors: GS_ERR_INVALID_ARG (NULL
+ * pointers, sizes out of range, record_capacity >= 2^32, V * max_chunks >=
+ * 2^31), GS_ERR_WORKSPACE (ws_bytes too small), before any launch. */
 #define GS_CHUNK 2048
 #define GS_PACKED_INDEX_BITS 29
 int64_t gs_chunk_capacity(const gs_gaussians* levels /* host [n_levels] */, const gs_blocks* blocks /* host */);
